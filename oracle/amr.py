@@ -1,0 +1,323 @@
+"""Berger-Oliger AMR hierarchy on dense per-level arrays (oracle; test infrastructure).
+
+Representation: level l is one dense periodic array over the whole domain at spacing
+dx_l = dx_0 / 2^l, plus a boolean mask of its valid cells (the union of its boxes).
+Cells next to the valid region (26-neighbourhood, periodic) are its ghost cells.  A
+ghost cell that is a valid cell of another box of the same level is simply that cell
+here, so same-level ghost copies (periodic images included) are implicit and always
+current; the remaining ghost cells are set by coarse-to-fine interpolation.
+
+Paper passages followed:
+* Subcycling (section II.A, Fig. 2): level l is advanced by dt_l, then level l+1 twice
+  by dt_l/2, then the two levels are synchronised.
+* Ghost cells of a fine level are interpolated from the coarse level in space and time,
+  at every intermediate stage, using the coarse states at the start and end of the
+  coarse step (section II.A).  Spatial scheme: linear conservative (interpolation type
+  1, appendix E "AMR parameters"), read here as unlimited central slopes
+      f = C_I + sum_d s_d (C_{I+e_d} - C_{I-e_d}) / 2,   s_d = +-1/4 the child offset,
+  evaluated as ((C_I + t_x) + t_y) + t_z with t_d = (C_{I+e_d} - C_{I-e_d}) * (+-1/8).
+  Temporal: C(alpha) = (1 - alpha) C_old + alpha C_new, interpolated in time first;
+  alpha = 0 and alpha = 1 take C_old and C_new themselves.  Fine sub-step j in {0, 1}
+  at RK stage fraction c_s has alpha = (j + c_s) / 2.
+* Synchronisation (section II.A): the fine level is averaged onto the coarse cells it
+  covers, c = ((((f000+f100)+(f010+f110))+((f001+f101)+(f011+f111))) * 1/8), and the
+  fine ghost cells are set again with no temporal interpolation (alpha = 1).
+* Operation order per level step, reproducing the numbering of Fig. 2: stage 1, then
+  (fill, stage) for the remaining stages; after the last stage a fill of the new state
+  at the step's end time unless the step is the second sub-step, whose end is the
+  synchronisation that sets the ghosts itself.
+* Regrid (section II "regridding"): new valid cells keep the old level's values where
+  it already had valid cells and are interpolated from the coarse level elsewhere.
+
+Interpolation and averaging are done in float64 from promoted values and rounded to
+the storage precision on store.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .scalars import RK4_C, level_dt, level_dx, level_time, int_power
+from .level import rk4_stage
+from .tagging import tag_cells
+from .energy import energy as _energy
+
+
+def boxes_mask(boxes, M: int) -> np.ndarray:
+    """Valid mask of boxes (x_lo, y_lo, z_lo, x_hi, y_hi, z_hi), inclusive, in [0, M)."""
+    m = np.zeros((M, M, M), dtype=bool)
+    for b in boxes:
+        xl, yl, zl, xh, yh, zh = (int(v) for v in b)
+        if min(xl, yl, zl) < 0 or max(xh, yh, zh) >= M or xl > xh or yl > yh or zl > zh:
+            raise ValueError(f"box {b} outside the level domain [0, {M})")
+        if m[zl:zh + 1, yl:yh + 1, xl:xh + 1].any():
+            raise ValueError(f"box {b} overlaps another box")
+        m[zl:zh + 1, yl:yh + 1, xl:xh + 1] = True
+    return m
+
+
+def dilate(mask: np.ndarray, r: int) -> np.ndarray:
+    """Periodic dilation by r cells in every direction (a (2r+1)^3 cube)."""
+    out = mask.copy()
+    for ax in range(3):
+        cur = out.copy()
+        for s in range(1, r + 1):
+            cur |= np.roll(out, s, axis=ax) | np.roll(out, -s, axis=ax)
+        out = cur
+    return out
+
+
+def erode(mask: np.ndarray, r: int) -> np.ndarray:
+    return ~dilate(~mask, r)
+
+
+def ghost_mask(valid: np.ndarray) -> np.ndarray:
+    return dilate(valid, 1) & ~valid
+
+
+def coarsen_mask(fine: np.ndarray) -> np.ndarray:
+    """Coarse cells any of whose 8 children is set."""
+    return fine.reshape(fine.shape[0] // 2, 2, fine.shape[1] // 2, 2,
+                        fine.shape[2] // 2, 2).any(axis=(1, 3, 5))
+
+
+def refine_mask(coarse: np.ndarray) -> np.ndarray:
+    return coarse.repeat(2, axis=0).repeat(2, axis=1).repeat(2, axis=2)
+
+
+def time_interp(Cold, Cnew, alpha: float) -> np.ndarray:
+    """(1 - alpha) C_old + alpha C_new in float64; alpha 0 / 1 return C_old / C_new."""
+    if alpha == 1.0:
+        return Cnew.astype(np.float64)
+    if alpha == 0.0:
+        return Cold.astype(np.float64)
+    return (1.0 - alpha) * Cold.astype(np.float64) + alpha * Cnew.astype(np.float64)
+
+
+def interp_cells(C: np.ndarray, fz: np.ndarray, fy: np.ndarray, fx: np.ndarray) -> np.ndarray:
+    """Linear conservative interpolation of coarse array C at fine cells (fz, fy, fx)."""
+    Mc = C.shape[0]
+    Iz, Iy, Ix = fz // 2, fy // 2, fx // 2
+    sx = np.where(fx & 1, 0.125, -0.125)
+    sy = np.where(fy & 1, 0.125, -0.125)
+    sz = np.where(fz & 1, 0.125, -0.125)
+    c0 = C[Iz, Iy, Ix]
+    tx = (C[Iz, Iy, (Ix + 1) % Mc] - C[Iz, Iy, (Ix - 1) % Mc]) * sx
+    ty = (C[Iz, (Iy + 1) % Mc, Ix] - C[Iz, (Iy - 1) % Mc, Ix]) * sy
+    tz = (C[(Iz + 1) % Mc, Iy, Ix] - C[(Iz - 1) % Mc, Iy, Ix]) * sz
+    return ((c0 + tx) + ty) + tz
+
+
+def interp_support(fz, fy, fx, Mc: int) -> np.ndarray:
+    """Coarse cells (as a mask) read by interp_cells at the given fine cells."""
+    m = np.zeros((Mc, Mc, Mc), dtype=bool)
+    Iz, Iy, Ix = fz // 2, fy // 2, fx // 2
+    m[Iz, Iy, Ix] = True
+    for d in (-1, 1):
+        m[Iz, Iy, (Ix + d) % Mc] = True
+        m[Iz, (Iy + d) % Mc, Ix] = True
+        m[(Iz + d) % Mc, Iy, Ix] = True
+    return m
+
+
+def average_down_arrays(F: np.ndarray) -> np.ndarray:
+    """2^3 -> 1 mean of a fine [z, y, x] array (float64), in the canonical order."""
+    f = F.astype(np.float64)
+
+    def c(dx, dy, dz):
+        return f[dz::2, dy::2, dx::2]
+
+    return ((((c(0, 0, 0) + c(1, 0, 0)) + (c(0, 1, 0) + c(1, 1, 0)))
+             + ((c(0, 0, 1) + c(1, 0, 1)) + (c(0, 1, 1) + c(1, 1, 1)))) * 0.125)
+
+
+def schedule(finest: int, nstages: int):
+    """Operations of one coarse step with levels 0..finest and an nstages integrator.
+
+    ("stage", l, s): RK stage s of level l;  ("fill", l, j, s): ghost fill of level l in
+    sub-step j before stage s (s == nstages: the new state at the step end);
+    ("sync", l): average level l onto l-1 and refill the ghosts of level l.
+    A step of level l >= 1 is the j-th of the two sub-steps of its parent's step.
+    """
+    ops = []
+
+    def step(lev, sub):
+        for s in range(nstages):
+            if s > 0:
+                ops.append(("fill", lev, sub, s))
+            ops.append(("stage", lev, s))
+        if lev > 0 and sub == 0:
+            ops.append(("fill", lev, sub, nstages))
+        if lev < finest:
+            step(lev + 1, 0)
+            step(lev + 1, 1)
+            ops.append(("sync", lev + 1))
+
+    step(0, 0)
+    return ops
+
+
+class Level:
+    def __init__(self, M: int, dx: float, dt: float):
+        self.M, self.dx, self.dt = M, dx, dt
+        self.valid = np.zeros((M, M, M), dtype=bool)
+        self.ghost = np.zeros((M, M, M), dtype=bool)
+        self.boxes = []
+        self.U = None
+        self.Uold = None
+        self.X = None
+        self.acc = None
+        self.k = 0
+
+
+class Hierarchy:
+    """Oracle AMR hierarchy.  Layouts are inputs (``set_layout``); nothing is clustered."""
+
+    def __init__(self, n0: int, L: float, cfl: float, eta0: float, max_level: int,
+                 alpha: float = 2.0, lam: float = 1.0, beta: int = 2,
+                 dtype=np.float64, check_nesting: bool = True):
+        self.n0, self.L, self.cfl, self.eta0 = n0, L, cfl, eta0
+        self.max_level = max_level
+        self.alpha, self.lam, self.beta = alpha, lam, beta
+        self.dtype = np.dtype(dtype)
+        self.check_nesting = check_nesting
+        self.levels: list[Level] = []
+        self.trace: list[tuple] = []
+
+    # ---- bookkeeping -------------------------------------------------------------
+    @property
+    def finest(self) -> int:
+        return len(self.levels) - 1
+
+    def time(self, lev: int) -> float:
+        L = self.levels[lev]
+        return level_time(self.eta0, L.k, L.dt)
+
+    def _new_level(self, lev: int) -> Level:
+        M = self.n0 << lev
+        return Level(M, level_dx(self.L, self.n0, lev), level_dt(self.L, self.n0, self.cfl, lev))
+
+    # ---- layout ------------------------------------------------------------------
+    def set_level0(self, U0: np.ndarray, boxes=None):
+        M = self.n0
+        L = self._new_level(0)
+        if boxes is None:
+            boxes = [(0, 0, 0, M - 1, M - 1, M - 1)]
+        L.valid = boxes_mask(boxes, M)
+        if not L.valid.all():
+            raise ValueError("level 0 must cover the whole domain")
+        L.boxes = [tuple(b) for b in boxes]
+        L.U = U0.astype(self.dtype).copy()
+        self.levels = [L]
+
+    def set_layout(self, lev: int, boxes):
+        """Set (or change, or with no boxes remove) the layout of level lev >= 1."""
+        if lev < 1 or lev > len(self.levels) or lev > self.max_level:
+            raise ValueError("bad level")
+        if len(boxes) == 0:
+            del self.levels[lev:]
+            return
+        C = self.levels[lev - 1]
+        if lev == len(self.levels):
+            L = self._new_level(lev)
+            L.k = 2 * C.k
+            old_valid = np.zeros((L.M,) * 3, dtype=bool)
+            oldU = None
+            self.levels.append(L)
+        else:
+            L = self.levels[lev]
+            old_valid = L.valid
+            oldU = L.U
+        new_valid = boxes_mask(boxes, L.M)
+        if self.check_nesting:
+            need = dilate(coarsen_mask(new_valid), 1)
+            if not np.all(C.valid[need]):
+                raise ValueError("level not nested in its coarse level")
+        U = np.full((4, L.M, L.M, L.M), np.nan, dtype=self.dtype)
+        keep = new_valid & old_valid
+        if oldU is not None:
+            U[:, keep] = oldU[:, keep]
+        fresh = new_valid & ~old_valid
+        fz, fy, fx = np.nonzero(fresh)
+        for c in range(4):
+            U[c][fz, fy, fx] = interp_cells(C.U[c].astype(np.float64), fz, fy, fx).astype(self.dtype)
+        L.valid = new_valid
+        L.ghost = ghost_mask(new_valid)
+        L.boxes = [tuple(b) for b in boxes]
+        L.U = U
+        L.Uold = None
+        self.fill(lev, L.U, 1.0)
+
+    # ---- ghost fill (coarse -> fine) ---------------------------------------------
+    def fill(self, lev: int, X: np.ndarray, alpha: float):
+        """Set the coarse/fine ghost cells of the psi components of X (level lev)."""
+        if lev == 0:
+            return
+        L, C = self.levels[lev], self.levels[lev - 1]
+        fz, fy, fx = np.nonzero(L.ghost)
+        if self.check_nesting and fz.size:
+            sup = interp_support(fz, fy, fx, C.M)
+            if not np.all(C.valid[sup]):
+                raise ValueError("ghost interpolation reads coarse cells outside the coarse level")
+        for c in (0, 1):
+            Cold = C.Uold[c] if C.Uold is not None else None
+            Ct = time_interp(Cold, C.U[c], alpha)
+            X[c][fz, fy, fx] = interp_cells(Ct, fz, fy, fx).astype(X.dtype)
+
+    # ---- stepping ----------------------------------------------------------------
+    def coarse_step(self, nstages: int = 4):
+        """One coarse step: every level advanced in the order of ``schedule``."""
+        ops = schedule(self.finest, nstages)
+        for op in ops:
+            self.trace.append(op)
+            if op[0] == "stage":
+                self._stage(op[1], op[2])
+            elif op[0] == "fill":
+                _, lev, sub, s = op
+                L = self.levels[lev]
+                c = 1.0 if s == nstages else RK4_C[s]
+                self.fill(lev, L.U if s == nstages else L.X, (sub + c) / 2.0)
+            else:
+                self.average_down(op[1])
+                self.fill(op[1], self.levels[op[1]].U, 1.0)
+
+    def _stage(self, lev: int, s: int):
+        L = self.levels[lev]
+        eta_n = level_time(self.eta0, L.k, L.dt)
+        X = L.U if s == 0 else L.X
+        with np.errstate(all="ignore"):
+            L.acc, Y = rk4_stage(s, X, L.U, L.acc if s else None, eta_n, L.dt,
+                                 1.0 / (L.dx * L.dx), self.alpha, self.lam, self.beta)
+        if s == 3:
+            L.Uold, L.U, L.X, L.acc = L.U, Y, None, None
+            L.k += 1
+        else:
+            L.X = Y
+
+    def average_down(self, fine: int):
+        F, C = self.levels[fine], self.levels[fine - 1]
+        cov = coarsen_mask(F.valid)
+        for c in range(4):
+            with np.errstate(all="ignore"):
+                avg = average_down_arrays(F.U[c])
+            C.U[c][cov] = avg[cov].astype(self.dtype)
+
+    # ---- diagnostics -------------------------------------------------------------
+    def tags(self, lev: int) -> np.ndarray:
+        L = self.levels[lev]
+        return tag_cells(L.U[0], L.U[1]) & L.valid.astype(np.uint8)
+
+    def covered(self, lev: int) -> np.ndarray:
+        """Cells of level lev under a finer level."""
+        if lev >= self.finest:
+            return np.zeros((self.levels[lev].M,) * 3, dtype=bool)
+        return coarsen_mask(self.levels[lev + 1].valid)
+
+    def energy(self):
+        """Composite [kin, grad, pot, total] over cells not covered by a finer level."""
+        tot = np.zeros(4)
+        for lev, L in enumerate(self.levels):
+            cp = self.lam * int_power(self.time(lev), self.beta)
+            mask = L.valid & ~self.covered(lev)
+            with np.errstate(all="ignore"):
+                tot += np.array(_energy(L.U, L.dx, cp, mask))
+        return tot.tolist()

@@ -1,0 +1,122 @@
+"""Right-hand side and classic RK4 step on one dense periodic lattice (oracle).
+
+Test infrastructure only.  Follows the minimal example of the paper (eqs. EOM1 and
+EOM2, the ``Rhs`` kernel function of section III.A) with the Laplacian of appendix A at
+order 1 (the 7-point stencil), and integrator type 4 (classic RK4, appendix E).
+
+Canonical operation order (both the oracle and the HIP path evaluate exactly these
+expressions, with no fused multiply-add):
+
+    lap   = ((((u[x-1] + u[x+1]) + (u[y-1] + u[y+1])) + (u[z-1] + u[z+1])) - 6 u) * inv_dx2
+    r2    = psi1*psi1 + psi2*psi2
+    pot   = c_pot * (r2 - 1)
+    k_psi = Pi
+    k_Pi  = (lap - c_fric * Pi) - pot * psi
+
+and RK4 in accumulator form (U_n the state at the step start, h = dt):
+
+    stage 1: k1 = f(U_n);  acc = U_n + (h/6) k1;   U_a = U_n + (h/2) k1
+    stage 2: k2 = f(U_a);  acc = acc + (h/3) k2;   U_b = U_n + (h/2) k2
+    stage 3: k3 = f(U_b);  acc = acc + (h/3) k3;   U_a = U_n + h k3
+    stage 4: k4 = f(U_a);  U_{n+1} = acc + (h/6) k4
+
+which is the textbook y + h/6 (k1 + 2 k2 + 2 k3 + k4) with the sum formed as it goes.
+
+Mixed precision (FP32 storage): U_n, U_a, U_b are float32 and the right-hand side is
+evaluated in float32 (scalars rounded to float32 once); every update above is done in
+float64 from the promoted float32 values and rounded to float32 on store, while ``acc``
+stays float64.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .scalars import rk4_weights, stage_scalars
+
+
+def lap7(u: np.ndarray, inv_dx2) -> np.ndarray:
+    """7-point Laplacian of a periodic [z, y, x] array, in the array's own precision."""
+    t = u.dtype.type
+    xm = np.roll(u, 1, axis=2)
+    xp = np.roll(u, -1, axis=2)
+    ym = np.roll(u, 1, axis=1)
+    yp = np.roll(u, -1, axis=1)
+    zm = np.roll(u, 1, axis=0)
+    zp = np.roll(u, -1, axis=0)
+    return ((((xm + xp) + (ym + yp)) + (zm + zp)) - t(6.0) * u) * t(inv_dx2)
+
+
+def rhs(U: np.ndarray, inv_dx2: float, c_fric: float, c_pot: float) -> np.ndarray:
+    """f(U) for eqs. EOM1/EOM2 on a periodic lattice, in U's precision."""
+    t = U.dtype.type
+    p1, p2, q1, q2 = U[0], U[1], U[2], U[3]
+    cf = t(c_fric)
+    cp = t(c_pot)
+    r2 = p1 * p1 + p2 * p2
+    pot = cp * (r2 - t(1.0))
+    K = np.empty_like(U)
+    K[0] = q1
+    K[1] = q2
+    K[2] = (lap7(p1, inv_dx2) - cf * q1) - pot * p1
+    K[3] = (lap7(p2, inv_dx2) - cf * q2) - pot * p2
+    return K
+
+
+def rk4_stage(s: int, X: np.ndarray, Un: np.ndarray, acc, eta_n: float, dt: float,
+              inv_dx2: float, alpha: float, lam: float, beta: int):
+    """Stage s (0-based) of classic RK4 in accumulator form.
+
+    X is the stage input (U_n itself for s = 0), Un the state at the step start, acc the
+    float64 accumulator (ignored for s = 0).  Returns (acc, Y): Y is the next stage input
+    for s < 3 and U_{n+1} for s = 3, in the storage precision of Un.
+    """
+    st = Un.dtype
+    h6, h3, h2, h1 = rk4_weights(dt)
+    _, cf, cp = stage_scalars(eta_n, dt, s, alpha, lam, beta)
+    k = rhs(X, inv_dx2, cf, cp).astype(np.float64)
+    if s == 3:
+        return acc, (acc + h6 * k).astype(st)
+    U64 = Un.astype(np.float64)
+    if s == 0:
+        acc = U64 + h6 * k
+        Y = U64 + h2 * k
+    elif s == 1:
+        acc = acc + h3 * k
+        Y = U64 + h2 * k
+    else:
+        acc = acc + h3 * k
+        Y = U64 + h1 * k
+    return acc, Y.astype(st)
+
+
+def rk4_step(U: np.ndarray, eta_n: float, dt: float, inv_dx2: float,
+             alpha: float, lam: float, beta: int, fill=None) -> np.ndarray:
+    """One classic RK4 step of size dt from time eta_n; returns U_{n+1} (U's dtype).
+
+    ``fill(s, X)``, if given, is called on the stage input X before stages s = 1, 2, 3
+    (0-based) to set ghost values in place; a periodic single level needs none.
+    """
+    X = U
+    acc = None
+    for s in range(4):
+        if s > 0 and fill is not None:
+            fill(s, X)
+        acc, X = rk4_stage(s, X, U, acc, eta_n, dt, inv_dx2, alpha, lam, beta)
+    return X
+
+
+def run_single_level(U0: np.ndarray, nsteps: int, eta0: float, dt: float, dx: float,
+                     alpha: float = 2.0, lam: float = 1.0, beta: int = 2,
+                     callback=None) -> np.ndarray:
+    """nsteps RK4 steps of a periodic lattice; step k starts at eta0 + k*dt.
+
+    ``callback(k, U)`` is called after each step with the 1-based step count.
+    """
+    from .scalars import level_time
+    inv_dx2 = 1.0 / (dx * dx)
+    U = U0.copy()
+    for k in range(nsteps):
+        U = rk4_step(U, level_time(eta0, k, dt), dt, inv_dx2, alpha, lam, beta)
+        if callback is not None:
+            callback(k + 1, U)
+    return U

@@ -1,0 +1,46 @@
+"""Time bookkeeping and per-stage scalars (oracle; test infrastructure only).
+
+* Delta x_l = Delta x_0 / 2^l, Delta t_l = cfl * Delta x_l (section II, eq. dtscaling).
+* The time of level l after k of its steps is eta0 + k * Delta t_l: one multiply and one
+  add from integers, so levels that align in time hold bit-identical times.
+* Classic RK4 (integrator type 4) evaluates the right-hand side at eta_n + c_s dt with
+  c = (0, 1/2, 1/2, 1).
+* The EOM (eq. EOM2 with lambda and the friction/potential exponents exposed) is
+      dPi_i/deta = lap psi_i - (alpha/eta) Pi_i - lambda eta^beta psi_i (|psi|^2 - 1)
+  so each stage needs c_fric = alpha / eta_s and c_pot = lambda * eta_s^beta, the
+  power taken by repeated multiplication (beta is a small non-negative integer).
+"""
+from __future__ import annotations
+
+RK4_C = (0.0, 0.5, 0.5, 1.0)
+
+
+def level_dx(L: float, n0: int, lev: int) -> float:
+    return (L / n0) / float(1 << lev)
+
+
+def level_dt(L: float, n0: int, cfl: float, lev: int) -> float:
+    return cfl * level_dx(L, n0, lev)
+
+
+def level_time(eta0: float, k: int, dt: float) -> float:
+    """Time after k steps of size dt from eta0."""
+    return eta0 + float(k) * dt
+
+
+def int_power(x: float, beta: int) -> float:
+    p = 1.0
+    for _ in range(beta):
+        p = p * x
+    return p
+
+
+def stage_scalars(eta_n: float, dt: float, s: int, alpha: float, lam: float, beta: int):
+    """(eta_s, c_fric, c_pot) for stage s in 0..3."""
+    eta_s = eta_n + RK4_C[s] * dt
+    return eta_s, alpha / eta_s, lam * int_power(eta_s, beta)
+
+
+def rk4_weights(dt: float):
+    """(dt/6, dt/3, dt/2, dt): the classic RK4 stage and accumulation weights."""
+    return dt / 6.0, dt / 3.0, dt * 0.5, dt
