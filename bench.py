@@ -1,0 +1,156 @@
+#!/usr/bin/env python3
+"""Throughput of the per-level RK4 time step on one MI355X.
+
+Workload (default): one periodic level of 512^3 cells (L = 512, dx = 1), the axion-string
+EOM with lambda = 1, alpha = 2, beta = 2, classic RK4 with dt = dx/4 from eta = 0.1, the
+seeded Gaussian-random-field initial state; FP64 (``--prec f64``) or FP32 storage with
+FP64 accumulation (``--prec f32``).  A step is one sh_advance_level: four fused stage
+kernels with the periodic ghost copy between them.
+
+Prints one JSON line: cell-updates/s per RK stage (whole job), the roofline of the
+dominant kernel (the fused stage kernel, HBM-bound) from HIP events recorded around each
+of its launches inside the timed region, and the CPU oracle timed on a bounded sample of
+the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
+# algorithmic bytes per cell of the fused stage kernel, stages 1-4 (each array element
+# moved once: 12/20/20/12 values; FP32-mixed keeps the accumulator in FP64)
+STAGE_BYTES = {"f64": (96, 160, 160, 96), "f32": (64, 112, 112, 64)}
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def traffic_from_profiles(prec: str, n: int):
+    """HBM bytes per stage launch from the committed rocprofv3 counter summary, if it was
+    taken on the current kernel source; None otherwise."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"stage_kernel_{n}cubed_{prec}_traffic.json")
+    src = os.path.join(ROOT, "paper_2404_02950_amd", "csrc", "kernels.hip")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if rec.get("kernels_hip_sha256") != sha:
+        return None
+    return rec.get("bytes_per_launch_mean")
+
+
+def cpu_baseline(U0, n: int):
+    """The oracle's first RK4 stage on the full lattice, timed on this host."""
+    from oracle.level import rk4_stage
+    t0 = time.perf_counter()
+    rk4_stage(0, U0, U0, None, 0.1, 0.25, 1.0, 2.0, 1.0, 2)
+    dt = time.perf_counter() - t0
+    return {"value": n ** 3 / dt, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"one RK4 stage (stage 1) of the {n}^3 FP64 lattice, numpy oracle, "
+                      f"{dt:.1f} s on one host core"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--n", type=int, default=512)
+    ap.add_argument("--prec", choices=("f64", "f32"), default="f64")
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU path is a design, "
+              "not part of this build", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2404_02950_amd import shamr
+    from synth import random_state
+
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    n, K, W = args.n, args.steps, args.warmup
+    log(f"initial state {n}^3 (seed {args.seed})")
+    U0 = random_state(n, float(n), args.seed)
+    prec = shamr.SH_F64 if args.prec == "f64" else shamr.SH_F32
+    h = shamr.Hierarchy(n, float(n), 0.25, 0.1, 1.0, 2.0, 2, max_level=0, prec=prec)
+    h.set_layout(0, [(0, 0, 0, n - 1, n - 1, n - 1)])
+    h.write_dense(0, U0)
+    h.fill_ghosts(0)
+    h.sync()
+    log(f"warmup {W} steps")
+    for _ in range(W):
+        h.advance(0)
+    h.sync()
+    torch.cuda.synchronize()
+    log(f"timing {K} steps")
+    h.profile(True)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(h.stream)
+    for _ in range(K):
+        h.advance(0)
+    e1.record(h.stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    prof = h.profile_read()
+    h.profile(False)
+    e, bad = h.energy()
+    cells = n ** 3
+    value = cells * 4 * K / (ms / 1e3)
+    sb = STAGE_BYTES[args.prec]
+    st_ms = sum(prof[f"stage{s + 1}"][0] for s in range(4))
+    st_n = sum(prof[f"stage{s + 1}"][1] for s in range(4))
+    st_bytes = sum(sb[s] * cells * prof[f"stage{s + 1}"][1] for s in range(4))
+    achieved = st_bytes / (st_ms / 1e3) / 1e9
+    traffic = traffic_from_profiles(args.prec, n)
+    log(f"{ms / K:.3f} ms/step (event), wall {wall / K * 1e3:.3f} ms/step; stage kernel "
+        f"{st_ms / st_n:.3f} ms/launch, {achieved:.0f} GB/s; energy {e[3]:.6g}, nonfinite cells {bad}")
+    out = {
+        "metric": "cell-updates/s per RK stage",
+        "value": value,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": ms / K,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.prec,
+        "data": "synthetic",
+        "config": {"workload": f"single-level periodic {n}^3, RK4 + 7-point Laplacian, "
+                               f"{'FP64' if args.prec == 'f64' else 'FP32 storage / FP64 accumulation'}",
+                   "lattice": n, "dx": 1.0, "dt": 0.25, "eta0": 0.1, "lambda": 1.0, "seed": args.seed},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
+        "kernel_ms": {k: (v[0] / v[1] if v[1] else None) for k, v in prof.items() if v[1]},
+        "wall_ms_per_step": wall / K * 1e3,
+        "nonfinite_cells_at_end": bad,
+    }
+    if not args.no_cpu_baseline and args.prec == "f64":
+        log("cpu baseline (oracle, one stage)")
+        out["cpu_baseline"] = cpu_baseline(U0, n)
+    else:
+        out["cpu_baseline"] = None
+    h.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,214 @@
+/*
+ * shamr.h -- C-ABI of libshamr: the per-level AMR time step of a two-component scalar
+ * field (axion strings) on one AMD Instinct MI355X (gfx950).
+ *
+ * Paper: M. Buschmann, "sledgehamr: Simulating scalar fields with adaptive mesh
+ * refinement", arXiv:2404.02950.  The problem solved (section "Minimal example",
+ * eqs. EOM1/EOM2): on a periodic cube of n0^3 coarse cells of side L,
+ *
+ *     d psi_i / d eta = Pi_i
+ *     d Pi_i  / d eta = lap psi_i - (alpha/eta) Pi_i - lambda eta^beta psi_i (psi1^2 + psi2^2 - 1)
+ *
+ * (the paper's example has alpha = 2, beta = 2, lambda = 1), discretised with the
+ * 7-point Laplacian (appendix A, order 1) and classic RK4 (appendix E, integrator
+ * type 4) on a block-structured hierarchy of levels with dx_l = (L/n0)/2^l and
+ * dt_l = cfl * dx_l (section II, eq. dtscaling), advanced by Berger-Oliger subcycling
+ * (section II.A, Fig. 2).
+ *
+ * Conventions
+ * -----------
+ * - Box: six int32 (x_lo, y_lo, z_lo, x_hi, y_hi, z_hi), inclusive, in the index space of
+ *   its level ([0, n0*2^l) per axis).  Boxes of a level are disjoint; boxes of a level
+ *   l >= 1 have even lo and odd hi.
+ * - Dense state arrays exchanged with the library are float64, laid out box after box
+ *   (in the order given to sh_set_level_layout), each box as [comp][z][y][x] with
+ *   comp = (psi1, psi2, Pi1, Pi2), x fastest; with_ghosts = 1 adds the one-cell ghost
+ *   shell, i.e. (nz+2)(ny+2)(nx+2) values per component.
+ * - Buffer roles: 0 = U_n (the current state of the level), 1 and 2 = the RK stage
+ *   states, 3 = the state before the last step of the level (the "old" coarse state
+ *   used by time interpolation).
+ * - Every call returns an sh_status and never throws or aborts across the ABI; after a
+ *   non-OK status, sh_last_error() gives a message (thread-local).
+ * - All device work is queued asynchronously on the HIP stream given at creation.  Calls
+ *   that return host data (sh_tag_cells, sh_energy, sh_read_state to host, sh_sync)
+ *   synchronise that stream and report kernel failures as SH_EDEVICE.
+ * - One handle must not be used from two threads at once.
+ * - Device memory for the fields is owned by the caller: one arena per level, sized by
+ *   sh_arena_bytes, kept alive until the level's next layout or sh_hierarchy_destroy.
+ *   The library allocates only its small index tables (at layout time), never on the
+ *   stepping path.
+ */
+#ifndef SHAMR_H
+#define SHAMR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sh_hierarchy_s* sh_hierarchy;
+
+typedef enum {
+  SH_OK = 0,
+  SH_EINVAL = 1,  /* bad argument or layout */
+  SH_ENOMEM = 2,  /* arena too small / host or table allocation failed */
+  SH_ENEST = 3,   /* a fine level is not properly nested in its coarse level */
+  SH_ESTATE = 4,  /* call not valid in the current state (e.g. no layout yet) */
+  SH_EDEVICE = 5  /* a HIP call or kernel failed */
+} sh_status;
+
+typedef enum { SH_F64 = 0, SH_F32 = 1 } sh_prec;
+
+typedef struct {
+  int32_t n0;           /* coarse cells per axis (amr.coarse_level_grid_size) */
+  double L;             /* box length (sim.L) */
+  double cfl;           /* dt_l / dx_l (sim.cfl) */
+  double eta0;          /* start time (sim.t_start); level time = eta0 + k_l * dt_l */
+  double lambda;        /* potential strength */
+  double alpha_fric;    /* friction coefficient: the -(alpha/eta) Pi term */
+  int32_t beta_pot;     /* potential time exponent, >= 0: lambda * eta^beta */
+  int32_t max_level;    /* finest level allowed (amr.max_refinement_levels) */
+  int32_t blocking_factor;  /* box sides are multiples of it (amr.blocking_factor) */
+  int32_t max_box;      /* largest box side produced by sh_cluster_tags */
+  int32_t n_error_buf;  /* tag buffer width in cells (amr.n_error_buf) */
+  int32_t prec;         /* sh_prec: SH_F64, or SH_F32 = float32 storage and stencil,
+                           float64 time, accumulator and reductions */
+} sh_params;
+
+/* Device bytes needed for the arena of a level with the given boxes.  Returns 0 for
+   invalid arguments. */
+size_t sh_arena_bytes(const sh_params* p, int32_t lev, int32_t nboxes, const int32_t* boxes);
+
+/* Create a hierarchy.  `hip_stream` is a hipStream_t (NULL = default stream) that all
+   device work of this hierarchy is queued on.  Errors: SH_EINVAL (n0 < 1, L or cfl not
+   positive, beta < 0, max_level < 0 or > 15, blocking_factor < 2, prec not 0/1),
+   SH_EDEVICE (no HIP device). */
+sh_status sh_hierarchy_create(const sh_params* p, void* hip_stream, sh_hierarchy* out);
+
+/* Set, change or remove the box layout of level `lev` (section II: boxes whose sides
+   are multiples of the blocking factor; section II.C: proper nesting).
+   - lev == 0: the boxes must tile the whole periodic domain.  Values are unset until
+     sh_write_state (unless a previous level-0 layout existed: its values are kept).
+   - lev == number of levels (a new level): valid cells are interpolated from level
+     lev-1 (linear conservative, all 4 components) and the ghost cells filled; the level
+     starts at the time of level lev-1.
+   - an existing level: cells valid in the old layout keep their values, the others are
+     interpolated from level lev-1 (a regrid); ghosts are refilled.
+   - nboxes == 0 removes level lev and every finer level.
+   `arena` is caller-owned device memory of at least sh_arena_bytes(...) bytes; the old
+   arena of the level must stay valid until the work queued by this call has run.
+   Errors: SH_EINVAL (bad box, overlap, level 0 not covering, lev > max_level or
+   > number of levels), SH_ENOMEM (arena too small), SH_ENEST (not nested in lev-1). */
+sh_status sh_set_level_layout(sh_hierarchy h, int32_t lev, int32_t nboxes, const int32_t* boxes,
+                              void* arena, size_t arena_bytes);
+
+/* Copy a dense float64 state (layout above) into buffer role `role` of level `lev`.
+   `src` is host memory (src_is_device = 0, the call copies it before returning) or
+   device memory (queued on the stream).  Errors: SH_EINVAL, SH_ESTATE (no layout). */
+sh_status sh_write_state(sh_hierarchy h, int32_t lev, int32_t role, const double* src, int32_t src_is_device,
+                         int32_t with_ghosts);
+
+/* Copy buffer role `role` of level `lev` out as a dense float64 state.  Host `dst`
+   synchronises the stream. */
+sh_status sh_read_state(sh_hierarchy h, int32_t lev, int32_t role, double* dst, int32_t dst_is_device,
+                        int32_t with_ghosts);
+
+/* Ghost fill of the psi components of buffer `role` of level `lev` (section II.A): copies
+   from the level's own boxes and periodic images, then, for lev >= 1, the remaining
+   ghost cells by linear conservative interpolation (appendix E, interpolation type 1)
+   of the coarse states at the start (role 3) and end (role 0) of the coarse step,
+   linear in time with alpha = alpha_num / 4 in [0, 4]. */
+sh_status sh_fill_ghosts(sh_hierarchy h, int32_t lev, int32_t role, int32_t alpha_num);
+
+/* One RK4 step of level `lev` by dt_lev (section II.A, Fig. 2): stage 1, then ghost fill
+   and stage for stages 2-4 (alpha = (substep + c_s)/2), then the same-level ghost copy of
+   the new state and, for lev >= 1 and substep == 0, its coarse/fine ghost fill at
+   alpha = 1/2 (a substep-1 step ends in the synchronisation, sh_average_down).
+   `substep` in {0, 1} is which half of the parent's step this is (ignored for lev 0).
+   Does not recurse into finer levels: the caller composes the subcycling order. */
+sh_status sh_advance_level(sh_hierarchy h, int32_t lev, int32_t substep);
+
+/* Synchronisation of levels fine_lev and fine_lev-1 (section II.A): average the fine
+   level's 2x2x2 children onto every covered coarse cell (all components), refresh the
+   coarse level's same-level ghosts, then refill the fine ghosts with no temporal
+   interpolation (alpha = 1).  Both levels must be at the same time. */
+sh_status sh_average_down(sh_hierarchy h, int32_t fine_lev);
+
+/* Problem-specific tagging (section "Problem-specific cell tagging"): a valid cell of
+   level `lev` is tagged iff the phase of psi1 + i psi2 winds around any of its 12
+   incident plaquettes (crossing-number rule).  Fills the level's ghosts first.
+   Writes `mask_dev` (device, one byte per valid cell in the dense box order, may be
+   NULL), and up to `cap` tagged cells as global (x, y, z) int32 triplets to host
+   `idx_host` (may be NULL); `*ntag` receives the total count.  Synchronises. */
+sh_status sh_tag_cells(sh_hierarchy h, int32_t lev, uint8_t* mask_dev, int32_t* idx_host, int64_t cap,
+                       int64_t* ntag);
+
+/* Composite energy over all levels, counting only cells not covered by a finer level
+   (appendix B's convergence measure for this field): e_host[4] = {kinetic, gradient,
+   potential, total}, float64, with forward-difference gradients and potential
+   lambda eta^beta / 4 (|psi|^2 - 1)^2.  `nonfinite` (may be NULL) receives the number
+   of counted cells holding a non-finite value.  Synchronises. */
+sh_status sh_energy(sh_hierarchy h, double* e_host, int64_t* nonfinite);
+
+/* Right-hand side f(U_n) of eqs. EOM1/EOM2 at the level's current time, with the
+   current ghost values, into device `out_dev` (dense float64 layout, no ghosts). */
+sh_status sh_eval_rhs(sh_hierarchy h, int32_t lev, double* out_dev);
+
+/* Level bookkeeping: steps taken, current time eta0 + k dt, boxes and valid cells. */
+sh_status sh_level_info(sh_hierarchy h, int32_t lev, int64_t* k, double* eta, int32_t* nboxes, int64_t* ncells);
+
+/* Number of levels with a layout. */
+int32_t sh_num_levels(sh_hierarchy h);
+
+/* Berger-Rigoutsos clustering on the host (section II.C, global regrid): from `ntag`
+   tagged cells of level `lev` (global (x, y, z) triplets) produce boxes of level lev+1
+   that cover the tags grown by n_error_buf cells, with sides multiples of the blocking
+   factor and at most max_box, properly nested in level lev's current layout (tags
+   whose refinement would break nesting are dropped).  Writes at most `cap` boxes to
+   `boxes_out` (6 int32 each) and the count to `*nboxes`; SH_ENOMEM if cap is too small
+   (the count is still written). */
+sh_status sh_cluster_tags(sh_hierarchy h, int32_t lev, int64_t ntag, const int32_t* tags, double efficiency,
+                          int32_t* boxes_out, int32_t cap, int32_t* nboxes);
+
+/* The same clustering without a hierarchy (host only, needs no GPU): tags of a level of
+   M^3 cells whose layout is `level_boxes` (nlevel_boxes == 0: the level covers the whole
+   domain, as level 0 does). */
+sh_status sh_cluster_boxes(int32_t M, int32_t nlevel_boxes, const int32_t* level_boxes, int32_t blocking_factor,
+                           int32_t max_box, int32_t n_error_buf, double efficiency, int64_t ntag,
+                           const int32_t* tags, int32_t* boxes_out, int32_t cap, int32_t* nboxes);
+
+/* Wait for all work queued by this hierarchy; SH_EDEVICE if any kernel failed. */
+sh_status sh_sync(sh_hierarchy h);
+
+sh_status sh_hierarchy_destroy(sh_hierarchy h);
+
+const char* sh_last_error(void);
+
+/* Stage scalars the device derives for `lev` at stage s (0..3) of the current step:
+   out[0..6] = {eta_s, c_fric, c_pot, dt/6, dt/3, dt/2, dt}.  Diagnostic. */
+sh_status sh_debug_stage_scalars(sh_hierarchy h, int32_t lev, int32_t s, double* out_host);
+
+/* Per-kernel timing (diagnostic).  sh_profile(h, 1) clears the totals and brackets every
+   launch that sh_advance_level and sh_average_down issue with HIP events on the
+   hierarchy's stream; sh_profile(h, 0) stops.  sh_profile_read fills ms[8] (summed
+   event time) and counts[8] (launches) per class: 0-3 = RK stage 1-4 kernel, 4 =
+   same-level ghost copy, 5 = coarse/fine ghost interpolation, 6 = average down,
+   7 = unused.  Reading synchronises the stream. */
+sh_status sh_profile(sh_hierarchy h, int32_t enable);
+sh_status sh_profile_read(sh_hierarchy h, double* ms, int64_t* counts);
+
+/* Orchestration trace (diagnostic).  sh_trace(h, 1) clears and starts recording every
+   operation that sh_advance_level and sh_average_down issue, as 4 int32 each
+   (op, level, a, b): op 1 = RK stage a (0..3) of substep b; op 2 = same-level ghost copy
+   of role a; op 3 = coarse/fine ghost interpolation of role a at alpha_num b; op 4 =
+   average down of level `level` onto level-1.  sh_trace(h, 0) stops.  sh_trace_read
+   copies up to `cap` records to `out` and returns the number recorded. */
+sh_status sh_trace(sh_hierarchy h, int32_t enable);
+int64_t sh_trace_read(sh_hierarchy h, int32_t* out, int64_t cap);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SHAMR_H */

@@ -1,0 +1,1009 @@
+// Host runtime of libshamr: hierarchy, box layouts, copy/interpolation/averaging plans,
+// the level step sequence and the C-ABI declared in include/shamr.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "shamr.h"
+#include "sh_geom.h"
+#include "sh_internal.h"
+#include "sh_launch.h"
+
+static thread_local std::string g_err;
+
+static sh_status fail(sh_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+#define HIPCHK(call)                                                                   \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return fail(SH_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_));      \
+  } while (0)
+
+#define LAUNCHCHK()                                                                    \
+  do {                                                                                 \
+    hipError_t e_ = hipGetLastError();                                                 \
+    if (e_ != hipSuccess) return fail(SH_EDEVICE, std::string("kernel launch: ") + hipGetErrorString(e_)); \
+  } while (0)
+
+// ---------------------------------------------------------------------------------
+// Device arrays for index tables (allocated at layout time only).
+// ---------------------------------------------------------------------------------
+template <typename T>
+struct DevArr {
+  T* p = nullptr;
+  size_t n = 0;
+  hipError_t upload(const std::vector<T>& v) {
+    release();
+    n = v.size();
+    if (n == 0) return hipSuccess;
+    hipError_t e = hipMalloc((void**)&p, n * sizeof(T));
+    if (e != hipSuccess) { p = nullptr; n = 0; return e; }
+    return hipMemcpy(p, v.data(), n * sizeof(T), hipMemcpyHostToDevice);
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+};
+
+template <typename S>
+struct SegPlan {
+  DevArr<S> segs;
+  DevArr<SegBlock> blocks;
+  long long ncells = 0;
+  int nblocks() const { return (int)blocks.n; }
+  hipError_t upload(const std::vector<S>& v, const std::vector<long long>& ncell_per_seg) {
+    std::vector<SegBlock> b;
+    ncells = 0;
+    for (size_t i = 0; i < v.size(); ++i) {
+      for (long long s = 0; s < ncell_per_seg[i]; s += SH_BLOCK) b.push_back(SegBlock{(int)i, (int)s});
+      ncells += ncell_per_seg[i];
+    }
+    hipError_t e = segs.upload(v);
+    if (e != hipSuccess) return e;
+    return blocks.upload(b);
+  }
+  void release() {
+    segs.release();
+    blocks.release();
+    ncells = 0;
+  }
+};
+
+// ---------------------------------------------------------------------------------
+// Level layout arithmetic (shared by sh_arena_bytes and sh_set_level_layout).
+// ---------------------------------------------------------------------------------
+struct LayoutGeom {
+  int esize;                        // bytes of a stored value (8 or 4)
+  int xoff;                         // elements before x = 0 in a row
+  std::vector<long long> box_off;   // element offset of each box block
+  std::vector<int> px;              // per-box x pitch
+  std::vector<long long> cs;        // per-box component stride
+  long long E = 0;                  // elements per slot
+  long long nvalid = 0;
+  std::vector<Tile> tiles;
+  // arena byte offsets
+  size_t off_slot[3], off_acc, off_mask, off_cov, off_cnt, off_toff, off_part, off_eout, total;
+};
+
+static long long round_up(long long v, long long a) { return (v + a - 1) / a * a; }
+
+static int tile_zc_default(long long cells) {
+  const char* env = std::getenv("SHAMR_TILE_Z");
+  if (env) {
+    int v = std::atoi(env);
+    if (v >= 1 && v <= 1024) return v;
+  }
+  long long zc = 64;
+  while (zc > 4 && cells / (64LL * zc) < 16384) zc >>= 1;
+  return (int)zc;
+}
+
+static void make_geom(int prec, const std::vector<IBox>& boxes, LayoutGeom& g) {
+  g.esize = prec == SH_F64 ? 8 : 4;
+  g.xoff = 64 / g.esize;
+  g.box_off.clear();
+  g.px.clear();
+  g.cs.clear();
+  g.tiles.clear();
+  g.E = 0;
+  g.nvalid = 0;
+  for (const IBox& b : boxes) {
+    const int nx = b.size(0), ny = b.size(1), nz = b.size(2);
+    const int px = (int)round_up(g.xoff + nx + 1, g.xoff);
+    const long long cs = round_up((long long)px * (ny + 2) * (nz + 2), 64);
+    g.box_off.push_back(g.E);
+    g.px.push_back(px);
+    g.cs.push_back(cs);
+    g.E += 4 * cs;
+    g.nvalid += (long long)nx * ny * nz;
+  }
+  const int zc = tile_zc_default(g.nvalid);
+  for (size_t bi = 0; bi < boxes.size(); ++bi) {
+    const IBox& b = boxes[bi];
+    const int nx = b.size(0), ny = b.size(1), nz = b.size(2);
+    int txs = 0;
+    while ((1 << txs) < nx && txs < 6) ++txs;
+    const int TX = 1 << txs, TY = 64 / TX;
+    for (int z0 = 0; z0 < nz; z0 += zc)
+      for (int y0 = 0; y0 < ny; y0 += TY)
+        for (int x0 = 0; x0 < nx; x0 += TX) {
+          Tile t;
+          t.box = (int)bi;
+          t.xy = x0 | (y0 << 16);
+          t.zz = z0 | (std::min(zc, nz - z0) << 16);
+          t.txs = txs;
+          g.tiles.push_back(t);
+        }
+  }
+  const long long nt = (long long)g.tiles.size();
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t r = o;
+    o = (size_t)round_up((long long)(o + bytes), 256);
+    return r;
+  };
+  for (int s = 0; s < 3; ++s) g.off_slot[s] = take((size_t)g.E * g.esize);
+  g.off_acc = take((size_t)g.E * 8);
+  g.off_mask = take((size_t)g.nvalid);
+  g.off_cov = take((size_t)g.nvalid);
+  g.off_cnt = take((size_t)nt * 4);
+  g.off_toff = take((size_t)(nt + 1) * 8);
+  g.off_part = take((size_t)nt * sizeof(EnergyPartial));
+  g.off_eout = take(4 * 8);
+  g.total = o + 256;  // slack for aligning the arena base
+}
+
+// ---------------------------------------------------------------------------------
+// Hierarchy
+// ---------------------------------------------------------------------------------
+struct Level {
+  int M = 0;
+  double dx = 0, dt = 0;
+  std::vector<IBox> boxes;
+  LayoutGeom g;
+  char* base = nullptr;  // aligned arena base
+  std::vector<BoxDev> hbox;
+  DevArr<BoxDev> dbox;
+  DevArr<Tile> tiles;
+  DevArr<long long> xoff_valid, xoff_ghost, rhs_off;
+  SegPlan<CopySeg> a1;
+  SegPlan<InterpSeg> a2;  // coarse -> this level's ghosts
+  SegPlan<AvgSeg> a5;     // this level -> coarse level
+  long long k = 0;        // host mirror of the device step counter
+  bool stale = false;     // coarse level changed; layout must be set again
+  int* d_idx = nullptr;   // tag compaction output (grown on demand)
+  long long d_idx_cap = 0;
+  BoxBins bins;
+
+  uint8_t* mask() const { return (uint8_t*)(base + g.off_mask); }
+  uint8_t* covered() const { return (uint8_t*)(base + g.off_cov); }
+  int* tile_count() const { return (int*)(base + g.off_cnt); }
+  long long* tile_off() const { return (long long*)(base + g.off_toff); }
+  EnergyPartial* epart() const { return (EnergyPartial*)(base + g.off_part); }
+  double* eout() const { return (double*)(base + g.off_eout); }
+  int ntiles() const { return (int)g.tiles.size(); }
+
+  void release_tables() {
+    dbox.release();
+    tiles.release();
+    xoff_valid.release();
+    xoff_ghost.release();
+    rhs_off.release();
+    a1.release();
+    a2.release();
+    a5.release();
+  }
+  void release() {
+    release_tables();
+    if (d_idx) (void)hipFree(d_idx);
+    d_idx = nullptr;
+    d_idx_cap = 0;
+  }
+};
+
+struct sh_hierarchy_s {
+  sh_params p;
+  hipStream_t st = nullptr;
+  LevelScal* d_ls = nullptr;  // 16 levels
+  double* d_dbg = nullptr;
+  std::vector<Level> lev;
+  bool tracing = false;
+  std::vector<int32_t> trace;  // (op, level, a, b) records
+  // per-kernel-class event timing: pairs of events around launches
+  bool profiling = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  std::vector<int> ev_class;  // class of each recorded pair
+  double prof_ms[8] = {0};
+  long long prof_n[8] = {0};
+  hipEvent_t prof_begin() {
+    if (!profiling) return nullptr;
+    if (ev_used + 2 > ev_pool.size()) {
+      for (int i = 0; i < 64; ++i) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        ev_pool.push_back(e);
+      }
+    }
+    hipEvent_t e = ev_pool[ev_used];
+    (void)hipEventRecord(e, st);
+    return e;
+  }
+  void prof_end(hipEvent_t b, int cls) {
+    if (!profiling || !b) return;
+    (void)hipEventRecord(ev_pool[ev_used + 1], st);
+    ev_used += 2;
+    ev_class.push_back(cls);
+  }
+  void prof_collect() {
+    if (ev_used == 0) return;
+    (void)hipStreamSynchronize(st);
+    for (size_t i = 0; i < ev_class.size(); ++i) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, ev_pool[2 * i], ev_pool[2 * i + 1]) == hipSuccess) {
+        prof_ms[ev_class[i]] += ms;
+        prof_n[ev_class[i]] += 1;
+      }
+    }
+    ev_used = 0;
+    ev_class.clear();
+  }
+  void rec(int op, int l, int a, int b) {
+    if (!tracing) return;
+    trace.push_back(op);
+    trace.push_back(l);
+    trace.push_back(a);
+    trace.push_back(b);
+  }
+};
+
+static double level_dx(const sh_params& p, int l) { return (p.L / (double)p.n0) / (double)(1 << l); }
+
+static LevelScal make_ls(const sh_params& p, int l, long long k) {
+  LevelScal s;
+  s.dx = level_dx(p, l);
+  s.dt = p.cfl * s.dx;
+  s.eta0 = p.eta0;
+  s.alpha = p.alpha_fric;
+  s.lam = p.lambda;
+  s.inv_dx2 = 1.0 / (s.dx * s.dx);
+  s.beta = p.beta_pot;
+  s.pad = 0;
+  s.k = k;
+  return s;
+}
+
+static sh_status upload_ls(sh_hierarchy h, int l) {
+  LevelScal s = make_ls(h->p, l, h->lev[l].k);
+  HIPCHK(hipMemcpyAsync(h->d_ls + l, &s, sizeof(s), hipMemcpyHostToDevice, h->st));
+  HIPCHK(hipStreamSynchronize(h->st));
+  return SH_OK;
+}
+
+static sh_status parse_boxes(const sh_params& p, int l, int nboxes, const int32_t* in, std::vector<IBox>& out) {
+  out.clear();
+  if (nboxes < 0 || (nboxes > 0 && !in)) return fail(SH_EINVAL, "bad box array");
+  const int M = p.n0 << l;
+  for (int i = 0; i < nboxes; ++i) {
+    IBox b;
+    for (int d = 0; d < 3; ++d) {
+      b.lo[d] = in[6 * i + d];
+      b.hi[d] = in[6 * i + 3 + d];
+      if (b.lo[d] < 0 || b.hi[d] >= M || b.lo[d] > b.hi[d])
+        return fail(SH_EINVAL, "box " + std::to_string(i) + " outside the level domain");
+      if (b.size(d) > 32767) return fail(SH_EINVAL, "box side too large");
+      if (l > 0 && ((b.lo[d] & 1) || !(b.hi[d] & 1)))
+        return fail(SH_EINVAL, "box " + std::to_string(i) + " of a refined level must start even and end odd");
+    }
+    out.push_back(b);
+  }
+  // disjointness
+  BoxBins bins;
+  bins.build(out, M);
+  for (int i = 0; i < nboxes; ++i) {
+    bool bad = false;
+    bins.query(out[i], [&](int j) {
+      if (j != i && !isect(out[i], out[j]).empty()) bad = true;
+    });
+    if (bad) return fail(SH_EINVAL, "boxes overlap");
+  }
+  return SH_OK;
+}
+
+// ---------------------------------------------------------------------------------
+// Plans
+// ---------------------------------------------------------------------------------
+static void build_a1(const Level& L, std::vector<CopySeg>& segs, std::vector<long long>& nc) {
+  segs.clear();
+  nc.clear();
+  for (int d = 0; d < (int)L.boxes.size(); ++d) {
+    const IBox& D = L.boxes[d];
+    const IBox G = grow(D, 1);
+    for_images(G, L.M, L.bins, [&](int s, const int sh[3]) {
+      if (s == d && sh[0] == 0 && sh[1] == 0 && sh[2] == 0) return;
+      const IBox img = shift(L.boxes[s], sh[0] * L.M, sh[1] * L.M, sh[2] * L.M);
+      const IBox R = isect(G, img);
+      if (R.empty()) return;
+      CopySeg c;
+      c.dbox = d;
+      c.sbox = s;
+      for (int k = 0; k < 3; ++k) {
+        c.dlo[k] = R.lo[k] - D.lo[k];
+        c.slo[k] = R.lo[k] - img.lo[k];
+        c.n[k] = R.size(k);
+      }
+      c.pad = 0;
+      segs.push_back(c);
+      nc.push_back(R.volume());
+    });
+  }
+}
+
+// Parents of fine region R (fine-global coordinates, possibly one cell outside the
+// domain) among the coarse boxes; appends InterpSegs for fine box d.  Returns false if
+// some cell (or the one-cell slope support of its parent) is not covered.
+static bool interp_segs(const Level& F, const Level& C, int d, const IBox& R, std::vector<InterpSeg>& segs,
+                        std::vector<long long>& nc) {
+  const IBox Pc = coarsen(R);
+  long long covered = 0;
+  for_images(Pc, C.M, C.bins, [&](int c, const int sh[3]) {
+    const IBox img = shift(C.boxes[c], sh[0] * C.M, sh[1] * C.M, sh[2] * C.M);
+    const IBox Q = isect(Pc, img);
+    if (Q.empty()) return;
+    const IBox sub = isect(R, refine(Q));
+    if (sub.empty()) return;
+    InterpSeg s;
+    s.fbox = d;
+    s.cbox = c;
+    for (int k = 0; k < 3; ++k) {
+      s.flo[k] = sub.lo[k] - F.boxes[d].lo[k];
+      s.n[k] = sub.size(k);
+      s.fg0[k] = sub.lo[k];
+      s.cshift[k] = -img.lo[k];
+    }
+    segs.push_back(s);
+    nc.push_back(sub.volume());
+    covered += sub.volume();
+  });
+  if (covered != R.volume()) return false;
+  const IBox sup = grow(Pc, 1);
+  return covered_volume(sup, C.M, C.bins, C.boxes) == sup.volume();
+}
+
+static bool build_a2(const Level& F, const Level& C, std::vector<InterpSeg>& segs, std::vector<long long>& nc) {
+  segs.clear();
+  nc.clear();
+  for (int d = 0; d < (int)F.boxes.size(); ++d) {
+    const IBox& D = F.boxes[d];
+    std::vector<IBox> shell;
+    subtract(grow(D, 1), D, shell);
+    for (const IBox& P : shell) {
+      std::vector<IBox> rem{P};
+      for_images(P, F.M, F.bins, [&](int s, const int sh[3]) {
+        const IBox img = shift(F.boxes[s], sh[0] * F.M, sh[1] * F.M, sh[2] * F.M);
+        std::vector<IBox> nxt;
+        for (const IBox& r : rem) subtract(r, img, nxt);
+        rem.swap(nxt);
+      });
+      for (const IBox& R : rem)
+        if (!interp_segs(F, C, d, R, segs, nc)) return false;
+    }
+  }
+  return true;
+}
+
+static bool build_a5(const Level& F, const Level& C, std::vector<AvgSeg>& segs, std::vector<long long>& nc) {
+  segs.clear();
+  nc.clear();
+  for (int d = 0; d < (int)F.boxes.size(); ++d) {
+    const IBox& D = F.boxes[d];
+    const IBox Pc = coarsen(D);
+    long long covered = 0;
+    C.bins.query(Pc, [&](int c) {
+      const IBox Q = isect(Pc, C.boxes[c]);
+      if (Q.empty()) return;
+      AvgSeg s;
+      s.cbox = c;
+      s.fbox = d;
+      for (int k = 0; k < 3; ++k) {
+        s.clo[k] = Q.lo[k] - C.boxes[c].lo[k];
+        s.n[k] = Q.size(k);
+        s.f0[k] = 2 * Q.lo[k] - D.lo[k];
+      }
+      s.pad = 0;
+      segs.push_back(s);
+      nc.push_back(Q.volume());
+      covered += Q.volume();
+    });
+    if (covered != Pc.volume()) return false;
+  }
+  return true;
+}
+
+static sh_status build_links(sh_hierarchy h, int l) {
+  // plans between level l-1 (coarse) and l (fine), and the coarse level's covered mask
+  Level& F = h->lev[l];
+  Level& C = h->lev[l - 1];
+  std::vector<InterpSeg> is;
+  std::vector<AvgSeg> as;
+  std::vector<long long> nc, nc5;
+  if (!build_a2(F, C, is, nc) || !build_a5(F, C, as, nc5)) {
+    F.stale = true;
+    F.a2.release();
+    F.a5.release();
+    return fail(SH_ENEST, "level " + std::to_string(l) + " is not nested in level " + std::to_string(l - 1));
+  }
+  HIPCHK(F.a2.upload(is, nc));
+  HIPCHK(F.a5.upload(as, nc5));
+  F.stale = false;
+  HIPCHK(hipMemsetAsync(C.covered(), 0, (size_t)C.g.nvalid, h->st));
+  sh_launch_mark_covered(F.a5.segs.p, F.a5.blocks.p, F.a5.nblocks(), C.dbox.p, C.covered(), h->st);
+  LAUNCHCHK();
+  return SH_OK;
+}
+
+// ---------------------------------------------------------------------------------
+// Level step pieces
+// ---------------------------------------------------------------------------------
+static sh_status same_level_fill(sh_hierarchy h, int l, int role) {
+  Level& L = h->lev[l];
+  h->rec(2, l, role, 0);
+  hipEvent_t ev = h->prof_begin();
+  sh_launch_ghost_copy(h->p.prec, L.a1.segs.p, L.a1.blocks.p, L.a1.nblocks(), L.dbox.p, role, h->st);
+  h->prof_end(ev, 4);
+  LAUNCHCHK();
+  return SH_OK;
+}
+
+static sh_status coarse_fine_fill(sh_hierarchy h, int l, int role, int anum) {
+  if (l == 0) return SH_OK;
+  Level& L = h->lev[l];
+  h->rec(3, l, role, anum);
+  hipEvent_t ev = h->prof_begin();
+  sh_launch_ghost_interp(h->p.prec, L.a2.segs.p, L.a2.blocks.p, L.a2.nblocks(), L.dbox.p, h->lev[l - 1].dbox.p, role,
+                         anum, 2, h->st);
+  h->prof_end(ev, 5);
+  LAUNCHCHK();
+  return SH_OK;
+}
+
+static sh_status fill(sh_hierarchy h, int l, int role, int anum) {
+  sh_status s = same_level_fill(h, l, role);
+  if (s != SH_OK) return s;
+  return coarse_fine_fill(h, l, role, anum);
+}
+
+static sh_status check_level(sh_hierarchy h, int l) {
+  if (!h) return fail(SH_EINVAL, "null handle");
+  if (l < 0 || l >= (int)h->lev.size()) return fail(SH_EINVAL, "no such level");
+  if (h->lev[l].stale) return fail(SH_ESTATE, "level layout must be set again after its coarse level changed");
+  return SH_OK;
+}
+
+// ---------------------------------------------------------------------------------
+// C-ABI
+// ---------------------------------------------------------------------------------
+extern "C" {
+
+const char* sh_last_error(void) { return g_err.c_str(); }
+
+static sh_status check_params(const sh_params* p) {
+  if (!p) return fail(SH_EINVAL, "null params");
+  if (p->n0 < 1 || !(p->L > 0) || !(p->cfl > 0) || p->beta_pot < 0 || p->max_level < 0 || p->max_level > 15 ||
+      p->blocking_factor < 2 || (p->blocking_factor & 1) || p->max_box < p->blocking_factor || p->n_error_buf < 0 ||
+      (p->prec != SH_F64 && p->prec != SH_F32))
+    return fail(SH_EINVAL, "invalid parameters");
+  if ((long long)p->n0 << p->max_level > 32767) return fail(SH_EINVAL, "finest level too large");
+  return SH_OK;
+}
+
+size_t sh_arena_bytes(const sh_params* p, int32_t lev, int32_t nboxes, const int32_t* boxes) {
+  if (check_params(p) != SH_OK || lev < 0 || lev > p->max_level) return 0;
+  std::vector<IBox> b;
+  if (parse_boxes(*p, lev, nboxes, boxes, b) != SH_OK) return 0;
+  LayoutGeom g;
+  make_geom(p->prec, b, g);
+  return g.total;
+}
+
+sh_status sh_hierarchy_create(const sh_params* p, void* hip_stream, sh_hierarchy* out) {
+  if (!out) return fail(SH_EINVAL, "null output");
+  *out = nullptr;
+  sh_status s = check_params(p);
+  if (s != SH_OK) return s;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(SH_EDEVICE, "no HIP device");
+  sh_hierarchy h = new (std::nothrow) sh_hierarchy_s;
+  if (!h) return fail(SH_ENOMEM, "host allocation failed");
+  h->p = *p;
+  h->st = (hipStream_t)hip_stream;
+  if (hipMalloc((void**)&h->d_ls, 16 * sizeof(LevelScal)) != hipSuccess ||
+      hipMalloc((void**)&h->d_dbg, 16 * sizeof(double)) != hipSuccess) {
+    if (h->d_ls) (void)hipFree(h->d_ls);
+    delete h;
+    return fail(SH_EDEVICE, "device allocation of level scalars failed");
+  }
+  *out = h;
+  return SH_OK;
+}
+
+sh_status sh_hierarchy_destroy(sh_hierarchy h) {
+  if (!h) return SH_OK;
+  (void)hipStreamSynchronize(h->st);
+  for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
+  for (Level& L : h->lev) L.release();
+  if (h->d_ls) (void)hipFree(h->d_ls);
+  if (h->d_dbg) (void)hipFree(h->d_dbg);
+  delete h;
+  return SH_OK;
+}
+
+int32_t sh_num_levels(sh_hierarchy h) { return h ? (int32_t)h->lev.size() : 0; }
+
+static sh_status set_box_tables(sh_hierarchy h, int l, Level& L) {
+  L.hbox.clear();
+  std::vector<long long> xv{0}, xg{0}, ro{0};
+  long long moff = 0;
+  for (size_t i = 0; i < L.boxes.size(); ++i) {
+    const IBox& b = L.boxes[i];
+    BoxDev d;
+    for (int s = 0; s < 3; ++s) d.slot[s] = L.base + L.g.off_slot[s] + (size_t)L.g.box_off[i] * L.g.esize;
+    d.acc = (double*)(L.base + L.g.off_acc) + L.g.box_off[i];
+    d.ls = h->d_ls + l;
+    d.cs = L.g.cs[i];
+    d.nx = b.size(0);
+    d.ny = b.size(1);
+    d.nz = b.size(2);
+    d.px = L.g.px[i];
+    d.py = d.ny + 2;
+    for (int k = 0; k < 3; ++k) d.lo[k] = b.lo[k];
+    if (moff > 0x7fffffffLL) return fail(SH_EINVAL, "level too large for 32-bit mask offsets");
+    d.mask_off = (int)moff;
+    d.pad = 0;
+    moff += (long long)d.nx * d.ny * d.nz;
+    L.hbox.push_back(d);
+    xv.push_back(xv.back() + 4LL * d.nx * d.ny * d.nz);
+    xg.push_back(xg.back() + 4LL * (d.nx + 2) * (d.ny + 2) * (d.nz + 2));
+    ro.push_back(ro.back() + 4LL * d.nx * d.ny * d.nz);
+  }
+  ro.pop_back();
+  HIPCHK(L.dbox.upload(L.hbox));
+  HIPCHK(L.tiles.upload(L.g.tiles));
+  HIPCHK(L.xoff_valid.upload(xv));
+  HIPCHK(L.xoff_ghost.upload(xg));
+  HIPCHK(L.rhs_off.upload(ro));
+  return SH_OK;
+}
+
+sh_status sh_set_level_layout(sh_hierarchy h, int32_t l, int32_t nboxes, const int32_t* boxes, void* arena,
+                              size_t arena_bytes) {
+  if (!h) return fail(SH_EINVAL, "null handle");
+  const sh_params& p = h->p;
+  if (l < 0 || l > p.max_level || l > (int)h->lev.size()) return fail(SH_EINVAL, "bad level");
+  if (nboxes == 0) {
+    if (l == 0) return fail(SH_EINVAL, "level 0 needs boxes");
+    HIPCHK(hipStreamSynchronize(h->st));
+    for (size_t i = l; i < h->lev.size(); ++i) h->lev[i].release();
+    h->lev.resize(l);
+    if (l >= 1) HIPCHK(hipMemsetAsync(h->lev[l - 1].covered(), 0, (size_t)h->lev[l - 1].g.nvalid, h->st));
+    return SH_OK;
+  }
+  if (l > 0 && h->lev[l - 1].stale) return fail(SH_ESTATE, "coarse level layout is stale");
+  Level N;
+  N.M = p.n0 << l;
+  N.dx = level_dx(p, l);
+  N.dt = p.cfl * N.dx;
+  sh_status s = parse_boxes(p, l, nboxes, boxes, N.boxes);
+  if (s != SH_OK) return s;
+  if (l == 0) {
+    long long v = 0;
+    for (auto& b : N.boxes) v += b.volume();
+    if (v != (long long)N.M * N.M * N.M) return fail(SH_EINVAL, "level 0 boxes must cover the domain");
+  }
+  make_geom(p.prec, N.boxes, N.g);
+  if (!arena || arena_bytes < N.g.total) return fail(SH_ENOMEM, "arena smaller than sh_arena_bytes");
+  N.base = (char*)round_up((long long)(uintptr_t)arena, 256);
+  N.bins.build(N.boxes, N.M);
+  const bool existing = l < (int)h->lev.size();
+  N.k = existing ? h->lev[l].k : (l == 0 ? 0 : 2 * h->lev[l - 1].k);
+
+  s = set_box_tables(h, l, N);
+  if (s != SH_OK) { N.release(); return s; }
+  {
+    std::vector<CopySeg> cs;
+    std::vector<long long> nc;
+    build_a1(N, cs, nc);
+    hipError_t e = N.a1.upload(cs, nc);
+    if (e != hipSuccess) { N.release(); return fail(SH_EDEVICE, "table upload failed"); }
+  }
+  // nesting and interpolation plans against the coarse level
+  SegPlan<InterpSeg> fresh;  // valid cells to interpolate from the coarse level
+  if (l > 0) {
+    const Level& C = h->lev[l - 1];
+    std::vector<InterpSeg> is;
+    std::vector<long long> nc;
+    std::vector<IBox> rem_all;
+    for (int d = 0; d < (int)N.boxes.size(); ++d) {
+      std::vector<IBox> rem{N.boxes[d]};
+      if (existing) {
+        const Level& O = h->lev[l];
+        O.bins.query(N.boxes[d], [&](int o) {
+          std::vector<IBox> nxt;
+          for (const IBox& r : rem) subtract(r, O.boxes[o], nxt);
+          rem.swap(nxt);
+        });
+      }
+      for (const IBox& R : rem)
+        if (!interp_segs(N, C, d, R, is, nc)) {
+          N.release();
+          return fail(SH_ENEST, "level " + std::to_string(l) + " not nested in level " + std::to_string(l - 1));
+        }
+    }
+    if (fresh.upload(is, nc) != hipSuccess) { N.release(); return fail(SH_EDEVICE, "table upload failed"); }
+  }
+  // copy plan from the old layout
+  SegPlan<CopySeg> keep;
+  if (existing) {
+    const Level& O = h->lev[l];
+    std::vector<CopySeg> cs;
+    std::vector<long long> nc;
+    for (int d = 0; d < (int)N.boxes.size(); ++d)
+      O.bins.query(N.boxes[d], [&](int o) {
+        const IBox R = isect(N.boxes[d], O.boxes[o]);
+        if (R.empty()) return;
+        CopySeg c;
+        c.dbox = d;
+        c.sbox = o;
+        for (int k = 0; k < 3; ++k) {
+          c.dlo[k] = R.lo[k] - N.boxes[d].lo[k];
+          c.slo[k] = R.lo[k] - O.boxes[o].lo[k];
+          c.n[k] = R.size(k);
+        }
+        c.pad = 0;
+        cs.push_back(c);
+        nc.push_back(R.volume());
+      });
+    if (keep.upload(cs, nc) != hipSuccess) { N.release(); fresh.release(); return fail(SH_EDEVICE, "table upload failed"); }
+  }
+  // level scalars (k unchanged for an existing level; a new level starts at its parent's time)
+  if (!existing) h->lev.push_back(Level());
+  Level old = h->lev[l];
+  h->lev[l] = N;
+  s = upload_ls(h, l);
+  if (s != SH_OK) return s;
+  if (existing) {
+    sh_launch_regrid_copy(p.prec, keep.segs.p, keep.blocks.p, keep.nblocks(), N.dbox.p, old.dbox.p, h->st);
+    LAUNCHCHK();
+  }
+  if (l > 0) {
+    sh_launch_ghost_interp(p.prec, fresh.segs.p, fresh.blocks.p, fresh.nblocks(), N.dbox.p, h->lev[l - 1].dbox.p,
+                           ROLE_UN, 4, 4, h->st);
+    LAUNCHCHK();
+  }
+  HIPCHK(hipMemsetAsync(N.covered(), 0, (size_t)N.g.nvalid, h->st));
+  HIPCHK(hipStreamSynchronize(h->st));
+  keep.release();
+  fresh.release();
+  if (existing) old.release();
+  if (l > 0) {
+    s = build_links(h, l);
+    if (s != SH_OK) return s;
+  }
+  if (l + 1 < (int)h->lev.size()) {
+    s = build_links(h, l + 1);
+    if (s != SH_OK && s != SH_ENEST) return s;
+  }
+  // ghosts of the new state (level 0: only meaningful once state is written)
+  s = fill(h, l, ROLE_UN, 4);
+  if (s != SH_OK) return s;
+  HIPCHK(hipStreamSynchronize(h->st));
+  g_err.clear();
+  return SH_OK;
+}
+
+static sh_status xfer(sh_hierarchy h, int l, int role, double* buf, int is_device, int g, bool to_box) {
+  sh_status s = check_level(h, l);
+  if (s != SH_OK) return s;
+  if (!buf) return fail(SH_EINVAL, "null buffer");
+  if (role < 0 || role > 3) return fail(SH_EINVAL, "bad role");
+  Level& L = h->lev[l];
+  const DevArr<long long>& off = g ? L.xoff_ghost : L.xoff_valid;
+  long long total = 0;
+  for (const BoxDev& b : L.hbox)
+    total += 4LL * (b.nx + 2 * g) * (b.ny + 2 * g) * (b.nz + 2 * g);
+  double* dev = buf;
+  if (!is_device) {
+    HIPCHK(hipMalloc((void**)&dev, (size_t)total * 8));
+    if (to_box) {
+      hipError_t e = hipMemcpyAsync(dev, buf, (size_t)total * 8, hipMemcpyHostToDevice, h->st);
+      if (e != hipSuccess) { (void)hipFree(dev); return fail(SH_EDEVICE, hipGetErrorString(e)); }
+    }
+  }
+  sh_launch_xfer(h->p.prec, to_box, L.dbox.p, off.p, (int)L.hbox.size(), dev, role, g, total, h->st);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess && !is_device) {
+    if (!to_box) e = hipMemcpyAsync(buf, dev, (size_t)total * 8, hipMemcpyDeviceToHost, h->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->st);
+    (void)hipFree(dev);
+  }
+  if (e != hipSuccess) return fail(SH_EDEVICE, hipGetErrorString(e));
+  return SH_OK;
+}
+
+sh_status sh_write_state(sh_hierarchy h, int32_t l, int32_t role, const double* src, int32_t src_is_device,
+                         int32_t with_ghosts) {
+  return xfer(h, l, role, (double*)src, src_is_device, with_ghosts ? 1 : 0, true);
+}
+
+sh_status sh_read_state(sh_hierarchy h, int32_t l, int32_t role, double* dst, int32_t dst_is_device,
+                        int32_t with_ghosts) {
+  return xfer(h, l, role, dst, dst_is_device, with_ghosts ? 1 : 0, false);
+}
+
+sh_status sh_fill_ghosts(sh_hierarchy h, int32_t l, int32_t role, int32_t anum) {
+  sh_status s = check_level(h, l);
+  if (s != SH_OK) return s;
+  if (role < 0 || role > 2 || anum < 0 || anum > 4) return fail(SH_EINVAL, "bad role or alpha");
+  return fill(h, l, role, anum);
+}
+
+sh_status sh_advance_level(sh_hierarchy h, int32_t l, int32_t sub) {
+  sh_status s = check_level(h, l);
+  if (s != SH_OK) return s;
+  if (l > 0 && sub != 0 && sub != 1) return fail(SH_EINVAL, "substep must be 0 or 1");
+  if (l == 0) sub = 0;
+  Level& L = h->lev[l];
+  const int prec = h->p.prec;
+  hipEvent_t ev;
+  // stage 1 reads U_n (ghosts set by the previous step end or synchronisation)
+  h->rec(1, l, 0, sub);
+  ev = h->prof_begin();
+  sh_launch_stage(prec, 0, L.tiles.p, L.ntiles(), L.dbox.p, h->st);
+  h->prof_end(ev, 0);
+  LAUNCHCHK();
+  // alpha in quarters: (sub + c_s)/2 * 4 = 2 sub + 2 c_s
+  if ((s = fill(h, l, ROLE_A, 2 * sub + 1)) != SH_OK) return s;
+  h->rec(1, l, 1, sub);
+  ev = h->prof_begin();
+  sh_launch_stage(prec, 1, L.tiles.p, L.ntiles(), L.dbox.p, h->st);
+  h->prof_end(ev, 1);
+  LAUNCHCHK();
+  if ((s = fill(h, l, ROLE_B, 2 * sub + 1)) != SH_OK) return s;
+  h->rec(1, l, 2, sub);
+  ev = h->prof_begin();
+  sh_launch_stage(prec, 2, L.tiles.p, L.ntiles(), L.dbox.p, h->st);
+  h->prof_end(ev, 2);
+  LAUNCHCHK();
+  if ((s = fill(h, l, ROLE_A, 2 * sub + 2)) != SH_OK) return s;
+  h->rec(1, l, 3, sub);
+  ev = h->prof_begin();
+  sh_launch_stage(prec, 3, L.tiles.p, L.ntiles(), L.dbox.p, h->st);
+  h->prof_end(ev, 3);
+  LAUNCHCHK();
+  sh_launch_counter_inc(h->d_ls + l, 1, h->st);
+  LAUNCHCHK();
+  L.k += 1;
+  if ((s = same_level_fill(h, l, ROLE_UN)) != SH_OK) return s;
+  if (l > 0 && sub == 0) return coarse_fine_fill(h, l, ROLE_UN, 2);
+  return SH_OK;
+}
+
+sh_status sh_average_down(sh_hierarchy h, int32_t f) {
+  sh_status s = check_level(h, f);
+  if (s != SH_OK) return s;
+  if (f < 1) return fail(SH_EINVAL, "fine level must be >= 1");
+  Level& F = h->lev[f];
+  Level& C = h->lev[f - 1];
+  if (F.k != 2 * C.k) return fail(SH_ESTATE, "levels are not at the same time");
+  h->rec(4, f, 0, 0);
+  hipEvent_t ev = h->prof_begin();
+  sh_launch_avgdown(h->p.prec, F.a5.segs.p, F.a5.blocks.p, F.a5.nblocks(), C.dbox.p, F.dbox.p, h->st);
+  h->prof_end(ev, 6);
+  LAUNCHCHK();
+  if ((s = same_level_fill(h, f - 1, ROLE_UN)) != SH_OK) return s;
+  return coarse_fine_fill(h, f, ROLE_UN, 4);
+}
+
+sh_status sh_tag_cells(sh_hierarchy h, int32_t l, uint8_t* mask_dev, int32_t* idx_host, int64_t cap,
+                       int64_t* ntag) {
+  sh_status s = check_level(h, l);
+  if (s != SH_OK) return s;
+  if (cap < 0) return fail(SH_EINVAL, "negative capacity");
+  Level& L = h->lev[l];
+  if ((s = fill(h, l, ROLE_UN, 4)) != SH_OK) return s;
+  uint8_t* mask = mask_dev ? mask_dev : L.mask();
+  const int nt = L.ntiles();
+  sh_launch_tag(h->p.prec, L.tiles.p, nt, L.dbox.p, mask, L.tile_count(), h->st);
+  LAUNCHCHK();
+  sh_launch_scan(L.tile_count(), L.tile_off(), nt, h->st);
+  LAUNCHCHK();
+  long long total = 0;
+  HIPCHK(hipMemcpyAsync(&total, L.tile_off() + nt, 8, hipMemcpyDeviceToHost, h->st));
+  HIPCHK(hipStreamSynchronize(h->st));
+  if (ntag) *ntag = total;
+  const long long want = std::min<long long>(total, cap);
+  if (idx_host && want > 0) {
+    if (L.d_idx_cap < want) {
+      if (L.d_idx) (void)hipFree(L.d_idx);
+      L.d_idx = nullptr;
+      L.d_idx_cap = 0;
+      HIPCHK(hipMalloc((void**)&L.d_idx, (size_t)want * 12));
+      L.d_idx_cap = want;
+    }
+    sh_launch_tag_compact(L.tiles.p, nt, L.dbox.p, mask, L.tile_off(), L.d_idx, want, h->st);
+    LAUNCHCHK();
+    HIPCHK(hipMemcpyAsync(idx_host, L.d_idx, (size_t)want * 12, hipMemcpyDeviceToHost, h->st));
+    HIPCHK(hipStreamSynchronize(h->st));
+  }
+  return SH_OK;
+}
+
+sh_status sh_energy(sh_hierarchy h, double* e_host, int64_t* nonfinite) {
+  if (!h || !e_host) return fail(SH_EINVAL, "null argument");
+  if (h->lev.empty()) return fail(SH_ESTATE, "no levels");
+  const int nl = (int)h->lev.size();
+  for (int l = 0; l < nl; ++l) {
+    if (h->lev[l].stale) return fail(SH_ESTATE, "stale level");
+    Level& L = h->lev[l];
+    const uint8_t* cov = (l + 1 < nl) ? L.covered() : nullptr;
+    sh_launch_energy(h->p.prec, L.tiles.p, L.ntiles(), L.dbox.p, cov, L.epart(), h->st);
+    LAUNCHCHK();
+    sh_launch_energy_final(L.epart(), L.ntiles(), L.dx * L.dx * L.dx, L.eout(), h->st);
+    LAUNCHCHK();
+  }
+  std::vector<double> all(4 * nl);
+  for (int l = 0; l < nl; ++l)
+    HIPCHK(hipMemcpyAsync(&all[4 * l], h->lev[l].eout(), 32, hipMemcpyDeviceToHost, h->st));
+  HIPCHK(hipStreamSynchronize(h->st));
+  double k = 0, g = 0, pt = 0, bad = 0;
+  for (int l = 0; l < nl; ++l) {
+    k += all[4 * l];
+    g += all[4 * l + 1];
+    pt += all[4 * l + 2];
+    bad += all[4 * l + 3];
+  }
+  e_host[0] = k;
+  e_host[1] = g;
+  e_host[2] = pt;
+  e_host[3] = k + g + pt;
+  if (nonfinite) *nonfinite = (int64_t)bad;
+  return SH_OK;
+}
+
+sh_status sh_eval_rhs(sh_hierarchy h, int32_t l, double* out_dev) {
+  sh_status s = check_level(h, l);
+  if (s != SH_OK) return s;
+  if (!out_dev) return fail(SH_EINVAL, "null output");
+  Level& L = h->lev[l];
+  sh_launch_rhs(h->p.prec, L.tiles.p, L.ntiles(), L.dbox.p, L.rhs_off.p, out_dev, h->st);
+  LAUNCHCHK();
+  return SH_OK;
+}
+
+sh_status sh_level_info(sh_hierarchy h, int32_t l, int64_t* k, double* eta, int32_t* nboxes, int64_t* ncells) {
+  if (!h || l < 0 || l >= (int)h->lev.size()) return fail(SH_EINVAL, "no such level");
+  const Level& L = h->lev[l];
+  if (k) *k = L.k;
+  if (eta) *eta = h->p.eta0 + (double)L.k * L.dt;
+  if (nboxes) *nboxes = (int32_t)L.boxes.size();
+  if (ncells) *ncells = L.g.nvalid;
+  return SH_OK;
+}
+
+sh_status sh_sync(sh_hierarchy h) {
+  if (!h) return fail(SH_EINVAL, "null handle");
+  HIPCHK(hipStreamSynchronize(h->st));
+  HIPCHK(hipGetLastError());
+  return SH_OK;
+}
+
+sh_status sh_debug_stage_scalars(sh_hierarchy h, int32_t l, int32_t s, double* out_host) {
+  sh_status st = check_level(h, l);
+  if (st != SH_OK) return st;
+  if (s < 0 || s > 3 || !out_host) return fail(SH_EINVAL, "bad stage");
+  sh_launch_debug_scalars(h->d_ls + l, s, h->d_dbg, h->st);
+  LAUNCHCHK();
+  HIPCHK(hipMemcpyAsync(out_host, h->d_dbg, 7 * 8, hipMemcpyDeviceToHost, h->st));
+  HIPCHK(hipStreamSynchronize(h->st));
+  return SH_OK;
+}
+
+static sh_status emit_boxes(const std::vector<IBox>& out, int32_t* boxes_out, int32_t cap, int32_t* nboxes) {
+  *nboxes = (int32_t)out.size();
+  if ((int)out.size() > cap) return fail(SH_ENOMEM, "box capacity too small");
+  for (size_t i = 0; i < out.size(); ++i)
+    for (int d = 0; d < 3; ++d) {
+      boxes_out[6 * i + d] = out[i].lo[d];
+      boxes_out[6 * i + 3 + d] = out[i].hi[d];
+    }
+  return SH_OK;
+}
+
+sh_status sh_cluster_boxes(int32_t M, int32_t nlevel_boxes, const int32_t* level_boxes, int32_t bf, int32_t max_box,
+                           int32_t n_error_buf, double efficiency, int64_t ntag, const int32_t* tags,
+                           int32_t* boxes_out, int32_t cap, int32_t* nboxes) {
+  if (M < 1 || nlevel_boxes < 0 || (nlevel_boxes > 0 && !level_boxes) || ntag < 0 || (ntag > 0 && !tags) ||
+      !nboxes || cap < 0 || (cap > 0 && !boxes_out) || !(efficiency > 0) || efficiency > 1 || n_error_buf < 0 ||
+      max_box < bf)
+    return fail(SH_EINVAL, "bad clustering arguments");
+  std::vector<IBox> lb;
+  for (int i = 0; i < nlevel_boxes; ++i) {
+    IBox b;
+    for (int d = 0; d < 3; ++d) {
+      b.lo[d] = level_boxes[6 * i + d];
+      b.hi[d] = level_boxes[6 * i + 3 + d];
+    }
+    lb.push_back(b);
+  }
+  std::vector<IBox> out;
+  std::string err;
+  if (!cluster_level(M, lb, nlevel_boxes == 0, bf, max_box, n_error_buf, efficiency, tags, ntag, out, err))
+    return fail(SH_EINVAL, err);
+  return emit_boxes(out, boxes_out, cap, nboxes);
+}
+
+sh_status sh_cluster_tags(sh_hierarchy h, int32_t l, int64_t ntag, const int32_t* tags, double efficiency,
+                          int32_t* boxes_out, int32_t cap, int32_t* nboxes) {
+  sh_status s = check_level(h, l);
+  if (s != SH_OK) return s;
+  if (ntag < 0 || (ntag > 0 && !tags) || !nboxes || cap < 0 || (cap > 0 && !boxes_out) || !(efficiency > 0) ||
+      efficiency > 1)
+    return fail(SH_EINVAL, "bad clustering arguments");
+  const sh_params& p = h->p;
+  const Level& L = h->lev[l];
+  std::vector<IBox> out;
+  std::string err;
+  if (!cluster_level(L.M, L.boxes, l == 0, p.blocking_factor, p.max_box, p.n_error_buf, efficiency, tags, ntag, out,
+                     err))
+    return fail(SH_EINVAL, err);
+  return emit_boxes(out, boxes_out, cap, nboxes);
+}
+
+sh_status sh_profile(sh_hierarchy h, int32_t enable) {
+  if (!h) return fail(SH_EINVAL, "null handle");
+  h->prof_collect();
+  h->profiling = enable != 0;
+  for (int i = 0; i < 8; ++i) {
+    h->prof_ms[i] = 0;
+    h->prof_n[i] = 0;
+  }
+  return SH_OK;
+}
+
+sh_status sh_profile_read(sh_hierarchy h, double* ms, int64_t* counts) {
+  if (!h || !ms || !counts) return fail(SH_EINVAL, "null argument");
+  h->prof_collect();
+  for (int i = 0; i < 8; ++i) {
+    ms[i] = h->prof_ms[i];
+    counts[i] = h->prof_n[i];
+  }
+  return SH_OK;
+}
+
+sh_status sh_trace(sh_hierarchy h, int32_t enable) {
+  if (!h) return fail(SH_EINVAL, "null handle");
+  h->tracing = enable != 0;
+  h->trace.clear();
+  return SH_OK;
+}
+
+int64_t sh_trace_read(sh_hierarchy h, int32_t* out, int64_t cap) {
+  if (!h) return -1;
+  const int64_t n = (int64_t)h->trace.size() / 4;
+  if (out) std::memcpy(out, h->trace.data(), (size_t)std::min(n, cap) * 16);
+  return n;
+}
+
+}  // extern "C"

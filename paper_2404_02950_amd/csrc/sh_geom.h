@@ -1,0 +1,157 @@
+// Integer box algebra on a periodic index space (host only, internal).
+#pragma once
+#include <stdint.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+struct IBox {
+  int lo[3], hi[3];  // inclusive
+  int size(int d) const { return hi[d] - lo[d] + 1; }
+  bool empty() const { return hi[0] < lo[0] || hi[1] < lo[1] || hi[2] < lo[2]; }
+  long long volume() const { return empty() ? 0 : (long long)size(0) * size(1) * size(2); }
+};
+
+inline IBox isect(const IBox& a, const IBox& b) {
+  IBox r;
+  for (int d = 0; d < 3; ++d) {
+    r.lo[d] = std::max(a.lo[d], b.lo[d]);
+    r.hi[d] = std::min(a.hi[d], b.hi[d]);
+  }
+  return r;
+}
+
+inline IBox grow(const IBox& a, int g) {
+  IBox r = a;
+  for (int d = 0; d < 3; ++d) {
+    r.lo[d] -= g;
+    r.hi[d] += g;
+  }
+  return r;
+}
+
+inline IBox shift(const IBox& a, int sx, int sy, int sz) {
+  IBox r = a;
+  const int s[3] = {sx, sy, sz};
+  for (int d = 0; d < 3; ++d) {
+    r.lo[d] += s[d];
+    r.hi[d] += s[d];
+  }
+  return r;
+}
+
+// floor division by 2 (arithmetic shift), for cells one outside the domain too
+inline IBox coarsen(const IBox& a) {
+  IBox r;
+  for (int d = 0; d < 3; ++d) {
+    r.lo[d] = a.lo[d] >> 1;
+    r.hi[d] = a.hi[d] >> 1;
+  }
+  return r;
+}
+
+inline IBox refine(const IBox& a) {
+  IBox r;
+  for (int d = 0; d < 3; ++d) {
+    r.lo[d] = 2 * a.lo[d];
+    r.hi[d] = 2 * a.hi[d] + 1;
+  }
+  return r;
+}
+
+// a \ b as disjoint boxes appended to out
+inline void subtract(const IBox& a, const IBox& b, std::vector<IBox>& out) {
+  const IBox i = isect(a, b);
+  if (i.empty()) {
+    out.push_back(a);
+    return;
+  }
+  IBox r = a;
+  for (int d = 0; d < 3; ++d) {
+    if (r.lo[d] < i.lo[d]) {
+      IBox p = r;
+      p.hi[d] = i.lo[d] - 1;
+      out.push_back(p);
+      r.lo[d] = i.lo[d];
+    }
+    if (r.hi[d] > i.hi[d]) {
+      IBox p = r;
+      p.lo[d] = i.hi[d] + 1;
+      out.push_back(p);
+      r.hi[d] = i.hi[d];
+    }
+  }
+}
+
+// Uniform bins over [0, M)^3 listing the boxes that overlap each bin.
+struct BoxBins {
+  int M = 0, B = 32, nb = 0;
+  std::vector<std::vector<int>> bins;
+  mutable std::vector<int> stamp;
+  mutable int cur = 0;
+
+  void build(const std::vector<IBox>& boxes, int M_) {
+    M = M_;
+    B = std::max(8, std::min(64, M));
+    nb = (M + B - 1) / B;
+    bins.assign((size_t)nb * nb * nb, {});
+    stamp.assign(boxes.size(), 0);
+    cur = 0;
+    for (int i = 0; i < (int)boxes.size(); ++i) {
+      const IBox& b = boxes[i];
+      for (int z = b.lo[2] / B; z <= b.hi[2] / B; ++z)
+        for (int y = b.lo[1] / B; y <= b.hi[1] / B; ++y)
+          for (int x = b.lo[0] / B; x <= b.hi[0] / B; ++x) bins[((size_t)z * nb + y) * nb + x].push_back(i);
+    }
+  }
+
+  // f(box) once for every box whose bins overlap q (q clipped to [0, M)^3)
+  template <class F>
+  void query(const IBox& q0, F f) const {
+    IBox q = q0;
+    for (int d = 0; d < 3; ++d) {
+      q.lo[d] = std::max(q.lo[d], 0);
+      q.hi[d] = std::min(q.hi[d], M - 1);
+    }
+    if (q.empty() || nb == 0) return;
+    if (++cur == 0x7fffffff) {
+      std::fill(stamp.begin(), stamp.end(), 0);
+      cur = 1;
+    }
+    for (int z = q.lo[2] / B; z <= q.hi[2] / B; ++z)
+      for (int y = q.lo[1] / B; y <= q.hi[1] / B; ++y)
+        for (int x = q.lo[0] / B; x <= q.hi[0] / B; ++x)
+          for (int i : bins[((size_t)z * nb + y) * nb + x])
+            if (stamp[i] != cur) {
+              stamp[i] = cur;
+              f(i);
+            }
+  }
+};
+
+// f(box, shift[3]) for every periodic image box + shift*M (shift in {-1,0,1}^3) that
+// may overlap q, which may reach up to M cells outside [0, M)^3.
+template <class F>
+inline void for_images(const IBox& q, int M, const BoxBins& bins, F f) {
+  for (int sz = -1; sz <= 1; ++sz)
+    for (int sy = -1; sy <= 1; ++sy)
+      for (int sx = -1; sx <= 1; ++sx) {
+        const int sh[3] = {sx, sy, sz};
+        const IBox qs = shift(q, -sx * M, -sy * M, -sz * M);
+        bins.query(qs, [&](int b) { f(b, sh); });
+      }
+}
+
+inline long long covered_volume(const IBox& q, int M, const BoxBins& bins, const std::vector<IBox>& boxes) {
+  long long v = 0;
+  for_images(q, M, bins, [&](int b, const int sh[3]) {
+    v += isect(q, shift(boxes[b], sh[0] * M, sh[1] * M, sh[2] * M)).volume();
+  });
+  return v;
+}
+
+// Berger-Rigoutsos clustering of the tags of a level into boxes of the next level
+// (implemented in cluster.cpp).
+bool cluster_level(int M, const std::vector<IBox>& level_boxes, bool full_level, int bf, int max_box, int nbuf,
+                   double efficiency, const int32_t* tags, long long ntag, std::vector<IBox>& out, std::string& err);

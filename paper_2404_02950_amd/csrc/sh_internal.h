@@ -1,0 +1,97 @@
+// Internal device/host structures of libshamr (not part of the public C-ABI).
+//
+// Storage of one box (all levels, all buffers): structure-of-arrays
+//   element(c, i, j, k) = off + c*cs + ((k+1)*py + (j+1))*px + XOFF + i
+// for component c in {psi1, psi2, Pi1, Pi2}, box-local cell (i, j, k) with
+// -1 <= i <= nx etc. (a one-cell ghost shell).  XOFF puts i = 0 on a 64-byte boundary
+// and px is a multiple of XOFF, so every x-row of valid cells starts 64-byte aligned.
+// A level owns three state slots of this layout in the storage precision T plus one
+// float64 accumulator slot with the same element offsets.
+#pragma once
+#include <stdint.h>
+
+#define SH_WAVE 64
+#define SH_BLOCK 256
+
+// Per-level scalars on the device.  k is the number of steps the level has taken; the
+// level time is eta0 + k*dt (one multiply and one add, so aligned levels hold
+// bit-identical times).  Every kernel resolves buffer roles from the parity of k, so a
+// launch sequence can be replayed without host updates.
+struct LevelScal {
+  double eta0, dt, alpha, lam, inv_dx2, dx;
+  int beta, pad;
+  long long k;
+};
+
+// Buffer roles.  With p = k & 1: U_n = slot[2p], A = slot[1], B = slot[2 - 2p].
+// RK4 stages read (U_n, A, B, A) and write (A, B, A, B); after stage 4 and the counter
+// increment, the old U_n (OLD) is slot B of the new parity until the next stage 2.
+enum { ROLE_UN = 0, ROLE_A = 1, ROLE_B = 2, ROLE_OLD = 3 };
+
+__host__ __device__ inline int role_slot(int role, long long k) {
+  int p = (int)(k & 1);
+  switch (role) {
+    case ROLE_UN: return 2 * p;
+    case ROLE_A: return 1;
+    case ROLE_B: return 2 - 2 * p;
+    default: return 2 - 2 * p;  // ROLE_OLD (valid once k has been incremented)
+  }
+}
+
+struct BoxDev {
+  void* slot[3];      // base of this box's storage block in each state slot (type T)
+  double* acc;        // base of this box's block in the accumulator slot
+  LevelScal* ls;      // scalars of the box's level
+  long long cs;       // component stride (elements)
+  int nx, ny, nz;     // valid cells
+  int px, py;         // x pitch (elements), y pitch (ny + 2)
+  int lo[3];          // global index of cell (0,0,0) on the box's level
+  int mask_off;       // offset of the box's valid cells in per-level byte masks
+  int pad;
+};
+
+// Wave tile: one wavefront covers a TX x (64/TX) footprint of a box and marches in z.
+struct Tile {
+  int box;
+  int xy;   // x0 | y0 << 16
+  int zz;   // z0 | zc << 16
+  int txs;  // log2(TX)
+};
+
+// Same-level ghost copy (psi components): dst region (box-local, inside the ghost
+// shell) <- src region (box-local, valid cells of src box).
+struct CopySeg {
+  int dbox, sbox;
+  int dlo[3], slo[3], n[3];
+  int pad;
+};
+
+// Coarse->fine interpolation: fine cells of region flo..flo+n-1 (fine box-local) whose
+// global index is fg = flo + fglo_minus_flo; parent in coarse box-local coordinates
+// is floor(fg/2) + cshift.
+struct InterpSeg {
+  int fbox, cbox;
+  int flo[3], n[3];
+  int fg0[3];      // global fine index of flo
+  int cshift[3];   // coarse local = floor(fg/2) + cshift
+};
+
+// Average down: coarse cells clo..clo+n-1 (coarse box-local) of box cbox from fine box
+// fbox whose child (0,0,0) of coarse cell clo sits at fine-local f0.
+struct AvgSeg {
+  int cbox, fbox;
+  int clo[3], n[3], f0[3];
+  int pad;
+};
+
+// Flat work decomposition of a segment list: block b covers cells
+// [start, start + SH_BLOCK) of segment seg.
+struct SegBlock {
+  int seg, start;
+};
+
+// Per-wave-tile partial reduction of the energy and the non-finite count.
+struct EnergyPartial {
+  double kin, grad, pot;
+  long long nonfinite;
+};

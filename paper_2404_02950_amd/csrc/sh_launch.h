@@ -1,0 +1,33 @@
+// Host-side launch wrappers of the kernels in kernels.hip (internal).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sh_internal.h"
+
+void sh_launch_stage(int prec, int s, const Tile* tiles, int ntiles, const BoxDev* boxes, hipStream_t st);
+void sh_launch_rhs(int prec, const Tile* tiles, int ntiles, const BoxDev* boxes, const long long* out_off,
+                   double* out, hipStream_t st);
+void sh_launch_counter_inc(LevelScal* ls, int n, hipStream_t st);
+void sh_launch_ghost_copy(int prec, const CopySeg* segs, const SegBlock* blocks, int nblocks, const BoxDev* boxes,
+                          int role, hipStream_t st);
+void sh_launch_ghost_interp(int prec, const InterpSeg* segs, const SegBlock* blocks, int nblocks,
+                            const BoxDev* fboxes, const BoxDev* cboxes, int role, int anum, int ncomp,
+                            hipStream_t st);
+void sh_launch_avgdown(int prec, const AvgSeg* segs, const SegBlock* blocks, int nblocks, const BoxDev* cboxes,
+                       const BoxDev* fboxes, hipStream_t st);
+void sh_launch_regrid_copy(int prec, const CopySeg* segs, const SegBlock* blocks, int nblocks, const BoxDev* dboxes,
+                           const BoxDev* sboxes, hipStream_t st);
+void sh_launch_tag(int prec, const Tile* tiles, int ntiles, const BoxDev* boxes, uint8_t* mask, int* tile_count,
+                   hipStream_t st);
+void sh_launch_scan(const int* in, long long* out, int n, hipStream_t st);
+void sh_launch_tag_compact(const Tile* tiles, int ntiles, const BoxDev* boxes, const uint8_t* mask,
+                           const long long* tile_off, int* idx, long long cap, hipStream_t st);
+void sh_launch_energy(int prec, const Tile* tiles, int ntiles, const BoxDev* boxes, const uint8_t* covered,
+                      EnergyPartial* part, hipStream_t st);
+void sh_launch_energy_final(const EnergyPartial* part, int n, double vol, double* out, hipStream_t st);
+void sh_launch_mark_covered(const AvgSeg* segs, const SegBlock* blocks, int nblocks, const BoxDev* cboxes,
+                            uint8_t* covered, hipStream_t st);
+void sh_launch_xfer(int prec, bool to_box, const BoxDev* boxes, const long long* off, int nbox, double* stage, int role,
+                    int g, long long total, hipStream_t st);
+void sh_launch_debug_scalars(const LevelScal* ls, int s, double* out, hipStream_t st);

@@ -1,0 +1,326 @@
+"""ctypes binding of libshamr (include/shamr.h): argument marshalling only.
+
+Every step of the path runs in the HIP library; PyTorch supplies device memory (one
+arena tensor per level) and the stream.  If the library is not built this module
+raises instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, Structure, c_char_p, c_double, c_int32, c_int64, c_size_t, c_void_p
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libshamr.so")
+
+SH_OK, SH_EINVAL, SH_ENOMEM, SH_ENEST, SH_ESTATE, SH_EDEVICE = range(6)
+SH_F64, SH_F32 = 0, 1
+ROLE_UN, ROLE_A, ROLE_B, ROLE_OLD = 0, 1, 2, 3
+_STATUS = {1: "SH_EINVAL", 2: "SH_ENOMEM", 3: "SH_ENEST", 4: "SH_ESTATE", 5: "SH_EDEVICE"}
+
+
+class ShError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class sh_params(Structure):
+    _fields_ = [
+        ("n0", c_int32), ("L", c_double), ("cfl", c_double), ("eta0", c_double),
+        ("lam", c_double), ("alpha_fric", c_double), ("beta_pot", c_int32),
+        ("max_level", c_int32), ("blocking_factor", c_int32), ("max_box", c_int32),
+        ("n_error_buf", c_int32), ("prec", c_int32),
+    ]
+
+
+_PROTOS = {
+    "sh_arena_bytes": (c_size_t, [POINTER(sh_params), c_int32, c_int32, POINTER(c_int32)]),
+    "sh_hierarchy_create": (c_int32, [POINTER(sh_params), c_void_p, POINTER(c_void_p)]),
+    "sh_set_level_layout": (c_int32, [c_void_p, c_int32, c_int32, POINTER(c_int32), c_void_p, c_size_t]),
+    "sh_write_state": (c_int32, [c_void_p, c_int32, c_int32, c_void_p, c_int32, c_int32]),
+    "sh_read_state": (c_int32, [c_void_p, c_int32, c_int32, c_void_p, c_int32, c_int32]),
+    "sh_fill_ghosts": (c_int32, [c_void_p, c_int32, c_int32, c_int32]),
+    "sh_advance_level": (c_int32, [c_void_p, c_int32, c_int32]),
+    "sh_average_down": (c_int32, [c_void_p, c_int32]),
+    "sh_tag_cells": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_int64, POINTER(c_int64)]),
+    "sh_energy": (c_int32, [c_void_p, POINTER(c_double), POINTER(c_int64)]),
+    "sh_eval_rhs": (c_int32, [c_void_p, c_int32, c_void_p]),
+    "sh_level_info": (c_int32, [c_void_p, c_int32, POINTER(c_int64), POINTER(c_double), POINTER(c_int32),
+                                POINTER(c_int64)]),
+    "sh_num_levels": (c_int32, [c_void_p]),
+    "sh_cluster_tags": (c_int32, [c_void_p, c_int32, c_int64, c_void_p, c_double, c_void_p, c_int32,
+                                  POINTER(c_int32)]),
+    "sh_cluster_boxes": (c_int32, [c_int32, c_int32, c_void_p, c_int32, c_int32, c_int32, c_double, c_int64,
+                                   c_void_p, c_void_p, c_int32, POINTER(c_int32)]),
+    "sh_sync": (c_int32, [c_void_p]),
+    "sh_hierarchy_destroy": (c_int32, [c_void_p]),
+    "sh_last_error": (c_char_p, []),
+    "sh_debug_stage_scalars": (c_int32, [c_void_p, c_int32, c_int32, POINTER(c_double)]),
+    "sh_profile": (c_int32, [c_void_p, c_int32]),
+    "sh_profile_read": (c_int32, [c_void_p, POINTER(c_double), POINTER(c_int64)]),
+    "sh_trace": (c_int32, [c_void_p, c_int32]),
+    "sh_trace_read": (c_int64, [c_void_p, c_void_p, c_int64]),
+}
+
+EXPORTED = tuple(_PROTOS)
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libshamr.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it first (python -m paper_2404_02950_amd.build_lib)")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in _PROTOS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(status: int):
+    if status != SH_OK:
+        raise ShError(status, _lib.sh_last_error().decode())
+
+
+def _boxes_arr(boxes):
+    b = np.ascontiguousarray(np.asarray(boxes, dtype=np.int32).reshape(-1, 6))
+    return b, b.ctypes.data_as(POINTER(c_int32))
+
+
+def box_shape(b):
+    """(nz, ny, nx) of a box (x_lo, y_lo, z_lo, x_hi, y_hi, z_hi)."""
+    return (b[5] - b[2] + 1, b[4] - b[1] + 1, b[3] - b[0] + 1)
+
+
+def cluster_boxes(M: int, level_boxes, tags, blocking_factor: int = 8, max_box: int = 64,
+                  n_error_buf: int = 2, efficiency: float = 0.7):
+    """Berger-Rigoutsos clustering of level tags into next-level boxes (host only)."""
+    lib = load()
+    lb = np.ascontiguousarray(np.asarray(level_boxes, np.int32).reshape(-1, 6))
+    t = np.ascontiguousarray(np.asarray(tags, np.int32).reshape(-1, 3))
+    cap = 4096
+    while True:
+        out = np.empty((cap, 6), np.int32)
+        nb = c_int32()
+        st = lib.sh_cluster_boxes(M, len(lb), lb.ctypes.data_as(c_void_p), blocking_factor, max_box, n_error_buf,
+                                  efficiency, len(t), t.ctypes.data_as(c_void_p), out.ctypes.data_as(c_void_p),
+                                  cap, ctypes.byref(nb))
+        if st == SH_ENOMEM and nb.value > cap:
+            cap = nb.value
+            continue
+        _check(st)
+        return [tuple(int(v) for v in r) for r in out[:nb.value]]
+
+
+class Hierarchy:
+    """One simulation: levels of boxes in caller-owned (torch) device arenas."""
+
+    def __init__(self, n0: int, L: float, cfl: float = 0.25, eta0: float = 0.1, lam: float = 1.0,
+                 alpha: float = 2.0, beta: int = 2, max_level: int = 0, blocking_factor: int = 8,
+                 max_box: int = 64, n_error_buf: int = 2, prec: int = SH_F64, stream=None):
+        import torch
+        self.torch = torch
+        self.lib = load()
+        self.params = sh_params(n0, L, cfl, eta0, lam, alpha, beta, max_level, blocking_factor, max_box,
+                                n_error_buf, prec)
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        h = c_void_p()
+        _check(self.lib.sh_hierarchy_create(ctypes.byref(self.params), c_void_p(self.stream.cuda_stream),
+                                            ctypes.byref(h)))
+        self.h = h
+        self.arenas = {}
+        self.boxes = {}
+
+    # -- lifetime ---------------------------------------------------------------------
+    def close(self):
+        if self.h is not None:
+            self.lib.sh_hierarchy_destroy(self.h)
+            self.h = None
+            self.arenas.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- layout -----------------------------------------------------------------------
+    def arena_bytes(self, lev: int, boxes) -> int:
+        b, ptr = _boxes_arr(boxes)
+        n = self.lib.sh_arena_bytes(ctypes.byref(self.params), lev, len(b), ptr)
+        if n == 0:
+            raise ShError(SH_EINVAL, "invalid layout")
+        return int(n)
+
+    def set_layout(self, lev: int, boxes):
+        b, ptr = _boxes_arr(boxes)
+        if len(b) == 0:
+            _check(self.lib.sh_set_level_layout(self.h, lev, 0, None, None, 0))
+            for l in [k for k in self.arenas if k >= lev]:
+                del self.arenas[l]
+                del self.boxes[l]
+            return
+        nbytes = self.arena_bytes(lev, b)
+        with self.torch.cuda.stream(self.stream):
+            arena = self.torch.empty(nbytes, dtype=self.torch.uint8, device="cuda")
+        _check(self.lib.sh_set_level_layout(self.h, lev, len(b), ptr, c_void_p(arena.data_ptr()), nbytes))
+        self.arenas[lev] = arena  # the previous arena is released after the call (stream-ordered)
+        self.boxes[lev] = [tuple(int(v) for v in row) for row in b]
+
+    def num_levels(self) -> int:
+        return int(self.lib.sh_num_levels(self.h))
+
+    def level_info(self, lev: int):
+        k, eta, nb, nc = c_int64(), c_double(), c_int32(), c_int64()
+        _check(self.lib.sh_level_info(self.h, lev, ctypes.byref(k), ctypes.byref(eta), ctypes.byref(nb),
+                                      ctypes.byref(nc)))
+        return {"k": k.value, "eta": eta.value, "nboxes": nb.value, "ncells": nc.value}
+
+    # -- state I/O --------------------------------------------------------------------
+    def _count(self, lev, ghosts):
+        g = 2 if ghosts else 0
+        return sum(4 * (s[0] + g) * (s[1] + g) * (s[2] + g) for s in map(box_shape, self.boxes[lev]))
+
+    def write_boxes(self, lev: int, arrays, role: int = ROLE_UN, ghosts: bool = False):
+        """arrays: per-box (4, nz, ny, nx) float64 arrays (with the ghost shell if ghosts)."""
+        flat = np.ascontiguousarray(np.concatenate([np.asarray(a, np.float64).ravel() for a in arrays]))
+        if flat.size != self._count(lev, ghosts):
+            raise ValueError("state size does not match the layout")
+        _check(self.lib.sh_write_state(self.h, lev, role, flat.ctypes.data_as(c_void_p), 0, int(ghosts)))
+
+    def read_boxes(self, lev: int, role: int = ROLE_UN, ghosts: bool = False):
+        n = self._count(lev, ghosts)
+        flat = np.empty(n, np.float64)
+        _check(self.lib.sh_read_state(self.h, lev, role, flat.ctypes.data_as(c_void_p), 0, int(ghosts)))
+        out, o = [], 0
+        g = 2 if ghosts else 0
+        for b in self.boxes[lev]:
+            nz, ny, nx = box_shape(b)
+            sz = 4 * (nz + g) * (ny + g) * (nx + g)
+            out.append(flat[o:o + sz].reshape(4, nz + g, ny + g, nx + g))
+            o += sz
+        return out
+
+    def write_dense(self, lev: int, U: np.ndarray, role: int = ROLE_UN):
+        """Write a dense (4, M, M, M) level array (valid cells of each box are taken)."""
+        arrs = []
+        for b in self.boxes[lev]:
+            arrs.append(U[:, b[2]:b[5] + 1, b[1]:b[4] + 1, b[0]:b[3] + 1])
+        self.write_boxes(lev, arrs, role)
+
+    def read_dense(self, lev: int, role: int = ROLE_UN, fill=np.nan) -> np.ndarray:
+        M = self.params.n0 << lev
+        U = np.full((4, M, M, M), fill)
+        for b, a in zip(self.boxes[lev], self.read_boxes(lev, role)):
+            U[:, b[2]:b[5] + 1, b[1]:b[4] + 1, b[0]:b[3] + 1] = a
+        return U
+
+    # -- the level step ---------------------------------------------------------------
+    def fill_ghosts(self, lev: int, role: int = ROLE_UN, alpha_num: int = 4):
+        _check(self.lib.sh_fill_ghosts(self.h, lev, role, alpha_num))
+
+    def advance(self, lev: int, substep: int = 0):
+        _check(self.lib.sh_advance_level(self.h, lev, substep))
+
+    def average_down(self, fine_lev: int):
+        _check(self.lib.sh_average_down(self.h, fine_lev))
+
+    def tag(self, lev: int, want_idx: bool = True, mask_dev=None):
+        """Tagged cells of a level: (count, (n, 3) int32 global x, y, z or None)."""
+        n = c_int64()
+        mptr = c_void_p(mask_dev.data_ptr()) if mask_dev is not None else None
+        _check(self.lib.sh_tag_cells(self.h, lev, mptr, None, 0, ctypes.byref(n)))
+        if not want_idx or n.value == 0:
+            return n.value, (np.zeros((0, 3), np.int32) if want_idx else None)
+        idx = np.empty((n.value, 3), np.int32)
+        _check(self.lib.sh_tag_cells(self.h, lev, mptr, idx.ctypes.data_as(c_void_p), n.value, ctypes.byref(n)))
+        return n.value, idx
+
+    def tag_mask_dense(self, lev: int) -> np.ndarray:
+        """Tag mask of a level as a dense uint8 (M, M, M) array (0 outside the level)."""
+        torch = self.torch
+        nv = sum(int(np.prod(box_shape(b))) for b in self.boxes[lev])
+        m = torch.zeros(nv, dtype=torch.uint8, device="cuda")
+        self.tag(lev, want_idx=False, mask_dev=m)
+        mh = m.cpu().numpy()
+        M = self.params.n0 << lev
+        out = np.zeros((M, M, M), np.uint8)
+        o = 0
+        for b in self.boxes[lev]:
+            nz, ny, nx = box_shape(b)
+            out[b[2]:b[5] + 1, b[1]:b[4] + 1, b[0]:b[3] + 1] = mh[o:o + nz * ny * nx].reshape(nz, ny, nx)
+            o += nz * ny * nx
+        return out
+
+    def energy(self):
+        e = (c_double * 4)()
+        bad = c_int64()
+        _check(self.lib.sh_energy(self.h, e, ctypes.byref(bad)))
+        return list(e), bad.value
+
+    def eval_rhs(self, lev: int):
+        torch = self.torch
+        n = self._count(lev, False)
+        out = torch.empty(n, dtype=torch.float64, device="cuda")
+        _check(self.lib.sh_eval_rhs(self.h, lev, c_void_p(out.data_ptr())))
+        self.sync()
+        flat = out.cpu().numpy()
+        res, o = [], 0
+        for b in self.boxes[lev]:
+            nz, ny, nx = box_shape(b)
+            sz = 4 * nz * ny * nx
+            res.append(flat[o:o + sz].reshape(4, nz, ny, nx))
+            o += sz
+        return res
+
+    def cluster(self, lev: int, tags: np.ndarray, efficiency: float = 0.7):
+        t = np.ascontiguousarray(np.asarray(tags, np.int32).reshape(-1, 3))
+        cap = 4096
+        while True:
+            out = np.empty((cap, 6), np.int32)
+            nb = c_int32()
+            st = self.lib.sh_cluster_tags(self.h, lev, len(t), t.ctypes.data_as(c_void_p), efficiency,
+                                          out.ctypes.data_as(c_void_p), cap, ctypes.byref(nb))
+            if st == SH_ENOMEM and nb.value > cap:
+                cap = nb.value
+                continue
+            _check(st)
+            return [tuple(int(v) for v in r) for r in out[:nb.value]]
+
+    def sync(self):
+        _check(self.lib.sh_sync(self.h))
+
+    def stage_scalars(self, lev: int, s: int):
+        out = (c_double * 7)()
+        _check(self.lib.sh_debug_stage_scalars(self.h, lev, s, out))
+        return list(out)
+
+    PROFILE_CLASSES = ("stage1", "stage2", "stage3", "stage4", "ghost_copy", "ghost_interp",
+                       "average_down", "unused")
+
+    def profile(self, enable: bool):
+        _check(self.lib.sh_profile(self.h, int(enable)))
+
+    def profile_read(self):
+        """{class: (total_ms, launches)} of the launches timed since profile(True)."""
+        ms = (c_double * 8)()
+        n = (c_int64 * 8)()
+        _check(self.lib.sh_profile_read(self.h, ms, n))
+        return {c: (ms[i], n[i]) for i, c in enumerate(self.PROFILE_CLASSES)}
+
+    def trace(self, enable: bool):
+        _check(self.lib.sh_trace(self.h, int(enable)))
+
+    def trace_read(self):
+        n = self.lib.sh_trace_read(self.h, None, 0)
+        buf = np.empty((max(n, 1), 4), np.int32)
+        self.lib.sh_trace_read(self.h, buf.ctypes.data_as(c_void_p), n)
+        return [tuple(int(v) for v in r) for r in buf[:n]]

@@ -1,0 +1,100 @@
+"""Host-side checks of the C-ABI library that need no GPU: it loads, exports every
+symbol include/shamr.h declares, sizes arenas, rejects bad arguments and clusters tags
+into properly nested, aligned layouts (checked by the oracle's layout checker)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle.amr import boxes_mask, coarsen_mask
+from oracle.layout import check_layout
+from oracle.tagging import tag_cells
+from synth import string_loop_state
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def shamr():
+    from paper_2404_02950_amd import shamr as m
+    m.load()
+    return m
+
+
+def test_library_exports_every_declared_symbol(shamr):
+    hdr = open(os.path.join(ROOT, "include", "shamr.h")).read()
+    declared = set(re.findall(r"^\s*(?:[\w\*]+\s+)+\**(sh_\w+)\s*\(", hdr, flags=re.M))
+    assert len(declared) >= 20
+    lib = ctypes.CDLL(shamr.LIB_PATH)
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert declared == set(shamr.EXPORTED)
+
+
+def test_arena_bytes_and_argument_checks(shamr):
+    lib = shamr.load()
+    p = shamr.sh_params(64, 64.0, 0.25, 0.1, 1.0, 2.0, 2, 2, 8, 64, 2, shamr.SH_F64)
+    b = np.array([0, 0, 0, 63, 63, 63], np.int32)
+    ptr = b.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    n64 = lib.sh_arena_bytes(ctypes.byref(p), 0, 1, ptr)
+    # 3 FP64 slots + FP64 accumulator of a 66^2 x ~ (8+64+1 -> 80) padded box, plus masks
+    assert n64 >= 4 * 4 * 66 * 66 * 80 * 8
+    p.prec = shamr.SH_F32
+    n32 = lib.sh_arena_bytes(ctypes.byref(p), 0, 1, ptr)
+    assert n32 < n64
+    bad = np.array([0, 0, 0, 64, 63, 63], np.int32)    # outside the level
+    assert lib.sh_arena_bytes(ctypes.byref(p), 0, 1, bad.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))) == 0
+    odd = np.array([1, 0, 0, 8, 7, 7], np.int32)       # refined level boxes start even
+    assert lib.sh_arena_bytes(ctypes.byref(p), 1, 1, odd.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))) == 0
+    two = np.array([0, 0, 0, 7, 7, 7, 4, 4, 4, 11, 11, 11], np.int32)   # overlapping
+    assert lib.sh_arena_bytes(ctypes.byref(p), 1, 2, two.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))) == 0
+    p.blocking_factor = 3
+    assert lib.sh_arena_bytes(ctypes.byref(p), 0, 1, ptr) == 0
+
+
+def test_create_without_device_fails_cleanly(shamr):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    lib = shamr.load()
+    p = shamr.sh_params(16, 16.0, 0.25, 0.1, 1.0, 2.0, 2, 0, 8, 64, 2, 0)
+    h = ctypes.c_void_p()
+    assert lib.sh_hierarchy_create(ctypes.byref(p), None, ctypes.byref(h)) == shamr.SH_EDEVICE
+    assert b"device" in lib.sh_last_error()
+
+
+@pytest.mark.parametrize("seed,nbuf,bf,max_box", [(1, 2, 8, 16), (2, 1, 8, 32), (3, 3, 16, 32)])
+def test_clustering_gives_proper_layouts(shamr, seed, nbuf, bf, max_box):
+    n0 = 32
+    U = string_loop_state(n0, float(n0), seed=seed, nloops=2, rmin=4.0, rmax=6.0, taper_in=2.0, taper_out=9.0)
+    tags = tag_cells(U[0], U[1])
+    idx = np.argwhere(tags)[:, ::-1]               # (x, y, z)
+    cv = np.ones((n0,) * 3, bool)
+    boxes = shamr.cluster_boxes(n0, [], idx, bf, max_box, nbuf, 0.7)
+    assert boxes
+    assert check_layout(boxes, 2 * n0, cv, bf, max_box, tags, nbuf) == []
+    # a second level clustered inside the first stays nested with the gap
+    M1 = 2 * n0
+    lev1 = boxes_mask(boxes, M1)
+    t1 = np.zeros((M1,) * 3, np.uint8)
+    t1[lev1] = 1                                    # tag everything refined
+    idx1 = np.argwhere(t1)[:, ::-1]
+    boxes2 = shamr.cluster_boxes(M1, boxes, idx1, bf, max_box, nbuf, 0.7)
+    assert check_layout(boxes2, 2 * M1, lev1, bf, max_box) == []
+    assert len(boxes2) > 0 or coarsen_mask(lev1).sum() < 64
+
+
+def test_clustering_efficiency_and_empty(shamr):
+    assert shamr.cluster_boxes(32, [], np.zeros((0, 3), np.int32)) == []
+    # two far-apart tags must not be merged into one big box at efficiency 0.7
+    b = shamr.cluster_boxes(64, [], [(3, 3, 3), (60, 60, 60)], 8, 64, 0, 0.7)
+    assert len(b) >= 2
+    vol = sum((x[3] - x[0] + 1) * (x[4] - x[1] + 1) * (x[5] - x[2] + 1) for x in b)
+    assert vol <= 2 * 8**3 * 8
+
+
+def test_clustering_rejects_bad_input(shamr):
+    with pytest.raises(shamr.ShError):
+        shamr.cluster_boxes(32, [], [(40, 0, 0)])

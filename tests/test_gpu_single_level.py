@@ -1,0 +1,180 @@
+"""GPU parity of the single-level path (ghost copy A1, RK4 stage A3, energy A6) against
+the oracle, through the C-ABI.  FP64 fields must match the oracle bit for bit (the two
+sides evaluate the same expressions in the same order without FMA); NaN/Inf positions
+of the diverging literal configuration must match too."""
+import numpy as np
+import pytest
+
+from oracle.energy import energy as oracle_energy
+from oracle.level import lap7, run_single_level
+from oracle.scalars import level_time, rk4_weights, stage_scalars
+from synth import gaussian_random_pair, plane_wave, quadratic_field, random_state, state_from_psi
+
+pytestmark = pytest.mark.gpu
+
+shamr = pytest.importorskip("paper_2404_02950_amd.shamr")
+from gpu_util import assert_bitwise, decompose, single_level  # noqa: E402
+
+
+def test_device_stage_scalars_match_host_definitions():
+    U0 = random_state(8, 8.0, 0)
+    for eta0, cfl, L, lam, alpha, beta in [(0.1, 0.25, 8.0, 1.0, 2.0, 2), (0.37, 0.3, 15.0, 0.7, 3.0, 0),
+                                           (1.3, 0.32, 8.0, 2.5, 2.0, 3)]:
+        h = single_level(U0, L=L, cfl=cfl, eta0=eta0, lam=lam, alpha=alpha, beta=beta)
+        dt = cfl * (L / 8)
+        for k in range(3):
+            for s in range(4):
+                got = h.stage_scalars(0, s)
+                eta_s, cf, cp = stage_scalars(level_time(eta0, k, dt), dt, s, alpha, lam, beta)
+                want = [eta_s, cf, cp, *rk4_weights(dt)]
+                assert got == want, (k, s, got, want)
+            h.advance(0)
+        h.close()
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_c0_literal_64cube_100_steps_bitwise(seed):
+    # configs[0]: 64^3, L = 64, dt = 1/4, eta from 0.1, 100 steps, lambda = 1, beta = 2
+    U0 = random_state(64, 64.0, seed)
+    h = single_level(U0)
+    checkpoints = {1, 10, 30, 50, 100}
+    ref = {}
+    run_single_level(U0, 100, 0.1, 0.25, 1.0, callback=lambda k, U: ref.__setitem__(k, U.copy()) if k in checkpoints else None)
+    for k in range(1, 101):
+        h.advance(0)
+        if k in checkpoints:
+            assert_bitwise(h.read_dense(0), ref[k], f"step {k}")
+    assert h.level_info(0)["k"] == 100
+    h.close()
+
+
+def test_stable_companion_energy_and_decomposition_invariance():
+    # beta = 0 (constant comoving core): finite throughout; a 3x2x4 uneven box
+    # decomposition must give the single-box result bit for bit
+    n = 48
+    U0 = random_state(n, float(n), 3)
+    a = single_level(U0, beta=0)
+    b = single_level(U0, beta=0, boxes=decompose(n, [[8, 24], [16], [8, 16, 40]]))
+    ref = run_single_level(U0, 12, 0.1, 0.25, 1.0, beta=0)
+    for _ in range(12):
+        a.advance(0)
+        b.advance(0)
+    Ua, Ub = a.read_dense(0), b.read_dense(0)
+    assert_bitwise(Ua, ref, "single box")
+    assert_bitwise(Ub, ref, "multi box")
+    e, bad = b.energy()
+    want = oracle_energy(ref, 1.0, 1.0 * 1.0)   # c_pot = lambda * eta^0
+    assert bad == 0
+    np.testing.assert_allclose(e, want, rtol=1e-12)
+    a.close()
+    b.close()
+
+
+@pytest.mark.parametrize("n,cuts", [(40, None), (24, [[8], [16], [8]]), (16, [[8], [8], [8]])])
+def test_ragged_and_small_boxes_bitwise(n, cuts):
+    # 40^3: 64-wide wave rows with 24 idle lanes and a ragged z tail; 8^3 / 8x16 boxes
+    U0 = random_state(n, float(n), 5)
+    h = single_level(U0, boxes=decompose(n, cuts), beta=0)
+    ref = run_single_level(U0, 6, 0.1, 0.25, 1.0, beta=0)
+    for _ in range(6):
+        h.advance(0)
+    assert_bitwise(h.read_dense(0), ref, f"n={n}")
+    h.close()
+
+
+def test_fp32_storage_matches_fp32_oracle_and_error_vs_fp64():
+    n = 32
+    U0 = random_state(n, float(n), 7)
+    h = single_level(U0, prec=shamr.SH_F32, beta=0)
+    ref32 = run_single_level(U0.astype(np.float32), 20, 0.1, 0.25, 1.0, beta=0)
+    ref64 = run_single_level(U0, 20, 0.1, 0.25, 1.0, beta=0)
+    for _ in range(20):
+        h.advance(0)
+    got = h.read_dense(0)
+    assert_bitwise(got, ref32.astype(np.float64), "fp32")
+    rel = np.max(np.abs(got - ref64)) / np.max(np.abs(ref64))
+    assert rel < 1e-5, rel
+    h.close()
+
+
+def test_laplacian_of_quadratic_exact_on_gpu():
+    # ghosts written directly: the 7-point Laplacian of an integer quadratic is 2(a+b+c)
+    n = 16
+    coeffs = (3, -1, 2, 5, -4, 7)
+    q = quadratic_field((n + 2, n + 2, n + 2), coeffs, origin=(-1, -1, -1))
+    U = np.zeros((4, n + 2, n + 2, n + 2))
+    U[0] = q
+    U[1] = -q
+    h = shamr.Hierarchy(n, float(n), 0.25, 0.1, 0.0, 0.0, 0, max_level=0)
+    h.set_layout(0, decompose(n))
+    h.write_boxes(0, [U], ghosts=True)
+    k = h.eval_rhs(0)[0]
+    assert np.all(k[2] == 2.0 * (3 - 1 + 2))
+    assert np.all(k[3] == -2.0 * (3 - 1 + 2))
+    assert np.all(k[0] == 0.0) and np.all(k[1] == 0.0)
+    h.close()
+
+
+def test_free_field_plane_wave_exact_discrete_solution_on_gpu():
+    n, L, dt = 32, 32.0, 0.25
+    k = 2 * np.pi / L * np.array([3.0, -2.0, 1.0])
+    omega = np.sqrt(4.0 * np.sum(np.sin(k / 2) ** 2))
+    cosk = plane_wave(n, L, k)
+    U0 = state_from_psi(cosk, np.zeros_like(cosk))
+    h = single_level(U0, lam=0.0, alpha=0.0, beta=0)
+    nsteps = 40
+    for _ in range(nsteps):
+        h.advance(0)
+    y = omega * dt
+    J = np.array([[0.0, 1.0], [-omega**2, 0.0]])
+    M = (1 - y * y / 2 + y**4 / 24) * np.eye(2) + (dt - omega**2 * dt**3 / 6) * J
+    a, b = np.linalg.matrix_power(M, nsteps) @ np.array([1.0, 0.0])
+    U = h.read_dense(0)
+    np.testing.assert_allclose(U[0], a * cosk, atol=1e-11)
+    np.testing.assert_allclose(U[2], b * cosk, atol=1e-11)
+    h.close()
+
+
+def test_energy_matches_oracle_fp64():
+    n = 32
+    p1, p2 = gaussian_random_pair(n, float(n), 9)
+    rng = np.random.default_rng(1)
+    U0 = state_from_psi(p1, p2, 0.3 * rng.standard_normal(p1.shape), 0.3 * rng.standard_normal(p1.shape))
+    h = single_level(U0)
+    e, bad = h.energy()
+    want = oracle_energy(U0, 1.0, 0.1 * 0.1)
+    np.testing.assert_allclose(e, want, rtol=1e-12)
+    assert bad == 0
+    h.close()
+
+
+def test_full_size_512_sampled_parity():
+    # configs[1] at full size, the launch configuration bench.py times: 2 steps, then
+    # sampled cells against the oracle run on periodic crops around each sample (after 2
+    # RK4 steps a cell depends only on cells within 8 of it)
+    n = 512
+    U0 = random_state(n, float(n), 0)
+    h = single_level(U0)
+    h.advance(0)
+    h.advance(0)
+    got = h.read_boxes(0)[0]
+    rng = np.random.default_rng(11)
+    samples = [tuple(rng.integers(0, n, 3)) for _ in range(6)] + [(0, 0, 0), (n - 1, n - 1, n - 1)]
+    r = 12
+    for (z, y, x) in samples:
+        iz = np.arange(z - r, z + r + 1) % n
+        iy = np.arange(y - r, y + r + 1) % n
+        ix = np.arange(x - r, x + r + 1) % n
+        crop = U0[:, iz][:, :, iy][:, :, :, ix]
+        ref = run_single_level(crop, 2, 0.1, 0.25, 1.0)
+        c = slice(r - 3, r + 4)
+        want = ref[:, c, c, c]
+        g = got[:, iz[c]][:, :, iy[c]][:, :, :, ix[c]]
+        assert_bitwise(g, want, f"sample {(z, y, x)}")
+    h.close()
+
+
+def test_lap7_reference_consistency():
+    # the oracle Laplacian used above is the 7-point one (sanity, CPU arithmetic only)
+    u = quadratic_field((6, 6, 6), (1, 1, 1, 0, 0, 0))
+    assert np.all(lap7(u, 1.0)[1:-1, 1:-1, 1:-1] == 6.0)
