@@ -68,6 +68,8 @@ def main():
     ap.add_argument("--prec", choices=("f64", "f32"), default="f64")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run a plain 2 GiB device copy (calibrates rocprofv3 byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU path is a design, "
@@ -149,6 +151,15 @@ def main():
     else:
         out["cpu_baseline"] = None
     h.close()
+    if args.calib_copy:
+        a = torch.empty(2 ** 28, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        a.fill_(1.0)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        out["calib_copy_bytes"] = 2 * a.numel() * 8
+        del a, b
     print(json.dumps(out), flush=True)
 
 

@@ -192,12 +192,13 @@ __global__ void k_counter_inc(LevelScal* ls, int n) {
 }
 
 // ---------------------------------------------------------------------------------
-// A1: same-level ghost copy of the psi components (periodic images included).
+// A1: same-level ghost copy (periodic images included) of the first ncomp components:
+// the psi pair on the stepping path, all four before a regrid interpolates from them.
 // ---------------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(SH_BLOCK) void k_ghost_copy(const CopySeg* __restrict__ segs,
                                                          const SegBlock* __restrict__ blocks,
-                                                         const BoxDev* __restrict__ boxes, int role) {
+                                                         const BoxDev* __restrict__ boxes, int role, int ncomp) {
   const SegBlock sb = blocks[blockIdx.x];
   const CopySeg s = segs[sb.seg];
   const int c = sb.start + threadIdx.x;
@@ -213,8 +214,7 @@ __global__ __launch_bounds__(SH_BLOCK) void k_ghost_copy(const CopySeg* __restri
   const T* src = (const T*)Sb.slot[role_slot(role, kk)];
   const long long ed = elem<T>(D, s.dlo[0] + i, s.dlo[1] + j, s.dlo[2] + k);
   const long long es = elem<T>(Sb, s.slo[0] + i, s.slo[1] + j, s.slo[2] + k);
-  dst[ed] = src[es];
-  dst[D.cs + ed] = src[Sb.cs + es];
+  for (int comp = 0; comp < ncomp; ++comp) dst[comp * D.cs + ed] = src[comp * Sb.cs + es];
 }
 
 // ---------------------------------------------------------------------------------
@@ -664,10 +664,12 @@ void sh_launch_counter_inc(LevelScal* ls, int n, hipStream_t st) {
 }
 
 void sh_launch_ghost_copy(int prec, const CopySeg* segs, const SegBlock* blocks, int nblocks, const BoxDev* boxes,
-                          int role, hipStream_t st) {
+                          int role, int ncomp, hipStream_t st) {
   if (nblocks == 0) return;
-  if (prec == 0) hipLaunchKernelGGL(k_ghost_copy<double>, dim3(nblocks), dim3(SH_BLOCK), 0, st, segs, blocks, boxes, role);
-  else hipLaunchKernelGGL(k_ghost_copy<float>, dim3(nblocks), dim3(SH_BLOCK), 0, st, segs, blocks, boxes, role);
+  if (prec == 0)
+    hipLaunchKernelGGL(k_ghost_copy<double>, dim3(nblocks), dim3(SH_BLOCK), 0, st, segs, blocks, boxes, role, ncomp);
+  else
+    hipLaunchKernelGGL(k_ghost_copy<float>, dim3(nblocks), dim3(SH_BLOCK), 0, st, segs, blocks, boxes, role, ncomp);
 }
 
 void sh_launch_ghost_interp(int prec, const InterpSeg* segs, const SegBlock* blocks, int nblocks,

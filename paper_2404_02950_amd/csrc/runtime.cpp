@@ -457,11 +457,11 @@ static sh_status build_links(sh_hierarchy h, int l) {
 // ---------------------------------------------------------------------------------
 // Level step pieces
 // ---------------------------------------------------------------------------------
-static sh_status same_level_fill(sh_hierarchy h, int l, int role) {
+static sh_status same_level_fill(sh_hierarchy h, int l, int role, int ncomp = 2) {
   Level& L = h->lev[l];
   h->rec(2, l, role, 0);
   hipEvent_t ev = h->prof_begin();
-  sh_launch_ghost_copy(h->p.prec, L.a1.segs.p, L.a1.blocks.p, L.a1.nblocks(), L.dbox.p, role, h->st);
+  sh_launch_ghost_copy(h->p.prec, L.a1.segs.p, L.a1.blocks.p, L.a1.nblocks(), L.dbox.p, role, ncomp, h->st);
   h->prof_end(ev, 4);
   LAUNCHCHK();
   return SH_OK;
@@ -688,6 +688,10 @@ sh_status sh_set_level_layout(sh_hierarchy h, int32_t l, int32_t nboxes, const i
     LAUNCHCHK();
   }
   if (l > 0) {
+    // the slopes of the interpolation read the coarse level's same-level ghosts of all
+    // four components (the stepping path keeps only the psi pair there)
+    s = same_level_fill(h, l - 1, ROLE_UN, 4);
+    if (s != SH_OK) return s;
     sh_launch_ghost_interp(p.prec, fresh.segs.p, fresh.blocks.p, fresh.nblocks(), N.dbox.p, h->lev[l - 1].dbox.p,
                            ROLE_UN, 4, 4, h->st);
     LAUNCHCHK();

@@ -10,7 +10,7 @@ void sh_launch_rhs(int prec, const Tile* tiles, int ntiles, const BoxDev* boxes,
                    double* out, hipStream_t st);
 void sh_launch_counter_inc(LevelScal* ls, int n, hipStream_t st);
 void sh_launch_ghost_copy(int prec, const CopySeg* segs, const SegBlock* blocks, int nblocks, const BoxDev* boxes,
-                          int role, hipStream_t st);
+                          int role, int ncomp, hipStream_t st);
 void sh_launch_ghost_interp(int prec, const InterpSeg* segs, const SegBlock* blocks, int nblocks,
                             const BoxDev* fboxes, const BoxDev* cboxes, int role, int anum, int ncomp,
                             hipStream_t st);
