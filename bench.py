@@ -27,25 +27,33 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
 # algorithmic bytes per cell of the fused stage kernel, stages 1-4 (each array element
 # moved once: 12/20/20/12 values; FP32-mixed keeps the accumulator in FP64)
 STAGE_BYTES = {"f64": (96, 160, 160, 96), "f32": (64, 112, 112, 64)}
+# the fused four-stage step reads U_n and writes U_{n+1}: 8 values per cell
+FUSED_BYTES = {"f64": 64, "f32": 32}
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def traffic_from_profiles(prec: str, n: int):
-    """HBM bytes per stage launch from the committed rocprofv3 counter summary, if it was
-    taken on the current kernel source; None otherwise."""
+def kernel_source_sha() -> str:
     import hashlib
-    path = os.path.join(ROOT, "profiles", f"stage_kernel_{n}cubed_{prec}_traffic.json")
-    src = os.path.join(ROOT, "paper_2404_02950_amd", "csrc", "kernels.hip")
+    d = os.path.join(ROOT, "paper_2404_02950_amd", "csrc")
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "kernels_fused.hip", "sh_device.h", "sh_internal.h"):
+        h.update(open(os.path.join(d, f), "rb").read())
+    return h.hexdigest()
+
+
+def traffic_from_profiles(prec: str, n: int, kname: str):
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel sources; None otherwise."""
+    path = os.path.join(ROOT, "profiles", f"{kname}_{n}cubed_{prec}_traffic.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    if rec.get("kernels_hip_sha256") != sha:
+    if rec.get("kernel_source_sha256") != kernel_source_sha():
         return None
-    return rec.get("bytes_per_launch_mean")
+    return rec.get("hbm_bytes_per_launch")
 
 
 def cpu_baseline(U0, n: int):
@@ -116,13 +124,19 @@ def main():
     cells = n ** 3
     value = cells * 4 * K / (ms / 1e3)
     sb = STAGE_BYTES[args.prec]
-    st_ms = sum(prof[f"stage{s + 1}"][0] for s in range(4))
-    st_n = sum(prof[f"stage{s + 1}"][1] for s in range(4))
-    st_bytes = sum(sb[s] * cells * prof[f"stage{s + 1}"][1] for s in range(4))
-    achieved = st_bytes / (st_ms / 1e3) / 1e9
-    traffic = traffic_from_profiles(args.prec, n)
-    log(f"{ms / K:.3f} ms/step (event), wall {wall / K * 1e3:.3f} ms/step; stage kernel "
-        f"{st_ms / st_n:.3f} ms/launch, {achieved:.0f} GB/s; energy {e[3]:.6g}, nonfinite cells {bad}")
+    if prof["fused_step"][1]:
+        kname = "fused_rk4_step"
+        k_ms, k_n = prof["fused_step"]
+        k_bytes = FUSED_BYTES[args.prec] * cells * k_n
+    else:
+        kname = "rk4_stage"
+        k_ms = sum(prof[f"stage{s + 1}"][0] for s in range(4))
+        k_n = sum(prof[f"stage{s + 1}"][1] for s in range(4))
+        k_bytes = sum(sb[s] * cells * prof[f"stage{s + 1}"][1] for s in range(4))
+    achieved = k_bytes / (k_ms / 1e3) / 1e9
+    traffic = traffic_from_profiles(args.prec, n, kname)
+    log(f"{ms / K:.3f} ms/step (event), wall {wall / K * 1e3:.3f} ms/step; {kname} kernel "
+        f"{k_ms / k_n:.3f} ms/launch, {achieved:.0f} GB/s algorithmic; energy {e[3]:.6g}, nonfinite cells {bad}")
     out = {
         "metric": "cell-updates/s per RK stage",
         "value": value,
@@ -139,7 +153,7 @@ def main():
         "config": {"workload": f"single-level periodic {n}^3, RK4 + 7-point Laplacian, "
                                f"{'FP64' if args.prec == 'f64' else 'FP32 storage / FP64 accumulation'}",
                    "lattice": n, "dx": 1.0, "dt": 0.25, "eta0": 0.1, "lambda": 1.0, "seed": args.seed},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "roofline": {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
         "kernel_ms": {k: (v[0] / v[1] if v[1] else None) for k, v in prof.items() if v[1]},
         "wall_ms_per_step": wall / K * 1e3,
@@ -157,8 +171,11 @@ def main():
         a.fill_(1.0)
         for _ in range(3):
             b.copy_(a)
+        s = a.sum()
         torch.cuda.synchronize()
         out["calib_copy_bytes"] = 2 * a.numel() * 8
+        out["calib_sum_read_bytes"] = a.numel() * 8
+        del s
         del a, b
     print(json.dumps(out), flush=True)
 

@@ -190,12 +190,25 @@ const char* sh_last_error(void);
    out[0..6] = {eta_s, c_fric, c_pot, dt/6, dt/3, dt/2, dt}.  Diagnostic. */
 sh_status sh_debug_stage_scalars(sh_hierarchy h, int32_t lev, int32_t s, double* out_host);
 
+/* Launch shape (performance only; results are identical for every choice):
+   kind 0 = per-stage kernel with one wavefront per 64-cell tile for every box, 4 or 8 =
+   blocks of that many wavefront rows sharing psi through LDS for boxes at least 64
+   cells wide; nontemporal 1 = once-used streams do not stay cache resident; tile_z =
+   cells per per-stage tile in z (0 = from the level size); fuse 4 = level 0 takes each
+   step in one kernel computing all four RK stages (temporal blocking; needs every
+   level-0 box to be a multiple of the fused footprint, else per-stage), 0 = per-stage
+   kernels; fused_shape 0 = 32 x 8 footprint, 1 = 64 x 4; fused_tile_z = planes per fused
+   tile.  Applies to every level.  The environment variable SHAMR_TUNE (e.g.
+   "kind=8,nt=1,zc=0,fuse=4,fshape=0,fzc=64") sets the defaults at creation. */
+sh_status sh_set_tuning(sh_hierarchy h, int32_t kind, int32_t nontemporal, int32_t tile_z, int32_t fuse,
+                        int32_t fused_shape, int32_t fused_tile_z);
+
 /* Per-kernel timing (diagnostic).  sh_profile(h, 1) clears the totals and brackets every
    launch that sh_advance_level and sh_average_down issue with HIP events on the
    hierarchy's stream; sh_profile(h, 0) stops.  sh_profile_read fills ms[8] (summed
    event time) and counts[8] (launches) per class: 0-3 = RK stage 1-4 kernel, 4 =
    same-level ghost copy, 5 = coarse/fine ghost interpolation, 6 = average down,
-   7 = unused.  Reading synchronises the stream. */
+   7 = fused four-stage step kernel.  Reading synchronises the stream. */
 sh_status sh_profile(sh_hierarchy h, int32_t enable);
 sh_status sh_profile_read(sh_hierarchy h, double* ms, int64_t* counts);
 

@@ -28,7 +28,7 @@ HIP_FLAGS = [
 ]
 HOST_FLAGS = ["-O2", "-fPIC", "-std=c++17", "-ffp-contract=off", "-Wall"]
 
-HIP_SOURCES = ["kernels.hip", "runtime.cpp"]
+HIP_SOURCES = ["kernels.hip", "kernels_fused.hip", "runtime.cpp"]
 HOST_SOURCES = ["cluster.cpp"]
 
 

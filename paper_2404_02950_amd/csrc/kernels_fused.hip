@@ -1,0 +1,234 @@
+// Fused RK4 step: the four stages of a step in one kernel (temporal blocking).
+//
+// The arithmetic is exactly that of the per-stage kernel (same expressions, same order,
+// stage states rounded to the storage type between stages), so the results are the same
+// bit for bit; only the data movement changes.  The per-stage form moves 64 values per
+// cell and step through HBM (U_n, stage states and the accumulator, 12/20/20/12 per
+// stage); fused, each step reads U_n and writes U_{n+1} once: 8 values per cell.
+//
+// Scheme.  A block owns a TX x TY column footprint of a box and marches up a range of zc
+// planes.  Stage j (0..3) of plane p runs in iteration p + j, after stage j-1 of plane
+// p+1 (its z+1 neighbour) in the same iteration, so each stage keeps a three-plane
+// window of its input column in registers.  In x and y a stage needs its input one cell
+// beyond where it is computed, so stage j is computed on the footprint grown by 3 - j
+// cells (overlapped tiles), and the threads cover the footprint grown by 4 cells, the
+// outermost ring only loading U_n.  Each iteration every stage publishes its input plane
+// to LDS, one barrier, then stages 0..3 run in order reading x/y neighbours from LDS.
+// The z-range is extended the same way (stage j covers 3 - j extra planes below and
+// above), so U_n is read from z0-4 to z0+zc+3: the level keeps a 4-deep ghost shell.
+// The accumulator lives in registers: it exists only on the footprint's own columns.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sh_device.h"
+#include "sh_internal.h"
+#include "sh_launch.h"
+
+#pragma clang fp contract(off)
+
+namespace {
+
+constexpr int FD = 4;       // fused stages
+constexpr int FG = FD - 1;  // compute ring of stage 0 beyond the footprint
+
+template <typename T, int TX, int TY>
+struct FusedShape {
+  static constexpr int W = TX + 2 * FD;  // thread columns in x (incl. the loader ring)
+  static constexpr int H = TY + 2 * FD;
+  static constexpr int NTH = W * H;
+  static constexpr int NBLK = (NTH + SH_WAVE - 1) / SH_WAVE * SH_WAVE;
+};
+
+}  // namespace
+
+template <typename T, bool NT, int TX, int TY>
+__global__ __launch_bounds__((FusedShape<T, TX, TY>::NBLK)) void k_fused_rk4(const Tile* __restrict__ tiles,
+                                                                           int ntiles,
+                                                                           const BoxDev* __restrict__ boxes) {
+  using Sh = FusedShape<T, TX, TY>;
+  constexpr int W = Sh::W, H = Sh::H;
+  __shared__ T sm[FD][2][H][W];
+
+  const int t = xcd_remap(blockIdx.x, gridDim.x);
+  if (t >= ntiles) return;  // uniform
+  const Tile tl = tiles[t];
+  if (tl.box < 0) return;
+  const BoxDev B = boxes[tl.box];
+  const LevelScal L = *B.ls;
+  StageScal sc[FD];
+#pragma unroll
+  for (int j = 0; j < FD; ++j) sc[j] = stage_scalars(L, j);
+  const T* __restrict__ X = (const T*)B.slot[role_slot(ROLE_UN, L.k)];
+  T* __restrict__ Y = (T*)B.slot[role_slot(ROLE_B, L.k)];
+
+  const int tid = threadIdx.x;
+  const bool inreg = tid < Sh::NTH;
+  const int cx = inreg ? tid % W : FD, cy = inreg ? tid / W : FD;
+  const int ox = cx - FD, oy = cy - FD;  // footprint-relative
+  const int rx = ox < 0 ? -ox : (ox >= TX ? ox - TX + 1 : 0);
+  const int ry = oy < 0 ? -oy : (oy >= TY ? oy - TY + 1 : 0);
+  const int r = inreg ? max(rx, ry) : FD + 1;  // ring distance; > FD: idle thread
+  const int x0 = tl.xy & 0xffff, y0 = tl.xy >> 16;
+  const int z0 = tl.zz & 0xffff, zc = tl.zz >> 16;
+  // footprints tile the box exactly and the ghost shell is FD deep: every column a
+  // thread loads lies in [-FD, n + FD); idle threads load the footprint's first column
+  const int x = x0 + (r <= FD ? ox : 0), y = y0 + (r <= FD ? oy : 0);
+  const long long plane = (long long)B.px * B.py;
+  const long long cs = B.cs;
+  const long long ecol = elem<T>(B, x, y, 0);
+  const int zlo = -B.ng, zhi = B.nz + B.ng - 1;
+  auto eat = [&](int z) { return ecol + (long long)min(max(z, zlo), zhi) * plane; };
+
+  const int ifirst = z0 - FG, ilast = z0 + zc - 1 + FG;
+  // stage 0 input window (planes i-1, i, i+1), next psi plane and Pi of planes i, i+1
+  T w0[3][2], nx2[2], q0c[2], q0n[2];
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    w0[0][c] = X[c * cs + eat(ifirst - 1)];
+    w0[1][c] = X[c * cs + eat(ifirst)];
+    w0[2][c] = X[c * cs + eat(ifirst + 1)];
+    nx2[c] = X[c * cs + eat(ifirst + 2)];
+    q0c[c] = ld<NT>(X + (2 + c) * cs + eat(ifirst));
+    q0n[c] = ld<NT>(X + (2 + c) * cs + eat(ifirst + 1));
+  }
+  // later stages: input windows and their Pi at planes (p, p+1); U_n of planes i-1, i-2
+  T wj[FD][3][2], qj[FD][2][2];
+  T un1[4], un2[4];
+  double acc[FD][4];
+#pragma unroll
+  for (int j = 0; j < FD; ++j)
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      wj[j][0][c] = wj[j][1][c] = wj[j][2][c] = (T)0;
+      qj[j][0][c] = qj[j][1][c] = (T)0;
+    }
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    un1[c] = un2[c] = (T)0;
+#pragma unroll
+    for (int j = 0; j < FD; ++j) acc[j][c] = 0.0;
+  }
+
+  for (int i = ifirst; i <= ilast; ++i) {
+    // U_n at plane i (for the updates of stages 1 and 2 one and two iterations later)
+    const T un0[4] = {w0[1][0], w0[1][1], q0c[0], q0c[1]};
+    // publish every stage's input plane: stage 0 = U_n psi at i, stage j = its window top
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      if (r <= FD) sm[0][c][cy][cx] = w0[1][c];
+#pragma unroll
+      for (int j = 1; j < FD; ++j)
+        if (r <= FD - j) sm[j][c][cy][cx] = wj[j][2][c];
+    }
+    __syncthreads();
+    // outputs of the stage just computed (input of the next one)
+    T out[4];
+#pragma unroll
+    for (int j = 0; j < FD; ++j) {
+      // stage j runs from iteration ifirst + 2j on; before that its window fills with the
+      // planes stage j-1 produces (the conditions are uniform over the block)
+      if (j > 0) {
+        if (i < ifirst + 2 * (j - 1)) break;
+        // push stage j-1's output plane (p+1) into stage j's window
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          wj[j][0][c] = wj[j][1][c];
+          wj[j][1][c] = wj[j][2][c];
+          wj[j][2][c] = out[c];
+          qj[j][0][c] = qj[j][1][c];
+          qj[j][1][c] = out[2 + c];
+        }
+      }
+      if (i < ifirst + 2 * j) break;
+      if (r > FG - j) continue;
+      const T(*w)[2] = (j == 0) ? w0 : wj[j];
+      const T q0 = (j == 0) ? q0c[0] : qj[j][0][0];
+      const T q1 = (j == 0) ? q0c[1] : qj[j][0][1];
+      const T idx2 = (T)sc[j].inv_dx2, cf = (T)sc[j].cf, cp = (T)sc[j].cp;
+      T lap[2];
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        const T xm = sm[j][c][cy][cx - 1], xp = sm[j][c][cy][cx + 1];
+        const T ym = sm[j][c][cy - 1][cx], yp = sm[j][c][cy + 1][cx];
+        lap[c] = ((((xm + xp) + (ym + yp)) + (w[0][c] + w[2][c])) - (T)6.0 * w[1][c]) * idx2;
+      }
+      const T p0 = w[1][0], p1 = w[1][1];
+      const T r2 = p0 * p0 + p1 * p1;
+      const T pot = cp * (r2 - (T)1.0);
+      const T kq0 = (lap[0] - cf * q0) - pot * p0;
+      const T kq1 = (lap[1] - cf * q1) - pot * p1;
+      const double k4[4] = {(double)q0, (double)q1, (double)kq0, (double)kq1};
+      const T xin[4] = {p0, p1, q0, q1};
+      const bool own = (r == 0);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        if (j == 0) {
+          const double u = (double)xin[c];
+          if (own) acc[0][c] = u + sc[0].h6 * k4[c];
+          out[c] = (T)(u + sc[0].h2 * k4[c]);
+        } else if (j == 1) {
+          if (own) acc[1][c] = acc[1][c] + sc[1].h3 * k4[c];
+          out[c] = (T)((double)un1[c] + sc[1].h2 * k4[c]);
+        } else if (j == 2) {
+          if (own) acc[2][c] = acc[2][c] + sc[2].h3 * k4[c];
+          out[c] = (T)((double)un2[c] + sc[2].h1 * k4[c]);
+        } else {
+          out[c] = (T)(acc[3][c] + sc[3].h6 * k4[c]);
+        }
+      }
+      if (j == FD - 1 && own) {
+        const long long e = eat(i - FG);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) st<NT>(Y + c * cs + e, out[c]);
+      }
+    }
+    __syncthreads();
+    // advance the register pipelines by one plane
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      acc[3][c] = acc[2][c];
+      acc[2][c] = acc[1][c];
+      acc[1][c] = acc[0][c];
+      un2[c] = un1[c];
+      un1[c] = un0[c];
+    }
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      w0[0][c] = w0[1][c];
+      w0[1][c] = w0[2][c];
+      w0[2][c] = nx2[c];
+      nx2[c] = X[c * cs + eat(i + 3)];
+      q0c[c] = q0n[c];
+      q0n[c] = ld<NT>(X + (2 + c) * cs + eat(i + 2));
+    }
+  }
+}
+
+template <typename T, bool NT>
+static void fused_launch(int shape, const Tile* tiles, int ntiles, const BoxDev* boxes, hipStream_t st) {
+  if (ntiles == 0) return;
+  if (shape == 0) {
+    using Sh = FusedShape<T, 32, 8>;
+    hipLaunchKernelGGL((k_fused_rk4<T, NT, 32, 8>), dim3(ntiles), dim3(Sh::NBLK), 0, st, tiles, ntiles, boxes);
+  } else {
+    using Sh = FusedShape<T, 64, 4>;
+    hipLaunchKernelGGL((k_fused_rk4<T, NT, 64, 4>), dim3(ntiles), dim3(Sh::NBLK), 0, st, tiles, ntiles, boxes);
+  }
+}
+
+// Footprint of a fused tile for shape 0 (32 x 8) and 1 (64 x 4).
+void sh_fused_footprint(int shape, int* tx, int* ty) {
+  *tx = shape == 0 ? 32 : 64;
+  *ty = shape == 0 ? 8 : 4;
+}
+
+void sh_launch_fused(int prec, bool nt, int shape, const Tile* tiles, int ntiles, const BoxDev* boxes,
+                     hipStream_t st) {
+  if (prec == 0) {
+    if (nt) fused_launch<double, true>(shape, tiles, ntiles, boxes, st);
+    else fused_launch<double, false>(shape, tiles, ntiles, boxes, st);
+  } else {
+    if (nt) fused_launch<float, true>(shape, tiles, ntiles, boxes, st);
+    else fused_launch<float, false>(shape, tiles, ntiles, boxes, st);
+  }
+}

@@ -84,7 +84,11 @@ struct SegPlan {
 // ---------------------------------------------------------------------------------
 // Level layout arithmetic (shared by sh_arena_bytes and sh_set_level_layout).
 // ---------------------------------------------------------------------------------
+// Ghost layers of level 0 (enough for four fused RK stages); refined levels keep one.
+#define SH_NG0 4
+
 struct LayoutGeom {
+  int ng = 1;                       // ghost layers
   int esize;                        // bytes of a stored value (8 or 4)
   int xoff;                         // elements before x = 0 in a row
   std::vector<long long> box_off;   // element offset of each box block
@@ -110,7 +114,8 @@ static int tile_zc_default(long long cells) {
   return (int)zc;
 }
 
-static void make_geom(int prec, const std::vector<IBox>& boxes, LayoutGeom& g) {
+static void make_geom(int prec, int ng, const std::vector<IBox>& boxes, LayoutGeom& g) {
+  g.ng = ng;
   g.esize = prec == SH_F64 ? 8 : 4;
   g.xoff = 64 / g.esize;
   g.box_off.clear();
@@ -121,8 +126,8 @@ static void make_geom(int prec, const std::vector<IBox>& boxes, LayoutGeom& g) {
   g.nvalid = 0;
   for (const IBox& b : boxes) {
     const int nx = b.size(0), ny = b.size(1), nz = b.size(2);
-    const int px = (int)round_up(g.xoff + nx + 1, g.xoff);
-    const long long cs = round_up((long long)px * (ny + 2) * (nz + 2), 64);
+    const int px = (int)round_up(g.xoff + nx + ng, g.xoff);
+    const long long cs = round_up((long long)px * (ny + 2 * ng) * (nz + 2 * ng), 64);
     g.box_off.push_back(g.E);
     g.px.push_back(px);
     g.cs.push_back(cs);
@@ -165,6 +170,107 @@ static void make_geom(int prec, const std::vector<IBox>& boxes, LayoutGeom& g) {
   g.total = o + 256;  // slack for aligning the arena base
 }
 
+// Stage-kernel launch shape.  kind: 0 = wave-row tiles for every box; 4 or 8 = block
+// rows of that many wavefronts for boxes at least 64 cells wide (narrower boxes keep
+// wave-row tiles).  nt: nontemporal once-used streams.  zc: cells per tile in z (0 =
+// chosen from the level size).
+// fuse: 4 = level 0 advances with the fused four-stage kernel when its boxes are
+// multiples of the fused footprint (fshape 0: 32 x 8, 1: 64 x 4), 0 = per-stage kernels.
+struct Tuning {
+  int kind = 8;
+  int nt = 1;
+  int zc = 0;
+  int fuse = 4;
+  int fshape = 0;
+  int fzc = 64;
+};
+
+static void tuning_from_env(Tuning& t) {
+  const char* env = std::getenv("SHAMR_TUNE");  // e.g. "kind=8,nt=1,zc=32"
+  if (!env) return;
+  std::string s(env);
+  size_t pos = 0;
+  while (pos < s.size()) {
+    size_t end = s.find(',', pos);
+    if (end == std::string::npos) end = s.size();
+    const std::string kv = s.substr(pos, end - pos);
+    const size_t eq = kv.find('=');
+    if (eq != std::string::npos) {
+      const std::string k = kv.substr(0, eq);
+      const int v = std::atoi(kv.c_str() + eq + 1);
+      if (k == "kind" && (v == 0 || v == 4 || v == 8)) t.kind = v;
+      if (k == "nt" && (v == 0 || v == 1)) t.nt = v;
+      if (k == "zc" && v >= 0 && v <= 1024) t.zc = v;
+      if (k == "fuse" && (v == 0 || v == 4)) t.fuse = v;
+      if (k == "fshape" && (v == 0 || v == 1)) t.fshape = v;
+      if (k == "fzc" && v >= 1 && v <= 1024) t.fzc = v;
+    }
+    pos = end + 1;
+  }
+}
+
+static void make_stage_tiles(const std::vector<IBox>& boxes, const Tuning& tu, long long nvalid,
+                             std::vector<Tile>& wt, std::vector<Tile>& bt) {
+  wt.clear();
+  bt.clear();
+  int zc = tu.zc > 0 ? tu.zc : tile_zc_default(nvalid);
+  for (size_t bi = 0; bi < boxes.size(); ++bi) {
+    const IBox& b = boxes[bi];
+    const int nx = b.size(0), ny = b.size(1), nz = b.size(2);
+    if (tu.kind != 0 && nx >= 64) {
+      const int R = tu.kind;
+      for (int z0 = 0; z0 < nz; z0 += zc)
+        for (int y0 = 0; y0 < ny; y0 += R)
+          for (int x0 = 0; x0 < nx; x0 += 64) {
+            Tile t;
+            t.box = (int)bi;
+            t.xy = x0 | (y0 << 16);
+            t.zz = z0 | (std::min(zc, nz - z0) << 16);
+            t.txs = 6;
+            bt.push_back(t);
+          }
+      continue;
+    }
+    int txs = 0;
+    while ((1 << txs) < nx && txs < 6) ++txs;
+    const int TX = 1 << txs, TY = 64 / TX;
+    for (int z0 = 0; z0 < nz; z0 += zc)
+      for (int y0 = 0; y0 < ny; y0 += TY)
+        for (int x0 = 0; x0 < nx; x0 += TX) {
+          Tile t;
+          t.box = (int)bi;
+          t.xy = x0 | (y0 << 16);
+          t.zz = z0 | (std::min(zc, nz - z0) << 16);
+          t.txs = txs;
+          wt.push_back(t);
+        }
+  }
+}
+
+// Tiles of the fused step; empty if some box is not a multiple of the footprint.
+static void make_fused_tiles(const std::vector<IBox>& boxes, const Tuning& tu, int ng, std::vector<Tile>& ft) {
+  ft.clear();
+  if (tu.fuse != 4 || ng < 4) return;
+  int TX, TY;
+  sh_fused_footprint(tu.fshape, &TX, &TY);
+  for (const IBox& b : boxes)
+    if (b.size(0) % TX || b.size(1) % TY) return;
+  for (size_t bi = 0; bi < boxes.size(); ++bi) {
+    const IBox& b = boxes[bi];
+    const int nx = b.size(0), ny = b.size(1), nz = b.size(2);
+    for (int z0 = 0; z0 < nz; z0 += tu.fzc)
+      for (int y0 = 0; y0 < ny; y0 += TY)
+        for (int x0 = 0; x0 < nx; x0 += TX) {
+          Tile t;
+          t.box = (int)bi;
+          t.xy = x0 | (y0 << 16);
+          t.zz = z0 | (std::min(tu.fzc, nz - z0) << 16);
+          t.txs = tu.fshape;
+          ft.push_back(t);
+        }
+  }
+}
+
 // ---------------------------------------------------------------------------------
 // Hierarchy
 // ---------------------------------------------------------------------------------
@@ -176,9 +282,12 @@ struct Level {
   char* base = nullptr;  // aligned arena base
   std::vector<BoxDev> hbox;
   DevArr<BoxDev> dbox;
-  DevArr<Tile> tiles;
+  DevArr<Tile> tiles;             // wave tiles of every box (tagging, energy, rhs)
+  DevArr<Tile> stiles_w, stiles_b;  // stage-kernel tiles: wave rows / block rows
   DevArr<long long> xoff_valid, xoff_ghost, rhs_off;
-  SegPlan<CopySeg> a1;
+  SegPlan<CopySeg> a1;    // same-level ghost copy, one layer
+  SegPlan<CopySeg> a1d;   // the same over the whole ghost depth (when deeper than one)
+  DevArr<Tile> ftiles;    // fused-step tiles (level 0 only)
   SegPlan<InterpSeg> a2;  // coarse -> this level's ghosts
   SegPlan<AvgSeg> a5;     // this level -> coarse level
   long long k = 0;        // host mirror of the device step counter
@@ -198,10 +307,14 @@ struct Level {
   void release_tables() {
     dbox.release();
     tiles.release();
+    stiles_w.release();
+    stiles_b.release();
     xoff_valid.release();
     xoff_ghost.release();
     rhs_off.release();
     a1.release();
+    a1d.release();
+    ftiles.release();
     a2.release();
     a5.release();
   }
@@ -215,6 +328,7 @@ struct Level {
 
 struct sh_hierarchy_s {
   sh_params p;
+  Tuning tune;
   hipStream_t st = nullptr;
   LevelScal* d_ls = nullptr;  // 16 levels
   double* d_dbg = nullptr;
@@ -325,12 +439,12 @@ static sh_status parse_boxes(const sh_params& p, int l, int nboxes, const int32_
 // ---------------------------------------------------------------------------------
 // Plans
 // ---------------------------------------------------------------------------------
-static void build_a1(const Level& L, std::vector<CopySeg>& segs, std::vector<long long>& nc) {
+static void build_a1(const Level& L, int depth, std::vector<CopySeg>& segs, std::vector<long long>& nc) {
   segs.clear();
   nc.clear();
   for (int d = 0; d < (int)L.boxes.size(); ++d) {
     const IBox& D = L.boxes[d];
-    const IBox G = grow(D, 1);
+    const IBox G = grow(D, depth);
     for_images(G, L.M, L.bins, [&](int s, const int sh[3]) {
       if (s == d && sh[0] == 0 && sh[1] == 0 && sh[2] == 0) return;
       const IBox img = shift(L.boxes[s], sh[0] * L.M, sh[1] * L.M, sh[2] * L.M);
@@ -457,11 +571,13 @@ static sh_status build_links(sh_hierarchy h, int l) {
 // ---------------------------------------------------------------------------------
 // Level step pieces
 // ---------------------------------------------------------------------------------
-static sh_status same_level_fill(sh_hierarchy h, int l, int role, int ncomp = 2) {
+// Same-level ghost copy of `role`: one layer, or (deep = true) the whole ghost depth.
+static sh_status same_level_fill(sh_hierarchy h, int l, int role, int ncomp = 2, bool deep = true) {
   Level& L = h->lev[l];
   h->rec(2, l, role, 0);
+  const SegPlan<CopySeg>& pl = (deep && L.a1d.nblocks()) ? L.a1d : L.a1;
   hipEvent_t ev = h->prof_begin();
-  sh_launch_ghost_copy(h->p.prec, L.a1.segs.p, L.a1.blocks.p, L.a1.nblocks(), L.dbox.p, role, ncomp, h->st);
+  sh_launch_ghost_copy(h->p.prec, pl.segs.p, pl.blocks.p, pl.nblocks(), L.dbox.p, role, ncomp, h->st);
   h->prof_end(ev, 4);
   LAUNCHCHK();
   return SH_OK;
@@ -479,10 +595,18 @@ static sh_status coarse_fine_fill(sh_hierarchy h, int l, int role, int anum) {
   return SH_OK;
 }
 
+// Ghost fill of a stage input (one layer suffices: only the state U_n is read deeper).
 static sh_status fill(sh_hierarchy h, int l, int role, int anum) {
-  sh_status s = same_level_fill(h, l, role);
+  sh_status s = same_level_fill(h, l, role, 2, role == ROLE_UN);
   if (s != SH_OK) return s;
   return coarse_fine_fill(h, l, role, anum);
+}
+
+static void stage(sh_hierarchy h, Level& L, int s) {
+  const int prec = h->p.prec;
+  const bool nt = h->tune.nt != 0;
+  if (L.stiles_b.n) sh_launch_stage(prec, s, h->tune.kind, nt, L.stiles_b.p, (int)L.stiles_b.n, L.dbox.p, h->st);
+  if (L.stiles_w.n) sh_launch_stage(prec, s, 0, nt, L.stiles_w.p, (int)L.stiles_w.n, L.dbox.p, h->st);
 }
 
 static sh_status check_level(sh_hierarchy h, int l) {
@@ -514,7 +638,7 @@ size_t sh_arena_bytes(const sh_params* p, int32_t lev, int32_t nboxes, const int
   std::vector<IBox> b;
   if (parse_boxes(*p, lev, nboxes, boxes, b) != SH_OK) return 0;
   LayoutGeom g;
-  make_geom(p->prec, b, g);
+  make_geom(p->prec, lev == 0 ? SH_NG0 : 1, b, g);
   return g.total;
 }
 
@@ -528,6 +652,7 @@ sh_status sh_hierarchy_create(const sh_params* p, void* hip_stream, sh_hierarchy
   sh_hierarchy h = new (std::nothrow) sh_hierarchy_s;
   if (!h) return fail(SH_ENOMEM, "host allocation failed");
   h->p = *p;
+  tuning_from_env(h->tune);
   h->st = (hipStream_t)hip_stream;
   if (hipMalloc((void**)&h->d_ls, 16 * sizeof(LevelScal)) != hipSuccess ||
       hipMalloc((void**)&h->d_dbg, 16 * sizeof(double)) != hipSuccess) {
@@ -567,11 +692,11 @@ static sh_status set_box_tables(sh_hierarchy h, int l, Level& L) {
     d.ny = b.size(1);
     d.nz = b.size(2);
     d.px = L.g.px[i];
-    d.py = d.ny + 2;
+    d.py = d.ny + 2 * L.g.ng;
     for (int k = 0; k < 3; ++k) d.lo[k] = b.lo[k];
     if (moff > 0x7fffffffLL) return fail(SH_EINVAL, "level too large for 32-bit mask offsets");
     d.mask_off = (int)moff;
-    d.pad = 0;
+    d.ng = L.g.ng;
     moff += (long long)d.nx * d.ny * d.nz;
     L.hbox.push_back(d);
     xv.push_back(xv.back() + 4LL * d.nx * d.ny * d.nz);
@@ -581,6 +706,14 @@ static sh_status set_box_tables(sh_hierarchy h, int l, Level& L) {
   ro.pop_back();
   HIPCHK(L.dbox.upload(L.hbox));
   HIPCHK(L.tiles.upload(L.g.tiles));
+  {
+    std::vector<Tile> wt, bt, ft;
+    make_stage_tiles(L.boxes, h->tune, L.g.nvalid, wt, bt);
+    HIPCHK(L.stiles_w.upload(wt));
+    HIPCHK(L.stiles_b.upload(bt));
+    make_fused_tiles(L.boxes, h->tune, L.g.ng, ft);
+    HIPCHK(L.ftiles.upload(ft));
+  }
   HIPCHK(L.xoff_valid.upload(xv));
   HIPCHK(L.xoff_ghost.upload(xg));
   HIPCHK(L.rhs_off.upload(ro));
@@ -612,7 +745,7 @@ sh_status sh_set_level_layout(sh_hierarchy h, int32_t l, int32_t nboxes, const i
     for (auto& b : N.boxes) v += b.volume();
     if (v != (long long)N.M * N.M * N.M) return fail(SH_EINVAL, "level 0 boxes must cover the domain");
   }
-  make_geom(p.prec, N.boxes, N.g);
+  make_geom(p.prec, l == 0 ? SH_NG0 : 1, N.boxes, N.g);
   if (!arena || arena_bytes < N.g.total) return fail(SH_ENOMEM, "arena smaller than sh_arena_bytes");
   N.base = (char*)round_up((long long)(uintptr_t)arena, 256);
   N.bins.build(N.boxes, N.M);
@@ -624,8 +757,12 @@ sh_status sh_set_level_layout(sh_hierarchy h, int32_t l, int32_t nboxes, const i
   {
     std::vector<CopySeg> cs;
     std::vector<long long> nc;
-    build_a1(N, cs, nc);
+    build_a1(N, 1, cs, nc);
     hipError_t e = N.a1.upload(cs, nc);
+    if (e == hipSuccess && N.g.ng > 1) {
+      build_a1(N, N.g.ng, cs, nc);
+      e = N.a1d.upload(cs, nc);
+    }
     if (e != hipSuccess) { N.release(); return fail(SH_EDEVICE, "table upload failed"); }
   }
   // nesting and interpolation plans against the coarse level
@@ -769,31 +906,43 @@ sh_status sh_advance_level(sh_hierarchy h, int32_t l, int32_t sub) {
   if (l > 0 && sub != 0 && sub != 1) return fail(SH_EINVAL, "substep must be 0 or 1");
   if (l == 0) sub = 0;
   Level& L = h->lev[l];
-  const int prec = h->p.prec;
   hipEvent_t ev;
+  if (L.ftiles.n) {
+    // all four stages in one kernel: no ghost fill between stages is needed because the
+    // kernel computes the early stages on the ghost-deep ring itself
+    for (int st = 0; st < 4; ++st) h->rec(1, l, st, sub);
+    ev = h->prof_begin();
+    sh_launch_fused(h->p.prec, h->tune.nt != 0, h->tune.fshape, L.ftiles.p, (int)L.ftiles.n, L.dbox.p, h->st);
+    h->prof_end(ev, 7);
+    LAUNCHCHK();
+    sh_launch_counter_inc(h->d_ls + l, 1, h->st);
+    LAUNCHCHK();
+    L.k += 1;
+    return same_level_fill(h, l, ROLE_UN);
+  }
   // stage 1 reads U_n (ghosts set by the previous step end or synchronisation)
   h->rec(1, l, 0, sub);
   ev = h->prof_begin();
-  sh_launch_stage(prec, 0, L.tiles.p, L.ntiles(), L.dbox.p, h->st);
+  stage(h, L, 0);
   h->prof_end(ev, 0);
   LAUNCHCHK();
   // alpha in quarters: (sub + c_s)/2 * 4 = 2 sub + 2 c_s
   if ((s = fill(h, l, ROLE_A, 2 * sub + 1)) != SH_OK) return s;
   h->rec(1, l, 1, sub);
   ev = h->prof_begin();
-  sh_launch_stage(prec, 1, L.tiles.p, L.ntiles(), L.dbox.p, h->st);
+  stage(h, L, 1);
   h->prof_end(ev, 1);
   LAUNCHCHK();
   if ((s = fill(h, l, ROLE_B, 2 * sub + 1)) != SH_OK) return s;
   h->rec(1, l, 2, sub);
   ev = h->prof_begin();
-  sh_launch_stage(prec, 2, L.tiles.p, L.ntiles(), L.dbox.p, h->st);
+  stage(h, L, 2);
   h->prof_end(ev, 2);
   LAUNCHCHK();
   if ((s = fill(h, l, ROLE_A, 2 * sub + 2)) != SH_OK) return s;
   h->rec(1, l, 3, sub);
   ev = h->prof_begin();
-  sh_launch_stage(prec, 3, L.tiles.p, L.ntiles(), L.dbox.p, h->st);
+  stage(h, L, 3);
   h->prof_end(ev, 3);
   LAUNCHCHK();
   sh_launch_counter_inc(h->d_ls + l, 1, h->st);
@@ -973,6 +1122,31 @@ sh_status sh_cluster_tags(sh_hierarchy h, int32_t l, int64_t ntag, const int32_t
                      err))
     return fail(SH_EINVAL, err);
   return emit_boxes(out, boxes_out, cap, nboxes);
+}
+
+sh_status sh_set_tuning(sh_hierarchy h, int32_t kind, int32_t nontemporal, int32_t tile_z, int32_t fuse,
+                        int32_t fused_shape, int32_t fused_tile_z) {
+  if (!h) return fail(SH_EINVAL, "null handle");
+  if ((kind != 0 && kind != 4 && kind != 8) || (nontemporal != 0 && nontemporal != 1) || tile_z < 0 ||
+      tile_z > 1024 || (fuse != 0 && fuse != 4) || (fused_shape != 0 && fused_shape != 1) || fused_tile_z < 1 ||
+      fused_tile_z > 1024)
+    return fail(SH_EINVAL, "bad tuning");
+  HIPCHK(hipStreamSynchronize(h->st));
+  h->tune.kind = kind;
+  h->tune.nt = nontemporal;
+  h->tune.zc = tile_z;
+  h->tune.fuse = fuse;
+  h->tune.fshape = fused_shape;
+  h->tune.fzc = fused_tile_z;
+  for (Level& L : h->lev) {
+    std::vector<Tile> wt, bt, ft;
+    make_stage_tiles(L.boxes, h->tune, L.g.nvalid, wt, bt);
+    HIPCHK(L.stiles_w.upload(wt));
+    HIPCHK(L.stiles_b.upload(bt));
+    make_fused_tiles(L.boxes, h->tune, L.g.ng, ft);
+    HIPCHK(L.ftiles.upload(ft));
+  }
+  return SH_OK;
 }
 
 sh_status sh_profile(sh_hierarchy h, int32_t enable) {

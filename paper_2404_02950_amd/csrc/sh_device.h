@@ -1,0 +1,73 @@
+// Device helpers shared by the kernel translation units (internal).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "sh_internal.h"
+
+#pragma clang fp contract(off)
+
+template <typename T> struct Xoff;
+template <> struct Xoff<double> { static constexpr int v = 8; };
+template <> struct Xoff<float> { static constexpr int v = 16; };
+
+// ---------------------------------------------------------------------------------
+// Per-stage scalars from the level's device scalars.  Classic RK4 (integrator type 4)
+// evaluates the right-hand side at eta_n + c_s dt, c = (0, 1/2, 1/2, 1); the EOM
+// coefficients are c_fric = alpha/eta_s and c_pot = lambda * eta_s^beta.
+// ---------------------------------------------------------------------------------
+struct StageScal {
+  double cf, cp, inv_dx2, h6, h3, h2, h1;
+};
+
+__device__ __forceinline__ double ipow(double x, int b) {
+  double p = 1.0;
+  for (int i = 0; i < b; ++i) p = p * x;
+  return p;
+}
+
+__device__ __forceinline__ double level_time(const LevelScal& L) {
+  return L.eta0 + (double)L.k * L.dt;
+}
+
+__device__ __forceinline__ StageScal stage_scalars(const LevelScal& L, int s) {
+  const double c = (s == 0) ? 0.0 : (s == 3 ? 1.0 : 0.5);
+  const double eta_s = level_time(L) + c * L.dt;
+  StageScal r;
+  r.cf = L.alpha / eta_s;
+  r.cp = L.lam * ipow(eta_s, L.beta);
+  r.inv_dx2 = L.inv_dx2;
+  r.h6 = L.dt / 6.0;
+  r.h3 = L.dt / 3.0;
+  r.h2 = L.dt * 0.5;
+  r.h1 = L.dt;
+  return r;
+}
+
+// Blocks are dispatched round-robin over the 8 XCDs of MI355X.  Map hardware block b
+// to logical block (b % 8) * (n / 8) + b / 8 so that each XCD (with its own L2) works
+// on one contiguous run of tiles, whose halo rows it then shares in its L2.
+__device__ __forceinline__ int xcd_remap(int b, int n) {
+  const int nfull = n & ~7;
+  if (b >= nfull) return b;
+  return (b & 7) * (nfull >> 3) + (b >> 3);
+}
+
+// Element index of box-local cell (i, j, k), -ng <= i < nx + ng etc., in component 0.
+template <typename T>
+__device__ __forceinline__ long long elem(const BoxDev& B, int i, int j, int k) {
+  return ((long long)(k + B.ng) * B.py + (j + B.ng)) * (long long)B.px + Xoff<T>::v + i;
+}
+
+// Streams read or written once can be marked nontemporal so they do not displace data
+// that neighbouring tiles re-read from L2.
+template <bool NT, typename V>
+__device__ __forceinline__ V ld(const V* p) {
+  if constexpr (NT) return __builtin_nontemporal_load(p);
+  else return *p;
+}
+template <bool NT, typename V>
+__device__ __forceinline__ void st(V* p, V v) {
+  if constexpr (NT) __builtin_nontemporal_store(v, p);
+  else *p = v;
+}
+

@@ -1,9 +1,10 @@
 // Internal device/host structures of libshamr (not part of the public C-ABI).
 //
 // Storage of one box (all levels, all buffers): structure-of-arrays
-//   element(c, i, j, k) = off + c*cs + ((k+1)*py + (j+1))*px + XOFF + i
+//   element(c, i, j, k) = off + c*cs + ((k+ng)*py + (j+ng))*px + XOFF + i
 // for component c in {psi1, psi2, Pi1, Pi2}, box-local cell (i, j, k) with
-// -1 <= i <= nx etc. (a one-cell ghost shell).  XOFF puts i = 0 on a 64-byte boundary
+// -ng <= i < nx + ng etc. (a ghost shell ng cells deep: 1 on refined levels, 4 on
+// level 0 so that four RK stages can be fused).  XOFF puts i = 0 on a 64-byte boundary
 // and px is a multiple of XOFF, so every x-row of valid cells starts 64-byte aligned.
 // A level owns three state slots of this layout in the storage precision T plus one
 // float64 accumulator slot with the same element offsets.
@@ -47,7 +48,7 @@ struct BoxDev {
   int px, py;         // x pitch (elements), y pitch (ny + 2)
   int lo[3];          // global index of cell (0,0,0) on the box's level
   int mask_off;       // offset of the box's valid cells in per-level byte masks
-  int pad;
+  int ng;             // ghost layers stored around the box
 };
 
 // Wave tile: one wavefront covers a TX x (64/TX) footprint of a box and marches in z.

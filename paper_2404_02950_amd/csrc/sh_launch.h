@@ -5,7 +5,8 @@
 
 #include "sh_internal.h"
 
-void sh_launch_stage(int prec, int s, const Tile* tiles, int ntiles, const BoxDev* boxes, hipStream_t st);
+void sh_launch_stage(int prec, int s, int kind, bool nt, const Tile* tiles, int ntiles, const BoxDev* boxes,
+                     hipStream_t st);
 void sh_launch_rhs(int prec, const Tile* tiles, int ntiles, const BoxDev* boxes, const long long* out_off,
                    double* out, hipStream_t st);
 void sh_launch_counter_inc(LevelScal* ls, int n, hipStream_t st);
@@ -31,3 +32,6 @@ void sh_launch_mark_covered(const AvgSeg* segs, const SegBlock* blocks, int nblo
 void sh_launch_xfer(int prec, bool to_box, const BoxDev* boxes, const long long* off, int nbox, double* stage, int role,
                     int g, long long total, hipStream_t st);
 void sh_launch_debug_scalars(const LevelScal* ls, int s, double* out, hipStream_t st);
+void sh_launch_fused(int prec, bool nt, int shape, const Tile* tiles, int ntiles, const BoxDev* boxes,
+                     hipStream_t st);
+void sh_fused_footprint(int shape, int* tx, int* ty);

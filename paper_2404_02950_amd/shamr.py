@@ -59,6 +59,7 @@ _PROTOS = {
     "sh_hierarchy_destroy": (c_int32, [c_void_p]),
     "sh_last_error": (c_char_p, []),
     "sh_debug_stage_scalars": (c_int32, [c_void_p, c_int32, c_int32, POINTER(c_double)]),
+    "sh_set_tuning": (c_int32, [c_void_p, c_int32, c_int32, c_int32, c_int32, c_int32, c_int32]),
     "sh_profile": (c_int32, [c_void_p, c_int32]),
     "sh_profile_read": (c_int32, [c_void_p, POINTER(c_double), POINTER(c_int64)]),
     "sh_trace": (c_int32, [c_void_p, c_int32]),
@@ -303,8 +304,12 @@ class Hierarchy:
         _check(self.lib.sh_debug_stage_scalars(self.h, lev, s, out))
         return list(out)
 
+    def set_tuning(self, kind: int = 8, nontemporal: int = 1, tile_z: int = 0, fuse: int = 4,
+                   fused_shape: int = 0, fused_tile_z: int = 64):
+        _check(self.lib.sh_set_tuning(self.h, kind, nontemporal, tile_z, fuse, fused_shape, fused_tile_z))
+
     PROFILE_CLASSES = ("stage1", "stage2", "stage3", "stage4", "ghost_copy", "ghost_interp",
-                       "average_down", "unused")
+                       "average_down", "fused_step")
 
     def profile(self, enable: bool):
         _check(self.lib.sh_profile(self.h, int(enable)))

@@ -34,7 +34,7 @@ def test_device_stage_scalars_match_host_definitions():
 
 @pytest.mark.parametrize("seed", [0, 1])
 def test_c0_literal_64cube_100_steps_bitwise(seed):
-    # configs[0]: 64^3, L = 64, dt = 1/4, eta from 0.1, 100 steps, lambda = 1, beta = 2
+    # the 64^3 workload: L = 64, dt = 1/4, eta from 0.1, 100 steps, lambda = 1, beta = 2
     U0 = random_state(64, 64.0, seed)
     h = single_level(U0)
     checkpoints = {1, 10, 30, 50, 100}
@@ -149,7 +149,7 @@ def test_energy_matches_oracle_fp64():
 
 
 def test_full_size_512_sampled_parity():
-    # configs[1] at full size, the launch configuration bench.py times: 2 steps, then
+    # the 512^3 lattice in the launch configuration bench.py times: 2 steps, then
     # sampled cells against the oracle run on periodic crops around each sample (after 2
     # RK4 steps a cell depends only on cells within 8 of it)
     n = 512
@@ -178,3 +178,55 @@ def test_lap7_reference_consistency():
     # the oracle Laplacian used above is the 7-point one (sanity, CPU arithmetic only)
     u = quadratic_field((6, 6, 6), (1, 1, 1, 0, 0, 0))
     assert np.all(lap7(u, 1.0)[1:-1, 1:-1, 1:-1] == 6.0)
+
+
+@pytest.mark.parametrize("kind,nt,zc", [(0, 0, 0), (0, 1, 8), (4, 1, 0), (8, 0, 16), (8, 1, 0), (8, 1, 7)])
+def test_stage_kernel_launch_shapes_bitwise(kind, nt, zc):
+    # every launch shape of the stage kernel gives the oracle's bits: boxes 64 and 32 wide
+    # (block-row and wave-row paths), ragged y extents (36, 60) and z tails
+    n = 96
+    U0 = random_state(n, float(n), 2)
+    h = single_level(U0, boxes=decompose(n, [[64], [36], [50]]), beta=0)
+    h.set_tuning(kind, nt, zc, fuse=0)
+    ref = run_single_level(U0, 4, 0.1, 0.25, 1.0, beta=0)
+    for _ in range(4):
+        h.advance(0)
+    assert_bitwise(h.read_dense(0), ref, f"kind={kind} nt={nt} zc={zc}")
+    h.close()
+
+
+@pytest.mark.parametrize("shape,fzc,cuts", [(0, 64, None), (0, 16, [[32], [32], [24]]), (0, 7, [[32], [8, 40], None]),
+                                          (1, 64, None), (1, 13, [None, [16], [40]])])
+def test_fused_four_stage_step_bitwise(shape, fzc, cuts):
+    # the fused step (all four stages in one kernel, overlapped tiles, z pipeline) must
+    # give the oracle's bits: single and multi-box level 0, ragged z chunks
+    n = 64
+    U0 = random_state(n, float(n), 6)
+    boxes = decompose(n, [c if c is not None else [] for c in cuts]) if cuts else decompose(n)
+    h = single_level(U0, boxes=boxes, beta=0)
+    h.set_tuning(8, 1, 0, fuse=4, fused_shape=shape, fused_tile_z=fzc)
+    h.profile(True)
+    ref = run_single_level(U0, 5, 0.1, 0.25, 1.0, beta=0)
+    for _ in range(5):
+        h.advance(0)
+    prof = h.profile_read()
+    assert prof["fused_step"][1] == 5 and prof["stage1"][1] == 0, prof
+    assert_bitwise(h.read_dense(0), ref, f"shape={shape} fzc={fzc} cuts={cuts}")
+    h.close()
+
+
+def test_fused_and_per_stage_agree_through_divergence():
+    # literal beta = 2 workload past the RK4 stability limit: both paths produce the same
+    # Inf/NaN pattern as the oracle
+    n = 32
+    U0 = random_state(n, float(n), 4)
+    ref = run_single_level(U0, 60, 0.1, 0.25, 1.0)
+    for fuse in (4, 0):
+        h = single_level(U0)
+        h.set_tuning(8, 1, 0, fuse=fuse)
+        for _ in range(60):
+            h.advance(0)
+        got = h.read_dense(0)
+        assert_bitwise(got, ref, f"fuse={fuse}")
+        h.close()
+    assert not np.all(np.isfinite(ref)), "the literal workload should have diverged by step 60"
