@@ -572,10 +572,14 @@ static sh_status build_links(sh_hierarchy h, int l) {
 // Level step pieces
 // ---------------------------------------------------------------------------------
 // Same-level ghost copy of `role`: one layer, or (deep = true) the whole ghost depth.
+// The deep copy carries all four components: the fused step computes its early stages
+// on the ghost ring, where it needs Pi as well as psi.
 static sh_status same_level_fill(sh_hierarchy h, int l, int role, int ncomp = 2, bool deep = true) {
   Level& L = h->lev[l];
   h->rec(2, l, role, 0);
-  const SegPlan<CopySeg>& pl = (deep && L.a1d.nblocks()) ? L.a1d : L.a1;
+  const bool use_deep = deep && L.a1d.nblocks();
+  const SegPlan<CopySeg>& pl = use_deep ? L.a1d : L.a1;
+  if (use_deep) ncomp = 4;
   hipEvent_t ev = h->prof_begin();
   sh_launch_ghost_copy(h->p.prec, pl.segs.p, pl.blocks.p, pl.nblocks(), L.dbox.p, role, ncomp, h->st);
   h->prof_end(ev, 4);
