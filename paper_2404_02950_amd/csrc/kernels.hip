@@ -206,7 +206,7 @@ __global__ __launch_bounds__(SH_WAVE * R) void k_stage_lds(const Tile* __restric
       if (has_h) sm[buf][c][hrow][lane + 1] = hv[c];
       if (has_x) sm[buf][c][w + 1][xcol] = xv[c];
     }
-    __syncthreads();
+    lds_barrier();
     T lap[2];
 #pragma unroll
     for (int c = 0; c < 2; ++c) {

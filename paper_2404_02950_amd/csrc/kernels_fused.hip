@@ -120,7 +120,7 @@ __global__ __launch_bounds__((FusedShape<T, TX, TY>::NBLK)) void k_fused_rk4(con
       for (int j = 1; j < FD; ++j)
         if (r <= FD - j) sm[j][c][cy][cx] = wj[j][2][c];
     }
-    __syncthreads();
+    lds_barrier();
     // outputs of the stage just computed (input of the next one)
     T out[4];
 #pragma unroll
@@ -182,7 +182,7 @@ __global__ __launch_bounds__((FusedShape<T, TX, TY>::NBLK)) void k_fused_rk4(con
         for (int c = 0; c < 4; ++c) st<NT>(Y + c * cs + e, out[c]);
       }
     }
-    __syncthreads();
+    lds_barrier();
     // advance the register pipelines by one plane
 #pragma unroll
     for (int c = 0; c < 4; ++c) {

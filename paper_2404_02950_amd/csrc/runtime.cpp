@@ -182,7 +182,7 @@ struct Tuning {
   int zc = 0;
   int fuse = 4;
   int fshape = 0;
-  int fzc = 64;
+  int fzc = 256;
 };
 
 static void tuning_from_env(Tuning& t) {

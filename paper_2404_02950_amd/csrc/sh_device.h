@@ -71,3 +71,12 @@ __device__ __forceinline__ void st(V* p, V v) {
   else *p = v;
 }
 
+
+// Workgroup barrier that orders LDS accesses only.  __syncthreads() also waits for every
+// outstanding global load of the wave, which would drain the plane prefetch of the
+// z-marching kernels at each barrier; these exchange data through LDS alone.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}

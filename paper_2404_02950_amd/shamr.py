@@ -305,7 +305,7 @@ class Hierarchy:
         return list(out)
 
     def set_tuning(self, kind: int = 8, nontemporal: int = 1, tile_z: int = 0, fuse: int = 4,
-                   fused_shape: int = 0, fused_tile_z: int = 64):
+                   fused_shape: int = 0, fused_tile_z: int = 256):
         _check(self.lib.sh_set_tuning(self.h, kind, nontemporal, tile_z, fuse, fused_shape, fused_tile_z))
 
     PROFILE_CLASSES = ("stage1", "stage2", "stage3", "stage4", "ghost_copy", "ghost_interp",
