@@ -197,7 +197,7 @@ sh_status sh_debug_stage_scalars(sh_hierarchy h, int32_t lev, int32_t s, double*
    cells per per-stage tile in z (0 = from the level size); fuse 4 = level 0 takes each
    step in one kernel computing all four RK stages (temporal blocking; needs every
    level-0 box to be a multiple of the fused footprint, else per-stage), 0 = per-stage
-   kernels; fused_shape 0 = 32 x 8 footprint, 1 = 64 x 4; fused_tile_z = planes per fused
+   kernels; fused_shape 0 = 32 x 8 footprint, 1 = 64 x 4, 2 = 32 x 16; fused_tile_z = planes per fused
    tile.  Applies to every level.  The environment variable SHAMR_TUNE (e.g.
    "kind=8,nt=1,zc=0,fuse=4,fshape=0,fzc=64") sets the defaults at creation. */
 sh_status sh_set_tuning(sh_hierarchy h, int32_t kind, int32_t nontemporal, int32_t tile_z, int32_t fuse,

@@ -20,6 +20,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "sh_device.h"
 #include "sh_internal.h"
 #include "sh_launch.h"
@@ -38,6 +40,33 @@ struct FusedShape {
   static constexpr int NTH = W * H;
   static constexpr int NBLK = (NTH + SH_WAVE - 1) / SH_WAVE * SH_WAVE;
 };
+
+// Thread -> column map sorted by ring distance from the footprint (footprint first, then
+// rings 1..FD), row-major within a ring.  Stage j is computed on rings 0..FG-j, so with
+// this order whole wavefronts skip the stages they have no columns for.
+template <int TX, int TY>
+struct RingMap {
+  static constexpr int W = TX + 2 * FD, H = TY + 2 * FD, N = W * H;
+  unsigned char cx[N], cy[N];
+  constexpr RingMap() : cx(), cy() {
+    int k = 0;
+    for (int r = 0; r <= FD; ++r)
+      for (int y = 0; y < H; ++y)
+        for (int x = 0; x < W; ++x) {
+          const int ox = x - FD, oy = y - FD;
+          const int rx = ox < 0 ? -ox : (ox >= TX ? ox - TX + 1 : 0);
+          const int ry = oy < 0 ? -oy : (oy >= TY ? oy - TY + 1 : 0);
+          if ((rx > ry ? rx : ry) == r) {
+            cx[k] = (unsigned char)x;
+            cy[k] = (unsigned char)y;
+            ++k;
+          }
+        }
+  }
+};
+
+template <int TX, int TY>
+__constant__ RingMap<TX, TY> ring_map = RingMap<TX, TY>();
 
 }  // namespace
 
@@ -63,7 +92,7 @@ __global__ __launch_bounds__((FusedShape<T, TX, TY>::NBLK)) void k_fused_rk4(con
 
   const int tid = threadIdx.x;
   const bool inreg = tid < Sh::NTH;
-  const int cx = inreg ? tid % W : FD, cy = inreg ? tid / W : FD;
+  const int cx = inreg ? ring_map<TX, TY>.cx[tid] : FD, cy = inreg ? ring_map<TX, TY>.cy[tid] : FD;
   const int ox = cx - FD, oy = cy - FD;  // footprint-relative
   const int rx = ox < 0 ? -ox : (ox >= TX ? ox - TX + 1 : 0);
   const int ry = oy < 0 ? -oy : (oy >= TY ? oy - TY + 1 : 0);
@@ -75,21 +104,25 @@ __global__ __launch_bounds__((FusedShape<T, TX, TY>::NBLK)) void k_fused_rk4(con
   const int x = x0 + (r <= FD ? ox : 0), y = y0 + (r <= FD ? oy : 0);
   const long long plane = (long long)B.px * B.py;
   const long long cs = B.cs;
-  const long long ecol = elem<T>(B, x, y, 0);
+  // this thread's column of U_n (psi1, psi2, Pi1, Pi2) and of the output, at plane 0
+  typedef __attribute__((address_space(1))) const T* gcptr;
+  typedef __attribute__((address_space(1))) T* gptr;
+  gcptr col = (gcptr)(X + elem<T>(B, x, y, 0));
+  gptr ocol = (gptr)(Y + elem<T>(B, x, y, 0));
   const int zlo = -B.ng, zhi = B.nz + B.ng - 1;
-  auto eat = [&](int z) { return ecol + (long long)min(max(z, zlo), zhi) * plane; };
+  auto eat = [&](int z) { return (long long)min(max(z, zlo), zhi) * plane; };
 
   const int ifirst = z0 - FG, ilast = z0 + zc - 1 + FG;
   // stage 0 input window (planes i-1, i, i+1), next psi plane and Pi of planes i, i+1
   T w0[3][2], nx2[2], q0c[2], q0n[2];
 #pragma unroll
   for (int c = 0; c < 2; ++c) {
-    w0[0][c] = X[c * cs + eat(ifirst - 1)];
-    w0[1][c] = X[c * cs + eat(ifirst)];
-    w0[2][c] = X[c * cs + eat(ifirst + 1)];
-    nx2[c] = X[c * cs + eat(ifirst + 2)];
-    q0c[c] = ld<NT>(X + (2 + c) * cs + eat(ifirst));
-    q0n[c] = ld<NT>(X + (2 + c) * cs + eat(ifirst + 1));
+    w0[0][c] = col[c * cs + eat(ifirst - 1)];
+    w0[1][c] = col[c * cs + eat(ifirst)];
+    w0[2][c] = col[c * cs + eat(ifirst + 1)];
+    nx2[c] = col[c * cs + eat(ifirst + 2)];
+    q0c[c] = col[(2 + c) * cs + eat(ifirst)];
+    q0n[c] = col[(2 + c) * cs + eat(ifirst + 1)];
   }
   // later stages: input windows and their Pi at planes (p, p+1); U_n of planes i-1, i-2
   T wj[FD][3][2], qj[FD][2][2];
@@ -109,7 +142,10 @@ __global__ __launch_bounds__((FusedShape<T, TX, TY>::NBLK)) void k_fused_rk4(con
     for (int j = 0; j < FD; ++j) acc[j][c] = 0.0;
   }
 
-  for (int i = ifirst; i <= ilast; ++i) {
+  // one iteration: stage j handles plane i - j.  FILL marks the first 2*FG iterations,
+  // in which the later stages are still waiting for their input windows to fill.
+  auto iteration = [&](const int i, auto fill_tag) {
+    constexpr bool FILL = decltype(fill_tag)::value;
     // U_n at plane i (for the updates of stages 1 and 2 one and two iterations later)
     const T un0[4] = {w0[1][0], w0[1][1], q0c[0], q0c[1]};
     // publish every stage's input plane: stage 0 = U_n psi at i, stage j = its window top
@@ -128,7 +164,7 @@ __global__ __launch_bounds__((FusedShape<T, TX, TY>::NBLK)) void k_fused_rk4(con
       // stage j runs from iteration ifirst + 2j on; before that its window fills with the
       // planes stage j-1 produces (the conditions are uniform over the block)
       if (j > 0) {
-        if (i < ifirst + 2 * (j - 1)) break;
+        if (FILL && i < ifirst + 2 * (j - 1)) break;
         // push stage j-1's output plane (p+1) into stage j's window
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
@@ -139,7 +175,7 @@ __global__ __launch_bounds__((FusedShape<T, TX, TY>::NBLK)) void k_fused_rk4(con
           qj[j][1][c] = out[2 + c];
         }
       }
-      if (i < ifirst + 2 * j) break;
+      if (FILL && i < ifirst + 2 * j) break;
       if (r > FG - j) continue;
       const T(*w)[2] = (j == 0) ? w0 : wj[j];
       const T q0 = (j == 0) ? q0c[0] : qj[j][0][0];
@@ -177,9 +213,12 @@ __global__ __launch_bounds__((FusedShape<T, TX, TY>::NBLK)) void k_fused_rk4(con
         }
       }
       if (j == FD - 1 && own) {
-        const long long e = eat(i - FG);
+        const long long e = (long long)(i - FG) * plane;
 #pragma unroll
-        for (int c = 0; c < 4; ++c) st<NT>(Y + c * cs + e, out[c]);
+        for (int c = 0; c < 4; ++c) {
+          if constexpr (NT) __builtin_nontemporal_store(out[c], ocol + c * cs + e);
+          else ocol[c * cs + e] = out[c];
+        }
       }
     }
     lds_barrier();
@@ -197,29 +236,34 @@ __global__ __launch_bounds__((FusedShape<T, TX, TY>::NBLK)) void k_fused_rk4(con
       w0[0][c] = w0[1][c];
       w0[1][c] = w0[2][c];
       w0[2][c] = nx2[c];
-      nx2[c] = X[c * cs + eat(i + 3)];
+      nx2[c] = col[c * cs + eat(i + 3)];
       q0c[c] = q0n[c];
-      q0n[c] = ld<NT>(X + (2 + c) * cs + eat(i + 2));
+      q0n[c] = col[(2 + c) * cs + eat(i + 2)];
     }
-  }
+  };
+  int i = ifirst;
+  for (; i <= ilast && i < ifirst + 2 * FG; ++i) iteration(i, std::true_type{});
+  for (; i <= ilast; ++i) iteration(i, std::false_type{});
+}
+
+template <typename T, bool NT, int TX, int TY>
+static void fused_launch_shape(const Tile* tiles, int ntiles, const BoxDev* boxes, hipStream_t st) {
+  using Sh = FusedShape<T, TX, TY>;
+  hipLaunchKernelGGL((k_fused_rk4<T, NT, TX, TY>), dim3(ntiles), dim3(Sh::NBLK), 0, st, tiles, ntiles, boxes);
 }
 
 template <typename T, bool NT>
 static void fused_launch(int shape, const Tile* tiles, int ntiles, const BoxDev* boxes, hipStream_t st) {
   if (ntiles == 0) return;
-  if (shape == 0) {
-    using Sh = FusedShape<T, 32, 8>;
-    hipLaunchKernelGGL((k_fused_rk4<T, NT, 32, 8>), dim3(ntiles), dim3(Sh::NBLK), 0, st, tiles, ntiles, boxes);
-  } else {
-    using Sh = FusedShape<T, 64, 4>;
-    hipLaunchKernelGGL((k_fused_rk4<T, NT, 64, 4>), dim3(ntiles), dim3(Sh::NBLK), 0, st, tiles, ntiles, boxes);
-  }
+  if (shape == 0) fused_launch_shape<T, NT, 32, 8>(tiles, ntiles, boxes, st);
+  else if (shape == 1) fused_launch_shape<T, NT, 64, 4>(tiles, ntiles, boxes, st);
+  else fused_launch_shape<T, NT, 32, 16>(tiles, ntiles, boxes, st);
 }
 
-// Footprint of a fused tile for shape 0 (32 x 8) and 1 (64 x 4).
+// Footprint of a fused tile: shape 0 = 32 x 8, 1 = 64 x 4, 2 = 32 x 16.
 void sh_fused_footprint(int shape, int* tx, int* ty) {
-  *tx = shape == 0 ? 32 : 64;
-  *ty = shape == 0 ? 8 : 4;
+  *tx = shape == 1 ? 64 : 32;
+  *ty = shape == 0 ? 8 : (shape == 1 ? 4 : 16);
 }
 
 void sh_launch_fused(int prec, bool nt, int shape, const Tile* tiles, int ntiles, const BoxDev* boxes,

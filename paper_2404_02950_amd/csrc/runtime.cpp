@@ -175,7 +175,8 @@ static void make_geom(int prec, int ng, const std::vector<IBox>& boxes, LayoutGe
 // wave-row tiles).  nt: nontemporal once-used streams.  zc: cells per tile in z (0 =
 // chosen from the level size).
 // fuse: 4 = level 0 advances with the fused four-stage kernel when its boxes are
-// multiples of the fused footprint (fshape 0: 32 x 8, 1: 64 x 4), 0 = per-stage kernels.
+// multiples of the fused footprint (fshape 0: 32 x 8, 1: 64 x 4, 2: 32 x 16), 0 =
+// per-stage kernels.
 struct Tuning {
   int kind = 8;
   int nt = 1;
@@ -202,7 +203,7 @@ static void tuning_from_env(Tuning& t) {
       if (k == "nt" && (v == 0 || v == 1)) t.nt = v;
       if (k == "zc" && v >= 0 && v <= 1024) t.zc = v;
       if (k == "fuse" && (v == 0 || v == 4)) t.fuse = v;
-      if (k == "fshape" && (v == 0 || v == 1)) t.fshape = v;
+      if (k == "fshape" && v >= 0 && v <= 2) t.fshape = v;
       if (k == "fzc" && v >= 1 && v <= 1024) t.fzc = v;
     }
     pos = end + 1;
@@ -1132,7 +1133,7 @@ sh_status sh_set_tuning(sh_hierarchy h, int32_t kind, int32_t nontemporal, int32
                         int32_t fused_shape, int32_t fused_tile_z) {
   if (!h) return fail(SH_EINVAL, "null handle");
   if ((kind != 0 && kind != 4 && kind != 8) || (nontemporal != 0 && nontemporal != 1) || tile_z < 0 ||
-      tile_z > 1024 || (fuse != 0 && fuse != 4) || (fused_shape != 0 && fused_shape != 1) || fused_tile_z < 1 ||
+      tile_z > 1024 || (fuse != 0 && fuse != 4) || (fused_shape < 0 || fused_shape > 2) || fused_tile_z < 1 ||
       fused_tile_z > 1024)
     return fail(SH_EINVAL, "bad tuning");
   HIPCHK(hipStreamSynchronize(h->st));
