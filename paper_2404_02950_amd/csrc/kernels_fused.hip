@@ -16,7 +16,7 @@
 // to LDS, one barrier, then stages 0..3 run in order reading x/y neighbours from LDS.
 // The z-range is extended the same way (stage j covers 3 - j extra planes below and
 // above), so U_n is read from z0-4 to z0+zc+3: the level keeps a 4-deep ghost shell.
-// The accumulator lives in registers: it exists only on the footprint's own columns.
+// The accumulator exists only on the footprint's own columns; it is kept in LDS.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -77,6 +77,9 @@ __global__ __launch_bounds__((FusedShape<T, TX, TY>::NBLK)) void k_fused_rk4(con
   using Sh = FusedShape<T, TX, TY>;
   constexpr int W = Sh::W, H = Sh::H;
   __shared__ T sm[FD][2][H][W];
+  // accumulator of the footprint's own columns for the four planes in flight (slot =
+  // plane mod 4); each thread touches only its own column, so no barrier is involved
+  __shared__ double sacc[4][4][TY][TX];
 
   const int t = xcd_remap(blockIdx.x, gridDim.x);
   if (t >= ntiles) return;  // uniform
@@ -124,10 +127,9 @@ __global__ __launch_bounds__((FusedShape<T, TX, TY>::NBLK)) void k_fused_rk4(con
     q0c[c] = col[(2 + c) * cs + eat(ifirst)];
     q0n[c] = col[(2 + c) * cs + eat(ifirst + 1)];
   }
-  // later stages: input windows and their Pi at planes (p, p+1); U_n of planes i-1, i-2
+  // later stages: input windows and their Pi at planes (p, p+1); Pi of U_n at plane i-1
   T wj[FD][3][2], qj[FD][2][2];
-  T un1[4], un2[4];
-  double acc[FD][4];
+  T q0p[2] = {(T)0, (T)0};
 #pragma unroll
   for (int j = 0; j < FD; ++j)
 #pragma unroll
@@ -135,19 +137,13 @@ __global__ __launch_bounds__((FusedShape<T, TX, TY>::NBLK)) void k_fused_rk4(con
       wj[j][0][c] = wj[j][1][c] = wj[j][2][c] = (T)0;
       qj[j][0][c] = qj[j][1][c] = (T)0;
     }
-#pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    un1[c] = un2[c] = (T)0;
-#pragma unroll
-    for (int j = 0; j < FD; ++j) acc[j][c] = 0.0;
-  }
+  const bool own = (r == 0);
+  const int ax = own ? ox : 0, ay = own ? oy : 0;
 
   // one iteration: stage j handles plane i - j.  FILL marks the first 2*FG iterations,
   // in which the later stages are still waiting for their input windows to fill.
   auto iteration = [&](const int i, auto fill_tag) {
     constexpr bool FILL = decltype(fill_tag)::value;
-    // U_n at plane i (for the updates of stages 1 and 2 one and two iterations later)
-    const T un0[4] = {w0[1][0], w0[1][1], q0c[0], q0c[1]};
     // publish every stage's input plane: stage 0 = U_n psi at i, stage j = its window top
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
@@ -195,21 +191,35 @@ __global__ __launch_bounds__((FusedShape<T, TX, TY>::NBLK)) void k_fused_rk4(con
       const T kq1 = (lap[1] - cf * q1) - pot * p1;
       const double k4[4] = {(double)q0, (double)q1, (double)kq0, (double)kq1};
       const T xin[4] = {p0, p1, q0, q1};
-      const bool own = (r == 0);
+      // U_n at the stage's plane: stage 1 (plane i-1) has it in registers, stage 2
+      // (plane i-2) reads it back (it was loaded two iterations ago: a cache hit)
+      T un[4] = {(T)0, (T)0, (T)0, (T)0};
+      if (j == 1) {
+        un[0] = w0[0][0];
+        un[1] = w0[0][1];
+        un[2] = q0p[0];
+        un[3] = q0p[1];
+      } else if (j == 2) {
+        const long long e = (long long)(i - 2) * plane;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) un[c] = col[c * cs + e];
+      }
+      double* ac = &sacc[(i - j) & 3][0][ay][ax];
+      constexpr int AST = TY * TX;  // component stride of sacc
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         if (j == 0) {
           const double u = (double)xin[c];
-          if (own) acc[0][c] = u + sc[0].h6 * k4[c];
+          if (own) ac[c * AST] = u + sc[0].h6 * k4[c];
           out[c] = (T)(u + sc[0].h2 * k4[c]);
         } else if (j == 1) {
-          if (own) acc[1][c] = acc[1][c] + sc[1].h3 * k4[c];
-          out[c] = (T)((double)un1[c] + sc[1].h2 * k4[c]);
+          if (own) ac[c * AST] = ac[c * AST] + sc[1].h3 * k4[c];
+          out[c] = (T)((double)un[c] + sc[1].h2 * k4[c]);
         } else if (j == 2) {
-          if (own) acc[2][c] = acc[2][c] + sc[2].h3 * k4[c];
-          out[c] = (T)((double)un2[c] + sc[2].h1 * k4[c]);
+          if (own) ac[c * AST] = ac[c * AST] + sc[2].h3 * k4[c];
+          out[c] = (T)((double)un[c] + sc[2].h1 * k4[c]);
         } else {
-          out[c] = (T)(acc[3][c] + sc[3].h6 * k4[c]);
+          out[c] = (T)(ac[c * AST] + sc[3].h6 * k4[c]);
         }
       }
       if (j == FD - 1 && own) {
@@ -222,21 +232,14 @@ __global__ __launch_bounds__((FusedShape<T, TX, TY>::NBLK)) void k_fused_rk4(con
       }
     }
     lds_barrier();
-    // advance the register pipelines by one plane
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      acc[3][c] = acc[2][c];
-      acc[2][c] = acc[1][c];
-      acc[1][c] = acc[0][c];
-      un2[c] = un1[c];
-      un1[c] = un0[c];
-    }
+    // advance the stage-0 window by one plane
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
       w0[0][c] = w0[1][c];
       w0[1][c] = w0[2][c];
       w0[2][c] = nx2[c];
       nx2[c] = col[c * cs + eat(i + 3)];
+      q0p[c] = q0c[c];
       q0c[c] = q0n[c];
       q0n[c] = col[(2 + c) * cs + eat(i + 2)];
     }
