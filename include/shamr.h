@@ -198,10 +198,13 @@ sh_status sh_debug_stage_scalars(sh_hierarchy h, int32_t lev, int32_t s, double*
    step in one kernel computing all four RK stages (temporal blocking; needs every
    level-0 box to be a multiple of the fused footprint, else per-stage), 0 = per-stage
    kernels; fused_shape 0 = 32 x 8 footprint, 1 = 64 x 4, 2 = 32 x 16; fused_tile_z = planes per fused
-   tile.  Applies to every level.  The environment variable SHAMR_TUNE (e.g.
-   "kind=8,nt=1,zc=0,fuse=4,fshape=0,fzc=64") sets the defaults at creation. */
+   tile; fused_variant 0-3 = thread order / x-neighbour exchange / accumulator placement
+   of the fused kernel (0: row-major, LDS, registers; 1: row-major, lane shifts,
+   registers; 2: row-major, lane shifts, LDS; 3: ring order, LDS, LDS).  Applies to every
+   level.  The environment variable SHAMR_TUNE (e.g.
+   "kind=8,nt=1,zc=0,fuse=4,fshape=0,fzc=256,fvar=0") sets the defaults at creation. */
 sh_status sh_set_tuning(sh_hierarchy h, int32_t kind, int32_t nontemporal, int32_t tile_z, int32_t fuse,
-                        int32_t fused_shape, int32_t fused_tile_z);
+                        int32_t fused_shape, int32_t fused_tile_z, int32_t fused_variant);
 
 /* Per-kernel timing (diagnostic).  sh_profile(h, 1) clears the totals and brackets every
    launch that sh_advance_level and sh_average_down issue with HIP events on the

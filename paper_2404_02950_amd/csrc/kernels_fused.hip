@@ -70,16 +70,34 @@ __constant__ RingMap<TX, TY> ring_map = RingMap<TX, TY>();
 
 }  // namespace
 
-template <typename T, bool NT, int TX, int TY>
+// DPP lane shifts (GFX9 wavefront shift by one lane; lane 0 / 63 receive `old`).
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v, double old) {
+  const int lo = __builtin_amdgcn_update_dpp(__double2loint(old), __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(__double2hiint(old), __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_move(float v, float old) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+constexpr int DPP_WAVE_SHR1 = 0x138;  // lane l takes lane l-1
+constexpr int DPP_WAVE_SHL1 = 0x130;  // lane l takes lane l+1
+
+// ORDER 0: threads row-major over the (TX+8) x (TY+8) columns; 1: sorted by ring.
+// XDPP: x neighbours by lane shifts (row-major only: the computing columns' x neighbours
+// are the adjacent lanes; the two wave-edge lanes read LDS).  ACCL: accumulator in LDS.
+template <typename T, bool NT, int TX, int TY, int ORDER, bool XDPP, bool ACCL>
 __global__ __launch_bounds__((FusedShape<T, TX, TY>::NBLK)) void k_fused_rk4(const Tile* __restrict__ tiles,
                                                                            int ntiles,
                                                                            const BoxDev* __restrict__ boxes) {
+  static_assert(!(XDPP && ORDER != 0), "lane shifts need the row-major order");
   using Sh = FusedShape<T, TX, TY>;
   constexpr int W = Sh::W, H = Sh::H;
   __shared__ T sm[FD][2][H][W];
   // accumulator of the footprint's own columns for the four planes in flight (slot =
   // plane mod 4); each thread touches only its own column, so no barrier is involved
-  __shared__ double sacc[4][4][TY][TX];
+  __shared__ double sacc[ACCL ? 4 : 1][4][ACCL ? TY : 1][ACCL ? TX : 1];
 
   const int t = xcd_remap(blockIdx.x, gridDim.x);
   if (t >= ntiles) return;  // uniform
@@ -94,8 +112,18 @@ __global__ __launch_bounds__((FusedShape<T, TX, TY>::NBLK)) void k_fused_rk4(con
   T* __restrict__ Y = (T*)B.slot[role_slot(ROLE_B, L.k)];
 
   const int tid = threadIdx.x;
+  const int lane = tid & (SH_WAVE - 1);
   const bool inreg = tid < Sh::NTH;
-  const int cx = inreg ? ring_map<TX, TY>.cx[tid] : FD, cy = inreg ? ring_map<TX, TY>.cy[tid] : FD;
+  int cx = FD, cy = FD;
+  if (inreg) {
+    if (ORDER == 0) {
+      cx = tid % W;
+      cy = tid / W;
+    } else {
+      cx = ring_map<TX, TY>.cx[tid];
+      cy = ring_map<TX, TY>.cy[tid];
+    }
+  }
   const int ox = cx - FD, oy = cy - FD;  // footprint-relative
   const int rx = ox < 0 ? -ox : (ox >= TX ? ox - TX + 1 : 0);
   const int ry = oy < 0 ? -oy : (oy >= TY ? oy - TY + 1 : 0);
@@ -130,15 +158,22 @@ __global__ __launch_bounds__((FusedShape<T, TX, TY>::NBLK)) void k_fused_rk4(con
   // later stages: input windows and their Pi at planes (p, p+1); Pi of U_n at plane i-1
   T wj[FD][3][2], qj[FD][2][2];
   T q0p[2] = {(T)0, (T)0};
+  double racc[FD][4];
 #pragma unroll
-  for (int j = 0; j < FD; ++j)
+  for (int j = 0; j < FD; ++j) {
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
       wj[j][0][c] = wj[j][1][c] = wj[j][2][c] = (T)0;
       qj[j][0][c] = qj[j][1][c] = (T)0;
     }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) racc[j][c] = 0.0;
+  }
   const bool own = (r == 0);
   const int ax = own ? ox : 0, ay = own ? oy : 0;
+  const bool edge_lane = (lane == 0) || (lane == SH_WAVE - 1);
+  const int cxm = max(cx - 1, 0), cxp = min(cx + 1, W - 1);
+  const int cym = max(cy - 1, 0), cyp = min(cy + 1, H - 1);
 
   // one iteration: stage j handles plane i - j.  FILL marks the first 2*FG iterations,
   // in which the later stages are still waiting for their input windows to fill.
@@ -172,16 +207,36 @@ __global__ __launch_bounds__((FusedShape<T, TX, TY>::NBLK)) void k_fused_rk4(con
         }
       }
       if (FILL && i < ifirst + 2 * j) break;
+      T(*w)[2] = (j == 0) ? w0 : wj[j];
+      // x neighbours by lane shifts: done with every lane active (before the ring test)
+      T xs[2][2];
+      if (XDPP) {
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          xs[c][0] = dpp_move<DPP_WAVE_SHR1>(w[1][c], w[1][c]);
+          xs[c][1] = dpp_move<DPP_WAVE_SHL1>(w[1][c], w[1][c]);
+        }
+      }
       if (r > FG - j) continue;
-      const T(*w)[2] = (j == 0) ? w0 : wj[j];
       const T q0 = (j == 0) ? q0c[0] : qj[j][0][0];
       const T q1 = (j == 0) ? q0c[1] : qj[j][0][1];
       const T idx2 = (T)sc[j].inv_dx2, cf = (T)sc[j].cf, cp = (T)sc[j].cp;
       T lap[2];
 #pragma unroll
       for (int c = 0; c < 2; ++c) {
-        const T xm = sm[j][c][cy][cx - 1], xp = sm[j][c][cy][cx + 1];
-        const T ym = sm[j][c][cy - 1][cx], yp = sm[j][c][cy + 1][cx];
+        T xm, xp;
+        if (XDPP) {
+          xm = xs[c][0];
+          xp = xs[c][1];
+          if (edge_lane) {
+            xm = sm[j][c][cy][cxm];
+            xp = sm[j][c][cy][cxp];
+          }
+        } else {
+          xm = sm[j][c][cy][cx - 1];
+          xp = sm[j][c][cy][cx + 1];
+        }
+        const T ym = sm[j][c][cym][cx], yp = sm[j][c][cyp][cx];
         lap[c] = ((((xm + xp) + (ym + yp)) + (w[0][c] + w[2][c])) - (T)6.0 * w[1][c]) * idx2;
       }
       const T p0 = w[1][0], p1 = w[1][1];
@@ -204,22 +259,23 @@ __global__ __launch_bounds__((FusedShape<T, TX, TY>::NBLK)) void k_fused_rk4(con
 #pragma unroll
         for (int c = 0; c < 4; ++c) un[c] = col[c * cs + e];
       }
-      double* ac = &sacc[(i - j) & 3][0][ay][ax];
-      constexpr int AST = TY * TX;  // component stride of sacc
+      constexpr int AST = ACCL ? TY * TX : 1;  // component stride of sacc
+      double* ac = ACCL ? &sacc[(i - j) & 3][0][ay][ax] : &racc[j][0];
+      const int ast = ACCL ? AST : 1;
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         if (j == 0) {
           const double u = (double)xin[c];
-          if (own) ac[c * AST] = u + sc[0].h6 * k4[c];
+          if (own) ac[c * ast] = u + sc[0].h6 * k4[c];
           out[c] = (T)(u + sc[0].h2 * k4[c]);
         } else if (j == 1) {
-          if (own) ac[c * AST] = ac[c * AST] + sc[1].h3 * k4[c];
+          if (own) ac[c * ast] = ac[c * ast] + sc[1].h3 * k4[c];
           out[c] = (T)((double)un[c] + sc[1].h2 * k4[c]);
         } else if (j == 2) {
-          if (own) ac[c * AST] = ac[c * AST] + sc[2].h3 * k4[c];
+          if (own) ac[c * ast] = ac[c * ast] + sc[2].h3 * k4[c];
           out[c] = (T)((double)un[c] + sc[2].h1 * k4[c]);
         } else {
-          out[c] = (T)(ac[c * AST] + sc[3].h6 * k4[c]);
+          out[c] = (T)(ac[c * ast] + sc[3].h6 * k4[c]);
         }
       }
       if (j == FD - 1 && own) {
@@ -232,6 +288,15 @@ __global__ __launch_bounds__((FusedShape<T, TX, TY>::NBLK)) void k_fused_rk4(con
       }
     }
     lds_barrier();
+    if (!ACCL) {
+      // register accumulator: advance the per-plane chain by one plane
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        racc[3][c] = racc[2][c];
+        racc[2][c] = racc[1][c];
+        racc[1][c] = racc[0][c];
+      }
+    }
     // advance the stage-0 window by one plane
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
@@ -249,18 +314,33 @@ __global__ __launch_bounds__((FusedShape<T, TX, TY>::NBLK)) void k_fused_rk4(con
   for (; i <= ilast; ++i) iteration(i, std::false_type{});
 }
 
-template <typename T, bool NT, int TX, int TY>
+template <typename T, bool NT, int TX, int TY, int ORDER, bool XDPP, bool ACCL>
 static void fused_launch_shape(const Tile* tiles, int ntiles, const BoxDev* boxes, hipStream_t st) {
   using Sh = FusedShape<T, TX, TY>;
-  hipLaunchKernelGGL((k_fused_rk4<T, NT, TX, TY>), dim3(ntiles), dim3(Sh::NBLK), 0, st, tiles, ntiles, boxes);
+  hipLaunchKernelGGL((k_fused_rk4<T, NT, TX, TY, ORDER, XDPP, ACCL>), dim3(ntiles), dim3(Sh::NBLK), 0, st, tiles,
+                     ntiles, boxes);
+}
+
+// variant: 0 = row-major threads, x neighbours through LDS, accumulator in registers;
+// 1 = row-major, x neighbours by lane shifts, registers; 2 = row-major, lane shifts,
+// accumulator in LDS; 3 = ring-ordered threads, LDS neighbours, accumulator in LDS.
+template <typename T, bool NT, int TX, int TY>
+static void fused_launch_variant(int variant, const Tile* tiles, int ntiles, const BoxDev* boxes, hipStream_t st) {
+  switch (variant) {
+    case 0: fused_launch_shape<T, NT, TX, TY, 0, false, false>(tiles, ntiles, boxes, st); break;
+    case 1: fused_launch_shape<T, NT, TX, TY, 0, true, false>(tiles, ntiles, boxes, st); break;
+    case 2: fused_launch_shape<T, NT, TX, TY, 0, true, true>(tiles, ntiles, boxes, st); break;
+    default: fused_launch_shape<T, NT, TX, TY, 1, false, true>(tiles, ntiles, boxes, st); break;
+  }
 }
 
 template <typename T, bool NT>
-static void fused_launch(int shape, const Tile* tiles, int ntiles, const BoxDev* boxes, hipStream_t st) {
+static void fused_launch(int shape, int variant, const Tile* tiles, int ntiles, const BoxDev* boxes,
+                         hipStream_t st) {
   if (ntiles == 0) return;
-  if (shape == 0) fused_launch_shape<T, NT, 32, 8>(tiles, ntiles, boxes, st);
-  else if (shape == 1) fused_launch_shape<T, NT, 64, 4>(tiles, ntiles, boxes, st);
-  else fused_launch_shape<T, NT, 32, 16>(tiles, ntiles, boxes, st);
+  if (shape == 0) fused_launch_variant<T, NT, 32, 8>(variant, tiles, ntiles, boxes, st);
+  else if (shape == 1) fused_launch_variant<T, NT, 64, 4>(variant, tiles, ntiles, boxes, st);
+  else fused_launch_variant<T, NT, 32, 16>(variant, tiles, ntiles, boxes, st);
 }
 
 // Footprint of a fused tile: shape 0 = 32 x 8, 1 = 64 x 4, 2 = 32 x 16.
@@ -269,13 +349,13 @@ void sh_fused_footprint(int shape, int* tx, int* ty) {
   *ty = shape == 0 ? 8 : (shape == 1 ? 4 : 16);
 }
 
-void sh_launch_fused(int prec, bool nt, int shape, const Tile* tiles, int ntiles, const BoxDev* boxes,
+void sh_launch_fused(int prec, bool nt, int shape, int variant, const Tile* tiles, int ntiles, const BoxDev* boxes,
                      hipStream_t st) {
   if (prec == 0) {
-    if (nt) fused_launch<double, true>(shape, tiles, ntiles, boxes, st);
-    else fused_launch<double, false>(shape, tiles, ntiles, boxes, st);
+    if (nt) fused_launch<double, true>(shape, variant, tiles, ntiles, boxes, st);
+    else fused_launch<double, false>(shape, variant, tiles, ntiles, boxes, st);
   } else {
-    if (nt) fused_launch<float, true>(shape, tiles, ntiles, boxes, st);
-    else fused_launch<float, false>(shape, tiles, ntiles, boxes, st);
+    if (nt) fused_launch<float, true>(shape, variant, tiles, ntiles, boxes, st);
+    else fused_launch<float, false>(shape, variant, tiles, ntiles, boxes, st);
   }
 }

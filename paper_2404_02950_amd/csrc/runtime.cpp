@@ -184,6 +184,7 @@ struct Tuning {
   int fuse = 4;
   int fshape = 0;
   int fzc = 256;
+  int fvar = 0;  // fused kernel variant (thread order / neighbour exchange / accumulator)
 };
 
 static void tuning_from_env(Tuning& t) {
@@ -205,6 +206,7 @@ static void tuning_from_env(Tuning& t) {
       if (k == "fuse" && (v == 0 || v == 4)) t.fuse = v;
       if (k == "fshape" && v >= 0 && v <= 2) t.fshape = v;
       if (k == "fzc" && v >= 1 && v <= 1024) t.fzc = v;
+      if (k == "fvar" && v >= 0 && v <= 3) t.fvar = v;
     }
     pos = end + 1;
   }
@@ -917,7 +919,8 @@ sh_status sh_advance_level(sh_hierarchy h, int32_t l, int32_t sub) {
     // kernel computes the early stages on the ghost-deep ring itself
     for (int st = 0; st < 4; ++st) h->rec(1, l, st, sub);
     ev = h->prof_begin();
-    sh_launch_fused(h->p.prec, h->tune.nt != 0, h->tune.fshape, L.ftiles.p, (int)L.ftiles.n, L.dbox.p, h->st);
+    sh_launch_fused(h->p.prec, h->tune.nt != 0, h->tune.fshape, h->tune.fvar, L.ftiles.p, (int)L.ftiles.n, L.dbox.p,
+                    h->st);
     h->prof_end(ev, 7);
     LAUNCHCHK();
     sh_launch_counter_inc(h->d_ls + l, 1, h->st);
@@ -1130,11 +1133,11 @@ sh_status sh_cluster_tags(sh_hierarchy h, int32_t l, int64_t ntag, const int32_t
 }
 
 sh_status sh_set_tuning(sh_hierarchy h, int32_t kind, int32_t nontemporal, int32_t tile_z, int32_t fuse,
-                        int32_t fused_shape, int32_t fused_tile_z) {
+                        int32_t fused_shape, int32_t fused_tile_z, int32_t fused_variant) {
   if (!h) return fail(SH_EINVAL, "null handle");
   if ((kind != 0 && kind != 4 && kind != 8) || (nontemporal != 0 && nontemporal != 1) || tile_z < 0 ||
       tile_z > 1024 || (fuse != 0 && fuse != 4) || (fused_shape < 0 || fused_shape > 2) || fused_tile_z < 1 ||
-      fused_tile_z > 1024)
+      fused_tile_z > 1024 || fused_variant < 0 || fused_variant > 3)
     return fail(SH_EINVAL, "bad tuning");
   HIPCHK(hipStreamSynchronize(h->st));
   h->tune.kind = kind;
@@ -1143,6 +1146,7 @@ sh_status sh_set_tuning(sh_hierarchy h, int32_t kind, int32_t nontemporal, int32
   h->tune.fuse = fuse;
   h->tune.fshape = fused_shape;
   h->tune.fzc = fused_tile_z;
+  h->tune.fvar = fused_variant;
   for (Level& L : h->lev) {
     std::vector<Tile> wt, bt, ft;
     make_stage_tiles(L.boxes, h->tune, L.g.nvalid, wt, bt);

@@ -59,7 +59,7 @@ _PROTOS = {
     "sh_hierarchy_destroy": (c_int32, [c_void_p]),
     "sh_last_error": (c_char_p, []),
     "sh_debug_stage_scalars": (c_int32, [c_void_p, c_int32, c_int32, POINTER(c_double)]),
-    "sh_set_tuning": (c_int32, [c_void_p, c_int32, c_int32, c_int32, c_int32, c_int32, c_int32]),
+    "sh_set_tuning": (c_int32, [c_void_p, c_int32, c_int32, c_int32, c_int32, c_int32, c_int32, c_int32]),
     "sh_profile": (c_int32, [c_void_p, c_int32]),
     "sh_profile_read": (c_int32, [c_void_p, POINTER(c_double), POINTER(c_int64)]),
     "sh_trace": (c_int32, [c_void_p, c_int32]),
@@ -305,8 +305,9 @@ class Hierarchy:
         return list(out)
 
     def set_tuning(self, kind: int = 8, nontemporal: int = 1, tile_z: int = 0, fuse: int = 4,
-                   fused_shape: int = 0, fused_tile_z: int = 256):
-        _check(self.lib.sh_set_tuning(self.h, kind, nontemporal, tile_z, fuse, fused_shape, fused_tile_z))
+                   fused_shape: int = 0, fused_tile_z: int = 256, fused_variant: int = 0):
+        _check(self.lib.sh_set_tuning(self.h, kind, nontemporal, tile_z, fuse, fused_shape, fused_tile_z,
+                                      fused_variant))
 
     PROFILE_CLASSES = ("stage1", "stage2", "stage3", "stage4", "ghost_copy", "ghost_interp",
                        "average_down", "fused_step")

@@ -195,24 +195,25 @@ def test_stage_kernel_launch_shapes_bitwise(kind, nt, zc):
     h.close()
 
 
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])
 @pytest.mark.parametrize("shape,fzc,cuts", [(0, 64, None), (0, 16, [[32], [32], [24]]), (0, 7, [[32], [8, 40], None]),
                                           (1, 64, None), (1, 13, [None, [16], [40]]), (2, 256, None),
                                           (2, 9, [[32], [16], [24]])])
-def test_fused_four_stage_step_bitwise(shape, fzc, cuts):
+def test_fused_four_stage_step_bitwise(shape, fzc, cuts, variant):
     # the fused step (all four stages in one kernel, overlapped tiles, z pipeline) must
     # give the oracle's bits: single and multi-box level 0, ragged z chunks
     n = 64
     U0 = random_state(n, float(n), 6)
     boxes = decompose(n, [c if c is not None else [] for c in cuts]) if cuts else decompose(n)
     h = single_level(U0, boxes=boxes, beta=0)
-    h.set_tuning(8, 1, 0, fuse=4, fused_shape=shape, fused_tile_z=fzc)
+    h.set_tuning(8, 1, 0, fuse=4, fused_shape=shape, fused_tile_z=fzc, fused_variant=variant)
     h.profile(True)
     ref = run_single_level(U0, 5, 0.1, 0.25, 1.0, beta=0)
     for _ in range(5):
         h.advance(0)
     prof = h.profile_read()
     assert prof["fused_step"][1] == 5 and prof["stage1"][1] == 0, prof
-    assert_bitwise(h.read_dense(0), ref, f"shape={shape} fzc={fzc} cuts={cuts}")
+    assert_bitwise(h.read_dense(0), ref, f"shape={shape} fzc={fzc} cuts={cuts} variant={variant}")
     h.close()
 
 
