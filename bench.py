@@ -78,6 +78,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 2 GiB device copy (calibrates rocprofv3 byte counters)")
+    ap.add_argument("--workload", choices=("single", "amr256", "amr512", "serve"), default="single",
+                    help="single: the 512^3 level step (default); amr256: 256^3 + 3 levels, 8 string loops, "
+                         "50 coarse steps; amr512: 512^3 + 2 levels, 16 loops, FP64 vs FP32, 20 coarse steps; "
+                         "serve: 256 Poisson-arriving ensemble jobs")
+    ap.add_argument("--beta", type=int, default=2, help="potential exponent (2: the paper's EOM; 0: stable companion)")
+    ap.add_argument("--coarse-steps", type=int, default=None)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU path is a design, "
@@ -91,6 +97,12 @@ def main():
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
+    if args.workload in ("amr256", "amr512"):
+        return bench_amr(args)
+    if args.workload == "serve":
+        from paper_2404_02950_amd.serve import bench_serving
+        print(json.dumps(bench_serving(log=log)), flush=True)
+        return
     n, K, W = args.n, args.steps, args.warmup
     log(f"initial state {n}^3 (seed {args.seed})")
     U0 = random_state(n, float(n), args.seed)
@@ -177,6 +189,35 @@ def main():
         out["calib_sum_read_bytes"] = a.numel() * 8
         del s
         del a, b
+    print(json.dumps(out), flush=True)
+
+
+def bench_amr(args):
+    """AMR hierarchies seeded with string loops (coarse dx = 1, dt_0 = 1/4, eta0 = 0.1)."""
+    from paper_2404_02950_amd import shamr, workloads
+    from synth import string_loop_state
+    if args.workload == "amr256":
+        n0, levels, loops, steps = 256, 3, 8, 50
+    else:
+        n0, levels, loops, steps = 512, 2, 16, 20
+    if args.coarse_steps is not None:
+        steps = args.coarse_steps
+    log(f"initial state {n0}^3 with {loops} string loops (seed {args.seed})")
+    U0 = string_loop_state(n0, float(n0), args.seed, loops)
+    out = {"metric": "cell-updates/s per RK stage (AMR, all levels)", "unit": "cell-updates/s",
+           "n_gpus": 1, "data": "synthetic", "higher_is_better": True,
+           "config": {"workload": f"AMR {n0}^3 + {levels} levels, {loops} string loops R in [20, 60], "
+                                  f"blocking factor 8, max box 64, tag buffer 2, regrid every 2 coarse steps, "
+                                  f"{steps} coarse steps, beta = {args.beta}", "seed": args.seed}}
+    if args.workload == "amr256":
+        prec = shamr.SH_F64 if args.prec == "f64" else shamr.SH_F32
+        h, rep = workloads.run_amr(U0, levels, steps, prec=prec, beta=args.beta, log=log)
+        h.close()
+        out.update({"value": rep["cell_updates_per_s_end_to_end"], "dtype": args.prec, "report": rep})
+    else:
+        res = workloads.fp32_vs_fp64(U0, levels, steps, beta=args.beta, log=log)
+        out.update({"value": res["f64"]["cell_updates_per_s_end_to_end"], "dtype": "f64 and f32",
+                    "value_f32": res["f32"]["cell_updates_per_s_end_to_end"], "report": res})
     print(json.dumps(out), flush=True)
 
 

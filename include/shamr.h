@@ -49,6 +49,7 @@ extern "C" {
 #endif
 
 typedef struct sh_hierarchy_s* sh_hierarchy;
+typedef struct sh_batch_s* sh_batch;
 
 typedef enum {
   SH_OK = 0,
@@ -214,6 +215,19 @@ sh_status sh_set_tuning(sh_hierarchy h, int32_t kind, int32_t nontemporal, int32
    7 = fused four-stage step kernel.  Reading synchronises the stream. */
 sh_status sh_profile(sh_hierarchy h, int32_t enable);
 sh_status sh_profile_read(sh_hierarchy h, double* ms, int64_t* counts);
+
+/* Batched stepping of independent simulations (ensemble serving).  A batch groups
+   single-level hierarchies of one precision created on one stream; sh_batch_advance
+   takes one RK4 step of every member with one launch per kernel (fused step, or the four
+   stage kernels and their ghost copies, then the step counters and the ghost copy of the
+   new states), so small lattices share the GPU instead of each filling it alone.  Each
+   member's result is bit-identical to stepping it alone (kernels are gather-only per
+   box).  Members must not be re-laid out or destroyed while the batch exists; the batch
+   borrows them.  Errors: SH_EINVAL (a member with more than one level, another
+   precision or stream). */
+sh_status sh_batch_create(int32_t njobs, const sh_hierarchy* jobs, sh_batch* out);
+sh_status sh_batch_advance(sh_batch b);
+sh_status sh_batch_destroy(sh_batch b);
 
 /* Orchestration trace (diagnostic).  sh_trace(h, 1) clears and starts recording every
    operation that sh_advance_level and sh_average_down issue, as 4 int32 each

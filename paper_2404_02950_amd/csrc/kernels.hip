@@ -264,6 +264,11 @@ __global__ __launch_bounds__(SH_BLOCK) void k_rhs(const Tile* __restrict__ tiles
   }
 }
 
+__global__ void k_counter_inc_list(LevelScal* const* ls, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) ls[i]->k += 1;
+}
+
 __global__ void k_counter_inc(LevelScal* ls, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) ls[i].k += 1;
@@ -752,6 +757,11 @@ void sh_launch_rhs(int prec, const Tile* tiles, int ntiles, const BoxDev* boxes,
   if (nb == 0) return;
   if (prec == 0) hipLaunchKernelGGL(k_rhs<double>, dim3(nb), dim3(SH_BLOCK), 0, st, tiles, ntiles, boxes, out_off, out);
   else hipLaunchKernelGGL(k_rhs<float>, dim3(nb), dim3(SH_BLOCK), 0, st, tiles, ntiles, boxes, out_off, out);
+}
+
+void sh_launch_counter_inc_list(LevelScal* const* ls, int n, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_counter_inc_list, dim3(nblk(n, 64)), dim3(64), 0, st, ls, n);
 }
 
 void sh_launch_counter_inc(LevelScal* ls, int n, hipStream_t st) {

@@ -155,9 +155,10 @@ __global__ __launch_bounds__((FusedShape<T, TX, TY>::NBLK)) void k_fused_rk4(con
     q0c[c] = col[(2 + c) * cs + eat(ifirst)];
     q0n[c] = col[(2 + c) * cs + eat(ifirst + 1)];
   }
-  // later stages: input windows and their Pi at planes (p, p+1); Pi of U_n at plane i-1
+  // later stages: input windows and their Pi at planes (p, p+1); U_n at planes i-1, i-2
+  // (psi of i-1 is the window bottom) for the updates of stages 1 and 2
   T wj[FD][3][2], qj[FD][2][2];
-  T q0p[2] = {(T)0, (T)0};
+  T q0p[2] = {(T)0, (T)0}, u2[4] = {(T)0, (T)0, (T)0, (T)0};
   double racc[FD][4];
 #pragma unroll
   for (int j = 0; j < FD; ++j) {
@@ -246,8 +247,7 @@ __global__ __launch_bounds__((FusedShape<T, TX, TY>::NBLK)) void k_fused_rk4(con
       const T kq1 = (lap[1] - cf * q1) - pot * p1;
       const double k4[4] = {(double)q0, (double)q1, (double)kq0, (double)kq1};
       const T xin[4] = {p0, p1, q0, q1};
-      // U_n at the stage's plane: stage 1 (plane i-1) has it in registers, stage 2
-      // (plane i-2) reads it back (it was loaded two iterations ago: a cache hit)
+      // U_n at the stage's plane (stage 1: plane i-1, stage 2: plane i-2)
       T un[4] = {(T)0, (T)0, (T)0, (T)0};
       if (j == 1) {
         un[0] = w0[0][0];
@@ -255,9 +255,8 @@ __global__ __launch_bounds__((FusedShape<T, TX, TY>::NBLK)) void k_fused_rk4(con
         un[2] = q0p[0];
         un[3] = q0p[1];
       } else if (j == 2) {
-        const long long e = (long long)(i - 2) * plane;
 #pragma unroll
-        for (int c = 0; c < 4; ++c) un[c] = col[c * cs + e];
+        for (int c = 0; c < 4; ++c) un[c] = u2[c];
       }
       constexpr int AST = ACCL ? TY * TX : 1;  // component stride of sacc
       double* ac = ACCL ? &sacc[(i - j) & 3][0][ay][ax] : &racc[j][0];
@@ -300,6 +299,8 @@ __global__ __launch_bounds__((FusedShape<T, TX, TY>::NBLK)) void k_fused_rk4(con
     // advance the stage-0 window by one plane
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
+      u2[c] = w0[0][c];
+      u2[2 + c] = q0p[c];
       w0[0][c] = w0[1][c];
       w0[1][c] = w0[2][c];
       w0[2][c] = nx2[c];

@@ -1194,3 +1194,134 @@ int64_t sh_trace_read(sh_hierarchy h, int32_t* out, int64_t cap) {
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------------
+// Batches: one RK4 step of level 0 of many single-level hierarchies per launch
+// ---------------------------------------------------------------------------------
+struct sh_batch_s {
+  std::vector<sh_hierarchy> jobs;
+  hipStream_t st = nullptr;
+  int prec = 0;
+  Tuning tune;
+  DevArr<BoxDev> boxes;          // every job's level-0 boxes, job after job
+  DevArr<Tile> ftiles;           // fused-step tiles of the jobs that take the fused path
+  DevArr<Tile> wtiles, btiles;   // per-stage tiles of the other jobs
+  SegPlan<CopySeg> a1_stage;     // one-layer ghost copy of the per-stage jobs
+  SegPlan<CopySeg> a1_deep;      // full-depth ghost copy of every job (after the step)
+  DevArr<LevelScal*> counters;
+  void release() {
+    boxes.release();
+    ftiles.release();
+    wtiles.release();
+    btiles.release();
+    a1_stage.release();
+    a1_deep.release();
+    counters.release();
+  }
+};
+
+extern "C" {
+
+sh_status sh_batch_create(int32_t njobs, const sh_hierarchy* jobs, sh_batch* out) {
+  if (!out || njobs < 1 || !jobs) return fail(SH_EINVAL, "bad batch arguments");
+  *out = nullptr;
+  sh_batch b = new (std::nothrow) sh_batch_s;
+  if (!b) return fail(SH_ENOMEM, "host allocation failed");
+  b->st = jobs[0]->st;
+  b->prec = jobs[0]->p.prec;
+  b->tune = jobs[0]->tune;
+  std::vector<BoxDev> boxes;
+  std::vector<Tile> ft, wt, bt;
+  std::vector<CopySeg> s1, sd;
+  std::vector<long long> n1, nd;
+  std::vector<LevelScal*> ctr;
+  for (int j = 0; j < njobs; ++j) {
+    sh_hierarchy h = jobs[j];
+    if (!h || h->lev.size() != 1 || h->st != b->st || h->p.prec != b->prec) {
+      delete b;
+      return fail(SH_EINVAL, "batched jobs must be single-level hierarchies of one precision on one stream");
+    }
+    const Level& L = h->lev[0];
+    const int off = (int)boxes.size();
+    boxes.insert(boxes.end(), L.hbox.begin(), L.hbox.end());
+    ctr.push_back(h->d_ls);
+    std::vector<Tile> f, w, k;
+    make_fused_tiles(L.boxes, b->tune, L.g.ng, f);
+    if (!f.empty()) {
+      for (Tile t : f) { t.box += off; ft.push_back(t); }
+    } else {
+      make_stage_tiles(L.boxes, b->tune, L.g.nvalid, w, k);
+      for (Tile t : w) { t.box += off; wt.push_back(t); }
+      for (Tile t : k) { t.box += off; bt.push_back(t); }
+      std::vector<CopySeg> c;
+      std::vector<long long> nc;
+      build_a1(L, 1, c, nc);
+      for (size_t i = 0; i < c.size(); ++i) {
+        c[i].dbox += off;
+        c[i].sbox += off;
+        s1.push_back(c[i]);
+        n1.push_back(nc[i]);
+      }
+    }
+    std::vector<CopySeg> c;
+    std::vector<long long> nc;
+    build_a1(L, L.g.ng, c, nc);
+    for (size_t i = 0; i < c.size(); ++i) {
+      c[i].dbox += off;
+      c[i].sbox += off;
+      sd.push_back(c[i]);
+      nd.push_back(nc[i]);
+    }
+  }
+  b->jobs.assign(jobs, jobs + njobs);
+  if (b->boxes.upload(boxes) != hipSuccess || b->ftiles.upload(ft) != hipSuccess ||
+      b->wtiles.upload(wt) != hipSuccess || b->btiles.upload(bt) != hipSuccess ||
+      b->a1_stage.upload(s1, n1) != hipSuccess || b->a1_deep.upload(sd, nd) != hipSuccess ||
+      b->counters.upload(ctr) != hipSuccess) {
+    b->release();
+    delete b;
+    return fail(SH_EDEVICE, "batch table upload failed");
+  }
+  *out = b;
+  return SH_OK;
+}
+
+sh_status sh_batch_advance(sh_batch b) {
+  if (!b) return fail(SH_EINVAL, "null batch");
+  const int prec = b->prec;
+  const bool nt = b->tune.nt != 0;
+  if (b->ftiles.n) {
+    sh_launch_fused(prec, nt, b->tune.fshape, b->tune.fvar, b->ftiles.p, (int)b->ftiles.n, b->boxes.p, b->st);
+    LAUNCHCHK();
+  }
+  if (b->wtiles.n || b->btiles.n) {
+    const int role_in[4] = {ROLE_UN, ROLE_A, ROLE_B, ROLE_A};
+    for (int s = 0; s < 4; ++s) {
+      if (s > 0) {
+        sh_launch_ghost_copy(prec, b->a1_stage.segs.p, b->a1_stage.blocks.p, b->a1_stage.nblocks(), b->boxes.p,
+                             role_in[s], 2, b->st);
+        LAUNCHCHK();
+      }
+      if (b->btiles.n) sh_launch_stage(prec, s, b->tune.kind, nt, b->btiles.p, (int)b->btiles.n, b->boxes.p, b->st);
+      if (b->wtiles.n) sh_launch_stage(prec, s, 0, nt, b->wtiles.p, (int)b->wtiles.n, b->boxes.p, b->st);
+      LAUNCHCHK();
+    }
+  }
+  sh_launch_counter_inc_list(b->counters.p, (int)b->counters.n, b->st);
+  LAUNCHCHK();
+  for (sh_hierarchy h : b->jobs) h->lev[0].k += 1;
+  sh_launch_ghost_copy(prec, b->a1_deep.segs.p, b->a1_deep.blocks.p, b->a1_deep.nblocks(), b->boxes.p, ROLE_UN, 4,
+                       b->st);
+  LAUNCHCHK();
+  return SH_OK;
+}
+
+sh_status sh_batch_destroy(sh_batch b) {
+  if (!b) return SH_OK;
+  (void)hipStreamSynchronize(b->st);
+  b->release();
+  delete b;
+  return SH_OK;
+}
+
+}  // extern "C"

@@ -10,6 +10,7 @@ void sh_launch_stage(int prec, int s, int kind, bool nt, const Tile* tiles, int 
 void sh_launch_rhs(int prec, const Tile* tiles, int ntiles, const BoxDev* boxes, const long long* out_off,
                    double* out, hipStream_t st);
 void sh_launch_counter_inc(LevelScal* ls, int n, hipStream_t st);
+void sh_launch_counter_inc_list(LevelScal* const* ls, int n, hipStream_t st);
 void sh_launch_ghost_copy(int prec, const CopySeg* segs, const SegBlock* blocks, int nblocks, const BoxDev* boxes,
                           int role, int ncomp, hipStream_t st);
 void sh_launch_ghost_interp(int prec, const InterpSeg* segs, const SegBlock* blocks, int nblocks,

@@ -62,6 +62,9 @@ _PROTOS = {
     "sh_set_tuning": (c_int32, [c_void_p, c_int32, c_int32, c_int32, c_int32, c_int32, c_int32, c_int32]),
     "sh_profile": (c_int32, [c_void_p, c_int32]),
     "sh_profile_read": (c_int32, [c_void_p, POINTER(c_double), POINTER(c_int64)]),
+    "sh_batch_create": (c_int32, [c_int32, POINTER(c_void_p), POINTER(c_void_p)]),
+    "sh_batch_advance": (c_int32, [c_void_p]),
+    "sh_batch_destroy": (c_int32, [c_void_p]),
     "sh_trace": (c_int32, [c_void_p, c_int32]),
     "sh_trace_read": (c_int64, [c_void_p, c_void_p, c_int64]),
 }
@@ -330,3 +333,29 @@ class Hierarchy:
         buf = np.empty((max(n, 1), 4), np.int32)
         self.lib.sh_trace_read(self.h, buf.ctypes.data_as(c_void_p), n)
         return [tuple(int(v) for v in r) for r in buf[:n]]
+
+
+class Batch:
+    """One RK4 step of many single-level hierarchies per launch (see sh_batch_create)."""
+
+    def __init__(self, hierarchies):
+        self.lib = load()
+        self.members = list(hierarchies)
+        arr = (c_void_p * len(self.members))(*[m.h.value for m in self.members])
+        b = c_void_p()
+        _check(self.lib.sh_batch_create(len(self.members), arr, ctypes.byref(b)))
+        self.b = b
+
+    def advance(self):
+        _check(self.lib.sh_batch_advance(self.b))
+
+    def close(self):
+        if self.b is not None:
+            self.lib.sh_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

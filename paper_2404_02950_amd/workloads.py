@@ -1,0 +1,111 @@
+"""Measured workloads beyond the single-level step: AMR hierarchies with string loops.
+
+``run_amr`` builds a hierarchy from seeded string loops (coarse level n0^3, dx = 1), tags
+and clusters it into refinement levels (Berger-Rigoutsos, blocking factor 8, boxes up to
+64^3, tag buffer 2), then advances it with Berger-Oliger subcycling, regridding every
+``regrid_every`` coarse steps, and reports per-level sizes, throughput and energies.
+"""
+from __future__ import annotations
+
+import time
+
+import numpy as np
+
+from . import driver, shamr
+
+
+def build_hierarchy(U0: np.ndarray, max_level: int, prec: int, beta: int = 2, max_box: int = 64,
+                    blocking_factor: int = 8, n_error_buf: int = 2, efficiency: float = 0.7):
+    n0 = U0.shape[-1]
+    h = shamr.Hierarchy(n0, float(n0), 0.25, 0.1, 1.0, 2.0, beta, max_level=max_level,
+                        blocking_factor=blocking_factor, max_box=max_box, n_error_buf=n_error_buf, prec=prec)
+    h.set_layout(0, [(0, 0, 0, n0 - 1, n0 - 1, n0 - 1)])
+    h.write_dense(0, U0)
+    h.fill_ghosts(0)
+    driver.regrid(h, max_level, efficiency=efficiency)
+    return h
+
+
+def level_summary(h):
+    out = []
+    for lev in range(h.num_levels()):
+        info = h.level_info(lev)
+        out.append({"level": lev, "boxes": info["nboxes"], "cells": info["ncells"], "k": info["k"]})
+    return out
+
+
+def run_amr(U0: np.ndarray, max_level: int, coarse_steps: int, prec: int = shamr.SH_F64, beta: int = 2,
+            regrid_every: int = 2, log=print, efficiency: float = 0.7):
+    """Advance an AMR hierarchy; returns (hierarchy, report dict)."""
+    import torch
+    t0 = time.perf_counter()
+    h = build_hierarchy(U0, max_level, prec, beta=beta, efficiency=efficiency)
+    h.sync()
+    t_build = time.perf_counter() - t0
+    e0, bad0 = h.energy()
+    levels0 = level_summary(h)
+    log(f"built hierarchy in {t_build:.1f} s: {levels0}")
+    cell_stages = 0
+    t_regrid = 0.0
+    h.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for step in range(coarse_steps):
+        if step > 0 and step % regrid_every == 0:
+            tr = time.perf_counter()
+            driver.regrid(h, max_level, efficiency=efficiency)
+            h.sync()
+            t_regrid += time.perf_counter() - tr
+        # cell updates of this coarse step: level l takes 2^l steps of 4 stages
+        for lev in range(h.num_levels()):
+            cell_stages += h.level_info(lev)["ncells"] * 4 * (1 << lev)
+        driver.coarse_step(h)
+        if (step + 1) % 10 == 0:
+            h.sync()
+            log(f"coarse step {step + 1}: {level_summary(h)}")
+    h.sync()
+    wall = time.perf_counter() - t0
+    prof = h.profile_read()
+    h.profile(False)
+    e1, bad1 = h.energy()
+    kernel_ms = sum(v[0] for v in prof.values())
+    report = {
+        "coarse_steps": coarse_steps,
+        "levels_start": levels0,
+        "levels_end": level_summary(h),
+        "wall_s": wall,
+        "regrid_s": t_regrid,
+        "build_s": t_build,
+        "cell_stage_updates": cell_stages,
+        "cell_updates_per_s_end_to_end": cell_stages / wall,
+        "cell_updates_per_s_kernels": cell_stages / (kernel_ms / 1e3) if kernel_ms else None,
+        "kernel_ms": {k: v[0] for k, v in prof.items() if v[1]},
+        "launches": {k: v[1] for k, v in prof.items() if v[1]},
+        "energy_start": e0,
+        "energy_end": e1,
+        "nonfinite_end": bad1,
+    }
+    return h, report
+
+
+def fp32_vs_fp64(U0: np.ndarray, max_level: int, coarse_steps: int, beta: int = 2, log=print):
+    """The same AMR run in FP64 and FP32-storage mode: energies, tag-mask differences
+    on the coarse level and the largest coarse-level field difference at the end."""
+    res = {}
+    fields = {}
+    masks = {}
+    for name, prec in (("f64", shamr.SH_F64), ("f32", shamr.SH_F32)):
+        h, rep = run_amr(U0, max_level, coarse_steps, prec=prec, beta=beta, log=log)
+        res[name] = rep
+        fields[name] = h.read_dense(0)
+        masks[name] = h.tag_mask_dense(0)
+        h.close()
+    d = np.abs(fields["f32"] - fields["f64"])
+    finite = np.isfinite(fields["f64"])
+    res["coarse_max_abs_diff"] = float(np.max(d[finite])) if finite.any() else None
+    res["coarse_max_rel_diff"] = (float(np.max(d[finite]) / np.max(np.abs(fields["f64"][finite])))
+                                  if finite.any() else None)
+    res["coarse_tag_mask_differences"] = int(np.count_nonzero(masks["f32"] != masks["f64"]))
+    e64, e32 = res["f64"]["energy_end"][3], res["f32"]["energy_end"][3]
+    res["energy_total_rel_diff"] = abs(e32 - e64) / abs(e64) if e64 else None
+    return res

@@ -81,8 +81,8 @@ def string_loop_state(n: int, L: float, seed: int, nloops: int,
     on the sphere, all from the same generator as the random field (drawn after it).
     Its phase theta_j = atan2(z', rho - R) - atan2(z', rho + R) winds once around the
     core circle (rho, z' cylindrical coordinates about the loop axis, minimum image);
-    theta_j is tapered to 0 by a cos^2 window between |r| = R + taper_in and
-    R + taper_out so the periodic seam carries no winding.  The amplitude is
+    theta_j is tapered by a cos^2 window between |r| = R + taper_in and R + taper_out
+    (exactly 0 beyond) so the periodic seam carries no winding.  The amplitude is
     prod_j tanh(d_j / 2), d_j the distance to core j.  Pi = 0.
     """
     rng = np.random.default_rng(seed)
@@ -98,13 +98,26 @@ def string_loop_state(n: int, L: float, seed: int, nloops: int,
         raise ValueError("loop plus taper does not fit in half the lattice")
     psi1 = np.empty((n, n, n))
     psi2 = np.empty((n, n, n))
+    # outside |r| > R + taper_out a loop contributes nothing: its phase is tapered to 0
+    # and, when taper_out/2 exceeds 19.1, tanh(d/2) of the core distance d rounds to 1
+    local = taper_out / 2 > 19.1
     idx = np.arange(n, dtype=np.float64)
-    Y, X = np.meshgrid(idx, idx, indexing="ij")
     for z in range(n):  # slab by slab to bound memory at large n
         amp = np.ones((n, n))
         theta = np.zeros((n, n))
         for R, c, v in loops:
-            d = np.stack([np.full((n, n), float(z)) - c[0], Y - c[1], X - c[2]])
+            reach = R + taper_out
+            dz = z - c[0]
+            dz -= n * np.round(dz / n)
+            if local and abs(dz) > reach:
+                continue
+            if local:
+                ys = np.nonzero(np.abs((idx - c[1]) - n * np.round((idx - c[1]) / n)) <= reach)[0]
+                xs = np.nonzero(np.abs((idx - c[2]) - n * np.round((idx - c[2]) / n)) <= reach)[0]
+            else:
+                ys = xs = np.arange(n)
+            Y, X = np.meshgrid(idx[ys], idx[xs], indexing="ij")
+            d = np.stack([np.full(Y.shape, float(z)) - c[0], Y - c[1], X - c[2]])
             d -= n * np.round(d / n)  # minimum image
             zp = d[0] * v[0] + d[1] * v[1] + d[2] * v[2]
             perp = d - zp[None] * v[:, None, None]
@@ -112,9 +125,11 @@ def string_loop_state(n: int, L: float, seed: int, nloops: int,
             dist = np.sqrt((rho - R) ** 2 + zp ** 2)
             th = np.arctan2(zp, rho - R) - np.arctan2(zp, rho + R)
             rr = np.sqrt(np.sum(d * d, axis=0))
-            s = np.clip((rr - (R + taper_in)) / (taper_out - taper_in), 0.0, 1.0)
-            theta += th * np.cos(0.5 * np.pi * s) ** 2
-            amp *= np.tanh(0.5 * dist)
+            sfr = (rr - (R + taper_in)) / (taper_out - taper_in)
+            taper = np.where(sfr >= 1.0, 0.0, np.cos(0.5 * np.pi * np.clip(sfr, 0.0, 1.0)) ** 2)
+            sub = np.ix_(ys, xs)
+            theta[sub] += th * taper
+            amp[sub] *= np.tanh(0.5 * dist)
         psi1[z] = amp * np.cos(theta) + delta * r1[z]
         psi2[z] = amp * np.sin(theta) + delta * r2[z]
     return state_from_psi(psi1, psi2)
