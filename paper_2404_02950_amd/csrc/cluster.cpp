@@ -13,8 +13,13 @@
 // is not inside the tagged level are dropped and may not lie inside an accepted box (a
 // box holding one is cut further), which keeps the new level properly nested with a gap
 // of one fine blocking factor.
+//
+// The recursion works on the list of tagged blocks (partitioned in place at each cut),
+// so its cost follows the number of tagged blocks, not the size of the domain; the only
+// whole-domain structures are two bitsets of one bit per block.
 #include <stdint.h>
 
+#include <algorithm>
 #include <cstdlib>
 #include <string>
 #include <vector>
@@ -23,67 +28,83 @@
 
 namespace {
 
-struct Grid {
+struct Bits {
   int n = 0;
-  std::vector<uint8_t> v;
-  std::vector<int> sat;  // summed-area table, (n+1)^3
-  uint8_t& at(int x, int y, int z) { return v[((size_t)z * n + y) * n + x]; }
-  int S(int x, int y, int z) const { return sat[((size_t)z * (n + 1) + y) * (n + 1) + x]; }
-  void build_sat() {
-    const int m = n + 1;
-    sat.assign((size_t)m * m * m, 0);
-    for (int z = 1; z <= n; ++z)
-      for (int y = 1; y <= n; ++y)
-        for (int x = 1; x <= n; ++x) {
-          const size_t i = ((size_t)z * m + y) * m + x;
-          sat[i] = v[((size_t)(z - 1) * n + (y - 1)) * n + (x - 1)] + sat[i - 1] + sat[i - m] + sat[i - (size_t)m * m] -
-                   sat[i - 1 - m] - sat[i - 1 - (size_t)m * m] - sat[i - m - (size_t)m * m] +
-                   sat[i - 1 - m - (size_t)m * m];
-        }
+  std::vector<uint64_t> w;
+  void init(int n_) {
+    n = n_;
+    w.assign(((size_t)n * n * n + 63) / 64, 0);
   }
-  long long count(const IBox& b) const {
-    if (b.empty()) return 0;
-    const int x0 = b.lo[0], y0 = b.lo[1], z0 = b.lo[2], x1 = b.hi[0] + 1, y1 = b.hi[1] + 1, z1 = b.hi[2] + 1;
-    return (long long)S(x1, y1, z1) - S(x0, y1, z1) - S(x1, y0, z1) - S(x1, y1, z0) + S(x0, y0, z1) + S(x0, y1, z0) +
-           S(x1, y0, z0) - S(x0, y0, z0);
+  static size_t key(int n, int x, int y, int z) { return ((size_t)z * n + y) * n + x; }
+  void set(int x, int y, int z) {
+    const size_t k = key(n, x, y, z);
+    w[k >> 6] |= 1ull << (k & 63);
+  }
+  bool get(int x, int y, int z) const {
+    const size_t k = key(n, x, y, z);
+    return (w[k >> 6] >> (k & 63)) & 1;
   }
 };
 
-IBox slice(const IBox& b, int d, int i) {
-  IBox s = b;
-  s.lo[d] = s.hi[d] = i;
-  return s;
-}
+int floordiv(int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
+int wrap(int a, int n) { return ((a % n) + n) % n; }
 
-IBox bounding(const Grid& g, IBox b) {
-  if (g.count(b) == 0) {
-    b.hi[0] = b.lo[0] - 1;
-    return b;
-  }
+struct Pt {
+  int c[3];
+};
+
+struct Ctx {
+  std::vector<Pt> pts;
+  const Bits* cov = nullptr;  // blocks inside the tagged level (null: the whole domain)
+  double eff = 0.7;
+  std::vector<IBox> out;
+  std::vector<long long> sig[3];
+};
+
+IBox bounding(const Pt* p, long long n) {
+  IBox b;
   for (int d = 0; d < 3; ++d) {
-    while (g.count(slice(b, d, b.lo[d])) == 0) ++b.lo[d];
-    while (g.count(slice(b, d, b.hi[d])) == 0) --b.hi[d];
+    b.lo[d] = p[0].c[d];
+    b.hi[d] = p[0].c[d];
   }
+  for (long long i = 1; i < n; ++i)
+    for (int d = 0; d < 3; ++d) {
+      b.lo[d] = std::min(b.lo[d], p[i].c[d]);
+      b.hi[d] = std::max(b.hi[d], p[i].c[d]);
+    }
   return b;
 }
 
-// g: tagged blocks; forbid: blocks a box may not contain (nesting), or null
-void br(const Grid& g, const Grid* forbid, IBox box, double eff, std::vector<IBox>& out) {
-  box = bounding(g, box);
-  if (box.empty()) return;
-  const long long n = g.count(box), vol = box.volume();
-  const bool clean = !forbid || forbid->count(box) == 0;
-  if (((double)n >= eff * (double)vol && clean) || vol == 1) {
-    out.push_back(box);
+// every block of the box has its one-block neighbourhood inside the level
+bool clean(const Bits& cov, const IBox& b) {
+  const int n = cov.n;
+  for (int z = b.lo[2] - 1; z <= b.hi[2] + 1; ++z)
+    for (int y = b.lo[1] - 1; y <= b.hi[1] + 1; ++y)
+      for (int x = b.lo[0] - 1; x <= b.hi[0] + 1; ++x)
+        if (!cov.get(wrap(x, n), wrap(y, n), wrap(z, n))) return false;
+  return true;
+}
+
+void br(Ctx& C, long long first, long long count) {
+  if (count == 0) return;
+  Pt* p = C.pts.data() + first;
+  const IBox box = bounding(p, count);
+  const long long vol = box.volume();
+  if (vol == 1 || ((double)count >= C.eff * (double)vol && (!C.cov || clean(*C.cov, box)))) {
+    C.out.push_back(box);
     return;
   }
+  // signatures: tagged blocks per slice along each direction
+  for (int d = 0; d < 3; ++d) C.sig[d].assign(box.size(d), 0);
+  for (long long i = 0; i < count; ++i)
+    for (int d = 0; d < 3; ++d) ++C.sig[d][p[i].c[d] - box.lo[d]];
   int best_d = -1, best_cut = 0;
   // 1) a hole in a signature, the one nearest the middle of its side
   double best_dist = 1e30;
   for (int d = 0; d < 3; ++d) {
     const double mid = 0.5 * (box.lo[d] + box.hi[d]);
     for (int i = box.lo[d] + 1; i < box.hi[d]; ++i)
-      if (g.count(slice(box, d, i)) == 0 && std::abs(i - mid) < best_dist) {
+      if (C.sig[d][i - box.lo[d]] == 0 && std::abs(i - mid) < best_dist) {
         best_dist = std::abs(i - mid);
         best_d = d;
         best_cut = i;
@@ -95,8 +116,8 @@ void br(const Grid& g, const Grid* forbid, IBox box, double eff, std::vector<IBo
     for (int d = 0; d < 3; ++d) {
       const int len = box.size(d);
       if (len < 4) continue;
-      std::vector<long long> sig(len), lap(len, 0);
-      for (int i = 0; i < len; ++i) sig[i] = g.count(slice(box, d, box.lo[d] + i));
+      const std::vector<long long>& sig = C.sig[d];
+      std::vector<long long> lap(len, 0);
       for (int i = 1; i + 1 < len; ++i) lap[i] = sig[i - 1] - 2 * sig[i] + sig[i + 1];
       const double mid = 0.5 * (len - 1);
       for (int i = 1; i + 2 < len; ++i) {
@@ -119,15 +140,12 @@ void br(const Grid& g, const Grid* forbid, IBox box, double eff, std::vector<IBo
       if (box.size(d) > box.size(best_d)) best_d = d;
     best_cut = box.lo[best_d] + box.size(best_d) / 2;
   }
-  IBox a = box, b = box;
-  a.hi[best_d] = best_cut - 1;
-  b.lo[best_d] = best_cut;
-  br(g, forbid, a, eff, out);
-  br(g, forbid, b, eff, out);
+  const int d = best_d, cut = best_cut;
+  Pt* mid = std::stable_partition(p, p + count, [&](const Pt& q) { return q.c[d] < cut; });
+  const long long nlo = mid - p;
+  br(C, first, nlo);
+  br(C, first + nlo, count - nlo);
 }
-
-int floordiv(int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
-int wrap(int a, int n) { return ((a % n) + n) % n; }
 
 }  // namespace
 
@@ -144,9 +162,14 @@ bool cluster_level(int M, const std::vector<IBox>& level_boxes, bool full_level,
     return false;
   }
   const int nb = M / b;
-  Grid g;
-  g.n = nb;
-  g.v.assign((size_t)nb * nb * nb, 0);
+  for (const IBox& L : level_boxes)
+    for (int d = 0; d < 3; ++d)
+      if (L.lo[d] < 0 || L.hi[d] >= M || L.lo[d] > L.hi[d]) {
+        err = "level box outside the level";
+        return false;
+      }
+  Bits tagged;
+  tagged.init(nb);
   for (long long t = 0; t < ntag; ++t) {
     int c[3], lo[3], hi[3];
     for (int d = 0; d < 3; ++d) {
@@ -164,47 +187,46 @@ bool cluster_level(int M, const std::vector<IBox>& level_boxes, bool full_level,
     }
     for (int z = lo[2]; z <= hi[2]; ++z)
       for (int y = lo[1]; y <= hi[1]; ++y)
-        for (int x = lo[0]; x <= hi[0]; ++x) g.at(wrap(x, nb), wrap(y, nb), wrap(z, nb)) = 1;
+        for (int x = lo[0]; x <= hi[0]; ++x) tagged.set(wrap(x, nb), wrap(y, nb), wrap(z, nb));
   }
-  Grid forbid;
+  Bits cov;
   if (!full_level) {
-    forbid.n = nb;
-    forbid.v.assign((size_t)nb * nb * nb, 0);
-    std::vector<uint8_t> cov((size_t)nb * nb * nb, 0);
+    cov.init(nb);
     for (const IBox& L : level_boxes) {
       // blocks fully inside the box
       const int x0 = (L.lo[0] + b - 1) / b, y0 = (L.lo[1] + b - 1) / b, z0 = (L.lo[2] + b - 1) / b;
       const int x1 = (L.hi[0] + 1) / b - 1, y1 = (L.hi[1] + 1) / b - 1, z1 = (L.hi[2] + 1) / b - 1;
       for (int z = z0; z <= z1; ++z)
         for (int y = y0; y <= y1; ++y)
-          for (int x = x0; x <= x1; ++x) cov[((size_t)z * nb + y) * nb + x] = 1;
+          for (int x = x0; x <= x1; ++x) cov.set(x, y, z);
     }
-    for (int z = 0; z < nb; ++z)
-      for (int y = 0; y < nb; ++y)
-        for (int x = 0; x < nb; ++x) {
-          bool ok = true;
-          for (int dz = -1; dz <= 1 && ok; ++dz)
-            for (int dy = -1; dy <= 1 && ok; ++dy)
-              for (int dx = -1; dx <= 1 && ok; ++dx)
-                ok = cov[((size_t)wrap(z + dz, nb) * nb + wrap(y + dy, nb)) * nb + wrap(x + dx, nb)] != 0;
-          if (!ok) {
-            g.at(x, y, z) = 0;
-            forbid.at(x, y, z) = 1;
-          }
-        }
-    forbid.build_sat();
   }
-  g.build_sat();
-  std::vector<IBox> blk;
-  IBox all;
-  for (int d = 0; d < 3; ++d) {
-    all.lo[d] = 0;
-    all.hi[d] = nb - 1;
+  Ctx C;
+  C.eff = efficiency;
+  C.cov = full_level ? nullptr : &cov;
+  // tagged blocks in (z, y, x) order, without those whose neighbourhood leaves the level
+  for (size_t wi = 0; wi < tagged.w.size(); ++wi) {
+    uint64_t word = tagged.w[wi];
+    while (word) {
+      const int bit = __builtin_ctzll(word);
+      word &= word - 1;
+      const size_t k = (wi << 6) + bit;
+      Pt q;
+      q.c[0] = (int)(k % nb);
+      q.c[1] = (int)((k / nb) % nb);
+      q.c[2] = (int)(k / ((size_t)nb * nb));
+      if (!full_level) {
+        IBox one;
+        for (int d = 0; d < 3; ++d) one.lo[d] = one.hi[d] = q.c[d];
+        if (!clean(cov, one)) continue;
+      }
+      C.pts.push_back(q);
+    }
   }
-  br(g, full_level ? nullptr : &forbid, all, efficiency, blk);
+  br(C, 0, (long long)C.pts.size());
   // refine to the next level (block = bf fine cells) and chop to max_box
   const int mb = std::max(bf, max_box / bf * bf);
-  for (const IBox& B : blk) {
+  for (const IBox& B : C.out) {
     int len[3], npc[3];
     for (int d = 0; d < 3; ++d) {
       len[d] = B.size(d);                   // in units of bf

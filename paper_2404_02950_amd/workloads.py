@@ -35,9 +35,14 @@ def level_summary(h):
 
 
 def run_amr(U0: np.ndarray, max_level: int, coarse_steps: int, prec: int = shamr.SH_F64, beta: int = 2,
-            regrid_every: int = 2, log=print, efficiency: float = 0.7):
-    """Advance an AMR hierarchy; returns (hierarchy, report dict)."""
+            regrid_every: int = 2, log=print, efficiency: float = 0.7, max_level_bytes: int | None = None):
+    """Advance an AMR hierarchy; returns (hierarchy, report dict).
+
+    ``max_level_bytes`` (default: a quarter of the device memory free at the start) caps
+    any one level's arena at regrid; see ``driver.regrid``."""
     import torch
+    if max_level_bytes is None:
+        max_level_bytes = torch.cuda.mem_get_info()[0] // 4
     t0 = time.perf_counter()
     h = build_hierarchy(U0, max_level, prec, beta=beta, efficiency=efficiency)
     h.sync()
@@ -47,14 +52,20 @@ def run_amr(U0: np.ndarray, max_level: int, coarse_steps: int, prec: int = shamr
     log(f"built hierarchy in {t_build:.1f} s: {levels0}")
     cell_stages = 0
     t_regrid = 0.0
+    regrid_parts = {}
+    capped = []
     h.profile(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for step in range(coarse_steps):
         if step > 0 and step % regrid_every == 0:
             tr = time.perf_counter()
-            driver.regrid(h, max_level, efficiency=efficiency)
+            nlev = h.num_levels()
+            driver.regrid(h, max_level, efficiency=efficiency, max_level_bytes=max_level_bytes, log=log,
+                          timing=regrid_parts)
             h.sync()
+            if h.num_levels() < nlev:
+                capped.append({"coarse_step": step, "levels": h.num_levels()})
             t_regrid += time.perf_counter() - tr
         # cell updates of this coarse step: level l takes 2^l steps of 4 stages
         for lev in range(h.num_levels()):
@@ -75,6 +86,8 @@ def run_amr(U0: np.ndarray, max_level: int, coarse_steps: int, prec: int = shamr
         "levels_end": level_summary(h),
         "wall_s": wall,
         "regrid_s": t_regrid,
+        "regrid_parts_s": regrid_parts,
+        "refinement_capped": capped,
         "build_s": t_build,
         "cell_stage_updates": cell_stages,
         "cell_updates_per_s_end_to_end": cell_stages / wall,

@@ -98,3 +98,8 @@ def test_clustering_efficiency_and_empty(shamr):
 def test_clustering_rejects_bad_input(shamr):
     with pytest.raises(shamr.ShError):
         shamr.cluster_boxes(32, [], [(40, 0, 0)])
+    # a level box that reaches outside [0, M) is an error, not an out-of-bounds write
+    with pytest.raises(shamr.ShError):
+        shamr.cluster_boxes(32, [(0, 0, 0, 63, 63, 63)], [(4, 4, 4)])
+    with pytest.raises(shamr.ShError):
+        shamr.cluster_boxes(32, [(-8, 0, 0, 7, 7, 7)], [(4, 4, 4)])
