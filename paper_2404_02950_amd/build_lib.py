@@ -32,6 +32,17 @@ HIP_SOURCES = ["kernels.hip", "kernels_fused.hip", "runtime.cpp"]
 HOST_SOURCES = ["cluster.cpp"]
 
 
+def kernel_source_sha() -> str:
+    """SHA-256 over the device-code sources; counter summaries record it so a figure taken
+    on other kernels is not reported for these."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "kernels_fused.hip", "sh_device.h", "sh_internal.h"):
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
 def _hipcc() -> str:
     for c in (os.environ.get("HIPCC"), "/opt/rocm/bin/hipcc", shutil.which("hipcc")):
         if c and os.path.exists(c):

@@ -13,7 +13,8 @@
 // beyond where it is computed, so stage j is computed on the footprint grown by 3 - j
 // cells (overlapped tiles), and the threads cover the footprint grown by 4 cells, the
 // outermost ring only loading U_n.  Each iteration every stage publishes its input plane
-// to LDS, one barrier, then stages 0..3 run in order reading x/y neighbours from LDS.
+// to LDS (two buffers alternating by iteration), one barrier, then stages 0..3 run in
+// order reading x/y neighbours from LDS.
 // The z-range is extended the same way (stage j covers 3 - j extra planes below and
 // above), so U_n is read from z0-4 to z0+zc+3: the level keeps a 4-deep ghost shell.
 // The accumulator exists only on the footprint's own columns; it is kept in LDS.
@@ -94,7 +95,13 @@ __global__ __launch_bounds__((FusedShape<T, TX, TY>::NBLK)) void k_fused_rk4(con
   static_assert(!(XDPP && ORDER != 0), "lane shifts need the row-major order");
   using Sh = FusedShape<T, TX, TY>;
   constexpr int W = Sh::W, H = Sh::H;
-  __shared__ T sm[FD][2][H][W];
+  // stage input planes, double-buffered by iteration parity where LDS allows: a buffer is
+  // rewritten two iterations later, after the next iteration's barrier, so one barrier per
+  // iteration orders every write after the reads of the same buffer (single-buffered, a
+  // second barrier closes each iteration)
+  constexpr size_t LDS_ACC = ACCL ? sizeof(double) * 4 * 4 * TY * TX : 0;
+  constexpr int NBUF = (2 * sizeof(T) * FD * 2 * H * W + LDS_ACC <= 160 * 1024) ? 2 : 1;
+  __shared__ T sm2[NBUF][FD][2][H][W];
   // accumulator of the footprint's own columns for the four planes in flight (slot =
   // plane mod 4); each thread touches only its own column, so no barrier is involved
   __shared__ double sacc[ACCL ? 4 : 1][4][ACCL ? TY : 1][ACCL ? TX : 1];
@@ -107,7 +114,7 @@ __global__ __launch_bounds__((FusedShape<T, TX, TY>::NBLK)) void k_fused_rk4(con
   const LevelScal L = *B.ls;
   StageScal sc[FD];
 #pragma unroll
-  for (int j = 0; j < FD; ++j) sc[j] = stage_scalars(L, j);
+  for (int j = 0; j < FD; ++j) sc[j] = uniform(stage_scalars(L, j));
   const T* __restrict__ X = (const T*)B.slot[role_slot(ROLE_UN, L.k)];
   T* __restrict__ Y = (T*)B.slot[role_slot(ROLE_B, L.k)];
 
@@ -144,16 +151,14 @@ __global__ __launch_bounds__((FusedShape<T, TX, TY>::NBLK)) void k_fused_rk4(con
   auto eat = [&](int z) { return (long long)min(max(z, zlo), zhi) * plane; };
 
   const int ifirst = z0 - FG, ilast = z0 + zc - 1 + FG;
-  // stage 0 input window (planes i-1, i, i+1), next psi plane and Pi of planes i, i+1
-  T w0[3][2], nx2[2], q0c[2], q0n[2];
+  // stage 0 input window (planes i-1, i, i+1) and Pi of plane i
+  T w0[3][2], q0c[2];
 #pragma unroll
   for (int c = 0; c < 2; ++c) {
     w0[0][c] = col[c * cs + eat(ifirst - 1)];
     w0[1][c] = col[c * cs + eat(ifirst)];
     w0[2][c] = col[c * cs + eat(ifirst + 1)];
-    nx2[c] = col[c * cs + eat(ifirst + 2)];
     q0c[c] = col[(2 + c) * cs + eat(ifirst)];
-    q0n[c] = col[(2 + c) * cs + eat(ifirst + 1)];
   }
   // later stages: input windows and their Pi at planes (p, p+1); U_n at planes i-1, i-2
   // (psi of i-1 is the window bottom) for the updates of stages 1 and 2
@@ -180,6 +185,16 @@ __global__ __launch_bounds__((FusedShape<T, TX, TY>::NBLK)) void k_fused_rk4(con
   // in which the later stages are still waiting for their input windows to fill.
   auto iteration = [&](const int i, auto fill_tag) {
     constexpr bool FILL = decltype(fill_tag)::value;
+    T(*sm)[2][H][W] = sm2[NBUF == 2 ? (i & 1) : 0];
+    // the U_n planes that enter the stage-0 window at the end of this iteration: issued
+    // first, so their latency is covered by this iteration's stages (a value loaded in one
+    // iteration and carried into the next would be waited for at the loop's back edge)
+    T lpsi[2], lpi[2];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      lpsi[c] = col[c * cs + eat(i + 2)];
+      lpi[c] = col[(2 + c) * cs + eat(i + 1)];
+    }
     // publish every stage's input plane: stage 0 = U_n psi at i, stage j = its window top
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
@@ -286,7 +301,7 @@ __global__ __launch_bounds__((FusedShape<T, TX, TY>::NBLK)) void k_fused_rk4(con
         }
       }
     }
-    lds_barrier();
+    if (NBUF == 1) lds_barrier();
     if (!ACCL) {
       // register accumulator: advance the per-plane chain by one plane
 #pragma unroll
@@ -303,11 +318,9 @@ __global__ __launch_bounds__((FusedShape<T, TX, TY>::NBLK)) void k_fused_rk4(con
       u2[2 + c] = q0p[c];
       w0[0][c] = w0[1][c];
       w0[1][c] = w0[2][c];
-      w0[2][c] = nx2[c];
-      nx2[c] = col[c * cs + eat(i + 3)];
+      w0[2][c] = lpsi[c];
       q0p[c] = q0c[c];
-      q0c[c] = q0n[c];
-      q0n[c] = col[(2 + c) * cs + eat(i + 2)];
+      q0c[c] = lpi[c];
     }
   };
   int i = ifirst;
@@ -341,13 +354,16 @@ static void fused_launch(int shape, int variant, const Tile* tiles, int ntiles, 
   if (ntiles == 0) return;
   if (shape == 0) fused_launch_variant<T, NT, 32, 8>(variant, tiles, ntiles, boxes, st);
   else if (shape == 1) fused_launch_variant<T, NT, 64, 4>(variant, tiles, ntiles, boxes, st);
-  else fused_launch_variant<T, NT, 32, 16>(variant, tiles, ntiles, boxes, st);
+  else if (shape == 2) fused_launch_variant<T, NT, 32, 16>(variant, tiles, ntiles, boxes, st);
+  else fused_launch_variant<T, NT, 16, 8>(variant, tiles, ntiles, boxes, st);
 }
 
-// Footprint of a fused tile: shape 0 = 32 x 8, 1 = 64 x 4, 2 = 32 x 16.
+// Footprint of a fused tile: shape 0 = 32 x 8, 1 = 64 x 4, 2 = 32 x 16, 3 = 16 x 8 (two
+// workgroups per CU).
 void sh_fused_footprint(int shape, int* tx, int* ty) {
-  *tx = shape == 1 ? 64 : 32;
-  *ty = shape == 0 ? 8 : (shape == 1 ? 4 : 16);
+  static const int fx[4] = {32, 64, 32, 16}, fy[4] = {8, 4, 16, 8};
+  *tx = fx[shape];
+  *ty = fy[shape];
 }
 
 void sh_launch_fused(int prec, bool nt, int shape, int variant, const Tile* tiles, int ntiles, const BoxDev* boxes,

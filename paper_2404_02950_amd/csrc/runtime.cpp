@@ -175,7 +175,7 @@ static void make_geom(int prec, int ng, const std::vector<IBox>& boxes, LayoutGe
 // wave-row tiles).  nt: nontemporal once-used streams.  zc: cells per tile in z (0 =
 // chosen from the level size).
 // fuse: 4 = level 0 advances with the fused four-stage kernel when its boxes are
-// multiples of the fused footprint (fshape 0: 32 x 8, 1: 64 x 4, 2: 32 x 16), 0 =
+// multiples of the fused footprint (fshape 0: 32 x 8, 1: 64 x 4, 2: 32 x 16, 3: 16 x 8), 0 =
 // per-stage kernels.
 struct Tuning {
   int kind = 8;
@@ -183,9 +183,21 @@ struct Tuning {
   int zc = 0;
   int fuse = 4;
   int fshape = 0;
-  int fzc = 256;
+  int fzc = 512;
   int fvar = 0;  // fused kernel variant (thread order / neighbour exchange / accumulator)
 };
+
+// Measured best fused launch per storage type on MI355X at 512^3: FP64 32 x 8 footprint,
+// row-major threads, registers (166 VGPRs, one 10-wave workgroup per CU); FP32 32 x 16,
+// ring-ordered threads, accumulator in LDS (15 waves per workgroup).
+static Tuning default_tuning(int prec) {
+  Tuning t;
+  if (prec == SH_F32) {
+    t.fshape = 2;
+    t.fvar = 3;
+  }
+  return t;
+}
 
 static void tuning_from_env(Tuning& t) {
   const char* env = std::getenv("SHAMR_TUNE");  // e.g. "kind=8,nt=1,zc=32"
@@ -204,7 +216,7 @@ static void tuning_from_env(Tuning& t) {
       if (k == "nt" && (v == 0 || v == 1)) t.nt = v;
       if (k == "zc" && v >= 0 && v <= 1024) t.zc = v;
       if (k == "fuse" && (v == 0 || v == 4)) t.fuse = v;
-      if (k == "fshape" && v >= 0 && v <= 2) t.fshape = v;
+      if (k == "fshape" && v >= 0 && v <= 3) t.fshape = v;
       if (k == "fzc" && v >= 1 && v <= 1024) t.fzc = v;
       if (k == "fvar" && v >= 0 && v <= 3) t.fvar = v;
     }
@@ -659,6 +671,7 @@ sh_status sh_hierarchy_create(const sh_params* p, void* hip_stream, sh_hierarchy
   sh_hierarchy h = new (std::nothrow) sh_hierarchy_s;
   if (!h) return fail(SH_ENOMEM, "host allocation failed");
   h->p = *p;
+  h->tune = default_tuning(p->prec);
   tuning_from_env(h->tune);
   h->st = (hipStream_t)hip_stream;
   if (hipMalloc((void**)&h->d_ls, 16 * sizeof(LevelScal)) != hipSuccess ||
@@ -1136,7 +1149,7 @@ sh_status sh_set_tuning(sh_hierarchy h, int32_t kind, int32_t nontemporal, int32
                         int32_t fused_shape, int32_t fused_tile_z, int32_t fused_variant) {
   if (!h) return fail(SH_EINVAL, "null handle");
   if ((kind != 0 && kind != 4 && kind != 8) || (nontemporal != 0 && nontemporal != 1) || tile_z < 0 ||
-      tile_z > 1024 || (fuse != 0 && fuse != 4) || (fused_shape < 0 || fused_shape > 2) || fused_tile_z < 1 ||
+      tile_z > 1024 || (fuse != 0 && fuse != 4) || (fused_shape < 0 || fused_shape > 3) || fused_tile_z < 1 ||
       fused_tile_z > 1024 || fused_variant < 0 || fused_variant > 3)
     return fail(SH_EINVAL, "bad tuning");
   HIPCHK(hipStreamSynchronize(h->st));

@@ -43,6 +43,26 @@ __device__ __forceinline__ StageScal stage_scalars(const LevelScal& L, int s) {
   return r;
 }
 
+// The stage scalars are the same for every lane; saying so keeps them in scalar
+// registers instead of occupying vector registers for the whole kernel.
+__device__ __forceinline__ double uniform(double v) {
+  const int lo = __builtin_amdgcn_readfirstlane(__double2loint(v));
+  const int hi = __builtin_amdgcn_readfirstlane(__double2hiint(v));
+  return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ StageScal uniform(const StageScal& s) {
+  StageScal r;
+  r.cf = uniform(s.cf);
+  r.cp = uniform(s.cp);
+  r.inv_dx2 = uniform(s.inv_dx2);
+  r.h6 = uniform(s.h6);
+  r.h3 = uniform(s.h3);
+  r.h2 = uniform(s.h2);
+  r.h1 = uniform(s.h1);
+  return r;
+}
+
 // Blocks are dispatched round-robin over the 8 XCDs of MI355X.  Map hardware block b
 // to logical block (b % 8) * (n / 8) + b / 8 so that each XCD (with its own L2) works
 // on one contiguous run of tiles, whose halo rows it then shares in its L2.

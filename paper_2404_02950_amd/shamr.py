@@ -308,7 +308,13 @@ class Hierarchy:
         return list(out)
 
     def set_tuning(self, kind: int = 8, nontemporal: int = 1, tile_z: int = 0, fuse: int = 4,
-                   fused_shape: int = 0, fused_tile_z: int = 256, fused_variant: int = 0):
+                   fused_shape: int | None = None, fused_tile_z: int = 512, fused_variant: int | None = None):
+        """Launch shape (see sh_set_tuning); the fused shape and variant default to the
+        library's choice for the hierarchy's precision."""
+        if fused_shape is None:
+            fused_shape = 2 if self.params.prec == SH_F32 else 0
+        if fused_variant is None:
+            fused_variant = 3 if self.params.prec == SH_F32 else 0
         _check(self.lib.sh_set_tuning(self.h, kind, nontemporal, tile_z, fuse, fused_shape, fused_tile_z,
                                       fused_variant))
 

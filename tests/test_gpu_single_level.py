@@ -198,7 +198,8 @@ def test_stage_kernel_launch_shapes_bitwise(kind, nt, zc):
 @pytest.mark.parametrize("variant", [0, 1, 2, 3])
 @pytest.mark.parametrize("shape,fzc,cuts", [(0, 64, None), (0, 16, [[32], [32], [24]]), (0, 7, [[32], [8, 40], None]),
                                           (1, 64, None), (1, 13, [None, [16], [40]]), (2, 256, None),
-                                          (2, 9, [[32], [16], [24]])])
+                                          (2, 9, [[32], [16], [24]]), (3, 64, None),
+                                          (3, 11, [[16], [8, 40], [24]])])
 def test_fused_four_stage_step_bitwise(shape, fzc, cuts, variant):
     # the fused step (all four stages in one kernel, overlapped tiles, z pipeline) must
     # give the oracle's bits: single and multi-box level 0, ragged z chunks
