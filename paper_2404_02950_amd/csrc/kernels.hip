@@ -37,9 +37,9 @@ __device__ __forceinline__ StagePtrs stage_ptrs(const BoxDev& B, long long k) {
   constexpr int in_role = (S == 0) ? ROLE_UN : (S == 2 ? ROLE_B : ROLE_A);
   constexpr int out_role = (S == 0 || S == 2) ? ROLE_A : ROLE_B;
   StagePtrs p;
-  p.X = B.slot[role_slot(in_role, k)];
-  p.Un = B.slot[role_slot(ROLE_UN, k)];
-  p.Y = B.slot[role_slot(out_role, k)];
+  p.X = slot_base(B, role_slot(in_role, k));
+  p.Un = slot_base(B, role_slot(ROLE_UN, k));
+  p.Y = slot_base(B, role_slot(out_role, k));
   p.acc = B.acc;
   return p;
 }
@@ -237,7 +237,7 @@ __global__ __launch_bounds__(SH_BLOCK) void k_rhs(const Tile* __restrict__ tiles
   const BoxDev B = boxes[tl.box];
   const LevelScal L = *B.ls;
   const StageScal sc = stage_scalars(L, 0);
-  const T* __restrict__ X = (const T*)B.slot[role_slot(ROLE_UN, L.k)];
+  const T* __restrict__ X = (const T*)slot_base(B, role_slot(ROLE_UN, L.k));
   const int tx = lane & ((1 << tl.txs) - 1), ty = lane >> tl.txs;
   const int x = (tl.xy & 0xffff) + tx, y = (tl.xy >> 16) + ty;
   if (x >= B.nx || y >= B.ny) return;
@@ -449,7 +449,7 @@ __global__ __launch_bounds__(SH_BLOCK) void k_tag(const Tile* __restrict__ tiles
     return;
   }
   const BoxDev B = boxes[tl.box];
-  const T* __restrict__ U = (const T*)B.slot[role_slot(ROLE_UN, B.ls->k)];
+  const T* __restrict__ U = (const T*)slot_base(B, role_slot(ROLE_UN, B.ls->k));
   const int tx = lane & ((1 << tl.txs) - 1), ty = lane >> tl.txs;
   int x = (tl.xy & 0xffff) + tx, y = (tl.xy >> 16) + ty;
   const bool active = (x < B.nx) && (y < B.ny);
@@ -593,7 +593,7 @@ __global__ __launch_bounds__(SH_BLOCK) void k_energy(const Tile* __restrict__ ti
     const BoxDev B = boxes[tl.box];
     const LevelScal L = *B.ls;
     const double cp = L.lam * ipow(level_time(L), L.beta);
-    const T* __restrict__ U = (const T*)B.slot[role_slot(ROLE_UN, L.k)];
+    const T* __restrict__ U = (const T*)slot_base(B, role_slot(ROLE_UN, L.k));
     const int tx = lane & ((1 << tl.txs) - 1), ty = lane >> tl.txs;
     const int x = (tl.xy & 0xffff) + tx, y = (tl.xy >> 16) + ty;
     if (x < B.nx && y < B.ny) {
@@ -705,7 +705,7 @@ __global__ __launch_bounds__(SH_BLOCK) void k_xfer(const BoxDev* __restrict__ bo
   const int i = (int)(r % ex) - g;
   const int j = (int)((r / ex) % ey) - g;
   const int k = (int)(r / ((long long)ex * ey)) - g;
-  T* S = (T*)B.slot[role_slot(role, B.ls->k)];
+  T* S = (T*)slot_base(B, role_slot(role, B.ls->k));
   const long long e = comp * B.cs + elem<T>(B, i, j, k);
   if (TO_BOX) S[e] = (T)stage[gid];
   else stage[gid] = (double)S[e];

@@ -115,8 +115,8 @@ __global__ __launch_bounds__((FusedShape<T, TX, TY>::NBLK)) void k_fused_rk4(con
   StageScal sc[FD];
 #pragma unroll
   for (int j = 0; j < FD; ++j) sc[j] = uniform(stage_scalars(L, j));
-  const T* __restrict__ X = (const T*)B.slot[role_slot(ROLE_UN, L.k)];
-  T* __restrict__ Y = (T*)B.slot[role_slot(ROLE_B, L.k)];
+  const T* __restrict__ X = (const T*)slot_base(B, role_slot(ROLE_UN, L.k));
+  T* __restrict__ Y = (T*)slot_base(B, role_slot(ROLE_B, L.k));
 
   const int tid = threadIdx.x;
   const int lane = tid & (SH_WAVE - 1);
@@ -158,7 +158,7 @@ __global__ __launch_bounds__((FusedShape<T, TX, TY>::NBLK)) void k_fused_rk4(con
     w0[0][c] = col[c * cs + eat(ifirst - 1)];
     w0[1][c] = col[c * cs + eat(ifirst)];
     w0[2][c] = col[c * cs + eat(ifirst + 1)];
-    q0c[c] = col[(2 + c) * cs + eat(ifirst)];
+    q0c[c] = (r <= FG) ? col[(2 + c) * cs + eat(ifirst)] : (T)0;
   }
   // later stages: input windows and their Pi at planes (p, p+1); U_n at planes i-1, i-2
   // (psi of i-1 is the window bottom) for the updates of stages 1 and 2
@@ -189,11 +189,13 @@ __global__ __launch_bounds__((FusedShape<T, TX, TY>::NBLK)) void k_fused_rk4(con
     // the U_n planes that enter the stage-0 window at the end of this iteration: issued
     // first, so their latency is covered by this iteration's stages (a value loaded in one
     // iteration and carried into the next would be waited for at the loop's back edge)
-    T lpsi[2], lpi[2];
+    // (Pi only where stage 0 is computed: the outer loader ring supplies psi alone)
+    T lpsi[2], lpi[2] = {(T)0, (T)0};
 #pragma unroll
-    for (int c = 0; c < 2; ++c) {
-      lpsi[c] = col[c * cs + eat(i + 2)];
-      lpi[c] = col[(2 + c) * cs + eat(i + 1)];
+    for (int c = 0; c < 2; ++c) lpsi[c] = col[c * cs + eat(i + 2)];
+    if (r <= FG) {
+#pragma unroll
+      for (int c = 0; c < 2; ++c) lpi[c] = col[(2 + c) * cs + eat(i + 1)];
     }
     // publish every stage's input plane: stage 0 = U_n psi at i, stage j = its window top
 #pragma unroll
@@ -276,17 +278,20 @@ __global__ __launch_bounds__((FusedShape<T, TX, TY>::NBLK)) void k_fused_rk4(con
       constexpr int AST = ACCL ? TY * TX : 1;  // component stride of sacc
       double* ac = ACCL ? &sacc[(i - j) & 3][0][ay][ax] : &racc[j][0];
       const int ast = ACCL ? AST : 1;
+      // the LDS accumulator exists for the footprint's columns only; the register one is
+      // updated on every computing column (values off the footprint are never stored)
+      const bool upd = ACCL ? own : true;
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         if (j == 0) {
           const double u = (double)xin[c];
-          if (own) ac[c * ast] = u + sc[0].h6 * k4[c];
+          if (upd) ac[c * ast] = u + sc[0].h6 * k4[c];
           out[c] = (T)(u + sc[0].h2 * k4[c]);
         } else if (j == 1) {
-          if (own) ac[c * ast] = ac[c * ast] + sc[1].h3 * k4[c];
+          if (upd) ac[c * ast] = ac[c * ast] + sc[1].h3 * k4[c];
           out[c] = (T)((double)un[c] + sc[1].h2 * k4[c]);
         } else if (j == 2) {
-          if (own) ac[c * ast] = ac[c * ast] + sc[2].h3 * k4[c];
+          if (upd) ac[c * ast] = ac[c * ast] + sc[2].h3 * k4[c];
           out[c] = (T)((double)un[c] + sc[2].h1 * k4[c]);
         } else {
           out[c] = (T)(ac[c * ast] + sc[3].h6 * k4[c]);
@@ -337,14 +342,16 @@ static void fused_launch_shape(const Tile* tiles, int ntiles, const BoxDev* boxe
 
 // variant: 0 = row-major threads, x neighbours through LDS, accumulator in registers;
 // 1 = row-major, x neighbours by lane shifts, registers; 2 = row-major, lane shifts,
-// accumulator in LDS; 3 = ring-ordered threads, LDS neighbours, accumulator in LDS.
+// accumulator in LDS; 3 = ring-ordered threads, LDS neighbours, accumulator in LDS;
+// 4 = ring-ordered threads, LDS neighbours, accumulator in registers.
 template <typename T, bool NT, int TX, int TY>
 static void fused_launch_variant(int variant, const Tile* tiles, int ntiles, const BoxDev* boxes, hipStream_t st) {
   switch (variant) {
     case 0: fused_launch_shape<T, NT, TX, TY, 0, false, false>(tiles, ntiles, boxes, st); break;
     case 1: fused_launch_shape<T, NT, TX, TY, 0, true, false>(tiles, ntiles, boxes, st); break;
     case 2: fused_launch_shape<T, NT, TX, TY, 0, true, true>(tiles, ntiles, boxes, st); break;
-    default: fused_launch_shape<T, NT, TX, TY, 1, false, true>(tiles, ntiles, boxes, st); break;
+    case 3: fused_launch_shape<T, NT, TX, TY, 1, false, true>(tiles, ntiles, boxes, st); break;
+    default: fused_launch_shape<T, NT, TX, TY, 1, false, false>(tiles, ntiles, boxes, st); break;
   }
 }
 

@@ -185,17 +185,16 @@ struct Tuning {
   int fshape = 0;
   int fzc = 512;
   int fvar = 0;  // fused kernel variant (thread order / neighbour exchange / accumulator)
+  int fgrp = 1;  // fused tile order: 1 = groups of 32 tiles on square-ish patches, 0 = rows
 };
 
-// Measured best fused launch per storage type on MI355X at 512^3: FP64 32 x 8 footprint,
-// row-major threads, registers (166 VGPRs, one 10-wave workgroup per CU); FP32 32 x 16,
-// ring-ordered threads, accumulator in LDS (15 waves per workgroup).
+// Measured best fused launch per storage type on MI355X at 512^3: ring-ordered threads,
+// x neighbours through LDS, accumulator in registers; FP64 on the 32 x 8 footprint (one
+// 10-wave workgroup per CU), FP32 on 32 x 16 (15 waves).
 static Tuning default_tuning(int prec) {
   Tuning t;
-  if (prec == SH_F32) {
-    t.fshape = 2;
-    t.fvar = 3;
-  }
+  t.fvar = 4;
+  if (prec == SH_F32) t.fshape = 2;
   return t;
 }
 
@@ -218,7 +217,8 @@ static void tuning_from_env(Tuning& t) {
       if (k == "fuse" && (v == 0 || v == 4)) t.fuse = v;
       if (k == "fshape" && v >= 0 && v <= 3) t.fshape = v;
       if (k == "fzc" && v >= 1 && v <= 1024) t.fzc = v;
-      if (k == "fvar" && v >= 0 && v <= 3) t.fvar = v;
+      if (k == "fvar" && v >= 0 && v <= 4) t.fvar = v;
+      if (k == "fgrp" && (v == 0 || v == 1)) t.fgrp = v;
     }
     pos = end + 1;
   }
@@ -263,6 +263,11 @@ static void make_stage_tiles(const std::vector<IBox>& boxes, const Tuning& tu, l
 }
 
 // Tiles of the fused step; empty if some box is not a multiple of the footprint.
+// Fused tiles in launch order.  Blocks go round-robin to the 8 XCDs and the kernel maps
+// each XCD to one contiguous run of the tile list, whose first 32 entries (one per CU)
+// then run together.  Listing the tiles of a box by groups of 32 that cover a square-ish
+// patch (not a strip of whole rows) lets those concurrent tiles share most of their
+// halo columns in the XCD's L2.
 static void make_fused_tiles(const std::vector<IBox>& boxes, const Tuning& tu, int ng, std::vector<Tile>& ft) {
   ft.clear();
   if (tu.fuse != 4 || ng < 4) return;
@@ -270,19 +275,30 @@ static void make_fused_tiles(const std::vector<IBox>& boxes, const Tuning& tu, i
   sh_fused_footprint(tu.fshape, &TX, &TY);
   for (const IBox& b : boxes)
     if (b.size(0) % TX || b.size(1) % TY) return;
+  // group of GX x GY tiles with GX * GY = 32 and GX * TX close to GY * TY
+  int GX = 1;
+  while (GX < 32 && (long long)(2 * GX) * TX <= (long long)(32 / (2 * GX)) * TY * 2) GX *= 2;
+  int GY = 32 / GX;
+  if (!tu.fgrp) {
+    GX = 1 << 30;
+    GY = 1;
+  }
   for (size_t bi = 0; bi < boxes.size(); ++bi) {
     const IBox& b = boxes[bi];
     const int nx = b.size(0), ny = b.size(1), nz = b.size(2);
+    const int ntx = nx / TX, nty = ny / TY;
     for (int z0 = 0; z0 < nz; z0 += tu.fzc)
-      for (int y0 = 0; y0 < ny; y0 += TY)
-        for (int x0 = 0; x0 < nx; x0 += TX) {
-          Tile t;
-          t.box = (int)bi;
-          t.xy = x0 | (y0 << 16);
-          t.zz = z0 | (std::min(tu.fzc, nz - z0) << 16);
-          t.txs = tu.fshape;
-          ft.push_back(t);
-        }
+      for (int gy = 0; gy < nty; gy += GY)
+        for (int gx = 0; gx < ntx; gx += GX)
+          for (int ty = gy; ty < std::min(gy + GY, nty); ++ty)
+            for (int tx = gx; tx < std::min(gx + GX, ntx); ++tx) {
+              Tile t;
+              t.box = (int)bi;
+              t.xy = (tx * TX) | ((ty * TY) << 16);
+              t.zz = z0 | (std::min(tu.fzc, nz - z0) << 16);
+              t.txs = tu.fshape;
+              ft.push_back(t);
+            }
   }
 }
 
@@ -1150,7 +1166,7 @@ sh_status sh_set_tuning(sh_hierarchy h, int32_t kind, int32_t nontemporal, int32
   if (!h) return fail(SH_EINVAL, "null handle");
   if ((kind != 0 && kind != 4 && kind != 8) || (nontemporal != 0 && nontemporal != 1) || tile_z < 0 ||
       tile_z > 1024 || (fuse != 0 && fuse != 4) || (fused_shape < 0 || fused_shape > 3) || fused_tile_z < 1 ||
-      fused_tile_z > 1024 || fused_variant < 0 || fused_variant > 3)
+      fused_tile_z > 1024 || fused_variant < 0 || fused_variant > 4)
     return fail(SH_EINVAL, "bad tuning");
   HIPCHK(hipStreamSynchronize(h->st));
   h->tune.kind = kind;

@@ -63,6 +63,12 @@ __device__ __forceinline__ StageScal uniform(const StageScal& s) {
   return r;
 }
 
+// Base of a box's block in state slot `slot` (0..2).  Selecting with constant indices
+// keeps the box record in registers (a computed index into it would go through memory).
+__device__ __forceinline__ void* slot_base(const BoxDev& B, int slot) {
+  return slot == 0 ? B.slot[0] : (slot == 1 ? B.slot[1] : B.slot[2]);
+}
+
 // Blocks are dispatched round-robin over the 8 XCDs of MI355X.  Map hardware block b
 // to logical block (b % 8) * (n / 8) + b / 8 so that each XCD (with its own L2) works
 // on one contiguous run of tiles, whose halo rows it then shares in its L2.

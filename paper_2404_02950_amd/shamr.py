@@ -142,6 +142,7 @@ class Hierarchy:
         self.h = h
         self.arenas = {}
         self.boxes = {}
+        self._tag_cap = {}
 
     # -- lifetime ---------------------------------------------------------------------
     def close(self):
@@ -241,12 +242,20 @@ class Hierarchy:
         """Tagged cells of a level: (count, (n, 3) int32 global x, y, z or None)."""
         n = c_int64()
         mptr = c_void_p(mask_dev.data_ptr()) if mask_dev is not None else None
-        _check(self.lib.sh_tag_cells(self.h, lev, mptr, None, 0, ctypes.byref(n)))
-        if not want_idx or n.value == 0:
-            return n.value, (np.zeros((0, 3), np.int32) if want_idx else None)
-        idx = np.empty((n.value, 3), np.int32)
-        _check(self.lib.sh_tag_cells(self.h, lev, mptr, idx.ctypes.data_as(c_void_p), n.value, ctypes.byref(n)))
-        return n.value, idx
+        if not want_idx:
+            _check(self.lib.sh_tag_cells(self.h, lev, mptr, None, 0, ctypes.byref(n)))
+            return n.value, None
+        # one call when the list fits the capacity remembered from this level's last
+        # tagging (the count is always exact), a second one only when it grew past it
+        cap = self._tag_cap.get(lev, 1 << 16)
+        idx = np.empty((cap, 3), np.int32)
+        _check(self.lib.sh_tag_cells(self.h, lev, mptr, idx.ctypes.data_as(c_void_p), cap, ctypes.byref(n)))
+        if n.value > cap:
+            cap = n.value + n.value // 4
+            idx = np.empty((cap, 3), np.int32)
+            _check(self.lib.sh_tag_cells(self.h, lev, mptr, idx.ctypes.data_as(c_void_p), cap, ctypes.byref(n)))
+        self._tag_cap[lev] = max(cap, 1 << 16)
+        return n.value, idx[:n.value]
 
     def tag_mask_dense(self, lev: int) -> np.ndarray:
         """Tag mask of a level as a dense uint8 (M, M, M) array (0 outside the level)."""
@@ -314,7 +323,7 @@ class Hierarchy:
         if fused_shape is None:
             fused_shape = 2 if self.params.prec == SH_F32 else 0
         if fused_variant is None:
-            fused_variant = 3 if self.params.prec == SH_F32 else 0
+            fused_variant = 4
         _check(self.lib.sh_set_tuning(self.h, kind, nontemporal, tile_z, fuse, fused_shape, fused_tile_z,
                                       fused_variant))
 
