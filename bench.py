@@ -172,7 +172,7 @@ def main():
         "nonfinite_cells_at_end": bad,
     }
     if not args.no_cpu_baseline and args.prec == "f64":
-        log("cpu baseline (oracle, one stage)")
+        log("cpu baseline (oracle, one full step)")
         out["cpu_baseline"] = cpu_baseline(U0, n)
     else:
         out["cpu_baseline"] = None
