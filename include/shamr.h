@@ -199,14 +199,15 @@ sh_status sh_debug_stage_scalars(sh_hierarchy h, int32_t lev, int32_t s, double*
    coarse/fine boundary) takes each step in one kernel computing all four RK stages
    (temporal blocking; needs every level-0 box to be a multiple of the fused footprint,
    else per-stage), 0 = per-stage kernels; fused_shape 0 = 32 x 8 footprint, 1 = 64 x 4,
-   2 = 32 x 16, 3 = 16 x 8; fused_tile_z = planes per fused tile; fused_variant 0-4 =
+   2 = 32 x 16, 3 = 16 x 8; fused_tile_z = planes per fused tile; fused_variant 0-6 =
    thread order / x-neighbour exchange / accumulator placement of the fused kernel
    (0: row-major, LDS, registers; 1: row-major, lane shifts, registers; 2: row-major,
-   lane shifts, LDS; 3: ring order, LDS, LDS; 4: ring order, LDS, registers).  Applies to every level.  Defaults at
-   creation: kind 8, nontemporal 1, tile_z 0, fuse 4, fused_tile_z 512, fused_variant 4,
-   and fused_shape 0 for SH_F64, 2 for SH_F32; the environment variable SHAMR_TUNE (e.g.
-   "kind=8,nt=1,zc=0,fuse=4,fshape=0,fzc=512,fvar=4,fgrp=1") overrides them (fgrp 1 =
-   fused tiles launched in groups of 32 covering square-ish patches, 0 = in rows). */
+   lane shifts, LDS; 3: ring order, LDS, LDS; 4: ring order, LDS, registers; 5: as 4,
+   with U_n planes loaded two iterations ahead; 6: as 5, accumulator in LDS).  Applies to every level.  Defaults at
+   creation: kind 8, nontemporal 1, tile_z 0, fuse 4, fused_tile_z 512, and fused_shape /
+   fused_variant 0 / 5 for SH_F64, 2 / 6 for SH_F32; the environment variable SHAMR_TUNE
+   (e.g. "kind=8,nt=1,zc=0,fuse=4,fshape=0,fzc=512,fvar=5,fgrp=1") overrides them (fgrp
+   1 = fused tiles launched in groups of 32 covering square-ish patches, 0 = in rows). */
 sh_status sh_set_tuning(sh_hierarchy h, int32_t kind, int32_t nontemporal, int32_t tile_z, int32_t fuse,
                         int32_t fused_shape, int32_t fused_tile_z, int32_t fused_variant);
 

@@ -88,7 +88,11 @@ constexpr int DPP_WAVE_SHL1 = 0x130;  // lane l takes lane l+1
 // ORDER 0: threads row-major over the (TX+8) x (TY+8) columns; 1: sorted by ring.
 // XDPP: x neighbours by lane shifts (row-major only: the computing columns' x neighbours
 // are the adjacent lanes; the two wave-edge lanes read LDS).  ACCL: accumulator in LDS.
-template <typename T, bool NT, int TX, int TY, int ORDER, bool XDPP, bool ACCL>
+// PF2: U_n planes are loaded two iterations before they enter the stage-0 window, into
+// two buffers that alternate between iterations (else in the iteration that uses them).
+// ZL: stages 1..3 read their z-1 neighbour from the previous iteration's LDS planes
+// instead of keeping it in registers (needs the double-buffered planes).
+template <typename T, bool NT, int TX, int TY, int ORDER, bool XDPP, bool ACCL, bool PF2, bool ZL>
 __global__ __launch_bounds__((FusedShape<T, TX, TY>::NBLK)) void k_fused_rk4(const Tile* __restrict__ tiles,
                                                                            int ntiles,
                                                                            const BoxDev* __restrict__ boxes) {
@@ -183,20 +187,27 @@ __global__ __launch_bounds__((FusedShape<T, TX, TY>::NBLK)) void k_fused_rk4(con
 
   // one iteration: stage j handles plane i - j.  FILL marks the first 2*FG iterations,
   // in which the later stages are still waiting for their input windows to fill.
-  auto iteration = [&](const int i, auto fill_tag) {
+  // U_n planes on their way into the stage-0 window: [psi / Pi][component].  Loads are
+  // issued at the top of an iteration; without PF2 they enter the window at its end, with
+  // PF2 at the end of the next one.  A value still in flight is never copied between
+  // registers (that would wait for it at the loop's back edge), so with PF2 the two
+  // buffers swap roles from one iteration to the next instead.
+  T pfa[2][2], pfb[2][2];
+  auto load_planes = [&](const int zpsi, T(&dst)[2][2]) {
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      dst[0][c] = col[c * cs + eat(zpsi)];
+      // Pi only where stage 0 is computed: the outer loader ring supplies psi alone
+      dst[1][c] = (r <= FG) ? col[(2 + c) * cs + eat(zpsi - 1)] : (T)0;
+    }
+  };
+  auto iteration = [&](const int i, auto fill_tag, T(&ldb)[2][2], T(&useb)[2][2]) {
     constexpr bool FILL = decltype(fill_tag)::value;
     T(*sm)[2][H][W] = sm2[NBUF == 2 ? (i & 1) : 0];
-    // the U_n planes that enter the stage-0 window at the end of this iteration: issued
-    // first, so their latency is covered by this iteration's stages (a value loaded in one
-    // iteration and carried into the next would be waited for at the loop's back edge)
-    // (Pi only where stage 0 is computed: the outer loader ring supplies psi alone)
-    T lpsi[2], lpi[2] = {(T)0, (T)0};
-#pragma unroll
-    for (int c = 0; c < 2; ++c) lpsi[c] = col[c * cs + eat(i + 2)];
-    if (r <= FG) {
-#pragma unroll
-      for (int c = 0; c < 2; ++c) lpi[c] = col[(2 + c) * cs + eat(i + 1)];
-    }
+    // with two buffers the other one still holds the planes published one iteration ago
+    constexpr bool ZLDS = ZL && NBUF == 2;
+    T(*smp)[2][H][W] = sm2[NBUF == 2 ? ((i + 1) & 1) : 0];
+    load_planes(PF2 ? i + 3 : i + 2, ldb);
     // publish every stage's input plane: stage 0 = U_n psi at i, stage j = its window top
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
@@ -217,7 +228,7 @@ __global__ __launch_bounds__((FusedShape<T, TX, TY>::NBLK)) void k_fused_rk4(con
         // push stage j-1's output plane (p+1) into stage j's window
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
-          wj[j][0][c] = wj[j][1][c];
+          if (!ZLDS) wj[j][0][c] = wj[j][1][c];
           wj[j][1][c] = wj[j][2][c];
           wj[j][2][c] = out[c];
           qj[j][0][c] = qj[j][1][c];
@@ -255,7 +266,8 @@ __global__ __launch_bounds__((FusedShape<T, TX, TY>::NBLK)) void k_fused_rk4(con
           xp = sm[j][c][cy][cx + 1];
         }
         const T ym = sm[j][c][cym][cx], yp = sm[j][c][cyp][cx];
-        lap[c] = ((((xm + xp) + (ym + yp)) + (w[0][c] + w[2][c])) - (T)6.0 * w[1][c]) * idx2;
+        const T zm = (ZLDS && j > 0) ? smp[j][c][cy][cx] : w[0][c];
+        lap[c] = ((((xm + xp) + (ym + yp)) + (zm + w[2][c])) - (T)6.0 * w[1][c]) * idx2;
       }
       const T p0 = w[1][0], p1 = w[1][1];
       const T r2 = p0 * p0 + p1 * p1;
@@ -323,27 +335,44 @@ __global__ __launch_bounds__((FusedShape<T, TX, TY>::NBLK)) void k_fused_rk4(con
       u2[2 + c] = q0p[c];
       w0[0][c] = w0[1][c];
       w0[1][c] = w0[2][c];
-      w0[2][c] = lpsi[c];
+      w0[2][c] = useb[0][c];
       q0p[c] = q0c[c];
-      q0c[c] = lpi[c];
+      q0c[c] = useb[1][c];
     }
   };
+  // every tile has zc + 2 FG >= 2 FG + 1 iterations: the filling ones (an even number)
+  // always run in full
   int i = ifirst;
-  for (; i <= ilast && i < ifirst + 2 * FG; ++i) iteration(i, std::true_type{});
-  for (; i <= ilast; ++i) iteration(i, std::false_type{});
+  if constexpr (PF2) {
+    load_planes(ifirst + 2, pfb);
+    for (; i < ifirst + 2 * FG; i += 2) {
+      iteration(i, std::true_type{}, pfa, pfb);
+      iteration(i + 1, std::true_type{}, pfb, pfa);
+    }
+    for (; i + 1 <= ilast; i += 2) {
+      iteration(i, std::false_type{}, pfa, pfb);
+      iteration(i + 1, std::false_type{}, pfb, pfa);
+    }
+    if (i <= ilast) iteration(i, std::false_type{}, pfa, pfb);
+  } else {
+    for (; i < ifirst + 2 * FG; ++i) iteration(i, std::true_type{}, pfa, pfa);
+    for (; i <= ilast; ++i) iteration(i, std::false_type{}, pfa, pfa);
+  }
 }
 
-template <typename T, bool NT, int TX, int TY, int ORDER, bool XDPP, bool ACCL>
+template <typename T, bool NT, int TX, int TY, int ORDER, bool XDPP, bool ACCL, bool PF2 = false, bool ZL = false>
 static void fused_launch_shape(const Tile* tiles, int ntiles, const BoxDev* boxes, hipStream_t st) {
   using Sh = FusedShape<T, TX, TY>;
-  hipLaunchKernelGGL((k_fused_rk4<T, NT, TX, TY, ORDER, XDPP, ACCL>), dim3(ntiles), dim3(Sh::NBLK), 0, st, tiles,
+  hipLaunchKernelGGL((k_fused_rk4<T, NT, TX, TY, ORDER, XDPP, ACCL, PF2, ZL>), dim3(ntiles), dim3(Sh::NBLK), 0, st, tiles,
                      ntiles, boxes);
 }
 
 // variant: 0 = row-major threads, x neighbours through LDS, accumulator in registers;
 // 1 = row-major, x neighbours by lane shifts, registers; 2 = row-major, lane shifts,
 // accumulator in LDS; 3 = ring-ordered threads, LDS neighbours, accumulator in LDS;
-// 4 = ring-ordered threads, LDS neighbours, accumulator in registers.
+// 4 = ring-ordered threads, LDS neighbours, accumulator in registers; 5 = variant 4 with
+// the two-iteration U_n prefetch, z-1 neighbours of stages 1..3 from LDS; 6 = variant 5
+// with the accumulator in LDS.
 template <typename T, bool NT, int TX, int TY>
 static void fused_launch_variant(int variant, const Tile* tiles, int ntiles, const BoxDev* boxes, hipStream_t st) {
   switch (variant) {
@@ -351,7 +380,9 @@ static void fused_launch_variant(int variant, const Tile* tiles, int ntiles, con
     case 1: fused_launch_shape<T, NT, TX, TY, 0, true, false>(tiles, ntiles, boxes, st); break;
     case 2: fused_launch_shape<T, NT, TX, TY, 0, true, true>(tiles, ntiles, boxes, st); break;
     case 3: fused_launch_shape<T, NT, TX, TY, 1, false, true>(tiles, ntiles, boxes, st); break;
-    default: fused_launch_shape<T, NT, TX, TY, 1, false, false>(tiles, ntiles, boxes, st); break;
+    case 4: fused_launch_shape<T, NT, TX, TY, 1, false, false>(tiles, ntiles, boxes, st); break;
+    case 5: fused_launch_shape<T, NT, TX, TY, 1, false, false, true, true>(tiles, ntiles, boxes, st); break;
+    default: fused_launch_shape<T, NT, TX, TY, 1, false, true, true, true>(tiles, ntiles, boxes, st); break;
   }
 }
 

@@ -189,12 +189,17 @@ struct Tuning {
 };
 
 // Measured best fused launch per storage type on MI355X at 512^3: ring-ordered threads,
-// x neighbours through LDS, accumulator in registers; FP64 on the 32 x 8 footprint (one
-// 10-wave workgroup per CU), FP32 on 32 x 16 (15 waves).
+// x neighbours through LDS, U_n loaded two iterations ahead, z-1 neighbours of the later
+// stages from LDS; FP64 on the 32 x 8 footprint with the accumulator in registers (one
+// 10-wave workgroup per CU), FP32 on 32 x 16 with the accumulator in LDS (15 waves,
+// within 128 registers).
 static Tuning default_tuning(int prec) {
   Tuning t;
-  t.fvar = 4;
-  if (prec == SH_F32) t.fshape = 2;
+  t.fvar = 5;
+  if (prec == SH_F32) {
+    t.fshape = 2;
+    t.fvar = 6;
+  }
   return t;
 }
 
@@ -217,7 +222,7 @@ static void tuning_from_env(Tuning& t) {
       if (k == "fuse" && (v == 0 || v == 4)) t.fuse = v;
       if (k == "fshape" && v >= 0 && v <= 3) t.fshape = v;
       if (k == "fzc" && v >= 1 && v <= 1024) t.fzc = v;
-      if (k == "fvar" && v >= 0 && v <= 4) t.fvar = v;
+      if (k == "fvar" && v >= 0 && v <= 6) t.fvar = v;
       if (k == "fgrp" && (v == 0 || v == 1)) t.fgrp = v;
     }
     pos = end + 1;
@@ -1166,7 +1171,7 @@ sh_status sh_set_tuning(sh_hierarchy h, int32_t kind, int32_t nontemporal, int32
   if (!h) return fail(SH_EINVAL, "null handle");
   if ((kind != 0 && kind != 4 && kind != 8) || (nontemporal != 0 && nontemporal != 1) || tile_z < 0 ||
       tile_z > 1024 || (fuse != 0 && fuse != 4) || (fused_shape < 0 || fused_shape > 3) || fused_tile_z < 1 ||
-      fused_tile_z > 1024 || fused_variant < 0 || fused_variant > 4)
+      fused_tile_z > 1024 || fused_variant < 0 || fused_variant > 6)
     return fail(SH_EINVAL, "bad tuning");
   HIPCHK(hipStreamSynchronize(h->st));
   h->tune.kind = kind;

@@ -323,7 +323,7 @@ class Hierarchy:
         if fused_shape is None:
             fused_shape = 2 if self.params.prec == SH_F32 else 0
         if fused_variant is None:
-            fused_variant = 4
+            fused_variant = 6 if self.params.prec == SH_F32 else 5
         _check(self.lib.sh_set_tuning(self.h, kind, nontemporal, tile_z, fuse, fused_shape, fused_tile_z,
                                       fused_variant))
 
