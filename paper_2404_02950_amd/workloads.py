@@ -59,6 +59,7 @@ def run_amr(U0: np.ndarray, max_level: int, coarse_steps: int, prec: int = shamr
     t0 = time.perf_counter()
     for step in range(coarse_steps):
         if step > 0 and step % regrid_every == 0:
+            h.sync()  # the queued level steps are not regrid time
             tr = time.perf_counter()
             nlev = h.num_levels()
             driver.regrid(h, max_level, efficiency=efficiency, max_level_bytes=max_level_bytes, log=log,
