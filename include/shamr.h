@@ -50,6 +50,7 @@ extern "C" {
 
 typedef struct sh_hierarchy_s* sh_hierarchy;
 typedef struct sh_batch_s* sh_batch;
+typedef struct sh_graph_s* sh_graph;  /* a recorded sequence of level steps (HIP graph) */
 
 typedef enum {
   SH_OK = 0,
@@ -228,10 +229,31 @@ sh_status sh_profile_read(sh_hierarchy h, double* ms, int64_t* counts);
    member's result is bit-identical to stepping it alone (kernels are gather-only per
    box).  Members must not be re-laid out or destroyed while the batch exists; the batch
    borrows them.  Errors: SH_EINVAL (a member with more than one level, another
-   precision or stream). */
+   precision or stream), SH_ESTATE from sh_batch_advance if a member's layout changed
+   since the batch was built. */
 sh_status sh_batch_create(int32_t njobs, const sh_hierarchy* jobs, sh_batch* out);
 sh_status sh_batch_advance(sh_batch b);
 sh_status sh_batch_destroy(sh_batch b);
+
+/* Recorded level steps (HIP graphs).  The Berger-Oliger order of Sec. II.A (Fig. 2) is a
+   fixed sequence of launches for a fixed layout, so a coarse step (or several) can be
+   recorded once and replayed with one launch; the step counters and level times live in
+   device memory, so every replay advances the simulation.
+   sh_capture_begin(h) starts recording on h's stream: until sh_capture_end, the calls
+   sh_advance_level, sh_average_down and sh_fill_ghosts are recorded, not run; every
+   call that synchronises, allocates, uploads or reads back (layout, state I/O, tagging,
+   energy, sync, tuning, profiling, tracing) fails with SH_ESTATE.  Profiling and tracing
+   must be off.  sh_capture_end(h, &g) stops recording and returns the graph; the host
+   step counters are as before the capture.  sh_batch_capture(b, nsteps, &g) records
+   nsteps batch steps.  sh_graph_launch(g) replays on the recording stream (asynchronous)
+   and advances the host step counters by what was recorded; SH_ESTATE if a recorded
+   hierarchy's layout changed since.  sh_graph_destroy releases it (the caller owns g;
+   destroy graphs before the hierarchies they record). */
+sh_status sh_capture_begin(sh_hierarchy h);
+sh_status sh_capture_end(sh_hierarchy h, sh_graph* out);
+sh_status sh_batch_capture(sh_batch b, int32_t nsteps, sh_graph* out);
+sh_status sh_graph_launch(sh_graph g);
+sh_status sh_graph_destroy(sh_graph g);
 
 /* Orchestration trace (diagnostic).  sh_trace(h, 1) clears and starts recording every
    operation that sh_advance_level and sh_average_down issue, as 4 int32 each

@@ -366,6 +366,11 @@ struct sh_hierarchy_s {
   sh_params p;
   Tuning tune;
   hipStream_t st = nullptr;
+  // graph capture: while capturing, level steps are recorded, not run; the host step
+  // counters are put back at the end and advanced by each replay instead
+  bool capturing = false;
+  std::vector<long long> k_at_capture;
+  long long layout_version = 0;  // bumped by every layout change (captured graphs go stale)
   LevelScal* d_ls = nullptr;  // 16 levels
   double* d_dbg = nullptr;
   std::vector<Level> lev;
@@ -656,6 +661,27 @@ static sh_status check_level(sh_hierarchy h, int l) {
   return SH_OK;
 }
 
+// Calls that synchronise, allocate, upload tables or read back results cannot be
+// recorded into a graph.
+static sh_status not_capturing(sh_hierarchy h) {
+  if (!h) return fail(SH_EINVAL, "null handle");
+  if (h->capturing) return fail(SH_ESTATE, "not allowed while a graph is being captured");
+  return SH_OK;
+}
+
+struct sh_graph_s {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipStream_t st = nullptr;
+  struct Adv {
+    sh_hierarchy h;
+    int level;
+    long long dk;
+    long long version;
+  };
+  std::vector<Adv> adv;  // host step counters a replay advances
+};
+
 // ---------------------------------------------------------------------------------
 // C-ABI
 // ---------------------------------------------------------------------------------
@@ -707,6 +733,11 @@ sh_status sh_hierarchy_create(const sh_params* p, void* hip_stream, sh_hierarchy
 
 sh_status sh_hierarchy_destroy(sh_hierarchy h) {
   if (!h) return SH_OK;
+  if (h->capturing) {
+    hipGraph_t g = nullptr;
+    (void)hipStreamEndCapture(h->st, &g);
+    if (g) (void)hipGraphDestroy(g);
+  }
   (void)hipStreamSynchronize(h->st);
   for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
   for (Level& L : h->lev) L.release();
@@ -764,6 +795,8 @@ static sh_status set_box_tables(sh_hierarchy h, int l, Level& L) {
 sh_status sh_set_level_layout(sh_hierarchy h, int32_t l, int32_t nboxes, const int32_t* boxes, void* arena,
                               size_t arena_bytes) {
   if (!h) return fail(SH_EINVAL, "null handle");
+  if (h->capturing) return not_capturing(h);
+  h->layout_version += 1;
   const sh_params& p = h->p;
   if (l < 0 || l > p.max_level || l > (int)h->lev.size()) return fail(SH_EINVAL, "bad level");
   if (nboxes == 0) {
@@ -897,7 +930,7 @@ sh_status sh_set_level_layout(sh_hierarchy h, int32_t l, int32_t nboxes, const i
 
 static sh_status xfer(sh_hierarchy h, int l, int role, double* buf, int is_device, int g, bool to_box) {
   sh_status s = check_level(h, l);
-  if (s != SH_OK) return s;
+  if (s != SH_OK || (s = not_capturing(h)) != SH_OK) return s;
   if (!buf) return fail(SH_EINVAL, "null buffer");
   if (role < 0 || role > 3) return fail(SH_EINVAL, "bad role");
   Level& L = h->lev[l];
@@ -1014,7 +1047,7 @@ sh_status sh_average_down(sh_hierarchy h, int32_t f) {
 sh_status sh_tag_cells(sh_hierarchy h, int32_t l, uint8_t* mask_dev, int32_t* idx_host, int64_t cap,
                        int64_t* ntag) {
   sh_status s = check_level(h, l);
-  if (s != SH_OK) return s;
+  if (s != SH_OK || (s = not_capturing(h)) != SH_OK) return s;
   if (cap < 0) return fail(SH_EINVAL, "negative capacity");
   Level& L = h->lev[l];
   if ((s = fill(h, l, ROLE_UN, 4)) != SH_OK) return s;
@@ -1047,6 +1080,7 @@ sh_status sh_tag_cells(sh_hierarchy h, int32_t l, uint8_t* mask_dev, int32_t* id
 
 sh_status sh_energy(sh_hierarchy h, double* e_host, int64_t* nonfinite) {
   if (!h || !e_host) return fail(SH_EINVAL, "null argument");
+  if (h->capturing) return not_capturing(h);
   if (h->lev.empty()) return fail(SH_ESTATE, "no levels");
   const int nl = (int)h->lev.size();
   for (int l = 0; l < nl; ++l) {
@@ -1079,7 +1113,7 @@ sh_status sh_energy(sh_hierarchy h, double* e_host, int64_t* nonfinite) {
 
 sh_status sh_eval_rhs(sh_hierarchy h, int32_t l, double* out_dev) {
   sh_status s = check_level(h, l);
-  if (s != SH_OK) return s;
+  if (s != SH_OK || (s = not_capturing(h)) != SH_OK) return s;
   if (!out_dev) return fail(SH_EINVAL, "null output");
   Level& L = h->lev[l];
   sh_launch_rhs(h->p.prec, L.tiles.p, L.ntiles(), L.dbox.p, L.rhs_off.p, out_dev, h->st);
@@ -1099,6 +1133,7 @@ sh_status sh_level_info(sh_hierarchy h, int32_t l, int64_t* k, double* eta, int3
 
 sh_status sh_sync(sh_hierarchy h) {
   if (!h) return fail(SH_EINVAL, "null handle");
+  if (h->capturing) return not_capturing(h);
   HIPCHK(hipStreamSynchronize(h->st));
   HIPCHK(hipGetLastError());
   return SH_OK;
@@ -1106,7 +1141,7 @@ sh_status sh_sync(sh_hierarchy h) {
 
 sh_status sh_debug_stage_scalars(sh_hierarchy h, int32_t l, int32_t s, double* out_host) {
   sh_status st = check_level(h, l);
-  if (st != SH_OK) return st;
+  if (st != SH_OK || (st = not_capturing(h)) != SH_OK) return st;
   if (s < 0 || s > 3 || !out_host) return fail(SH_EINVAL, "bad stage");
   sh_launch_debug_scalars(h->d_ls + l, s, h->d_dbg, h->st);
   LAUNCHCHK();
@@ -1169,6 +1204,7 @@ sh_status sh_cluster_tags(sh_hierarchy h, int32_t l, int64_t ntag, const int32_t
 sh_status sh_set_tuning(sh_hierarchy h, int32_t kind, int32_t nontemporal, int32_t tile_z, int32_t fuse,
                         int32_t fused_shape, int32_t fused_tile_z, int32_t fused_variant) {
   if (!h) return fail(SH_EINVAL, "null handle");
+  if (h->capturing) return not_capturing(h);
   if ((kind != 0 && kind != 4 && kind != 8) || (nontemporal != 0 && nontemporal != 1) || tile_z < 0 ||
       tile_z > 1024 || (fuse != 0 && fuse != 4) || (fused_shape < 0 || fused_shape > 3) || fused_tile_z < 1 ||
       fused_tile_z > 1024 || fused_variant < 0 || fused_variant > 6)
@@ -1194,6 +1230,7 @@ sh_status sh_set_tuning(sh_hierarchy h, int32_t kind, int32_t nontemporal, int32
 
 sh_status sh_profile(sh_hierarchy h, int32_t enable) {
   if (!h) return fail(SH_EINVAL, "null handle");
+  if (h->capturing) return not_capturing(h);
   h->prof_collect();
   h->profiling = enable != 0;
   for (int i = 0; i < 8; ++i) {
@@ -1205,6 +1242,7 @@ sh_status sh_profile(sh_hierarchy h, int32_t enable) {
 
 sh_status sh_profile_read(sh_hierarchy h, double* ms, int64_t* counts) {
   if (!h || !ms || !counts) return fail(SH_EINVAL, "null argument");
+  if (h->capturing) return not_capturing(h);
   h->prof_collect();
   for (int i = 0; i < 8; ++i) {
     ms[i] = h->prof_ms[i];
@@ -1215,6 +1253,7 @@ sh_status sh_profile_read(sh_hierarchy h, double* ms, int64_t* counts) {
 
 sh_status sh_trace(sh_hierarchy h, int32_t enable) {
   if (!h) return fail(SH_EINVAL, "null handle");
+  if (h->capturing) return not_capturing(h);
   h->tracing = enable != 0;
   h->trace.clear();
   return SH_OK;
@@ -1225,6 +1264,72 @@ int64_t sh_trace_read(sh_hierarchy h, int32_t* out, int64_t cap) {
   const int64_t n = (int64_t)h->trace.size() / 4;
   if (out) std::memcpy(out, h->trace.data(), (size_t)std::min(n, cap) * 16);
   return n;
+}
+
+sh_status sh_capture_begin(sh_hierarchy h) {
+  sh_status s = not_capturing(h);
+  if (s != SH_OK) return s;
+  if (h->profiling || h->tracing) return fail(SH_ESTATE, "switch profiling and tracing off before capturing");
+  if (!h->st) return fail(SH_EINVAL, "the legacy default stream cannot be captured: create the hierarchy on a stream");
+  if (h->lev.empty()) return fail(SH_ESTATE, "no levels");
+  for (const Level& L : h->lev)
+    if (L.stale) return fail(SH_ESTATE, "a level layout is stale");
+  HIPCHK(hipStreamBeginCapture(h->st, hipStreamCaptureModeThreadLocal));
+  h->k_at_capture.clear();
+  for (const Level& L : h->lev) h->k_at_capture.push_back(L.k);
+  h->capturing = true;
+  return SH_OK;
+}
+
+sh_status sh_capture_end(sh_hierarchy h, sh_graph* out) {
+  if (!h || !out) return fail(SH_EINVAL, "null argument");
+  *out = nullptr;
+  if (!h->capturing) return fail(SH_ESTATE, "no capture in progress");
+  h->capturing = false;
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(h->st, &g);
+  sh_graph G = new (std::nothrow) sh_graph_s;
+  // the captured steps have not run: put the host counters back
+  for (size_t l = 0; l < h->lev.size() && l < h->k_at_capture.size(); ++l) {
+    const long long dk = h->lev[l].k - h->k_at_capture[l];
+    h->lev[l].k = h->k_at_capture[l];
+    if (G && dk) G->adv.push_back({h, (int)l, dk, h->layout_version});
+  }
+  if (e != hipSuccess || !g || !G) {
+    if (g) (void)hipGraphDestroy(g);
+    delete G;
+    return fail(e != hipSuccess ? SH_EDEVICE : SH_ENOMEM, e != hipSuccess ? hipGetErrorString(e) : "capture failed");
+  }
+  G->graph = g;
+  G->st = h->st;
+  e = hipGraphInstantiate(&G->exec, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    delete G;
+    return fail(SH_EDEVICE, hipGetErrorString(e));
+  }
+  *out = G;
+  return SH_OK;
+}
+
+sh_status sh_graph_launch(sh_graph g) {
+  if (!g || !g->exec) return fail(SH_EINVAL, "null graph");
+  for (const auto& a : g->adv) {
+    if (a.h->capturing) return fail(SH_ESTATE, "not allowed while a graph is being captured");
+    if (a.h->layout_version != a.version || a.level >= (int)a.h->lev.size())
+      return fail(SH_ESTATE, "the layout changed since the graph was captured");
+  }
+  HIPCHK(hipGraphLaunch(g->exec, g->st));
+  for (const auto& a : g->adv) a.h->lev[a.level].k += a.dk;
+  return SH_OK;
+}
+
+sh_status sh_graph_destroy(sh_graph g) {
+  if (!g) return SH_OK;
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  delete g;
+  return SH_OK;
 }
 
 }  // extern "C"
@@ -1243,6 +1348,7 @@ struct sh_batch_s {
   SegPlan<CopySeg> a1_stage;     // one-layer ghost copy of the per-stage jobs
   SegPlan<CopySeg> a1_deep;      // full-depth ghost copy of every job (after the step)
   DevArr<LevelScal*> counters;
+  std::vector<long long> versions;  // each job's layout version when the batch was built
   void release() {
     boxes.release();
     ftiles.release();
@@ -1275,6 +1381,11 @@ sh_status sh_batch_create(int32_t njobs, const sh_hierarchy* jobs, sh_batch* out
       delete b;
       return fail(SH_EINVAL, "batched jobs must be single-level hierarchies of one precision on one stream");
     }
+    if (h->capturing) {
+      delete b;
+      return not_capturing(h);
+    }
+    b->versions.push_back(h->layout_version);
     const Level& L = h->lev[0];
     const int off = (int)boxes.size();
     boxes.insert(boxes.end(), L.hbox.begin(), L.hbox.end());
@@ -1322,6 +1433,8 @@ sh_status sh_batch_create(int32_t njobs, const sh_hierarchy* jobs, sh_batch* out
 
 sh_status sh_batch_advance(sh_batch b) {
   if (!b) return fail(SH_EINVAL, "null batch");
+  for (size_t j = 0; j < b->jobs.size(); ++j)
+    if (b->jobs[j]->layout_version != b->versions[j]) return fail(SH_ESTATE, "a job's layout changed since batching");
   const int prec = b->prec;
   const bool nt = b->tune.nt != 0;
   if (b->ftiles.n) {
@@ -1347,6 +1460,44 @@ sh_status sh_batch_advance(sh_batch b) {
   sh_launch_ghost_copy(prec, b->a1_deep.segs.p, b->a1_deep.blocks.p, b->a1_deep.nblocks(), b->boxes.p, ROLE_UN, 4,
                        b->st);
   LAUNCHCHK();
+  return SH_OK;
+}
+
+sh_status sh_batch_capture(sh_batch b, int32_t nsteps, sh_graph* out) {
+  if (!b || !out || nsteps < 1) return fail(SH_EINVAL, "bad arguments");
+  *out = nullptr;
+  for (size_t j = 0; j < b->jobs.size(); ++j) {
+    sh_status s = not_capturing(b->jobs[j]);
+    if (s != SH_OK) return s;
+    if (b->jobs[j]->layout_version != b->versions[j]) return fail(SH_ESTATE, "a job's layout changed since batching");
+  }
+  if (!b->st) return fail(SH_EINVAL, "the legacy default stream cannot be captured: create the jobs on a stream");
+  HIPCHK(hipStreamBeginCapture(b->st, hipStreamCaptureModeThreadLocal));
+  sh_status s = SH_OK;
+  int recorded = 0;
+  for (; recorded < nsteps && (s = sh_batch_advance(b)) == SH_OK; ++recorded) {
+  }
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(b->st, &g);
+  for (sh_hierarchy h : b->jobs) h->lev[0].k -= recorded;  // recorded, not run
+  if (s != SH_OK || e != hipSuccess || !g) {
+    if (g) (void)hipGraphDestroy(g);
+    return s != SH_OK ? s : fail(SH_EDEVICE, hipGetErrorString(e));
+  }
+  sh_graph G = new (std::nothrow) sh_graph_s;
+  if (!G) {
+    (void)hipGraphDestroy(g);
+    return fail(SH_ENOMEM, "host allocation failed");
+  }
+  G->graph = g;
+  G->st = b->st;
+  for (size_t j = 0; j < b->jobs.size(); ++j) G->adv.push_back({b->jobs[j], 0, (long long)nsteps, b->versions[j]});
+  e = hipGraphInstantiate(&G->exec, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    sh_graph_destroy(G);
+    return fail(SH_EDEVICE, hipGetErrorString(e));
+  }
+  *out = G;
   return SH_OK;
 }
 

@@ -67,6 +67,11 @@ _PROTOS = {
     "sh_batch_destroy": (c_int32, [c_void_p]),
     "sh_trace": (c_int32, [c_void_p, c_int32]),
     "sh_trace_read": (c_int64, [c_void_p, c_void_p, c_int64]),
+    "sh_capture_begin": (c_int32, [c_void_p]),
+    "sh_capture_end": (c_int32, [c_void_p, POINTER(c_void_p)]),
+    "sh_batch_capture": (c_int32, [c_void_p, c_int32, POINTER(c_void_p)]),
+    "sh_graph_launch": (c_int32, [c_void_p]),
+    "sh_graph_destroy": (c_int32, [c_void_p]),
 }
 
 EXPORTED = tuple(_PROTOS)
@@ -327,6 +332,11 @@ class Hierarchy:
         _check(self.lib.sh_set_tuning(self.h, kind, nontemporal, tile_z, fuse, fused_shape, fused_tile_z,
                                       fused_variant))
 
+    def capture(self):
+        """``with h.capture() as c: driver.coarse_step(h)`` records the level steps issued
+        inside the block (they do not run); ``c.graph.launch()`` replays them."""
+        return _Capture(self)
+
     PROFILE_CLASSES = ("stage1", "stage2", "stage3", "stage4", "ghost_copy", "ghost_interp",
                        "average_down", "fused_step")
 
@@ -364,6 +374,12 @@ class Batch:
     def advance(self):
         _check(self.lib.sh_batch_advance(self.b))
 
+    def capture(self, nsteps: int) -> "Graph":
+        """Record ``nsteps`` batch steps as one replayable graph (see sh_batch_capture)."""
+        g = c_void_p()
+        _check(self.lib.sh_batch_capture(self.b, nsteps, ctypes.byref(g)))
+        return Graph(g)
+
     def close(self):
         if self.b is not None:
             self.lib.sh_batch_destroy(self.b)
@@ -374,3 +390,46 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+class Graph:
+    """A recorded sequence of level steps; ``launch()`` replays it on the recording stream."""
+
+    def __init__(self, g):
+        self.lib = load()
+        self.g = g
+
+    def launch(self):
+        _check(self.lib.sh_graph_launch(self.g))
+
+    def close(self):
+        if self.g is not None:
+            self.lib.sh_graph_destroy(self.g)
+            self.g = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class _Capture:
+    def __init__(self, h):
+        self.h = h
+        self.graph = None
+
+    def __enter__(self):
+        _check(self.h.lib.sh_capture_begin(self.h.h))
+        return self
+
+    def __exit__(self, exc_type, exc, tb):
+        g = c_void_p()
+        st = self.h.lib.sh_capture_end(self.h.h, ctypes.byref(g))
+        if exc_type is None:
+            _check(st)
+            self.graph = Graph(g)
+        elif g.value:
+            self.h.lib.sh_graph_destroy(g)
+        return False
+
