@@ -79,6 +79,9 @@ def main():
                          "serve: 256 Poisson-arriving ensemble jobs")
     ap.add_argument("--beta", type=int, default=2, help="potential exponent (2: the paper's EOM; 0: stable companion)")
     ap.add_argument("--coarse-steps", type=int, default=None)
+    ap.add_argument("--graph-steps", type=int, default=0,
+                    help="single workload: record this many level steps as one HIP graph and time its "
+                         "replays (per-kernel timing and the roofline are then not collected)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU path is a design, "
@@ -102,7 +105,8 @@ def main():
     log(f"initial state {n}^3 (seed {args.seed})")
     U0 = random_state(n, float(n), args.seed)
     prec = shamr.SH_F64 if args.prec == "f64" else shamr.SH_F32
-    h = shamr.Hierarchy(n, float(n), 0.25, 0.1, 1.0, 2.0, 2, max_level=0, prec=prec)
+    stream = torch.cuda.Stream()
+    h = shamr.Hierarchy(n, float(n), 0.25, 0.1, 1.0, 2.0, 2, max_level=0, prec=prec, stream=stream)
     h.set_layout(0, [(0, 0, 0, n - 1, n - 1, n - 1)])
     h.write_dense(0, U0)
     h.fill_ghosts(0)
@@ -112,15 +116,29 @@ def main():
         h.advance(0)
     h.sync()
     torch.cuda.synchronize()
-    log(f"timing {K} steps")
-    h.profile(True)
+    graph = None
+    G = args.graph_steps
+    if G > 1:
+        if K % G:
+            print("--steps must be a multiple of --graph-steps", file=sys.stderr)
+            sys.exit(2)
+        with h.capture() as c:
+            for _ in range(G):
+                h.advance(0)
+        graph = c.graph
+    log(f"timing {K} steps" + (f" as {K // G} replays of a {G}-step graph" if graph else ""))
+    h.profile(graph is None)
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     e0.record(h.stream)
-    for _ in range(K):
-        h.advance(0)
+    if graph is not None:
+        for _ in range(K // G):
+            graph.launch()
+    else:
+        for _ in range(K):
+            h.advance(0)
     e1.record(h.stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -131,6 +149,7 @@ def main():
     cells = n ** 3
     value = cells * 4 * K / (ms / 1e3)
     sb = STAGE_BYTES[args.prec]
+    roofline = None
     if prof["fused_step"][1]:
         kname = "fused_rk4_step"
         k_ms, k_n = prof["fused_step"]
@@ -140,10 +159,13 @@ def main():
         k_ms = sum(prof[f"stage{s + 1}"][0] for s in range(4))
         k_n = sum(prof[f"stage{s + 1}"][1] for s in range(4))
         k_bytes = sum(sb[s] * cells * prof[f"stage{s + 1}"][1] for s in range(4))
-    achieved = k_bytes / (k_ms / 1e3) / 1e9
-    traffic = traffic_from_profiles(args.prec, n, kname)
-    log(f"{ms / K:.3f} ms/step (event), wall {wall / K * 1e3:.3f} ms/step; {kname} kernel "
-        f"{k_ms / k_n:.3f} ms/launch, {achieved:.0f} GB/s algorithmic; energy {e[3]:.6g}, nonfinite cells {bad}")
+    if k_n:  # (not collected for graph replays)
+        achieved = k_bytes / (k_ms / 1e3) / 1e9
+        roofline = {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_from_profiles(args.prec, n, kname)}
+        log(f"{kname} kernel {k_ms / k_n:.3f} ms/launch, {achieved:.0f} GB/s algorithmic")
+    log(f"{ms / K:.3f} ms/step (event), wall {wall / K * 1e3:.3f} ms/step; energy {e[3]:.6g}, "
+        f"nonfinite cells {bad}")
     out = {
         "metric": "cell-updates/s per RK stage",
         "value": value,
@@ -159,9 +181,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"single-level periodic {n}^3, RK4 + 7-point Laplacian, "
                                f"{'FP64' if args.prec == 'f64' else 'FP32 storage / FP64 accumulation'}",
-                   "lattice": n, "dx": 1.0, "dt": 0.25, "eta0": 0.1, "lambda": 1.0, "seed": args.seed},
-        "roofline": {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
+                   "lattice": n, "dx": 1.0, "dt": 0.25, "eta0": 0.1, "lambda": 1.0, "seed": args.seed,
+                   "graph_steps": G if graph is not None else None},
+        "roofline": roofline,
         # the same cell-update rate priced at the bytes a one-stage-per-pass kernel must
         # move (mean over the four stages), against the same peak
         "per_stage_equivalent": {"bytes_per_cell_stage": sum(sb) / 4,
@@ -176,6 +198,8 @@ def main():
         out["cpu_baseline"] = cpu_baseline(U0, n)
     else:
         out["cpu_baseline"] = None
+    if graph is not None:
+        graph.close()
     h.close()
     if args.calib_copy:
         a = torch.empty(2 ** 28, dtype=torch.float64, device="cuda")

@@ -192,23 +192,28 @@ const char* sh_last_error(void);
    out[0..6] = {eta_s, c_fric, c_pot, dt/6, dt/3, dt/2, dt}.  Diagnostic. */
 sh_status sh_debug_stage_scalars(sh_hierarchy h, int32_t lev, int32_t s, double* out_host);
 
-/* Launch shape (performance only; results are identical for every choice):
-   kind 0 = per-stage kernel with one wavefront per 64-cell tile for every box, 4 or 8 =
-   blocks of that many wavefront rows sharing psi through LDS for boxes at least 64
-   cells wide; nontemporal 1 = once-used streams do not stay cache resident; tile_z =
-   cells per per-stage tile in z (0 = from the level size); fuse 4 = level 0 (which has no
-   coarse/fine boundary) takes each step in one kernel computing all four RK stages
-   (temporal blocking; needs every level-0 box to be a multiple of the fused footprint,
-   else per-stage), 0 = per-stage kernels; fused_shape 0 = 32 x 8 footprint, 1 = 64 x 4,
-   2 = 32 x 16, 3 = 16 x 8; fused_tile_z = planes per fused tile; fused_variant 0-6 =
-   thread order / x-neighbour exchange / accumulator placement of the fused kernel
-   (0: row-major, LDS, registers; 1: row-major, lane shifts, registers; 2: row-major,
-   lane shifts, LDS; 3: ring order, LDS, LDS; 4: ring order, LDS, registers; 5: as 4,
-   with U_n planes loaded two iterations ahead; 6: as 5, accumulator in LDS).  Applies to every level.  Defaults at
-   creation: kind 8, nontemporal 1, tile_z 0, fuse 4, fused_tile_z 512, and fused_shape /
-   fused_variant 0 / 5 for SH_F64, 2 / 6 for SH_F32; the environment variable SHAMR_TUNE
-   (e.g. "kind=8,nt=1,zc=0,fuse=4,fshape=0,fzc=512,fvar=5,fgrp=1") overrides them (fgrp
-   1 = fused tiles launched in groups of 32 covering square-ish patches, 0 = in rows). */
+/* Launch shape (performance only; results are identical for every choice).
+   kind: 0 = per-stage kernel with one wavefront per 64-cell tile for every box; 4 or 8 =
+     blocks of that many wavefront rows sharing psi through LDS for boxes at least 64
+     cells wide.
+   nontemporal: 1 = once-used streams do not stay cache resident.
+   tile_z: cells per per-stage tile in z (0 = from the level size).
+   fuse: 4 = level 0 (which has no coarse/fine boundary) takes each step in one kernel
+     computing all four RK stages (temporal blocking; needs every level-0 box to be a
+     multiple of the fused footprint, else per-stage); 0 = per-stage kernels.
+   fused_shape: footprint 0 = 32 x 8, 1 = 64 x 4, 2 = 32 x 16, 3 = 16 x 8.
+   fused_tile_z: planes per fused tile; 0 = 512, halved while that gives fewer than 1024
+     tiles, down to 16 (a batch decides once for all its members).
+   fused_variant: thread order / x-neighbour exchange / accumulator placement / U_n
+     prefetch of the fused kernel: 0 = row-major, LDS, registers; 1 = row-major, lane
+     shifts, registers; 2 = row-major, lane shifts, LDS; 3 = ring order, LDS, LDS; 4 =
+     ring order, LDS, registers; 5 = as 4 with U_n planes loaded two iterations ahead and
+     the later stages' z-1 neighbours from LDS; 6 = as 5 with the accumulator in LDS.
+   Applies to every level.  Defaults at creation: kind 8, nontemporal 1, tile_z 0, fuse 4,
+   fused_tile_z 0, fused_shape / fused_variant 0 / 5 for SH_F64 and 2 / 6 for SH_F32.  The
+   environment variable SHAMR_TUNE (e.g. "kind=8,nt=1,zc=0,fuse=4,fshape=0,fzc=0,fvar=5,
+   fgrp=1") overrides them; fgrp 1 = fused tiles launched in groups of 32 covering
+   square-ish patches, 0 = in rows. */
 sh_status sh_set_tuning(sh_hierarchy h, int32_t kind, int32_t nontemporal, int32_t tile_z, int32_t fuse,
                         int32_t fused_shape, int32_t fused_tile_z, int32_t fused_variant);
 

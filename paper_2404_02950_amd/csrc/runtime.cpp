@@ -183,7 +183,7 @@ struct Tuning {
   int zc = 0;
   int fuse = 4;
   int fshape = 0;
-  int fzc = 512;
+  int fzc = 0;   // planes per fused tile; 0 = chosen from the number of tiles
   int fvar = 0;  // fused kernel variant (thread order / neighbour exchange / accumulator)
   int fgrp = 1;  // fused tile order: 1 = groups of 32 tiles on square-ish patches, 0 = rows
 };
@@ -221,7 +221,7 @@ static void tuning_from_env(Tuning& t) {
       if (k == "zc" && v >= 0 && v <= 1024) t.zc = v;
       if (k == "fuse" && (v == 0 || v == 4)) t.fuse = v;
       if (k == "fshape" && v >= 0 && v <= 3) t.fshape = v;
-      if (k == "fzc" && v >= 1 && v <= 1024) t.fzc = v;
+      if (k == "fzc" && v >= 0 && v <= 1024) t.fzc = v;
       if (k == "fvar" && v >= 0 && v <= 6) t.fvar = v;
       if (k == "fgrp" && (v == 0 || v == 1)) t.fgrp = v;
     }
@@ -273,13 +273,40 @@ static void make_stage_tiles(const std::vector<IBox>& boxes, const Tuning& tu, l
 // then run together.  Listing the tiles of a box by groups of 32 that cover a square-ish
 // patch (not a strip of whole rows) lets those concurrent tiles share most of their
 // halo columns in the XCD's L2.
-static void make_fused_tiles(const std::vector<IBox>& boxes, const Tuning& tu, int ng, std::vector<Tile>& ft) {
-  ft.clear();
-  if (tu.fuse != 4 || ng < 4) return;
+// Whether a level's boxes can take the fused step, and how many footprint columns they
+// have in total.
+static long long fused_columns(const std::vector<IBox>& boxes, const Tuning& tu, int ng) {
+  if (tu.fuse != 4 || ng < 4) return 0;
   int TX, TY;
   sh_fused_footprint(tu.fshape, &TX, &TY);
-  for (const IBox& b : boxes)
-    if (b.size(0) % TX || b.size(1) % TY) return;
+  long long n = 0;
+  for (const IBox& b : boxes) {
+    if (b.size(0) % TX || b.size(1) % TY) return 0;
+    n += (long long)(b.size(0) / TX) * (b.size(1) / TY);
+  }
+  return n;
+}
+
+// Planes per fused tile when not set: long columns (each tile re-reads and recomputes
+// 2 * FG planes at its ends) unless that leaves fewer than 4 tiles per CU, then shorter
+// ones down to 16 planes (small lattices would otherwise run on a few CUs).
+static int fused_zc(const Tuning& tu, long long columns, int nz_max) {
+  if (tu.fzc > 0) return tu.fzc;
+  int zc = 512;
+  while (zc > 16 && columns * ((nz_max + zc - 1) / zc) < 1024) zc >>= 1;
+  return zc;
+}
+
+static void make_fused_tiles(const std::vector<IBox>& boxes, const Tuning& tu, int ng, std::vector<Tile>& ft,
+                             int zc_given = 0) {
+  ft.clear();
+  const long long columns = fused_columns(boxes, tu, ng);
+  if (columns == 0) return;
+  int TX, TY;
+  sh_fused_footprint(tu.fshape, &TX, &TY);
+  int nz_max = 1;
+  for (const IBox& b : boxes) nz_max = std::max(nz_max, b.size(2));
+  const int fzc = zc_given > 0 ? zc_given : fused_zc(tu, columns, nz_max);
   // group of GX x GY tiles with GX * GY = 32 and GX * TX close to GY * TY
   int GX = 1;
   while (GX < 32 && (long long)(2 * GX) * TX <= (long long)(32 / (2 * GX)) * TY * 2) GX *= 2;
@@ -292,7 +319,7 @@ static void make_fused_tiles(const std::vector<IBox>& boxes, const Tuning& tu, i
     const IBox& b = boxes[bi];
     const int nx = b.size(0), ny = b.size(1), nz = b.size(2);
     const int ntx = nx / TX, nty = ny / TY;
-    for (int z0 = 0; z0 < nz; z0 += tu.fzc)
+    for (int z0 = 0; z0 < nz; z0 += fzc)
       for (int gy = 0; gy < nty; gy += GY)
         for (int gx = 0; gx < ntx; gx += GX)
           for (int ty = gy; ty < std::min(gy + GY, nty); ++ty)
@@ -300,7 +327,7 @@ static void make_fused_tiles(const std::vector<IBox>& boxes, const Tuning& tu, i
               Tile t;
               t.box = (int)bi;
               t.xy = (tx * TX) | ((ty * TY) << 16);
-              t.zz = z0 | (std::min(tu.fzc, nz - z0) << 16);
+              t.zz = z0 | (std::min(fzc, nz - z0) << 16);
               t.txs = tu.fshape;
               ft.push_back(t);
             }
@@ -1206,7 +1233,7 @@ sh_status sh_set_tuning(sh_hierarchy h, int32_t kind, int32_t nontemporal, int32
   if (!h) return fail(SH_EINVAL, "null handle");
   if (h->capturing) return not_capturing(h);
   if ((kind != 0 && kind != 4 && kind != 8) || (nontemporal != 0 && nontemporal != 1) || tile_z < 0 ||
-      tile_z > 1024 || (fuse != 0 && fuse != 4) || (fused_shape < 0 || fused_shape > 3) || fused_tile_z < 1 ||
+      tile_z > 1024 || (fuse != 0 && fuse != 4) || (fused_shape < 0 || fused_shape > 3) || fused_tile_z < 0 ||
       fused_tile_z > 1024 || fused_variant < 0 || fused_variant > 6)
     return fail(SH_EINVAL, "bad tuning");
   HIPCHK(hipStreamSynchronize(h->st));
@@ -1375,6 +1402,16 @@ sh_status sh_batch_create(int32_t njobs, const sh_hierarchy* jobs, sh_batch* out
   std::vector<CopySeg> s1, sd;
   std::vector<long long> n1, nd;
   std::vector<LevelScal*> ctr;
+  // one fused tile depth for the whole batch, from all members' columns together
+  long long columns = 0;
+  int nz_max = 1;
+  for (int j = 0; j < njobs; ++j)
+    if (jobs[j] && jobs[j]->lev.size() == 1) {
+      const Level& L = jobs[j]->lev[0];
+      columns += fused_columns(L.boxes, b->tune, L.g.ng);
+      for (const IBox& x : L.boxes) nz_max = std::max(nz_max, x.size(2));
+    }
+  const int batch_zc = fused_zc(b->tune, columns, nz_max);
   for (int j = 0; j < njobs; ++j) {
     sh_hierarchy h = jobs[j];
     if (!h || h->lev.size() != 1 || h->st != b->st || h->p.prec != b->prec) {
@@ -1391,7 +1428,7 @@ sh_status sh_batch_create(int32_t njobs, const sh_hierarchy* jobs, sh_batch* out
     boxes.insert(boxes.end(), L.hbox.begin(), L.hbox.end());
     ctr.push_back(h->d_ls);
     std::vector<Tile> f, w, k;
-    make_fused_tiles(L.boxes, b->tune, L.g.ng, f);
+    make_fused_tiles(L.boxes, b->tune, L.g.ng, f, batch_zc);
     if (!f.empty()) {
       for (Tile t : f) { t.box += off; ft.push_back(t); }
     } else {

@@ -322,7 +322,7 @@ class Hierarchy:
         return list(out)
 
     def set_tuning(self, kind: int = 8, nontemporal: int = 1, tile_z: int = 0, fuse: int = 4,
-                   fused_shape: int | None = None, fused_tile_z: int = 512, fused_variant: int | None = None):
+                   fused_shape: int | None = None, fused_tile_z: int = 0, fused_variant: int | None = None):
         """Launch shape (see sh_set_tuning); the fused shape and variant default to the
         library's choice for the hierarchy's precision."""
         if fused_shape is None:
