@@ -29,6 +29,21 @@ Paper passages followed:
 * Regrid (section II "regridding"): new valid cells keep the old level's values where
   it already had valid cells and are interpolated from the coarse level elsewhere.
 
+* Truncation error estimates (section II.B, "self-shadow"; section IV.C): a fine level
+  and its coarse level are evolved independently between synchronisations, so just
+  before the fine level is averaged onto the coarse one their difference estimates the
+  truncation error.  Read here as the difference at the coarse resolution,
+      TEE(X) = max over the four components of |C(X) - avg(children of X)|,
+  the average taken in the order above, every fine cell carrying the value of its coarse
+  parent (the maximum keeps the first component unless a later one compares greater).
+  Level 0 has no coarser level; a shadow level (level 0 averaged onto half its
+  resolution, when level 0 has taken an even number of steps) is evolved by one step of
+  twice the level-0 step while level 0 takes two, and the same difference between the
+  shadow and level 0 gives the estimate on level 0.  Cells are tagged where the estimate
+  exceeds a threshold (te_crit, one for all components), alone or together with the
+  plaquette criterion.  On a regrid the estimate of kept cells is kept and new cells
+  start at 0.
+
 Interpolation and averaging are done in float64 from promoted values and rounded to
 the storage precision on store.
 """
@@ -130,6 +145,22 @@ def average_down_arrays(F: np.ndarray) -> np.ndarray:
              + ((c(0, 0, 1) + c(1, 0, 1)) + (c(0, 1, 1) + c(1, 1, 1)))) * 0.125)
 
 
+def tee_coarse(C: np.ndarray, F: np.ndarray) -> np.ndarray:
+    """TEE at the coarse resolution: max over components of |C - avg(F children)|
+    (C: (4, M, M, M) coarse state, F: (4, 2M, 2M, 2M) fine state; float64)."""
+    t = None
+    for c in range(4):
+        with np.errstate(all="ignore"):
+            d = np.abs(C[c].astype(np.float64) - average_down_arrays(F[c]))
+        t = d if t is None else np.where(d > t, d, t)
+    return t
+
+
+def refine_values(T: np.ndarray) -> np.ndarray:
+    """Each coarse value onto its 2^3 children."""
+    return np.repeat(np.repeat(np.repeat(T, 2, axis=0), 2, axis=1), 2, axis=2)
+
+
 def schedule(finest: int, nstages: int):
     """Operations of one coarse step with levels 0..finest and an nstages integrator.
 
@@ -167,6 +198,7 @@ class Level:
         self.X = None
         self.acc = None
         self.k = 0
+        self.tee = np.zeros((M, M, M))
 
 
 class Hierarchy:
@@ -182,6 +214,10 @@ class Hierarchy:
         self.check_nesting = check_nesting
         self.levels: list[Level] = []
         self.trace: list[tuple] = []
+        self.tee_on = False
+        self.te_crit = 0.0
+        self.tag_mode = 1  # bit 0: plaquette winding, bit 1: truncation error estimate
+        self.shadow: Level | None = None
 
     # ---- bookkeeping -------------------------------------------------------------
     @property
@@ -236,6 +272,9 @@ class Hierarchy:
         keep = new_valid & old_valid
         if oldU is not None:
             U[:, keep] = oldU[:, keep]
+        tee = np.zeros((L.M,) * 3)
+        tee[keep] = L.tee[keep]
+        L.tee = tee
         fresh = new_valid & ~old_valid
         fz, fy, fx = np.nonzero(fresh)
         for c in range(4):
@@ -296,15 +335,58 @@ class Hierarchy:
     def average_down(self, fine: int):
         F, C = self.levels[fine], self.levels[fine - 1]
         cov = coarsen_mask(F.valid)
+        if self.tee_on:
+            T = tee_coarse(C.U, F.U)
+            F.tee = np.where(F.valid, refine_values(T), 0.0)
         for c in range(4):
             with np.errstate(all="ignore"):
                 avg = average_down_arrays(F.U[c])
             C.U[c][cov] = avg[cov].astype(self.dtype)
 
     # ---- diagnostics -------------------------------------------------------------
+    def set_tee(self, enable: bool, te_crit: float = 0.0, tag_mode: int = 1):
+        self.tee_on, self.te_crit, self.tag_mode = bool(enable), float(te_crit), int(tag_mode)
+
     def tags(self, lev: int) -> np.ndarray:
         L = self.levels[lev]
-        return tag_cells(L.U[0], L.U[1]) & L.valid.astype(np.uint8)
+        t = np.zeros((L.M,) * 3, dtype=bool)
+        if self.tag_mode & 1:
+            t |= tag_cells(L.U[0], L.U[1]).astype(bool)
+        if self.tag_mode & 2:
+            t |= L.tee > self.te_crit
+        return (t & L.valid).astype(np.uint8)
+
+    # ---- shadow level (truncation error estimate of level 0) --------------------
+    def shadow_begin(self):
+        L0 = self.levels[0]
+        if L0.k % 2:
+            raise ValueError("the shadow starts when level 0 has taken an even number of steps")
+        dx = level_dx(self.L, self.n0, 0) * 2.0
+        S = Level(self.n0 // 2, dx, self.cfl * dx)
+        S.k = L0.k // 2
+        S.k_start = S.k
+        S.valid[:] = True
+        S.U = np.stack([average_down_arrays(L0.U[c]) for c in range(4)]).astype(self.dtype)
+        self.shadow = S
+
+    def shadow_advance(self):
+        S = self.shadow
+        if S.k != S.k_start:
+            raise ValueError("the shadow takes a single step")
+        eta_n = level_time(self.eta0, S.k, S.dt)
+        X, acc = S.U, None
+        with np.errstate(all="ignore"):
+            for s in range(4):
+                acc, X = rk4_stage(s, X, S.U, acc, eta_n, S.dt, 1.0 / (S.dx * S.dx), self.alpha, self.lam, self.beta)
+        S.U = X
+        S.k += 1
+
+    def shadow_end(self):
+        S, L0 = self.shadow, self.levels[0]
+        if S.k != S.k_start + 1 or L0.k != 2 * S.k:
+            raise ValueError("level 0 and the shadow are not at the same time after one shadow step")
+        L0.tee = refine_values(tee_coarse(S.U, L0.U))
+        self.shadow = None
 
     def covered(self, lev: int) -> np.ndarray:
         """Cells of level lev under a finer level."""
