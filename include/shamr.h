@@ -240,6 +240,27 @@ sh_status sh_batch_create(int32_t njobs, const sh_hierarchy* jobs, sh_batch* out
 sh_status sh_batch_advance(sh_batch b);
 sh_status sh_batch_destroy(sh_batch b);
 
+/* Truncation error estimates (Sec. II.B "self-shadow"; Sec. IV.C).  With sh_set_tee(h, 1,
+   te_crit, tag_mode) every sh_average_down first computes, per coarse cell it covers,
+   TEE = max over the four components of |C - avg(children)| (float64, the first
+   component's value unless a later one compares greater) and stores it on the fine
+   level's cells (all 8 children), before overwriting C.  Level 0 has no coarser level:
+   sh_shadow_begin(h) (level 0 at an even step count, even-aligned level-0 boxes) builds
+   the shadow level, level 0 averaged onto half its resolution; sh_shadow_advance(h)
+   takes its single step of twice the level-0 step; once level 0 has taken its two steps,
+   sh_shadow_end(h) stores the same estimate (shadow against level 0 averaged) on level
+   0 and releases the shadow.  On a regrid kept cells keep their estimate and new cells
+   start at 0.  tag_mode selects what sh_tag_cells tags: 1 = plaquette winding, 2 =
+   estimate > te_crit, 3 = either.  sh_read_tee copies a level's estimates (one double
+   per valid cell, boxes in layout order, x fastest) to device memory of the caller.
+   Errors: SH_EINVAL (bad tag_mode or te_crit, odd or misaligned level 0), SH_ESTATE
+   (shadow calls out of order). */
+sh_status sh_set_tee(sh_hierarchy h, int32_t enable, double te_crit, int32_t tag_mode);
+sh_status sh_shadow_begin(sh_hierarchy h);
+sh_status sh_shadow_advance(sh_hierarchy h);
+sh_status sh_shadow_end(sh_hierarchy h);
+sh_status sh_read_tee(sh_hierarchy h, int32_t lev, double* out_dev);
+
 /* Recorded level steps (HIP graphs).  The Berger-Oliger order of Sec. II.A (Fig. 2) is a
    fixed sequence of launches for a fixed layout, so a coarse step (or several) can be
    recorded once and replayed with one launch; the step counters and level times live in

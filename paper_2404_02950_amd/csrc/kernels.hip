@@ -362,12 +362,17 @@ __global__ __launch_bounds__(SH_BLOCK) void k_ghost_interp(const InterpSeg* __re
 // ---------------------------------------------------------------------------------
 // A5: average down, all 4 components, fine U_n -> coarse U_n:
 //   c = ((((f000+f100)+(f010+f110))+((f001+f101)+(f011+f111))) * 0.125)
+// With tee: first the truncation error estimate, max over the components of
+// |C - avg| (float64; the first component's value unless a later one compares greater),
+// stored on the 8 children in the fine level's per-cell array.  write_coarse = 0 keeps
+// the coarse state (the shadow-level comparison).
 // ---------------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(SH_BLOCK) void k_avgdown(const AvgSeg* __restrict__ segs,
                                                       const SegBlock* __restrict__ blocks,
                                                       const BoxDev* __restrict__ cboxes,
-                                                      const BoxDev* __restrict__ fboxes) {
+                                                      const BoxDev* __restrict__ fboxes, double* __restrict__ tee,
+                                                      int write_coarse) {
   const SegBlock sb = blocks[blockIdx.x];
   const AvgSeg s = segs[sb.seg];
   const int c = sb.start + threadIdx.x;
@@ -378,16 +383,31 @@ __global__ __launch_bounds__(SH_BLOCK) void k_avgdown(const AvgSeg* __restrict__
   const int k = r / s.n[1];
   const BoxDev& C = cboxes[s.cbox];
   const BoxDev& F = fboxes[s.fbox];
-  T* dst = (T*)C.slot[role_slot(ROLE_UN, C.ls->k)];
-  const T* src = (const T*)F.slot[role_slot(ROLE_UN, F.ls->k)];
+  T* dst = (T*)slot_base(C, role_slot(ROLE_UN, C.ls->k));
+  const T* src = (const T*)slot_base(F, role_slot(ROLE_UN, F.ls->k));
   const long long ec = elem<T>(C, s.clo[0] + i, s.clo[1] + j, s.clo[2] + k);
   const long long ef = elem<T>(F, s.f0[0] + 2 * i, s.f0[1] + 2 * j, s.f0[2] + 2 * k);
   const long long px = F.px, plane = px * F.py;
+  double t = 0.0;
   for (int comp = 0; comp < 4; ++comp) {
     const T* f = src + comp * F.cs + ef;
     const double f000 = f[0], f100 = f[1], f010 = f[px], f110 = f[px + 1];
     const double f001 = f[plane], f101 = f[plane + 1], f011 = f[plane + px], f111 = f[plane + px + 1];
-    dst[comp * C.cs + ec] = (T)(((((f000 + f100) + (f010 + f110)) + ((f001 + f101) + (f011 + f111))) * 0.125));
+    const double avg = ((((f000 + f100) + (f010 + f110)) + ((f001 + f101) + (f011 + f111))) * 0.125);
+    if (tee) {
+      const double d = fabs((double)dst[comp * C.cs + ec] - avg);
+      t = (comp == 0 || d > t) ? d : t;
+    }
+    if (write_coarse) dst[comp * C.cs + ec] = (T)avg;
+  }
+  if (tee) {
+    const int x0 = s.f0[0] + 2 * i, y0 = s.f0[1] + 2 * j, z0 = s.f0[2] + 2 * k;
+    for (int dz = 0; dz < 2; ++dz)
+      for (int dy = 0; dy < 2; ++dy) {
+        const long long row = F.mask_off + ((long long)(z0 + dz) * F.ny + (y0 + dy)) * F.nx + x0;
+        tee[row] = t;
+        tee[row + 1] = t;
+      }
   }
 }
 
@@ -396,7 +416,9 @@ template <typename T>
 __global__ __launch_bounds__(SH_BLOCK) void k_regrid_copy(const CopySeg* __restrict__ segs,
                                                           const SegBlock* __restrict__ blocks,
                                                           const BoxDev* __restrict__ dboxes,
-                                                          const BoxDev* __restrict__ sboxes) {
+                                                          const BoxDev* __restrict__ sboxes,
+                                                          const double* __restrict__ tee_src,
+                                                          double* __restrict__ tee_dst) {
   const SegBlock sb = blocks[blockIdx.x];
   const CopySeg s = segs[sb.seg];
   const int c = sb.start + threadIdx.x;
@@ -412,6 +434,10 @@ __global__ __launch_bounds__(SH_BLOCK) void k_regrid_copy(const CopySeg* __restr
   const long long ed = elem<T>(D, s.dlo[0] + i, s.dlo[1] + j, s.dlo[2] + k);
   const long long es = elem<T>(Sb, s.slo[0] + i, s.slo[1] + j, s.slo[2] + k);
   for (int comp = 0; comp < 4; ++comp) dst[comp * D.cs + ed] = src[comp * Sb.cs + es];
+  // the truncation error estimate of a kept cell stays with it
+  if (tee_src)
+    tee_dst[D.mask_off + ((long long)(s.dlo[2] + k) * D.ny + (s.dlo[1] + j)) * D.nx + (s.dlo[0] + i)] =
+        tee_src[Sb.mask_off + ((long long)(s.slo[2] + k) * Sb.ny + (s.slo[1] + j)) * Sb.nx + (s.slo[0] + i)];
 }
 
 // ---------------------------------------------------------------------------------
@@ -439,7 +465,8 @@ __device__ __forceinline__ bool pierced(const double* X, const double* Y, int a,
 template <typename T>
 __global__ __launch_bounds__(SH_BLOCK) void k_tag(const Tile* __restrict__ tiles, int ntiles,
                                                   const BoxDev* __restrict__ boxes, uint8_t* __restrict__ mask,
-                                                  int* __restrict__ tile_count) {
+                                                  int* __restrict__ tile_count, const double* __restrict__ tee,
+                                                  double te_crit, int mode) {
   const int lane = threadIdx.x & (SH_WAVE - 1);
   const int t = blockIdx.x * (SH_BLOCK / SH_WAVE) + (threadIdx.x >> 6);
   if (t >= ntiles) return;
@@ -459,6 +486,14 @@ __global__ __launch_bounds__(SH_BLOCK) void k_tag(const Tile* __restrict__ tiles
   const long long px = B.px, plane = px * B.py, cs = B.cs;
   int count = 0;
   for (int z = z0; z < zend; ++z) {
+    const long long cell = B.mask_off + ((long long)z * B.ny + y) * B.nx + x;
+    bool tag = (mode & 2) && tee[cell] > te_crit;
+    if (!(mode & 1)) {
+      tag = tag && active;
+      if (active) mask[cell] = tag ? 1 : 0;
+      count += __popcll(__ballot(tag));
+      continue;
+    }
     const long long e = elem<T>(B, x, y, z);
     // 3x3x3 neighbourhood, index (dz+1)*9 + (dy+1)*3 + (dx+1); corners unused
     double X[27], Y[27];
@@ -479,7 +514,6 @@ __global__ __launch_bounds__(SH_BLOCK) void k_tag(const Tile* __restrict__ tiles
           Y[id] = (double)U[cs + o];
         }
 #define ID(dx, dy, dz) (((dz) + 1) * 9 + ((dy) + 1) * 3 + ((dx) + 1))
-    bool tag = false;
     // normal z, axes (x, y): lower corners (x-1..x, y-1..y) in plane z
 #pragma unroll
     for (int cy = -1; cy <= 0; ++cy)
@@ -500,7 +534,7 @@ __global__ __launch_bounds__(SH_BLOCK) void k_tag(const Tile* __restrict__ tiles
         tag |= pierced(X, Y, ID(cx, 0, cz), ID(cx, 0, cz + 1), ID(cx + 1, 0, cz + 1), ID(cx + 1, 0, cz));
 #undef ID
     tag = tag && active;
-    if (active) mask[B.mask_off + ((long long)z * B.ny + y) * B.nx + x] = tag ? 1 : 0;
+    if (active) mask[cell] = tag ? 1 : 0;
     count += __popcll(__ballot(tag));
   }
   if (lane == 0) tile_count[t] = count;
@@ -791,27 +825,37 @@ void sh_launch_ghost_interp(int prec, const InterpSeg* segs, const SegBlock* blo
 }
 
 void sh_launch_avgdown(int prec, const AvgSeg* segs, const SegBlock* blocks, int nblocks, const BoxDev* cboxes,
-                       const BoxDev* fboxes, hipStream_t st) {
+                       const BoxDev* fboxes, double* tee, int write_coarse, hipStream_t st) {
   if (nblocks == 0) return;
-  if (prec == 0) hipLaunchKernelGGL(k_avgdown<double>, dim3(nblocks), dim3(SH_BLOCK), 0, st, segs, blocks, cboxes, fboxes);
-  else hipLaunchKernelGGL(k_avgdown<float>, dim3(nblocks), dim3(SH_BLOCK), 0, st, segs, blocks, cboxes, fboxes);
+  if (prec == 0)
+    hipLaunchKernelGGL(k_avgdown<double>, dim3(nblocks), dim3(SH_BLOCK), 0, st, segs, blocks, cboxes, fboxes, tee,
+                       write_coarse);
+  else
+    hipLaunchKernelGGL(k_avgdown<float>, dim3(nblocks), dim3(SH_BLOCK), 0, st, segs, blocks, cboxes, fboxes, tee,
+                       write_coarse);
 }
 
 void sh_launch_regrid_copy(int prec, const CopySeg* segs, const SegBlock* blocks, int nblocks, const BoxDev* dboxes,
-                           const BoxDev* sboxes, hipStream_t st) {
+                           const BoxDev* sboxes, const double* tee_src, double* tee_dst, hipStream_t st) {
   if (nblocks == 0) return;
   if (prec == 0)
-    hipLaunchKernelGGL(k_regrid_copy<double>, dim3(nblocks), dim3(SH_BLOCK), 0, st, segs, blocks, dboxes, sboxes);
+    hipLaunchKernelGGL(k_regrid_copy<double>, dim3(nblocks), dim3(SH_BLOCK), 0, st, segs, blocks, dboxes, sboxes,
+                       tee_src, tee_dst);
   else
-    hipLaunchKernelGGL(k_regrid_copy<float>, dim3(nblocks), dim3(SH_BLOCK), 0, st, segs, blocks, dboxes, sboxes);
+    hipLaunchKernelGGL(k_regrid_copy<float>, dim3(nblocks), dim3(SH_BLOCK), 0, st, segs, blocks, dboxes, sboxes,
+                       tee_src, tee_dst);
 }
 
 void sh_launch_tag(int prec, const Tile* tiles, int ntiles, const BoxDev* boxes, uint8_t* mask, int* tile_count,
-                   hipStream_t st) {
+                   const double* tee, double te_crit, int mode, hipStream_t st) {
   const int nb = nblk(ntiles, SH_BLOCK / SH_WAVE);
   if (nb == 0) return;
-  if (prec == 0) hipLaunchKernelGGL(k_tag<double>, dim3(nb), dim3(SH_BLOCK), 0, st, tiles, ntiles, boxes, mask, tile_count);
-  else hipLaunchKernelGGL(k_tag<float>, dim3(nb), dim3(SH_BLOCK), 0, st, tiles, ntiles, boxes, mask, tile_count);
+  if (prec == 0)
+    hipLaunchKernelGGL(k_tag<double>, dim3(nb), dim3(SH_BLOCK), 0, st, tiles, ntiles, boxes, mask, tile_count, tee,
+                       te_crit, mode);
+  else
+    hipLaunchKernelGGL(k_tag<float>, dim3(nb), dim3(SH_BLOCK), 0, st, tiles, ntiles, boxes, mask, tile_count, tee,
+                       te_crit, mode);
 }
 
 void sh_launch_scan(const int* in, long long* out, int n, hipStream_t st) {

@@ -98,7 +98,7 @@ struct LayoutGeom {
   long long nvalid = 0;
   std::vector<Tile> tiles;
   // arena byte offsets
-  size_t off_slot[3], off_acc, off_mask, off_cov, off_cnt, off_toff, off_part, off_eout, total;
+  size_t off_slot[3], off_acc, off_mask, off_cov, off_cnt, off_toff, off_part, off_eout, off_tee, total;
 };
 
 static long long round_up(long long v, long long a) { return (v + a - 1) / a * a; }
@@ -167,6 +167,7 @@ static void make_geom(int prec, int ng, const std::vector<IBox>& boxes, LayoutGe
   g.off_toff = take((size_t)(nt + 1) * 8);
   g.off_part = take((size_t)nt * sizeof(EnergyPartial));
   g.off_eout = take(4 * 8);
+  g.off_tee = take((size_t)g.nvalid * 8);  // truncation error estimate per valid cell
   g.total = o + 256;  // slack for aligning the arena base
 }
 
@@ -361,6 +362,7 @@ struct Level {
 
   uint8_t* mask() const { return (uint8_t*)(base + g.off_mask); }
   uint8_t* covered() const { return (uint8_t*)(base + g.off_cov); }
+  double* tee() const { return (double*)(base + g.off_tee); }
   int* tile_count() const { return (int*)(base + g.off_cnt); }
   long long* tile_off() const { return (long long*)(base + g.off_toff); }
   EnergyPartial* epart() const { return (EnergyPartial*)(base + g.off_part); }
@@ -397,8 +399,20 @@ struct sh_hierarchy_s {
   // counters are put back at the end and advanced by each replay instead
   bool capturing = false;
   std::vector<long long> k_at_capture;
+  // truncation error estimates (computed at every synchronisation when on) and the
+  // tagging criterion: bit 0 plaquette winding, bit 1 estimate above te_crit
+  bool tee_on = false;
+  double te_crit = 0.0;
+  int tag_mode = 1;
+  // shadow level: level 0 averaged onto half its resolution, evolved by one step of
+  // twice the level-0 step (its scalars live in d_ls[SH_SHADOW_LS]; arena owned here)
+  bool has_shadow = false;
+  Level shadow;
+  char* shadow_arena = nullptr;
+  long long shadow_k0 = 0;
+  SegPlan<AvgSeg> shadow_a5;
   long long layout_version = 0;  // bumped by every layout change (captured graphs go stale)
-  LevelScal* d_ls = nullptr;  // 16 levels
+  LevelScal* d_ls = nullptr;  // 16 levels, then the shadow level
   double* d_dbg = nullptr;
   std::vector<Level> lev;
   bool tracing = false;
@@ -450,6 +464,8 @@ struct sh_hierarchy_s {
     trace.push_back(b);
   }
 };
+
+constexpr int SH_SHADOW_LS = 16;  // slot of the shadow level's scalars in d_ls (after 16 levels)
 
 static double level_dx(const sh_params& p, int l) { return (p.L / (double)p.n0) / (double)(1 << l); }
 
@@ -709,6 +725,8 @@ struct sh_graph_s {
   std::vector<Adv> adv;  // host step counters a replay advances
 };
 
+static void shadow_release(sh_hierarchy h);
+
 // ---------------------------------------------------------------------------------
 // C-ABI
 // ---------------------------------------------------------------------------------
@@ -748,7 +766,7 @@ sh_status sh_hierarchy_create(const sh_params* p, void* hip_stream, sh_hierarchy
   h->tune = default_tuning(p->prec);
   tuning_from_env(h->tune);
   h->st = (hipStream_t)hip_stream;
-  if (hipMalloc((void**)&h->d_ls, 16 * sizeof(LevelScal)) != hipSuccess ||
+  if (hipMalloc((void**)&h->d_ls, (SH_SHADOW_LS + 1) * sizeof(LevelScal)) != hipSuccess ||
       hipMalloc((void**)&h->d_dbg, 16 * sizeof(double)) != hipSuccess) {
     if (h->d_ls) (void)hipFree(h->d_ls);
     delete h;
@@ -767,6 +785,7 @@ sh_status sh_hierarchy_destroy(sh_hierarchy h) {
   }
   (void)hipStreamSynchronize(h->st);
   for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
+  shadow_release(h);
   for (Level& L : h->lev) L.release();
   if (h->d_ls) (void)hipFree(h->d_ls);
   if (h->d_dbg) (void)hipFree(h->d_dbg);
@@ -776,7 +795,7 @@ sh_status sh_hierarchy_destroy(sh_hierarchy h) {
 
 int32_t sh_num_levels(sh_hierarchy h) { return h ? (int32_t)h->lev.size() : 0; }
 
-static sh_status set_box_tables(sh_hierarchy h, int l, Level& L) {
+static sh_status set_box_tables(sh_hierarchy h, LevelScal* ls, Level& L) {
   L.hbox.clear();
   std::vector<long long> xv{0}, xg{0}, ro{0};
   long long moff = 0;
@@ -785,7 +804,7 @@ static sh_status set_box_tables(sh_hierarchy h, int l, Level& L) {
     BoxDev d;
     for (int s = 0; s < 3; ++s) d.slot[s] = L.base + L.g.off_slot[s] + (size_t)L.g.box_off[i] * L.g.esize;
     d.acc = (double*)(L.base + L.g.off_acc) + L.g.box_off[i];
-    d.ls = h->d_ls + l;
+    d.ls = ls;
     d.cs = L.g.cs[i];
     d.nx = b.size(0);
     d.ny = b.size(1);
@@ -853,7 +872,7 @@ sh_status sh_set_level_layout(sh_hierarchy h, int32_t l, int32_t nboxes, const i
   const bool existing = l < (int)h->lev.size();
   N.k = existing ? h->lev[l].k : (l == 0 ? 0 : 2 * h->lev[l - 1].k);
 
-  s = set_box_tables(h, l, N);
+  s = set_box_tables(h, h->d_ls + l, N);
   if (s != SH_OK) { N.release(); return s; }
   {
     std::vector<CopySeg> cs;
@@ -921,8 +940,11 @@ sh_status sh_set_level_layout(sh_hierarchy h, int32_t l, int32_t nboxes, const i
   h->lev[l] = N;
   s = upload_ls(h, l);
   if (s != SH_OK) return s;
+  // truncation error estimates: 0 for new cells, kept cells keep theirs
+  HIPCHK(hipMemsetAsync(N.tee(), 0, (size_t)N.g.nvalid * 8, h->st));
   if (existing) {
-    sh_launch_regrid_copy(p.prec, keep.segs.p, keep.blocks.p, keep.nblocks(), N.dbox.p, old.dbox.p, h->st);
+    sh_launch_regrid_copy(p.prec, keep.segs.p, keep.blocks.p, keep.nblocks(), N.dbox.p, old.dbox.p, old.tee(),
+                          N.tee(), h->st);
     LAUNCHCHK();
   }
   if (l > 0) {
@@ -1064,11 +1086,144 @@ sh_status sh_average_down(sh_hierarchy h, int32_t f) {
   if (F.k != 2 * C.k) return fail(SH_ESTATE, "levels are not at the same time");
   h->rec(4, f, 0, 0);
   hipEvent_t ev = h->prof_begin();
-  sh_launch_avgdown(h->p.prec, F.a5.segs.p, F.a5.blocks.p, F.a5.nblocks(), C.dbox.p, F.dbox.p, h->st);
+  sh_launch_avgdown(h->p.prec, F.a5.segs.p, F.a5.blocks.p, F.a5.nblocks(), C.dbox.p, F.dbox.p,
+                    h->tee_on ? F.tee() : nullptr, 1, h->st);
   h->prof_end(ev, 6);
   LAUNCHCHK();
   if ((s = same_level_fill(h, f - 1, ROLE_UN)) != SH_OK) return s;
   return coarse_fine_fill(h, f, ROLE_UN, 4);
+}
+
+sh_status sh_set_tee(sh_hierarchy h, int32_t enable, double te_crit, int32_t tag_mode) {
+  sh_status s = not_capturing(h);
+  if (s != SH_OK) return s;
+  if (tag_mode < 1 || tag_mode > 3 || !(te_crit >= 0) || te_crit == HUGE_VAL)
+    return fail(SH_EINVAL, "tag_mode must be 1, 2 or 3 and te_crit finite and >= 0");
+  h->tee_on = enable != 0;
+  h->te_crit = te_crit;
+  h->tag_mode = tag_mode;
+  return SH_OK;
+}
+
+static void shadow_release(sh_hierarchy h) {
+  if (!h->has_shadow) return;
+  (void)hipStreamSynchronize(h->st);
+  h->shadow.release();
+  h->shadow_a5.release();
+  if (h->shadow_arena) (void)hipFree(h->shadow_arena);
+  h->shadow_arena = nullptr;
+  h->shadow = Level();
+  h->has_shadow = false;
+}
+
+static void shadow_copy(sh_hierarchy h, int role) {
+  Level& S = h->shadow;
+  sh_launch_ghost_copy(h->p.prec, S.a1.segs.p, S.a1.blocks.p, S.a1.nblocks(), S.dbox.p, role, 2, h->st);
+}
+
+sh_status sh_shadow_begin(sh_hierarchy h) {
+  sh_status s = check_level(h, 0);
+  if (s != SH_OK || (s = not_capturing(h)) != SH_OK) return s;
+  const sh_params& p = h->p;
+  Level& L0 = h->lev[0];
+  if (L0.k % 2) return fail(SH_ESTATE, "the shadow starts when level 0 has taken an even number of steps");
+  if (p.n0 % 2) return fail(SH_EINVAL, "the shadow level needs an even coarse size");
+  for (const IBox& b : L0.boxes)
+    for (int d = 0; d < 3; ++d)
+      if ((b.lo[d] & 1) || !(b.hi[d] & 1)) return fail(SH_EINVAL, "level-0 boxes must start and end on even cells");
+  shadow_release(h);
+  Level S;
+  S.M = p.n0 / 2;
+  S.dx = level_dx(p, 0) * 2.0;
+  S.dt = p.cfl * S.dx;
+  S.boxes = {IBox{{0, 0, 0}, {S.M - 1, S.M - 1, S.M - 1}}};
+  make_geom(p.prec, 1, S.boxes, S.g);
+  if (hipMalloc((void**)&h->shadow_arena, S.g.total) != hipSuccess) return fail(SH_ENOMEM, "shadow level allocation");
+  S.base = (char*)round_up((long long)(uintptr_t)h->shadow_arena, 256);
+  S.bins.build(S.boxes, S.M);
+  S.k = L0.k / 2;
+  h->shadow = S;
+  h->has_shadow = true;
+  h->shadow_k0 = S.k;
+  Level& Sh = h->shadow;
+  if ((s = set_box_tables(h, h->d_ls + SH_SHADOW_LS, Sh)) != SH_OK) {
+    shadow_release(h);
+    return s;
+  }
+  std::vector<CopySeg> cs;
+  std::vector<long long> nc;
+  build_a1(Sh, 1, cs, nc);
+  std::vector<AvgSeg> as;
+  std::vector<long long> nc5;
+  if (!build_a5(L0, Sh, as, nc5)) {
+    shadow_release(h);
+    return fail(SH_EINVAL, "level 0 does not cover the shadow level");
+  }
+  if (Sh.a1.upload(cs, nc) != hipSuccess || h->shadow_a5.upload(as, nc5) != hipSuccess) {
+    shadow_release(h);
+    return fail(SH_EDEVICE, "table upload failed");
+  }
+  LevelScal ls = make_ls(p, 0, Sh.k);
+  ls.dx = Sh.dx;
+  ls.dt = Sh.dt;
+  ls.inv_dx2 = 1.0 / (Sh.dx * Sh.dx);
+  HIPCHK(hipMemcpyAsync(h->d_ls + SH_SHADOW_LS, &ls, sizeof(ls), hipMemcpyHostToDevice, h->st));
+  // the shadow's state: level 0 averaged onto it, then its periodic ghosts
+  sh_launch_avgdown(p.prec, h->shadow_a5.segs.p, h->shadow_a5.blocks.p, h->shadow_a5.nblocks(), Sh.dbox.p,
+                    L0.dbox.p, nullptr, 1, h->st);
+  LAUNCHCHK();
+  shadow_copy(h, ROLE_UN);
+  LAUNCHCHK();
+  HIPCHK(hipStreamSynchronize(h->st));
+  return SH_OK;
+}
+
+sh_status sh_shadow_advance(sh_hierarchy h) {
+  sh_status s = not_capturing(h);
+  if (s != SH_OK) return s;
+  if (!h->has_shadow) return fail(SH_ESTATE, "no shadow level");
+  Level& S = h->shadow;
+  if (S.k != h->shadow_k0) return fail(SH_ESTATE, "the shadow takes a single step");
+  // one RK4 step of twice the level-0 step on the periodic shadow lattice
+  stage(h, S, 0);
+  shadow_copy(h, ROLE_A);
+  stage(h, S, 1);
+  shadow_copy(h, ROLE_B);
+  stage(h, S, 2);
+  shadow_copy(h, ROLE_A);
+  stage(h, S, 3);
+  sh_launch_counter_inc(h->d_ls + SH_SHADOW_LS, 1, h->st);
+  S.k += 1;
+  shadow_copy(h, ROLE_UN);
+  LAUNCHCHK();
+  return SH_OK;
+}
+
+sh_status sh_shadow_end(sh_hierarchy h) {
+  sh_status s = check_level(h, 0);
+  if (s != SH_OK || (s = not_capturing(h)) != SH_OK) return s;
+  if (!h->has_shadow) return fail(SH_ESTATE, "no shadow level");
+  Level& L0 = h->lev[0];
+  Level& S = h->shadow;
+  if (S.k != h->shadow_k0 + 1 || L0.k != 2 * S.k) {
+    return fail(SH_ESTATE, "level 0 and the shadow are not at the same time after one shadow step");
+  }
+  // estimate on level 0: shadow against level 0 averaged, the shadow itself unchanged
+  sh_launch_avgdown(h->p.prec, h->shadow_a5.segs.p, h->shadow_a5.blocks.p, h->shadow_a5.nblocks(), S.dbox.p,
+                    L0.dbox.p, L0.tee(), 0, h->st);
+  LAUNCHCHK();
+  shadow_release(h);
+  return SH_OK;
+}
+
+sh_status sh_read_tee(sh_hierarchy h, int32_t l, double* out_dev) {
+  sh_status s = check_level(h, l);
+  if (s != SH_OK || (s = not_capturing(h)) != SH_OK) return s;
+  if (!out_dev) return fail(SH_EINVAL, "null output");
+  const Level& L = h->lev[l];
+  HIPCHK(hipMemcpyAsync(out_dev, L.tee(), (size_t)L.g.nvalid * 8, hipMemcpyDeviceToDevice, h->st));
+  HIPCHK(hipStreamSynchronize(h->st));
+  return SH_OK;
 }
 
 sh_status sh_tag_cells(sh_hierarchy h, int32_t l, uint8_t* mask_dev, int32_t* idx_host, int64_t cap,
@@ -1080,7 +1235,7 @@ sh_status sh_tag_cells(sh_hierarchy h, int32_t l, uint8_t* mask_dev, int32_t* id
   if ((s = fill(h, l, ROLE_UN, 4)) != SH_OK) return s;
   uint8_t* mask = mask_dev ? mask_dev : L.mask();
   const int nt = L.ntiles();
-  sh_launch_tag(h->p.prec, L.tiles.p, nt, L.dbox.p, mask, L.tile_count(), h->st);
+  sh_launch_tag(h->p.prec, L.tiles.p, nt, L.dbox.p, mask, L.tile_count(), L.tee(), h->te_crit, h->tag_mode, h->st);
   LAUNCHCHK();
   sh_launch_scan(L.tile_count(), L.tile_off(), nt, h->st);
   LAUNCHCHK();

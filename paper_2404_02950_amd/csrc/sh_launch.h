@@ -17,11 +17,11 @@ void sh_launch_ghost_interp(int prec, const InterpSeg* segs, const SegBlock* blo
                             const BoxDev* fboxes, const BoxDev* cboxes, int role, int anum, int ncomp,
                             hipStream_t st);
 void sh_launch_avgdown(int prec, const AvgSeg* segs, const SegBlock* blocks, int nblocks, const BoxDev* cboxes,
-                       const BoxDev* fboxes, hipStream_t st);
+                       const BoxDev* fboxes, double* tee, int write_coarse, hipStream_t st);
 void sh_launch_regrid_copy(int prec, const CopySeg* segs, const SegBlock* blocks, int nblocks, const BoxDev* dboxes,
-                           const BoxDev* sboxes, hipStream_t st);
+                           const BoxDev* sboxes, const double* tee_src, double* tee_dst, hipStream_t st);
 void sh_launch_tag(int prec, const Tile* tiles, int ntiles, const BoxDev* boxes, uint8_t* mask, int* tile_count,
-                   hipStream_t st);
+                   const double* tee, double te_crit, int mode, hipStream_t st);
 void sh_launch_scan(const int* in, long long* out, int n, hipStream_t st);
 void sh_launch_tag_compact(const Tile* tiles, int ntiles, const BoxDev* boxes, const uint8_t* mask,
                            const long long* tile_off, int* idx, long long cap, hipStream_t st);

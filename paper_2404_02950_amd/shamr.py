@@ -72,6 +72,11 @@ _PROTOS = {
     "sh_batch_capture": (c_int32, [c_void_p, c_int32, POINTER(c_void_p)]),
     "sh_graph_launch": (c_int32, [c_void_p]),
     "sh_graph_destroy": (c_int32, [c_void_p]),
+    "sh_set_tee": (c_int32, [c_void_p, c_int32, c_double, c_int32]),
+    "sh_shadow_begin": (c_int32, [c_void_p]),
+    "sh_shadow_advance": (c_int32, [c_void_p]),
+    "sh_shadow_end": (c_int32, [c_void_p]),
+    "sh_read_tee": (c_int32, [c_void_p, c_int32, c_void_p]),
 }
 
 EXPORTED = tuple(_PROTOS)
@@ -275,6 +280,38 @@ class Hierarchy:
         for b in self.boxes[lev]:
             nz, ny, nx = box_shape(b)
             out[b[2]:b[5] + 1, b[1]:b[4] + 1, b[0]:b[3] + 1] = mh[o:o + nz * ny * nx].reshape(nz, ny, nx)
+            o += nz * ny * nx
+        return out
+
+    # -- truncation error estimates ---------------------------------------------------
+    def set_tee(self, enable: bool = True, te_crit: float = 0.0, tag_mode: int = 3):
+        """Compute estimates at every synchronisation; tag by plaquettes (1), by estimate
+        above te_crit (2) or either (3)."""
+        _check(self.lib.sh_set_tee(self.h, int(enable), float(te_crit), int(tag_mode)))
+
+    def shadow_begin(self):
+        _check(self.lib.sh_shadow_begin(self.h))
+
+    def shadow_advance(self):
+        _check(self.lib.sh_shadow_advance(self.h))
+
+    def shadow_end(self):
+        _check(self.lib.sh_shadow_end(self.h))
+
+    def tee_dense(self, lev: int) -> np.ndarray:
+        """A level's estimates as a dense float64 (M, M, M) array (0 outside the level)."""
+        torch = self.torch
+        nv = sum(int(np.prod(box_shape(b))) for b in self.boxes[lev])
+        with torch.cuda.stream(self.stream):
+            t = torch.empty(max(nv, 1), dtype=torch.float64, device="cuda")
+        _check(self.lib.sh_read_tee(self.h, lev, c_void_p(t.data_ptr())))
+        th = t.cpu().numpy()
+        M = self.params.n0 << lev
+        out = np.zeros((M, M, M))
+        o = 0
+        for b in self.boxes[lev]:
+            nz, ny, nx = box_shape(b)
+            out[b[2]:b[5] + 1, b[1]:b[4] + 1, b[0]:b[3] + 1] = th[o:o + nz * ny * nx].reshape(nz, ny, nx)
             o += nz * ny * nx
         return out
 
