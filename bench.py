@@ -79,6 +79,9 @@ def main():
                          "serve: 256 Poisson-arriving ensemble jobs")
     ap.add_argument("--beta", type=int, default=2, help="potential exponent (2: the paper's EOM; 0: stable companion)")
     ap.add_argument("--coarse-steps", type=int, default=None)
+    ap.add_argument("--tag-mode", type=int, default=1, choices=(1, 2, 3),
+                    help="amr256: refine by plaquette winding (1), truncation error estimate (2) or either (3)")
+    ap.add_argument("--te-crit", type=float, default=1e-2, help="amr256: truncation error threshold")
     ap.add_argument("--graph-steps", type=int, default=0,
                     help="single workload: record this many level steps as one HIP graph and time its "
                          "replays (per-kernel timing and the roofline are then not collected)")
@@ -232,10 +235,13 @@ def bench_amr(args):
            "n_gpus": 1, "data": "synthetic", "higher_is_better": True,
            "config": {"workload": f"AMR {n0}^3 + {levels} levels, {loops} string loops R in [20, 60], "
                                   f"blocking factor 8, max box 64, tag buffer 2, regrid every 2 coarse steps, "
-                                  f"{steps} coarse steps, beta = {args.beta}", "seed": args.seed}}
+                                  f"{steps} coarse steps, beta = {args.beta}"
+                                  + (f", tag mode {args.tag_mode}, te_crit {args.te_crit}" if args.tag_mode != 1 else ""),
+                      "seed": args.seed}}
     if args.workload == "amr256":
         prec = shamr.SH_F64 if args.prec == "f64" else shamr.SH_F32
-        h, rep = workloads.run_amr(U0, levels, steps, prec=prec, beta=args.beta, log=log)
+        h, rep = workloads.run_amr(U0, levels, steps, prec=prec, beta=args.beta, log=log, tag_mode=args.tag_mode,
+                                   te_crit=args.te_crit)
         h.close()
         out.update({"value": rep["cell_updates_per_s_end_to_end"], "dtype": args.prec, "report": rep})
     else:

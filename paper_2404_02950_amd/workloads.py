@@ -35,16 +35,26 @@ def level_summary(h):
 
 
 def run_amr(U0: np.ndarray, max_level: int, coarse_steps: int, prec: int = shamr.SH_F64, beta: int = 2,
-            regrid_every: int = 2, log=print, efficiency: float = 0.7, max_level_bytes: int | None = None):
+            regrid_every: int = 2, log=print, efficiency: float = 0.7, max_level_bytes: int | None = None,
+            tag_mode: int = 1, te_crit: float = 1e-2):
     """Advance an AMR hierarchy; returns (hierarchy, report dict).
 
     ``max_level_bytes`` (default: a quarter of the device memory free at the start) caps
-    any one level's arena at regrid; see ``driver.regrid``."""
+    any one level's arena at regrid; see ``driver.regrid``.  ``tag_mode``: 1 = plaquette
+    winding, 2 = truncation error estimate above ``te_crit``, 3 = either.  With estimates
+    the shadow level is started two coarse steps before each regrid, takes its one step,
+    and gives level 0 its estimate at the regrid (the finer levels get theirs at every
+    synchronisation); the initial layout uses the plaquettes, no estimate existing yet."""
     import torch
     if max_level_bytes is None:
         max_level_bytes = torch.cuda.mem_get_info()[0] // 4
+    use_tee = bool(tag_mode & 2)
+    if use_tee and regrid_every < 2:
+        raise ValueError("estimates need at least two coarse steps between regrids (the shadow step)")
     t0 = time.perf_counter()
     h = build_hierarchy(U0, max_level, prec, beta=beta, efficiency=efficiency)
+    if use_tee:
+        h.set_tee(True, te_crit, tag_mode)
     h.sync()
     t_build = time.perf_counter() - t0
     e0, bad0 = h.energy()
@@ -57,8 +67,12 @@ def run_amr(U0: np.ndarray, max_level: int, coarse_steps: int, prec: int = shamr
     h.profile(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    shadow = False
     for step in range(coarse_steps):
         if step > 0 and step % regrid_every == 0:
+            if shadow:
+                h.shadow_end()
+                shadow = False
             h.sync()  # the queued level steps are not regrid time
             tr = time.perf_counter()
             nlev = h.num_levels()
@@ -68,6 +82,10 @@ def run_amr(U0: np.ndarray, max_level: int, coarse_steps: int, prec: int = shamr
             if h.num_levels() < nlev:
                 capped.append({"coarse_step": step, "levels": h.num_levels()})
             t_regrid += time.perf_counter() - tr
+        if use_tee and step % regrid_every == regrid_every - 2 and step + 2 <= coarse_steps:
+            h.shadow_begin()
+            h.shadow_advance()
+            shadow = True
         # cell updates of this coarse step: level l takes 2^l steps of 4 stages
         for lev in range(h.num_levels()):
             cell_stages += h.level_info(lev)["ncells"] * 4 * (1 << lev)
@@ -75,6 +93,8 @@ def run_amr(U0: np.ndarray, max_level: int, coarse_steps: int, prec: int = shamr
         if (step + 1) % 10 == 0:
             h.sync()
             log(f"coarse step {step + 1}: {level_summary(h)}")
+    if shadow:
+        h.shadow_end()
     h.sync()
     wall = time.perf_counter() - t0
     prof = h.profile_read()
@@ -98,6 +118,8 @@ def run_amr(U0: np.ndarray, max_level: int, coarse_steps: int, prec: int = shamr
         "energy_start": e0,
         "energy_end": e1,
         "nonfinite_end": bad1,
+        "tag_mode": tag_mode,
+        "te_crit": te_crit if use_tee else None,
     }
     return h, report
 
