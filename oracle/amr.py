@@ -18,7 +18,8 @@ Paper passages followed:
   evaluated as ((C_I + t_x) + t_y) + t_z with t_d = (C_{I+e_d} - C_{I-e_d}) * (+-1/8).
   Temporal: C(alpha) = (1 - alpha) C_old + alpha C_new, interpolated in time first;
   alpha = 0 and alpha = 1 take C_old and C_new themselves.  Fine sub-step j in {0, 1}
-  at RK stage fraction c_s has alpha = (j + c_s) / 2.
+  at stage fraction c_s has alpha = (j + c_s) / 2; c = (0, 1/2, 1/2, 1) for RK4 and
+  (0, 1, 1/2) for SSPRK3 (the three-stage method of appendix E's parameter list).
 * Synchronisation (section II.A): the fine level is averaged onto the coarse cells it
   covers, c = ((((f000+f100)+(f010+f110))+((f001+f101)+(f011+f111))) * 1/8), and the
   fine ghost cells are set again with no temporal interpolation (alpha = 1).
@@ -51,8 +52,8 @@ from __future__ import annotations
 
 import numpy as np
 
-from .scalars import RK4_C, level_dt, level_dx, level_time, int_power
-from .level import rk4_stage
+from .scalars import level_dt, level_dx, level_time, int_power, stage_fractions
+from .level import rk4_stage, ssprk3_stage
 from .tagging import tag_cells
 from .energy import energy as _energy
 
@@ -206,12 +207,14 @@ class Hierarchy:
 
     def __init__(self, n0: int, L: float, cfl: float, eta0: float, max_level: int,
                  alpha: float = 2.0, lam: float = 1.0, beta: int = 2,
-                 dtype=np.float64, check_nesting: bool = True):
+                 dtype=np.float64, check_nesting: bool = True, integrator: int = 4):
         self.n0, self.L, self.cfl, self.eta0 = n0, L, cfl, eta0
         self.max_level = max_level
         self.alpha, self.lam, self.beta = alpha, lam, beta
         self.dtype = np.dtype(dtype)
         self.check_nesting = check_nesting
+        self.integrator = integrator
+        self.cs = stage_fractions(integrator)
         self.levels: list[Level] = []
         self.trace: list[tuple] = []
         self.tee_on = False
@@ -303,8 +306,9 @@ class Hierarchy:
             X[c][fz, fy, fx] = interp_cells(Ct, fz, fy, fx).astype(X.dtype)
 
     # ---- stepping ----------------------------------------------------------------
-    def coarse_step(self, nstages: int = 4):
+    def coarse_step(self):
         """One coarse step: every level advanced in the order of ``schedule``."""
+        nstages = len(self.cs)
         ops = schedule(self.finest, nstages)
         for op in ops:
             self.trace.append(op)
@@ -313,7 +317,7 @@ class Hierarchy:
             elif op[0] == "fill":
                 _, lev, sub, s = op
                 L = self.levels[lev]
-                c = 1.0 if s == nstages else RK4_C[s]
+                c = 1.0 if s == nstages else self.cs[s]
                 self.fill(lev, L.U if s == nstages else L.X, (sub + c) / 2.0)
             else:
                 self.average_down(op[1])
@@ -323,10 +327,14 @@ class Hierarchy:
         L = self.levels[lev]
         eta_n = level_time(self.eta0, L.k, L.dt)
         X = L.U if s == 0 else L.X
+        last = len(self.cs) - 1
         with np.errstate(all="ignore"):
-            L.acc, Y = rk4_stage(s, X, L.U, L.acc if s else None, eta_n, L.dt,
-                                 1.0 / (L.dx * L.dx), self.alpha, self.lam, self.beta)
-        if s == 3:
+            if self.integrator == 4:
+                L.acc, Y = rk4_stage(s, X, L.U, L.acc if s else None, eta_n, L.dt,
+                                     1.0 / (L.dx * L.dx), self.alpha, self.lam, self.beta)
+            else:
+                Y = ssprk3_stage(s, X, L.U, eta_n, L.dt, 1.0 / (L.dx * L.dx), self.alpha, self.lam, self.beta)
+        if s == last:
             L.Uold, L.U, L.X, L.acc = L.U, Y, None, None
             L.k += 1
         else:
@@ -376,8 +384,12 @@ class Hierarchy:
         eta_n = level_time(self.eta0, S.k, S.dt)
         X, acc = S.U, None
         with np.errstate(all="ignore"):
-            for s in range(4):
-                acc, X = rk4_stage(s, X, S.U, acc, eta_n, S.dt, 1.0 / (S.dx * S.dx), self.alpha, self.lam, self.beta)
+            for s in range(len(self.cs)):
+                if self.integrator == 4:
+                    acc, X = rk4_stage(s, X, S.U, acc, eta_n, S.dt, 1.0 / (S.dx * S.dx), self.alpha, self.lam,
+                                       self.beta)
+                else:
+                    X = ssprk3_stage(s, X, S.U, eta_n, S.dt, 1.0 / (S.dx * S.dx), self.alpha, self.lam, self.beta)
         S.U = X
         S.k += 1
 

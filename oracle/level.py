@@ -22,6 +22,13 @@ and RK4 in accumulator form (U_n the state at the step start, h = dt):
 
 which is the textbook y + h/6 (k1 + 2 k2 + 2 k3 + k4) with the sum formed as it goes.
 
+SSPRK3 (integrator types 3 and 10, appendix E; the Shu-Osher form of the three-stage
+third-order strong-stability-preserving method, stage times eta_n + (0, 1, 1/2) h):
+
+    stage 1: U_a     = U_n + h f(U_n)
+    stage 2: U_b     = 3/4 U_n + 1/4 (U_a + h f(U_a))
+    stage 3: U_{n+1} = 1/3 U_n + 2/3 (U_b + h f(U_b))
+
 Mixed precision (FP32 storage): U_n, U_a, U_b are float32 and the right-hand side is
 evaluated in float32 (scalars rounded to float32 once); every update above is done in
 float64 from the promoted float32 values and rounded to float32 on store, while ``acc``
@@ -89,6 +96,34 @@ def rk4_stage(s: int, X: np.ndarray, Un: np.ndarray, acc, eta_n: float, dt: floa
     return acc, Y.astype(st)
 
 
+def ssprk3_stage(s: int, X: np.ndarray, Un: np.ndarray, eta_n: float, dt: float, inv_dx2: float,
+                 alpha: float, lam: float, beta: int) -> np.ndarray:
+    """Stage s (0-based) of SSPRK3: the next stage input (s < 2) or U_{n+1} (s = 2), in
+    the storage precision of Un; updates in float64 from promoted values."""
+    st = Un.dtype
+    _, cf, cp = stage_scalars(eta_n, dt, s, alpha, lam, beta, integrator=10)
+    k = rhs(X, inv_dx2, cf, cp).astype(np.float64)
+    U64 = Un.astype(np.float64)
+    if s == 0:
+        Y = U64 + dt * k
+    elif s == 1:
+        Y = 0.75 * U64 + 0.25 * (X.astype(np.float64) + dt * k)
+    else:
+        Y = (1.0 / 3.0) * U64 + (2.0 / 3.0) * (X.astype(np.float64) + dt * k)
+    return Y.astype(st)
+
+
+def ssprk3_step(U: np.ndarray, eta_n: float, dt: float, inv_dx2: float,
+                alpha: float, lam: float, beta: int, fill=None) -> np.ndarray:
+    """One SSPRK3 step; ``fill(s, X)`` as for ``rk4_step``."""
+    X = U
+    for s in range(3):
+        if s > 0 and fill is not None:
+            fill(s, X)
+        X = ssprk3_stage(s, X, U, eta_n, dt, inv_dx2, alpha, lam, beta)
+    return X
+
+
 def rk4_step(U: np.ndarray, eta_n: float, dt: float, inv_dx2: float,
              alpha: float, lam: float, beta: int, fill=None) -> np.ndarray:
     """One classic RK4 step of size dt from time eta_n; returns U_{n+1} (U's dtype).
@@ -107,16 +142,19 @@ def rk4_step(U: np.ndarray, eta_n: float, dt: float, inv_dx2: float,
 
 def run_single_level(U0: np.ndarray, nsteps: int, eta0: float, dt: float, dx: float,
                      alpha: float = 2.0, lam: float = 1.0, beta: int = 2,
-                     callback=None) -> np.ndarray:
-    """nsteps RK4 steps of a periodic lattice; step k starts at eta0 + k*dt.
+                     callback=None, integrator: int = 4) -> np.ndarray:
+    """nsteps steps (RK4, or SSPRK3 for integrator 3/10) of a periodic lattice; step k
+    starts at eta0 + k*dt.
 
     ``callback(k, U)`` is called after each step with the 1-based step count.
     """
-    from .scalars import level_time
+    from .scalars import level_time, stage_fractions
+    stage_fractions(integrator)  # validates
+    step = rk4_step if integrator == 4 else ssprk3_step
     inv_dx2 = 1.0 / (dx * dx)
     U = U0.copy()
     for k in range(nsteps):
-        U = rk4_step(U, level_time(eta0, k, dt), dt, inv_dx2, alpha, lam, beta)
+        U = step(U, level_time(eta0, k, dt), dt, inv_dx2, alpha, lam, beta)
         if callback is not None:
             callback(k + 1, U)
     return U

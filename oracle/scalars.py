@@ -4,7 +4,8 @@
 * The time of level l after k of its steps is eta0 + k * Delta t_l: one multiply and one
   add from integers, so levels that align in time hold bit-identical times.
 * Classic RK4 (integrator type 4) evaluates the right-hand side at eta_n + c_s dt with
-  c = (0, 1/2, 1/2, 1).
+  c = (0, 1/2, 1/2, 1); the three-stage SSPRK3 (integrator types 3 and 10, the latter
+  the same method stored in fewer buffers) at c = (0, 1, 1/2).
 * The EOM (eq. EOM2 with lambda and the friction/potential exponents exposed) is
       dPi_i/deta = lap psi_i - (alpha/eta) Pi_i - lambda eta^beta psi_i (|psi|^2 - 1)
   so each stage needs c_fric = alpha / eta_s and c_pot = lambda * eta_s^beta, the
@@ -13,6 +14,16 @@
 from __future__ import annotations
 
 RK4_C = (0.0, 0.5, 0.5, 1.0)
+SSP3_C = (0.0, 1.0, 0.5)
+
+
+def stage_fractions(integrator: int):
+    """c_s of the integrator: 4 = classic RK4, 3 or 10 = SSPRK3."""
+    if integrator == 4:
+        return RK4_C
+    if integrator in (3, 10):
+        return SSP3_C
+    raise ValueError(f"unknown integrator {integrator}")
 
 
 def level_dx(L: float, n0: int, lev: int) -> float:
@@ -35,9 +46,9 @@ def int_power(x: float, beta: int) -> float:
     return p
 
 
-def stage_scalars(eta_n: float, dt: float, s: int, alpha: float, lam: float, beta: int):
-    """(eta_s, c_fric, c_pot) for stage s in 0..3."""
-    eta_s = eta_n + RK4_C[s] * dt
+def stage_scalars(eta_n: float, dt: float, s: int, alpha: float, lam: float, beta: int, integrator: int = 4):
+    """(eta_s, c_fric, c_pot) for stage s of the integrator."""
+    eta_s = eta_n + stage_fractions(integrator)[s] * dt
     return eta_s, alpha / eta_s, lam * int_power(eta_s, beta)
 
 
