@@ -1,5 +1,5 @@
 #!/usr/bin/env python3
-"""Throughput of the per-level RK4 time step on one MI355X.
+"""Throughput of the per-level time step on one MI355X.
 
 Workload (default): one periodic level of 512^3 cells (L = 512, dx = 1), the axion-string
 EOM with lambda = 1, alpha = 2, beta = 2, classic RK4 with dt = dx/4 from eta = 0.1, the
@@ -7,7 +7,8 @@ seeded Gaussian-random-field initial state; FP64 (``--prec f64``) or FP32 storag
 FP64 accumulation (``--prec f32``).  A step is one sh_advance_level: by default one kernel
 that computes all four RK stages of the step, then one refill of the level's 4-deep
 periodic ghost shell (with ``SHAMR_TUNE=fuse=0``: four stage kernels with a ghost copy
-between them).
+between them).  ``--integrator 10`` (or 3) runs SSPRK3 instead: three stage kernels with a
+ghost copy between them (the fused step is RK4's).
 
 Prints one JSON line: cell-updates/s per RK stage (whole job), the roofline of the
 dominant kernel from HIP events recorded around each of its launches inside the timed
@@ -31,6 +32,8 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
 STAGE_BYTES = {"f64": (96, 160, 160, 96), "f32": (64, 112, 112, 64)}
 # the fused four-stage step reads U_n and writes U_{n+1}: 8 values per cell
 FUSED_BYTES = {"f64": 64, "f32": 32}
+# SSPRK3 stages 1-3: X in, Y out (8 values); X and U_n in, Y out (12 values) twice
+SSP_STAGE_BYTES = {"f64": (64, 96, 96), "f32": (32, 48, 48)}
 
 
 def log(msg):
@@ -50,15 +53,16 @@ def traffic_from_profiles(prec: str, n: int, kname: str):
     return rec.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(U0, n: int):
-    """One full RK4 step (four stages) of the oracle on the whole lattice, timed on this
-    host (numpy, one core; about 20 s at 512^3)."""
-    from oracle.level import rk4_step
+def cpu_baseline(U0, n: int, integrator: int = 4):
+    """One full step of the oracle on the whole lattice, timed on this host (numpy, one
+    core; about 20 s at 512^3 for RK4)."""
+    from oracle.level import rk4_step, ssprk3_step
+    nst, step, name = (4, rk4_step, "RK4") if integrator == 4 else (3, ssprk3_step, "SSPRK3")
     t0 = time.perf_counter()
-    rk4_step(U0, 0.1, 0.25, 1.0, 2.0, 1.0, 2)
+    step(U0, 0.1, 0.25, 1.0, 2.0, 1.0, 2)
     dt = time.perf_counter() - t0
-    return {"value": 4 * n ** 3 / dt, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"one RK4 step (4 stages) of the {n}^3 FP64 lattice, numpy oracle, "
+    return {"value": nst * n ** 3 / dt, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"one {name} step ({nst} stages) of the {n}^3 FP64 lattice, numpy oracle, "
                       f"{dt:.1f} s on one host core"}
 
 
@@ -77,6 +81,8 @@ def main():
                     help="single: the 512^3 level step (default); amr256: 256^3 + 3 levels, 8 string loops, "
                          "50 coarse steps; amr512: 512^3 + 2 levels, 16 loops, FP64 vs FP32, 20 coarse steps; "
                          "serve: 256 Poisson-arriving ensemble jobs")
+    ap.add_argument("--integrator", type=int, default=4, choices=(3, 4, 10),
+                    help="4: classic RK4 (default); 3 or 10: SSPRK3")
     ap.add_argument("--beta", type=int, default=2, help="potential exponent (2: the paper's EOM; 0: stable companion)")
     ap.add_argument("--coarse-steps", type=int, default=None)
     ap.add_argument("--tag-mode", type=int, default=1, choices=(1, 2, 3),
@@ -109,7 +115,9 @@ def main():
     U0 = random_state(n, float(n), args.seed)
     prec = shamr.SH_F64 if args.prec == "f64" else shamr.SH_F32
     stream = torch.cuda.Stream()
-    h = shamr.Hierarchy(n, float(n), 0.25, 0.1, 1.0, 2.0, 2, max_level=0, prec=prec, stream=stream)
+    h = shamr.Hierarchy(n, float(n), 0.25, 0.1, 1.0, 2.0, 2, max_level=0, prec=prec, stream=stream,
+                        integrator=args.integrator)
+    nst = 4 if args.integrator == 4 else 3
     h.set_layout(0, [(0, 0, 0, n - 1, n - 1, n - 1)])
     h.write_dense(0, U0)
     h.fill_ghosts(0)
@@ -150,18 +158,18 @@ def main():
     h.profile(False)
     e, bad = h.energy()
     cells = n ** 3
-    value = cells * 4 * K / (ms / 1e3)
-    sb = STAGE_BYTES[args.prec]
+    value = cells * nst * K / (ms / 1e3)
+    sb = STAGE_BYTES[args.prec] if nst == 4 else SSP_STAGE_BYTES[args.prec]
     roofline = None
     if prof["fused_step"][1]:
         kname = "fused_rk4_step"
         k_ms, k_n = prof["fused_step"]
         k_bytes = FUSED_BYTES[args.prec] * cells * k_n
     else:
-        kname = "rk4_stage"
-        k_ms = sum(prof[f"stage{s + 1}"][0] for s in range(4))
-        k_n = sum(prof[f"stage{s + 1}"][1] for s in range(4))
-        k_bytes = sum(sb[s] * cells * prof[f"stage{s + 1}"][1] for s in range(4))
+        kname = "rk4_stage" if nst == 4 else "ssprk3_stage"
+        k_ms = sum(prof[f"stage{s + 1}"][0] for s in range(nst))
+        k_n = sum(prof[f"stage{s + 1}"][1] for s in range(nst))
+        k_bytes = sum(sb[s] * cells * prof[f"stage{s + 1}"][1] for s in range(nst))
     if k_n:  # (not collected for graph replays)
         achieved = k_bytes / (k_ms / 1e3) / 1e9
         roofline = {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -182,23 +190,24 @@ def main():
         "vs_baseline": None,
         "dtype": args.prec,
         "data": "synthetic",
-        "config": {"workload": f"single-level periodic {n}^3, RK4 + 7-point Laplacian, "
+        "config": {"workload": f"single-level periodic {n}^3, {'RK4' if nst == 4 else 'SSPRK3'} + 7-point Laplacian, "
                                f"{'FP64' if args.prec == 'f64' else 'FP32 storage / FP64 accumulation'}",
                    "lattice": n, "dx": 1.0, "dt": 0.25, "eta0": 0.1, "lambda": 1.0, "seed": args.seed,
-                   "graph_steps": G if graph is not None else None},
+                   "integrator": args.integrator, "graph_steps": G if graph is not None else None},
         "roofline": roofline,
         # the same cell-update rate priced at the bytes a one-stage-per-pass kernel must
-        # move (mean over the four stages), against the same peak
-        "per_stage_equivalent": {"bytes_per_cell_stage": sum(sb) / 4,
-                                 "achieved": value * sum(sb) / 4 / 1e9, "peak": HBM_PEAK_GBS,
-                                 "frac": value * sum(sb) / 4 / 1e9 / HBM_PEAK_GBS},
+        # move (mean over the stages), against the same peak
+        "per_stage_equivalent": {"bytes_per_cell_stage": sum(sb) / nst,
+                                 "achieved": value * sum(sb) / nst / 1e9, "peak": HBM_PEAK_GBS,
+                                 "frac": value * sum(sb) / nst / 1e9 / HBM_PEAK_GBS},
+        "cell_steps_per_s": value / nst,
         "kernel_ms": {k: (v[0] / v[1] if v[1] else None) for k, v in prof.items() if v[1]},
         "wall_ms_per_step": wall / K * 1e3,
         "nonfinite_cells_at_end": bad,
     }
     if not args.no_cpu_baseline and args.prec == "f64":
         log("cpu baseline (oracle, one full step)")
-        out["cpu_baseline"] = cpu_baseline(U0, n)
+        out["cpu_baseline"] = cpu_baseline(U0, n, args.integrator)
     else:
         out["cpu_baseline"] = None
     if graph is not None:
@@ -236,12 +245,13 @@ def bench_amr(args):
            "config": {"workload": f"AMR {n0}^3 + {levels} levels, {loops} string loops R in [20, 60], "
                                   f"blocking factor 8, max box 64, tag buffer 2, regrid every 2 coarse steps, "
                                   f"{steps} coarse steps, beta = {args.beta}"
-                                  + (f", tag mode {args.tag_mode}, te_crit {args.te_crit}" if args.tag_mode != 1 else ""),
+                                  + (f", tag mode {args.tag_mode}, te_crit {args.te_crit}" if args.tag_mode != 1 else "")
+                                  + (", SSPRK3" if args.integrator != 4 else ""),
                       "seed": args.seed}}
     if args.workload == "amr256":
         prec = shamr.SH_F64 if args.prec == "f64" else shamr.SH_F32
         h, rep = workloads.run_amr(U0, levels, steps, prec=prec, beta=args.beta, log=log, tag_mode=args.tag_mode,
-                                   te_crit=args.te_crit)
+                                   te_crit=args.te_crit, integrator=args.integrator)
         h.close()
         out.update({"value": rep["cell_updates_per_s_end_to_end"], "dtype": args.prec, "report": rep})
     else:

@@ -77,6 +77,10 @@ typedef struct {
   int32_t n_error_buf;  /* tag buffer width in cells (amr.n_error_buf) */
   int32_t prec;         /* sh_prec: SH_F64, or SH_F32 = float32 storage and stencil,
                            float64 time, accumulator and reductions */
+  int32_t integrator;   /* integrator.type of appendix E: 4 (or 0) = classic RK4;
+                           3 or 10 = SSPRK3, the three-stage strong-stability-preserving
+                           method (both run its Shu-Osher form in three state buffers and
+                           no accumulator, so sh_arena_bytes is smaller) */
 } sh_params;
 
 /* Device bytes needed for the arena of a level with the given boxes.  Returns 0 for
@@ -85,8 +89,8 @@ size_t sh_arena_bytes(const sh_params* p, int32_t lev, int32_t nboxes, const int
 
 /* Create a hierarchy.  `hip_stream` is a hipStream_t (NULL = default stream) that all
    device work of this hierarchy is queued on.  Errors: SH_EINVAL (n0 < 1, L or cfl not
-   positive, beta < 0, max_level < 0 or > 15, blocking_factor < 2, prec not 0/1),
-   SH_EDEVICE (no HIP device). */
+   positive, beta < 0, max_level < 0 or > 15, blocking_factor < 2, prec not 0/1,
+   integrator not 0, 3, 4 or 10), SH_EDEVICE (no HIP device). */
 sh_status sh_hierarchy_create(const sh_params* p, void* hip_stream, sh_hierarchy* out);
 
 /* Set, change or remove the box layout of level `lev` (section II: boxes whose sides
@@ -124,10 +128,11 @@ sh_status sh_read_state(sh_hierarchy h, int32_t lev, int32_t role, double* dst, 
    linear in time with alpha = alpha_num / 4 in [0, 4]. */
 sh_status sh_fill_ghosts(sh_hierarchy h, int32_t lev, int32_t role, int32_t alpha_num);
 
-/* One RK4 step of level `lev` by dt_lev (section II.A, Fig. 2): stage 1, then ghost fill
-   and stage for stages 2-4 (alpha = (substep + c_s)/2), then the same-level ghost copy of
-   the new state and, for lev >= 1 and substep == 0, its coarse/fine ghost fill at
-   alpha = 1/2 (a substep-1 step ends in the synchronisation, sh_average_down).
+/* One integrator step of level `lev` by dt_lev (section II.A, Fig. 2): stage 1, then
+   ghost fill and stage for the remaining stages (alpha = (substep + c_s)/2 with
+   c = (0, 1/2, 1/2, 1) for RK4 and (0, 1, 1/2) for SSPRK3), then the same-level ghost
+   copy of the new state and, for lev >= 1 and substep == 0, its coarse/fine ghost fill
+   at alpha = 1/2 (a substep-1 step ends in the synchronisation, sh_average_down).
    `substep` in {0, 1} is which half of the parent's step this is (ignored for lev 0).
    Does not recurse into finer levels: the caller composes the subcycling order. */
 sh_status sh_advance_level(sh_hierarchy h, int32_t lev, int32_t substep);
@@ -188,8 +193,9 @@ sh_status sh_hierarchy_destroy(sh_hierarchy h);
 
 const char* sh_last_error(void);
 
-/* Stage scalars the device derives for `lev` at stage s (0..3) of the current step:
-   out[0..6] = {eta_s, c_fric, c_pot, dt/6, dt/3, dt/2, dt}.  Diagnostic. */
+/* Stage scalars the device derives for `lev` at stage s (0..3 for RK4, 0..2 for SSPRK3)
+   of the current step: out[0..6] = {eta_s, c_fric, c_pot, dt/6, dt/3, dt/2, dt}.
+   Diagnostic. */
 sh_status sh_debug_stage_scalars(sh_hierarchy h, int32_t lev, int32_t s, double* out_host);
 
 /* Launch shape (performance only; results are identical for every choice).
@@ -200,7 +206,7 @@ sh_status sh_debug_stage_scalars(sh_hierarchy h, int32_t lev, int32_t s, double*
    tile_z: cells per per-stage tile in z (0 = from the level size).
    fuse: 4 = level 0 (which has no coarse/fine boundary) takes each step in one kernel
      computing all four RK stages (temporal blocking; needs every level-0 box to be a
-     multiple of the fused footprint, else per-stage); 0 = per-stage kernels.
+     multiple of the fused footprint, else per-stage; RK4 only); 0 = per-stage kernels.
    fused_shape: footprint 0 = 32 x 8, 1 = 64 x 4, 2 = 32 x 16, 3 = 16 x 8.
    fused_tile_z: planes per fused tile; 0 = 512, halved while that gives fewer than 1024
      tiles, down to 16 (a batch decides once for all its members).
@@ -234,7 +240,7 @@ sh_status sh_profile_read(sh_hierarchy h, double* ms, int64_t* counts);
    member's result is bit-identical to stepping it alone (kernels are gather-only per
    box).  Members must not be re-laid out or destroyed while the batch exists; the batch
    borrows them.  Errors: SH_EINVAL (a member with more than one level, another
-   precision or stream), SH_ESTATE from sh_batch_advance if a member's layout changed
+   precision or stream, or an integrator other than RK4), SH_ESTATE from sh_batch_advance if a member's layout changed
    since the batch was built. */
 sh_status sh_batch_create(int32_t njobs, const sh_hierarchy* jobs, sh_batch* out);
 sh_status sh_batch_advance(sh_batch b);

@@ -21,6 +21,11 @@
 //   stage 2: acc = acc + h/3 k;   B = U_n + h/2 k
 //   stage 3: acc = acc + h/3 k;   A = U_n + h k
 //   stage 4: B = acc + h/6 k      (the new U_n)
+// SSPRK3 (stage ids 4..6; appendix E's three-stage strong-stability-preserving method
+// in Shu-Osher form):
+//   stage 1: A = U_n + h k
+//   stage 2: B = 3/4 U_n + 1/4 (A + h k)
+//   stage 3: A = 1/3 U_n + 2/3 (B + h k)   (the new U_n)
 // The right-hand side is evaluated in T; updates in float64, rounded to T on store.
 // NT = 1 marks the streams read or written once (Pi, U_n, acc, the stage output) as
 // nontemporal so they do not push the psi planes, which neighbours re-read, out of L2.
@@ -33,13 +38,13 @@ struct StagePtrs {
 };
 
 template <typename T, int S>
-__device__ __forceinline__ StagePtrs stage_ptrs(const BoxDev& B, long long k) {
-  constexpr int in_role = (S == 0) ? ROLE_UN : (S == 2 ? ROLE_B : ROLE_A);
-  constexpr int out_role = (S == 0 || S == 2) ? ROLE_A : ROLE_B;
+__device__ __forceinline__ StagePtrs stage_ptrs(const BoxDev& B, const LevelScal& L) {
+  constexpr int in_role = (S == 0 || S == 4) ? ROLE_UN : ((S == 2 || S == 6) ? ROLE_B : ROLE_A);
+  constexpr int out_role = (S == 1 || S == 3 || S == 5) ? ROLE_B : ROLE_A;
   StagePtrs p;
-  p.X = slot_base(B, role_slot(in_role, k));
-  p.Un = slot_base(B, role_slot(ROLE_UN, k));
-  p.Y = slot_base(B, role_slot(out_role, k));
+  p.X = slot_base(B, role_slot(in_role, L));
+  p.Un = slot_base(B, role_slot(ROLE_UN, L));
+  p.Y = slot_base(B, role_slot(out_role, L));
   p.acc = B.acc;
   return p;
 }
@@ -67,20 +72,27 @@ __device__ __forceinline__ void stage_cell(const StageScal& sc, const T* __restr
     } else if constexpr (S == 1 || S == 2) {
       st<NT>(acc + ec, acc4[c] + sc.h3 * k4[c]);
       st<NT>(Y + ec, (T)(un4[c] + (S == 1 ? sc.h2 : sc.h1) * k4[c]));
-    } else {
+    } else if constexpr (S == 3) {
       st<NT>(Y + ec, (T)(acc4[c] + sc.h6 * k4[c]));
+    } else if constexpr (S == 4) {
+      st<NT>(Y + ec, (T)((double)xv[c] + sc.h1 * k4[c]));
+    } else if constexpr (S == 5) {
+      st<NT>(Y + ec, (T)(0.75 * un4[c] + 0.25 * ((double)xv[c] + sc.h1 * k4[c])));
+    } else {
+      st<NT>(Y + ec, (T)((1.0 / 3.0) * un4[c] + (2.0 / 3.0) * ((double)xv[c] + sc.h1 * k4[c])));
     }
   }
 }
 
-// Loads of the once-read streams of a cell: U_n (stages 2, 3) and acc (stages 2-4).
+// Loads of the once-read streams of a cell: U_n (RK4 stages 2, 3; SSPRK3 stages 2, 3)
+// and acc (RK4 stages 2-4).
 template <typename T, int S, bool NT>
 __device__ __forceinline__ void stage_loads(const T* __restrict__ Un, const double* __restrict__ acc, long long cs,
                                             long long e, double* un4, double* acc4) {
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
-    if constexpr (S == 1 || S == 2) un4[c] = (double)ld<NT>(Un + c * cs + e);
-    if constexpr (S != 0) acc4[c] = ld<NT>(acc + c * cs + e);
+    if constexpr (S == 1 || S == 2 || S == 5 || S == 6) un4[c] = (double)ld<NT>(Un + c * cs + e);
+    if constexpr (S >= 1 && S <= 3) acc4[c] = ld<NT>(acc + c * cs + e);
   }
 }
 
@@ -98,7 +110,7 @@ __global__ __launch_bounds__(SH_BLOCK) void k_stage(const Tile* __restrict__ til
   const BoxDev B = boxes[tl.box];
   const LevelScal L = *B.ls;
   const StageScal sc = stage_scalars(L, S);
-  const StagePtrs P = stage_ptrs<T, S>(B, L.k);
+  const StagePtrs P = stage_ptrs<T, S>(B, L);
   const T* __restrict__ X = (const T*)P.X;
   const T* __restrict__ Un = (const T*)P.Un;
   T* __restrict__ Y = (T*)P.Y;
@@ -155,7 +167,7 @@ __global__ __launch_bounds__(SH_WAVE * R) void k_stage_lds(const Tile* __restric
   const BoxDev B = boxes[tl.box];
   const LevelScal L = *B.ls;
   const StageScal sc = stage_scalars(L, S);
-  const StagePtrs P = stage_ptrs<T, S>(B, L.k);
+  const StagePtrs P = stage_ptrs<T, S>(B, L);
   const T* __restrict__ X = (const T*)P.X;
   const T* __restrict__ Un = (const T*)P.Un;
   T* __restrict__ Y = (T*)P.Y;
@@ -237,7 +249,7 @@ __global__ __launch_bounds__(SH_BLOCK) void k_rhs(const Tile* __restrict__ tiles
   const BoxDev B = boxes[tl.box];
   const LevelScal L = *B.ls;
   const StageScal sc = stage_scalars(L, 0);
-  const T* __restrict__ X = (const T*)slot_base(B, role_slot(ROLE_UN, L.k));
+  const T* __restrict__ X = (const T*)slot_base(B, role_slot(ROLE_UN, L));
   const int tx = lane & ((1 << tl.txs) - 1), ty = lane >> tl.txs;
   const int x = (tl.xy & 0xffff) + tx, y = (tl.xy >> 16) + ty;
   if (x >= B.nx || y >= B.ny) return;
@@ -292,9 +304,9 @@ __global__ __launch_bounds__(SH_BLOCK) void k_ghost_copy(const CopySeg* __restri
   const int k = r / s.n[1];
   const BoxDev& D = boxes[s.dbox];
   const BoxDev& Sb = boxes[s.sbox];
-  const long long kk = D.ls->k;
-  T* dst = (T*)D.slot[role_slot(role, kk)];
-  const T* src = (const T*)Sb.slot[role_slot(role, kk)];
+  const int sl = role_slot(role, *D.ls);
+  T* dst = (T*)D.slot[sl];
+  const T* src = (const T*)Sb.slot[sl];
   const long long ed = elem<T>(D, s.dlo[0] + i, s.dlo[1] + j, s.dlo[2] + k);
   const long long es = elem<T>(Sb, s.slo[0] + i, s.slo[1] + j, s.slo[2] + k);
   for (int comp = 0; comp < ncomp; ++comp) dst[comp * D.cs + ed] = src[comp * Sb.cs + es];
@@ -346,10 +358,10 @@ __global__ __launch_bounds__(SH_BLOCK) void k_ghost_interp(const InterpSeg* __re
   const int k = r / s.n[1];
   const BoxDev& F = fboxes[s.fbox];
   const BoxDev& C = cboxes[s.cbox];
-  const long long kc = C.ls->k, kf = F.ls->k;
-  const T* Cnew = (const T*)C.slot[role_slot(ROLE_UN, kc)];
-  const T* Cold = (const T*)C.slot[role_slot(ROLE_OLD, kc)];
-  T* dst = (T*)F.slot[role_slot(role, kf)];
+  const LevelScal& LC = *C.ls;
+  const T* Cnew = (const T*)C.slot[role_slot(ROLE_UN, LC)];
+  const T* Cold = (const T*)C.slot[role_slot(ROLE_OLD, LC)];
+  T* dst = (T*)F.slot[role_slot(role, *F.ls)];
   const int fx = s.fg0[0] + i, fy = s.fg0[1] + j, fz = s.fg0[2] + k;
   const int ci = (fx >> 1) + s.cshift[0], cj = (fy >> 1) + s.cshift[1], ck = (fz >> 1) + s.cshift[2];
   const long long ed = elem<T>(F, s.flo[0] + i, s.flo[1] + j, s.flo[2] + k);
@@ -383,8 +395,8 @@ __global__ __launch_bounds__(SH_BLOCK) void k_avgdown(const AvgSeg* __restrict__
   const int k = r / s.n[1];
   const BoxDev& C = cboxes[s.cbox];
   const BoxDev& F = fboxes[s.fbox];
-  T* dst = (T*)slot_base(C, role_slot(ROLE_UN, C.ls->k));
-  const T* src = (const T*)slot_base(F, role_slot(ROLE_UN, F.ls->k));
+  T* dst = (T*)slot_base(C, role_slot(ROLE_UN, *C.ls));
+  const T* src = (const T*)slot_base(F, role_slot(ROLE_UN, *F.ls));
   const long long ec = elem<T>(C, s.clo[0] + i, s.clo[1] + j, s.clo[2] + k);
   const long long ef = elem<T>(F, s.f0[0] + 2 * i, s.f0[1] + 2 * j, s.f0[2] + 2 * k);
   const long long px = F.px, plane = px * F.py;
@@ -429,8 +441,8 @@ __global__ __launch_bounds__(SH_BLOCK) void k_regrid_copy(const CopySeg* __restr
   const int k = r / s.n[1];
   const BoxDev& D = dboxes[s.dbox];
   const BoxDev& Sb = sboxes[s.sbox];
-  T* dst = (T*)D.slot[role_slot(ROLE_UN, D.ls->k)];
-  const T* src = (const T*)Sb.slot[role_slot(ROLE_UN, Sb.ls->k)];
+  T* dst = (T*)D.slot[role_slot(ROLE_UN, *D.ls)];
+  const T* src = (const T*)Sb.slot[role_slot(ROLE_UN, *Sb.ls)];
   const long long ed = elem<T>(D, s.dlo[0] + i, s.dlo[1] + j, s.dlo[2] + k);
   const long long es = elem<T>(Sb, s.slo[0] + i, s.slo[1] + j, s.slo[2] + k);
   for (int comp = 0; comp < 4; ++comp) dst[comp * D.cs + ed] = src[comp * Sb.cs + es];
@@ -476,7 +488,7 @@ __global__ __launch_bounds__(SH_BLOCK) void k_tag(const Tile* __restrict__ tiles
     return;
   }
   const BoxDev B = boxes[tl.box];
-  const T* __restrict__ U = (const T*)slot_base(B, role_slot(ROLE_UN, B.ls->k));
+  const T* __restrict__ U = (const T*)slot_base(B, role_slot(ROLE_UN, *B.ls));
   const int tx = lane & ((1 << tl.txs) - 1), ty = lane >> tl.txs;
   int x = (tl.xy & 0xffff) + tx, y = (tl.xy >> 16) + ty;
   const bool active = (x < B.nx) && (y < B.ny);
@@ -627,7 +639,7 @@ __global__ __launch_bounds__(SH_BLOCK) void k_energy(const Tile* __restrict__ ti
     const BoxDev B = boxes[tl.box];
     const LevelScal L = *B.ls;
     const double cp = L.lam * ipow(level_time(L), L.beta);
-    const T* __restrict__ U = (const T*)slot_base(B, role_slot(ROLE_UN, L.k));
+    const T* __restrict__ U = (const T*)slot_base(B, role_slot(ROLE_UN, L));
     const int tx = lane & ((1 << tl.txs) - 1), ty = lane >> tl.txs;
     const int x = (tl.xy & 0xffff) + tx, y = (tl.xy >> 16) + ty;
     if (x < B.nx && y < B.ny) {
@@ -739,7 +751,7 @@ __global__ __launch_bounds__(SH_BLOCK) void k_xfer(const BoxDev* __restrict__ bo
   const int i = (int)(r % ex) - g;
   const int j = (int)((r / ex) % ey) - g;
   const int k = (int)(r / ((long long)ex * ey)) - g;
-  T* S = (T*)slot_base(B, role_slot(role, B.ls->k));
+  T* S = (T*)slot_base(B, role_slot(role, *B.ls));
   const long long e = comp * B.cs + elem<T>(B, i, j, k);
   if (TO_BOX) S[e] = (T)stage[gid];
   else stage[gid] = (double)S[e];
@@ -769,7 +781,10 @@ static void stage_launch2(int s, int kind, const Tile* tiles, int ntiles, const 
     case 0: stage_launch3<T, 0, NT>(kind, tiles, ntiles, boxes, st); break;
     case 1: stage_launch3<T, 1, NT>(kind, tiles, ntiles, boxes, st); break;
     case 2: stage_launch3<T, 2, NT>(kind, tiles, ntiles, boxes, st); break;
-    default: stage_launch3<T, 3, NT>(kind, tiles, ntiles, boxes, st); break;
+    case 3: stage_launch3<T, 3, NT>(kind, tiles, ntiles, boxes, st); break;
+    case 4: stage_launch3<T, 4, NT>(kind, tiles, ntiles, boxes, st); break;
+    case 5: stage_launch3<T, 5, NT>(kind, tiles, ntiles, boxes, st); break;
+    default: stage_launch3<T, 6, NT>(kind, tiles, ntiles, boxes, st); break;
   }
 }
 
@@ -904,8 +919,7 @@ void sh_launch_xfer(int prec, bool to_box, const BoxDev* boxes, const long long*
 __global__ void k_debug_scalars(const LevelScal* ls, int s, double* out) {
   const LevelScal L = *ls;
   const StageScal sc = stage_scalars(L, s);
-  const double c = (s == 0) ? 0.0 : (s == 3 ? 1.0 : 0.5);
-  out[0] = level_time(L) + c * L.dt;
+  out[0] = level_time(L) + stage_frac(s) * L.dt;
   out[1] = sc.cf;
   out[2] = sc.cp;
   out[3] = sc.h6;

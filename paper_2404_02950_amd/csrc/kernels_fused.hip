@@ -119,8 +119,9 @@ __global__ __launch_bounds__((FusedShape<T, TX, TY>::NBLK)) void k_fused_rk4(con
   StageScal sc[FD];
 #pragma unroll
   for (int j = 0; j < FD; ++j) sc[j] = uniform(stage_scalars(L, j));
-  const T* __restrict__ X = (const T*)slot_base(B, role_slot(ROLE_UN, L.k));
-  T* __restrict__ Y = (T*)slot_base(B, role_slot(ROLE_B, L.k));
+  // the fused step is classic RK4's (four stages), whose roles follow the parity of k
+  const T* __restrict__ X = (const T*)slot_base(B, role_slot(ROLE_UN, L.k, 4));
+  T* __restrict__ Y = (T*)slot_base(B, role_slot(ROLE_B, L.k, 4));
 
   const int tid = threadIdx.x;
   const int lane = tid & (SH_WAVE - 1);

@@ -114,7 +114,12 @@ static int tile_zc_default(long long cells) {
   return (int)zc;
 }
 
-static void make_geom(int prec, int ng, const std::vector<IBox>& boxes, LayoutGeom& g) {
+// Stages per step of the integrator: 4 for classic RK4 (types 0 and 4), 3 for SSPRK3
+// (types 3 and 10).  SSPRK3 keeps no accumulator, so its levels store three states per
+// cell instead of three plus a float64 accumulator.
+static int stages_of(const sh_params& p) { return (p.integrator == 3 || p.integrator == 10) ? 3 : 4; }
+
+static void make_geom(int prec, int ng, const std::vector<IBox>& boxes, LayoutGeom& g, bool acc) {
   g.ng = ng;
   g.esize = prec == SH_F64 ? 8 : 4;
   g.xoff = 64 / g.esize;
@@ -160,7 +165,7 @@ static void make_geom(int prec, int ng, const std::vector<IBox>& boxes, LayoutGe
     return r;
   };
   for (int s = 0; s < 3; ++s) g.off_slot[s] = take((size_t)g.E * g.esize);
-  g.off_acc = take((size_t)g.E * 8);
+  g.off_acc = acc ? take((size_t)g.E * 8) : 0;
   g.off_mask = take((size_t)g.nvalid);
   g.off_cov = take((size_t)g.nvalid);
   g.off_cnt = take((size_t)nt * 4);
@@ -478,7 +483,7 @@ static LevelScal make_ls(const sh_params& p, int l, long long k) {
   s.lam = p.lambda;
   s.inv_dx2 = 1.0 / (s.dx * s.dx);
   s.beta = p.beta_pot;
-  s.pad = 0;
+  s.nst = stages_of(p);
   s.k = k;
   return s;
 }
@@ -740,6 +745,8 @@ static sh_status check_params(const sh_params* p) {
       p->blocking_factor < 2 || (p->blocking_factor & 1) || p->max_box < p->blocking_factor || p->n_error_buf < 0 ||
       (p->prec != SH_F64 && p->prec != SH_F32))
     return fail(SH_EINVAL, "invalid parameters");
+  if (p->integrator != 0 && p->integrator != 3 && p->integrator != 4 && p->integrator != 10)
+    return fail(SH_EINVAL, "integrator must be 0 or 4 (RK4) or 3 or 10 (SSPRK3)");
   if ((long long)p->n0 << p->max_level > 32767) return fail(SH_EINVAL, "finest level too large");
   return SH_OK;
 }
@@ -749,7 +756,7 @@ size_t sh_arena_bytes(const sh_params* p, int32_t lev, int32_t nboxes, const int
   std::vector<IBox> b;
   if (parse_boxes(*p, lev, nboxes, boxes, b) != SH_OK) return 0;
   LayoutGeom g;
-  make_geom(p->prec, lev == 0 ? SH_NG0 : 1, b, g);
+  make_geom(p->prec, lev == 0 ? SH_NG0 : 1, b, g, stages_of(*p) == 4);
   return g.total;
 }
 
@@ -803,7 +810,7 @@ static sh_status set_box_tables(sh_hierarchy h, LevelScal* ls, Level& L) {
     const IBox& b = L.boxes[i];
     BoxDev d;
     for (int s = 0; s < 3; ++s) d.slot[s] = L.base + L.g.off_slot[s] + (size_t)L.g.box_off[i] * L.g.esize;
-    d.acc = (double*)(L.base + L.g.off_acc) + L.g.box_off[i];
+    d.acc = stages_of(h->p) == 4 ? (double*)(L.base + L.g.off_acc) + L.g.box_off[i] : nullptr;
     d.ls = ls;
     d.cs = L.g.cs[i];
     d.nx = b.size(0);
@@ -829,7 +836,7 @@ static sh_status set_box_tables(sh_hierarchy h, LevelScal* ls, Level& L) {
     make_stage_tiles(L.boxes, h->tune, L.g.nvalid, wt, bt);
     HIPCHK(L.stiles_w.upload(wt));
     HIPCHK(L.stiles_b.upload(bt));
-    make_fused_tiles(L.boxes, h->tune, L.g.ng, ft);
+    if (stages_of(h->p) == 4) make_fused_tiles(L.boxes, h->tune, L.g.ng, ft);  // the fused step is RK4's
     HIPCHK(L.ftiles.upload(ft));
   }
   HIPCHK(L.xoff_valid.upload(xv));
@@ -865,7 +872,7 @@ sh_status sh_set_level_layout(sh_hierarchy h, int32_t l, int32_t nboxes, const i
     for (auto& b : N.boxes) v += b.volume();
     if (v != (long long)N.M * N.M * N.M) return fail(SH_EINVAL, "level 0 boxes must cover the domain");
   }
-  make_geom(p.prec, l == 0 ? SH_NG0 : 1, N.boxes, N.g);
+  make_geom(p.prec, l == 0 ? SH_NG0 : 1, N.boxes, N.g, stages_of(p) == 4);
   if (!arena || arena_bytes < N.g.total) return fail(SH_ENOMEM, "arena smaller than sh_arena_bytes");
   N.base = (char*)round_up((long long)(uintptr_t)arena, 256);
   N.bins.build(N.boxes, N.M);
@@ -1044,31 +1051,52 @@ sh_status sh_advance_level(sh_hierarchy h, int32_t l, int32_t sub) {
     L.k += 1;
     return same_level_fill(h, l, ROLE_UN);
   }
-  // stage 1 reads U_n (ghosts set by the previous step end or synchronisation)
-  h->rec(1, l, 0, sub);
-  ev = h->prof_begin();
-  stage(h, L, 0);
-  h->prof_end(ev, 0);
-  LAUNCHCHK();
-  // alpha in quarters: (sub + c_s)/2 * 4 = 2 sub + 2 c_s
-  if ((s = fill(h, l, ROLE_A, 2 * sub + 1)) != SH_OK) return s;
-  h->rec(1, l, 1, sub);
-  ev = h->prof_begin();
-  stage(h, L, 1);
-  h->prof_end(ev, 1);
-  LAUNCHCHK();
-  if ((s = fill(h, l, ROLE_B, 2 * sub + 1)) != SH_OK) return s;
-  h->rec(1, l, 2, sub);
-  ev = h->prof_begin();
-  stage(h, L, 2);
-  h->prof_end(ev, 2);
-  LAUNCHCHK();
-  if ((s = fill(h, l, ROLE_A, 2 * sub + 2)) != SH_OK) return s;
-  h->rec(1, l, 3, sub);
-  ev = h->prof_begin();
-  stage(h, L, 3);
-  h->prof_end(ev, 3);
-  LAUNCHCHK();
+  if (stages_of(h->p) == 3) {
+    // SSPRK3: stage inputs at c = 1 (A) and c = 1/2 (B); alpha in quarters 2 sub + 2 c_s
+    h->rec(1, l, 0, sub);
+    ev = h->prof_begin();
+    stage(h, L, 4);
+    h->prof_end(ev, 0);
+    LAUNCHCHK();
+    if ((s = fill(h, l, ROLE_A, 2 * sub + 2)) != SH_OK) return s;
+    h->rec(1, l, 1, sub);
+    ev = h->prof_begin();
+    stage(h, L, 5);
+    h->prof_end(ev, 1);
+    LAUNCHCHK();
+    if ((s = fill(h, l, ROLE_B, 2 * sub + 1)) != SH_OK) return s;
+    h->rec(1, l, 2, sub);
+    ev = h->prof_begin();
+    stage(h, L, 6);
+    h->prof_end(ev, 2);
+    LAUNCHCHK();
+  } else {
+    // stage 1 reads U_n (ghosts set by the previous step end or synchronisation)
+    h->rec(1, l, 0, sub);
+    ev = h->prof_begin();
+    stage(h, L, 0);
+    h->prof_end(ev, 0);
+    LAUNCHCHK();
+    // alpha in quarters: (sub + c_s)/2 * 4 = 2 sub + 2 c_s
+    if ((s = fill(h, l, ROLE_A, 2 * sub + 1)) != SH_OK) return s;
+    h->rec(1, l, 1, sub);
+    ev = h->prof_begin();
+    stage(h, L, 1);
+    h->prof_end(ev, 1);
+    LAUNCHCHK();
+    if ((s = fill(h, l, ROLE_B, 2 * sub + 1)) != SH_OK) return s;
+    h->rec(1, l, 2, sub);
+    ev = h->prof_begin();
+    stage(h, L, 2);
+    h->prof_end(ev, 2);
+    LAUNCHCHK();
+    if ((s = fill(h, l, ROLE_A, 2 * sub + 2)) != SH_OK) return s;
+    h->rec(1, l, 3, sub);
+    ev = h->prof_begin();
+    stage(h, L, 3);
+    h->prof_end(ev, 3);
+    LAUNCHCHK();
+  }
   sh_launch_counter_inc(h->d_ls + l, 1, h->st);
   LAUNCHCHK();
   L.k += 1;
@@ -1137,7 +1165,7 @@ sh_status sh_shadow_begin(sh_hierarchy h) {
   S.dx = level_dx(p, 0) * 2.0;
   S.dt = p.cfl * S.dx;
   S.boxes = {IBox{{0, 0, 0}, {S.M - 1, S.M - 1, S.M - 1}}};
-  make_geom(p.prec, 1, S.boxes, S.g);
+  make_geom(p.prec, 1, S.boxes, S.g, stages_of(p) == 4);
   if (hipMalloc((void**)&h->shadow_arena, S.g.total) != hipSuccess) return fail(SH_ENOMEM, "shadow level allocation");
   S.base = (char*)round_up((long long)(uintptr_t)h->shadow_arena, 256);
   S.bins.build(S.boxes, S.M);
@@ -1184,14 +1212,22 @@ sh_status sh_shadow_advance(sh_hierarchy h) {
   if (!h->has_shadow) return fail(SH_ESTATE, "no shadow level");
   Level& S = h->shadow;
   if (S.k != h->shadow_k0) return fail(SH_ESTATE, "the shadow takes a single step");
-  // one RK4 step of twice the level-0 step on the periodic shadow lattice
-  stage(h, S, 0);
-  shadow_copy(h, ROLE_A);
-  stage(h, S, 1);
-  shadow_copy(h, ROLE_B);
-  stage(h, S, 2);
-  shadow_copy(h, ROLE_A);
-  stage(h, S, 3);
+  // one step of twice the level-0 step on the periodic shadow lattice
+  if (stages_of(h->p) == 3) {
+    stage(h, S, 4);
+    shadow_copy(h, ROLE_A);
+    stage(h, S, 5);
+    shadow_copy(h, ROLE_B);
+    stage(h, S, 6);
+  } else {
+    stage(h, S, 0);
+    shadow_copy(h, ROLE_A);
+    stage(h, S, 1);
+    shadow_copy(h, ROLE_B);
+    stage(h, S, 2);
+    shadow_copy(h, ROLE_A);
+    stage(h, S, 3);
+  }
   sh_launch_counter_inc(h->d_ls + SH_SHADOW_LS, 1, h->st);
   S.k += 1;
   shadow_copy(h, ROLE_UN);
@@ -1324,8 +1360,9 @@ sh_status sh_sync(sh_hierarchy h) {
 sh_status sh_debug_stage_scalars(sh_hierarchy h, int32_t l, int32_t s, double* out_host) {
   sh_status st = check_level(h, l);
   if (st != SH_OK || (st = not_capturing(h)) != SH_OK) return st;
-  if (s < 0 || s > 3 || !out_host) return fail(SH_EINVAL, "bad stage");
-  sh_launch_debug_scalars(h->d_ls + l, s, h->d_dbg, h->st);
+  const int nst = stages_of(h->p);
+  if (s < 0 || s >= nst || !out_host) return fail(SH_EINVAL, "bad stage");
+  sh_launch_debug_scalars(h->d_ls + l, nst == 3 ? s + 4 : s, h->d_dbg, h->st);
   LAUNCHCHK();
   HIPCHK(hipMemcpyAsync(out_host, h->d_dbg, 7 * 8, hipMemcpyDeviceToHost, h->st));
   HIPCHK(hipStreamSynchronize(h->st));
@@ -1404,7 +1441,7 @@ sh_status sh_set_tuning(sh_hierarchy h, int32_t kind, int32_t nontemporal, int32
     make_stage_tiles(L.boxes, h->tune, L.g.nvalid, wt, bt);
     HIPCHK(L.stiles_w.upload(wt));
     HIPCHK(L.stiles_b.upload(bt));
-    make_fused_tiles(L.boxes, h->tune, L.g.ng, ft);
+    if (stages_of(h->p) == 4) make_fused_tiles(L.boxes, h->tune, L.g.ng, ft);
     HIPCHK(L.ftiles.upload(ft));
   }
   return SH_OK;
@@ -1572,6 +1609,10 @@ sh_status sh_batch_create(int32_t njobs, const sh_hierarchy* jobs, sh_batch* out
     if (!h || h->lev.size() != 1 || h->st != b->st || h->p.prec != b->prec) {
       delete b;
       return fail(SH_EINVAL, "batched jobs must be single-level hierarchies of one precision on one stream");
+    }
+    if (stages_of(h->p) != 4) {
+      delete b;
+      return fail(SH_EINVAL, "batched jobs must use the RK4 integrator");
     }
     if (h->capturing) {
       delete b;

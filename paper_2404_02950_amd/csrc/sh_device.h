@@ -11,9 +11,9 @@ template <> struct Xoff<double> { static constexpr int v = 8; };
 template <> struct Xoff<float> { static constexpr int v = 16; };
 
 // ---------------------------------------------------------------------------------
-// Per-stage scalars from the level's device scalars.  Classic RK4 (integrator type 4)
-// evaluates the right-hand side at eta_n + c_s dt, c = (0, 1/2, 1/2, 1); the EOM
-// coefficients are c_fric = alpha/eta_s and c_pot = lambda * eta_s^beta.
+// Per-stage scalars from the level's device scalars.  The right-hand side of stage s is
+// evaluated at eta_n + c_s dt (c_s = stage_frac(s)); the EOM coefficients are
+// c_fric = alpha/eta_s and c_pot = lambda * eta_s^beta.
 // ---------------------------------------------------------------------------------
 struct StageScal {
   double cf, cp, inv_dx2, h6, h3, h2, h1;
@@ -30,8 +30,7 @@ __device__ __forceinline__ double level_time(const LevelScal& L) {
 }
 
 __device__ __forceinline__ StageScal stage_scalars(const LevelScal& L, int s) {
-  const double c = (s == 0) ? 0.0 : (s == 3 ? 1.0 : 0.5);
-  const double eta_s = level_time(L) + c * L.dt;
+  const double eta_s = level_time(L) + stage_frac(s) * L.dt;
   StageScal r;
   r.cf = L.alpha / eta_s;
   r.cp = L.lam * ipow(eta_s, L.beta);

@@ -16,27 +16,55 @@
 
 // Per-level scalars on the device.  k is the number of steps the level has taken; the
 // level time is eta0 + k*dt (one multiply and one add, so aligned levels hold
-// bit-identical times).  Every kernel resolves buffer roles from the parity of k, so a
+// bit-identical times).  nst is the number of stages per step of the integrator (4:
+// classic RK4, 3: SSPRK3).  Every kernel resolves buffer roles from k and nst, so a
 // launch sequence can be replayed without host updates.
 struct LevelScal {
   double eta0, dt, alpha, lam, inv_dx2, dx;
-  int beta, pad;
+  int beta, nst;
   long long k;
 };
 
-// Buffer roles.  With p = k & 1: U_n = slot[2p], A = slot[1], B = slot[2 - 2p].
-// RK4 stages read (U_n, A, B, A) and write (A, B, A, B); after stage 4 and the counter
-// increment, the old U_n (OLD) is slot B of the new parity until the next stage 2.
+// Buffer roles.
+// RK4, with p = k & 1: U_n = slot[2p], A = slot[1], B = slot[2 - 2p].  The stages read
+// (U_n, A, B, A) and write (A, B, A, B); after stage 4 and the counter increment, the
+// old U_n (OLD) is slot B of the new parity until the next stage 2.
+// SSPRK3, with q = k mod 3: U_n = slot[q], A = slot[q+1], B = slot[q+2] (mod 3).  The
+// stages read (U_n, A, B) and write (A, B, A): the new state lands in slot[q+1], which
+// is U_n of step k+1, and the old U_n is then slot B = slot[(k+1)+2] until the next
+// stage 2 overwrites it.
 enum { ROLE_UN = 0, ROLE_A = 1, ROLE_B = 2, ROLE_OLD = 3 };
 
-__host__ __device__ inline int role_slot(int role, long long k) {
-  int p = (int)(k & 1);
+// k mod 3 for k >= 0 from 32-bit halves (2^32 = 1 mod 3): a 64-bit division would be
+// expanded into a long vector sequence in every kernel that resolves a role.
+__host__ __device__ inline int mod3(long long k) {
+  const unsigned long long u = (unsigned long long)k;
+  return (int)(((unsigned)u % 3u + (unsigned)(u >> 32) % 3u) % 3u);
+}
+
+__host__ __device__ inline int role_slot(int role, long long k, int nst) {
+  if (nst == 3) {
+    const int q = mod3(k);
+    if (role == ROLE_UN) return q;
+    if (role == ROLE_A) return q == 2 ? 0 : q + 1;
+    return q == 0 ? 2 : q - 1;  // ROLE_B and ROLE_OLD
+  }
+  const int p = (int)(k & 1);
   switch (role) {
     case ROLE_UN: return 2 * p;
     case ROLE_A: return 1;
     case ROLE_B: return 2 - 2 * p;
     default: return 2 - 2 * p;  // ROLE_OLD (valid once k has been incremented)
   }
+}
+
+__host__ __device__ inline int role_slot(int role, const LevelScal& L) { return role_slot(role, L.k, L.nst); }
+
+// Stage ids of the kernels: 0..3 the four RK4 stages, 4..6 the three SSPRK3 stages.
+// Fraction c_s of the step at which each evaluates the right-hand side:
+// RK4 (0, 1/2, 1/2, 1), SSPRK3 (0, 1, 1/2).
+__host__ __device__ inline double stage_frac(int s) {
+  return (s == 0 || s == 4) ? 0.0 : ((s == 3 || s == 5) ? 1.0 : 0.5);
 }
 
 struct BoxDev {
