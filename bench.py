@@ -7,8 +7,8 @@ seeded Gaussian-random-field initial state; FP64 (``--prec f64``) or FP32 storag
 FP64 accumulation (``--prec f32``).  A step is one sh_advance_level: by default one kernel
 that computes all four RK stages of the step, then one refill of the level's 4-deep
 periodic ghost shell (with ``SHAMR_TUNE=fuse=0``: four stage kernels with a ghost copy
-between them).  ``--integrator 10`` (or 3) runs SSPRK3 instead: three stage kernels with a
-ghost copy between them (the fused step is RK4's).
+between them).  ``--integrator 10`` (or 3) runs SSPRK3 instead: by default one kernel for
+its three stages (with ``fuse=0``: three stage kernels with a ghost copy between them).
 
 Prints one JSON line: cell-updates/s per RK stage (whole job), the roofline of the
 dominant kernel from HIP events recorded around each of its launches inside the timed
@@ -162,7 +162,7 @@ def main():
     sb = STAGE_BYTES[args.prec] if nst == 4 else SSP_STAGE_BYTES[args.prec]
     roofline = None
     if prof["fused_step"][1]:
-        kname = "fused_rk4_step"
+        kname = "fused_rk4_step" if nst == 4 else "fused_ssprk3_step"
         k_ms, k_n = prof["fused_step"]
         k_bytes = FUSED_BYTES[args.prec] * cells * k_n
     else:

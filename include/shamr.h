@@ -205,8 +205,8 @@ sh_status sh_debug_stage_scalars(sh_hierarchy h, int32_t lev, int32_t s, double*
    nontemporal: 1 = once-used streams do not stay cache resident.
    tile_z: cells per per-stage tile in z (0 = from the level size).
    fuse: 4 = level 0 (which has no coarse/fine boundary) takes each step in one kernel
-     computing all four RK stages (temporal blocking; needs every level-0 box to be a
-     multiple of the fused footprint, else per-stage; RK4 only); 0 = per-stage kernels.
+     computing all the integrator's stages (temporal blocking; needs every level-0 box to
+     be a multiple of the fused footprint, else per-stage); 0 = per-stage kernels.
    fused_shape: footprint 0 = 32 x 8, 1 = 64 x 4, 2 = 32 x 16, 3 = 16 x 8.
    fused_tile_z: planes per fused tile; 0 = 512, halved while that gives fewer than 1024
      tiles, down to 16 (a batch decides once for all its members).
@@ -214,12 +214,13 @@ sh_status sh_debug_stage_scalars(sh_hierarchy h, int32_t lev, int32_t s, double*
      prefetch of the fused kernel: 0 = row-major, LDS, registers; 1 = row-major, lane
      shifts, registers; 2 = row-major, lane shifts, LDS; 3 = ring order, LDS, LDS; 4 =
      ring order, LDS, registers; 5 = as 4 with U_n planes loaded two iterations ahead and
-     the later stages' z-1 neighbours from LDS; 6 = as 5 with the accumulator in LDS.
+     the later stages' z-1 neighbours from LDS; 6 = as 5 with the accumulator in LDS
+     (SSPRK3 has no accumulator: 2, 3 and 6 run as 1, 4 and 5).
    Applies to every level.  Defaults at creation: kind 8, nontemporal 1, tile_z 0, fuse 4,
-   fused_tile_z 0, fused_shape / fused_variant 0 / 5 for SH_F64 and 2 / 6 for SH_F32.  The
-   environment variable SHAMR_TUNE (e.g. "kind=8,nt=1,zc=0,fuse=4,fshape=0,fzc=0,fvar=5,
-   fgrp=1") overrides them; fgrp 1 = fused tiles launched in groups of 32 covering
-   square-ish patches, 0 = in rows. */
+   fused_tile_z 0, fused_shape / fused_variant 0 / 5 for RK4 in SH_F64, 2 / 6 for RK4 in
+   SH_F32 and 2 / 5 for SSPRK3.  The environment variable SHAMR_TUNE (e.g.
+   "kind=8,nt=1,zc=0,fuse=4,fshape=0,fzc=0,fvar=5,fgrp=1") overrides them; fgrp 1 = fused
+   tiles launched in groups of 32 covering square-ish patches, 0 = in rows. */
 sh_status sh_set_tuning(sh_hierarchy h, int32_t kind, int32_t nontemporal, int32_t tile_z, int32_t fuse,
                         int32_t fused_shape, int32_t fused_tile_z, int32_t fused_variant);
 

@@ -1,23 +1,25 @@
-// Fused RK4 step: the four stages of a step in one kernel (temporal blocking).
+// Fused step: all NS stages of a step in one kernel (temporal blocking), for classic RK4
+// (NS = 4) and SSPRK3 (NS = 3).
 //
 // The arithmetic is exactly that of the per-stage kernel (same expressions, same order,
 // stage states rounded to the storage type between stages), so the results are the same
-// bit for bit; only the data movement changes.  The per-stage form moves 64 values per
-// cell and step through HBM (U_n, stage states and the accumulator, 12/20/20/12 per
-// stage); fused, each step reads U_n and writes U_{n+1} once: 8 values per cell.
+// bit for bit; only the data movement changes.  The per-stage form moves 64 (RK4: U_n,
+// stage states and the accumulator, 12/20/20/12 per stage) or 32 (SSPRK3: 8/12/12)
+// values per cell and step through HBM; fused, each step reads U_n and writes U_{n+1}
+// once: 8 values per cell.
 //
 // Scheme.  A block owns a TX x TY column footprint of a box and marches up a range of zc
-// planes.  Stage j (0..3) of plane p runs in iteration p + j, after stage j-1 of plane
+// planes.  Stage j (0..NS-1) of plane p runs in iteration p + j, after stage j-1 of plane
 // p+1 (its z+1 neighbour) in the same iteration, so each stage keeps a three-plane
 // window of its input column in registers.  In x and y a stage needs its input one cell
-// beyond where it is computed, so stage j is computed on the footprint grown by 3 - j
-// cells (overlapped tiles), and the threads cover the footprint grown by 4 cells, the
-// outermost ring only loading U_n.  Each iteration every stage publishes its input plane
-// to LDS (two buffers alternating by iteration), one barrier, then stages 0..3 run in
-// order reading x/y neighbours from LDS.
-// The z-range is extended the same way (stage j covers 3 - j extra planes below and
-// above), so U_n is read from z0-4 to z0+zc+3: the level keeps a 4-deep ghost shell.
-// The accumulator exists only on the footprint's own columns; it is kept in LDS.
+// beyond where it is computed, so stage j is computed on the footprint grown by
+// NS - 1 - j cells (overlapped tiles), and the threads cover the footprint grown by NS
+// cells, the outermost ring only loading U_n.  Each iteration every stage publishes its
+// input plane to LDS (two buffers alternating by iteration), one barrier, then the stages
+// run in order reading x/y neighbours from LDS.
+// The z-range is extended the same way (stage j covers NS - 1 - j extra planes below and
+// above), so U_n is read from z0-NS to z0+zc+NS-1: the level keeps a 4-deep ghost shell.
+// The RK4 accumulator exists only on the footprint's own columns (registers or LDS).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -31,10 +33,8 @@
 
 namespace {
 
-constexpr int FD = 4;       // fused stages
-constexpr int FG = FD - 1;  // compute ring of stage 0 beyond the footprint
-
-template <typename T, int TX, int TY>
+// FD = NS fused stages; stage 0 is computed on the footprint grown by FG = FD - 1 cells
+template <typename T, int TX, int TY, int FD>
 struct FusedShape {
   static constexpr int W = TX + 2 * FD;  // thread columns in x (incl. the loader ring)
   static constexpr int H = TY + 2 * FD;
@@ -45,7 +45,7 @@ struct FusedShape {
 // Thread -> column map sorted by ring distance from the footprint (footprint first, then
 // rings 1..FD), row-major within a ring.  Stage j is computed on rings 0..FG-j, so with
 // this order whole wavefronts skip the stages they have no columns for.
-template <int TX, int TY>
+template <int TX, int TY, int FD>
 struct RingMap {
   static constexpr int W = TX + 2 * FD, H = TY + 2 * FD, N = W * H;
   unsigned char cx[N], cy[N];
@@ -66,8 +66,8 @@ struct RingMap {
   }
 };
 
-template <int TX, int TY>
-__constant__ RingMap<TX, TY> ring_map = RingMap<TX, TY>();
+template <int TX, int TY, int FD>
+__constant__ RingMap<TX, TY, FD> ring_map = RingMap<TX, TY, FD>();
 
 }  // namespace
 
@@ -85,19 +85,24 @@ __device__ __forceinline__ float dpp_move(float v, float old) {
 constexpr int DPP_WAVE_SHR1 = 0x138;  // lane l takes lane l-1
 constexpr int DPP_WAVE_SHL1 = 0x130;  // lane l takes lane l+1
 
-// ORDER 0: threads row-major over the (TX+8) x (TY+8) columns; 1: sorted by ring.
+// NS: 4 = classic RK4, 3 = SSPRK3 (stage updates as in the per-stage kernel).
+// ORDER 0: threads row-major over the (TX+2NS) x (TY+2NS) columns; 1: sorted by ring.
 // XDPP: x neighbours by lane shifts (row-major only: the computing columns' x neighbours
-// are the adjacent lanes; the two wave-edge lanes read LDS).  ACCL: accumulator in LDS.
+// are the adjacent lanes; the two wave-edge lanes read LDS).  ACCL: RK4 accumulator in
+// LDS.
 // PF2: U_n planes are loaded two iterations before they enter the stage-0 window, into
 // two buffers that alternate between iterations (else in the iteration that uses them).
 // ZL: stages 1..3 read their z-1 neighbour from the previous iteration's LDS planes
 // instead of keeping it in registers (needs the double-buffered planes).
-template <typename T, bool NT, int TX, int TY, int ORDER, bool XDPP, bool ACCL, bool PF2, bool ZL>
-__global__ __launch_bounds__((FusedShape<T, TX, TY>::NBLK)) void k_fused_rk4(const Tile* __restrict__ tiles,
-                                                                           int ntiles,
-                                                                           const BoxDev* __restrict__ boxes) {
+template <typename T, bool NT, int TX, int TY, int ORDER, bool XDPP, bool ACCL, bool PF2, bool ZL, int NS>
+__global__ __launch_bounds__((FusedShape<T, TX, TY, NS>::NBLK)) void k_fused_step(const Tile* __restrict__ tiles,
+                                                                                int ntiles,
+                                                                                const BoxDev* __restrict__ boxes) {
   static_assert(!(XDPP && ORDER != 0), "lane shifts need the row-major order");
-  using Sh = FusedShape<T, TX, TY>;
+  static_assert(NS == 4 || (NS == 3 && !ACCL), "RK4 (with either accumulator) or SSPRK3 (none)");
+  constexpr int FD = NS;      // fused stages
+  constexpr int FG = FD - 1;  // compute ring of stage 0 beyond the footprint
+  using Sh = FusedShape<T, TX, TY, FD>;
   constexpr int W = Sh::W, H = Sh::H;
   // stage input planes, double-buffered by iteration parity where LDS allows: a buffer is
   // rewritten two iterations later, after the next iteration's barrier, so one barrier per
@@ -106,7 +111,7 @@ __global__ __launch_bounds__((FusedShape<T, TX, TY>::NBLK)) void k_fused_rk4(con
   constexpr size_t LDS_ACC = ACCL ? sizeof(double) * 4 * 4 * TY * TX : 0;
   constexpr int NBUF = (2 * sizeof(T) * FD * 2 * H * W + LDS_ACC <= 160 * 1024) ? 2 : 1;
   __shared__ T sm2[NBUF][FD][2][H][W];
-  // accumulator of the footprint's own columns for the four planes in flight (slot =
+  // RK4 accumulator of the footprint's own columns for the four planes in flight (slot =
   // plane mod 4); each thread touches only its own column, so no barrier is involved
   __shared__ double sacc[ACCL ? 4 : 1][4][ACCL ? TY : 1][ACCL ? TX : 1];
 
@@ -118,10 +123,11 @@ __global__ __launch_bounds__((FusedShape<T, TX, TY>::NBLK)) void k_fused_rk4(con
   const LevelScal L = *B.ls;
   StageScal sc[FD];
 #pragma unroll
-  for (int j = 0; j < FD; ++j) sc[j] = uniform(stage_scalars(L, j));
-  // the fused step is classic RK4's (four stages), whose roles follow the parity of k
-  const T* __restrict__ X = (const T*)slot_base(B, role_slot(ROLE_UN, L.k, 4));
-  T* __restrict__ Y = (T*)slot_base(B, role_slot(ROLE_B, L.k, 4));
+  for (int j = 0; j < FD; ++j) sc[j] = uniform(stage_scalars(L, NS == 4 ? j : j + 4));
+  // U_n in, U_{n+1} out: RK4's last stage writes B, SSPRK3's writes A (the role cycle of
+  // the integrator, which the launch matches)
+  const T* __restrict__ X = (const T*)slot_base(B, role_slot(ROLE_UN, L.k, NS));
+  T* __restrict__ Y = (T*)slot_base(B, role_slot(NS == 4 ? ROLE_B : ROLE_A, L.k, NS));
 
   const int tid = threadIdx.x;
   const int lane = tid & (SH_WAVE - 1);
@@ -132,8 +138,8 @@ __global__ __launch_bounds__((FusedShape<T, TX, TY>::NBLK)) void k_fused_rk4(con
       cx = tid % W;
       cy = tid / W;
     } else {
-      cx = ring_map<TX, TY>.cx[tid];
-      cy = ring_map<TX, TY>.cy[tid];
+      cx = ring_map<TX, TY, FD>.cx[tid];
+      cy = ring_map<TX, TY, FD>.cy[tid];
     }
   }
   const int ox = cx - FD, oy = cy - FD;  // footprint-relative
@@ -169,7 +175,7 @@ __global__ __launch_bounds__((FusedShape<T, TX, TY>::NBLK)) void k_fused_rk4(con
   // (psi of i-1 is the window bottom) for the updates of stages 1 and 2
   T wj[FD][3][2], qj[FD][2][2];
   T q0p[2] = {(T)0, (T)0}, u2[4] = {(T)0, (T)0, (T)0, (T)0};
-  double racc[FD][4];
+  double racc[NS == 4 ? FD : 1][4];
 #pragma unroll
   for (int j = 0; j < FD; ++j) {
 #pragma unroll
@@ -177,8 +183,10 @@ __global__ __launch_bounds__((FusedShape<T, TX, TY>::NBLK)) void k_fused_rk4(con
       wj[j][0][c] = wj[j][1][c] = wj[j][2][c] = (T)0;
       qj[j][0][c] = qj[j][1][c] = (T)0;
     }
+    if constexpr (NS == 4) {
 #pragma unroll
-    for (int c = 0; c < 4; ++c) racc[j][c] = 0.0;
+      for (int c = 0; c < 4; ++c) racc[j][c] = 0.0;
+    }
   }
   const bool own = (r == 0);
   const int ax = own ? ox : 0, ay = own ? oy : 0;
@@ -289,14 +297,20 @@ __global__ __launch_bounds__((FusedShape<T, TX, TY>::NBLK)) void k_fused_rk4(con
         for (int c = 0; c < 4; ++c) un[c] = u2[c];
       }
       constexpr int AST = ACCL ? TY * TX : 1;  // component stride of sacc
-      double* ac = ACCL ? &sacc[(i - j) & 3][0][ay][ax] : &racc[j][0];
+      double* ac = ACCL ? &sacc[(i - j) & 3][0][ay][ax] : &racc[NS == 4 ? j : 0][0];
       const int ast = ACCL ? AST : 1;
       // the LDS accumulator exists for the footprint's columns only; the register one is
       // updated on every computing column (values off the footprint are never stored)
       const bool upd = ACCL ? own : true;
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
-        if (j == 0) {
+        if constexpr (NS == 3) {
+          // SSPRK3: U_n + h k;  3/4 U_n + 1/4 (X + h k);  1/3 U_n + 2/3 (X + h k)
+          const double xk = (double)xin[c] + sc[j].h1 * k4[c];
+          if (j == 0) out[c] = (T)xk;
+          else if (j == 1) out[c] = (T)(0.75 * (double)un[c] + 0.25 * xk);
+          else out[c] = (T)((1.0 / 3.0) * (double)un[c] + (2.0 / 3.0) * xk);
+        } else if (j == 0) {
           const double u = (double)xin[c];
           if (upd) ac[c * ast] = u + sc[0].h6 * k4[c];
           out[c] = (T)(u + sc[0].h2 * k4[c]);
@@ -320,14 +334,12 @@ __global__ __launch_bounds__((FusedShape<T, TX, TY>::NBLK)) void k_fused_rk4(con
       }
     }
     if (NBUF == 1) lds_barrier();
-    if (!ACCL) {
+    if constexpr (NS == 4 && !ACCL) {
       // register accumulator: advance the per-plane chain by one plane
 #pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        racc[3][c] = racc[2][c];
-        racc[2][c] = racc[1][c];
-        racc[1][c] = racc[0][c];
-      }
+      for (int c = 0; c < 4; ++c)
+#pragma unroll
+        for (int j = FD - 1; j > 0; --j) racc[j][c] = racc[j - 1][c];
     }
     // advance the stage-0 window by one plane
 #pragma unroll
@@ -361,11 +373,12 @@ __global__ __launch_bounds__((FusedShape<T, TX, TY>::NBLK)) void k_fused_rk4(con
   }
 }
 
-template <typename T, bool NT, int TX, int TY, int ORDER, bool XDPP, bool ACCL, bool PF2 = false, bool ZL = false>
+template <typename T, bool NT, int TX, int TY, int NS, int ORDER, bool XDPP, bool ACCL, bool PF2 = false,
+          bool ZL = false>
 static void fused_launch_shape(const Tile* tiles, int ntiles, const BoxDev* boxes, hipStream_t st) {
-  using Sh = FusedShape<T, TX, TY>;
-  hipLaunchKernelGGL((k_fused_rk4<T, NT, TX, TY, ORDER, XDPP, ACCL, PF2, ZL>), dim3(ntiles), dim3(Sh::NBLK), 0, st, tiles,
-                     ntiles, boxes);
+  using Sh = FusedShape<T, TX, TY, NS>;
+  hipLaunchKernelGGL((k_fused_step<T, NT, TX, TY, ORDER, XDPP, ACCL, PF2, ZL, NS>), dim3(ntiles), dim3(Sh::NBLK), 0,
+                     st, tiles, ntiles, boxes);
 }
 
 // variant: 0 = row-major threads, x neighbours through LDS, accumulator in registers;
@@ -373,28 +386,30 @@ static void fused_launch_shape(const Tile* tiles, int ntiles, const BoxDev* boxe
 // accumulator in LDS; 3 = ring-ordered threads, LDS neighbours, accumulator in LDS;
 // 4 = ring-ordered threads, LDS neighbours, accumulator in registers; 5 = variant 4 with
 // the two-iteration U_n prefetch, z-1 neighbours of stages 1..3 from LDS; 6 = variant 5
-// with the accumulator in LDS.
-template <typename T, bool NT, int TX, int TY>
+// with the accumulator in LDS.  SSPRK3 has no accumulator: variants 2, 3 and 6 run as
+// 1, 4 and 5.
+template <typename T, bool NT, int TX, int TY, int NS>
 static void fused_launch_variant(int variant, const Tile* tiles, int ntiles, const BoxDev* boxes, hipStream_t st) {
+  constexpr bool AL = NS == 4;  // the LDS accumulator variants exist for RK4
   switch (variant) {
-    case 0: fused_launch_shape<T, NT, TX, TY, 0, false, false>(tiles, ntiles, boxes, st); break;
-    case 1: fused_launch_shape<T, NT, TX, TY, 0, true, false>(tiles, ntiles, boxes, st); break;
-    case 2: fused_launch_shape<T, NT, TX, TY, 0, true, true>(tiles, ntiles, boxes, st); break;
-    case 3: fused_launch_shape<T, NT, TX, TY, 1, false, true>(tiles, ntiles, boxes, st); break;
-    case 4: fused_launch_shape<T, NT, TX, TY, 1, false, false>(tiles, ntiles, boxes, st); break;
-    case 5: fused_launch_shape<T, NT, TX, TY, 1, false, false, true, true>(tiles, ntiles, boxes, st); break;
-    default: fused_launch_shape<T, NT, TX, TY, 1, false, true, true, true>(tiles, ntiles, boxes, st); break;
+    case 0: fused_launch_shape<T, NT, TX, TY, NS, 0, false, false>(tiles, ntiles, boxes, st); break;
+    case 1: fused_launch_shape<T, NT, TX, TY, NS, 0, true, false>(tiles, ntiles, boxes, st); break;
+    case 2: fused_launch_shape<T, NT, TX, TY, NS, 0, true, AL>(tiles, ntiles, boxes, st); break;
+    case 3: fused_launch_shape<T, NT, TX, TY, NS, 1, false, AL>(tiles, ntiles, boxes, st); break;
+    case 4: fused_launch_shape<T, NT, TX, TY, NS, 1, false, false>(tiles, ntiles, boxes, st); break;
+    case 5: fused_launch_shape<T, NT, TX, TY, NS, 1, false, false, true, true>(tiles, ntiles, boxes, st); break;
+    default: fused_launch_shape<T, NT, TX, TY, NS, 1, false, AL, true, true>(tiles, ntiles, boxes, st); break;
   }
 }
 
-template <typename T, bool NT>
+template <typename T, bool NT, int NS>
 static void fused_launch(int shape, int variant, const Tile* tiles, int ntiles, const BoxDev* boxes,
                          hipStream_t st) {
   if (ntiles == 0) return;
-  if (shape == 0) fused_launch_variant<T, NT, 32, 8>(variant, tiles, ntiles, boxes, st);
-  else if (shape == 1) fused_launch_variant<T, NT, 64, 4>(variant, tiles, ntiles, boxes, st);
-  else if (shape == 2) fused_launch_variant<T, NT, 32, 16>(variant, tiles, ntiles, boxes, st);
-  else fused_launch_variant<T, NT, 16, 8>(variant, tiles, ntiles, boxes, st);
+  if (shape == 0) fused_launch_variant<T, NT, 32, 8, NS>(variant, tiles, ntiles, boxes, st);
+  else if (shape == 1) fused_launch_variant<T, NT, 64, 4, NS>(variant, tiles, ntiles, boxes, st);
+  else if (shape == 2) fused_launch_variant<T, NT, 32, 16, NS>(variant, tiles, ntiles, boxes, st);
+  else fused_launch_variant<T, NT, 16, 8, NS>(variant, tiles, ntiles, boxes, st);
 }
 
 // Footprint of a fused tile: shape 0 = 32 x 8, 1 = 64 x 4, 2 = 32 x 16, 3 = 16 x 8 (two
@@ -405,13 +420,21 @@ void sh_fused_footprint(int shape, int* tx, int* ty) {
   *ty = fy[shape];
 }
 
-void sh_launch_fused(int prec, bool nt, int shape, int variant, const Tile* tiles, int ntiles, const BoxDev* boxes,
-                     hipStream_t st) {
-  if (prec == 0) {
-    if (nt) fused_launch<double, true>(shape, variant, tiles, ntiles, boxes, st);
-    else fused_launch<double, false>(shape, variant, tiles, ntiles, boxes, st);
+void sh_launch_fused(int prec, bool nt, int shape, int variant, int nst, const Tile* tiles, int ntiles,
+                     const BoxDev* boxes, hipStream_t st) {
+  if (nst == 3) {
+    if (prec == 0) {
+      if (nt) fused_launch<double, true, 3>(shape, variant, tiles, ntiles, boxes, st);
+      else fused_launch<double, false, 3>(shape, variant, tiles, ntiles, boxes, st);
+    } else {
+      if (nt) fused_launch<float, true, 3>(shape, variant, tiles, ntiles, boxes, st);
+      else fused_launch<float, false, 3>(shape, variant, tiles, ntiles, boxes, st);
+    }
+  } else if (prec == 0) {
+    if (nt) fused_launch<double, true, 4>(shape, variant, tiles, ntiles, boxes, st);
+    else fused_launch<double, false, 4>(shape, variant, tiles, ntiles, boxes, st);
   } else {
-    if (nt) fused_launch<float, true>(shape, variant, tiles, ntiles, boxes, st);
-    else fused_launch<float, false>(shape, variant, tiles, ntiles, boxes, st);
+    if (nt) fused_launch<float, true, 4>(shape, variant, tiles, ntiles, boxes, st);
+    else fused_launch<float, false, 4>(shape, variant, tiles, ntiles, boxes, st);
   }
 }

@@ -180,8 +180,8 @@ static void make_geom(int prec, int ng, const std::vector<IBox>& boxes, LayoutGe
 // rows of that many wavefronts for boxes at least 64 cells wide (narrower boxes keep
 // wave-row tiles).  nt: nontemporal once-used streams.  zc: cells per tile in z (0 =
 // chosen from the level size).
-// fuse: 4 = level 0 advances with the fused four-stage kernel when its boxes are
-// multiples of the fused footprint (fshape 0: 32 x 8, 1: 64 x 4, 2: 32 x 16, 3: 16 x 8), 0 =
+// fuse: 4 = level 0 advances with the fused kernel (all stages of a step in one launch)
+// when its boxes are multiples of the fused footprint (fshape 0: 32 x 8, 1: 64 x 4, 2: 32 x 16, 3: 16 x 8), 0 =
 // per-stage kernels.
 struct Tuning {
   int kind = 8;
@@ -199,10 +199,14 @@ struct Tuning {
 // stages from LDS; FP64 on the 32 x 8 footprint with the accumulator in registers (one
 // 10-wave workgroup per CU), FP32 on 32 x 16 with the accumulator in LDS (15 waves,
 // within 128 registers).
-static Tuning default_tuning(int prec) {
+// Fastest fused shapes measured at 512^3 on MI355X: RK4 FP64 32 x 8 variant 5, RK4 FP32
+// 32 x 16 variant 6; SSPRK3 (fewer registers per stage) 32 x 16 variant 5 in both.
+static Tuning default_tuning(const sh_params& p) {
   Tuning t;
   t.fvar = 5;
-  if (prec == SH_F32) {
+  if (stages_of(p) == 3) {
+    t.fshape = 2;
+  } else if (p.prec == SH_F32) {
     t.fshape = 2;
     t.fvar = 6;
   }
@@ -770,7 +774,7 @@ sh_status sh_hierarchy_create(const sh_params* p, void* hip_stream, sh_hierarchy
   sh_hierarchy h = new (std::nothrow) sh_hierarchy_s;
   if (!h) return fail(SH_ENOMEM, "host allocation failed");
   h->p = *p;
-  h->tune = default_tuning(p->prec);
+  h->tune = default_tuning(*p);
   tuning_from_env(h->tune);
   h->st = (hipStream_t)hip_stream;
   if (hipMalloc((void**)&h->d_ls, (SH_SHADOW_LS + 1) * sizeof(LevelScal)) != hipSuccess ||
@@ -836,7 +840,7 @@ static sh_status set_box_tables(sh_hierarchy h, LevelScal* ls, Level& L) {
     make_stage_tiles(L.boxes, h->tune, L.g.nvalid, wt, bt);
     HIPCHK(L.stiles_w.upload(wt));
     HIPCHK(L.stiles_b.upload(bt));
-    if (stages_of(h->p) == 4) make_fused_tiles(L.boxes, h->tune, L.g.ng, ft);  // the fused step is RK4's
+    make_fused_tiles(L.boxes, h->tune, L.g.ng, ft);
     HIPCHK(L.ftiles.upload(ft));
   }
   HIPCHK(L.xoff_valid.upload(xv));
@@ -1038,12 +1042,13 @@ sh_status sh_advance_level(sh_hierarchy h, int32_t l, int32_t sub) {
   Level& L = h->lev[l];
   hipEvent_t ev;
   if (L.ftiles.n) {
-    // all four stages in one kernel: no ghost fill between stages is needed because the
+    // all stages in one kernel: no ghost fill between stages is needed because the
     // kernel computes the early stages on the ghost-deep ring itself
-    for (int st = 0; st < 4; ++st) h->rec(1, l, st, sub);
+    const int nst = stages_of(h->p);
+    for (int st = 0; st < nst; ++st) h->rec(1, l, st, sub);
     ev = h->prof_begin();
-    sh_launch_fused(h->p.prec, h->tune.nt != 0, h->tune.fshape, h->tune.fvar, L.ftiles.p, (int)L.ftiles.n, L.dbox.p,
-                    h->st);
+    sh_launch_fused(h->p.prec, h->tune.nt != 0, h->tune.fshape, h->tune.fvar, nst, L.ftiles.p, (int)L.ftiles.n,
+                    L.dbox.p, h->st);
     h->prof_end(ev, 7);
     LAUNCHCHK();
     sh_launch_counter_inc(h->d_ls + l, 1, h->st);
@@ -1441,7 +1446,7 @@ sh_status sh_set_tuning(sh_hierarchy h, int32_t kind, int32_t nontemporal, int32
     make_stage_tiles(L.boxes, h->tune, L.g.nvalid, wt, bt);
     HIPCHK(L.stiles_w.upload(wt));
     HIPCHK(L.stiles_b.upload(bt));
-    if (stages_of(h->p) == 4) make_fused_tiles(L.boxes, h->tune, L.g.ng, ft);
+    make_fused_tiles(L.boxes, h->tune, L.g.ng, ft);
     HIPCHK(L.ftiles.upload(ft));
   }
   return SH_OK;
@@ -1671,7 +1676,7 @@ sh_status sh_batch_advance(sh_batch b) {
   const int prec = b->prec;
   const bool nt = b->tune.nt != 0;
   if (b->ftiles.n) {
-    sh_launch_fused(prec, nt, b->tune.fshape, b->tune.fvar, b->ftiles.p, (int)b->ftiles.n, b->boxes.p, b->st);
+    sh_launch_fused(prec, nt, b->tune.fshape, b->tune.fvar, 4, b->ftiles.p, (int)b->ftiles.n, b->boxes.p, b->st);
     LAUNCHCHK();
   }
   if (b->wtiles.n || b->btiles.n) {

@@ -33,6 +33,6 @@ void sh_launch_mark_covered(const AvgSeg* segs, const SegBlock* blocks, int nblo
 void sh_launch_xfer(int prec, bool to_box, const BoxDev* boxes, const long long* off, int nbox, double* stage, int role,
                     int g, long long total, hipStream_t st);
 void sh_launch_debug_scalars(const LevelScal* ls, int s, double* out, hipStream_t st);
-void sh_launch_fused(int prec, bool nt, int shape, int variant, const Tile* tiles, int ntiles, const BoxDev* boxes,
-                     hipStream_t st);
+void sh_launch_fused(int prec, bool nt, int shape, int variant, int nst, const Tile* tiles, int ntiles,
+                     const BoxDev* boxes, hipStream_t st);
 void sh_fused_footprint(int shape, int* tx, int* ty);

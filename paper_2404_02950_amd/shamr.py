@@ -363,10 +363,11 @@ class Hierarchy:
                    fused_shape: int | None = None, fused_tile_z: int = 0, fused_variant: int | None = None):
         """Launch shape (see sh_set_tuning); the fused shape and variant default to the
         library's choice for the hierarchy's precision."""
+        ssp = self.params.integrator in (3, 10)
         if fused_shape is None:
-            fused_shape = 2 if self.params.prec == SH_F32 else 0
+            fused_shape = 2 if (ssp or self.params.prec == SH_F32) else 0
         if fused_variant is None:
-            fused_variant = 6 if self.params.prec == SH_F32 else 5
+            fused_variant = 6 if (self.params.prec == SH_F32 and not ssp) else 5
         _check(self.lib.sh_set_tuning(self.h, kind, nontemporal, tile_z, fuse, fused_shape, fused_tile_z,
                                       fused_variant))
 

@@ -1,8 +1,9 @@
 """GPU parity of the SSPRK3 integrator (integrator types 3 and 10: three stages, three
 state buffers, no accumulator) against the oracle, through the C-ABI: stage scalars,
-single levels under every per-stage launch shape, a three-level hierarchy with regrids in
-FP64 and FP32, the subcycling order of Fig. 2 (drawn for a three-stage integrator),
-truncation error estimates with the shadow level, and recorded (graph) steps."""
+single levels under every per-stage launch shape and every fused-step shape and variant,
+a three-level hierarchy with regrids in FP64 and FP32, the subcycling order of Fig. 2
+(drawn for a three-stage integrator), truncation error estimates with the shadow level,
+and recorded (graph) steps."""
 import numpy as np
 import pytest
 
@@ -46,11 +47,13 @@ def test_device_stage_scalars():
 
 
 @pytest.mark.parametrize("integrator", [3, 10])
-def test_literal_64cube_bitwise(integrator):
-    # the literal configuration (beta = 2) through its first 40 steps, every step checked
-    # at a few points and the whole lattice at the end
+@pytest.mark.parametrize("fuse", [4, 0])
+def test_literal_64cube_bitwise(integrator, fuse):
+    # the literal configuration (beta = 2, diverging) through its first 40 steps, fused and
+    # per-stage, the whole lattice checked at a few steps (NaN/Inf positions included)
     U0 = random_state(64, 64.0, 1)
     h = _level(U0, integrator=integrator)
+    h.set_tuning(fuse=fuse)
     ref = {}
     run_single_level(U0, 40, 0.1, 0.25, 1.0, integrator=integrator,
                      callback=lambda k, U: ref.__setitem__(k, U.copy()) if k in (1, 2, 3, 7, 40) else None)
@@ -68,7 +71,7 @@ def test_launch_shapes_and_ragged_boxes_bitwise(kind, nt, zc, n, cuts):
     U0 = random_state(n, float(n), 7)
     boxes = decompose(n, cuts) if cuts else None
     h = _level(U0, boxes=boxes, beta=0)
-    h.set_tuning(kind, nt, zc)
+    h.set_tuning(kind, nt, zc, fuse=0)
     ref = run_single_level(U0, 7, 0.1, 0.25, 1.0, beta=0, integrator=10)
     for _ in range(7):
         h.advance(0)
@@ -87,15 +90,39 @@ def test_fp32_storage_bitwise_with_fp32_oracle():
     h.close()
 
 
-def test_fused_step_is_not_used_and_batches_refuse_ssprk3():
+@pytest.mark.parametrize("variant", [0, 1, 4, 5, 6])
+@pytest.mark.parametrize("prec,shape,fzc,cuts", [(0, 0, 64, None), (0, 0, 7, [[32], [8, 40], []]),
+                                                 (0, 1, 13, [[], [16], [40]]), (0, 2, 9, [[32], [16], [24]]),
+                                                 (0, 3, 11, [[16], [8, 40], [24]]), (1, 2, 0, None),
+                                                 (1, 0, 5, [[32], [24], [16, 40]])])
+def test_fused_three_stage_step_bitwise(prec, shape, fzc, cuts, variant):
+    # the fused step with the three SSPRK3 stages in one kernel must give the oracle's bits
+    n = 64
+    U0 = random_state(n, float(n), 6)
+    h = _level(U0, prec=prec, beta=0, boxes=decompose(n, cuts) if cuts else None)
+    h.set_tuning(8, 1, 0, fuse=4, fused_shape=shape, fused_tile_z=fzc, fused_variant=variant)
+    h.profile(True)
+    ref = run_single_level(U0.astype(np.float32) if prec else U0, 5, 0.1, 0.25, 1.0, beta=0, integrator=10)
+    for _ in range(5):
+        h.advance(0)
+    prof = h.profile_read()
+    assert prof["fused_step"][1] == 5 and prof["stage1"][1] == 0, prof
+    assert_bitwise(h.read_dense(0), ref.astype(np.float64), f"prec={prec} shape={shape} fzc={fzc} variant={variant}")
+    h.close()
+
+
+def test_stage_counts_and_batches_refuse_ssprk3():
     n = 32
     U0 = random_state(n, float(n), 2)
     h = _level(U0, beta=0)
-    h.profile(True)
-    h.advance(0)
-    prof = h.profile_read()
-    assert prof["fused_step"][1] == 0 and prof["stage4"][1] == 0
-    assert prof["stage1"][1] == prof["stage2"][1] == prof["stage3"][1] == 1
+    for fuse, want in ((4, (1, 0, 0, 0, 0)), (0, (0, 1, 1, 1, 0))):
+        h.set_tuning(fuse=fuse)
+        h.profile(True)
+        h.advance(0)
+        prof = h.profile_read()
+        h.profile(False)
+        got = tuple(prof[k][1] for k in ("fused_step", "stage1", "stage2", "stage3", "stage4"))
+        assert got == want, (fuse, got)
     with pytest.raises(shamr.ShError):
         shamr.Batch([h])
     h.close()

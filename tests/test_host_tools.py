@@ -22,14 +22,14 @@ def test_traffic_summary_scales_by_the_copy_kernel(tmp_path):
     fetch, write = tmp_path / "f.csv", tmp_path / "w.csv"
     # the read counter sees half of what is read; the write counter is exact
     _counter_csv(fetch, "FETCH_SIZE", [("void k_xfer<double, true>(...)", ref / 2 / 1024),
-                                       ("void k_fused_rk4<double, ...>(...)", 3000.0),
-                                       ("void k_fused_rk4<double, ...>(...)", 3200.0),
+                                       ("void k_fused_step<double, ...>(...)", 3000.0),
+                                       ("void k_fused_step<double, ...>(...)", 3200.0),
                                        ("other", 1.0)])
     _counter_csv(write, "WRITE_SIZE", [("void k_xfer<double, true>(...)", ref / 1024),
-                                       ("void k_fused_rk4<double, ...>(...)", 4000.0),
-                                       ("void k_fused_rk4<double, ...>(...)", 4000.0)])
+                                       ("void k_fused_step<double, ...>(...)", 4000.0),
+                                       ("void k_fused_step<double, ...>(...)", 4000.0)])
     out_json, out_md = tmp_path / "t.json", tmp_path / "t.md"
-    rocprof_summary.main(["traffic", str(fetch), str(write), str(out_json), str(out_md), "--kernel", "k_fused_rk4",
+    rocprof_summary.main(["traffic", str(fetch), str(write), str(out_json), str(out_md), "--kernel", "k_fused_step",
                           "--n", str(n), "--prec", "f64", "--alg-bytes", "64", "--cmd-fetch", "a", "--cmd-write", "b"])
     rec = json.load(open(out_json))
     assert rec["calibration"]["fetch_factor"] == pytest.approx(2.0)
@@ -39,18 +39,18 @@ def test_traffic_summary_scales_by_the_copy_kernel(tmp_path):
     assert rec["algorithmic_bytes_per_launch"] == 64 * n ** 3
     assert rec["dispatches"] == 2
     assert len(rec["kernel_source_sha256"]) == 64
-    assert "k_fused_rk4" in open(out_md).read()
+    assert "k_fused_step" in open(out_md).read()
 
 
 def test_traffic_summary_fp32_reference_reads_fp64(tmp_path):
     # in FP32 mode k_xfer still reads the dense FP64 state but writes FP32 boxes
     n = 4
     fetch, write = tmp_path / "f.csv", tmp_path / "w.csv"
-    _counter_csv(fetch, "FETCH_SIZE", [("k_xfer<float>", 4 * n ** 3 * 8 / 1024), ("k_fused_rk4<float>", 10.0)])
-    _counter_csv(write, "WRITE_SIZE", [("k_xfer<float>", 4 * n ** 3 * 4 / 1024), ("k_fused_rk4<float>", 10.0)])
+    _counter_csv(fetch, "FETCH_SIZE", [("k_xfer<float>", 4 * n ** 3 * 8 / 1024), ("k_fused_step<float>", 10.0)])
+    _counter_csv(write, "WRITE_SIZE", [("k_xfer<float>", 4 * n ** 3 * 4 / 1024), ("k_fused_step<float>", 10.0)])
     out_json = tmp_path / "t.json"
     rocprof_summary.main(["traffic", str(fetch), str(write), str(out_json), str(tmp_path / "t.md"), "--kernel",
-                          "k_fused_rk4", "--n", str(n), "--prec", "f32", "--alg-bytes", "32", "--cmd-fetch", "a",
+                          "k_fused_step", "--n", str(n), "--prec", "f32", "--alg-bytes", "32", "--cmd-fetch", "a",
                           "--cmd-write", "b"])
     rec = json.load(open(out_json))
     assert rec["calibration"]["fetch_factor"] == pytest.approx(1.0)
@@ -59,10 +59,10 @@ def test_traffic_summary_fp32_reference_reads_fp64(tmp_path):
 
 def test_ambiguous_kernel_name_is_an_error(tmp_path):
     fetch = tmp_path / "f.csv"
-    _counter_csv(fetch, "FETCH_SIZE", [("k_xfer", 1.0), ("k_fused_rk4<a>", 1.0), ("k_fused_rk4<b>", 1.0)])
+    _counter_csv(fetch, "FETCH_SIZE", [("k_xfer", 1.0), ("k_fused_step<a>", 1.0), ("k_fused_step<b>", 1.0)])
     with pytest.raises(SystemExit):
         rocprof_summary.main(["traffic", str(fetch), str(fetch), str(tmp_path / "t.json"), str(tmp_path / "t.md"),
-                              "--kernel", "k_fused_rk4", "--n", "4", "--prec", "f64", "--alg-bytes", "64",
+                              "--kernel", "k_fused_step", "--n", "4", "--prec", "f64", "--alg-bytes", "64",
                               "--cmd-fetch", "a", "--cmd-write", "b"])
 
 
