@@ -2,7 +2,8 @@
 
 Representation: level l is one dense periodic array over the whole domain at spacing
 dx_l = dx_0 / 2^l, plus a boolean mask of its valid cells (the union of its boxes).
-Cells next to the valid region (26-neighbourhood, periodic) are its ghost cells.  A
+Cells within `order` cells of the valid region (Chebyshev distance, periodic; order =
+the Laplacian order of appendix A, 1 for the 7-point stencil) are its ghost cells.  A
 ghost cell that is a valid cell of another box of the same level is simply that cell
 here, so same-level ghost copies (periodic images included) are implicit and always
 current; the remaining ghost cells are set by coarse-to-fine interpolation.
@@ -86,8 +87,8 @@ def erode(mask: np.ndarray, r: int) -> np.ndarray:
     return ~dilate(~mask, r)
 
 
-def ghost_mask(valid: np.ndarray) -> np.ndarray:
-    return dilate(valid, 1) & ~valid
+def ghost_mask(valid: np.ndarray, depth: int = 1) -> np.ndarray:
+    return dilate(valid, depth) & ~valid
 
 
 def coarsen_mask(fine: np.ndarray) -> np.ndarray:
@@ -207,7 +208,7 @@ class Hierarchy:
 
     def __init__(self, n0: int, L: float, cfl: float, eta0: float, max_level: int,
                  alpha: float = 2.0, lam: float = 1.0, beta: int = 2,
-                 dtype=np.float64, check_nesting: bool = True, integrator: int = 4):
+                 dtype=np.float64, check_nesting: bool = True, integrator: int = 4, order: int = 1):
         self.n0, self.L, self.cfl, self.eta0 = n0, L, cfl, eta0
         self.max_level = max_level
         self.alpha, self.lam, self.beta = alpha, lam, beta
@@ -215,6 +216,7 @@ class Hierarchy:
         self.check_nesting = check_nesting
         self.integrator = integrator
         self.cs = stage_fractions(integrator)
+        self.order = order  # Laplacian order = ghost depth of the refined levels
         self.levels: list[Level] = []
         self.trace: list[tuple] = []
         self.tee_on = False
@@ -283,7 +285,7 @@ class Hierarchy:
         for c in range(4):
             U[c][fz, fy, fx] = interp_cells(C.U[c].astype(np.float64), fz, fy, fx).astype(self.dtype)
         L.valid = new_valid
-        L.ghost = ghost_mask(new_valid)
+        L.ghost = ghost_mask(new_valid, self.order)
         L.boxes = [tuple(b) for b in boxes]
         L.U = U
         L.Uold = None
@@ -331,9 +333,10 @@ class Hierarchy:
         with np.errstate(all="ignore"):
             if self.integrator == 4:
                 L.acc, Y = rk4_stage(s, X, L.U, L.acc if s else None, eta_n, L.dt,
-                                     1.0 / (L.dx * L.dx), self.alpha, self.lam, self.beta)
+                                     1.0 / (L.dx * L.dx), self.alpha, self.lam, self.beta, self.order)
             else:
-                Y = ssprk3_stage(s, X, L.U, eta_n, L.dt, 1.0 / (L.dx * L.dx), self.alpha, self.lam, self.beta)
+                Y = ssprk3_stage(s, X, L.U, eta_n, L.dt, 1.0 / (L.dx * L.dx), self.alpha, self.lam, self.beta,
+                                 self.order)
         if s == last:
             L.Uold, L.U, L.X, L.acc = L.U, Y, None, None
             L.k += 1
@@ -387,9 +390,10 @@ class Hierarchy:
             for s in range(len(self.cs)):
                 if self.integrator == 4:
                     acc, X = rk4_stage(s, X, S.U, acc, eta_n, S.dt, 1.0 / (S.dx * S.dx), self.alpha, self.lam,
-                                       self.beta)
+                                       self.beta, self.order)
                 else:
-                    X = ssprk3_stage(s, X, S.U, eta_n, S.dt, 1.0 / (S.dx * S.dx), self.alpha, self.lam, self.beta)
+                    X = ssprk3_stage(s, X, S.U, eta_n, S.dt, 1.0 / (S.dx * S.dx), self.alpha, self.lam, self.beta,
+                                     self.order)
         S.U = X
         S.k += 1
 

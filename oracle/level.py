@@ -2,12 +2,24 @@
 
 Test infrastructure only.  Follows the minimal example of the paper (eqs. EOM1 and
 EOM2, the ``Rhs`` kernel function of section III.A) with the Laplacian of appendix A at
-order 1 (the 7-point stencil), and integrator type 4 (classic RK4, appendix E).
+order 1, 2 or 3 (the 7-, 13- and 19-point stencils: order = ghost cells used per
+direction), and integrator type 4 (classic RK4, appendix E) or SSPRK3.
+
+The order-2 and order-3 stencils are the sums over the three axes of the standard
+fourth- and sixth-order central second differences (coefficients 4/3, -1/12, -5/2 and
+3/2, -3/20, 1/90, -49/18 per axis).  With S_r the sum of the six cells at distance r,
+
+    S_r  = ((u[x-r] + u[x+r]) + (u[y-r] + u[y+r])) + (u[z-r] + u[z+r])
+    lap1 = (S_1 - 6 u) * inv_dx2
+    lap2 = ((4/3 S_1 + (-1/12) S_2) + (-15/2) u) * inv_dx2
+    lap3 = (((3/2 S_1 + (-3/20) S_2) + 1/90 S_3) + (-49/6) u) * inv_dx2
+
+(coefficients rounded once to the storage type).
 
 Canonical operation order (both the oracle and the HIP path evaluate exactly these
 expressions, with no fused multiply-add):
 
-    lap   = ((((u[x-1] + u[x+1]) + (u[y-1] + u[y+1])) + (u[z-1] + u[z+1])) - 6 u) * inv_dx2
+    lap   = lap1, lap2 or lap3 above
     r2    = psi1*psi1 + psi2*psi2
     pot   = c_pot * (r2 - 1)
     k_psi = Pi
@@ -53,7 +65,32 @@ def lap7(u: np.ndarray, inv_dx2) -> np.ndarray:
     return ((((xm + xp) + (ym + yp)) + (zm + zp)) - t(6.0) * u) * t(inv_dx2)
 
 
-def rhs(U: np.ndarray, inv_dx2: float, c_fric: float, c_pot: float) -> np.ndarray:
+# per-order coefficients of S_1, S_2, S_3 and of the centre cell (appendix A orders 2, 3)
+LAP_COEF = {2: (4.0 / 3.0, -1.0 / 12.0, None, -15.0 / 2.0),
+            3: (3.0 / 2.0, -3.0 / 20.0, 1.0 / 90.0, -49.0 / 6.0)}
+
+
+def lap(u: np.ndarray, inv_dx2, order: int = 1) -> np.ndarray:
+    """Laplacian of appendix A at the given order (1, 2, 3: 7-, 13-, 19-point) of a
+    periodic [z, y, x] array, in the array's own precision."""
+    if order == 1:
+        return lap7(u, inv_dx2)
+    if order not in LAP_COEF:
+        raise ValueError(f"no Laplacian of order {order}")
+    t = u.dtype.type
+
+    def S(r):
+        return (((np.roll(u, r, axis=2) + np.roll(u, -r, axis=2)) + (np.roll(u, r, axis=1) + np.roll(u, -r, axis=1)))
+                + (np.roll(u, r, axis=0) + np.roll(u, -r, axis=0)))
+
+    c1, c2, c3, c0 = LAP_COEF[order]
+    acc = t(c1) * S(1) + t(c2) * S(2)
+    if order == 3:
+        acc = acc + t(c3) * S(3)
+    return (acc + t(c0) * u) * t(inv_dx2)
+
+
+def rhs(U: np.ndarray, inv_dx2: float, c_fric: float, c_pot: float, order: int = 1) -> np.ndarray:
     """f(U) for eqs. EOM1/EOM2 on a periodic lattice, in U's precision."""
     t = U.dtype.type
     p1, p2, q1, q2 = U[0], U[1], U[2], U[3]
@@ -64,13 +101,13 @@ def rhs(U: np.ndarray, inv_dx2: float, c_fric: float, c_pot: float) -> np.ndarra
     K = np.empty_like(U)
     K[0] = q1
     K[1] = q2
-    K[2] = (lap7(p1, inv_dx2) - cf * q1) - pot * p1
-    K[3] = (lap7(p2, inv_dx2) - cf * q2) - pot * p2
+    K[2] = (lap(p1, inv_dx2, order) - cf * q1) - pot * p1
+    K[3] = (lap(p2, inv_dx2, order) - cf * q2) - pot * p2
     return K
 
 
 def rk4_stage(s: int, X: np.ndarray, Un: np.ndarray, acc, eta_n: float, dt: float,
-              inv_dx2: float, alpha: float, lam: float, beta: int):
+              inv_dx2: float, alpha: float, lam: float, beta: int, order: int = 1):
     """Stage s (0-based) of classic RK4 in accumulator form.
 
     X is the stage input (U_n itself for s = 0), Un the state at the step start, acc the
@@ -80,7 +117,7 @@ def rk4_stage(s: int, X: np.ndarray, Un: np.ndarray, acc, eta_n: float, dt: floa
     st = Un.dtype
     h6, h3, h2, h1 = rk4_weights(dt)
     _, cf, cp = stage_scalars(eta_n, dt, s, alpha, lam, beta)
-    k = rhs(X, inv_dx2, cf, cp).astype(np.float64)
+    k = rhs(X, inv_dx2, cf, cp, order).astype(np.float64)
     if s == 3:
         return acc, (acc + h6 * k).astype(st)
     U64 = Un.astype(np.float64)
@@ -97,12 +134,12 @@ def rk4_stage(s: int, X: np.ndarray, Un: np.ndarray, acc, eta_n: float, dt: floa
 
 
 def ssprk3_stage(s: int, X: np.ndarray, Un: np.ndarray, eta_n: float, dt: float, inv_dx2: float,
-                 alpha: float, lam: float, beta: int) -> np.ndarray:
+                 alpha: float, lam: float, beta: int, order: int = 1) -> np.ndarray:
     """Stage s (0-based) of SSPRK3: the next stage input (s < 2) or U_{n+1} (s = 2), in
     the storage precision of Un; updates in float64 from promoted values."""
     st = Un.dtype
     _, cf, cp = stage_scalars(eta_n, dt, s, alpha, lam, beta, integrator=10)
-    k = rhs(X, inv_dx2, cf, cp).astype(np.float64)
+    k = rhs(X, inv_dx2, cf, cp, order).astype(np.float64)
     U64 = Un.astype(np.float64)
     if s == 0:
         Y = U64 + dt * k
@@ -114,18 +151,18 @@ def ssprk3_stage(s: int, X: np.ndarray, Un: np.ndarray, eta_n: float, dt: float,
 
 
 def ssprk3_step(U: np.ndarray, eta_n: float, dt: float, inv_dx2: float,
-                alpha: float, lam: float, beta: int, fill=None) -> np.ndarray:
+                alpha: float, lam: float, beta: int, fill=None, order: int = 1) -> np.ndarray:
     """One SSPRK3 step; ``fill(s, X)`` as for ``rk4_step``."""
     X = U
     for s in range(3):
         if s > 0 and fill is not None:
             fill(s, X)
-        X = ssprk3_stage(s, X, U, eta_n, dt, inv_dx2, alpha, lam, beta)
+        X = ssprk3_stage(s, X, U, eta_n, dt, inv_dx2, alpha, lam, beta, order)
     return X
 
 
 def rk4_step(U: np.ndarray, eta_n: float, dt: float, inv_dx2: float,
-             alpha: float, lam: float, beta: int, fill=None) -> np.ndarray:
+             alpha: float, lam: float, beta: int, fill=None, order: int = 1) -> np.ndarray:
     """One classic RK4 step of size dt from time eta_n; returns U_{n+1} (U's dtype).
 
     ``fill(s, X)``, if given, is called on the stage input X before stages s = 1, 2, 3
@@ -136,15 +173,15 @@ def rk4_step(U: np.ndarray, eta_n: float, dt: float, inv_dx2: float,
     for s in range(4):
         if s > 0 and fill is not None:
             fill(s, X)
-        acc, X = rk4_stage(s, X, U, acc, eta_n, dt, inv_dx2, alpha, lam, beta)
+        acc, X = rk4_stage(s, X, U, acc, eta_n, dt, inv_dx2, alpha, lam, beta, order)
     return X
 
 
 def run_single_level(U0: np.ndarray, nsteps: int, eta0: float, dt: float, dx: float,
                      alpha: float = 2.0, lam: float = 1.0, beta: int = 2,
-                     callback=None, integrator: int = 4) -> np.ndarray:
-    """nsteps steps (RK4, or SSPRK3 for integrator 3/10) of a periodic lattice; step k
-    starts at eta0 + k*dt.
+                     callback=None, integrator: int = 4, order: int = 1) -> np.ndarray:
+    """nsteps steps (RK4, or SSPRK3 for integrator 3/10) of a periodic lattice with the
+    Laplacian of the given order; step k starts at eta0 + k*dt.
 
     ``callback(k, U)`` is called after each step with the 1-based step count.
     """
@@ -154,7 +191,7 @@ def run_single_level(U0: np.ndarray, nsteps: int, eta0: float, dt: float, dx: fl
     inv_dx2 = 1.0 / (dx * dx)
     U = U0.copy()
     for k in range(nsteps):
-        U = step(U, level_time(eta0, k, dt), dt, inv_dx2, alpha, lam, beta)
+        U = step(U, level_time(eta0, k, dt), dt, inv_dx2, alpha, lam, beta, order=order)
         if callback is not None:
             callback(k + 1, U)
     return U
