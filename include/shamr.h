@@ -10,8 +10,9 @@
  *     d Pi_i  / d eta = lap psi_i - (alpha/eta) Pi_i - lambda eta^beta psi_i (psi1^2 + psi2^2 - 1)
  *
  * (the paper's example has alpha = 2, beta = 2, lambda = 1), discretised with the
- * 7-point Laplacian (appendix A, order 1) and classic RK4 (appendix E, integrator
- * type 4) on a block-structured hierarchy of levels with dx_l = (L/n0)/2^l and
+ * Laplacian of appendix A (order 1, 2 or 3: the 7-, 13- or 19-point stencil) and
+ * classic RK4 or SSPRK3 (appendix E, integrator types 4 and 3/10) on a
+ * block-structured hierarchy of levels with dx_l = (L/n0)/2^l and
  * dt_l = cfl * dx_l (section II, eq. dtscaling), advanced by Berger-Oliger subcycling
  * (section II.A, Fig. 2).
  *
@@ -81,6 +82,10 @@ typedef struct {
                            3 or 10 = SSPRK3, the three-stage strong-stability-preserving
                            method (both run its Shu-Osher form in three state buffers and
                            no accumulator, so sh_arena_bytes is smaller) */
+  int32_t lap_order;    /* Laplacian order of appendix A (the minimal example's `order`):
+                           1 (or 0) = 7-point, 2 = 13-point, 3 = 19-point stencil.  The
+                           ghost shell of refined levels is that many cells deep (and so
+                           is every ghost fill between stages); the fused step needs 1 */
 } sh_params;
 
 /* Device bytes needed for the arena of a level with the given boxes.  Returns 0 for
@@ -90,7 +95,7 @@ size_t sh_arena_bytes(const sh_params* p, int32_t lev, int32_t nboxes, const int
 /* Create a hierarchy.  `hip_stream` is a hipStream_t (NULL = default stream) that all
    device work of this hierarchy is queued on.  Errors: SH_EINVAL (n0 < 1, L or cfl not
    positive, beta < 0, max_level < 0 or > 15, blocking_factor < 2, prec not 0/1,
-   integrator not 0, 3, 4 or 10), SH_EDEVICE (no HIP device). */
+   integrator not 0, 3, 4 or 10, lap_order not 0..3), SH_EDEVICE (no HIP device). */
 sh_status sh_hierarchy_create(const sh_params* p, void* hip_stream, sh_hierarchy* out);
 
 /* Set, change or remove the box layout of level `lev` (section II: boxes whose sides
@@ -241,7 +246,8 @@ sh_status sh_profile_read(sh_hierarchy h, double* ms, int64_t* counts);
    member's result is bit-identical to stepping it alone (kernels are gather-only per
    box).  Members must not be re-laid out or destroyed while the batch exists; the batch
    borrows them.  Errors: SH_EINVAL (a member with more than one level, another
-   precision or stream, or an integrator other than RK4), SH_ESTATE from sh_batch_advance if a member's layout changed
+   precision or stream, an integrator other than RK4 or a Laplacian order other than 1),
+   SH_ESTATE from sh_batch_advance if a member's layout changed
    since the batch was built. */
 sh_status sh_batch_create(int32_t njobs, const sh_hierarchy* jobs, sh_batch* out);
 sh_status sh_batch_advance(sh_batch b);

@@ -28,7 +28,7 @@ HIP_FLAGS = [
 ]
 HOST_FLAGS = ["-O2", "-fPIC", "-std=c++17", "-ffp-contract=off", "-Wall"]
 
-HIP_SOURCES = ["kernels.hip", "kernels_fused.hip", "runtime.cpp"]
+HIP_SOURCES = ["kernels.hip", "kernels_hilap.hip", "kernels_fused.hip", "runtime.cpp"]
 HOST_SOURCES = ["cluster.cpp"]
 
 
@@ -37,7 +37,8 @@ def kernel_source_sha() -> str:
     on other kernels is not reported for these."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("kernels.hip", "kernels_fused.hip", "sh_device.h", "sh_internal.h"):
+    for f in ("kernels.hip", "kernels_hilap.hip", "kernels_fused.hip", "sh_stage.h", "sh_device.h",
+              "sh_internal.h"):
         with open(os.path.join(CSRC, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
@@ -61,20 +62,24 @@ def _run(cmd, verbose):
 
 
 def build(verbose: bool = False) -> str:
-    """Compile every source and link libshamr.so; returns the library path."""
+    """Compile every source (in parallel) and link libshamr.so; returns the library path."""
+    from concurrent.futures import ThreadPoolExecutor
     os.makedirs(BUILD, exist_ok=True)
     hipcc = _hipcc()
-    objs = []
     inc = ["-I", INCLUDE, "-I", CSRC]
+    cmds, objs = [], []
     for src in HIP_SOURCES:
         obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
         lang = ["-x", "hip"] if src.endswith(".cpp") else []
-        _run([hipcc] + HIP_FLAGS + inc + lang + ["-c", os.path.join(CSRC, src), "-o", obj], verbose)
+        cmds.append([hipcc] + HIP_FLAGS + inc + lang + ["-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
     for src in HOST_SOURCES:
         obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-        _run(["g++"] + HOST_FLAGS + inc + ["-c", os.path.join(CSRC, src), "-o", obj], verbose)
+        cmds.append(["g++"] + HOST_FLAGS + inc + ["-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
+    with ThreadPoolExecutor(max_workers=max(1, min(len(cmds), os.cpu_count() or 1))) as ex:
+        for f in [ex.submit(_run, c, verbose) for c in cmds]:
+            f.result()
     tmp = LIB + ".tmp"
     _run([hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs, verbose)
     os.replace(tmp, LIB)

@@ -10,271 +10,9 @@
 #include "sh_internal.h"
 #include "sh_launch.h"
 #include "sh_device.h"
+#include "sh_stage.h"
 
 #pragma clang fp contract(off)
-
-// ---------------------------------------------------------------------------------
-// A3: fused RK4 stage.
-//   lap   = ((((u[x-1]+u[x+1]) + (u[y-1]+u[y+1])) + (u[z-1]+u[z+1])) - 6u) * inv_dx2
-//   k_psi = Pi,  k_Pi = (lap - c_fric Pi) - c_pot (r2 - 1) psi
-//   stage 1: acc = U_n + h/6 k;   A = U_n + h/2 k
-//   stage 2: acc = acc + h/3 k;   B = U_n + h/2 k
-//   stage 3: acc = acc + h/3 k;   A = U_n + h k
-//   stage 4: B = acc + h/6 k      (the new U_n)
-// SSPRK3 (stage ids 4..6; appendix E's three-stage strong-stability-preserving method
-// in Shu-Osher form):
-//   stage 1: A = U_n + h k
-//   stage 2: B = 3/4 U_n + 1/4 (A + h k)
-//   stage 3: A = 1/3 U_n + 2/3 (B + h k)   (the new U_n)
-// The right-hand side is evaluated in T; updates in float64, rounded to T on store.
-// NT = 1 marks the streams read or written once (Pi, U_n, acc, the stage output) as
-// nontemporal so they do not push the psi planes, which neighbours re-read, out of L2.
-// ---------------------------------------------------------------------------------
-struct StagePtrs {
-  const void* X;
-  const void* Un;
-  void* Y;
-  double* acc;
-};
-
-template <typename T, int S>
-__device__ __forceinline__ StagePtrs stage_ptrs(const BoxDev& B, const LevelScal& L) {
-  constexpr int in_role = (S == 0 || S == 4) ? ROLE_UN : ((S == 2 || S == 6) ? ROLE_B : ROLE_A);
-  constexpr int out_role = (S == 1 || S == 3 || S == 5) ? ROLE_B : ROLE_A;
-  StagePtrs p;
-  p.X = slot_base(B, role_slot(in_role, L));
-  p.Un = slot_base(B, role_slot(ROLE_UN, L));
-  p.Y = slot_base(B, role_slot(out_role, L));
-  p.acc = B.acc;
-  return p;
-}
-
-// Per-cell right-hand side and stage update.  p0/p1 = psi at the cell, lap0/lap1 their
-// Laplacians, q0/q1 = Pi at the cell (all in T); e = element index of the cell.
-template <typename T, int S, bool NT>
-__device__ __forceinline__ void stage_cell(const StageScal& sc, const T* __restrict__ Un, T* __restrict__ Y,
-                                           double* __restrict__ acc, long long cs, long long e, T p0, T p1,
-                                           T q0, T q1, T lap0, T lap1, const double* un4, const double* acc4) {
-  const T cf = (T)sc.cf, cp = (T)sc.cp;
-  const T r2 = p0 * p0 + p1 * p1;
-  const T pot = cp * (r2 - (T)1.0);
-  const T kq0 = (lap0 - cf * q0) - pot * p0;
-  const T kq1 = (lap1 - cf * q1) - pot * p1;
-  const double k4[4] = {(double)q0, (double)q1, (double)kq0, (double)kq1};
-  const T xv[4] = {p0, p1, q0, q1};
-#pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    const long long ec = c * cs + e;
-    if constexpr (S == 0) {
-      const double u = (double)xv[c];
-      st<NT>(acc + ec, u + sc.h6 * k4[c]);
-      st<NT>(Y + ec, (T)(u + sc.h2 * k4[c]));
-    } else if constexpr (S == 1 || S == 2) {
-      st<NT>(acc + ec, acc4[c] + sc.h3 * k4[c]);
-      st<NT>(Y + ec, (T)(un4[c] + (S == 1 ? sc.h2 : sc.h1) * k4[c]));
-    } else if constexpr (S == 3) {
-      st<NT>(Y + ec, (T)(acc4[c] + sc.h6 * k4[c]));
-    } else if constexpr (S == 4) {
-      st<NT>(Y + ec, (T)((double)xv[c] + sc.h1 * k4[c]));
-    } else if constexpr (S == 5) {
-      st<NT>(Y + ec, (T)(0.75 * un4[c] + 0.25 * ((double)xv[c] + sc.h1 * k4[c])));
-    } else {
-      st<NT>(Y + ec, (T)((1.0 / 3.0) * un4[c] + (2.0 / 3.0) * ((double)xv[c] + sc.h1 * k4[c])));
-    }
-  }
-}
-
-// Loads of the once-read streams of a cell: U_n (RK4 stages 2, 3; SSPRK3 stages 2, 3)
-// and acc (RK4 stages 2-4).
-template <typename T, int S, bool NT>
-__device__ __forceinline__ void stage_loads(const T* __restrict__ Un, const double* __restrict__ acc, long long cs,
-                                            long long e, double* un4, double* acc4) {
-#pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    if constexpr (S == 1 || S == 2 || S == 5 || S == 6) un4[c] = (double)ld<NT>(Un + c * cs + e);
-    if constexpr (S >= 1 && S <= 3) acc4[c] = ld<NT>(acc + c * cs + e);
-  }
-}
-
-// Wave-row kernel: one wavefront per tile (a TX x 64/TX footprint of a box, marching
-// in z); psi(z-1), psi(z), psi(z+1) of both components stay in registers, x and y
-// neighbours are read through the caches.  Used for boxes narrower than 64 cells.
-template <typename T, int S, bool NT>
-__global__ __launch_bounds__(SH_BLOCK) void k_stage(const Tile* __restrict__ tiles, int ntiles,
-                                                    const BoxDev* __restrict__ boxes) {
-  const int lane = threadIdx.x & (SH_WAVE - 1);
-  const int t = xcd_remap(blockIdx.x, gridDim.x) * (SH_BLOCK / SH_WAVE) + (threadIdx.x >> 6);
-  if (t >= ntiles) return;
-  const Tile tl = tiles[t];
-  if (tl.box < 0) return;
-  const BoxDev B = boxes[tl.box];
-  const LevelScal L = *B.ls;
-  const StageScal sc = stage_scalars(L, S);
-  const StagePtrs P = stage_ptrs<T, S>(B, L);
-  const T* __restrict__ X = (const T*)P.X;
-  const T* __restrict__ Un = (const T*)P.Un;
-  T* __restrict__ Y = (T*)P.Y;
-
-  const int tx = lane & ((1 << tl.txs) - 1);
-  const int ty = lane >> tl.txs;
-  const int x0 = tl.xy & 0xffff, y0 = tl.xy >> 16;
-  const int z0 = tl.zz & 0xffff, zc = tl.zz >> 16;
-  int x = x0 + tx, y = y0 + ty;
-  const bool active = (x < B.nx) && (y < B.ny);
-  x = min(x, B.nx - 1);
-  y = min(y, B.ny - 1);
-  const long long px = B.px;
-  const long long plane = px * B.py;
-  const long long cs = B.cs;
-  const int zend = min(z0 + zc, B.nz);
-  const T idx2 = (T)sc.inv_dx2;
-
-  long long e = elem<T>(B, x, y, z0);
-  T pm0 = X[e - plane], p00 = X[e];
-  T pm1 = X[cs + e - plane], p01 = X[cs + e];
-  for (int z = z0; z < zend; ++z, e += plane) {
-    const T pp0 = X[e + plane];
-    const T pp1 = X[cs + e + plane];
-    const T xm0 = X[e - 1], xp0 = X[e + 1], ym0 = X[e - px], yp0 = X[e + px];
-    const T xm1 = X[cs + e - 1], xp1 = X[cs + e + 1], ym1 = X[cs + e - px], yp1 = X[cs + e + px];
-    const T q0 = ld<NT>(X + 2 * cs + e), q1 = ld<NT>(X + 3 * cs + e);
-    double un4[4], acc4[4];
-    stage_loads<T, S, NT>(Un, P.acc, cs, e, un4, acc4);
-    const T lap0 = ((((xm0 + xp0) + (ym0 + yp0)) + (pm0 + pp0)) - (T)6.0 * p00) * idx2;
-    const T lap1 = ((((xm1 + xp1) + (ym1 + yp1)) + (pm1 + pp1)) - (T)6.0 * p01) * idx2;
-    if (active) stage_cell<T, S, NT>(sc, Un, Y, P.acc, cs, e, p00, p01, q0, q1, lap0, lap1, un4, acc4);
-    pm0 = p00; p00 = pp0;
-    pm1 = p01; p01 = pp1;
-  }
-}
-
-// Block-row kernel for boxes at least 64 cells wide: a block of R wavefronts covers a
-// 64 x R footprint (wave w owns row y0 + w) and marches in z in lock step.  Each wave
-// keeps psi(z-1..z+1) of its own row in registers and publishes psi(z) of the row to LDS,
-// where the rows above and below (and the two x-halo columns, loaded by the edge lanes;
-// the halo rows y0-1 and y0+R, loaded by the first and last wave) are read back.  psi is
-// therefore fetched about (R+2)/R times per plane instead of five times through the caches.
-template <typename T, int S, bool NT, int R>
-__global__ __launch_bounds__(SH_WAVE * R) void k_stage_lds(const Tile* __restrict__ tiles, int ntiles,
-                                                           const BoxDev* __restrict__ boxes) {
-  __shared__ T sm[2][2][R + 2][SH_WAVE + 2];
-  const int lane = threadIdx.x & (SH_WAVE - 1);
-  const int w = threadIdx.x >> 6;
-  const int t = xcd_remap(blockIdx.x, gridDim.x);
-  if (t >= ntiles) return;  // uniform over the block
-  const Tile tl = tiles[t];
-  if (tl.box < 0) return;
-  const BoxDev B = boxes[tl.box];
-  const LevelScal L = *B.ls;
-  const StageScal sc = stage_scalars(L, S);
-  const StagePtrs P = stage_ptrs<T, S>(B, L);
-  const T* __restrict__ X = (const T*)P.X;
-  const T* __restrict__ Un = (const T*)P.Un;
-  T* __restrict__ Y = (T*)P.Y;
-
-  const int x0 = tl.xy & 0xffff, y0 = tl.xy >> 16;
-  const int z0 = tl.zz & 0xffff, zc = tl.zz >> 16;
-  const int x = x0 + lane, y = y0 + w;
-  const bool active = (x < B.nx) && (y < B.ny);
-  // rows and columns past the box edge load the ghost row/column instead (valid memory)
-  const int xl = min(x, B.nx), yl = min(y, B.ny);
-  const long long px = B.px;
-  const long long plane = px * B.py;
-  const long long cs = B.cs;
-  const int zend = min(z0 + zc, B.nz);
-  const T idx2 = (T)sc.inv_dx2;
-
-  long long e = elem<T>(B, xl, yl, z0);
-  // halo row below (wave 0) / above (wave R-1), x-halo columns (lanes 0 / 63)
-  const long long eh = (w == 0) ? elem<T>(B, xl, y0 - 1, z0) : elem<T>(B, xl, min(y0 + R, B.ny), z0);
-  const bool has_h = (w == 0) || (w == R - 1);
-  const long long ex = (lane == 0) ? elem<T>(B, x0 - 1, yl, z0) : elem<T>(B, min(x0 + SH_WAVE, B.nx), yl, z0);
-  const bool has_x = (lane == 0) || (lane == SH_WAVE - 1);
-  const int hrow = (w == 0) ? 0 : R + 1;
-  const int xcol = (lane == 0) ? 0 : SH_WAVE + 1;
-
-  T pm[2], p0[2], pp[2];
-#pragma unroll
-  for (int c = 0; c < 2; ++c) {
-    pm[c] = X[c * cs + e - plane];
-    p0[c] = X[c * cs + e];
-  }
-  int buf = 0;
-  for (int z = z0; z < zend; ++z, e += plane, buf ^= 1) {
-    const long long zo = (long long)(z - z0) * plane;
-    T hv[2] = {(T)0, (T)0}, xv[2] = {(T)0, (T)0};
-#pragma unroll
-    for (int c = 0; c < 2; ++c) {
-      pp[c] = X[c * cs + e + plane];
-      if (has_h) hv[c] = X[c * cs + eh + zo];
-      if (has_x) xv[c] = X[c * cs + ex + zo];
-    }
-    const T q0 = ld<NT>(X + 2 * cs + e), q1 = ld<NT>(X + 3 * cs + e);
-    double un4[4], acc4[4];
-    stage_loads<T, S, NT>(Un, P.acc, cs, e, un4, acc4);
-#pragma unroll
-    for (int c = 0; c < 2; ++c) {
-      sm[buf][c][w + 1][lane + 1] = p0[c];
-      if (has_h) sm[buf][c][hrow][lane + 1] = hv[c];
-      if (has_x) sm[buf][c][w + 1][xcol] = xv[c];
-    }
-    lds_barrier();
-    T lap[2];
-#pragma unroll
-    for (int c = 0; c < 2; ++c) {
-      const T xm = sm[buf][c][w + 1][lane], xp = sm[buf][c][w + 1][lane + 2];
-      const T ym = sm[buf][c][w][lane + 1], yp = sm[buf][c][w + 2][lane + 1];
-      lap[c] = ((((xm + xp) + (ym + yp)) + (pm[c] + pp[c])) - (T)6.0 * p0[c]) * idx2;
-    }
-    if (active) stage_cell<T, S, NT>(sc, Un, Y, P.acc, cs, e, p0[0], p0[1], q0, q1, lap[0], lap[1], un4, acc4);
-#pragma unroll
-    for (int c = 0; c < 2; ++c) {
-      pm[c] = p0[c];
-      p0[c] = pp[c];
-    }
-  }
-}
-
-// Right-hand side only (diagnostic): out[box][c][z][y][x] = f(U_n) at stage-1 scalars.
-template <typename T>
-__global__ __launch_bounds__(SH_BLOCK) void k_rhs(const Tile* __restrict__ tiles, int ntiles,
-                                                  const BoxDev* __restrict__ boxes,
-                                                  const long long* __restrict__ out_off,
-                                                  double* __restrict__ out) {
-  const int lane = threadIdx.x & (SH_WAVE - 1);
-  const int t = blockIdx.x * (SH_BLOCK / SH_WAVE) + (threadIdx.x >> 6);
-  if (t >= ntiles) return;
-  const Tile tl = tiles[t];
-  if (tl.box < 0) return;
-  const BoxDev B = boxes[tl.box];
-  const LevelScal L = *B.ls;
-  const StageScal sc = stage_scalars(L, 0);
-  const T* __restrict__ X = (const T*)slot_base(B, role_slot(ROLE_UN, L));
-  const int tx = lane & ((1 << tl.txs) - 1), ty = lane >> tl.txs;
-  const int x = (tl.xy & 0xffff) + tx, y = (tl.xy >> 16) + ty;
-  if (x >= B.nx || y >= B.ny) return;
-  const int z0 = tl.zz & 0xffff, zend = min(z0 + (tl.zz >> 16), B.nz);
-  const long long px = B.px, plane = px * B.py, cs = B.cs;
-  const long long nv = (long long)B.nx * B.ny * B.nz;
-  const T cf = (T)sc.cf, cp = (T)sc.cp, idx2 = (T)sc.inv_dx2;
-  for (int z = z0; z < zend; ++z) {
-    const long long e = elem<T>(B, x, y, z);
-    T lap[2];
-    for (int c = 0; c < 2; ++c) {
-      const T* u = X + c * cs;
-      lap[c] = ((((u[e - 1] + u[e + 1]) + (u[e - px] + u[e + px])) + (u[e - plane] + u[e + plane])) -
-                (T)6.0 * u[e]) * idx2;
-    }
-    const T p0 = X[e], p1 = X[cs + e], q0 = X[2 * cs + e], q1 = X[3 * cs + e];
-    const T r2 = p0 * p0 + p1 * p1;
-    const T pot = cp * (r2 - (T)1.0);
-    const long long o = out_off[tl.box] + ((long long)z * B.ny + y) * B.nx + x;
-    out[o] = (double)q0;
-    out[o + nv] = (double)q1;
-    out[o + 2 * nv] = (double)((lap[0] - cf * q0) - pot * p0);
-    out[o + 3 * nv] = (double)((lap[1] - cf * q1) - pot * p1);
-  }
-}
 
 __global__ void k_counter_inc_list(LevelScal* const* ls, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -762,50 +500,18 @@ __global__ __launch_bounds__(SH_BLOCK) void k_xfer(const BoxDev* __restrict__ bo
 // ---------------------------------------------------------------------------------
 static inline int nblk(long long n, int per) { return (int)((n + per - 1) / per); }
 
-template <typename T, int S, bool NT>
-static void stage_launch3(int kind, const Tile* tiles, int ntiles, const BoxDev* boxes, hipStream_t st) {
-  if (ntiles == 0) return;
-  if (kind == 0) {
-    hipLaunchKernelGGL((k_stage<T, S, NT>), dim3(nblk(ntiles, SH_BLOCK / SH_WAVE)), dim3(SH_BLOCK), 0, st, tiles,
-                       ntiles, boxes);
-  } else if (kind == 4) {
-    hipLaunchKernelGGL((k_stage_lds<T, S, NT, 4>), dim3(ntiles), dim3(SH_WAVE * 4), 0, st, tiles, ntiles, boxes);
-  } else {
-    hipLaunchKernelGGL((k_stage_lds<T, S, NT, 8>), dim3(ntiles), dim3(SH_WAVE * 8), 0, st, tiles, ntiles, boxes);
-  }
+// kind: 0 = wave-row tiles (k_stage), 4 or 8 = block-row tiles of that many rows;
+// order: the Laplacian order (1 here, 2 and 3 in kernels_hilap.hip)
+void sh_launch_stage(int prec, int s, int kind, bool nt, int order, const Tile* tiles, int ntiles,
+                     const BoxDev* boxes, hipStream_t st) {
+  if (order > 1) sh_launch_stage_hilap(prec, s, kind, nt, order, tiles, ntiles, boxes, st);
+  else stage_launch_radius<1>(prec, s, kind, nt, tiles, ntiles, boxes, st);
 }
 
-template <typename T, bool NT>
-static void stage_launch2(int s, int kind, const Tile* tiles, int ntiles, const BoxDev* boxes, hipStream_t st) {
-  switch (s) {
-    case 0: stage_launch3<T, 0, NT>(kind, tiles, ntiles, boxes, st); break;
-    case 1: stage_launch3<T, 1, NT>(kind, tiles, ntiles, boxes, st); break;
-    case 2: stage_launch3<T, 2, NT>(kind, tiles, ntiles, boxes, st); break;
-    case 3: stage_launch3<T, 3, NT>(kind, tiles, ntiles, boxes, st); break;
-    case 4: stage_launch3<T, 4, NT>(kind, tiles, ntiles, boxes, st); break;
-    case 5: stage_launch3<T, 5, NT>(kind, tiles, ntiles, boxes, st); break;
-    default: stage_launch3<T, 6, NT>(kind, tiles, ntiles, boxes, st); break;
-  }
-}
-
-// kind: 0 = wave-row tiles (k_stage), 4 or 8 = block-row tiles of that many rows
-void sh_launch_stage(int prec, int s, int kind, bool nt, const Tile* tiles, int ntiles, const BoxDev* boxes,
-                     hipStream_t st) {
-  if (prec == 0) {
-    if (nt) stage_launch2<double, true>(s, kind, tiles, ntiles, boxes, st);
-    else stage_launch2<double, false>(s, kind, tiles, ntiles, boxes, st);
-  } else {
-    if (nt) stage_launch2<float, true>(s, kind, tiles, ntiles, boxes, st);
-    else stage_launch2<float, false>(s, kind, tiles, ntiles, boxes, st);
-  }
-}
-
-void sh_launch_rhs(int prec, const Tile* tiles, int ntiles, const BoxDev* boxes, const long long* out_off,
+void sh_launch_rhs(int prec, int order, const Tile* tiles, int ntiles, const BoxDev* boxes, const long long* out_off,
                    double* out, hipStream_t st) {
-  const int nb = nblk(ntiles, SH_BLOCK / SH_WAVE);
-  if (nb == 0) return;
-  if (prec == 0) hipLaunchKernelGGL(k_rhs<double>, dim3(nb), dim3(SH_BLOCK), 0, st, tiles, ntiles, boxes, out_off, out);
-  else hipLaunchKernelGGL(k_rhs<float>, dim3(nb), dim3(SH_BLOCK), 0, st, tiles, ntiles, boxes, out_off, out);
+  if (order > 1) sh_launch_rhs_hilap(prec, order, tiles, ntiles, boxes, out_off, out, st);
+  else rhs_launch_radius<1>(prec, tiles, ntiles, boxes, out_off, out, st);
 }
 
 void sh_launch_counter_inc_list(LevelScal* const* ls, int n, hipStream_t st) {

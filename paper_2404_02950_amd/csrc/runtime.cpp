@@ -119,6 +119,11 @@ static int tile_zc_default(long long cells) {
 // cell instead of three plus a float64 accumulator.
 static int stages_of(const sh_params& p) { return (p.integrator == 3 || p.integrator == 10) ? 3 : 4; }
 
+// Laplacian order of appendix A (1, 2, 3: the 7-, 13-, 19-point stencil; 0 reads as 1).
+// Refined levels (and the shadow level) keep a ghost shell of that depth; level 0 keeps
+// SH_NG0 >= 3 for the fused step.
+static int lap_order_of(const sh_params& p) { return p.lap_order > 1 ? p.lap_order : 1; }
+
 static void make_geom(int prec, int ng, const std::vector<IBox>& boxes, LayoutGeom& g, bool acc) {
   g.ng = ng;
   g.esize = prec == SH_F64 ? 8 : 4;
@@ -558,7 +563,7 @@ static void build_a1(const Level& L, int depth, std::vector<CopySeg>& segs, std:
   }
 }
 
-// Parents of fine region R (fine-global coordinates, possibly one cell outside the
+// Parents of fine region R (fine-global coordinates, possibly a ghost shell outside the
 // domain) among the coarse boxes; appends InterpSegs for fine box d.  Returns false if
 // some cell (or the one-cell slope support of its parent) is not covered.
 static bool interp_segs(const Level& F, const Level& C, int d, const IBox& R, std::vector<InterpSeg>& segs,
@@ -595,7 +600,7 @@ static bool build_a2(const Level& F, const Level& C, std::vector<InterpSeg>& seg
   for (int d = 0; d < (int)F.boxes.size(); ++d) {
     const IBox& D = F.boxes[d];
     std::vector<IBox> shell;
-    subtract(grow(D, 1), D, shell);
+    subtract(grow(D, F.g.ng), D, shell);
     for (const IBox& P : shell) {
       std::vector<IBox> rem{P};
       for_images(P, F.M, F.bins, [&](int s, const int sh[3]) {
@@ -702,8 +707,10 @@ static sh_status fill(sh_hierarchy h, int l, int role, int anum) {
 static void stage(sh_hierarchy h, Level& L, int s) {
   const int prec = h->p.prec;
   const bool nt = h->tune.nt != 0;
-  if (L.stiles_b.n) sh_launch_stage(prec, s, h->tune.kind, nt, L.stiles_b.p, (int)L.stiles_b.n, L.dbox.p, h->st);
-  if (L.stiles_w.n) sh_launch_stage(prec, s, 0, nt, L.stiles_w.p, (int)L.stiles_w.n, L.dbox.p, h->st);
+  const int order = lap_order_of(h->p);
+  if (L.stiles_b.n)
+    sh_launch_stage(prec, s, h->tune.kind, nt, order, L.stiles_b.p, (int)L.stiles_b.n, L.dbox.p, h->st);
+  if (L.stiles_w.n) sh_launch_stage(prec, s, 0, nt, order, L.stiles_w.p, (int)L.stiles_w.n, L.dbox.p, h->st);
 }
 
 static sh_status check_level(sh_hierarchy h, int l) {
@@ -751,6 +758,7 @@ static sh_status check_params(const sh_params* p) {
     return fail(SH_EINVAL, "invalid parameters");
   if (p->integrator != 0 && p->integrator != 3 && p->integrator != 4 && p->integrator != 10)
     return fail(SH_EINVAL, "integrator must be 0 or 4 (RK4) or 3 or 10 (SSPRK3)");
+  if (p->lap_order < 0 || p->lap_order > 3) return fail(SH_EINVAL, "lap_order must be 0..3");
   if ((long long)p->n0 << p->max_level > 32767) return fail(SH_EINVAL, "finest level too large");
   return SH_OK;
 }
@@ -760,7 +768,7 @@ size_t sh_arena_bytes(const sh_params* p, int32_t lev, int32_t nboxes, const int
   std::vector<IBox> b;
   if (parse_boxes(*p, lev, nboxes, boxes, b) != SH_OK) return 0;
   LayoutGeom g;
-  make_geom(p->prec, lev == 0 ? SH_NG0 : 1, b, g, stages_of(*p) == 4);
+  make_geom(p->prec, lev == 0 ? SH_NG0 : lap_order_of(*p), b, g, stages_of(*p) == 4);
   return g.total;
 }
 
@@ -840,7 +848,7 @@ static sh_status set_box_tables(sh_hierarchy h, LevelScal* ls, Level& L) {
     make_stage_tiles(L.boxes, h->tune, L.g.nvalid, wt, bt);
     HIPCHK(L.stiles_w.upload(wt));
     HIPCHK(L.stiles_b.upload(bt));
-    make_fused_tiles(L.boxes, h->tune, L.g.ng, ft);
+    if (lap_order_of(h->p) == 1) make_fused_tiles(L.boxes, h->tune, L.g.ng, ft);  // fused: 7-point only
     HIPCHK(L.ftiles.upload(ft));
   }
   HIPCHK(L.xoff_valid.upload(xv));
@@ -876,7 +884,7 @@ sh_status sh_set_level_layout(sh_hierarchy h, int32_t l, int32_t nboxes, const i
     for (auto& b : N.boxes) v += b.volume();
     if (v != (long long)N.M * N.M * N.M) return fail(SH_EINVAL, "level 0 boxes must cover the domain");
   }
-  make_geom(p.prec, l == 0 ? SH_NG0 : 1, N.boxes, N.g, stages_of(p) == 4);
+  make_geom(p.prec, l == 0 ? SH_NG0 : lap_order_of(p), N.boxes, N.g, stages_of(p) == 4);
   if (!arena || arena_bytes < N.g.total) return fail(SH_ENOMEM, "arena smaller than sh_arena_bytes");
   N.base = (char*)round_up((long long)(uintptr_t)arena, 256);
   N.bins.build(N.boxes, N.M);
@@ -888,9 +896,12 @@ sh_status sh_set_level_layout(sh_hierarchy h, int32_t l, int32_t nboxes, const i
   {
     std::vector<CopySeg> cs;
     std::vector<long long> nc;
-    build_a1(N, 1, cs, nc);
+    // stage inputs: a shell as deep as the stencil; the state after a step: the whole
+    // shell (level 0's is deeper, for the fused step)
+    const int r = lap_order_of(h->p);
+    build_a1(N, r, cs, nc);
     hipError_t e = N.a1.upload(cs, nc);
-    if (e == hipSuccess && N.g.ng > 1) {
+    if (e == hipSuccess && N.g.ng > r) {
       build_a1(N, N.g.ng, cs, nc);
       e = N.a1d.upload(cs, nc);
     }
@@ -1170,7 +1181,7 @@ sh_status sh_shadow_begin(sh_hierarchy h) {
   S.dx = level_dx(p, 0) * 2.0;
   S.dt = p.cfl * S.dx;
   S.boxes = {IBox{{0, 0, 0}, {S.M - 1, S.M - 1, S.M - 1}}};
-  make_geom(p.prec, 1, S.boxes, S.g, stages_of(p) == 4);
+  make_geom(p.prec, lap_order_of(p), S.boxes, S.g, stages_of(p) == 4);
   if (hipMalloc((void**)&h->shadow_arena, S.g.total) != hipSuccess) return fail(SH_ENOMEM, "shadow level allocation");
   S.base = (char*)round_up((long long)(uintptr_t)h->shadow_arena, 256);
   S.bins.build(S.boxes, S.M);
@@ -1185,7 +1196,7 @@ sh_status sh_shadow_begin(sh_hierarchy h) {
   }
   std::vector<CopySeg> cs;
   std::vector<long long> nc;
-  build_a1(Sh, 1, cs, nc);
+  build_a1(Sh, lap_order_of(p), cs, nc);
   std::vector<AvgSeg> as;
   std::vector<long long> nc5;
   if (!build_a5(L0, Sh, as, nc5)) {
@@ -1339,7 +1350,7 @@ sh_status sh_eval_rhs(sh_hierarchy h, int32_t l, double* out_dev) {
   if (s != SH_OK || (s = not_capturing(h)) != SH_OK) return s;
   if (!out_dev) return fail(SH_EINVAL, "null output");
   Level& L = h->lev[l];
-  sh_launch_rhs(h->p.prec, L.tiles.p, L.ntiles(), L.dbox.p, L.rhs_off.p, out_dev, h->st);
+  sh_launch_rhs(h->p.prec, lap_order_of(h->p), L.tiles.p, L.ntiles(), L.dbox.p, L.rhs_off.p, out_dev, h->st);
   LAUNCHCHK();
   return SH_OK;
 }
@@ -1446,7 +1457,7 @@ sh_status sh_set_tuning(sh_hierarchy h, int32_t kind, int32_t nontemporal, int32
     make_stage_tiles(L.boxes, h->tune, L.g.nvalid, wt, bt);
     HIPCHK(L.stiles_w.upload(wt));
     HIPCHK(L.stiles_b.upload(bt));
-    make_fused_tiles(L.boxes, h->tune, L.g.ng, ft);
+    if (lap_order_of(h->p) == 1) make_fused_tiles(L.boxes, h->tune, L.g.ng, ft);  // fused: 7-point only
     HIPCHK(L.ftiles.upload(ft));
   }
   return SH_OK;
@@ -1615,9 +1626,9 @@ sh_status sh_batch_create(int32_t njobs, const sh_hierarchy* jobs, sh_batch* out
       delete b;
       return fail(SH_EINVAL, "batched jobs must be single-level hierarchies of one precision on one stream");
     }
-    if (stages_of(h->p) != 4) {
+    if (stages_of(h->p) != 4 || lap_order_of(h->p) != 1) {
       delete b;
-      return fail(SH_EINVAL, "batched jobs must use the RK4 integrator");
+      return fail(SH_EINVAL, "batched jobs must use the RK4 integrator and the 7-point Laplacian");
     }
     if (h->capturing) {
       delete b;
@@ -1687,8 +1698,9 @@ sh_status sh_batch_advance(sh_batch b) {
                              role_in[s], 2, b->st);
         LAUNCHCHK();
       }
-      if (b->btiles.n) sh_launch_stage(prec, s, b->tune.kind, nt, b->btiles.p, (int)b->btiles.n, b->boxes.p, b->st);
-      if (b->wtiles.n) sh_launch_stage(prec, s, 0, nt, b->wtiles.p, (int)b->wtiles.n, b->boxes.p, b->st);
+      if (b->btiles.n)
+        sh_launch_stage(prec, s, b->tune.kind, nt, 1, b->btiles.p, (int)b->btiles.n, b->boxes.p, b->st);
+      if (b->wtiles.n) sh_launch_stage(prec, s, 0, nt, 1, b->wtiles.p, (int)b->wtiles.n, b->boxes.p, b->st);
       LAUNCHCHK();
     }
   }

@@ -5,10 +5,16 @@
 
 #include "sh_internal.h"
 
-void sh_launch_stage(int prec, int s, int kind, bool nt, const Tile* tiles, int ntiles, const BoxDev* boxes,
-                     hipStream_t st);
-void sh_launch_rhs(int prec, const Tile* tiles, int ntiles, const BoxDev* boxes, const long long* out_off,
+// order: the Laplacian order of appendix A (1, 2, 3: 7-, 13-, 19-point stencil)
+void sh_launch_stage(int prec, int s, int kind, bool nt, int order, const Tile* tiles, int ntiles,
+                     const BoxDev* boxes, hipStream_t st);
+void sh_launch_rhs(int prec, int order, const Tile* tiles, int ntiles, const BoxDev* boxes, const long long* out_off,
                    double* out, hipStream_t st);
+// orders 2 and 3 (kernels_hilap.hip)
+void sh_launch_stage_hilap(int prec, int s, int kind, bool nt, int order, const Tile* tiles, int ntiles,
+                           const BoxDev* boxes, hipStream_t st);
+void sh_launch_rhs_hilap(int prec, int order, const Tile* tiles, int ntiles, const BoxDev* boxes,
+                         const long long* out_off, double* out, hipStream_t st);
 void sh_launch_counter_inc(LevelScal* ls, int n, hipStream_t st);
 void sh_launch_counter_inc_list(LevelScal* const* ls, int n, hipStream_t st);
 void sh_launch_ghost_copy(int prec, const CopySeg* segs, const SegBlock* blocks, int nblocks, const BoxDev* boxes,

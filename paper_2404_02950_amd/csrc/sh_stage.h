@@ -1,0 +1,383 @@
+// Per-stage kernels of the level step (internal), templated on the stencil radius H:
+// the Laplacian of appendix A at order H = 1, 2, 3 (7-, 13-, 19-point).  Included by
+// kernels.hip (H = 1) and kernels_hilap.hip (H = 2, 3), which instantiate them.
+//
+// A3: stage kernel.  With S_r the sum of the six cells at distance r,
+//   S_r   = ((u[x-r]+u[x+r]) + (u[y-r]+u[y+r])) + (u[z-r]+u[z+r])
+//   lap   = (S_1 - 6u) * inv_dx2                                           H = 1
+//         = ((4/3 S_1 + (-1/12) S_2) + (-15/2) u) * inv_dx2                  H = 2
+//         = (((3/2 S_1 + (-3/20) S_2) + 1/90 S_3) + (-49/6) u) * inv_dx2     H = 3
+//   (coefficients rounded once to T)
+//   k_psi = Pi,  k_Pi = (lap - c_fric Pi) - c_pot (r2 - 1) psi
+// RK4 (stage ids 0..3):
+//   stage 1: acc = U_n + h/6 k;   A = U_n + h/2 k
+//   stage 2: acc = acc + h/3 k;   B = U_n + h/2 k
+//   stage 3: acc = acc + h/3 k;   A = U_n + h k
+//   stage 4: B = acc + h/6 k      (the new U_n)
+// SSPRK3 (stage ids 4..6; appendix E's three-stage strong-stability-preserving method
+// in Shu-Osher form):
+//   stage 1: A = U_n + h k
+//   stage 2: B = 3/4 U_n + 1/4 (A + h k)
+//   stage 3: A = 1/3 U_n + 2/3 (B + h k)   (the new U_n)
+// The right-hand side is evaluated in T; updates in float64, rounded to T on store.
+// NT = 1 marks the streams read or written once (Pi, U_n, acc, the stage output) as
+// nontemporal so they do not push the psi planes, which neighbours re-read, out of L2.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "sh_device.h"
+#include "sh_internal.h"
+
+#pragma clang fp contract(off)
+
+// Laplacian from the per-radius neighbour sums S[r-1] and the centre value u.
+template <typename T, int H>
+__device__ __forceinline__ T lap_combine(const T (&S)[H], T u, T idx2) {
+  if constexpr (H == 1) {
+    return (S[0] - (T)6.0 * u) * idx2;
+  } else if constexpr (H == 2) {
+    return (((T)(4.0 / 3.0) * S[0] + (T)(-1.0 / 12.0) * S[1]) + (T)(-15.0 / 2.0) * u) * idx2;
+  } else {
+    static_assert(H == 3, "Laplacian orders 1, 2, 3");
+    return ((((T)(3.0 / 2.0) * S[0] + (T)(-3.0 / 20.0) * S[1]) + (T)(1.0 / 90.0) * S[2]) +
+            (T)(-49.0 / 6.0) * u) *
+           idx2;
+  }
+}
+
+struct StagePtrs {
+  const void* X;
+  const void* Un;
+  void* Y;
+  double* acc;
+};
+
+template <typename T, int S>
+__device__ __forceinline__ StagePtrs stage_ptrs(const BoxDev& B, const LevelScal& L) {
+  constexpr int in_role = (S == 0 || S == 4) ? ROLE_UN : ((S == 2 || S == 6) ? ROLE_B : ROLE_A);
+  constexpr int out_role = (S == 1 || S == 3 || S == 5) ? ROLE_B : ROLE_A;
+  StagePtrs p;
+  p.X = slot_base(B, role_slot(in_role, L));
+  p.Un = slot_base(B, role_slot(ROLE_UN, L));
+  p.Y = slot_base(B, role_slot(out_role, L));
+  p.acc = B.acc;
+  return p;
+}
+
+// Per-cell right-hand side and stage update.  p0/p1 = psi at the cell, lap0/lap1 their
+// Laplacians, q0/q1 = Pi at the cell (all in T); e = element index of the cell.
+template <typename T, int S, bool NT>
+__device__ __forceinline__ void stage_cell(const StageScal& sc, const T* __restrict__ Un, T* __restrict__ Y,
+                                           double* __restrict__ acc, long long cs, long long e, T p0, T p1,
+                                           T q0, T q1, T lap0, T lap1, const double* un4, const double* acc4) {
+  const T cf = (T)sc.cf, cp = (T)sc.cp;
+  const T r2 = p0 * p0 + p1 * p1;
+  const T pot = cp * (r2 - (T)1.0);
+  const T kq0 = (lap0 - cf * q0) - pot * p0;
+  const T kq1 = (lap1 - cf * q1) - pot * p1;
+  const double k4[4] = {(double)q0, (double)q1, (double)kq0, (double)kq1};
+  const T xv[4] = {p0, p1, q0, q1};
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const long long ec = c * cs + e;
+    if constexpr (S == 0) {
+      const double u = (double)xv[c];
+      st<NT>(acc + ec, u + sc.h6 * k4[c]);
+      st<NT>(Y + ec, (T)(u + sc.h2 * k4[c]));
+    } else if constexpr (S == 1 || S == 2) {
+      st<NT>(acc + ec, acc4[c] + sc.h3 * k4[c]);
+      st<NT>(Y + ec, (T)(un4[c] + (S == 1 ? sc.h2 : sc.h1) * k4[c]));
+    } else if constexpr (S == 3) {
+      st<NT>(Y + ec, (T)(acc4[c] + sc.h6 * k4[c]));
+    } else if constexpr (S == 4) {
+      st<NT>(Y + ec, (T)((double)xv[c] + sc.h1 * k4[c]));
+    } else if constexpr (S == 5) {
+      st<NT>(Y + ec, (T)(0.75 * un4[c] + 0.25 * ((double)xv[c] + sc.h1 * k4[c])));
+    } else {
+      st<NT>(Y + ec, (T)((1.0 / 3.0) * un4[c] + (2.0 / 3.0) * ((double)xv[c] + sc.h1 * k4[c])));
+    }
+  }
+}
+
+// Loads of the once-read streams of a cell: U_n (RK4 stages 2, 3; SSPRK3 stages 2, 3)
+// and acc (RK4 stages 2-4).
+template <typename T, int S, bool NT>
+__device__ __forceinline__ void stage_loads(const T* __restrict__ Un, const double* __restrict__ acc, long long cs,
+                                            long long e, double* un4, double* acc4) {
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    if constexpr (S == 1 || S == 2 || S == 5 || S == 6) un4[c] = (double)ld<NT>(Un + c * cs + e);
+    if constexpr (S >= 1 && S <= 3) acc4[c] = ld<NT>(acc + c * cs + e);
+  }
+}
+
+// Wave-row kernel: one wavefront per tile (a TX x 64/TX footprint of a box, marching
+// in z); psi of planes z-H..z+H of both components stay in registers, x and y
+// neighbours are read through the caches.  Used for boxes narrower than 64 cells.
+template <typename T, int S, bool NT, int H>
+__global__ __launch_bounds__(SH_BLOCK) void k_stage(const Tile* __restrict__ tiles, int ntiles,
+                                                    const BoxDev* __restrict__ boxes) {
+  const int lane = threadIdx.x & (SH_WAVE - 1);
+  const int t = xcd_remap(blockIdx.x, gridDim.x) * (SH_BLOCK / SH_WAVE) + (threadIdx.x >> 6);
+  if (t >= ntiles) return;
+  const Tile tl = tiles[t];
+  if (tl.box < 0) return;
+  const BoxDev B = boxes[tl.box];
+  const LevelScal L = *B.ls;
+  const StageScal sc = stage_scalars(L, S);
+  const StagePtrs P = stage_ptrs<T, S>(B, L);
+  const T* __restrict__ X = (const T*)P.X;
+  const T* __restrict__ Un = (const T*)P.Un;
+  T* __restrict__ Y = (T*)P.Y;
+
+  const int tx = lane & ((1 << tl.txs) - 1);
+  const int ty = lane >> tl.txs;
+  const int x0 = tl.xy & 0xffff, y0 = tl.xy >> 16;
+  const int z0 = tl.zz & 0xffff, zc = tl.zz >> 16;
+  int x = x0 + tx, y = y0 + ty;
+  const bool active = (x < B.nx) && (y < B.ny);
+  // inactive lanes work on a valid cell (its neighbours stay within the ghost shell)
+  x = min(x, B.nx - 1);
+  y = min(y, B.ny - 1);
+  const long long px = B.px;
+  const long long plane = px * B.py;
+  const long long cs = B.cs;
+  const int zend = min(z0 + zc, B.nz);
+  const T idx2 = (T)sc.inv_dx2;
+
+  long long e = elem<T>(B, x, y, z0);
+  // window: w[c][j] = psi_c at plane z - H + j
+  T w[2][2 * H + 1];
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int j = 0; j < 2 * H; ++j) w[c][j] = X[c * cs + e + (j - H) * plane];
+  for (int z = z0; z < zend; ++z, e += plane) {
+#pragma unroll
+    for (int c = 0; c < 2; ++c) w[c][2 * H] = X[c * cs + e + H * plane];
+    T Ssum[2][H];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const T* u = X + c * cs;
+#pragma unroll
+      for (int r = 1; r <= H; ++r)
+        Ssum[c][r - 1] = ((u[e - r] + u[e + r]) + (u[e - r * px] + u[e + r * px])) + (w[c][H - r] + w[c][H + r]);
+    }
+    const T q0 = ld<NT>(X + 2 * cs + e), q1 = ld<NT>(X + 3 * cs + e);
+    double un4[4], acc4[4];
+    stage_loads<T, S, NT>(Un, P.acc, cs, e, un4, acc4);
+    const T lap0 = lap_combine<T, H>(Ssum[0], w[0][H], idx2);
+    const T lap1 = lap_combine<T, H>(Ssum[1], w[1][H], idx2);
+    if (active) stage_cell<T, S, NT>(sc, Un, Y, P.acc, cs, e, w[0][H], w[1][H], q0, q1, lap0, lap1, un4, acc4);
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int j = 0; j < 2 * H; ++j) w[c][j] = w[c][j + 1];
+  }
+}
+
+// Block-row kernel for boxes at least 64 cells wide: a block of ROWS wavefronts covers a
+// 64 x ROWS footprint (wave w owns row y0 + w) and marches in z in lock step.  Each wave
+// keeps psi(z-H..z+H) of its own row in registers and publishes psi(z) of the row to
+// LDS, where the rows above and below (and the H x-halo columns on each side, loaded by
+// the edge lanes; the H halo rows on each side, loaded by the first and last waves) are
+// read back.  psi is therefore fetched about (ROWS+2H)/ROWS times per plane instead of
+// 4H+1 times through the caches.
+template <typename T, int S, bool NT, int ROWS, int H>
+__global__ __launch_bounds__(SH_WAVE * ROWS) void k_stage_lds(const Tile* __restrict__ tiles, int ntiles,
+                                                              const BoxDev* __restrict__ boxes) {
+  static_assert(H <= ROWS && H < SH_WAVE / 2, "halo loads by the edge waves and lanes");
+  __shared__ T sm[2][2][ROWS + 2 * H][SH_WAVE + 2 * H];
+  const int lane = threadIdx.x & (SH_WAVE - 1);
+  const int w = threadIdx.x >> 6;
+  const int t = xcd_remap(blockIdx.x, gridDim.x);
+  if (t >= ntiles) return;  // uniform over the block
+  const Tile tl = tiles[t];
+  if (tl.box < 0) return;
+  const BoxDev B = boxes[tl.box];
+  const LevelScal L = *B.ls;
+  const StageScal sc = stage_scalars(L, S);
+  const StagePtrs P = stage_ptrs<T, S>(B, L);
+  const T* __restrict__ X = (const T*)P.X;
+  const T* __restrict__ Un = (const T*)P.Un;
+  T* __restrict__ Y = (T*)P.Y;
+
+  const int x0 = tl.xy & 0xffff, y0 = tl.xy >> 16;
+  const int z0 = tl.zz & 0xffff, zc = tl.zz >> 16;
+  const int x = x0 + lane, y = y0 + w;
+  const bool active = (x < B.nx) && (y < B.ny);
+  // rows and columns past the box edge load the ghost rows/columns instead (valid
+  // memory: the shell is at least H deep), so the active cells next to the edge read
+  // their true neighbours from LDS
+  const int xl = min(x, B.nx + H - 1), yl = min(y, B.ny + H - 1);
+  const long long px = B.px;
+  const long long plane = px * B.py;
+  const long long cs = B.cs;
+  const int zend = min(z0 + zc, B.nz);
+  const T idx2 = (T)sc.inv_dx2;
+
+  long long e = elem<T>(B, xl, yl, z0);
+  // halo rows: waves 0..H-1 load rows y0-H.., waves ROWS-H.. load rows y0+ROWS..; when
+  // the two sets are disjoint (ROWS >= 2H) a wave holds one halo row (one address, one
+  // value per component), else the middle waves hold two
+  constexpr bool ONE_H = ROWS >= 2 * H;
+  const bool has_lo = w < H, has_hi = w >= ROWS - H;
+  const long long elo = elem<T>(B, xl, has_lo ? y0 - H + w : yl, z0);
+  const long long ehi = elem<T>(B, xl, has_hi ? min(y0 + ROWS + w - (ROWS - H), B.ny + H - 1) : yl, z0);
+  const long long eh1 = has_lo ? elo : ehi;  // ONE_H: the wave's halo row
+  const int hrow1 = has_lo ? w : w + 2 * H;
+  // x-halo columns: lanes 0..H-1 load x0-H.., lanes 64-H.. load x0+64.. (disjoint sets)
+  const bool has_x = lane < H || lane >= SH_WAVE - H;
+  const long long ex = elem<T>(B, lane < H ? x0 - H + lane : min(x0 + lane + H, B.nx + H - 1), yl, z0);
+  const int xcol = lane < H ? lane : lane + 2 * H;
+
+  T win[2][2 * H + 1];
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int j = 0; j < 2 * H; ++j) win[c][j] = X[c * cs + e + (j - H) * plane];
+  int buf = 0;
+  for (int z = z0; z < zend; ++z, e += plane, buf ^= 1) {
+    const long long zo = (long long)(z - z0) * plane;
+    T hlo[2] = {(T)0, (T)0}, hhi[2] = {(T)0, (T)0}, vx[2] = {(T)0, (T)0};
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      win[c][2 * H] = X[c * cs + e + H * plane];
+      if constexpr (ONE_H) {
+        if (has_lo || has_hi) hlo[c] = X[c * cs + eh1 + zo];
+      } else {
+        if (has_lo) hlo[c] = X[c * cs + elo + zo];
+        if (has_hi) hhi[c] = X[c * cs + ehi + zo];
+      }
+      if (has_x) vx[c] = X[c * cs + ex + zo];
+    }
+    const T q0 = ld<NT>(X + 2 * cs + e), q1 = ld<NT>(X + 3 * cs + e);
+    double un4[4], acc4[4];
+    stage_loads<T, S, NT>(Un, P.acc, cs, e, un4, acc4);
+    // LDS row j holds y = y0 - H + j, column i holds x = x0 - H + i
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      sm[buf][c][w + H][lane + H] = win[c][H];
+      if constexpr (ONE_H) {
+        if (has_lo || has_hi) sm[buf][c][hrow1][lane + H] = hlo[c];
+      } else {
+        if (has_lo) sm[buf][c][w][lane + H] = hlo[c];
+        if (has_hi) sm[buf][c][w + 2 * H][lane + H] = hhi[c];
+      }
+      if (has_x) sm[buf][c][w + H][xcol] = vx[c];
+    }
+    lds_barrier();
+    T lap[2];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      T Ssum[H];
+#pragma unroll
+      for (int r = 1; r <= H; ++r) {
+        const T xm = sm[buf][c][w + H][lane + H - r], xp = sm[buf][c][w + H][lane + H + r];
+        const T ym = sm[buf][c][w + H - r][lane + H], yp = sm[buf][c][w + H + r][lane + H];
+        Ssum[r - 1] = ((xm + xp) + (ym + yp)) + (win[c][H - r] + win[c][H + r]);
+      }
+      lap[c] = lap_combine<T, H>(Ssum, win[c][H], idx2);
+    }
+    if (active) stage_cell<T, S, NT>(sc, Un, Y, P.acc, cs, e, win[0][H], win[1][H], q0, q1, lap[0], lap[1], un4, acc4);
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int j = 0; j < 2 * H; ++j) win[c][j] = win[c][j + 1];
+  }
+}
+
+// Right-hand side only (diagnostic): out[box][c][z][y][x] = f(U_n) at stage-1 scalars.
+template <typename T, int H>
+__global__ __launch_bounds__(SH_BLOCK) void k_rhs(const Tile* __restrict__ tiles, int ntiles,
+                                                  const BoxDev* __restrict__ boxes,
+                                                  const long long* __restrict__ out_off,
+                                                  double* __restrict__ out) {
+  const int lane = threadIdx.x & (SH_WAVE - 1);
+  const int t = blockIdx.x * (SH_BLOCK / SH_WAVE) + (threadIdx.x >> 6);
+  if (t >= ntiles) return;
+  const Tile tl = tiles[t];
+  if (tl.box < 0) return;
+  const BoxDev B = boxes[tl.box];
+  const LevelScal L = *B.ls;
+  const StageScal sc = stage_scalars(L, 0);
+  const T* __restrict__ X = (const T*)slot_base(B, role_slot(ROLE_UN, L));
+  const int tx = lane & ((1 << tl.txs) - 1), ty = lane >> tl.txs;
+  const int x = (tl.xy & 0xffff) + tx, y = (tl.xy >> 16) + ty;
+  if (x >= B.nx || y >= B.ny) return;
+  const int z0 = tl.zz & 0xffff, zend = min(z0 + (tl.zz >> 16), B.nz);
+  const long long px = B.px, plane = px * B.py, cs = B.cs;
+  const long long nv = (long long)B.nx * B.ny * B.nz;
+  const T cf = (T)sc.cf, cp = (T)sc.cp, idx2 = (T)sc.inv_dx2;
+  for (int z = z0; z < zend; ++z) {
+    const long long e = elem<T>(B, x, y, z);
+    T lap[2];
+    for (int c = 0; c < 2; ++c) {
+      const T* u = X + c * cs;
+      T Ssum[H];
+#pragma unroll
+      for (int r = 1; r <= H; ++r)
+        Ssum[r - 1] = ((u[e - r] + u[e + r]) + (u[e - r * px] + u[e + r * px])) + (u[e - r * plane] + u[e + r * plane]);
+      lap[c] = lap_combine<T, H>(Ssum, u[e], idx2);
+    }
+    const T p0 = X[e], p1 = X[cs + e], q0 = X[2 * cs + e], q1 = X[3 * cs + e];
+    const T r2 = p0 * p0 + p1 * p1;
+    const T pot = cp * (r2 - (T)1.0);
+    const long long o = out_off[tl.box] + ((long long)z * B.ny + y) * B.nx + x;
+    out[o] = (double)q0;
+    out[o + nv] = (double)q1;
+    out[o + 2 * nv] = (double)((lap[0] - cf * q0) - pot * p0);
+    out[o + 3 * nv] = (double)((lap[1] - cf * q1) - pot * p1);
+  }
+}
+
+// ---------------------------------------------------------------------------------
+// Host-side launch of one stage (kind: 0 = wave-row tiles, 4 or 8 = block-row tiles of
+// that many rows) and of the diagnostic right-hand side, for stencil radius H.
+// ---------------------------------------------------------------------------------
+template <typename T, int S, bool NT, int H>
+static void stage_launch3(int kind, const Tile* tiles, int ntiles, const BoxDev* boxes, hipStream_t st) {
+  if (ntiles == 0) return;
+  if (kind == 0) {
+    hipLaunchKernelGGL((k_stage<T, S, NT, H>), dim3((ntiles + SH_BLOCK / SH_WAVE - 1) / (SH_BLOCK / SH_WAVE)),
+                       dim3(SH_BLOCK), 0, st, tiles, ntiles, boxes);
+  } else if (kind == 4) {
+    hipLaunchKernelGGL((k_stage_lds<T, S, NT, 4, H>), dim3(ntiles), dim3(SH_WAVE * 4), 0, st, tiles, ntiles, boxes);
+  } else {
+    hipLaunchKernelGGL((k_stage_lds<T, S, NT, 8, H>), dim3(ntiles), dim3(SH_WAVE * 8), 0, st, tiles, ntiles, boxes);
+  }
+}
+
+template <typename T, bool NT, int H>
+static void stage_launch2(int s, int kind, const Tile* tiles, int ntiles, const BoxDev* boxes, hipStream_t st) {
+  switch (s) {
+    case 0: stage_launch3<T, 0, NT, H>(kind, tiles, ntiles, boxes, st); break;
+    case 1: stage_launch3<T, 1, NT, H>(kind, tiles, ntiles, boxes, st); break;
+    case 2: stage_launch3<T, 2, NT, H>(kind, tiles, ntiles, boxes, st); break;
+    case 3: stage_launch3<T, 3, NT, H>(kind, tiles, ntiles, boxes, st); break;
+    case 4: stage_launch3<T, 4, NT, H>(kind, tiles, ntiles, boxes, st); break;
+    case 5: stage_launch3<T, 5, NT, H>(kind, tiles, ntiles, boxes, st); break;
+    default: stage_launch3<T, 6, NT, H>(kind, tiles, ntiles, boxes, st); break;
+  }
+}
+
+template <int H>
+static void stage_launch_radius(int prec, int s, int kind, bool nt, const Tile* tiles, int ntiles,
+                                const BoxDev* boxes, hipStream_t st) {
+  if (prec == 0) {
+    if (nt) stage_launch2<double, true, H>(s, kind, tiles, ntiles, boxes, st);
+    else stage_launch2<double, false, H>(s, kind, tiles, ntiles, boxes, st);
+  } else {
+    if (nt) stage_launch2<float, true, H>(s, kind, tiles, ntiles, boxes, st);
+    else stage_launch2<float, false, H>(s, kind, tiles, ntiles, boxes, st);
+  }
+}
+
+template <int H>
+static void rhs_launch_radius(int prec, const Tile* tiles, int ntiles, const BoxDev* boxes, const long long* out_off,
+                              double* out, hipStream_t st) {
+  const int nb = (ntiles + SH_BLOCK / SH_WAVE - 1) / (SH_BLOCK / SH_WAVE);
+  if (nb == 0) return;
+  if (prec == 0) hipLaunchKernelGGL((k_rhs<double, H>), dim3(nb), dim3(SH_BLOCK), 0, st, tiles, ntiles, boxes, out_off, out);
+  else hipLaunchKernelGGL((k_rhs<float, H>), dim3(nb), dim3(SH_BLOCK), 0, st, tiles, ntiles, boxes, out_off, out);
+}
