@@ -53,13 +53,13 @@ def traffic_from_profiles(prec: str, n: int, kname: str):
     return rec.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(U0, n: int, integrator: int = 4):
+def cpu_baseline(U0, n: int, integrator: int = 4, order: int = 1):
     """One full step of the oracle on the whole lattice, timed on this host (numpy, one
     core; about 20 s at 512^3 for RK4)."""
     from oracle.level import rk4_step, ssprk3_step
     nst, step, name = (4, rk4_step, "RK4") if integrator == 4 else (3, ssprk3_step, "SSPRK3")
     t0 = time.perf_counter()
-    step(U0, 0.1, 0.25, 1.0, 2.0, 1.0, 2)
+    step(U0, 0.1, 0.25, 1.0, 2.0, 1.0, 2, order=order)
     dt = time.perf_counter() - t0
     return {"value": nst * n ** 3 / dt, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
             "sample": f"one {name} step ({nst} stages) of the {n}^3 FP64 lattice, numpy oracle, "
@@ -83,6 +83,8 @@ def main():
                          "serve: 256 Poisson-arriving ensemble jobs")
     ap.add_argument("--integrator", type=int, default=4, choices=(3, 4, 10),
                     help="4: classic RK4 (default); 3 or 10: SSPRK3")
+    ap.add_argument("--lap-order", type=int, default=1, choices=(1, 2, 3),
+                    help="Laplacian order: 1 = 7-point (default), 2 = 13-point, 3 = 19-point (per-stage kernels)")
     ap.add_argument("--beta", type=int, default=2, help="potential exponent (2: the paper's EOM; 0: stable companion)")
     ap.add_argument("--coarse-steps", type=int, default=None)
     ap.add_argument("--tag-mode", type=int, default=1, choices=(1, 2, 3),
@@ -116,7 +118,7 @@ def main():
     prec = shamr.SH_F64 if args.prec == "f64" else shamr.SH_F32
     stream = torch.cuda.Stream()
     h = shamr.Hierarchy(n, float(n), 0.25, 0.1, 1.0, 2.0, 2, max_level=0, prec=prec, stream=stream,
-                        integrator=args.integrator)
+                        integrator=args.integrator, lap_order=args.lap_order)
     nst = 4 if args.integrator == 4 else 3
     h.set_layout(0, [(0, 0, 0, n - 1, n - 1, n - 1)])
     h.write_dense(0, U0)
@@ -166,7 +168,7 @@ def main():
         k_ms, k_n = prof["fused_step"]
         k_bytes = FUSED_BYTES[args.prec] * cells * k_n
     else:
-        kname = "rk4_stage" if nst == 4 else "ssprk3_stage"
+        kname = ("rk4_stage" if nst == 4 else "ssprk3_stage") + ("" if args.lap_order == 1 else f"_lap{args.lap_order}")
         k_ms = sum(prof[f"stage{s + 1}"][0] for s in range(nst))
         k_n = sum(prof[f"stage{s + 1}"][1] for s in range(nst))
         k_bytes = sum(sb[s] * cells * prof[f"stage{s + 1}"][1] for s in range(nst))
@@ -190,10 +192,12 @@ def main():
         "vs_baseline": None,
         "dtype": args.prec,
         "data": "synthetic",
-        "config": {"workload": f"single-level periodic {n}^3, {'RK4' if nst == 4 else 'SSPRK3'} + 7-point Laplacian, "
+        "config": {"workload": f"single-level periodic {n}^3, {'RK4' if nst == 4 else 'SSPRK3'} + "
+                               f"{ {1: 7, 2: 13, 3: 19}[args.lap_order]}-point Laplacian, "
                                f"{'FP64' if args.prec == 'f64' else 'FP32 storage / FP64 accumulation'}",
                    "lattice": n, "dx": 1.0, "dt": 0.25, "eta0": 0.1, "lambda": 1.0, "seed": args.seed,
-                   "integrator": args.integrator, "graph_steps": G if graph is not None else None},
+                   "integrator": args.integrator, "lap_order": args.lap_order,
+                   "graph_steps": G if graph is not None else None},
         "roofline": roofline,
         # the same cell-update rate priced at the bytes a one-stage-per-pass kernel must
         # move (mean over the stages), against the same peak
@@ -207,7 +211,7 @@ def main():
     }
     if not args.no_cpu_baseline and args.prec == "f64":
         log("cpu baseline (oracle, one full step)")
-        out["cpu_baseline"] = cpu_baseline(U0, n, args.integrator)
+        out["cpu_baseline"] = cpu_baseline(U0, n, args.integrator, args.lap_order)
     else:
         out["cpu_baseline"] = None
     if graph is not None:
@@ -246,12 +250,13 @@ def bench_amr(args):
                                   f"blocking factor 8, max box 64, tag buffer 2, regrid every 2 coarse steps, "
                                   f"{steps} coarse steps, beta = {args.beta}"
                                   + (f", tag mode {args.tag_mode}, te_crit {args.te_crit}" if args.tag_mode != 1 else "")
-                                  + (", SSPRK3" if args.integrator != 4 else ""),
+                                  + (", SSPRK3" if args.integrator != 4 else "")
+                                  + (f", Laplacian order {args.lap_order}" if args.lap_order != 1 else ""),
                       "seed": args.seed}}
     if args.workload == "amr256":
         prec = shamr.SH_F64 if args.prec == "f64" else shamr.SH_F32
         h, rep = workloads.run_amr(U0, levels, steps, prec=prec, beta=args.beta, log=log, tag_mode=args.tag_mode,
-                                   te_crit=args.te_crit, integrator=args.integrator)
+                                   te_crit=args.te_crit, integrator=args.integrator, lap_order=args.lap_order)
         h.close()
         out.update({"value": rep["cell_updates_per_s_end_to_end"], "dtype": args.prec, "report": rep})
     else:
