@@ -18,7 +18,13 @@ Paper passages followed:
       f = C_I + sum_d s_d (C_{I+e_d} - C_{I-e_d}) / 2,   s_d = +-1/4 the child offset,
   evaluated as ((C_I + t_x) + t_y) + t_z with t_d = (C_{I+e_d} - C_{I-e_d}) * (+-1/8).
   Temporal: C(alpha) = (1 - alpha) C_old + alpha C_new, interpolated in time first;
-  alpha = 0 and alpha = 1 take C_old and C_new themselves.  Fine sub-step j in {0, 1}
+  alpha = 0 and alpha = 1 take C_old and C_new themselves.
+  Quartic conservative (interpolation type 4, the paper's default) is read as the tensor
+  product of the 1-D conservative quartic: the quartic whose averages over the five coarse
+  cells I-2..I+2 are the coarse values, averaged over the child half-cells, which gives
+      f = C_I + t,  t = (C_{I+1} - C_{I-1}) * (+-11/64) + (C_{I+2} - C_{I-2}) * (-+3/128)
+  (upper signs for the upper child); applied along x for the 5 x 5 (y, z) neighbours of
+  the parent, then along y for the 5 z neighbours, then along z.  Fine sub-step j in {0, 1}
   at stage fraction c_s has alpha = (j + c_s) / 2; c = (0, 1/2, 1/2, 1) for RK4 and
   (0, 1, 1/2) for SSPRK3 (the three-stage method of appendix E's parameter list).
 * Synchronisation (section II.A): the fine level is averaged onto the coarse cells it
@@ -110,8 +116,38 @@ def time_interp(Cold, Cnew, alpha: float) -> np.ndarray:
     return (1.0 - alpha) * Cold.astype(np.float64) + alpha * Cnew.astype(np.float64)
 
 
-def interp_cells(C: np.ndarray, fz: np.ndarray, fy: np.ndarray, fx: np.ndarray) -> np.ndarray:
-    """Linear conservative interpolation of coarse array C at fine cells (fz, fy, fx)."""
+def _quartic_1d(cm2, cm1, c0, cp1, cp2, upper):
+    """1-D conservative quartic child average (float64): c0 + t in the canonical order."""
+    a = np.where(upper, 11.0 / 64.0, -11.0 / 64.0)
+    b = np.where(upper, -3.0 / 128.0, 3.0 / 128.0)
+    return c0 + ((cp1 - cm1) * a + (cp2 - cm2) * b)
+
+
+def interp_cells_quartic(C: np.ndarray, fz: np.ndarray, fy: np.ndarray, fx: np.ndarray) -> np.ndarray:
+    """Quartic conservative interpolation of coarse array C at fine cells (fz, fy, fx)."""
+    Mc = C.shape[0]
+    Iz, Iy, Ix = fz // 2, fy // 2, fx // 2
+    ux, uy, uz = (fx & 1) == 1, (fy & 1) == 1, (fz & 1) == 1
+
+    def at(dz, dy, dx):
+        return C[(Iz + dz) % Mc, (Iy + dy) % Mc, (Ix + dx) % Mc]
+
+    hz = []
+    for dz in range(-2, 3):
+        gy = []
+        for dy in range(-2, 3):
+            gy.append(_quartic_1d(at(dz, dy, -2), at(dz, dy, -1), at(dz, dy, 0), at(dz, dy, 1), at(dz, dy, 2), ux))
+        hz.append(_quartic_1d(gy[0], gy[1], gy[2], gy[3], gy[4], uy))
+    return _quartic_1d(hz[0], hz[1], hz[2], hz[3], hz[4], uz)
+
+
+def interp_cells(C: np.ndarray, fz: np.ndarray, fy: np.ndarray, fx: np.ndarray, kind: int = 1) -> np.ndarray:
+    """Conservative interpolation of coarse array C at fine cells (fz, fy, fx): linear
+    (kind 1) or quartic (kind 4)."""
+    if kind == 4:
+        return interp_cells_quartic(C, fz, fy, fx)
+    if kind != 1:
+        raise ValueError(f"no interpolation of type {kind}")
     Mc = C.shape[0]
     Iz, Iy, Ix = fz // 2, fy // 2, fx // 2
     sx = np.where(fx & 1, 0.125, -0.125)
@@ -124,10 +160,16 @@ def interp_cells(C: np.ndarray, fz: np.ndarray, fy: np.ndarray, fx: np.ndarray) 
     return ((c0 + tx) + ty) + tz
 
 
-def interp_support(fz, fy, fx, Mc: int) -> np.ndarray:
+def interp_support(fz, fy, fx, Mc: int, kind: int = 1) -> np.ndarray:
     """Coarse cells (as a mask) read by interp_cells at the given fine cells."""
     m = np.zeros((Mc, Mc, Mc), dtype=bool)
     Iz, Iy, Ix = fz // 2, fy // 2, fx // 2
+    if kind == 4:
+        for dz in range(-2, 3):
+            for dy in range(-2, 3):
+                for dx in range(-2, 3):
+                    m[(Iz + dz) % Mc, (Iy + dy) % Mc, (Ix + dx) % Mc] = True
+        return m
     m[Iz, Iy, Ix] = True
     for d in (-1, 1):
         m[Iz, Iy, (Ix + d) % Mc] = True
@@ -208,7 +250,8 @@ class Hierarchy:
 
     def __init__(self, n0: int, L: float, cfl: float, eta0: float, max_level: int,
                  alpha: float = 2.0, lam: float = 1.0, beta: int = 2,
-                 dtype=np.float64, check_nesting: bool = True, integrator: int = 4, order: int = 1):
+                 dtype=np.float64, check_nesting: bool = True, integrator: int = 4, order: int = 1,
+                 interp: int = 1):
         self.n0, self.L, self.cfl, self.eta0 = n0, L, cfl, eta0
         self.max_level = max_level
         self.alpha, self.lam, self.beta = alpha, lam, beta
@@ -217,6 +260,7 @@ class Hierarchy:
         self.integrator = integrator
         self.cs = stage_fractions(integrator)
         self.order = order  # Laplacian order = ghost depth of the refined levels
+        self.interp = interp  # spatial interpolation: 1 linear, 4 quartic (conservative)
         self.levels: list[Level] = []
         self.trace: list[tuple] = []
         self.tee_on = False
@@ -270,7 +314,7 @@ class Hierarchy:
             oldU = L.U
         new_valid = boxes_mask(boxes, L.M)
         if self.check_nesting:
-            need = dilate(coarsen_mask(new_valid), 1)
+            need = dilate(coarsen_mask(new_valid), 1 if self.interp == 1 else 2)
             if not np.all(C.valid[need]):
                 raise ValueError("level not nested in its coarse level")
         U = np.full((4, L.M, L.M, L.M), np.nan, dtype=self.dtype)
@@ -283,7 +327,7 @@ class Hierarchy:
         fresh = new_valid & ~old_valid
         fz, fy, fx = np.nonzero(fresh)
         for c in range(4):
-            U[c][fz, fy, fx] = interp_cells(C.U[c].astype(np.float64), fz, fy, fx).astype(self.dtype)
+            U[c][fz, fy, fx] = interp_cells(C.U[c].astype(np.float64), fz, fy, fx, self.interp).astype(self.dtype)
         L.valid = new_valid
         L.ghost = ghost_mask(new_valid, self.order)
         L.boxes = [tuple(b) for b in boxes]
@@ -299,13 +343,13 @@ class Hierarchy:
         L, C = self.levels[lev], self.levels[lev - 1]
         fz, fy, fx = np.nonzero(L.ghost)
         if self.check_nesting and fz.size:
-            sup = interp_support(fz, fy, fx, C.M)
+            sup = interp_support(fz, fy, fx, C.M, self.interp)
             if not np.all(C.valid[sup]):
                 raise ValueError("ghost interpolation reads coarse cells outside the coarse level")
         for c in (0, 1):
             Cold = C.Uold[c] if C.Uold is not None else None
             Ct = time_interp(Cold, C.U[c], alpha)
-            X[c][fz, fy, fx] = interp_cells(Ct, fz, fy, fx).astype(X.dtype)
+            X[c][fz, fy, fx] = interp_cells(Ct, fz, fy, fx, self.interp).astype(X.dtype)
 
     # ---- stepping ----------------------------------------------------------------
     def coarse_step(self):
