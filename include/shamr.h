@@ -86,6 +86,12 @@ typedef struct {
                            1 (or 0) = 7-point, 2 = 13-point, 3 = 19-point stencil.  The
                            ghost shell of refined levels is that many cells deep (and so
                            is every ghost fill between stages); the fused step needs 1 */
+  int32_t interp;       /* amr.interpolation_type of appendix E for ghost cells and new fine
+                           cells: 1 (or 0) = linear conservative, 4 = quartic conservative
+                           (the paper's default; tensor product of the 1-D conservative
+                           quartic through five coarse averages).  Quartic interpolation
+                           reads two coarse cells beyond each parent: refined levels then
+                           keep at least two ghost layers, and nesting needs that margin */
 } sh_params;
 
 /* Device bytes needed for the arena of a level with the given boxes.  Returns 0 for
@@ -95,7 +101,8 @@ size_t sh_arena_bytes(const sh_params* p, int32_t lev, int32_t nboxes, const int
 /* Create a hierarchy.  `hip_stream` is a hipStream_t (NULL = default stream) that all
    device work of this hierarchy is queued on.  Errors: SH_EINVAL (n0 < 1, L or cfl not
    positive, beta < 0, max_level < 0 or > 15, blocking_factor < 2, prec not 0/1,
-   integrator not 0, 3, 4 or 10, lap_order not 0..3), SH_EDEVICE (no HIP device). */
+   integrator not 0, 3, 4 or 10, lap_order not 0..3, interp not 0, 1 or 4), SH_EDEVICE (no
+   HIP device). */
 sh_status sh_hierarchy_create(const sh_params* p, void* hip_stream, sh_hierarchy* out);
 
 /* Set, change or remove the box layout of level `lev` (section II: boxes whose sides
@@ -103,7 +110,7 @@ sh_status sh_hierarchy_create(const sh_params* p, void* hip_stream, sh_hierarchy
    - lev == 0: the boxes must tile the whole periodic domain.  Values are unset until
      sh_write_state (unless a previous level-0 layout existed: its values are kept).
    - lev == number of levels (a new level): valid cells are interpolated from level
-     lev-1 (linear conservative, all 4 components) and the ghost cells filled; the level
+     lev-1 (sh_params.interp, all 4 components) and the ghost cells filled; the level
      starts at the time of level lev-1.
    - an existing level: cells valid in the old layout keep their values, the others are
      interpolated from level lev-1 (a regrid); ghosts are refilled.
@@ -128,9 +135,10 @@ sh_status sh_read_state(sh_hierarchy h, int32_t lev, int32_t role, double* dst, 
 
 /* Ghost fill of the psi components of buffer `role` of level `lev` (section II.A): copies
    from the level's own boxes and periodic images, then, for lev >= 1, the remaining
-   ghost cells by linear conservative interpolation (appendix E, interpolation type 1)
-   of the coarse states at the start (role 3) and end (role 0) of the coarse step,
-   linear in time with alpha = alpha_num / 4 in [0, 4]. */
+   ghost cells (as deep as the Laplacian order) by linear or quartic conservative
+   interpolation (appendix E, interpolation type 1 or 4, sh_params.interp) of the coarse
+   states at the start (role 3) and end (role 0) of the coarse step, linear in time with
+   alpha = alpha_num / 4 in [0, 4]. */
 sh_status sh_fill_ghosts(sh_hierarchy h, int32_t lev, int32_t role, int32_t alpha_num);
 
 /* One integrator step of level `lev` by dt_lev (section II.A, Fig. 2): stage 1, then

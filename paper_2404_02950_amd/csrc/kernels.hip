@@ -53,8 +53,12 @@ __global__ __launch_bounds__(SH_BLOCK) void k_ghost_copy(const CopySeg* __restri
 // ---------------------------------------------------------------------------------
 // A2: coarse->fine ghost interpolation of the psi components.  Time first:
 //   C(alpha) = (1 - alpha) C_old + alpha C_new  (alpha = 0, 1: the stored state itself)
-// then linear conservative space interpolation with central slopes:
+// then linear conservative space interpolation with central slopes (type 1):
 //   f = ((C_I + t_x) + t_y) + t_z,  t_d = (C_{I+e_d} - C_{I-e_d}) * (+-1/8)
+// or quartic conservative (type 4): the 1-D conservative quartic through the averages of
+// the five coarse cells I-2..I+2, averaged over the child half-cell,
+//   q(c) = c_0 + ((c_1 - c_-1) * (+-11/64) + (c_2 - c_-2) * (-+3/128)),
+// applied along x for the 5 x 5 (y, z) neighbours, then along y, then along z.
 // Arithmetic in float64, rounded to T on store.
 // ---------------------------------------------------------------------------------
 template <typename T>
@@ -81,6 +85,33 @@ __device__ __forceinline__ double interp_one(const BoxDev& C, const T* Cold, con
 }
 
 template <typename T>
+__device__ __forceinline__ double interp_quartic(const BoxDev& C, const T* Cold, const T* Cnew, int ci, int cj,
+                                                 int ck, int fx, int fy, int fz, int anum) {
+  const double a = 0.25 * (double)anum;
+  const long long px = C.px, plane = px * C.py;
+  const double ax = (fx & 1) ? 11.0 / 64.0 : -11.0 / 64.0, bx = (fx & 1) ? -3.0 / 128.0 : 3.0 / 128.0;
+  const double ay = (fy & 1) ? 11.0 / 64.0 : -11.0 / 64.0, by = (fy & 1) ? -3.0 / 128.0 : 3.0 / 128.0;
+  const double az = (fz & 1) ? 11.0 / 64.0 : -11.0 / 64.0, bz = (fz & 1) ? -3.0 / 128.0 : 3.0 / 128.0;
+  const long long e0 = elem<T>(C, ci, cj, ck);
+  double hz[5];
+#pragma unroll
+  for (int dz = 0; dz < 5; ++dz) {
+    double gy[5];
+#pragma unroll
+    for (int dy = 0; dy < 5; ++dy) {
+      const long long e = e0 + (dz - 2) * plane + (dy - 2) * px;
+      const double cm2 = tinterp(Cold, Cnew, e - 2, anum, a), cm1 = tinterp(Cold, Cnew, e - 1, anum, a);
+      const double c0 = tinterp(Cold, Cnew, e, anum, a);
+      const double cp1 = tinterp(Cold, Cnew, e + 1, anum, a), cp2 = tinterp(Cold, Cnew, e + 2, anum, a);
+      gy[dy] = c0 + ((cp1 - cm1) * ax + (cp2 - cm2) * bx);
+    }
+    hz[dz] = gy[2] + ((gy[3] - gy[1]) * ay + (gy[4] - gy[0]) * by);
+  }
+  return hz[2] + ((hz[3] - hz[1]) * az + (hz[4] - hz[0]) * bz);
+}
+
+// IT: 1 = linear conservative, 4 = quartic conservative (reads two coarse ghost layers)
+template <typename T, int IT>
 __global__ __launch_bounds__(SH_BLOCK) void k_ghost_interp(const InterpSeg* __restrict__ segs,
                                                            const SegBlock* __restrict__ blocks,
                                                            const BoxDev* __restrict__ fboxes,
@@ -104,7 +135,9 @@ __global__ __launch_bounds__(SH_BLOCK) void k_ghost_interp(const InterpSeg* __re
   const int ci = (fx >> 1) + s.cshift[0], cj = (fy >> 1) + s.cshift[1], ck = (fz >> 1) + s.cshift[2];
   const long long ed = elem<T>(F, s.flo[0] + i, s.flo[1] + j, s.flo[2] + k);
   for (int comp = 0; comp < ncomp; ++comp) {
-    const double v = interp_one<T>(C, Cold + comp * C.cs, Cnew + comp * C.cs, ci, cj, ck, fx, fy, fz, anum);
+    const double v = IT == 4
+                         ? interp_quartic<T>(C, Cold + comp * C.cs, Cnew + comp * C.cs, ci, cj, ck, fx, fy, fz, anum)
+                         : interp_one<T>(C, Cold + comp * C.cs, Cnew + comp * C.cs, ci, cj, ck, fx, fy, fz, anum);
     dst[comp * F.cs + ed] = (T)v;
   }
 }
@@ -533,16 +566,24 @@ void sh_launch_ghost_copy(int prec, const CopySeg* segs, const SegBlock* blocks,
     hipLaunchKernelGGL(k_ghost_copy<float>, dim3(nblocks), dim3(SH_BLOCK), 0, st, segs, blocks, boxes, role, ncomp);
 }
 
-void sh_launch_ghost_interp(int prec, const InterpSeg* segs, const SegBlock* blocks, int nblocks,
+template <int IT>
+static void ghost_interp_launch(int prec, const InterpSeg* segs, const SegBlock* blocks, int nblocks,
+                                const BoxDev* fboxes, const BoxDev* cboxes, int role, int anum, int ncomp,
+                                hipStream_t st) {
+  if (prec == 0)
+    hipLaunchKernelGGL((k_ghost_interp<double, IT>), dim3(nblocks), dim3(SH_BLOCK), 0, st, segs, blocks, fboxes, cboxes,
+                       role, anum, ncomp);
+  else
+    hipLaunchKernelGGL((k_ghost_interp<float, IT>), dim3(nblocks), dim3(SH_BLOCK), 0, st, segs, blocks, fboxes, cboxes,
+                       role, anum, ncomp);
+}
+
+void sh_launch_ghost_interp(int prec, int interp, const InterpSeg* segs, const SegBlock* blocks, int nblocks,
                             const BoxDev* fboxes, const BoxDev* cboxes, int role, int anum, int ncomp,
                             hipStream_t st) {
   if (nblocks == 0) return;
-  if (prec == 0)
-    hipLaunchKernelGGL(k_ghost_interp<double>, dim3(nblocks), dim3(SH_BLOCK), 0, st, segs, blocks, fboxes, cboxes, role,
-                       anum, ncomp);
-  else
-    hipLaunchKernelGGL(k_ghost_interp<float>, dim3(nblocks), dim3(SH_BLOCK), 0, st, segs, blocks, fboxes, cboxes, role,
-                       anum, ncomp);
+  if (interp == 4) ghost_interp_launch<4>(prec, segs, blocks, nblocks, fboxes, cboxes, role, anum, ncomp, st);
+  else ghost_interp_launch<1>(prec, segs, blocks, nblocks, fboxes, cboxes, role, anum, ncomp, st);
 }
 
 void sh_launch_avgdown(int prec, const AvgSeg* segs, const SegBlock* blocks, int nblocks, const BoxDev* cboxes,

@@ -124,6 +124,14 @@ static int stages_of(const sh_params& p) { return (p.integrator == 3 || p.integr
 // SH_NG0 >= 3 for the fused step.
 static int lap_order_of(const sh_params& p) { return p.lap_order > 1 ? p.lap_order : 1; }
 
+// Spatial interpolation of appendix E: 1 = linear conservative (0 reads as 1), 4 = quartic
+// conservative.  Its coarse support reaches 1 or 2 coarse cells beyond the parent, so with
+// quartic interpolation refined levels keep at least two ghost layers (a level is the
+// coarse level of the next one).
+static int interp_of(const sh_params& p) { return p.interp == 4 ? 4 : 1; }
+static int interp_reach(const sh_params& p) { return interp_of(p) == 4 ? 2 : 1; }
+static int refined_ng(const sh_params& p) { return std::max(lap_order_of(p), interp_reach(p)); }
+
 static void make_geom(int prec, int ng, const std::vector<IBox>& boxes, LayoutGeom& g, bool acc) {
   g.ng = ng;
   g.esize = prec == SH_F64 ? 8 : 4;
@@ -566,7 +574,7 @@ static void build_a1(const Level& L, int depth, std::vector<CopySeg>& segs, std:
 // Parents of fine region R (fine-global coordinates, possibly a ghost shell outside the
 // domain) among the coarse boxes; appends InterpSegs for fine box d.  Returns false if
 // some cell (or the one-cell slope support of its parent) is not covered.
-static bool interp_segs(const Level& F, const Level& C, int d, const IBox& R, std::vector<InterpSeg>& segs,
+static bool interp_segs(const Level& F, const Level& C, int d, const IBox& R, int reach, std::vector<InterpSeg>& segs,
                         std::vector<long long>& nc) {
   const IBox Pc = coarsen(R);
   long long covered = 0;
@@ -590,17 +598,21 @@ static bool interp_segs(const Level& F, const Level& C, int d, const IBox& R, st
     covered += sub.volume();
   });
   if (covered != R.volume()) return false;
-  const IBox sup = grow(Pc, 1);
+  const IBox sup = grow(Pc, reach);
   return covered_volume(sup, C.M, C.bins, C.boxes) == sup.volume();
 }
 
-static bool build_a2(const Level& F, const Level& C, std::vector<InterpSeg>& segs, std::vector<long long>& nc) {
+// Coarse/fine ghost cells of F to a depth of `depth` cells (the stencil's reach; deeper
+// ghost layers are only ever read as same-level copies), interpolated with coarse support
+// `reach` cells around each parent.
+static bool build_a2(const Level& F, const Level& C, int depth, int reach, std::vector<InterpSeg>& segs,
+                     std::vector<long long>& nc) {
   segs.clear();
   nc.clear();
   for (int d = 0; d < (int)F.boxes.size(); ++d) {
     const IBox& D = F.boxes[d];
     std::vector<IBox> shell;
-    subtract(grow(D, F.g.ng), D, shell);
+    subtract(grow(D, depth), D, shell);
     for (const IBox& P : shell) {
       std::vector<IBox> rem{P};
       for_images(P, F.M, F.bins, [&](int s, const int sh[3]) {
@@ -610,7 +622,7 @@ static bool build_a2(const Level& F, const Level& C, std::vector<InterpSeg>& seg
         rem.swap(nxt);
       });
       for (const IBox& R : rem)
-        if (!interp_segs(F, C, d, R, segs, nc)) return false;
+        if (!interp_segs(F, C, d, R, reach, segs, nc)) return false;
     }
   }
   return true;
@@ -651,7 +663,7 @@ static sh_status build_links(sh_hierarchy h, int l) {
   std::vector<InterpSeg> is;
   std::vector<AvgSeg> as;
   std::vector<long long> nc, nc5;
-  if (!build_a2(F, C, is, nc) || !build_a5(F, C, as, nc5)) {
+  if (!build_a2(F, C, lap_order_of(h->p), interp_reach(h->p), is, nc) || !build_a5(F, C, as, nc5)) {
     F.stale = true;
     F.a2.release();
     F.a5.release();
@@ -690,7 +702,7 @@ static sh_status coarse_fine_fill(sh_hierarchy h, int l, int role, int anum) {
   Level& L = h->lev[l];
   h->rec(3, l, role, anum);
   hipEvent_t ev = h->prof_begin();
-  sh_launch_ghost_interp(h->p.prec, L.a2.segs.p, L.a2.blocks.p, L.a2.nblocks(), L.dbox.p, h->lev[l - 1].dbox.p, role,
+  sh_launch_ghost_interp(h->p.prec, interp_of(h->p), L.a2.segs.p, L.a2.blocks.p, L.a2.nblocks(), L.dbox.p, h->lev[l - 1].dbox.p, role,
                          anum, 2, h->st);
   h->prof_end(ev, 5);
   LAUNCHCHK();
@@ -759,6 +771,7 @@ static sh_status check_params(const sh_params* p) {
   if (p->integrator != 0 && p->integrator != 3 && p->integrator != 4 && p->integrator != 10)
     return fail(SH_EINVAL, "integrator must be 0 or 4 (RK4) or 3 or 10 (SSPRK3)");
   if (p->lap_order < 0 || p->lap_order > 3) return fail(SH_EINVAL, "lap_order must be 0..3");
+  if (p->interp != 0 && p->interp != 1 && p->interp != 4) return fail(SH_EINVAL, "interp must be 0, 1 or 4");
   if ((long long)p->n0 << p->max_level > 32767) return fail(SH_EINVAL, "finest level too large");
   return SH_OK;
 }
@@ -768,7 +781,7 @@ size_t sh_arena_bytes(const sh_params* p, int32_t lev, int32_t nboxes, const int
   std::vector<IBox> b;
   if (parse_boxes(*p, lev, nboxes, boxes, b) != SH_OK) return 0;
   LayoutGeom g;
-  make_geom(p->prec, lev == 0 ? SH_NG0 : lap_order_of(*p), b, g, stages_of(*p) == 4);
+  make_geom(p->prec, lev == 0 ? SH_NG0 : refined_ng(*p), b, g, stages_of(*p) == 4);
   return g.total;
 }
 
@@ -884,7 +897,7 @@ sh_status sh_set_level_layout(sh_hierarchy h, int32_t l, int32_t nboxes, const i
     for (auto& b : N.boxes) v += b.volume();
     if (v != (long long)N.M * N.M * N.M) return fail(SH_EINVAL, "level 0 boxes must cover the domain");
   }
-  make_geom(p.prec, l == 0 ? SH_NG0 : lap_order_of(p), N.boxes, N.g, stages_of(p) == 4);
+  make_geom(p.prec, l == 0 ? SH_NG0 : refined_ng(p), N.boxes, N.g, stages_of(p) == 4);
   if (!arena || arena_bytes < N.g.total) return fail(SH_ENOMEM, "arena smaller than sh_arena_bytes");
   N.base = (char*)round_up((long long)(uintptr_t)arena, 256);
   N.bins.build(N.boxes, N.M);
@@ -925,7 +938,7 @@ sh_status sh_set_level_layout(sh_hierarchy h, int32_t l, int32_t nboxes, const i
         });
       }
       for (const IBox& R : rem)
-        if (!interp_segs(N, C, d, R, is, nc)) {
+        if (!interp_segs(N, C, d, R, interp_reach(p), is, nc)) {
           N.release();
           return fail(SH_ENEST, "level " + std::to_string(l) + " not nested in level " + std::to_string(l - 1));
         }
@@ -974,7 +987,7 @@ sh_status sh_set_level_layout(sh_hierarchy h, int32_t l, int32_t nboxes, const i
     // four components (the stepping path keeps only the psi pair there)
     s = same_level_fill(h, l - 1, ROLE_UN, 4);
     if (s != SH_OK) return s;
-    sh_launch_ghost_interp(p.prec, fresh.segs.p, fresh.blocks.p, fresh.nblocks(), N.dbox.p, h->lev[l - 1].dbox.p,
+    sh_launch_ghost_interp(p.prec, interp_of(p), fresh.segs.p, fresh.blocks.p, fresh.nblocks(), N.dbox.p, h->lev[l - 1].dbox.p,
                            ROLE_UN, 4, 4, h->st);
     LAUNCHCHK();
   }

@@ -19,7 +19,8 @@ void sh_launch_counter_inc(LevelScal* ls, int n, hipStream_t st);
 void sh_launch_counter_inc_list(LevelScal* const* ls, int n, hipStream_t st);
 void sh_launch_ghost_copy(int prec, const CopySeg* segs, const SegBlock* blocks, int nblocks, const BoxDev* boxes,
                           int role, int ncomp, hipStream_t st);
-void sh_launch_ghost_interp(int prec, const InterpSeg* segs, const SegBlock* blocks, int nblocks,
+// interp: 1 = linear conservative, 4 = quartic conservative
+void sh_launch_ghost_interp(int prec, int interp, const InterpSeg* segs, const SegBlock* blocks, int nblocks,
                             const BoxDev* fboxes, const BoxDev* cboxes, int role, int anum, int ncomp,
                             hipStream_t st);
 void sh_launch_avgdown(int prec, const AvgSeg* segs, const SegBlock* blocks, int nblocks, const BoxDev* cboxes,
