@@ -2,8 +2,9 @@
 
 Representation: level l is one dense periodic array over the whole domain at spacing
 dx_l = dx_0 / 2^l, plus a boolean mask of its valid cells (the union of its boxes).
-Cells within `order` cells of the valid region (Chebyshev distance, periodic; order =
-the Laplacian order of appendix A, 1 for the 7-point stencil) are its ghost cells.  A
+Cells within `depth` cells of the valid region (Chebyshev distance, periodic; depth =
+the widest stencil: the Laplacian order of appendix A, 1 for the 7-point stencil, or the
+Kreiss-Oliger dissipation order) are its ghost cells.  A
 ghost cell that is a valid cell of another box of the same level is simply that cell
 here, so same-level ghost copies (periodic images included) are implicit and always
 current; the remaining ghost cells are set by coarse-to-fine interpolation.
@@ -60,7 +61,7 @@ from __future__ import annotations
 import numpy as np
 
 from .scalars import level_dt, level_dx, level_time, int_power, stage_fractions
-from .level import rk4_stage, ssprk3_stage
+from .level import ko_coef, rk4_stage, ssprk3_stage
 from .tagging import tag_cells
 from .energy import energy as _energy
 
@@ -251,7 +252,7 @@ class Hierarchy:
     def __init__(self, n0: int, L: float, cfl: float, eta0: float, max_level: int,
                  alpha: float = 2.0, lam: float = 1.0, beta: int = 2,
                  dtype=np.float64, check_nesting: bool = True, integrator: int = 4, order: int = 1,
-                 interp: int = 1):
+                 interp: int = 1, ko_order: int = 0, ko_eps: float = 0.0):
         self.n0, self.L, self.cfl, self.eta0 = n0, L, cfl, eta0
         self.max_level = max_level
         self.alpha, self.lam, self.beta = alpha, lam, beta
@@ -261,6 +262,10 @@ class Hierarchy:
         self.cs = stage_fractions(integrator)
         self.order = order  # Laplacian order = ghost depth of the refined levels
         self.interp = interp  # spatial interpolation: 1 linear, 4 quartic (conservative)
+        # Kreiss-Oliger dissipation (order 2 or 3, 0 = off): it stencils every component,
+        # so fills then cover Pi too, and ghost shells are as deep as the widest stencil
+        self.ko_order, self.ko_eps = ko_order, ko_eps
+        self.depth = max(order, ko_order)
         self.levels: list[Level] = []
         self.trace: list[tuple] = []
         self.tee_on = False
@@ -329,7 +334,7 @@ class Hierarchy:
         for c in range(4):
             U[c][fz, fy, fx] = interp_cells(C.U[c].astype(np.float64), fz, fy, fx, self.interp).astype(self.dtype)
         L.valid = new_valid
-        L.ghost = ghost_mask(new_valid, self.order)
+        L.ghost = ghost_mask(new_valid, self.depth)
         L.boxes = [tuple(b) for b in boxes]
         L.U = U
         L.Uold = None
@@ -346,7 +351,7 @@ class Hierarchy:
             sup = interp_support(fz, fy, fx, C.M, self.interp)
             if not np.all(C.valid[sup]):
                 raise ValueError("ghost interpolation reads coarse cells outside the coarse level")
-        for c in (0, 1):
+        for c in ((0, 1, 2, 3) if self.ko_order else (0, 1)):
             Cold = C.Uold[c] if C.Uold is not None else None
             Ct = time_interp(Cold, C.U[c], alpha)
             X[c][fz, fy, fx] = interp_cells(Ct, fz, fy, fx, self.interp).astype(X.dtype)
@@ -374,18 +379,22 @@ class Hierarchy:
         eta_n = level_time(self.eta0, L.k, L.dt)
         X = L.U if s == 0 else L.X
         last = len(self.cs) - 1
+        ko = self._ko(L.dx)
         with np.errstate(all="ignore"):
             if self.integrator == 4:
                 L.acc, Y = rk4_stage(s, X, L.U, L.acc if s else None, eta_n, L.dt,
-                                     1.0 / (L.dx * L.dx), self.alpha, self.lam, self.beta, self.order)
+                                     1.0 / (L.dx * L.dx), self.alpha, self.lam, self.beta, self.order, ko)
             else:
                 Y = ssprk3_stage(s, X, L.U, eta_n, L.dt, 1.0 / (L.dx * L.dx), self.alpha, self.lam, self.beta,
-                                 self.order)
+                                 self.order, ko)
         if s == last:
             L.Uold, L.U, L.X, L.acc = L.U, Y, None, None
             L.k += 1
         else:
             L.X = Y
+
+    def _ko(self, dx: float):
+        return (self.ko_order, ko_coef(self.ko_order, self.ko_eps, dx)) if self.ko_order else None
 
     def average_down(self, fine: int):
         F, C = self.levels[fine], self.levels[fine - 1]
@@ -430,14 +439,15 @@ class Hierarchy:
             raise ValueError("the shadow takes a single step")
         eta_n = level_time(self.eta0, S.k, S.dt)
         X, acc = S.U, None
+        ko = self._ko(S.dx)
         with np.errstate(all="ignore"):
             for s in range(len(self.cs)):
                 if self.integrator == 4:
                     acc, X = rk4_stage(s, X, S.U, acc, eta_n, S.dt, 1.0 / (S.dx * S.dx), self.alpha, self.lam,
-                                       self.beta, self.order)
+                                       self.beta, self.order, ko)
                 else:
                     X = ssprk3_stage(s, X, S.U, eta_n, S.dt, 1.0 / (S.dx * S.dx), self.alpha, self.lam, self.beta,
-                                     self.order)
+                                     self.order, ko)
         S.U = X
         S.k += 1
 

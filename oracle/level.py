@@ -16,14 +16,25 @@ fourth- and sixth-order central second differences (coefficients 4/3, -1/12, -5/
 
 (coefficients rounded once to the storage type).
 
+Kreiss-Oliger dissipation (section II, "Kreiss-Oliger dissipation"): the operator
+(-1)^((p+3)/2) eps dx^p / 2^(p+1) (d^(p+1)/dx^(p+1) + ...) is added to the right-hand side
+of every component (psi and Pi), with the dissipation order d = 2 or 3 (the ghost cells it
+needs) read as p = 2d - 1 and the (p+1)-st derivatives as the standard central
+differences (1, -4, 6, -4, 1) / dx^4 and (1, -6, 15, -20, 15, -6, 1) / dx^6, so that
+
+    K_2 = (S_2 + (-4) S_1) + 18 u                         Q = (-eps / (16 dx)) K_2
+    K_3 = ((S_3 + (-6) S_2) + 15 S_1) + (-60) u           Q = ( eps / (64 dx)) K_3
+
+with the coefficient formed in float64 and rounded once to the storage type.
+
 Canonical operation order (both the oracle and the HIP path evaluate exactly these
 expressions, with no fused multiply-add):
 
     lap   = lap1, lap2 or lap3 above
     r2    = psi1*psi1 + psi2*psi2
     pot   = c_pot * (r2 - 1)
-    k_psi = Pi
-    k_Pi  = (lap - c_fric * Pi) - pot * psi
+    k_psi = Pi                                  (+ Q(psi) with dissipation)
+    k_Pi  = (lap - c_fric * Pi) - pot * psi     (+ Q(Pi) with dissipation)
 
 and RK4 in accumulator form (U_n the state at the step start, h = dt):
 
@@ -70,6 +81,33 @@ LAP_COEF = {2: (4.0 / 3.0, -1.0 / 12.0, None, -15.0 / 2.0),
             3: (3.0 / 2.0, -3.0 / 20.0, 1.0 / 90.0, -49.0 / 6.0)}
 
 
+def _S(u: np.ndarray, r: int) -> np.ndarray:
+    """Sum of the six cells at distance r, ((x-r + x+r) + (y-r + y+r)) + (z-r + z+r)."""
+    return (((np.roll(u, r, axis=2) + np.roll(u, -r, axis=2)) + (np.roll(u, r, axis=1) + np.roll(u, -r, axis=1)))
+            + (np.roll(u, r, axis=0) + np.roll(u, -r, axis=0)))
+
+
+def ko_coef(ko_order: int, eps: float, dx: float) -> float:
+    """Coefficient of the Kreiss-Oliger sum K for dissipation order 2 (p = 3) or 3 (p = 5)."""
+    if ko_order == 2:
+        return -eps / (16.0 * dx)
+    if ko_order == 3:
+        return eps / (64.0 * dx)
+    raise ValueError(f"no dissipation of order {ko_order}")
+
+
+def ko_term(u: np.ndarray, ko_order: int, coef) -> np.ndarray:
+    """Kreiss-Oliger term coef * K of a periodic array, in its own precision."""
+    t = u.dtype.type
+    if ko_order == 2:
+        K = (_S(u, 2) + t(-4.0) * _S(u, 1)) + t(18.0) * u
+    elif ko_order == 3:
+        K = ((_S(u, 3) + t(-6.0) * _S(u, 2)) + t(15.0) * _S(u, 1)) + t(-60.0) * u
+    else:
+        raise ValueError(f"no dissipation of order {ko_order}")
+    return t(coef) * K
+
+
 def lap(u: np.ndarray, inv_dx2, order: int = 1) -> np.ndarray:
     """Laplacian of appendix A at the given order (1, 2, 3: 7-, 13-, 19-point) of a
     periodic [z, y, x] array, in the array's own precision."""
@@ -79,19 +117,16 @@ def lap(u: np.ndarray, inv_dx2, order: int = 1) -> np.ndarray:
         raise ValueError(f"no Laplacian of order {order}")
     t = u.dtype.type
 
-    def S(r):
-        return (((np.roll(u, r, axis=2) + np.roll(u, -r, axis=2)) + (np.roll(u, r, axis=1) + np.roll(u, -r, axis=1)))
-                + (np.roll(u, r, axis=0) + np.roll(u, -r, axis=0)))
-
     c1, c2, c3, c0 = LAP_COEF[order]
-    acc = t(c1) * S(1) + t(c2) * S(2)
+    acc = t(c1) * _S(u, 1) + t(c2) * _S(u, 2)
     if order == 3:
-        acc = acc + t(c3) * S(3)
+        acc = acc + t(c3) * _S(u, 3)
     return (acc + t(c0) * u) * t(inv_dx2)
 
 
-def rhs(U: np.ndarray, inv_dx2: float, c_fric: float, c_pot: float, order: int = 1) -> np.ndarray:
-    """f(U) for eqs. EOM1/EOM2 on a periodic lattice, in U's precision."""
+def rhs(U: np.ndarray, inv_dx2: float, c_fric: float, c_pot: float, order: int = 1, ko=None) -> np.ndarray:
+    """f(U) for eqs. EOM1/EOM2 on a periodic lattice, in U's precision; ``ko`` = (dissipation
+    order, coefficient from ko_coef) adds Kreiss-Oliger dissipation to every component."""
     t = U.dtype.type
     p1, p2, q1, q2 = U[0], U[1], U[2], U[3]
     cf = t(c_fric)
@@ -103,11 +138,14 @@ def rhs(U: np.ndarray, inv_dx2: float, c_fric: float, c_pot: float, order: int =
     K[1] = q2
     K[2] = (lap(p1, inv_dx2, order) - cf * q1) - pot * p1
     K[3] = (lap(p2, inv_dx2, order) - cf * q2) - pot * p2
+    if ko is not None and ko[0]:
+        for c in range(4):
+            K[c] = K[c] + ko_term(U[c], ko[0], ko[1])
     return K
 
 
 def rk4_stage(s: int, X: np.ndarray, Un: np.ndarray, acc, eta_n: float, dt: float,
-              inv_dx2: float, alpha: float, lam: float, beta: int, order: int = 1):
+              inv_dx2: float, alpha: float, lam: float, beta: int, order: int = 1, ko=None):
     """Stage s (0-based) of classic RK4 in accumulator form.
 
     X is the stage input (U_n itself for s = 0), Un the state at the step start, acc the
@@ -117,7 +155,7 @@ def rk4_stage(s: int, X: np.ndarray, Un: np.ndarray, acc, eta_n: float, dt: floa
     st = Un.dtype
     h6, h3, h2, h1 = rk4_weights(dt)
     _, cf, cp = stage_scalars(eta_n, dt, s, alpha, lam, beta)
-    k = rhs(X, inv_dx2, cf, cp, order).astype(np.float64)
+    k = rhs(X, inv_dx2, cf, cp, order, ko).astype(np.float64)
     if s == 3:
         return acc, (acc + h6 * k).astype(st)
     U64 = Un.astype(np.float64)
@@ -134,12 +172,12 @@ def rk4_stage(s: int, X: np.ndarray, Un: np.ndarray, acc, eta_n: float, dt: floa
 
 
 def ssprk3_stage(s: int, X: np.ndarray, Un: np.ndarray, eta_n: float, dt: float, inv_dx2: float,
-                 alpha: float, lam: float, beta: int, order: int = 1) -> np.ndarray:
+                 alpha: float, lam: float, beta: int, order: int = 1, ko=None) -> np.ndarray:
     """Stage s (0-based) of SSPRK3: the next stage input (s < 2) or U_{n+1} (s = 2), in
     the storage precision of Un; updates in float64 from promoted values."""
     st = Un.dtype
     _, cf, cp = stage_scalars(eta_n, dt, s, alpha, lam, beta, integrator=10)
-    k = rhs(X, inv_dx2, cf, cp, order).astype(np.float64)
+    k = rhs(X, inv_dx2, cf, cp, order, ko).astype(np.float64)
     U64 = Un.astype(np.float64)
     if s == 0:
         Y = U64 + dt * k
@@ -151,18 +189,18 @@ def ssprk3_stage(s: int, X: np.ndarray, Un: np.ndarray, eta_n: float, dt: float,
 
 
 def ssprk3_step(U: np.ndarray, eta_n: float, dt: float, inv_dx2: float,
-                alpha: float, lam: float, beta: int, fill=None, order: int = 1) -> np.ndarray:
+                alpha: float, lam: float, beta: int, fill=None, order: int = 1, ko=None) -> np.ndarray:
     """One SSPRK3 step; ``fill(s, X)`` as for ``rk4_step``."""
     X = U
     for s in range(3):
         if s > 0 and fill is not None:
             fill(s, X)
-        X = ssprk3_stage(s, X, U, eta_n, dt, inv_dx2, alpha, lam, beta, order)
+        X = ssprk3_stage(s, X, U, eta_n, dt, inv_dx2, alpha, lam, beta, order, ko)
     return X
 
 
 def rk4_step(U: np.ndarray, eta_n: float, dt: float, inv_dx2: float,
-             alpha: float, lam: float, beta: int, fill=None, order: int = 1) -> np.ndarray:
+             alpha: float, lam: float, beta: int, fill=None, order: int = 1, ko=None) -> np.ndarray:
     """One classic RK4 step of size dt from time eta_n; returns U_{n+1} (U's dtype).
 
     ``fill(s, X)``, if given, is called on the stage input X before stages s = 1, 2, 3
@@ -173,15 +211,17 @@ def rk4_step(U: np.ndarray, eta_n: float, dt: float, inv_dx2: float,
     for s in range(4):
         if s > 0 and fill is not None:
             fill(s, X)
-        acc, X = rk4_stage(s, X, U, acc, eta_n, dt, inv_dx2, alpha, lam, beta, order)
+        acc, X = rk4_stage(s, X, U, acc, eta_n, dt, inv_dx2, alpha, lam, beta, order, ko)
     return X
 
 
 def run_single_level(U0: np.ndarray, nsteps: int, eta0: float, dt: float, dx: float,
                      alpha: float = 2.0, lam: float = 1.0, beta: int = 2,
-                     callback=None, integrator: int = 4, order: int = 1) -> np.ndarray:
+                     callback=None, integrator: int = 4, order: int = 1, ko_order: int = 0,
+                     ko_eps: float = 0.0) -> np.ndarray:
     """nsteps steps (RK4, or SSPRK3 for integrator 3/10) of a periodic lattice with the
-    Laplacian of the given order; step k starts at eta0 + k*dt.
+    Laplacian of the given order and, for ko_order 2 or 3, Kreiss-Oliger dissipation of
+    strength ko_eps; step k starts at eta0 + k*dt.
 
     ``callback(k, U)`` is called after each step with the 1-based step count.
     """
@@ -189,9 +229,10 @@ def run_single_level(U0: np.ndarray, nsteps: int, eta0: float, dt: float, dx: fl
     stage_fractions(integrator)  # validates
     step = rk4_step if integrator == 4 else ssprk3_step
     inv_dx2 = 1.0 / (dx * dx)
+    ko = (ko_order, ko_coef(ko_order, ko_eps, dx)) if ko_order else None
     U = U0.copy()
     for k in range(nsteps):
-        U = step(U, level_time(eta0, k, dt), dt, inv_dx2, alpha, lam, beta, order=order)
+        U = step(U, level_time(eta0, k, dt), dt, inv_dx2, alpha, lam, beta, order=order, ko=ko)
         if callback is not None:
             callback(k + 1, U)
     return U
