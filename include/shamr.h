@@ -92,6 +92,14 @@ typedef struct {
                            quartic through five coarse averages).  Quartic interpolation
                            reads two coarse cells beyond each parent: refined levels then
                            keep at least two ghost layers, and nesting needs that margin */
+  int32_t ko_order;     /* sim.dissipation_order (section II, Kreiss-Oliger dissipation):
+                           0 = off, 2 or 3 = the ghost cells the operator needs, read as
+                           p = 3 or 5: Q = (-1)^((p+3)/2) eps dx^p / 2^(p+1) times the sum
+                           of the (p+1)-st central differences, added to the right-hand
+                           side of all four components.  Refined levels then keep that
+                           many ghost layers, the fills between stages carry Pi too, every
+                           stage runs on wave-row tiles and the fused step is not used */
+  double ko_eps;        /* sim.dissipation_strength eps >= 0 */
 } sh_params;
 
 /* Device bytes needed for the arena of a level with the given boxes.  Returns 0 for
@@ -101,8 +109,8 @@ size_t sh_arena_bytes(const sh_params* p, int32_t lev, int32_t nboxes, const int
 /* Create a hierarchy.  `hip_stream` is a hipStream_t (NULL = default stream) that all
    device work of this hierarchy is queued on.  Errors: SH_EINVAL (n0 < 1, L or cfl not
    positive, beta < 0, max_level < 0 or > 15, blocking_factor < 2, prec not 0/1,
-   integrator not 0, 3, 4 or 10, lap_order not 0..3, interp not 0, 1 or 4), SH_EDEVICE (no
-   HIP device). */
+   integrator not 0, 3, 4 or 10, lap_order not 0..3, interp not 0, 1 or 4, ko_order not 0,
+   2 or 3, ko_eps negative or not finite), SH_EDEVICE (no HIP device). */
 sh_status sh_hierarchy_create(const sh_params* p, void* hip_stream, sh_hierarchy* out);
 
 /* Set, change or remove the box layout of level `lev` (section II: boxes whose sides
@@ -254,7 +262,8 @@ sh_status sh_profile_read(sh_hierarchy h, double* ms, int64_t* counts);
    member's result is bit-identical to stepping it alone (kernels are gather-only per
    box).  Members must not be re-laid out or destroyed while the batch exists; the batch
    borrows them.  Errors: SH_EINVAL (a member with more than one level, another
-   precision or stream, an integrator other than RK4 or a Laplacian order other than 1),
+   precision or stream, an integrator other than RK4, a Laplacian order other than 1 or
+   dissipation),
    SH_ESTATE from sh_batch_advance if a member's layout changed
    since the batch was built. */
 sh_status sh_batch_create(int32_t njobs, const sh_hierarchy* jobs, sh_batch* out);

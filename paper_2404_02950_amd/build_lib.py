@@ -28,7 +28,7 @@ HIP_FLAGS = [
 ]
 HOST_FLAGS = ["-O2", "-fPIC", "-std=c++17", "-ffp-contract=off", "-Wall"]
 
-HIP_SOURCES = ["kernels.hip", "kernels_hilap.hip", "kernels_fused.hip", "runtime.cpp"]
+HIP_SOURCES = ["kernels.hip", "kernels_hilap.hip", "kernels_ko.hip", "kernels_fused.hip", "runtime.cpp"]
 HOST_SOURCES = ["cluster.cpp"]
 
 
@@ -37,7 +37,7 @@ def kernel_source_sha() -> str:
     on other kernels is not reported for these."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("kernels.hip", "kernels_hilap.hip", "kernels_fused.hip", "sh_stage.h", "sh_device.h",
+    for f in ("kernels.hip", "kernels_hilap.hip", "kernels_ko.hip", "kernels_fused.hip", "sh_stage.h", "sh_device.h",
               "sh_internal.h"):
         with open(os.path.join(CSRC, f), "rb") as fh:
             h.update(fh.read())

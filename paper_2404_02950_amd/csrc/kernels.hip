@@ -534,16 +534,19 @@ __global__ __launch_bounds__(SH_BLOCK) void k_xfer(const BoxDev* __restrict__ bo
 static inline int nblk(long long n, int per) { return (int)((n + per - 1) / per); }
 
 // kind: 0 = wave-row tiles (k_stage), 4 or 8 = block-row tiles of that many rows;
-// order: the Laplacian order (1 here, 2 and 3 in kernels_hilap.hip)
-void sh_launch_stage(int prec, int s, int kind, bool nt, int order, const Tile* tiles, int ntiles,
+// order: the Laplacian order (1 here, 2 and 3 in kernels_hilap.hip); ko: dissipation
+// order (kernels_ko.hip)
+void sh_launch_stage(int prec, int s, int kind, bool nt, int order, int ko, const Tile* tiles, int ntiles,
                      const BoxDev* boxes, hipStream_t st) {
-  if (order > 1) sh_launch_stage_hilap(prec, s, kind, nt, order, tiles, ntiles, boxes, st);
+  if (ko > 0) sh_launch_stage_ko(prec, s, nt, order, ko, tiles, ntiles, boxes, st);
+  else if (order > 1) sh_launch_stage_hilap(prec, s, kind, nt, order, tiles, ntiles, boxes, st);
   else stage_launch_radius<1>(prec, s, kind, nt, tiles, ntiles, boxes, st);
 }
 
-void sh_launch_rhs(int prec, int order, const Tile* tiles, int ntiles, const BoxDev* boxes, const long long* out_off,
-                   double* out, hipStream_t st) {
-  if (order > 1) sh_launch_rhs_hilap(prec, order, tiles, ntiles, boxes, out_off, out, st);
+void sh_launch_rhs(int prec, int order, int ko, const Tile* tiles, int ntiles, const BoxDev* boxes,
+                   const long long* out_off, double* out, hipStream_t st) {
+  if (ko > 0) sh_launch_rhs_ko(prec, order, ko, tiles, ntiles, boxes, out_off, out, st);
+  else if (order > 1) sh_launch_rhs_hilap(prec, order, tiles, ntiles, boxes, out_off, out, st);
   else rhs_launch_radius<1>(prec, tiles, ntiles, boxes, out_off, out, st);
 }
 

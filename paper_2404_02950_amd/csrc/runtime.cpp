@@ -130,7 +130,22 @@ static int lap_order_of(const sh_params& p) { return p.lap_order > 1 ? p.lap_ord
 // coarse level of the next one).
 static int interp_of(const sh_params& p) { return p.interp == 4 ? 4 : 1; }
 static int interp_reach(const sh_params& p) { return interp_of(p) == 4 ? 2 : 1; }
-static int refined_ng(const sh_params& p) { return std::max(lap_order_of(p), interp_reach(p)); }
+
+// Kreiss-Oliger dissipation order (0 = off, 2, 3 = the ghost cells its stencil needs).  It
+// stencils Pi as well as psi, so the fills between stages then carry all four
+// components, and every stage runs on wave-row tiles.
+static int ko_of(const sh_params& p) { return p.ko_order; }
+static double ko_coef(const sh_params& p, double dx) {
+  if (p.ko_order == 2) return -p.ko_eps / (16.0 * dx);
+  if (p.ko_order == 3) return p.ko_eps / (64.0 * dx);
+  return 0.0;
+}
+// ghost cells a stage reads, and components the fills between stages carry
+static int stencil_depth(const sh_params& p) { return std::max(lap_order_of(p), ko_of(p)); }
+static int fill_comps(const sh_params& p) { return ko_of(p) ? 4 : 2; }
+static int refined_ng(const sh_params& p) { return std::max(stencil_depth(p), interp_reach(p)); }
+// the fused level-0 step: 7-point stencil, no dissipation
+static bool fusable(const sh_params& p) { return lap_order_of(p) == 1 && ko_of(p) == 0; }
 
 static void make_geom(int prec, int ng, const std::vector<IBox>& boxes, LayoutGeom& g, bool acc) {
   g.ng = ng;
@@ -223,6 +238,12 @@ static Tuning default_tuning(const sh_params& p) {
     t.fshape = 2;
     t.fvar = 6;
   }
+  return t;
+}
+
+// per-stage launch shape: wave rows for every box under dissipation
+static Tuning stage_tuning(const sh_params& p, Tuning t) {
+  if (ko_of(p)) t.kind = 0;
   return t;
 }
 
@@ -499,6 +520,7 @@ static LevelScal make_ls(const sh_params& p, int l, long long k) {
   s.alpha = p.alpha_fric;
   s.lam = p.lambda;
   s.inv_dx2 = 1.0 / (s.dx * s.dx);
+  s.ko = ko_coef(p, s.dx);
   s.beta = p.beta_pot;
   s.nst = stages_of(p);
   s.k = k;
@@ -663,7 +685,7 @@ static sh_status build_links(sh_hierarchy h, int l) {
   std::vector<InterpSeg> is;
   std::vector<AvgSeg> as;
   std::vector<long long> nc, nc5;
-  if (!build_a2(F, C, lap_order_of(h->p), interp_reach(h->p), is, nc) || !build_a5(F, C, as, nc5)) {
+  if (!build_a2(F, C, stencil_depth(h->p), interp_reach(h->p), is, nc) || !build_a5(F, C, as, nc5)) {
     F.stale = true;
     F.a2.release();
     F.a5.release();
@@ -684,11 +706,13 @@ static sh_status build_links(sh_hierarchy h, int l) {
 // Same-level ghost copy of `role`: one layer, or (deep = true) the whole ghost depth.
 // The deep copy carries all four components: the fused step computes its early stages
 // on the ghost ring, where it needs Pi as well as psi.
-static sh_status same_level_fill(sh_hierarchy h, int l, int role, int ncomp = 2, bool deep = true) {
+// ncomp 0: the components the stencils read (psi, and Pi under dissipation).
+static sh_status same_level_fill(sh_hierarchy h, int l, int role, int ncomp = 0, bool deep = true) {
   Level& L = h->lev[l];
   h->rec(2, l, role, 0);
   const bool use_deep = deep && L.a1d.nblocks();
   const SegPlan<CopySeg>& pl = use_deep ? L.a1d : L.a1;
+  if (ncomp == 0) ncomp = fill_comps(h->p);
   if (use_deep) ncomp = 4;
   hipEvent_t ev = h->prof_begin();
   sh_launch_ghost_copy(h->p.prec, pl.segs.p, pl.blocks.p, pl.nblocks(), L.dbox.p, role, ncomp, h->st);
@@ -703,7 +727,7 @@ static sh_status coarse_fine_fill(sh_hierarchy h, int l, int role, int anum) {
   h->rec(3, l, role, anum);
   hipEvent_t ev = h->prof_begin();
   sh_launch_ghost_interp(h->p.prec, interp_of(h->p), L.a2.segs.p, L.a2.blocks.p, L.a2.nblocks(), L.dbox.p, h->lev[l - 1].dbox.p, role,
-                         anum, 2, h->st);
+                         anum, fill_comps(h->p), h->st);
   h->prof_end(ev, 5);
   LAUNCHCHK();
   return SH_OK;
@@ -711,7 +735,7 @@ static sh_status coarse_fine_fill(sh_hierarchy h, int l, int role, int anum) {
 
 // Ghost fill of a stage input (one layer suffices: only the state U_n is read deeper).
 static sh_status fill(sh_hierarchy h, int l, int role, int anum) {
-  sh_status s = same_level_fill(h, l, role, 2, role == ROLE_UN);
+  sh_status s = same_level_fill(h, l, role, fill_comps(h->p), role == ROLE_UN);
   if (s != SH_OK) return s;
   return coarse_fine_fill(h, l, role, anum);
 }
@@ -719,10 +743,10 @@ static sh_status fill(sh_hierarchy h, int l, int role, int anum) {
 static void stage(sh_hierarchy h, Level& L, int s) {
   const int prec = h->p.prec;
   const bool nt = h->tune.nt != 0;
-  const int order = lap_order_of(h->p);
+  const int order = lap_order_of(h->p), ko = ko_of(h->p);
   if (L.stiles_b.n)
-    sh_launch_stage(prec, s, h->tune.kind, nt, order, L.stiles_b.p, (int)L.stiles_b.n, L.dbox.p, h->st);
-  if (L.stiles_w.n) sh_launch_stage(prec, s, 0, nt, order, L.stiles_w.p, (int)L.stiles_w.n, L.dbox.p, h->st);
+    sh_launch_stage(prec, s, h->tune.kind, nt, order, ko, L.stiles_b.p, (int)L.stiles_b.n, L.dbox.p, h->st);
+  if (L.stiles_w.n) sh_launch_stage(prec, s, 0, nt, order, ko, L.stiles_w.p, (int)L.stiles_w.n, L.dbox.p, h->st);
 }
 
 static sh_status check_level(sh_hierarchy h, int l) {
@@ -772,6 +796,8 @@ static sh_status check_params(const sh_params* p) {
     return fail(SH_EINVAL, "integrator must be 0 or 4 (RK4) or 3 or 10 (SSPRK3)");
   if (p->lap_order < 0 || p->lap_order > 3) return fail(SH_EINVAL, "lap_order must be 0..3");
   if (p->interp != 0 && p->interp != 1 && p->interp != 4) return fail(SH_EINVAL, "interp must be 0, 1 or 4");
+  if ((p->ko_order != 0 && p->ko_order != 2 && p->ko_order != 3) || !(p->ko_eps >= 0) || p->ko_eps == HUGE_VAL)
+    return fail(SH_EINVAL, "ko_order must be 0, 2 or 3 and ko_eps finite and >= 0");
   if ((long long)p->n0 << p->max_level > 32767) return fail(SH_EINVAL, "finest level too large");
   return SH_OK;
 }
@@ -858,10 +884,10 @@ static sh_status set_box_tables(sh_hierarchy h, LevelScal* ls, Level& L) {
   HIPCHK(L.tiles.upload(L.g.tiles));
   {
     std::vector<Tile> wt, bt, ft;
-    make_stage_tiles(L.boxes, h->tune, L.g.nvalid, wt, bt);
+    make_stage_tiles(L.boxes, stage_tuning(h->p, h->tune), L.g.nvalid, wt, bt);
     HIPCHK(L.stiles_w.upload(wt));
     HIPCHK(L.stiles_b.upload(bt));
-    if (lap_order_of(h->p) == 1) make_fused_tiles(L.boxes, h->tune, L.g.ng, ft);  // fused: 7-point only
+    if (fusable(h->p)) make_fused_tiles(L.boxes, h->tune, L.g.ng, ft);
     HIPCHK(L.ftiles.upload(ft));
   }
   HIPCHK(L.xoff_valid.upload(xv));
@@ -911,7 +937,7 @@ sh_status sh_set_level_layout(sh_hierarchy h, int32_t l, int32_t nboxes, const i
     std::vector<long long> nc;
     // stage inputs: a shell as deep as the stencil; the state after a step: the whole
     // shell (level 0's is deeper, for the fused step)
-    const int r = lap_order_of(h->p);
+    const int r = stencil_depth(h->p);
     build_a1(N, r, cs, nc);
     hipError_t e = N.a1.upload(cs, nc);
     if (e == hipSuccess && N.g.ng > r) {
@@ -1175,7 +1201,8 @@ static void shadow_release(sh_hierarchy h) {
 
 static void shadow_copy(sh_hierarchy h, int role) {
   Level& S = h->shadow;
-  sh_launch_ghost_copy(h->p.prec, S.a1.segs.p, S.a1.blocks.p, S.a1.nblocks(), S.dbox.p, role, 2, h->st);
+  sh_launch_ghost_copy(h->p.prec, S.a1.segs.p, S.a1.blocks.p, S.a1.nblocks(), S.dbox.p, role, fill_comps(h->p),
+                       h->st);
 }
 
 sh_status sh_shadow_begin(sh_hierarchy h) {
@@ -1194,7 +1221,7 @@ sh_status sh_shadow_begin(sh_hierarchy h) {
   S.dx = level_dx(p, 0) * 2.0;
   S.dt = p.cfl * S.dx;
   S.boxes = {IBox{{0, 0, 0}, {S.M - 1, S.M - 1, S.M - 1}}};
-  make_geom(p.prec, lap_order_of(p), S.boxes, S.g, stages_of(p) == 4);
+  make_geom(p.prec, stencil_depth(p), S.boxes, S.g, stages_of(p) == 4);
   if (hipMalloc((void**)&h->shadow_arena, S.g.total) != hipSuccess) return fail(SH_ENOMEM, "shadow level allocation");
   S.base = (char*)round_up((long long)(uintptr_t)h->shadow_arena, 256);
   S.bins.build(S.boxes, S.M);
@@ -1209,7 +1236,7 @@ sh_status sh_shadow_begin(sh_hierarchy h) {
   }
   std::vector<CopySeg> cs;
   std::vector<long long> nc;
-  build_a1(Sh, lap_order_of(p), cs, nc);
+  build_a1(Sh, stencil_depth(p), cs, nc);
   std::vector<AvgSeg> as;
   std::vector<long long> nc5;
   if (!build_a5(L0, Sh, as, nc5)) {
@@ -1224,6 +1251,7 @@ sh_status sh_shadow_begin(sh_hierarchy h) {
   ls.dx = Sh.dx;
   ls.dt = Sh.dt;
   ls.inv_dx2 = 1.0 / (Sh.dx * Sh.dx);
+  ls.ko = ko_coef(p, Sh.dx);
   HIPCHK(hipMemcpyAsync(h->d_ls + SH_SHADOW_LS, &ls, sizeof(ls), hipMemcpyHostToDevice, h->st));
   // the shadow's state: level 0 averaged onto it, then its periodic ghosts
   sh_launch_avgdown(p.prec, h->shadow_a5.segs.p, h->shadow_a5.blocks.p, h->shadow_a5.nblocks(), Sh.dbox.p,
@@ -1363,7 +1391,7 @@ sh_status sh_eval_rhs(sh_hierarchy h, int32_t l, double* out_dev) {
   if (s != SH_OK || (s = not_capturing(h)) != SH_OK) return s;
   if (!out_dev) return fail(SH_EINVAL, "null output");
   Level& L = h->lev[l];
-  sh_launch_rhs(h->p.prec, lap_order_of(h->p), L.tiles.p, L.ntiles(), L.dbox.p, L.rhs_off.p, out_dev, h->st);
+  sh_launch_rhs(h->p.prec, lap_order_of(h->p), ko_of(h->p), L.tiles.p, L.ntiles(), L.dbox.p, L.rhs_off.p, out_dev, h->st);
   LAUNCHCHK();
   return SH_OK;
 }
@@ -1467,10 +1495,10 @@ sh_status sh_set_tuning(sh_hierarchy h, int32_t kind, int32_t nontemporal, int32
   h->tune.fvar = fused_variant;
   for (Level& L : h->lev) {
     std::vector<Tile> wt, bt, ft;
-    make_stage_tiles(L.boxes, h->tune, L.g.nvalid, wt, bt);
+    make_stage_tiles(L.boxes, stage_tuning(h->p, h->tune), L.g.nvalid, wt, bt);
     HIPCHK(L.stiles_w.upload(wt));
     HIPCHK(L.stiles_b.upload(bt));
-    if (lap_order_of(h->p) == 1) make_fused_tiles(L.boxes, h->tune, L.g.ng, ft);  // fused: 7-point only
+    if (fusable(h->p)) make_fused_tiles(L.boxes, h->tune, L.g.ng, ft);
     HIPCHK(L.ftiles.upload(ft));
   }
   return SH_OK;
@@ -1639,9 +1667,9 @@ sh_status sh_batch_create(int32_t njobs, const sh_hierarchy* jobs, sh_batch* out
       delete b;
       return fail(SH_EINVAL, "batched jobs must be single-level hierarchies of one precision on one stream");
     }
-    if (stages_of(h->p) != 4 || lap_order_of(h->p) != 1) {
+    if (stages_of(h->p) != 4 || lap_order_of(h->p) != 1 || ko_of(h->p) != 0) {
       delete b;
-      return fail(SH_EINVAL, "batched jobs must use the RK4 integrator and the 7-point Laplacian");
+      return fail(SH_EINVAL, "batched jobs must use the RK4 integrator, the 7-point Laplacian and no dissipation");
     }
     if (h->capturing) {
       delete b;
@@ -1712,8 +1740,8 @@ sh_status sh_batch_advance(sh_batch b) {
         LAUNCHCHK();
       }
       if (b->btiles.n)
-        sh_launch_stage(prec, s, b->tune.kind, nt, 1, b->btiles.p, (int)b->btiles.n, b->boxes.p, b->st);
-      if (b->wtiles.n) sh_launch_stage(prec, s, 0, nt, 1, b->wtiles.p, (int)b->wtiles.n, b->boxes.p, b->st);
+        sh_launch_stage(prec, s, b->tune.kind, nt, 1, 0, b->btiles.p, (int)b->btiles.n, b->boxes.p, b->st);
+      if (b->wtiles.n) sh_launch_stage(prec, s, 0, nt, 1, 0, b->wtiles.p, (int)b->wtiles.n, b->boxes.p, b->st);
       LAUNCHCHK();
     }
   }

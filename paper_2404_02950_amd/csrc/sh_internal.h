@@ -18,9 +18,10 @@
 // level time is eta0 + k*dt (one multiply and one add, so aligned levels hold
 // bit-identical times).  nst is the number of stages per step of the integrator (4:
 // classic RK4, 3: SSPRK3).  Every kernel resolves buffer roles from k and nst, so a
-// launch sequence can be replayed without host updates.
+// launch sequence can be replayed without host updates.  ko is the coefficient of the
+// Kreiss-Oliger sum on this level (-eps/(16 dx) or eps/(64 dx); 0 without dissipation).
 struct LevelScal {
-  double eta0, dt, alpha, lam, inv_dx2, dx;
+  double eta0, dt, alpha, lam, inv_dx2, dx, ko;
   int beta, nst;
   long long k;
 };

@@ -19,6 +19,12 @@
 //   stage 1: A = U_n + h k
 //   stage 2: B = 3/4 U_n + 1/4 (A + h k)
 //   stage 3: A = 1/3 U_n + 2/3 (B + h k)   (the new U_n)
+// Kreiss-Oliger dissipation (KD = dissipation order 2 or 3; 0 = off) adds to the
+// right-hand side of every component Q = ko * K with
+//   K = (S_2 + (-4) S_1) + 18 u                    KD = 2
+//     = ((S_3 + (-6) S_2) + 15 S_1) + (-60) u      KD = 3
+// and ko = -eps / (16 dx) or eps / (64 dx) from the level scalars (rounded once to T):
+//   k_psi = Pi + Q(psi),  k_Pi = ((lap - c_fric Pi) - c_pot (r2 - 1) psi) + Q(Pi).
 // The right-hand side is evaluated in T; updates in float64, rounded to T on store.
 // NT = 1 marks the streams read or written once (Pi, U_n, acc, the stage output) as
 // nontemporal so they do not push the psi planes, which neighbours re-read, out of L2.
@@ -32,7 +38,7 @@
 
 // Laplacian from the per-radius neighbour sums S[r-1] and the centre value u.
 template <typename T, int H>
-__device__ __forceinline__ T lap_combine(const T (&S)[H], T u, T idx2) {
+__device__ __forceinline__ T lap_combine(const T* S, T u, T idx2) {
   if constexpr (H == 1) {
     return (S[0] - (T)6.0 * u) * idx2;
   } else if constexpr (H == 2) {
@@ -43,6 +49,23 @@ __device__ __forceinline__ T lap_combine(const T (&S)[H], T u, T idx2) {
             (T)(-49.0 / 6.0) * u) *
            idx2;
   }
+}
+
+// Kreiss-Oliger sum K of dissipation order KD from the neighbour sums S[r-1].
+template <typename T, int KD>
+__device__ __forceinline__ T ko_sum(const T* S, T u) {
+  if constexpr (KD == 2) {
+    return (S[1] + (T)(-4.0) * S[0]) + (T)18.0 * u;
+  } else {
+    static_assert(KD == 3, "dissipation orders 2, 3");
+    return ((S[2] + (T)(-6.0) * S[1]) + (T)15.0 * S[0]) + (T)(-60.0) * u;
+  }
+}
+
+// Six-neighbour sum at distance r read straight from memory (x, y, z).
+template <typename T>
+__device__ __forceinline__ T nsum(const T* u, long long e, int r, long long px, long long plane) {
+  return ((u[e - r] + u[e + r]) + (u[e - r * px] + u[e + r * px])) + (u[e - r * plane] + u[e + r * plane]);
 }
 
 struct StagePtrs {
@@ -66,16 +89,25 @@ __device__ __forceinline__ StagePtrs stage_ptrs(const BoxDev& B, const LevelScal
 
 // Per-cell right-hand side and stage update.  p0/p1 = psi at the cell, lap0/lap1 their
 // Laplacians, q0/q1 = Pi at the cell (all in T); e = element index of the cell.
-template <typename T, int S, bool NT>
+// With KO, ko4 holds the dissipation terms Q of the four components.
+template <typename T, int S, bool NT, bool KO = false>
 __device__ __forceinline__ void stage_cell(const StageScal& sc, const T* __restrict__ Un, T* __restrict__ Y,
                                            double* __restrict__ acc, long long cs, long long e, T p0, T p1,
-                                           T q0, T q1, T lap0, T lap1, const double* un4, const double* acc4) {
+                                           T q0, T q1, T lap0, T lap1, const double* un4, const double* acc4,
+                                           const T* ko4 = nullptr) {
   const T cf = (T)sc.cf, cp = (T)sc.cp;
   const T r2 = p0 * p0 + p1 * p1;
   const T pot = cp * (r2 - (T)1.0);
-  const T kq0 = (lap0 - cf * q0) - pot * p0;
-  const T kq1 = (lap1 - cf * q1) - pot * p1;
-  const double k4[4] = {(double)q0, (double)q1, (double)kq0, (double)kq1};
+  T kp0 = q0, kp1 = q1;
+  T kq0 = (lap0 - cf * q0) - pot * p0;
+  T kq1 = (lap1 - cf * q1) - pot * p1;
+  if constexpr (KO) {
+    kp0 = kp0 + ko4[0];
+    kp1 = kp1 + ko4[1];
+    kq0 = kq0 + ko4[2];
+    kq1 = kq1 + ko4[3];
+  }
+  const double k4[4] = {(double)kp0, (double)kp1, (double)kq0, (double)kq1};
   const T xv[4] = {p0, p1, q0, q1};
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
@@ -112,11 +144,14 @@ __device__ __forceinline__ void stage_loads(const T* __restrict__ Un, const doub
 }
 
 // Wave-row kernel: one wavefront per tile (a TX x 64/TX footprint of a box, marching
-// in z); psi of planes z-H..z+H of both components stay in registers, x and y
-// neighbours are read through the caches.  Used for boxes narrower than 64 cells.
-template <typename T, int S, bool NT, int H>
+// in z); psi of planes z-HR..z+HR of both components stay in registers (HR = the wider
+// of the Laplacian and dissipation radii), x and y neighbours are read through the
+// caches.  Used for boxes narrower than 64 cells, and for every box with dissipation
+// (whose Pi neighbours are read through the caches as well).
+template <typename T, int S, bool NT, int H, int KD = 0>
 __global__ __launch_bounds__(SH_BLOCK) void k_stage(const Tile* __restrict__ tiles, int ntiles,
                                                     const BoxDev* __restrict__ boxes) {
+  constexpr int HR = H > KD ? H : KD;
   const int lane = threadIdx.x & (SH_WAVE - 1);
   const int t = xcd_remap(blockIdx.x, gridDim.x) * (SH_BLOCK / SH_WAVE) + (threadIdx.x >> 6);
   if (t >= ntiles) return;
@@ -146,33 +181,49 @@ __global__ __launch_bounds__(SH_BLOCK) void k_stage(const Tile* __restrict__ til
   const T idx2 = (T)sc.inv_dx2;
 
   long long e = elem<T>(B, x, y, z0);
-  // window: w[c][j] = psi_c at plane z - H + j
-  T w[2][2 * H + 1];
+  // window: w[c][j] = psi_c at plane z - HR + j
+  T w[2][2 * HR + 1];
 #pragma unroll
   for (int c = 0; c < 2; ++c)
 #pragma unroll
-    for (int j = 0; j < 2 * H; ++j) w[c][j] = X[c * cs + e + (j - H) * plane];
+    for (int j = 0; j < 2 * HR; ++j) w[c][j] = X[c * cs + e + (j - HR) * plane];
+  const T kc = (T)L.ko;
   for (int z = z0; z < zend; ++z, e += plane) {
 #pragma unroll
-    for (int c = 0; c < 2; ++c) w[c][2 * H] = X[c * cs + e + H * plane];
-    T Ssum[2][H];
+    for (int c = 0; c < 2; ++c) w[c][2 * HR] = X[c * cs + e + HR * plane];
+    T Ssum[2][HR];
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
       const T* u = X + c * cs;
 #pragma unroll
-      for (int r = 1; r <= H; ++r)
-        Ssum[c][r - 1] = ((u[e - r] + u[e + r]) + (u[e - r * px] + u[e + r * px])) + (w[c][H - r] + w[c][H + r]);
+      for (int r = 1; r <= HR; ++r)
+        Ssum[c][r - 1] = ((u[e - r] + u[e + r]) + (u[e - r * px] + u[e + r * px])) + (w[c][HR - r] + w[c][HR + r]);
     }
     const T q0 = ld<NT>(X + 2 * cs + e), q1 = ld<NT>(X + 3 * cs + e);
     double un4[4], acc4[4];
     stage_loads<T, S, NT>(Un, P.acc, cs, e, un4, acc4);
-    const T lap0 = lap_combine<T, H>(Ssum[0], w[0][H], idx2);
-    const T lap1 = lap_combine<T, H>(Ssum[1], w[1][H], idx2);
-    if (active) stage_cell<T, S, NT>(sc, Un, Y, P.acc, cs, e, w[0][H], w[1][H], q0, q1, lap0, lap1, un4, acc4);
+    const T lap0 = lap_combine<T, H>(Ssum[0], w[0][HR], idx2);
+    const T lap1 = lap_combine<T, H>(Ssum[1], w[1][HR], idx2);
+    if constexpr (KD > 0) {
+      T ko4[4];
+      ko4[0] = kc * ko_sum<T, KD>(Ssum[0], w[0][HR]);
+      ko4[1] = kc * ko_sum<T, KD>(Ssum[1], w[1][HR]);
+      T Sq[2][KD];
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int r = 1; r <= KD; ++r) Sq[c][r - 1] = nsum(X + (2 + c) * cs, e, r, px, plane);
+      ko4[2] = kc * ko_sum<T, KD>(Sq[0], q0);
+      ko4[3] = kc * ko_sum<T, KD>(Sq[1], q1);
+      if (active)
+        stage_cell<T, S, NT, true>(sc, Un, Y, P.acc, cs, e, w[0][HR], w[1][HR], q0, q1, lap0, lap1, un4, acc4, ko4);
+    } else {
+      if (active) stage_cell<T, S, NT>(sc, Un, Y, P.acc, cs, e, w[0][HR], w[1][HR], q0, q1, lap0, lap1, un4, acc4);
+    }
 #pragma unroll
     for (int c = 0; c < 2; ++c)
 #pragma unroll
-      for (int j = 0; j < 2 * H; ++j) w[c][j] = w[c][j + 1];
+      for (int j = 0; j < 2 * HR; ++j) w[c][j] = w[c][j + 1];
   }
 }
 
@@ -288,7 +339,7 @@ __global__ __launch_bounds__(SH_WAVE * ROWS) void k_stage_lds(const Tile* __rest
 }
 
 // Right-hand side only (diagnostic): out[box][c][z][y][x] = f(U_n) at stage-1 scalars.
-template <typename T, int H>
+template <typename T, int H, int KD = 0>
 __global__ __launch_bounds__(SH_BLOCK) void k_rhs(const Tile* __restrict__ tiles, int ntiles,
                                                   const BoxDev* __restrict__ boxes,
                                                   const long long* __restrict__ out_off,
@@ -309,25 +360,42 @@ __global__ __launch_bounds__(SH_BLOCK) void k_rhs(const Tile* __restrict__ tiles
   const long long px = B.px, plane = px * B.py, cs = B.cs;
   const long long nv = (long long)B.nx * B.ny * B.nz;
   const T cf = (T)sc.cf, cp = (T)sc.cp, idx2 = (T)sc.inv_dx2;
+  constexpr int HR = H > KD ? H : KD;
+  const T kc = (T)L.ko;
   for (int z = z0; z < zend; ++z) {
     const long long e = elem<T>(B, x, y, z);
-    T lap[2];
+    T lap[2], ko4[4] = {(T)0, (T)0, (T)0, (T)0};
     for (int c = 0; c < 2; ++c) {
       const T* u = X + c * cs;
-      T Ssum[H];
+      T Ssum[HR];
 #pragma unroll
-      for (int r = 1; r <= H; ++r)
-        Ssum[r - 1] = ((u[e - r] + u[e + r]) + (u[e - r * px] + u[e + r * px])) + (u[e - r * plane] + u[e + r * plane]);
+      for (int r = 1; r <= HR; ++r) Ssum[r - 1] = nsum(u, e, r, px, plane);
       lap[c] = lap_combine<T, H>(Ssum, u[e], idx2);
+      if constexpr (KD > 0) ko4[c] = kc * ko_sum<T, KD>(Ssum, u[e]);
     }
     const T p0 = X[e], p1 = X[cs + e], q0 = X[2 * cs + e], q1 = X[3 * cs + e];
+    if constexpr (KD > 0) {
+      for (int c = 0; c < 2; ++c) {
+        T Sq[KD];
+#pragma unroll
+        for (int r = 1; r <= KD; ++r) Sq[r - 1] = nsum(X + (2 + c) * cs, e, r, px, plane);
+        ko4[2 + c] = kc * ko_sum<T, KD>(Sq, c == 0 ? q0 : q1);
+      }
+    }
     const T r2 = p0 * p0 + p1 * p1;
     const T pot = cp * (r2 - (T)1.0);
     const long long o = out_off[tl.box] + ((long long)z * B.ny + y) * B.nx + x;
-    out[o] = (double)q0;
-    out[o + nv] = (double)q1;
-    out[o + 2 * nv] = (double)((lap[0] - cf * q0) - pot * p0);
-    out[o + 3 * nv] = (double)((lap[1] - cf * q1) - pot * p1);
+    T kp0 = q0, kp1 = q1, kq0 = (lap[0] - cf * q0) - pot * p0, kq1 = (lap[1] - cf * q1) - pot * p1;
+    if constexpr (KD > 0) {
+      kp0 = kp0 + ko4[0];
+      kp1 = kp1 + ko4[1];
+      kq0 = kq0 + ko4[2];
+      kq1 = kq1 + ko4[3];
+    }
+    out[o] = (double)kp0;
+    out[o + nv] = (double)kp1;
+    out[o + 2 * nv] = (double)kq0;
+    out[o + 3 * nv] = (double)kq1;
   }
 }
 

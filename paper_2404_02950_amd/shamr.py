@@ -33,7 +33,7 @@ class sh_params(Structure):
         ("lam", c_double), ("alpha_fric", c_double), ("beta_pot", c_int32),
         ("max_level", c_int32), ("blocking_factor", c_int32), ("max_box", c_int32),
         ("n_error_buf", c_int32), ("prec", c_int32), ("integrator", c_int32), ("lap_order", c_int32),
-        ("interp", c_int32),
+        ("interp", c_int32), ("ko_order", c_int32), ("ko_eps", c_double),
     ]
 
 
@@ -141,12 +141,13 @@ class Hierarchy:
     def __init__(self, n0: int, L: float, cfl: float = 0.25, eta0: float = 0.1, lam: float = 1.0,
                  alpha: float = 2.0, beta: int = 2, max_level: int = 0, blocking_factor: int = 8,
                  max_box: int = 64, n_error_buf: int = 2, prec: int = SH_F64, stream=None,
-                 integrator: int = 4, lap_order: int = 1, interp: int = 1):
+                 integrator: int = 4, lap_order: int = 1, interp: int = 1, ko_order: int = 0,
+                 ko_eps: float = 0.0):
         import torch
         self.torch = torch
         self.lib = load()
         self.params = sh_params(n0, L, cfl, eta0, lam, alpha, beta, max_level, blocking_factor, max_box,
-                                n_error_buf, prec, integrator, lap_order, interp)
+                                n_error_buf, prec, integrator, lap_order, interp, ko_order, ko_eps)
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         h = c_void_p()
         _check(self.lib.sh_hierarchy_create(ctypes.byref(self.params), c_void_p(self.stream.cuda_stream),
