@@ -53,13 +53,14 @@ def traffic_from_profiles(prec: str, n: int, kname: str):
     return rec.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(U0, n: int, integrator: int = 4, order: int = 1):
+def cpu_baseline(U0, n: int, integrator: int = 4, order: int = 1, ko_order: int = 0, ko_eps: float = 0.0):
     """One full step of the oracle on the whole lattice, timed on this host (numpy, one
     core; about 20 s at 512^3 for RK4)."""
-    from oracle.level import rk4_step, ssprk3_step
+    from oracle.level import ko_coef, rk4_step, ssprk3_step
     nst, step, name = (4, rk4_step, "RK4") if integrator == 4 else (3, ssprk3_step, "SSPRK3")
+    ko = (ko_order, ko_coef(ko_order, ko_eps, 1.0)) if ko_order else None
     t0 = time.perf_counter()
-    step(U0, 0.1, 0.25, 1.0, 2.0, 1.0, 2, order=order)
+    step(U0, 0.1, 0.25, 1.0, 2.0, 1.0, 2, order=order, ko=ko)
     dt = time.perf_counter() - t0
     return {"value": nst * n ** 3 / dt, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
             "sample": f"one {name} step ({nst} stages) of the {n}^3 FP64 lattice, numpy oracle, "
@@ -85,6 +86,11 @@ def main():
                     help="4: classic RK4 (default); 3 or 10: SSPRK3")
     ap.add_argument("--lap-order", type=int, default=1, choices=(1, 2, 3),
                     help="Laplacian order: 1 = 7-point (default), 2 = 13-point, 3 = 19-point (per-stage kernels)")
+    ap.add_argument("--ko-order", type=int, default=0, choices=(0, 2, 3),
+                    help="Kreiss-Oliger dissipation order (0 = off; per-stage wave-row kernels)")
+    ap.add_argument("--ko-eps", type=float, default=0.01, help="Kreiss-Oliger dissipation strength")
+    ap.add_argument("--interp", type=int, default=1, choices=(1, 4),
+                    help="AMR workloads: ghost/new-cell interpolation, 1 = linear, 4 = quartic conservative")
     ap.add_argument("--beta", type=int, default=2, help="potential exponent (2: the paper's EOM; 0: stable companion)")
     ap.add_argument("--coarse-steps", type=int, default=None)
     ap.add_argument("--tag-mode", type=int, default=1, choices=(1, 2, 3),
@@ -118,7 +124,8 @@ def main():
     prec = shamr.SH_F64 if args.prec == "f64" else shamr.SH_F32
     stream = torch.cuda.Stream()
     h = shamr.Hierarchy(n, float(n), 0.25, 0.1, 1.0, 2.0, 2, max_level=0, prec=prec, stream=stream,
-                        integrator=args.integrator, lap_order=args.lap_order)
+                        integrator=args.integrator, lap_order=args.lap_order, ko_order=args.ko_order,
+                        ko_eps=args.ko_eps)
     nst = 4 if args.integrator == 4 else 3
     h.set_layout(0, [(0, 0, 0, n - 1, n - 1, n - 1)])
     h.write_dense(0, U0)
@@ -168,7 +175,8 @@ def main():
         k_ms, k_n = prof["fused_step"]
         k_bytes = FUSED_BYTES[args.prec] * cells * k_n
     else:
-        kname = ("rk4_stage" if nst == 4 else "ssprk3_stage") + ("" if args.lap_order == 1 else f"_lap{args.lap_order}")
+        kname = (("rk4_stage" if nst == 4 else "ssprk3_stage") + ("" if args.lap_order == 1 else f"_lap{args.lap_order}")
+                 + ("" if args.ko_order == 0 else f"_ko{args.ko_order}"))
         k_ms = sum(prof[f"stage{s + 1}"][0] for s in range(nst))
         k_n = sum(prof[f"stage{s + 1}"][1] for s in range(nst))
         k_bytes = sum(sb[s] * cells * prof[f"stage{s + 1}"][1] for s in range(nst))
@@ -194,9 +202,10 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"single-level periodic {n}^3, {'RK4' if nst == 4 else 'SSPRK3'} + "
                                f"{ {1: 7, 2: 13, 3: 19}[args.lap_order]}-point Laplacian, "
-                               f"{'FP64' if args.prec == 'f64' else 'FP32 storage / FP64 accumulation'}",
+                               + (f"Kreiss-Oliger order {args.ko_order} (eps {args.ko_eps}), " if args.ko_order else "")
+                               + ('FP64' if args.prec == 'f64' else 'FP32 storage / FP64 accumulation'),
                    "lattice": n, "dx": 1.0, "dt": 0.25, "eta0": 0.1, "lambda": 1.0, "seed": args.seed,
-                   "integrator": args.integrator, "lap_order": args.lap_order,
+                   "integrator": args.integrator, "lap_order": args.lap_order, "ko_order": args.ko_order,
                    "graph_steps": G if graph is not None else None},
         "roofline": roofline,
         # the same cell-update rate priced at the bytes a one-stage-per-pass kernel must
@@ -211,7 +220,7 @@ def main():
     }
     if not args.no_cpu_baseline and args.prec == "f64":
         log("cpu baseline (oracle, one full step)")
-        out["cpu_baseline"] = cpu_baseline(U0, n, args.integrator, args.lap_order)
+        out["cpu_baseline"] = cpu_baseline(U0, n, args.integrator, args.lap_order, args.ko_order, args.ko_eps)
     else:
         out["cpu_baseline"] = None
     if graph is not None:
@@ -251,12 +260,15 @@ def bench_amr(args):
                                   f"{steps} coarse steps, beta = {args.beta}"
                                   + (f", tag mode {args.tag_mode}, te_crit {args.te_crit}" if args.tag_mode != 1 else "")
                                   + (", SSPRK3" if args.integrator != 4 else "")
-                                  + (f", Laplacian order {args.lap_order}" if args.lap_order != 1 else ""),
+                                  + (f", Laplacian order {args.lap_order}" if args.lap_order != 1 else "")
+                                  + (", quartic interpolation" if args.interp == 4 else "")
+                                  + (f", Kreiss-Oliger order {args.ko_order} eps {args.ko_eps}" if args.ko_order else ""),
                       "seed": args.seed}}
     if args.workload == "amr256":
         prec = shamr.SH_F64 if args.prec == "f64" else shamr.SH_F32
         h, rep = workloads.run_amr(U0, levels, steps, prec=prec, beta=args.beta, log=log, tag_mode=args.tag_mode,
-                                   te_crit=args.te_crit, integrator=args.integrator, lap_order=args.lap_order)
+                                   te_crit=args.te_crit, integrator=args.integrator, lap_order=args.lap_order,
+                                   interp=args.interp, ko_order=args.ko_order, ko_eps=args.ko_eps)
         h.close()
         out.update({"value": rep["cell_updates_per_s_end_to_end"], "dtype": args.prec, "report": rep})
     else:

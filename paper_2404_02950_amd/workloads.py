@@ -16,11 +16,12 @@ from . import driver, shamr
 
 def build_hierarchy(U0: np.ndarray, max_level: int, prec: int, beta: int = 2, max_box: int = 64,
                     blocking_factor: int = 8, n_error_buf: int = 2, efficiency: float = 0.7, integrator: int = 4,
-                    lap_order: int = 1):
+                    lap_order: int = 1, interp: int = 1, ko_order: int = 0, ko_eps: float = 0.0):
     n0 = U0.shape[-1]
     h = shamr.Hierarchy(n0, float(n0), 0.25, 0.1, 1.0, 2.0, beta, max_level=max_level,
                         blocking_factor=blocking_factor, max_box=max_box, n_error_buf=n_error_buf, prec=prec,
-                        integrator=integrator, lap_order=lap_order)
+                        integrator=integrator, lap_order=lap_order, interp=interp, ko_order=ko_order,
+                        ko_eps=ko_eps)
     h.set_layout(0, [(0, 0, 0, n0 - 1, n0 - 1, n0 - 1)])
     h.write_dense(0, U0)
     h.fill_ghosts(0)
@@ -38,7 +39,8 @@ def level_summary(h):
 
 def run_amr(U0: np.ndarray, max_level: int, coarse_steps: int, prec: int = shamr.SH_F64, beta: int = 2,
             regrid_every: int = 2, log=print, efficiency: float = 0.7, max_level_bytes: int | None = None,
-            tag_mode: int = 1, te_crit: float = 1e-2, integrator: int = 4, lap_order: int = 1):
+            tag_mode: int = 1, te_crit: float = 1e-2, integrator: int = 4, lap_order: int = 1, interp: int = 1,
+            ko_order: int = 0, ko_eps: float = 0.0):
     """Advance an AMR hierarchy; returns (hierarchy, report dict).
 
     ``max_level_bytes`` (default: a quarter of the device memory free at the start) caps
@@ -48,7 +50,8 @@ def run_amr(U0: np.ndarray, max_level: int, coarse_steps: int, prec: int = shamr
     and gives level 0 its estimate at the regrid (the finer levels get theirs at every
     synchronisation); the initial layout uses the plaquettes, no estimate existing yet.
     ``integrator``: 4 = classic RK4, 3 or 10 = SSPRK3; ``lap_order``: 1, 2, 3 = 7-, 13-,
-    19-point Laplacian."""
+    19-point Laplacian; ``interp``: 1 linear, 4 quartic conservative; ``ko_order``/``ko_eps``:
+    Kreiss-Oliger dissipation."""
     import torch
     if max_level_bytes is None:
         max_level_bytes = torch.cuda.mem_get_info()[0] // 4
@@ -57,7 +60,7 @@ def run_amr(U0: np.ndarray, max_level: int, coarse_steps: int, prec: int = shamr
         raise ValueError("estimates need at least two coarse steps between regrids (the shadow step)")
     t0 = time.perf_counter()
     h = build_hierarchy(U0, max_level, prec, beta=beta, efficiency=efficiency, integrator=integrator,
-                        lap_order=lap_order)
+                        lap_order=lap_order, interp=interp, ko_order=ko_order, ko_eps=ko_eps)
     nst = 3 if integrator in (3, 10) else 4
     if use_tee:
         h.set_tee(True, te_crit, tag_mode)
@@ -127,6 +130,8 @@ def run_amr(U0: np.ndarray, max_level: int, coarse_steps: int, prec: int = shamr
         "tag_mode": tag_mode,
         "integrator": integrator,
         "lap_order": lap_order,
+        "interp": interp,
+        "ko_order": ko_order,
         "cell_steps_per_s_end_to_end": cell_stages / nst / wall,
         "te_crit": te_crit if use_tee else None,
     }
