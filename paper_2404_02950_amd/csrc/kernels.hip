@@ -85,33 +85,6 @@ __device__ __forceinline__ double interp_one(const BoxDev& C, const T* Cold, con
 }
 
 template <typename T>
-__device__ __forceinline__ double interp_quartic(const BoxDev& C, const T* Cold, const T* Cnew, int ci, int cj,
-                                                 int ck, int fx, int fy, int fz, int anum) {
-  const double a = 0.25 * (double)anum;
-  const long long px = C.px, plane = px * C.py;
-  const double ax = (fx & 1) ? 11.0 / 64.0 : -11.0 / 64.0, bx = (fx & 1) ? -3.0 / 128.0 : 3.0 / 128.0;
-  const double ay = (fy & 1) ? 11.0 / 64.0 : -11.0 / 64.0, by = (fy & 1) ? -3.0 / 128.0 : 3.0 / 128.0;
-  const double az = (fz & 1) ? 11.0 / 64.0 : -11.0 / 64.0, bz = (fz & 1) ? -3.0 / 128.0 : 3.0 / 128.0;
-  const long long e0 = elem<T>(C, ci, cj, ck);
-  double hz[5];
-#pragma unroll
-  for (int dz = 0; dz < 5; ++dz) {
-    double gy[5];
-#pragma unroll
-    for (int dy = 0; dy < 5; ++dy) {
-      const long long e = e0 + (dz - 2) * plane + (dy - 2) * px;
-      const double cm2 = tinterp(Cold, Cnew, e - 2, anum, a), cm1 = tinterp(Cold, Cnew, e - 1, anum, a);
-      const double c0 = tinterp(Cold, Cnew, e, anum, a);
-      const double cp1 = tinterp(Cold, Cnew, e + 1, anum, a), cp2 = tinterp(Cold, Cnew, e + 2, anum, a);
-      gy[dy] = c0 + ((cp1 - cm1) * ax + (cp2 - cm2) * bx);
-    }
-    hz[dz] = gy[2] + ((gy[3] - gy[1]) * ay + (gy[4] - gy[0]) * by);
-  }
-  return hz[2] + ((hz[3] - hz[1]) * az + (hz[4] - hz[0]) * bz);
-}
-
-// IT: 1 = linear conservative, 4 = quartic conservative (reads two coarse ghost layers)
-template <typename T, int IT>
 __global__ __launch_bounds__(SH_BLOCK) void k_ghost_interp(const InterpSeg* __restrict__ segs,
                                                            const SegBlock* __restrict__ blocks,
                                                            const BoxDev* __restrict__ fboxes,
@@ -135,10 +108,98 @@ __global__ __launch_bounds__(SH_BLOCK) void k_ghost_interp(const InterpSeg* __re
   const int ci = (fx >> 1) + s.cshift[0], cj = (fy >> 1) + s.cshift[1], ck = (fz >> 1) + s.cshift[2];
   const long long ed = elem<T>(F, s.flo[0] + i, s.flo[1] + j, s.flo[2] + k);
   for (int comp = 0; comp < ncomp; ++comp) {
-    const double v = IT == 4
-                         ? interp_quartic<T>(C, Cold + comp * C.cs, Cnew + comp * C.cs, ci, cj, ck, fx, fy, fz, anum)
-                         : interp_one<T>(C, Cold + comp * C.cs, Cnew + comp * C.cs, ci, cj, ck, fx, fy, fz, anum);
+    const double v = interp_one<T>(C, Cold + comp * C.cs, Cnew + comp * C.cs, ci, cj, ck, fx, fy, fz, anum);
     dst[comp * F.cs + ed] = (T)v;
+  }
+}
+
+// Quartic: one workgroup per tile of parents of a segment (qtile_dims).  The
+// time-interpolated coarse values of the tile grown by two cells go to LDS once per
+// component; each thread then forms all eight children of its parent by the separable
+// passes (x for both child parities on the 25 (y, z) rows, y, then z), each child with the
+// same operations in the same order as one child alone, and stores those that lie in the
+// segment's fine region.
+template <typename T>
+__global__ __launch_bounds__(SH_BLOCK) void k_ghost_interp_q(const InterpSeg* __restrict__ segs,
+                                                             const SegBlock* __restrict__ blocks,
+                                                             const BoxDev* __restrict__ fboxes,
+                                                             const BoxDev* __restrict__ cboxes, int role,
+                                                             int anum, int ncomp) {
+  __shared__ double sm[QT_LDS];
+  const SegBlock sb = blocks[blockIdx.x];
+  const InterpSeg s = segs[sb.seg];
+  const int tile = sb.start / SH_BLOCK;
+  int p0[3], np[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    p0[d] = s.fg0[d] >> 1;  // floor: fine ghost indices may be negative
+    np[d] = ((s.fg0[d] + s.n[d] - 1) >> 1) - p0[d] + 1;
+  }
+  int qt[3];
+  qtile_dims(np, qt);
+  const int ntx = (np[0] + qt[0] - 1) / qt[0], nty = (np[1] + qt[1] - 1) / qt[1];
+  const int ix = tile % ntx, iy = (tile / ntx) % nty, iz = tile / (ntx * nty);
+  const int t0[3] = {p0[0] + ix * qt[0], p0[1] + iy * qt[1], p0[2] + iz * qt[2]};
+  const int tn[3] = {min(qt[0], np[0] - ix * qt[0]), min(qt[1], np[1] - iy * qt[1]), min(qt[2], np[2] - iz * qt[2])};
+  const int sx = tn[0] + 4, sy = tn[1] + 4, sz = tn[2] + 4;
+  const BoxDev& F = fboxes[s.fbox];
+  const BoxDev& C = cboxes[s.cbox];
+  const LevelScal& LC = *C.ls;
+  const T* Cnew = (const T*)C.slot[role_slot(ROLE_UN, LC)];
+  const T* Cold = (const T*)C.slot[role_slot(ROLE_OLD, LC)];
+  T* dst = (T*)F.slot[role_slot(role, *F.ls)];
+  const double a = 0.25 * (double)anum;
+  const int tid = threadIdx.x;
+  const bool has_p = tid < tn[0] * tn[1] * tn[2];
+  const int pi = tid % tn[0], pj = (tid / tn[0]) % tn[1], pk = tid / (tn[0] * tn[1]);
+  const double lo1 = -11.0 / 64.0, lo2 = 3.0 / 128.0, hi1 = 11.0 / 64.0, hi2 = -3.0 / 128.0;
+  for (int comp = 0; comp < ncomp; ++comp) {
+    const T* co = Cold + comp * C.cs;
+    const T* cn = Cnew + comp * C.cs;
+    for (int idx = tid; idx < sx * sy * sz; idx += SH_BLOCK) {
+      const int u = idx % sx, v = (idx / sx) % sy, w = idx / (sx * sy);
+      const long long e = elem<T>(C, t0[0] + u - 2 + s.cshift[0], t0[1] + v - 2 + s.cshift[1],
+                                  t0[2] + w - 2 + s.cshift[2]);
+      sm[idx] = tinterp(co, cn, e, anum, a);
+    }
+    __syncthreads();
+    if (has_p) {
+      double hz[2][2][5];  // [x child][y child][z row]
+#pragma unroll
+      for (int dz = 0; dz < 5; ++dz) {
+        double g[2][5];  // [x child][y row]
+#pragma unroll
+        for (int dy = 0; dy < 5; ++dy) {
+          const double* r = &sm[((pk + dz) * sy + (pj + dy)) * sx + pi];
+          const double d1 = r[3] - r[1], d2 = r[4] - r[0];
+          g[0][dy] = r[2] + (d1 * lo1 + d2 * lo2);
+          g[1][dy] = r[2] + (d1 * hi1 + d2 * hi2);
+        }
+#pragma unroll
+        for (int xc = 0; xc < 2; ++xc) {
+          const double d1 = g[xc][3] - g[xc][1], d2 = g[xc][4] - g[xc][0];
+          hz[xc][0][dz] = g[xc][2] + (d1 * lo1 + d2 * lo2);
+          hz[xc][1][dz] = g[xc][2] + (d1 * hi1 + d2 * hi2);
+        }
+      }
+#pragma unroll
+      for (int zc = 0; zc < 2; ++zc)
+#pragma unroll
+        for (int yc = 0; yc < 2; ++yc)
+#pragma unroll
+          for (int xc = 0; xc < 2; ++xc) {
+            const int fx = 2 * (t0[0] + pi) + xc, fy = 2 * (t0[1] + pj) + yc, fz = 2 * (t0[2] + pk) + zc;
+            if (fx < s.fg0[0] || fx >= s.fg0[0] + s.n[0] || fy < s.fg0[1] || fy >= s.fg0[1] + s.n[1] ||
+                fz < s.fg0[2] || fz >= s.fg0[2] + s.n[2])
+              continue;
+            const double* h = hz[xc][yc];
+            const double d1 = h[3] - h[1], d2 = h[4] - h[0];
+            const double val = h[2] + (zc ? (d1 * hi1 + d2 * hi2) : (d1 * lo1 + d2 * lo2));
+            const long long ed = elem<T>(F, s.flo[0] + fx - s.fg0[0], s.flo[1] + fy - s.fg0[1], s.flo[2] + fz - s.fg0[2]);
+            dst[comp * F.cs + ed] = (T)val;
+          }
+    }
+    __syncthreads();
   }
 }
 
@@ -569,24 +630,25 @@ void sh_launch_ghost_copy(int prec, const CopySeg* segs, const SegBlock* blocks,
     hipLaunchKernelGGL(k_ghost_copy<float>, dim3(nblocks), dim3(SH_BLOCK), 0, st, segs, blocks, boxes, role, ncomp);
 }
 
-template <int IT>
-static void ghost_interp_launch(int prec, const InterpSeg* segs, const SegBlock* blocks, int nblocks,
-                                const BoxDev* fboxes, const BoxDev* cboxes, int role, int anum, int ncomp,
-                                hipStream_t st) {
-  if (prec == 0)
-    hipLaunchKernelGGL((k_ghost_interp<double, IT>), dim3(nblocks), dim3(SH_BLOCK), 0, st, segs, blocks, fboxes, cboxes,
-                       role, anum, ncomp);
-  else
-    hipLaunchKernelGGL((k_ghost_interp<float, IT>), dim3(nblocks), dim3(SH_BLOCK), 0, st, segs, blocks, fboxes, cboxes,
-                       role, anum, ncomp);
-}
-
+// interp 4: the plan's blocks are quartic tiles (qtile_dims)
 void sh_launch_ghost_interp(int prec, int interp, const InterpSeg* segs, const SegBlock* blocks, int nblocks,
                             const BoxDev* fboxes, const BoxDev* cboxes, int role, int anum, int ncomp,
                             hipStream_t st) {
   if (nblocks == 0) return;
-  if (interp == 4) ghost_interp_launch<4>(prec, segs, blocks, nblocks, fboxes, cboxes, role, anum, ncomp, st);
-  else ghost_interp_launch<1>(prec, segs, blocks, nblocks, fboxes, cboxes, role, anum, ncomp, st);
+  if (interp == 4) {
+    if (prec == 0)
+      hipLaunchKernelGGL(k_ghost_interp_q<double>, dim3(nblocks), dim3(SH_BLOCK), 0, st, segs, blocks, fboxes, cboxes,
+                         role, anum, ncomp);
+    else
+      hipLaunchKernelGGL(k_ghost_interp_q<float>, dim3(nblocks), dim3(SH_BLOCK), 0, st, segs, blocks, fboxes, cboxes,
+                         role, anum, ncomp);
+  } else if (prec == 0) {
+    hipLaunchKernelGGL(k_ghost_interp<double>, dim3(nblocks), dim3(SH_BLOCK), 0, st, segs, blocks, fboxes, cboxes,
+                       role, anum, ncomp);
+  } else {
+    hipLaunchKernelGGL(k_ghost_interp<float>, dim3(nblocks), dim3(SH_BLOCK), 0, st, segs, blocks, fboxes, cboxes,
+                       role, anum, ncomp);
+  }
 }
 
 void sh_launch_avgdown(int prec, const AvgSeg* segs, const SegBlock* blocks, int nblocks, const BoxDev* cboxes,
