@@ -89,6 +89,8 @@ def main():
     ap.add_argument("--ko-order", type=int, default=0, choices=(0, 2, 3),
                     help="Kreiss-Oliger dissipation order (0 = off; per-stage wave-row kernels)")
     ap.add_argument("--ko-eps", type=float, default=0.01, help="Kreiss-Oliger dissipation strength")
+    ap.add_argument("--regrid", choices=("global", "local"), default="global",
+                    help="AMR workloads: global regrids, or local regrids with a global one when due")
     ap.add_argument("--interp", type=int, default=1, choices=(1, 4),
                     help="AMR workloads: ghost/new-cell interpolation, 1 = linear, 4 = quartic conservative")
     ap.add_argument("--beta", type=int, default=2, help="potential exponent (2: the paper's EOM; 0: stable companion)")
@@ -262,13 +264,15 @@ def bench_amr(args):
                                   + (", SSPRK3" if args.integrator != 4 else "")
                                   + (f", Laplacian order {args.lap_order}" if args.lap_order != 1 else "")
                                   + (", quartic interpolation" if args.interp == 4 else "")
+                                  + (", local regrids" if args.regrid == "local" else "")
                                   + (f", Kreiss-Oliger order {args.ko_order} eps {args.ko_eps}" if args.ko_order else ""),
                       "seed": args.seed}}
     if args.workload == "amr256":
         prec = shamr.SH_F64 if args.prec == "f64" else shamr.SH_F32
         h, rep = workloads.run_amr(U0, levels, steps, prec=prec, beta=args.beta, log=log, tag_mode=args.tag_mode,
                                    te_crit=args.te_crit, integrator=args.integrator, lap_order=args.lap_order,
-                                   interp=args.interp, ko_order=args.ko_order, ko_eps=args.ko_eps)
+                                   interp=args.interp, ko_order=args.ko_order, ko_eps=args.ko_eps,
+                                   regrid_mode=args.regrid)
         h.close()
         out.update({"value": rep["cell_updates_per_s_end_to_end"], "dtype": args.prec, "report": rep})
     else:

@@ -207,6 +207,30 @@ sh_status sh_cluster_boxes(int32_t M, int32_t nlevel_boxes, const int32_t* level
                            int32_t max_box, int32_t n_error_buf, double efficiency, int64_t ntag,
                            const int32_t* tags, int32_t* boxes_out, int32_t cap, int32_t* nboxes);
 
+/* Local regrid (section II, "Local versus global regrid"): instead of clustering all tags
+   anew, keep every box of the finer level and grow it, by whole blocks of the blocking
+   factor bf, where tagged cells (with their n_error_buf buffer) reach past it; coarser
+   levels grow where the added blocks need the nesting gap.  Host computations on box
+   lists (the tags come from sh_tag_cells); the caller applies the result with
+   sh_set_level_layout (old boxes + added ones, coarsest changed level first).
+   sh_local_tag_boxes: boxes to add to a level of M_fine cells per axis, given its current
+   boxes (none for a new level) and the tags (x, y, z int32 triples) of the level below;
+   the blocks that meet the refinement of each cube [tag - n_error_buf, tag + n_error_buf]
+   (periodic) and are not yet in the level.
+   sh_local_nest_boxes: boxes to add to a level of M_level cells per axis so that the
+   added boxes of the next finer level (added_fine, its index space) keep the nesting gap
+   of bf/2 cells of this level.
+   Added blocks are merged into runs along x of at most max_box cells, listed in (z, y, x)
+   block order; *nboxes receives their number.  Errors: SH_EINVAL (boxes not made of whole
+   blocks inside the level, a tag outside the coarser level, bad sizes), SH_ENOMEM (cap too
+   small; *nboxes is still set). */
+sh_status sh_local_tag_boxes(int32_t M_fine, int32_t nfine, const int32_t* fine_boxes, int32_t bf, int32_t n_error_buf,
+                             int32_t max_box, int64_t ntag, const int32_t* tags, int32_t* boxes_out, int32_t cap,
+                             int32_t* nboxes);
+sh_status sh_local_nest_boxes(int32_t M_level, int32_t nadded, const int32_t* added_fine, int32_t nlevel,
+                              const int32_t* level_boxes, int32_t bf, int32_t max_box, int32_t* boxes_out, int32_t cap,
+                              int32_t* nboxes);
+
 /* Wait for all work queued by this hierarchy; SH_EDEVICE if any kernel failed. */
 sh_status sh_sync(sh_hierarchy h);
 

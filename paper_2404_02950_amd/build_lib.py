@@ -29,7 +29,7 @@ HIP_FLAGS = [
 HOST_FLAGS = ["-O2", "-fPIC", "-std=c++17", "-ffp-contract=off", "-Wall"]
 
 HIP_SOURCES = ["kernels.hip", "kernels_hilap.hip", "kernels_ko.hip", "kernels_fused.hip", "runtime.cpp"]
-HOST_SOURCES = ["cluster.cpp"]
+HOST_SOURCES = ["cluster.cpp", "local_regrid.cpp"]
 
 
 def kernel_source_sha() -> str:

@@ -1470,6 +1470,44 @@ sh_status sh_cluster_boxes(int32_t M, int32_t nlevel_boxes, const int32_t* level
   return emit_boxes(out, boxes_out, cap, nboxes);
 }
 
+static bool read_boxes(int32_t n, const int32_t* in, std::vector<IBox>& out) {
+  out.clear();
+  if (n < 0 || (n > 0 && !in)) return false;
+  for (int i = 0; i < n; ++i) {
+    IBox b;
+    for (int d = 0; d < 3; ++d) {
+      b.lo[d] = in[6 * i + d];
+      b.hi[d] = in[6 * i + 3 + d];
+    }
+    out.push_back(b);
+  }
+  return true;
+}
+
+sh_status sh_local_tag_boxes(int32_t M_fine, int32_t nfine, const int32_t* fine_boxes, int32_t bf, int32_t n_error_buf,
+                             int32_t max_box, int64_t ntag, const int32_t* tags, int32_t* boxes_out, int32_t cap,
+                             int32_t* nboxes) {
+  std::vector<IBox> fb, out;
+  if (!read_boxes(nfine, fine_boxes, fb) || ntag < 0 || (ntag > 0 && !tags) || !nboxes || cap < 0 ||
+      (cap > 0 && !boxes_out) || n_error_buf < 0 || max_box < bf)
+    return fail(SH_EINVAL, "bad local regrid arguments");
+  std::string err;
+  if (!local_tag_boxes(M_fine, fb, bf, n_error_buf, max_box, tags, ntag, out, err)) return fail(SH_EINVAL, err);
+  return emit_boxes(out, boxes_out, cap, nboxes);
+}
+
+sh_status sh_local_nest_boxes(int32_t M_level, int32_t nadded, const int32_t* added_fine, int32_t nlevel,
+                              const int32_t* level_boxes, int32_t bf, int32_t max_box, int32_t* boxes_out, int32_t cap,
+                              int32_t* nboxes) {
+  std::vector<IBox> ab, lb, out;
+  if (!read_boxes(nadded, added_fine, ab) || !read_boxes(nlevel, level_boxes, lb) || !nboxes || cap < 0 ||
+      (cap > 0 && !boxes_out) || max_box < bf)
+    return fail(SH_EINVAL, "bad local regrid arguments");
+  std::string err;
+  if (!local_nest_boxes(M_level, ab, lb, bf, max_box, out, err)) return fail(SH_EINVAL, err);
+  return emit_boxes(out, boxes_out, cap, nboxes);
+}
+
 sh_status sh_cluster_tags(sh_hierarchy h, int32_t l, int64_t ntag, const int32_t* tags, double efficiency,
                           int32_t* boxes_out, int32_t cap, int32_t* nboxes) {
   sh_status s = check_level(h, l);

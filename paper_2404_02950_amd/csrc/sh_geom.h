@@ -155,3 +155,15 @@ inline long long covered_volume(const IBox& q, int M, const BoxBins& bins, const
 // (implemented in cluster.cpp).
 bool cluster_level(int M, const std::vector<IBox>& level_boxes, bool full_level, int bf, int max_box, int nbuf,
                    double efficiency, const int32_t* tags, long long ntag, std::vector<IBox>& out, std::string& err);
+
+// Local regrid (implemented in local_regrid.cpp), on the block grid of the finer level
+// (blocks of bf cells).  local_tag_boxes: boxes to add to level l+1 (fine index, M_fine
+// cells per axis) so that every tagged level-l cell with its n_error_buf buffer is
+// refined, given the level's current boxes.  local_nest_boxes: boxes to add to level k
+// (M_k cells per axis) so that the added level-(k+1) boxes keep a nesting gap of bf/2
+// level-k cells.  Added blocks are merged into x runs of at most max_box cells, listed in
+// (z, y, x) block order.
+bool local_tag_boxes(int M_fine, const std::vector<IBox>& fine_boxes, int bf, int nbuf, int max_box,
+                     const int32_t* tags, long long ntag, std::vector<IBox>& out, std::string& err);
+bool local_nest_boxes(int M_k, const std::vector<IBox>& added_fine, const std::vector<IBox>& level_boxes, int bf,
+                      int max_box, std::vector<IBox>& out, std::string& err);

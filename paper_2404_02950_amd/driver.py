@@ -12,6 +12,8 @@ from __future__ import annotations
 
 import time
 
+from . import shamr
+
 
 def _advance(h, lev: int, sub: int, finest: int):
     h.advance(lev, sub)
@@ -27,8 +29,8 @@ def coarse_step(h):
 
 
 def regrid(h, max_level: int, layout_for=None, efficiency: float = 0.7, max_level_bytes: int | None = None,
-           log=None, timing: dict | None = None):
-    """Rebuild levels 1..max_level from tags.
+           log=None, timing: dict | None = None, start: int = 1):
+    """Rebuild levels start..max_level from tags (levels below start are kept).
 
     ``layout_for(lev, ntag, idx)`` may return the boxes of level lev+1; by default the
     tags are clustered by the library (Berger-Rigoutsos).  ``max_level_bytes`` caps the
@@ -39,7 +41,7 @@ def regrid(h, max_level: int, layout_for=None, efficiency: float = 0.7, max_leve
     the tag counts.
     """
     counts = []
-    for lev in range(max_level):
+    for lev in range(max(0, start - 1), max_level):
         if lev >= h.num_levels():
             break
         t0 = time.perf_counter()
@@ -64,3 +66,92 @@ def regrid(h, max_level: int, layout_for=None, efficiency: float = 0.7, max_leve
         if not boxes:
             break
     return counts
+
+
+def local_regrid(h, max_level: int, log=None, timing: dict | None = None):
+    """Local regrid (section II, "Local versus global regrid"): every existing box stays;
+    from the coarsest level up, the tags of level l grow level l+1 (creating it if it is
+    the next level below max_level) where they come within n_error_buf cells of its
+    boundary, and coarser levels grow where the added boxes need the nesting gap.  Changed
+    levels are laid out again coarsest first (old cells kept, new ones interpolated).
+    Returns {level: cells added}."""
+    p = h.params
+    bf, nbuf, mb = p.blocking_factor, p.n_error_buf, p.max_box
+    added_cells = {}
+    for lev in range(max_level):
+        if lev >= h.num_levels():
+            break
+        t0 = time.perf_counter()
+        ntag, idx = h.tag(lev)
+        t1 = time.perf_counter()
+        fine = lev + 1
+        cur = h.boxes.get(fine, []) if fine < h.num_levels() else []
+        add = {}
+        new = shamr.local_tag_boxes(p.n0 << fine, cur, idx, bf, nbuf, mb) if ntag else []
+        if new:
+            add[fine] = new
+            k = lev
+            while new and k >= 1:
+                new = shamr.local_nest_boxes(p.n0 << k, new, h.boxes[k], bf, mb)
+                if new:
+                    add[k] = new
+                k -= 1
+        t2 = time.perf_counter()
+        for k in sorted(add):
+            old = h.boxes.get(k, []) if k < h.num_levels() else []
+            h.set_layout(k, list(old) + add[k])
+            added_cells[k] = added_cells.get(k, 0) + sum(
+                (b[3] - b[0] + 1) * (b[4] - b[1] + 1) * (b[5] - b[2] + 1) for b in add[k])
+        if timing is not None:
+            t3 = time.perf_counter()
+            for key, v in (("tag", t1 - t0), ("cluster", t2 - t1), ("layout", t3 - t2)):
+                timing[key] = timing.get(key, 0.0) + v
+        if log is not None and add:
+            log(f"local regrid from level {lev}: added " + ", ".join(f"{len(v)} boxes to level {k}"
+                                                                  for k, v in sorted(add.items())))
+    return added_cells
+
+
+class RegridPolicy:
+    """Choice between a local and a global regrid (section II, "Local versus global
+    regrid"): the volume added to each level by local regrids since the last global one,
+    as a fraction dV_l of the level's volume then, triggers a global regrid once some dV_l
+    exceeds eps_strong, starting at the lowest level with dV_l >= eps_weak (that level and
+    every finer one are rebuilt from the tags of the level below); so does the
+    max_local-th consecutive local regrid (then from level 1).  Defaults as in the paper:
+    10 %, 5 %, 10."""
+
+    def __init__(self, eps_strong: float = 0.10, eps_weak: float = 0.05, max_local: int = 10):
+        self.eps_s, self.eps_w, self.max_local = eps_strong, eps_weak, max_local
+        self.base = {}
+        self.added = {}
+        self.nlocal = 0
+
+    def after_global(self, cells_per_level):
+        """cells_per_level[l] = cells of level l right after a global regrid."""
+        self.base = {k: int(v) for k, v in enumerate(cells_per_level) if k >= 1}
+        self.added = {}
+        self.nlocal = 0
+
+    def after_local(self, added_cells):
+        for k, v in added_cells.items():
+            self.added[k] = self.added.get(k, 0) + int(v)
+        self.nlocal += 1
+
+    def fractions(self):
+        out = {}
+        for k in set(self.base) | set(self.added):
+            b, a = self.base.get(k, 0), self.added.get(k, 0)
+            out[k] = a / b if b else (float("inf") if a else 0.0)
+        return out
+
+    def decide(self):
+        """("local", None), or ("global", l): rebuild levels >= l (l >= 1) from the tags of
+        level l-1."""
+        if self.nlocal >= self.max_local:
+            return "global", 1
+        dv = self.fractions()
+        if any(v > self.eps_s for v in dv.values()):
+            return "global", max(1, min(k for k, v in dv.items() if v >= self.eps_w))
+        return "local", None
+

@@ -56,6 +56,10 @@ _PROTOS = {
                                   POINTER(c_int32)]),
     "sh_cluster_boxes": (c_int32, [c_int32, c_int32, c_void_p, c_int32, c_int32, c_int32, c_double, c_int64,
                                    c_void_p, c_void_p, c_int32, POINTER(c_int32)]),
+    "sh_local_tag_boxes": (c_int32, [c_int32, c_int32, c_void_p, c_int32, c_int32, c_int32, c_int64, c_void_p,
+                                     c_void_p, c_int32, POINTER(c_int32)]),
+    "sh_local_nest_boxes": (c_int32, [c_int32, c_int32, c_void_p, c_int32, c_void_p, c_int32, c_int32, c_void_p,
+                                      c_int32, POINTER(c_int32)]),
     "sh_sync": (c_int32, [c_void_p]),
     "sh_hierarchy_destroy": (c_int32, [c_void_p]),
     "sh_last_error": (c_char_p, []),
@@ -133,6 +137,43 @@ def cluster_boxes(M: int, level_boxes, tags, blocking_factor: int = 8, max_box: 
             continue
         _check(st)
         return [tuple(int(v) for v in r) for r in out[:nb.value]]
+
+
+def _boxes_call(fn):
+    """Run a box-producing library call with a growing output capacity."""
+    cap = 4096
+    while True:
+        out = np.empty((cap, 6), np.int32)
+        nb = c_int32()
+        st = fn(out.ctypes.data_as(c_void_p), cap, ctypes.byref(nb))
+        if st == SH_ENOMEM and nb.value > cap:
+            cap = nb.value
+            continue
+        _check(st)
+        return [tuple(int(v) for v in r) for r in out[:nb.value]]
+
+
+def local_tag_boxes(M_fine: int, fine_boxes, tags, blocking_factor: int = 8, n_error_buf: int = 2,
+                    max_box: int = 64):
+    """Boxes to add to a level (M_fine cells per axis) for the tags of the level below
+    (local regrid, see sh_local_tag_boxes; host only)."""
+    lib = load()
+    fb = np.ascontiguousarray(np.asarray(fine_boxes, np.int32).reshape(-1, 6))
+    t = np.ascontiguousarray(np.asarray(tags, np.int32).reshape(-1, 3))
+    return _boxes_call(lambda out, cap, nb: lib.sh_local_tag_boxes(
+        M_fine, len(fb), fb.ctypes.data_as(c_void_p), blocking_factor, n_error_buf, max_box, len(t),
+        t.ctypes.data_as(c_void_p), out, cap, nb))
+
+
+def local_nest_boxes(M_level: int, added_fine, level_boxes, blocking_factor: int = 8, max_box: int = 64):
+    """Boxes to add to a level so that the added boxes of the next finer level keep their
+    nesting gap (local regrid, see sh_local_nest_boxes; host only)."""
+    lib = load()
+    ab = np.ascontiguousarray(np.asarray(added_fine, np.int32).reshape(-1, 6))
+    lb = np.ascontiguousarray(np.asarray(level_boxes, np.int32).reshape(-1, 6))
+    return _boxes_call(lambda out, cap, nb: lib.sh_local_nest_boxes(
+        M_level, len(ab), ab.ctypes.data_as(c_void_p), len(lb), lb.ctypes.data_as(c_void_p), blocking_factor,
+        max_box, out, cap, nb))
 
 
 class Hierarchy:

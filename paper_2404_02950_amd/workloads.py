@@ -40,7 +40,7 @@ def level_summary(h):
 def run_amr(U0: np.ndarray, max_level: int, coarse_steps: int, prec: int = shamr.SH_F64, beta: int = 2,
             regrid_every: int = 2, log=print, efficiency: float = 0.7, max_level_bytes: int | None = None,
             tag_mode: int = 1, te_crit: float = 1e-2, integrator: int = 4, lap_order: int = 1, interp: int = 1,
-            ko_order: int = 0, ko_eps: float = 0.0):
+            ko_order: int = 0, ko_eps: float = 0.0, regrid_mode: str = "global"):
     """Advance an AMR hierarchy; returns (hierarchy, report dict).
 
     ``max_level_bytes`` (default: a quarter of the device memory free at the start) caps
@@ -51,7 +51,8 @@ def run_amr(U0: np.ndarray, max_level: int, coarse_steps: int, prec: int = shamr
     synchronisation); the initial layout uses the plaquettes, no estimate existing yet.
     ``integrator``: 4 = classic RK4, 3 or 10 = SSPRK3; ``lap_order``: 1, 2, 3 = 7-, 13-,
     19-point Laplacian; ``interp``: 1 linear, 4 quartic conservative; ``ko_order``/``ko_eps``:
-    Kreiss-Oliger dissipation."""
+    Kreiss-Oliger dissipation; ``regrid_mode``: "global" (cluster all tags every time) or
+    "local" (local regrids, with a global one when driver.RegridPolicy asks for it)."""
     import torch
     if max_level_bytes is None:
         max_level_bytes = torch.cuda.mem_get_info()[0] // 4
@@ -77,6 +78,9 @@ def run_amr(U0: np.ndarray, max_level: int, coarse_steps: int, prec: int = shamr
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     shadow = False
+    policy = driver.RegridPolicy()
+    policy.after_global([lv["cells"] for lv in levels0])
+    kinds = {"global": 0, "local": 0}
     for step in range(coarse_steps):
         if step > 0 and step % regrid_every == 0:
             if shadow:
@@ -85,8 +89,14 @@ def run_amr(U0: np.ndarray, max_level: int, coarse_steps: int, prec: int = shamr
             h.sync()  # the queued level steps are not regrid time
             tr = time.perf_counter()
             nlev = h.num_levels()
-            driver.regrid(h, max_level, efficiency=efficiency, max_level_bytes=max_level_bytes, log=log,
-                          timing=regrid_parts)
+            kind, start = policy.decide() if regrid_mode == "local" else ("global", 1)
+            if kind == "local":
+                policy.after_local(driver.local_regrid(h, max_level, log=None, timing=regrid_parts))
+            else:
+                driver.regrid(h, max_level, efficiency=efficiency, max_level_bytes=max_level_bytes, log=log,
+                              timing=regrid_parts, start=start)
+                policy.after_global([h.level_info(lev)["ncells"] for lev in range(h.num_levels())])
+            kinds[kind] += 1
             h.sync()
             if h.num_levels() < nlev:
                 capped.append({"coarse_step": step, "levels": h.num_levels()})
@@ -129,6 +139,8 @@ def run_amr(U0: np.ndarray, max_level: int, coarse_steps: int, prec: int = shamr
         "nonfinite_end": bad1,
         "tag_mode": tag_mode,
         "integrator": integrator,
+        "regrid_mode": regrid_mode,
+        "regrids": kinds,
         "lap_order": lap_order,
         "interp": interp,
         "ko_order": ko_order,
