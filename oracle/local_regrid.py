@@ -14,9 +14,11 @@ made of):
 * a level-(k+1) block B needs the level-k blocks that meet its coarsening grown by bf/2
   level-k cells (the nesting gap); missing ones are added to level k (k >= 1; level 0
   covers the domain), and in turn need their own support on level k-1;
-* added blocks become boxes by merging runs of consecutive blocks along x in the same
-  (y, z) block row, at most ``max_box`` cells long, without wrapping; boxes are listed in
-  (z, y, x) block order.
+* added blocks become boxes in three merges, each at most ``max_box`` cells long and
+  without wrapping: runs of consecutive blocks along x in each (y, z) block row (from the
+  lowest x); then runs with the same x extent in consecutive y rows of a z plane (from
+  the lowest y); then rectangles with the same x and y extents in consecutive z planes
+  (from the lowest z).  Boxes are listed by (z, y, x) of their lowest corner.
 """
 from __future__ import annotations
 
@@ -46,11 +48,31 @@ def _mark_range(need: np.ndarray, lo, hi):
     need[np.ix_(zs, ys, xs)] = True
 
 
+def _merge_runs(items, key, pos, run_max):
+    """Greedy merge of items whose ``key`` agrees and whose ``pos`` are consecutive: items
+    sorted by (key, pos), a run grows from its lowest pos while the next item continues it
+    and the run is shorter than run_max.  Items are (key..., lo, hi) with lo/hi = pos
+    extent; returns merged (key, lo, hi)."""
+    out = []
+    items = sorted(items, key=lambda t: (key(t), pos(t)[0]))
+    i = 0
+    while i < len(items):
+        k, (lo, hi) = key(items[i]), pos(items[i])
+        j = i + 1
+        while (j < len(items) and key(items[j]) == k and pos(items[j])[0] == hi + 1
+               and pos(items[j])[1] - lo + 1 <= run_max):
+            hi = pos(items[j])[1]
+            j += 1
+        out.append((k, lo, hi))
+        i = j
+    return out
+
+
 def blocks_to_boxes(new: np.ndarray, bf: int, max_box: int):
-    """Boxes (fine index, inclusive) from a block mask: x runs, at most max_box long."""
+    """Boxes (fine index, inclusive) from a block mask by the three merges above."""
     nb = new.shape[0]
     run_max = max(1, max_box // bf)
-    out = []
+    runs = []                                            # (z, y, x0, x1)
     for bz in range(nb):
         for by in range(nb):
             bx = 0
@@ -61,8 +83,17 @@ def blocks_to_boxes(new: np.ndarray, bf: int, max_box: int):
                 start = bx
                 while bx < nb and new[bz, by, bx] and bx - start < run_max:
                     bx += 1
-                out.append((start * bf, by * bf, bz * bf, bx * bf - 1, (by + 1) * bf - 1, (bz + 1) * bf - 1))
-    return out
+                runs.append((bz, by, start, bx - 1))
+    # y: same (z, x0, x1), consecutive y
+    rects = [(k[0], lo, hi, k[1], k[2]) for k, lo, hi in
+             _merge_runs(runs, key=lambda r: (r[0], r[2], r[3]), pos=lambda r: (r[1], r[1]), run_max=run_max)]
+    # z: same (y0, y1, x0, x1), consecutive z; rects are (z, y0, y1, x0, x1)
+    boxes = [(lo, k[0], k[1], k[2], k[3], hi) for k, lo, hi in
+             _merge_runs(rects, key=lambda r: (r[1], r[2], r[3], r[4]), pos=lambda r: (r[0], r[0]), run_max=run_max)]
+    # (z0, y0, y1, x0, x1, z1) -> fine boxes, ordered by lowest corner (z, y, x)
+    boxes.sort(key=lambda b: (b[0], b[1], b[3]))
+    return [(x0 * bf, y0 * bf, z0 * bf, (x1 + 1) * bf - 1, (y1 + 1) * bf - 1, (z1 + 1) * bf - 1)
+            for z0, y0, y1, x0, x1, z1 in boxes]
 
 
 def tag_blocks(tag_idx, M_coarse: int, bf: int, n_error_buf: int) -> np.ndarray:

@@ -27,8 +27,7 @@ def test_boundary_tag_adds_the_blocks_its_buffer_reaches():
     # y and z ranges 28..37 need blocks 3 and 4
     boxes = [[_cube(0, 31)], [_cube(16, 47)]]
     out = local_regrid(boxes, 32, 0, np.array([[23, 16, 16]]), 8, 2, 64)
-    assert out == {1: [(48, 24, 24, 55, 31, 31), (48, 32, 24, 55, 39, 31),
-                       (48, 24, 32, 55, 31, 39), (48, 32, 32, 55, 39, 39)]}
+    assert out == {1: [(48, 24, 24, 55, 39, 39)]}                # 1 x 2 x 2 blocks, merged
 
 
 def test_blocks_merge_along_x_up_to_max_box():
@@ -36,6 +35,20 @@ def test_blocks_merge_along_x_up_to_max_box():
     new[1, 2, 0:7] = True
     assert blocks_to_boxes(new, 8, 24) == [(0, 16, 8, 23, 23, 15), (24, 16, 8, 47, 23, 15),
                                            (48, 16, 8, 55, 23, 15)]
+
+
+def test_blocks_merge_in_y_and_z():
+    new = np.zeros((8, 8, 8), dtype=bool)
+    new[0:2, 0:5, 0:2] = True                   # 2 x 5 x 2 blocks: y extent capped at 3 blocks
+    new[3, 0, 4] = True                         # a lone block
+    assert blocks_to_boxes(new, 8, 24) == [(0, 0, 0, 15, 23, 15), (0, 24, 0, 15, 39, 15),
+                                           (32, 0, 24, 39, 7, 31)]
+    # every block exactly once
+    m = np.zeros((64,) * 3, dtype=bool)
+    for b in blocks_to_boxes(new, 8, 24):
+        assert not m[b[2]:b[5] + 1, b[1]:b[4] + 1, b[0]:b[3] + 1].any()
+        m[b[2]:b[5] + 1, b[1]:b[4] + 1, b[0]:b[3] + 1] = True
+    assert m.sum() == new.sum() * 512
 
 
 def test_periodic_wrap():
