@@ -68,59 +68,15 @@ __device__ __forceinline__ double tinterp(const T* Cold, const T* Cnew, long lon
   return (1.0 - a) * (double)Cold[e] + a * (double)Cnew[e];
 }
 
-template <typename T>
-__device__ __forceinline__ double interp_one(const BoxDev& C, const T* Cold, const T* Cnew, int ci, int cj,
-                                             int ck, int fx, int fy, int fz, int anum) {
-  const double a = 0.25 * (double)anum;
-  const long long px = C.px, plane = px * C.py;
-  const long long e = elem<T>(C, ci, cj, ck);
-  const double c0 = tinterp(Cold, Cnew, e, anum, a);
-  const double sx = (fx & 1) ? 0.125 : -0.125;
-  const double sy = (fy & 1) ? 0.125 : -0.125;
-  const double sz = (fz & 1) ? 0.125 : -0.125;
-  const double tx = (tinterp(Cold, Cnew, e + 1, anum, a) - tinterp(Cold, Cnew, e - 1, anum, a)) * sx;
-  const double ty = (tinterp(Cold, Cnew, e + px, anum, a) - tinterp(Cold, Cnew, e - px, anum, a)) * sy;
-  const double tz = (tinterp(Cold, Cnew, e + plane, anum, a) - tinterp(Cold, Cnew, e - plane, anum, a)) * sz;
-  return ((c0 + tx) + ty) + tz;
-}
-
-template <typename T>
+// One workgroup per tile of parent cells of a segment (qtile_dims).  The time-interpolated
+// coarse values of the tile grown by the reach G (1 linear, 2 quartic) go to LDS once per
+// component, so every coarse value is read and time-interpolated once; each thread then
+// forms all eight children of its parent, each child with the same operations in the same
+// order as one child alone (quartic: the separable passes, x for both child parities on
+// the 25 (y, z) rows, then y, then z), and stores those that lie in the segment's fine
+// region.
+template <typename T, int IT>
 __global__ __launch_bounds__(SH_BLOCK) void k_ghost_interp(const InterpSeg* __restrict__ segs,
-                                                           const SegBlock* __restrict__ blocks,
-                                                           const BoxDev* __restrict__ fboxes,
-                                                           const BoxDev* __restrict__ cboxes, int role,
-                                                           int anum, int ncomp) {
-  const SegBlock sb = blocks[blockIdx.x];
-  const InterpSeg s = segs[sb.seg];
-  const int c = sb.start + threadIdx.x;
-  if (c >= s.n[0] * s.n[1] * s.n[2]) return;
-  const int i = c % s.n[0];
-  const int r = c / s.n[0];
-  const int j = r % s.n[1];
-  const int k = r / s.n[1];
-  const BoxDev& F = fboxes[s.fbox];
-  const BoxDev& C = cboxes[s.cbox];
-  const LevelScal& LC = *C.ls;
-  const T* Cnew = (const T*)C.slot[role_slot(ROLE_UN, LC)];
-  const T* Cold = (const T*)C.slot[role_slot(ROLE_OLD, LC)];
-  T* dst = (T*)F.slot[role_slot(role, *F.ls)];
-  const int fx = s.fg0[0] + i, fy = s.fg0[1] + j, fz = s.fg0[2] + k;
-  const int ci = (fx >> 1) + s.cshift[0], cj = (fy >> 1) + s.cshift[1], ck = (fz >> 1) + s.cshift[2];
-  const long long ed = elem<T>(F, s.flo[0] + i, s.flo[1] + j, s.flo[2] + k);
-  for (int comp = 0; comp < ncomp; ++comp) {
-    const double v = interp_one<T>(C, Cold + comp * C.cs, Cnew + comp * C.cs, ci, cj, ck, fx, fy, fz, anum);
-    dst[comp * F.cs + ed] = (T)v;
-  }
-}
-
-// Quartic: one workgroup per tile of parents of a segment (qtile_dims).  The
-// time-interpolated coarse values of the tile grown by two cells go to LDS once per
-// component; each thread then forms all eight children of its parent by the separable
-// passes (x for both child parities on the 25 (y, z) rows, y, then z), each child with the
-// same operations in the same order as one child alone, and stores those that lie in the
-// segment's fine region.
-template <typename T>
-__global__ __launch_bounds__(SH_BLOCK) void k_ghost_interp_q(const InterpSeg* __restrict__ segs,
                                                              const SegBlock* __restrict__ blocks,
                                                              const BoxDev* __restrict__ fboxes,
                                                              const BoxDev* __restrict__ cboxes, int role,
@@ -141,7 +97,8 @@ __global__ __launch_bounds__(SH_BLOCK) void k_ghost_interp_q(const InterpSeg* __
   const int ix = tile % ntx, iy = (tile / ntx) % nty, iz = tile / (ntx * nty);
   const int t0[3] = {p0[0] + ix * qt[0], p0[1] + iy * qt[1], p0[2] + iz * qt[2]};
   const int tn[3] = {min(qt[0], np[0] - ix * qt[0]), min(qt[1], np[1] - iy * qt[1]), min(qt[2], np[2] - iz * qt[2])};
-  const int sx = tn[0] + 4, sy = tn[1] + 4, sz = tn[2] + 4;
+  constexpr int G = IT == 4 ? 2 : 1;
+  const int sx = tn[0] + 2 * G, sy = tn[1] + 2 * G, sz = tn[2] + 2 * G;
   const BoxDev& F = fboxes[s.fbox];
   const BoxDev& C = cboxes[s.cbox];
   const LevelScal& LC = *C.ls;
@@ -158,12 +115,33 @@ __global__ __launch_bounds__(SH_BLOCK) void k_ghost_interp_q(const InterpSeg* __
     const T* cn = Cnew + comp * C.cs;
     for (int idx = tid; idx < sx * sy * sz; idx += SH_BLOCK) {
       const int u = idx % sx, v = (idx / sx) % sy, w = idx / (sx * sy);
-      const long long e = elem<T>(C, t0[0] + u - 2 + s.cshift[0], t0[1] + v - 2 + s.cshift[1],
-                                  t0[2] + w - 2 + s.cshift[2]);
+      const long long e = elem<T>(C, t0[0] + u - G + s.cshift[0], t0[1] + v - G + s.cshift[1],
+                                  t0[2] + w - G + s.cshift[2]);
       sm[idx] = tinterp(co, cn, e, anum, a);
     }
     __syncthreads();
-    if (has_p) {
+    if (IT == 1 && has_p) {
+      // linear: f = ((C + t_x) + t_y) + t_z, t_d = (C_{+d} - C_{-d}) * (+-1/8)
+      const int c = ((pk + 1) * sy + (pj + 1)) * sx + pi + 1;
+      const double c0 = sm[c];
+      const double dx = sm[c + 1] - sm[c - 1], dy = sm[c + sx] - sm[c - sx], dz = sm[c + sx * sy] - sm[c - sx * sy];
+#pragma unroll
+      for (int zc = 0; zc < 2; ++zc)
+#pragma unroll
+        for (int yc = 0; yc < 2; ++yc)
+#pragma unroll
+          for (int xc = 0; xc < 2; ++xc) {
+            const int fx = 2 * (t0[0] + pi) + xc, fy = 2 * (t0[1] + pj) + yc, fz = 2 * (t0[2] + pk) + zc;
+            if (fx < s.fg0[0] || fx >= s.fg0[0] + s.n[0] || fy < s.fg0[1] || fy >= s.fg0[1] + s.n[1] ||
+                fz < s.fg0[2] || fz >= s.fg0[2] + s.n[2])
+              continue;
+            const double tx = dx * (xc ? 0.125 : -0.125), ty = dy * (yc ? 0.125 : -0.125);
+            const double tz = dz * (zc ? 0.125 : -0.125);
+            const long long ed = elem<T>(F, s.flo[0] + fx - s.fg0[0], s.flo[1] + fy - s.fg0[1], s.flo[2] + fz - s.fg0[2]);
+            dst[comp * F.cs + ed] = (T)(((c0 + tx) + ty) + tz);
+          }
+    }
+    if (IT == 4 && has_p) {
       double hz[2][2][5];  // [x child][y child][z row]
 #pragma unroll
       for (int dz = 0; dz < 5; ++dz) {
@@ -630,25 +608,25 @@ void sh_launch_ghost_copy(int prec, const CopySeg* segs, const SegBlock* blocks,
     hipLaunchKernelGGL(k_ghost_copy<float>, dim3(nblocks), dim3(SH_BLOCK), 0, st, segs, blocks, boxes, role, ncomp);
 }
 
-// interp 4: the plan's blocks are quartic tiles (qtile_dims)
+// the plan's blocks are parent tiles (qtile_dims)
+template <int IT>
+static void ghost_interp_launch(int prec, const InterpSeg* segs, const SegBlock* blocks, int nblocks,
+                                const BoxDev* fboxes, const BoxDev* cboxes, int role, int anum, int ncomp,
+                                hipStream_t st) {
+  if (prec == 0)
+    hipLaunchKernelGGL((k_ghost_interp<double, IT>), dim3(nblocks), dim3(SH_BLOCK), 0, st, segs, blocks, fboxes,
+                       cboxes, role, anum, ncomp);
+  else
+    hipLaunchKernelGGL((k_ghost_interp<float, IT>), dim3(nblocks), dim3(SH_BLOCK), 0, st, segs, blocks, fboxes, cboxes,
+                       role, anum, ncomp);
+}
+
 void sh_launch_ghost_interp(int prec, int interp, const InterpSeg* segs, const SegBlock* blocks, int nblocks,
                             const BoxDev* fboxes, const BoxDev* cboxes, int role, int anum, int ncomp,
                             hipStream_t st) {
   if (nblocks == 0) return;
-  if (interp == 4) {
-    if (prec == 0)
-      hipLaunchKernelGGL(k_ghost_interp_q<double>, dim3(nblocks), dim3(SH_BLOCK), 0, st, segs, blocks, fboxes, cboxes,
-                         role, anum, ncomp);
-    else
-      hipLaunchKernelGGL(k_ghost_interp_q<float>, dim3(nblocks), dim3(SH_BLOCK), 0, st, segs, blocks, fboxes, cboxes,
-                         role, anum, ncomp);
-  } else if (prec == 0) {
-    hipLaunchKernelGGL(k_ghost_interp<double>, dim3(nblocks), dim3(SH_BLOCK), 0, st, segs, blocks, fboxes, cboxes,
-                       role, anum, ncomp);
-  } else {
-    hipLaunchKernelGGL(k_ghost_interp<float>, dim3(nblocks), dim3(SH_BLOCK), 0, st, segs, blocks, fboxes, cboxes,
-                       role, anum, ncomp);
-  }
+  if (interp == 4) ghost_interp_launch<4>(prec, segs, blocks, nblocks, fboxes, cboxes, role, anum, ncomp, st);
+  else ghost_interp_launch<1>(prec, segs, blocks, nblocks, fboxes, cboxes, role, anum, ncomp, st);
 }
 
 void sh_launch_avgdown(int prec, const AvgSeg* segs, const SegBlock* blocks, int nblocks, const BoxDev* cboxes,

@@ -616,16 +616,14 @@ static bool interp_segs(const Level& F, const Level& C, int d, const IBox& R, in
       s.cshift[k] = -img.lo[k];
     }
     segs.push_back(s);
-    if (reach == 2) {
-      // quartic: the plan counts tiles of parents (one SH_BLOCK-sized slot each)
+    {
+      // the plan counts tiles of parent cells (one SH_BLOCK-sized slot each)
       int np[3], qt[3];
       for (int k = 0; k < 3; ++k) np[k] = (sub.hi[k] >> 1) - (sub.lo[k] >> 1) + 1;
       qtile_dims(np, qt);
       long long nt = 1;
       for (int k = 0; k < 3; ++k) nt *= (np[k] + qt[k] - 1) / qt[k];
       nc.push_back(nt * SH_BLOCK);
-    } else {
-      nc.push_back(sub.volume());
     }
     covered += sub.volume();
   });

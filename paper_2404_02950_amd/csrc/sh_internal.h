@@ -106,11 +106,12 @@ struct InterpSeg {
   int cshift[3];   // coarse local = floor(fg/2) + cshift
 };
 
-// Quartic interpolation works on tiles of parent cells of a segment (one workgroup each,
-// the time-interpolated coarse support in LDS); its block plan lists tile t of a segment
-// as SegBlock{seg, t * SH_BLOCK}.  Tile extents: the segment's parent extents capped at
-// 16, the largest halved until at most SH_BLOCK parents remain (thin ghost shells get
-// wide, flat tiles).  The support (extents + 4) then holds at most QT_LDS values.
+// Coarse-to-fine interpolation works on tiles of parent cells of a segment (one workgroup
+// each, the time-interpolated coarse support in LDS); its block plan lists tile t of a
+// segment as SegBlock{seg, t * SH_BLOCK}.  Tile extents: the segment's parent extents
+// capped at 16, the largest halved until at most SH_BLOCK parents remain (thin ghost
+// shells get wide, flat tiles).  The support (extents + 4 for the quartic reach of two
+// cells) then holds at most QT_LDS values.
 #define QT_LDS 2000
 __host__ __device__ inline void qtile_dims(const int np[3], int t[3]) {
   for (int d = 0; d < 3; ++d) t[d] = np[d] < 16 ? np[d] : 16;
