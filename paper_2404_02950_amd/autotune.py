@@ -18,13 +18,20 @@ FUSED_SHAPES = {0: (32, 8), 1: (64, 4), 2: (32, 16), 3: (16, 8)}
 FUSED_VARIANTS = (0, 3, 4, 5, 6)
 
 
-def candidates(boxes):
+def candidates(boxes, params=None):
     """Launch shapes that apply to a level with these boxes:
-    (kind, nontemporal, tile_z, fuse, fused_shape, fused_tile_z, fused_variant)."""
+    (kind, nontemporal, tile_z, fuse, fused_shape, fused_tile_z, fused_variant).  With the
+    hierarchy's params, fused shapes are offered only where the fused step applies (the
+    7-point stencil without dissipation), and SSPRK3 skips the accumulator variants."""
     out = [(8, 1, 0, 0, 0, 0, 0), (0, 1, 0, 0, 0, 0, 0)]
+    if params is not None and (params.lap_order > 1 or params.ko_order):
+        return out
+    variants = FUSED_VARIANTS
+    if params is not None and params.integrator in (3, 10):
+        variants = tuple(v for v in FUSED_VARIANTS if v not in (3, 6))   # they run as 4 and 5
     for shape, (tx, ty) in FUSED_SHAPES.items():
         if all(shamr.box_shape(b)[2] % tx == 0 and shamr.box_shape(b)[1] % ty == 0 for b in boxes):
-            out += [(8, 1, 0, 4, shape, 0, v) for v in FUSED_VARIANTS]
+            out += [(8, 1, 0, 4, shape, 0, v) for v in variants]
     return out
 
 
@@ -32,7 +39,8 @@ def _twin(h, stream):
     p = h.params
     t = shamr.Hierarchy(p.n0, p.L, p.cfl, p.eta0, p.lam, p.alpha_fric, p.beta_pot, max_level=0,
                         blocking_factor=p.blocking_factor, max_box=p.max_box, n_error_buf=p.n_error_buf,
-                        prec=p.prec, stream=stream)
+                        prec=p.prec, stream=stream, integrator=p.integrator, lap_order=p.lap_order,
+                        interp=p.interp, ko_order=p.ko_order, ko_eps=p.ko_eps)
     t.set_layout(0, h.boxes[0])
     t.write_dense(0, h.read_dense(0))
     t.fill_ghosts(0)
@@ -45,7 +53,7 @@ def tune(h, steps: int = 5, cands=None, log=None):
     import torch
     stream = torch.cuda.Stream()
     twin = _twin(h, stream)
-    cands = cands if cands is not None else candidates(h.boxes[0])
+    cands = cands if cands is not None else candidates(h.boxes[0], h.params)
     times = {}
     try:
         for c in cands:
