@@ -67,6 +67,27 @@ def cpu_baseline(U0, n: int, integrator: int = 4, order: int = 1, ko_order: int 
                       f"{dt:.1f} s on one host core"}
 
 
+def copy_bandwidth(stream, nbytes: int = 2 ** 31, reps: int = 10) -> float:
+    """GB/s of a device-to-device copy of nbytes (read + write counted), events on stream."""
+    import torch
+    with torch.cuda.stream(stream):
+        a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            b.copy_(a)
+        e1.record(stream)
+    torch.cuda.synchronize()
+    bw = 2 * nbytes * reps / (e0.elapsed_time(e1) / 1e3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    return bw
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -228,6 +249,13 @@ def main():
     if graph is not None:
         graph.close()
     h.close()
+    if out["roofline"] is not None:
+        # achievable HBM bandwidth on this machine: a plain device copy of 2 x 2 GiB, timed the
+        # same way (events on the same stream), beside the nominal peak
+        bw = copy_bandwidth(stream)
+        out["roofline"]["copy_GBs"] = bw
+        out["roofline"]["frac_of_copy"] = out["roofline"]["achieved"] / bw
+        log(f"device copy {bw:.0f} GB/s")
     if args.calib_copy:
         a = torch.empty(2 ** 28, dtype=torch.float64, device="cuda")
         b = torch.empty_like(a)
