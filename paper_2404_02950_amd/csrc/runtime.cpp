@@ -8,6 +8,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "shamr.h"
@@ -593,6 +594,12 @@ static void build_a1(const Level& L, int depth, std::vector<CopySeg>& segs, std:
   }
 }
 
+// Host threads for the plan of a level with n boxes: one per 64 boxes, at most 8.
+static int plan_workers(int n) {
+  const int hw = (int)std::max(1u, std::thread::hardware_concurrency());
+  return std::max(1, std::min({8, hw, n / 64}));
+}
+
 // Parents of fine region R (fine-global coordinates, possibly a ghost shell outside the
 // domain) among the coarse boxes; appends InterpSegs for fine box d.  Returns false if
 // some cell (or the one-cell slope support of its parent) is not covered.
@@ -635,25 +642,51 @@ static bool interp_segs(const Level& F, const Level& C, int d, const IBox& R, in
 // Coarse/fine ghost cells of F to a depth of `depth` cells (the stencil's reach; deeper
 // ghost layers are only ever read as same-level copies), interpolated with coarse support
 // `reach` cells around each parent.
-static bool build_a2(const Level& F, const Level& C, int depth, int reach, std::vector<InterpSeg>& segs,
-                     std::vector<long long>& nc) {
-  segs.clear();
-  nc.clear();
-  for (int d = 0; d < (int)F.boxes.size(); ++d) {
+// Boxes [b0, b1) of F; the plan is the concatenation over boxes in order.
+static bool build_a2_range(const Level& F, const Level& C, int depth, int reach, int b0, int b1,
+                           std::vector<InterpSeg>& segs, std::vector<long long>& nc) {
+  std::vector<IBox> shell, rem, nxt;
+  for (int d = b0; d < b1; ++d) {
     const IBox& D = F.boxes[d];
-    std::vector<IBox> shell;
+    shell.clear();
     subtract(grow(D, depth), D, shell);
     for (const IBox& P : shell) {
-      std::vector<IBox> rem{P};
+      rem.assign(1, P);
       for_images(P, F.M, F.bins, [&](int s, const int sh[3]) {
         const IBox img = shift(F.boxes[s], sh[0] * F.M, sh[1] * F.M, sh[2] * F.M);
-        std::vector<IBox> nxt;
+        if (rem.empty() || isect(P, img).empty()) return;  // leaves rem as it is
+        nxt.clear();
         for (const IBox& r : rem) subtract(r, img, nxt);
         rem.swap(nxt);
       });
       for (const IBox& R : rem)
         if (!interp_segs(F, C, d, R, reach, segs, nc)) return false;
     }
+  }
+  return true;
+}
+
+static bool build_a2(const Level& F, const Level& C, int depth, int reach, std::vector<InterpSeg>& segs,
+                     std::vector<long long>& nc) {
+  segs.clear();
+  nc.clear();
+  const int n = (int)F.boxes.size();
+  const int nw = plan_workers(n);
+  if (nw == 1) return build_a2_range(F, C, depth, reach, 0, n, segs, nc);
+  std::vector<std::vector<InterpSeg>> ps(nw);
+  std::vector<std::vector<long long>> pn(nw);
+  std::vector<char> ok(nw, 0);
+  std::vector<std::thread> th;
+  for (int w = 0; w < nw; ++w)
+    th.emplace_back([&, w] {
+      ok[w] = build_a2_range(F, C, depth, reach, (int)((long long)n * w / nw), (int)((long long)n * (w + 1) / nw),
+                             ps[w], pn[w]);
+    });
+  for (auto& t : th) t.join();
+  for (int w = 0; w < nw; ++w) {
+    if (!ok[w]) return false;
+    segs.insert(segs.end(), ps[w].begin(), ps[w].end());
+    nc.insert(nc.end(), pn[w].begin(), pn[w].end());
   }
   return true;
 }

@@ -84,20 +84,28 @@ inline void subtract(const IBox& a, const IBox& b, std::vector<IBox>& out) {
   }
 }
 
+// Visit marks of BoxBins::query, one set per thread (queries of one or several bins may
+// run on several threads at once; every query takes a fresh mark).
+struct BinStamps {
+  std::vector<int> stamp;
+  int cur = 0;
+};
+inline BinStamps& bin_stamps() {
+  thread_local BinStamps s;
+  return s;
+}
+
 // Uniform bins over [0, M)^3 listing the boxes that overlap each bin.
 struct BoxBins {
-  int M = 0, B = 32, nb = 0;
+  int M = 0, B = 32, nb = 0, nbox = 0;
   std::vector<std::vector<int>> bins;
-  mutable std::vector<int> stamp;
-  mutable int cur = 0;
 
   void build(const std::vector<IBox>& boxes, int M_) {
     M = M_;
     B = std::max(8, std::min(64, M));
     nb = (M + B - 1) / B;
     bins.assign((size_t)nb * nb * nb, {});
-    stamp.assign(boxes.size(), 0);
-    cur = 0;
+    nbox = (int)boxes.size();
     for (int i = 0; i < (int)boxes.size(); ++i) {
       const IBox& b = boxes[i];
       for (int z = b.lo[2] / B; z <= b.hi[2] / B; ++z)
@@ -115,16 +123,20 @@ struct BoxBins {
       q.hi[d] = std::min(q.hi[d], M - 1);
     }
     if (q.empty() || nb == 0) return;
-    if (++cur == 0x7fffffff) {
-      std::fill(stamp.begin(), stamp.end(), 0);
-      cur = 1;
+    BinStamps& st = bin_stamps();
+    if ((int)st.stamp.size() < nbox) st.stamp.resize(nbox, 0);
+    if (++st.cur == 0x7fffffff) {
+      std::fill(st.stamp.begin(), st.stamp.end(), 0);
+      st.cur = 1;
     }
+    const int mark = st.cur;
+    int* stamp = st.stamp.data();
     for (int z = q.lo[2] / B; z <= q.hi[2] / B; ++z)
       for (int y = q.lo[1] / B; y <= q.hi[1] / B; ++y)
         for (int x = q.lo[0] / B; x <= q.hi[0] / B; ++x)
           for (int i : bins[((size_t)z * nb + y) * nb + x])
-            if (stamp[i] != cur) {
-              stamp[i] = cur;
+            if (stamp[i] != mark) {
+              stamp[i] = mark;
               f(i);
             }
   }
@@ -132,11 +144,17 @@ struct BoxBins {
 
 // f(box, shift[3]) for every periodic image box + shift*M (shift in {-1,0,1}^3) that
 // may overlap q, which may reach up to M cells outside [0, M)^3.
+// Only shifts whose image of the domain meets q are visited.
 template <class F>
 inline void for_images(const IBox& q, int M, const BoxBins& bins, F f) {
-  for (int sz = -1; sz <= 1; ++sz)
-    for (int sy = -1; sy <= 1; ++sy)
-      for (int sx = -1; sx <= 1; ++sx) {
+  int s0[3], s1[3];
+  for (int d = 0; d < 3; ++d) {
+    s0[d] = q.lo[d] < 0 ? -1 : (q.lo[d] < M ? 0 : 1);
+    s1[d] = q.hi[d] >= M ? 1 : (q.hi[d] >= 0 ? 0 : -1);
+  }
+  for (int sz = s0[2]; sz <= s1[2]; ++sz)
+    for (int sy = s0[1]; sy <= s1[1]; ++sy)
+      for (int sx = s0[0]; sx <= s1[0]; ++sx) {
         const int sh[3] = {sx, sy, sz};
         const IBox qs = shift(q, -sx * M, -sy * M, -sz * M);
         bins.query(qs, [&](int b) { f(b, sh); });

@@ -136,7 +136,7 @@ def cluster_boxes(M: int, level_boxes, tags, blocking_factor: int = 8, max_box: 
             cap = nb.value
             continue
         _check(st)
-        return [tuple(int(v) for v in r) for r in out[:nb.value]]
+        return [tuple(r) for r in out[:nb.value].tolist()]
 
 
 def _boxes_call(fn):
@@ -150,7 +150,7 @@ def _boxes_call(fn):
             cap = nb.value
             continue
         _check(st)
-        return [tuple(int(v) for v in r) for r in out[:nb.value]]
+        return [tuple(r) for r in out[:nb.value].tolist()]
 
 
 def local_tag_boxes(M_fine: int, fine_boxes, tags, blocking_factor: int = 8, n_error_buf: int = 2,
@@ -232,7 +232,7 @@ class Hierarchy:
             arena = self.torch.empty(nbytes, dtype=self.torch.uint8, device="cuda")
         _check(self.lib.sh_set_level_layout(self.h, lev, len(b), ptr, c_void_p(arena.data_ptr()), nbytes))
         self.arenas[lev] = arena  # the previous arena is released after the call (stream-ordered)
-        self.boxes[lev] = [tuple(int(v) for v in row) for row in b]
+        self.boxes[lev] = [tuple(r) for r in b.tolist()]
 
     def num_levels(self) -> int:
         return int(self.lib.sh_num_levels(self.h))
@@ -392,7 +392,7 @@ class Hierarchy:
                 cap = nb.value
                 continue
             _check(st)
-            return [tuple(int(v) for v in r) for r in out[:nb.value]]
+            return [tuple(r) for r in out[:nb.value].tolist()]
 
     def sync(self):
         _check(self.lib.sh_sync(self.h))
@@ -439,7 +439,7 @@ class Hierarchy:
         n = self.lib.sh_trace_read(self.h, None, 0)
         buf = np.empty((max(n, 1), 4), np.int32)
         self.lib.sh_trace_read(self.h, buf.ctypes.data_as(c_void_p), n)
-        return [tuple(int(v) for v in r) for r in buf[:n]]
+        return [tuple(r) for r in buf[:n].tolist()]
 
 
 class Batch:
