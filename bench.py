@@ -47,8 +47,8 @@ def traffic_from_profiles(prec: str, n: int, kname: str):
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    from paper_2404_02950_amd.build_lib import kernel_source_sha
-    if rec.get("kernel_source_sha256") != kernel_source_sha():
+    from paper_2404_02950_amd.build_lib import kernel_family, kernel_source_sha
+    if rec.get("kernel_source_sha256") != kernel_source_sha(kernel_family(kname)):
         return None
     return rec.get("hbm_bytes_per_launch")
 

@@ -32,13 +32,24 @@ HIP_SOURCES = ["kernels.hip", "kernels_hilap.hip", "kernels_ko.hip", "kernels_fu
 HOST_SOURCES = ["cluster.cpp", "local_regrid.cpp"]
 
 
-def kernel_source_sha() -> str:
-    """SHA-256 over the device-code sources; counter summaries record it so a figure taken
-    on other kernels is not reported for these."""
+# the device-code sources each kernel family is compiled from
+KERNEL_SOURCES = {
+    "fused": ("kernels_fused.hip", "sh_device.h", "sh_internal.h"),
+    "stage": ("kernels.hip", "kernels_hilap.hip", "kernels_ko.hip", "sh_stage.h", "sh_device.h", "sh_internal.h"),
+}
+
+
+def kernel_family(kernel: str) -> str:
+    """'fused' for the fused step (k_fused_step, fused_* bench names), else 'stage'."""
+    return "fused" if ("fused" in kernel) else "stage"
+
+
+def kernel_source_sha(family: str = "fused") -> str:
+    """SHA-256 over the sources of one kernel family; counter summaries record it so a
+    figure taken on other kernels is not reported for these."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("kernels.hip", "kernels_hilap.hip", "kernels_ko.hip", "kernels_fused.hip", "sh_stage.h", "sh_device.h",
-              "sh_internal.h"):
+    for f in KERNEL_SOURCES[family]:
         with open(os.path.join(CSRC, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()

@@ -53,7 +53,7 @@ def stats(args):
 
 
 def traffic(args):
-    from paper_2404_02950_amd.build_lib import kernel_source_sha
+    from paper_2404_02950_amd.build_lib import KERNEL_SOURCES, kernel_family, kernel_source_sha
     fetch = _per_kernel(args.fetch, "FETCH_SIZE")
     write = _per_kernel(args.write, "WRITE_SIZE")
     esize = 8 if args.prec == "f64" else 4
@@ -83,7 +83,8 @@ def traffic(args):
         "hbm_bytes_per_launch": fb + wb,
         "algorithmic_bytes_per_launch": alg,
         "traffic_over_algorithmic": (fb + wb) / alg,
-        "kernel_source_sha256": kernel_source_sha(),
+        "kernel_source_sha256": kernel_source_sha(kernel_family(kname)),
+        "kernel_sources": list(KERNEL_SOURCES[kernel_family(kname)]),
         "command_fetch": args.cmd_fetch,
         "command_write": args.cmd_write,
     }
