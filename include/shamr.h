@@ -97,8 +97,9 @@ typedef struct {
                            p = 3 or 5: Q = (-1)^((p+3)/2) eps dx^p / 2^(p+1) times the sum
                            of the (p+1)-st central differences, added to the right-hand
                            side of all four components.  Refined levels then keep that
-                           many ghost layers, the fills between stages carry Pi too, every
-                           stage runs on wave-row tiles and the fused step is not used */
+                           many ghost layers, the fills between stages carry Pi too, the
+                           block-row stage kernel stages Pi through LDS as well, and the
+                           fused step is not used */
   double ko_eps;        /* sim.dissipation_strength eps >= 0 */
 } sh_params;
 
@@ -245,8 +246,8 @@ sh_status sh_debug_stage_scalars(sh_hierarchy h, int32_t lev, int32_t s, double*
 
 /* Launch shape (performance only; results are identical for every choice).
    kind: 0 = per-stage kernel with one wavefront per 64-cell tile for every box; 4 or 8 =
-     blocks of that many wavefront rows sharing psi through LDS for boxes at least 64
-     cells wide.
+     blocks of that many wavefront rows sharing psi (and Pi under dissipation) through
+     LDS for boxes at least 64 cells wide.
    nontemporal: 1 = once-used streams do not stay cache resident.
    tile_z: cells per per-stage tile in z (0 = from the level size).
    fuse: 4 = level 0 (which has no coarse/fine boundary) takes each step in one kernel

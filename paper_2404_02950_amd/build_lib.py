@@ -28,14 +28,14 @@ HIP_FLAGS = [
 ]
 HOST_FLAGS = ["-O2", "-fPIC", "-std=c++17", "-ffp-contract=off", "-Wall"]
 
-HIP_SOURCES = ["kernels.hip", "kernels_hilap.hip", "kernels_ko.hip", "kernels_fused.hip", "runtime.cpp"]
+HIP_SOURCES = ["kernels.hip", "kernels_hilap.hip", "kernels_ko.hip", "kernels_ko_lds.hip", "kernels_fused.hip", "runtime.cpp"]
 HOST_SOURCES = ["cluster.cpp", "local_regrid.cpp"]
 
 
 # the device-code sources each kernel family is compiled from
 KERNEL_SOURCES = {
     "fused": ("kernels_fused.hip", "sh_device.h", "sh_internal.h"),
-    "stage": ("kernels.hip", "kernels_hilap.hip", "kernels_ko.hip", "sh_stage.h", "sh_device.h", "sh_internal.h"),
+    "stage": ("kernels.hip", "kernels_hilap.hip", "kernels_ko.hip", "kernels_ko_lds.hip", "sh_stage.h", "sh_device.h", "sh_internal.h"),
 }
 
 

@@ -577,7 +577,8 @@ static inline int nblk(long long n, int per) { return (int)((n + per - 1) / per)
 // order (kernels_ko.hip)
 void sh_launch_stage(int prec, int s, int kind, bool nt, int order, int ko, const Tile* tiles, int ntiles,
                      const BoxDev* boxes, hipStream_t st) {
-  if (ko > 0) sh_launch_stage_ko(prec, s, nt, order, ko, tiles, ntiles, boxes, st);
+  if (ko > 0 && kind != 0) sh_launch_stage_ko_lds(prec, s, kind, nt, order, ko, tiles, ntiles, boxes, st);
+  else if (ko > 0) sh_launch_stage_ko(prec, s, nt, order, ko, tiles, ntiles, boxes, st);
   else if (order > 1) sh_launch_stage_hilap(prec, s, kind, nt, order, tiles, ntiles, boxes, st);
   else stage_launch_radius<1>(prec, s, kind, nt, tiles, ntiles, boxes, st);
 }

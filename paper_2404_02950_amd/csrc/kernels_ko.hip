@@ -1,6 +1,7 @@
-// Per-stage and right-hand-side kernels with Kreiss-Oliger dissipation (orders 2 and 3)
-// for every Laplacian order, instantiated from sh_stage.h (wave-row tiles: the
-// dissipation stencils Pi as well, whose neighbours are read through the caches).
+// Per-stage kernels with Kreiss-Oliger dissipation (orders 2 and 3) on wave-row tiles
+// (boxes narrower than 64 cells; the dissipation stencils Pi as well, whose neighbours are
+// read through the caches), and the right-hand-side kernels, for every Laplacian order,
+// instantiated from sh_stage.h.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 

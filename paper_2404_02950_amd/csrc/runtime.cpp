@@ -134,7 +134,7 @@ static int interp_reach(const sh_params& p) { return interp_of(p) == 4 ? 2 : 1; 
 
 // Kreiss-Oliger dissipation order (0 = off, 2, 3 = the ghost cells its stencil needs).  It
 // stencils Pi as well as psi, so the fills between stages then carry all four
-// components, and every stage runs on wave-row tiles.
+// components (and the block-row stage kernel stages Pi through LDS as well).
 static int ko_of(const sh_params& p) { return p.ko_order; }
 static double ko_coef(const sh_params& p, double dx) {
   if (p.ko_order == 2) return -p.ko_eps / (16.0 * dx);
@@ -239,12 +239,6 @@ static Tuning default_tuning(const sh_params& p) {
     t.fshape = 2;
     t.fvar = 6;
   }
-  return t;
-}
-
-// per-stage launch shape: wave rows for every box under dissipation
-static Tuning stage_tuning(const sh_params& p, Tuning t) {
-  if (ko_of(p)) t.kind = 0;
   return t;
 }
 
@@ -925,7 +919,7 @@ static sh_status set_box_tables(sh_hierarchy h, LevelScal* ls, Level& L) {
   HIPCHK(L.tiles.upload(L.g.tiles));
   {
     std::vector<Tile> wt, bt, ft;
-    make_stage_tiles(L.boxes, stage_tuning(h->p, h->tune), L.g.nvalid, wt, bt);
+    make_stage_tiles(L.boxes, h->tune, L.g.nvalid, wt, bt);
     HIPCHK(L.stiles_w.upload(wt));
     HIPCHK(L.stiles_b.upload(bt));
     if (fusable(h->p)) make_fused_tiles(L.boxes, h->tune, L.g.ng, ft);
@@ -1574,7 +1568,7 @@ sh_status sh_set_tuning(sh_hierarchy h, int32_t kind, int32_t nontemporal, int32
   h->tune.fvar = fused_variant;
   for (Level& L : h->lev) {
     std::vector<Tile> wt, bt, ft;
-    make_stage_tiles(L.boxes, stage_tuning(h->p, h->tune), L.g.nvalid, wt, bt);
+    make_stage_tiles(L.boxes, h->tune, L.g.nvalid, wt, bt);
     HIPCHK(L.stiles_w.upload(wt));
     HIPCHK(L.stiles_b.upload(bt));
     if (fusable(h->p)) make_fused_tiles(L.boxes, h->tune, L.g.ng, ft);

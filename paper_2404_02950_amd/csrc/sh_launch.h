@@ -6,14 +6,17 @@
 #include "sh_internal.h"
 
 // order: the Laplacian order of appendix A (1, 2, 3: 7-, 13-, 19-point stencil); ko:
-// the Kreiss-Oliger dissipation order (0 = off, 2, 3; wave-row tiles only)
+// the Kreiss-Oliger dissipation order (0 = off, 2, 3); kind: 0 = wave-row tiles, 4 or 8 =
+// block-row tiles of that many rows
 void sh_launch_stage(int prec, int s, int kind, bool nt, int order, int ko, const Tile* tiles, int ntiles,
                      const BoxDev* boxes, hipStream_t st);
 void sh_launch_rhs(int prec, int order, int ko, const Tile* tiles, int ntiles, const BoxDev* boxes,
                    const long long* out_off, double* out, hipStream_t st);
-// with dissipation (kernels_ko.hip)
+// with dissipation (kernels_ko.hip: wave rows; kernels_ko_lds.hip: block rows)
 void sh_launch_stage_ko(int prec, int s, bool nt, int order, int ko, const Tile* tiles, int ntiles,
                         const BoxDev* boxes, hipStream_t st);
+void sh_launch_stage_ko_lds(int prec, int s, int kind, bool nt, int order, int ko, const Tile* tiles, int ntiles,
+                            const BoxDev* boxes, hipStream_t st);
 void sh_launch_rhs_ko(int prec, int order, int ko, const Tile* tiles, int ntiles, const BoxDev* boxes,
                       const long long* out_off, double* out, hipStream_t st);
 // orders 2 and 3 (kernels_hilap.hip)

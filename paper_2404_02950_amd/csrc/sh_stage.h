@@ -229,16 +229,20 @@ __global__ __launch_bounds__(SH_BLOCK) void k_stage(const Tile* __restrict__ til
 
 // Block-row kernel for boxes at least 64 cells wide: a block of ROWS wavefronts covers a
 // 64 x ROWS footprint (wave w owns row y0 + w) and marches in z in lock step.  Each wave
-// keeps psi(z-H..z+H) of its own row in registers and publishes psi(z) of the row to
-// LDS, where the rows above and below (and the H x-halo columns on each side, loaded by
-// the edge lanes; the H halo rows on each side, loaded by the first and last waves) are
-// read back.  psi is therefore fetched about (ROWS+2H)/ROWS times per plane instead of
-// 4H+1 times through the caches.
-template <typename T, int S, bool NT, int ROWS, int H>
+// keeps the stencilled components at planes z-HR..z+HR of its own row in registers and
+// publishes plane z of the row to LDS, where the rows above and below (and the HR x-halo
+// columns on each side, loaded by the edge lanes; the HR halo rows on each side, loaded
+// by the first and last waves) are read back.  The stencilled components are psi (the
+// Laplacian, radius H) and, with dissipation (order KD), Pi as well; HR is the wider
+// radius.  Each is therefore fetched about (ROWS+2HR)/ROWS times per plane instead of
+// 4HR+1 times through the caches.
+template <typename T, int S, bool NT, int ROWS, int H, int KD = 0>
 __global__ __launch_bounds__(SH_WAVE * ROWS) void k_stage_lds(const Tile* __restrict__ tiles, int ntiles,
                                                               const BoxDev* __restrict__ boxes) {
-  static_assert(H <= ROWS && H < SH_WAVE / 2, "halo loads by the edge waves and lanes");
-  __shared__ T sm[2][2][ROWS + 2 * H][SH_WAVE + 2 * H];
+  constexpr int HR = H > KD ? H : KD;  // halo radius
+  constexpr int NC = KD > 0 ? 4 : 2;   // stencilled components
+  static_assert(HR <= ROWS && HR < SH_WAVE / 2, "halo loads by the edge waves and lanes");
+  __shared__ T sm[2][NC][ROWS + 2 * HR][SH_WAVE + 2 * HR];
   const int lane = threadIdx.x & (SH_WAVE - 1);
   const int w = threadIdx.x >> 6;
   const int t = xcd_remap(blockIdx.x, gridDim.x);
@@ -258,42 +262,44 @@ __global__ __launch_bounds__(SH_WAVE * ROWS) void k_stage_lds(const Tile* __rest
   const int x = x0 + lane, y = y0 + w;
   const bool active = (x < B.nx) && (y < B.ny);
   // rows and columns past the box edge load the ghost rows/columns instead (valid
-  // memory: the shell is at least H deep), so the active cells next to the edge read
+  // memory: the shell is at least HR deep), so the active cells next to the edge read
   // their true neighbours from LDS
-  const int xl = min(x, B.nx + H - 1), yl = min(y, B.ny + H - 1);
+  const int xl = min(x, B.nx + HR - 1), yl = min(y, B.ny + HR - 1);
   const long long px = B.px;
   const long long plane = px * B.py;
   const long long cs = B.cs;
   const int zend = min(z0 + zc, B.nz);
   const T idx2 = (T)sc.inv_dx2;
+  const T kc = (T)L.ko;
 
   long long e = elem<T>(B, xl, yl, z0);
-  // halo rows: waves 0..H-1 load rows y0-H.., waves ROWS-H.. load rows y0+ROWS..; when
-  // the two sets are disjoint (ROWS >= 2H) a wave holds one halo row (one address, one
+  // halo rows: waves 0..HR-1 load rows y0-HR.., waves ROWS-HR.. load rows y0+ROWS..; when
+  // the two sets are disjoint (ROWS >= 2HR) a wave holds one halo row (one address, one
   // value per component), else the middle waves hold two
-  constexpr bool ONE_H = ROWS >= 2 * H;
-  const bool has_lo = w < H, has_hi = w >= ROWS - H;
-  const long long elo = elem<T>(B, xl, has_lo ? y0 - H + w : yl, z0);
-  const long long ehi = elem<T>(B, xl, has_hi ? min(y0 + ROWS + w - (ROWS - H), B.ny + H - 1) : yl, z0);
+  constexpr bool ONE_H = ROWS >= 2 * HR;
+  const bool has_lo = w < HR, has_hi = w >= ROWS - HR;
+  const long long elo = elem<T>(B, xl, has_lo ? y0 - HR + w : yl, z0);
+  const long long ehi = elem<T>(B, xl, has_hi ? min(y0 + ROWS + w - (ROWS - HR), B.ny + HR - 1) : yl, z0);
   const long long eh1 = has_lo ? elo : ehi;  // ONE_H: the wave's halo row
-  const int hrow1 = has_lo ? w : w + 2 * H;
-  // x-halo columns: lanes 0..H-1 load x0-H.., lanes 64-H.. load x0+64.. (disjoint sets)
-  const bool has_x = lane < H || lane >= SH_WAVE - H;
-  const long long ex = elem<T>(B, lane < H ? x0 - H + lane : min(x0 + lane + H, B.nx + H - 1), yl, z0);
-  const int xcol = lane < H ? lane : lane + 2 * H;
+  const int hrow1 = has_lo ? w : w + 2 * HR;
+  // x-halo columns: lanes 0..HR-1 load x0-HR.., lanes 64-HR.. load x0+64.. (disjoint sets)
+  const bool has_x = lane < HR || lane >= SH_WAVE - HR;
+  const long long ex = elem<T>(B, lane < HR ? x0 - HR + lane : min(x0 + lane + HR, B.nx + HR - 1), yl, z0);
+  const int xcol = lane < HR ? lane : lane + 2 * HR;
 
-  T win[2][2 * H + 1];
+  T win[NC][2 * HR + 1];
 #pragma unroll
-  for (int c = 0; c < 2; ++c)
+  for (int c = 0; c < NC; ++c)
 #pragma unroll
-    for (int j = 0; j < 2 * H; ++j) win[c][j] = X[c * cs + e + (j - H) * plane];
+    for (int j = 0; j < 2 * HR; ++j) win[c][j] = X[c * cs + e + (j - HR) * plane];
   int buf = 0;
   for (int z = z0; z < zend; ++z, e += plane, buf ^= 1) {
     const long long zo = (long long)(z - z0) * plane;
-    T hlo[2] = {(T)0, (T)0}, hhi[2] = {(T)0, (T)0}, vx[2] = {(T)0, (T)0};
+    T hlo[NC], hhi[NC], vx[NC];
 #pragma unroll
-    for (int c = 0; c < 2; ++c) {
-      win[c][2 * H] = X[c * cs + e + H * plane];
+    for (int c = 0; c < NC; ++c) {
+      hlo[c] = hhi[c] = vx[c] = (T)0;
+      win[c][2 * HR] = X[c * cs + e + HR * plane];
       if constexpr (ONE_H) {
         if (has_lo || has_hi) hlo[c] = X[c * cs + eh1 + zo];
       } else {
@@ -302,39 +308,56 @@ __global__ __launch_bounds__(SH_WAVE * ROWS) void k_stage_lds(const Tile* __rest
       }
       if (has_x) vx[c] = X[c * cs + ex + zo];
     }
-    const T q0 = ld<NT>(X + 2 * cs + e), q1 = ld<NT>(X + 3 * cs + e);
+    T q0, q1;
+    if constexpr (KD > 0) {
+      q0 = win[2][HR];
+      q1 = win[3][HR];
+    } else {
+      q0 = ld<NT>(X + 2 * cs + e);
+      q1 = ld<NT>(X + 3 * cs + e);
+    }
     double un4[4], acc4[4];
     stage_loads<T, S, NT>(Un, P.acc, cs, e, un4, acc4);
-    // LDS row j holds y = y0 - H + j, column i holds x = x0 - H + i
+    // LDS row j holds y = y0 - HR + j, column i holds x = x0 - HR + i
 #pragma unroll
-    for (int c = 0; c < 2; ++c) {
-      sm[buf][c][w + H][lane + H] = win[c][H];
+    for (int c = 0; c < NC; ++c) {
+      sm[buf][c][w + HR][lane + HR] = win[c][HR];
       if constexpr (ONE_H) {
-        if (has_lo || has_hi) sm[buf][c][hrow1][lane + H] = hlo[c];
+        if (has_lo || has_hi) sm[buf][c][hrow1][lane + HR] = hlo[c];
       } else {
-        if (has_lo) sm[buf][c][w][lane + H] = hlo[c];
-        if (has_hi) sm[buf][c][w + 2 * H][lane + H] = hhi[c];
+        if (has_lo) sm[buf][c][w][lane + HR] = hlo[c];
+        if (has_hi) sm[buf][c][w + 2 * HR][lane + HR] = hhi[c];
       }
-      if (has_x) sm[buf][c][w + H][xcol] = vx[c];
+      if (has_x) sm[buf][c][w + HR][xcol] = vx[c];
     }
     lds_barrier();
-    T lap[2];
+    // per-radius neighbour sums of every stencilled component (Laplacian: psi, radii
+    // 1..H; dissipation: every component, radii 1..KD)
+    T Ssum[NC][HR];
 #pragma unroll
-    for (int c = 0; c < 2; ++c) {
-      T Ssum[H];
+    for (int c = 0; c < NC; ++c)
 #pragma unroll
-      for (int r = 1; r <= H; ++r) {
-        const T xm = sm[buf][c][w + H][lane + H - r], xp = sm[buf][c][w + H][lane + H + r];
-        const T ym = sm[buf][c][w + H - r][lane + H], yp = sm[buf][c][w + H + r][lane + H];
-        Ssum[r - 1] = ((xm + xp) + (ym + yp)) + (win[c][H - r] + win[c][H + r]);
+      for (int r = 1; r <= HR; ++r) {
+        const T xm = sm[buf][c][w + HR][lane + HR - r], xp = sm[buf][c][w + HR][lane + HR + r];
+        const T ym = sm[buf][c][w + HR - r][lane + HR], yp = sm[buf][c][w + HR + r][lane + HR];
+        Ssum[c][r - 1] = ((xm + xp) + (ym + yp)) + (win[c][HR - r] + win[c][HR + r]);
       }
-      lap[c] = lap_combine<T, H>(Ssum, win[c][H], idx2);
+    const T lap0 = lap_combine<T, H>(Ssum[0], win[0][HR], idx2);
+    const T lap1 = lap_combine<T, H>(Ssum[1], win[1][HR], idx2);
+    if constexpr (KD > 0) {
+      T ko4[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) ko4[c] = kc * ko_sum<T, KD>(Ssum[c], win[c][HR]);
+      if (active)
+        stage_cell<T, S, NT, true>(sc, Un, Y, P.acc, cs, e, win[0][HR], win[1][HR], q0, q1, lap0, lap1, un4, acc4,
+                                   ko4);
+    } else {
+      if (active) stage_cell<T, S, NT>(sc, Un, Y, P.acc, cs, e, win[0][HR], win[1][HR], q0, q1, lap0, lap1, un4, acc4);
     }
-    if (active) stage_cell<T, S, NT>(sc, Un, Y, P.acc, cs, e, win[0][H], win[1][H], q0, q1, lap[0], lap[1], un4, acc4);
 #pragma unroll
-    for (int c = 0; c < 2; ++c)
+    for (int c = 0; c < NC; ++c)
 #pragma unroll
-      for (int j = 0; j < 2 * H; ++j) win[c][j] = win[c][j + 1];
+      for (int j = 0; j < 2 * HR; ++j) win[c][j] = win[c][j + 1];
   }
 }
 

@@ -46,11 +46,15 @@ def test_right_hand_side_bitwise(ko, order):
 
 
 @pytest.mark.parametrize("ko", [2, 3])
-@pytest.mark.parametrize("integrator,order,prec", [(4, 1, 0), (10, 2, 0), (4, 3, 1), (10, 1, 1)])
-def test_single_level_bitwise(ko, integrator, order, prec):
+@pytest.mark.parametrize("integrator,order,prec,kind", [(4, 1, 0, 8), (10, 2, 0, 8), (4, 3, 1, 8), (10, 1, 1, 8),
+                                                         (4, 3, 0, 4), (10, 1, 0, 4), (4, 2, 1, 0)])
+def test_single_level_bitwise(ko, integrator, order, prec, kind):
+    # boxes 64 wide run on block-row tiles of `kind` rows (psi and Pi staged through LDS),
+    # the narrower ones on wave rows; kind 0 puts every box on wave rows
     n = 72
     U0 = random_state(n, float(n), 7)
     h = _level(U0, ko, order, integrator, boxes=decompose(n, [[64], [36], [40]]), prec=prec)
+    h.set_tuning(kind=kind)
     h.profile(True)
     ref = run_single_level(U0.astype(np.float32) if prec else U0, 4, 0.1, 0.25, 1.0, beta=0, integrator=integrator,
                            order=order, ko_order=ko, ko_eps=EPS)
