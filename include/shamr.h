@@ -249,7 +249,8 @@ sh_status sh_debug_stage_scalars(sh_hierarchy h, int32_t lev, int32_t s, double*
      blocks of that many wavefront rows sharing psi (and Pi under dissipation) through
      LDS for boxes at least 64 cells wide.
    nontemporal: 1 = once-used streams do not stay cache resident.
-   tile_z: cells per per-stage tile in z (0 = from the level size).
+   tile_z: cells per per-stage tile in z (0 = from the level size: 64, halved down to 1
+     while the level has fewer than 16384 tiles).
    fuse: 4 = level 0 (which has no coarse/fine boundary) takes each step in one kernel
      computing all the integrator's stages (temporal blocking; needs every level-0 box to
      be a multiple of the fused footprint, else per-stage); 0 = per-stage kernels.

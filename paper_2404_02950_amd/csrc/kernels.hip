@@ -28,13 +28,17 @@ __global__ void k_counter_inc(LevelScal* ls, int n) {
 // A1: same-level ghost copy (periodic images included) of the first ncomp components:
 // the psi pair on the stepping path, all four before a regrid interpolates from them.
 // ---------------------------------------------------------------------------------
+// One wavefront per chunk of up to 64 cells of a segment (four chunks per workgroup), so
+// the many small edge and corner pieces of small boxes do not each take a workgroup.
 template <typename T>
 __global__ __launch_bounds__(SH_BLOCK) void k_ghost_copy(const CopySeg* __restrict__ segs,
-                                                         const SegBlock* __restrict__ blocks,
+                                                         const SegBlock* __restrict__ chunks, int nchunks,
                                                          const BoxDev* __restrict__ boxes, int role, int ncomp) {
-  const SegBlock sb = blocks[blockIdx.x];
+  const int ch = __builtin_amdgcn_readfirstlane(blockIdx.x * (SH_BLOCK / SH_WAVE) + (threadIdx.x >> 6));
+  if (ch >= nchunks) return;  // uniform over the wavefront
+  const SegBlock sb = chunks[ch];
   const CopySeg s = segs[sb.seg];
-  const int c = sb.start + threadIdx.x;
+  const int c = sb.start + (threadIdx.x & (SH_WAVE - 1));
   if (c >= s.n[0] * s.n[1] * s.n[2]) return;
   const int i = c % s.n[0];
   const int r = c / s.n[0];
@@ -600,13 +604,15 @@ void sh_launch_counter_inc(LevelScal* ls, int n, hipStream_t st) {
   hipLaunchKernelGGL(k_counter_inc, dim3(nblk(n, 64)), dim3(64), 0, st, ls, n);
 }
 
-void sh_launch_ghost_copy(int prec, const CopySeg* segs, const SegBlock* blocks, int nblocks, const BoxDev* boxes,
+void sh_launch_ghost_copy(int prec, const CopySeg* segs, const SegBlock* chunks, int nchunks, const BoxDev* boxes,
                           int role, int ncomp, hipStream_t st) {
-  if (nblocks == 0) return;
+  if (nchunks == 0) return;
+  const int per = SH_BLOCK / SH_WAVE;
+  const dim3 grid((nchunks + per - 1) / per);
   if (prec == 0)
-    hipLaunchKernelGGL(k_ghost_copy<double>, dim3(nblocks), dim3(SH_BLOCK), 0, st, segs, blocks, boxes, role, ncomp);
+    hipLaunchKernelGGL(k_ghost_copy<double>, grid, dim3(SH_BLOCK), 0, st, segs, chunks, nchunks, boxes, role, ncomp);
   else
-    hipLaunchKernelGGL(k_ghost_copy<float>, dim3(nblocks), dim3(SH_BLOCK), 0, st, segs, blocks, boxes, role, ncomp);
+    hipLaunchKernelGGL(k_ghost_copy<float>, grid, dim3(SH_BLOCK), 0, st, segs, chunks, nchunks, boxes, role, ncomp);
 }
 
 // the plan's blocks are parent tiles (qtile_dims)

@@ -58,7 +58,9 @@ struct DevArr {
   }
 };
 
-template <typename S>
+// Segments and their work chunks: chunk k covers cells [start, start + CHUNK) of one
+// segment (one workgroup per chunk, or one wavefront for CHUNK = SH_WAVE).
+template <typename S, int CHUNK = SH_BLOCK>
 struct SegPlan {
   DevArr<S> segs;
   DevArr<SegBlock> blocks;
@@ -68,7 +70,7 @@ struct SegPlan {
     std::vector<SegBlock> b;
     ncells = 0;
     for (size_t i = 0; i < v.size(); ++i) {
-      for (long long s = 0; s < ncell_per_seg[i]; s += SH_BLOCK) b.push_back(SegBlock{(int)i, (int)s});
+      for (long long s = 0; s < ncell_per_seg[i]; s += CHUNK) b.push_back(SegBlock{(int)i, (int)s});
       ncells += ncell_per_seg[i];
     }
     hipError_t e = segs.upload(v);
@@ -104,14 +106,18 @@ struct LayoutGeom {
 
 static long long round_up(long long v, long long a) { return (v + a - 1) / a * a; }
 
-static int tile_zc_default(long long cells) {
+// Planes per tile: 64, halved (down to zmin) while the level would have fewer than 16384
+// wave tiles.  The per-stage kernels of small refined levels run fastest with single-plane
+// tiles (more wavefronts in flight outweigh the z-window reuse); tagging and energy tiles
+// keep at least 4.
+static int tile_zc_default(long long cells, int zmin = 4) {
   const char* env = std::getenv("SHAMR_TILE_Z");
   if (env) {
     int v = std::atoi(env);
     if (v >= 1 && v <= 1024) return v;
   }
   long long zc = 64;
-  while (zc > 4 && cells / (64LL * zc) < 16384) zc >>= 1;
+  while (zc > zmin && cells / (64LL * zc) < 16384) zc >>= 1;
   return (int)zc;
 }
 
@@ -272,7 +278,7 @@ static void make_stage_tiles(const std::vector<IBox>& boxes, const Tuning& tu, l
                              std::vector<Tile>& wt, std::vector<Tile>& bt) {
   wt.clear();
   bt.clear();
-  int zc = tu.zc > 0 ? tu.zc : tile_zc_default(nvalid);
+  int zc = tu.zc > 0 ? tu.zc : tile_zc_default(nvalid, 1);
   for (size_t bi = 0; bi < boxes.size(); ++bi) {
     const IBox& b = boxes[bi];
     const int nx = b.size(0), ny = b.size(1), nz = b.size(2);
@@ -387,8 +393,8 @@ struct Level {
   DevArr<Tile> tiles;             // wave tiles of every box (tagging, energy, rhs)
   DevArr<Tile> stiles_w, stiles_b;  // stage-kernel tiles: wave rows / block rows
   DevArr<long long> xoff_valid, xoff_ghost, rhs_off;
-  SegPlan<CopySeg> a1;    // same-level ghost copy, one layer
-  SegPlan<CopySeg> a1d;   // the same over the whole ghost depth (when deeper than one)
+  SegPlan<CopySeg, SH_WAVE> a1;    // same-level ghost copy, one layer (a wavefront per chunk)
+  SegPlan<CopySeg, SH_WAVE> a1d;   // the same over the whole ghost depth (when deeper than one)
   DevArr<Tile> ftiles;    // fused-step tiles (level 0 only)
   SegPlan<InterpSeg> a2;  // coarse -> this level's ghosts
   SegPlan<AvgSeg> a5;     // this level -> coarse level
@@ -746,7 +752,7 @@ static sh_status same_level_fill(sh_hierarchy h, int l, int role, int ncomp = 0,
   Level& L = h->lev[l];
   h->rec(2, l, role, 0);
   const bool use_deep = deep && L.a1d.nblocks();
-  const SegPlan<CopySeg>& pl = use_deep ? L.a1d : L.a1;
+  const SegPlan<CopySeg, SH_WAVE>& pl = use_deep ? L.a1d : L.a1;
   if (ncomp == 0) ncomp = fill_comps(h->p);
   if (use_deep) ncomp = 4;
   hipEvent_t ev = h->prof_begin();
@@ -1694,8 +1700,8 @@ struct sh_batch_s {
   DevArr<BoxDev> boxes;          // every job's level-0 boxes, job after job
   DevArr<Tile> ftiles;           // fused-step tiles of the jobs that take the fused path
   DevArr<Tile> wtiles, btiles;   // per-stage tiles of the other jobs
-  SegPlan<CopySeg> a1_stage;     // one-layer ghost copy of the per-stage jobs
-  SegPlan<CopySeg> a1_deep;      // full-depth ghost copy of every job (after the step)
+  SegPlan<CopySeg, SH_WAVE> a1_stage;  // one-layer ghost copy of the per-stage jobs
+  SegPlan<CopySeg, SH_WAVE> a1_deep;   // full-depth ghost copy of every job (after the step)
   DevArr<LevelScal*> counters;
   std::vector<long long> versions;  // each job's layout version when the batch was built
   void release() {

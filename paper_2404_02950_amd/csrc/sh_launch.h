@@ -26,7 +26,8 @@ void sh_launch_rhs_hilap(int prec, int order, const Tile* tiles, int ntiles, con
                          const long long* out_off, double* out, hipStream_t st);
 void sh_launch_counter_inc(LevelScal* ls, int n, hipStream_t st);
 void sh_launch_counter_inc_list(LevelScal* const* ls, int n, hipStream_t st);
-void sh_launch_ghost_copy(int prec, const CopySeg* segs, const SegBlock* blocks, int nblocks, const BoxDev* boxes,
+// chunks of up to SH_WAVE cells (one wavefront each)
+void sh_launch_ghost_copy(int prec, const CopySeg* segs, const SegBlock* chunks, int nchunks, const BoxDev* boxes,
                           int role, int ncomp, hipStream_t st);
 // interp: 1 = linear conservative, 4 = quartic conservative
 void sh_launch_ghost_interp(int prec, int interp, const InterpSeg* segs, const SegBlock* blocks, int nblocks,
