@@ -148,13 +148,17 @@ def test_energy_matches_oracle_fp64():
     h.close()
 
 
-def test_full_size_512_sampled_parity():
-    # the 512^3 lattice in the launch configuration bench.py times: 2 steps, then
-    # sampled cells against the oracle run on periodic crops around each sample (after 2
-    # RK4 steps a cell depends only on cells within 8 of it)
+@pytest.mark.parametrize("prec,integrator", [(shamr.SH_F64, 4), (shamr.SH_F32, 4), (shamr.SH_F64, 10)])
+def test_full_size_512_sampled_parity(prec, integrator):
+    # the 512^3 lattice in the launch configuration bench.py times (FP64 and FP32 storage,
+    # RK4 and SSPRK3): 2 steps, then sampled cells against the oracle run on periodic crops
+    # around each sample (after 2 steps a cell depends only on cells within 8 of it)
     n = 512
     U0 = random_state(n, float(n), 0)
-    h = single_level(U0)
+    h = shamr.Hierarchy(n, float(n), 0.25, 0.1, 1.0, 2.0, 2, max_level=0, prec=prec, integrator=integrator)
+    h.set_layout(0, decompose(n))
+    h.write_dense(0, U0)
+    h.fill_ghosts(0)
     h.advance(0)
     h.advance(0)
     got = h.read_boxes(0)[0]
@@ -166,9 +170,11 @@ def test_full_size_512_sampled_parity():
         iy = np.arange(y - r, y + r + 1) % n
         ix = np.arange(x - r, x + r + 1) % n
         crop = U0[:, iz][:, :, iy][:, :, :, ix]
-        ref = run_single_level(crop, 2, 0.1, 0.25, 1.0)
+        if prec == shamr.SH_F32:
+            crop = crop.astype(np.float32)
+        ref = run_single_level(crop, 2, 0.1, 0.25, 1.0, integrator=integrator)
         c = slice(r - 3, r + 4)
-        want = ref[:, c, c, c]
+        want = ref[:, c, c, c].astype(np.float64)
         g = got[:, iz[c]][:, :, iy[c]][:, :, :, ix[c]]
         assert_bitwise(g, want, f"sample {(z, y, x)}")
     h.close()
