@@ -592,6 +592,28 @@ static void build_a1(const Level& L, int depth, std::vector<CopySeg>& segs, std:
       nc.push_back(R.volume());
     });
   }
+  // One box spanning the periodic domain: its x-ghost runs are `depth` cells wide, a part
+  // of one 64-byte memory sector on each side.  Widening them to the whole sector (the
+  // x-padding before x = 0 and after the shell, which nothing reads) turns the partial
+  // sector reads and writes of these runs into whole ones; the extra cells copy valid
+  // cells.  Needs nx a multiple of the sector's element count and that much row padding.
+  if (L.boxes.size() == 1) {
+    const int xo = L.g.xoff, nx = L.boxes[0].size(0);
+    if (L.boxes[0].size(0) == L.M && nx % xo == 0 && nx >= xo && L.g.px[0] >= 2 * xo + nx && depth <= xo) {
+      for (size_t i = 0; i < segs.size(); ++i) {
+        CopySeg& c = segs[i];
+        if (c.n[0] != depth) continue;
+        if (c.dlo[0] == -depth) {
+          c.dlo[0] = -xo;
+          c.slo[0] -= xo - depth;
+        } else if (c.dlo[0] != nx) {
+          continue;
+        }
+        c.n[0] = xo;
+        nc[i] = (long long)c.n[0] * c.n[1] * c.n[2];
+      }
+    }
+  }
 }
 
 // Host threads for the plan of a level with n boxes: one per 64 boxes, at most 8.
