@@ -44,6 +44,29 @@ struct Bits {
     const size_t k = key(n, x, y, z);
     return (w[k >> 6] >> (k & 63)) & 1;
   }
+  // bits k0..k1 (inclusive)
+  void set_range(size_t k0, size_t k1) {
+    const size_t w0 = k0 >> 6, w1 = k1 >> 6;
+    const uint64_t m0 = ~0ull << (k0 & 63), m1 = ~0ull >> (63 - (k1 & 63));
+    if (w0 == w1) {
+      w[w0] |= m0 & m1;
+      return;
+    }
+    w[w0] |= m0;
+    for (size_t i = w0 + 1; i < w1; ++i) w[i] = ~0ull;
+    w[w1] |= m1;
+  }
+  // x = lo..hi (periodic, fewer than n cells) of row (y, z)
+  void set_x(int lo, int hi, int y, int z) {
+    const size_t row = key(n, 0, y, z);
+    const int a = ((lo % n) + n) % n, b = ((hi % n) + n) % n;
+    if (a <= b) {
+      set_range(row + a, row + b);
+    } else {
+      set_range(row + a, row + n - 1);
+      set_range(row, row + b);
+    }
+  }
 };
 
 int floordiv(int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
@@ -59,6 +82,8 @@ struct Ctx {
   double eff = 0.7;
   std::vector<IBox> out;
   std::vector<long long> sig[3];
+  std::vector<long long> lap;  // second differences of a signature (reused)
+  std::vector<Pt> tmp;         // upper part during a cut (reused)
 };
 
 IBox bounding(const Pt* p, long long n) {
@@ -117,7 +142,8 @@ void br(Ctx& C, long long first, long long count) {
       const int len = box.size(d);
       if (len < 4) continue;
       const std::vector<long long>& sig = C.sig[d];
-      std::vector<long long> lap(len, 0);
+      std::vector<long long>& lap = C.lap;
+      lap.assign(len, 0);
       for (int i = 1; i + 1 < len; ++i) lap[i] = sig[i - 1] - 2 * sig[i] + sig[i + 1];
       const double mid = 0.5 * (len - 1);
       for (int i = 1; i + 2 < len; ++i) {
@@ -141,8 +167,14 @@ void br(Ctx& C, long long first, long long count) {
     best_cut = box.lo[best_d] + box.size(best_d) / 2;
   }
   const int d = best_d, cut = best_cut;
-  Pt* mid = std::stable_partition(p, p + count, [&](const Pt& q) { return q.c[d] < cut; });
-  const long long nlo = mid - p;
+  // stable partition: the lower part in place, the upper part through C.tmp
+  long long nlo = 0;
+  C.tmp.clear();
+  for (long long i = 0; i < count; ++i) {
+    if (p[i].c[d] < cut) p[nlo++] = p[i];
+    else C.tmp.push_back(p[i]);
+  }
+  std::copy(C.tmp.begin(), C.tmp.end(), p + nlo);
   br(C, first, nlo);
   br(C, first + nlo, count - nlo);
 }
@@ -168,7 +200,9 @@ bool cluster_level(int M, const std::vector<IBox>& level_boxes, bool full_level,
         err = "level box outside the level";
         return false;
       }
-  Bits tagged;
+  // the two bitsets keep their storage between calls on a thread (fresh allocations of a
+  // few MB would be page-faulted in on every regrid)
+  thread_local Bits tagged, cov;
   tagged.init(nb);
   for (long long t = 0; t < ntag; ++t) {
     int c[3], lo[3], hi[3];
@@ -186,27 +220,42 @@ bool cluster_level(int M, const std::vector<IBox>& level_boxes, bool full_level,
       }
     }
     for (int z = lo[2]; z <= hi[2]; ++z)
-      for (int y = lo[1]; y <= hi[1]; ++y)
-        for (int x = lo[0]; x <= hi[0]; ++x) tagged.set(wrap(x, nb), wrap(y, nb), wrap(z, nb));
+      for (int y = lo[1]; y <= hi[1]; ++y) tagged.set_x(lo[0], hi[0], wrap(y, nb), wrap(z, nb));
   }
-  Bits cov;
   if (!full_level) {
     cov.init(nb);
     for (const IBox& L : level_boxes) {
       // blocks fully inside the box
       const int x0 = (L.lo[0] + b - 1) / b, y0 = (L.lo[1] + b - 1) / b, z0 = (L.lo[2] + b - 1) / b;
       const int x1 = (L.hi[0] + 1) / b - 1, y1 = (L.hi[1] + 1) / b - 1, z1 = (L.hi[2] + 1) / b - 1;
+      if (x1 < x0) continue;
       for (int z = z0; z <= z1; ++z)
-        for (int y = y0; y <= y1; ++y)
-          for (int x = x0; x <= x1; ++x) cov.set(x, y, z);
+        for (int y = y0; y <= y1; ++y) cov.set_x(x0, x1, y, z);
     }
   }
   Ctx C;
   C.eff = efficiency;
   C.cov = full_level ? nullptr : &cov;
-  // tagged blocks in (z, y, x) order, without those whose neighbourhood leaves the level
+  // tagged blocks in (z, y, x) order, without those whose neighbourhood leaves the level.
+  // When rows are whole words, the neighbourhood test runs on 64 blocks at once: a block
+  // is allowed iff the allowed-block bits of the 3 x 3 rows around its row, each also
+  // shifted by one block either way, all hold.
+  const bool rows_in_words = !full_level && nb % 64 == 0;
+  const int W = nb / 64;
   for (size_t wi = 0; wi < tagged.w.size(); ++wi) {
     uint64_t word = tagged.w[wi];
+    if (word && rows_in_words) {
+      const size_t row = wi / W;
+      const int wx = (int)(wi % W), y = (int)(row % nb), z = (int)(row / nb);
+      uint64_t ok = ~0ull;
+      for (int dz = -1; dz <= 1; ++dz)
+        for (int dy = -1; dy <= 1; ++dy) {
+          const size_t r = ((size_t)wrap(z + dz, nb) * nb + wrap(y + dy, nb)) * W;
+          const uint64_t c = cov.w[r + wx], cl = cov.w[r + (wx + W - 1) % W], cr = cov.w[r + (wx + 1) % W];
+          ok &= c & ((c << 1) | (cl >> 63)) & ((c >> 1) | (cr << 63));
+        }
+      word &= ok;
+    }
     while (word) {
       const int bit = __builtin_ctzll(word);
       word &= word - 1;
@@ -215,7 +264,7 @@ bool cluster_level(int M, const std::vector<IBox>& level_boxes, bool full_level,
       q.c[0] = (int)(k % nb);
       q.c[1] = (int)((k / nb) % nb);
       q.c[2] = (int)(k / ((size_t)nb * nb));
-      if (!full_level) {
+      if (!full_level && !rows_in_words) {
         IBox one;
         for (int d = 0; d < 3; ++d) one.lo[d] = one.hi[d] = q.c[d];
         if (!clean(cov, one)) continue;
