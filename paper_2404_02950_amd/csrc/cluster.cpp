@@ -59,6 +59,10 @@ struct Bits {
   // x = lo..hi (periodic, fewer than n cells) of row (y, z)
   void set_x(int lo, int hi, int y, int z) {
     const size_t row = key(n, 0, y, z);
+    if (lo >= 0 && hi < n) {
+      set_range(row + lo, row + hi);
+      return;
+    }
     const int a = ((lo % n) + n) % n, b = ((hi % n) + n) % n;
     if (a <= b) {
       set_range(row + a, row + b);
@@ -70,7 +74,12 @@ struct Bits {
 };
 
 int floordiv(int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
-int wrap(int a, int n) { return ((a % n) + n) % n; }
+// periodic index (no division for indices within one period of [0, n))
+int wrap(int a, int n) {
+  if (a >= 0 && a < n) return a;
+  if (a >= -n && a < 2 * n) return a < 0 ? a + n : a - n;
+  return ((a % n) + n) % n;
+}
 
 struct Pt {
   int c[3];
@@ -204,6 +213,9 @@ bool cluster_level(int M, const std::vector<IBox>& level_boxes, bool full_level,
   // few MB would be page-faulted in on every regrid)
   thread_local Bits tagged, cov;
   tagged.init(nb);
+  // neighbouring tags (the list comes in row order) mostly need the same blocks: a tag
+  // whose block ranges equal the previous tag's marks nothing new
+  int plo[3] = {1, 1, 1}, phi[3] = {0, 0, 0};
   for (long long t = 0; t < ntag; ++t) {
     int c[3], lo[3], hi[3];
     for (int d = 0; d < 3; ++d) {
@@ -218,6 +230,13 @@ bool cluster_level(int M, const std::vector<IBox>& level_boxes, bool full_level,
         lo[d] = 0;
         hi[d] = nb - 1;
       }
+    }
+    if (lo[0] == plo[0] && lo[1] == plo[1] && lo[2] == plo[2] && hi[0] == phi[0] && hi[1] == phi[1] &&
+        hi[2] == phi[2])
+      continue;
+    for (int d = 0; d < 3; ++d) {
+      plo[d] = lo[d];
+      phi[d] = hi[d];
     }
     for (int z = lo[2]; z <= hi[2]; ++z)
       for (int y = lo[1]; y <= hi[1]; ++y) tagged.set_x(lo[0], hi[0], wrap(y, nb), wrap(z, nb));
