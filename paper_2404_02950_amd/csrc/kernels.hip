@@ -146,40 +146,40 @@ __global__ __launch_bounds__(SH_BLOCK) void k_ghost_interp(const InterpSeg* __re
           }
     }
     if (IT == 4 && has_p) {
-      double hz[2][2][5];  // [x child][y child][z row]
+      // one x child at a time (the 25 x-rows are read from LDS twice), which halves the
+      // registers the separable passes hold; each child's operations are unchanged
 #pragma unroll
-      for (int dz = 0; dz < 5; ++dz) {
-        double g[2][5];  // [x child][y row]
+      for (int xc = 0; xc < 2; ++xc) {
+        const double a1 = xc ? hi1 : lo1, a2 = xc ? hi2 : lo2;
+        double hz[2][5];  // [y child][z row]
 #pragma unroll
-        for (int dy = 0; dy < 5; ++dy) {
-          const double* r = &sm[((pk + dz) * sy + (pj + dy)) * sx + pi];
-          const double d1 = r[3] - r[1], d2 = r[4] - r[0];
-          g[0][dy] = r[2] + (d1 * lo1 + d2 * lo2);
-          g[1][dy] = r[2] + (d1 * hi1 + d2 * hi2);
+        for (int dz = 0; dz < 5; ++dz) {
+          double g[5];  // [y row]
+#pragma unroll
+          for (int dy = 0; dy < 5; ++dy) {
+            const double* r = &sm[((pk + dz) * sy + (pj + dy)) * sx + pi];
+            const double d1 = r[3] - r[1], d2 = r[4] - r[0];
+            g[dy] = r[2] + (d1 * a1 + d2 * a2);
+          }
+          const double d1 = g[3] - g[1], d2 = g[4] - g[0];
+          hz[0][dz] = g[2] + (d1 * lo1 + d2 * lo2);
+          hz[1][dz] = g[2] + (d1 * hi1 + d2 * hi2);
         }
 #pragma unroll
-        for (int xc = 0; xc < 2; ++xc) {
-          const double d1 = g[xc][3] - g[xc][1], d2 = g[xc][4] - g[xc][0];
-          hz[xc][0][dz] = g[xc][2] + (d1 * lo1 + d2 * lo2);
-          hz[xc][1][dz] = g[xc][2] + (d1 * hi1 + d2 * hi2);
-        }
-      }
+        for (int zc = 0; zc < 2; ++zc)
 #pragma unroll
-      for (int zc = 0; zc < 2; ++zc)
-#pragma unroll
-        for (int yc = 0; yc < 2; ++yc)
-#pragma unroll
-          for (int xc = 0; xc < 2; ++xc) {
+          for (int yc = 0; yc < 2; ++yc) {
             const int fx = 2 * (t0[0] + pi) + xc, fy = 2 * (t0[1] + pj) + yc, fz = 2 * (t0[2] + pk) + zc;
             if (fx < s.fg0[0] || fx >= s.fg0[0] + s.n[0] || fy < s.fg0[1] || fy >= s.fg0[1] + s.n[1] ||
                 fz < s.fg0[2] || fz >= s.fg0[2] + s.n[2])
               continue;
-            const double* h = hz[xc][yc];
+            const double* h = hz[yc];
             const double d1 = h[3] - h[1], d2 = h[4] - h[0];
             const double val = h[2] + (zc ? (d1 * hi1 + d2 * hi2) : (d1 * lo1 + d2 * lo2));
             const long long ed = elem<T>(F, s.flo[0] + fx - s.fg0[0], s.flo[1] + fy - s.fg0[1], s.flo[2] + fz - s.fg0[2]);
             dst[comp * F.cs + ed] = (T)val;
           }
+      }
     }
     __syncthreads();
   }
