@@ -332,22 +332,22 @@ __global__ __launch_bounds__(SH_WAVE * ROWS) void k_stage_lds(const Tile* __rest
     }
     lds_barrier();
     // per-radius neighbour sums of every stencilled component (Laplacian: psi, radii
-    // 1..H; dissipation: every component, radii 1..KD)
-    T Ssum[NC][HR];
+    // 1..H; dissipation: every component, radii 1..KD), used up one component at a time
+    T lapc[2], ko4[4];
 #pragma unroll
-    for (int c = 0; c < NC; ++c)
+    for (int c = 0; c < NC; ++c) {
+      T Ssum[HR];
 #pragma unroll
       for (int r = 1; r <= HR; ++r) {
         const T xm = sm[buf][c][w + HR][lane + HR - r], xp = sm[buf][c][w + HR][lane + HR + r];
         const T ym = sm[buf][c][w + HR - r][lane + HR], yp = sm[buf][c][w + HR + r][lane + HR];
-        Ssum[c][r - 1] = ((xm + xp) + (ym + yp)) + (win[c][HR - r] + win[c][HR + r]);
+        Ssum[r - 1] = ((xm + xp) + (ym + yp)) + (win[c][HR - r] + win[c][HR + r]);
       }
-    const T lap0 = lap_combine<T, H>(Ssum[0], win[0][HR], idx2);
-    const T lap1 = lap_combine<T, H>(Ssum[1], win[1][HR], idx2);
+      if (c < 2) lapc[c] = lap_combine<T, H>(Ssum, win[c][HR], idx2);
+      if constexpr (KD > 0) ko4[c] = kc * ko_sum<T, KD>(Ssum, win[c][HR]);
+    }
+    const T lap0 = lapc[0], lap1 = lapc[1];
     if constexpr (KD > 0) {
-      T ko4[4];
-#pragma unroll
-      for (int c = 0; c < 4; ++c) ko4[c] = kc * ko_sum<T, KD>(Ssum[c], win[c][HR]);
       if (active)
         stage_cell<T, S, NT, true>(sc, Un, Y, P.acc, cs, e, win[0][HR], win[1][HR], q0, q1, lap0, lap1, un4, acc4,
                                    ko4);
