@@ -19,7 +19,12 @@ namespace {
 struct BlockBits {
   int nb = 0;
   std::vector<uint64_t> w;
-  explicit BlockBits(int nb_) : nb(nb_), w(((size_t)nb_ * nb_ * nb_ + 63) / 64, 0) {}
+  // cleared to nb^3 blocks (the storage is kept: a few MB freshly allocated on every
+  // regrid would be page-faulted in each time)
+  void reset(int nb_) {
+    nb = nb_;
+    w.assign(((size_t)nb_ * nb_ * nb_ + 63) / 64, 0);
+  }
   static int wrap(int a, int n) { return ((a % n) + n) % n; }
   void set(int x, int y, int z) {
     const size_t k = ((size_t)z * nb + y) * nb + x;
@@ -161,7 +166,9 @@ bool local_tag_boxes(int M_fine, const std::vector<IBox>& fine_boxes, int bf, in
   out.clear();
   if (!check_grid(M_fine, bf, err)) return false;
   const int nb = M_fine / bf, Mc = M_fine / 2;
-  BlockBits have(nb), need(nb);
+  thread_local BlockBits have, need;
+  have.reset(nb);
+  need.reset(nb);
   if (!occupy(have, fine_boxes, bf, M_fine, err)) return false;
   for (long long t = 0; t < ntag; ++t) {
     int lo[3], hi[3];
@@ -186,7 +193,9 @@ bool local_nest_boxes(int M_k, const std::vector<IBox>& added_fine, const std::v
   out.clear();
   if (!check_grid(M_k, bf, err)) return false;
   const int nb = M_k / bf, h = bf / 2;
-  BlockBits have(nb), need(nb);
+  thread_local BlockBits have, need;
+  have.reset(nb);
+  need.reset(nb);
   if (!occupy(have, level_boxes, bf, M_k, err)) return false;
   for (const IBox& b : added_fine) {
     int lo[3], hi[3];

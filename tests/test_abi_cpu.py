@@ -93,6 +93,26 @@ def test_clustering_gives_proper_layouts(shamr, seed, nbuf, bf, max_box):
     assert len(boxes2) > 0 or coarsen_mask(lev1).sum() < 64
 
 
+def test_clustering_nested_on_word_rows(shamr):
+    # a refined tagged level whose block rows are whole 64-bit words (256 cells, blocks of
+    # 4): the nesting test runs 64 blocks at a time there; the next level must stay
+    # properly nested, also when called again after clusterings of other sizes
+    n0, bf, max_box, nbuf = 128, 8, 32, 2
+    U = string_loop_state(n0, float(n0), seed=4, nloops=3, rmin=8.0, rmax=14.0, taper_in=3.0, taper_out=12.0)
+    tags = tag_cells(U[0], U[1])
+    boxes = shamr.cluster_boxes(n0, [], np.argwhere(tags)[:, ::-1], bf, max_box, nbuf, 0.7)
+    M1 = 2 * n0
+    lev1 = boxes_mask(boxes, M1)
+    t1 = np.zeros((M1,) * 3, np.uint8)
+    t1[lev1] = 1
+    idx1 = np.argwhere(t1)[:, ::-1]
+    boxes2 = shamr.cluster_boxes(M1, boxes, idx1, bf, max_box, nbuf, 0.7)
+    assert boxes2
+    assert check_layout(boxes2, 2 * M1, lev1, bf, max_box) == []
+    shamr.cluster_boxes(32, [], [(3, 3, 3)], bf, max_box, nbuf, 0.7)
+    assert shamr.cluster_boxes(M1, boxes, idx1, bf, max_box, nbuf, 0.7) == boxes2
+
+
 def test_clustering_efficiency_and_empty(shamr):
     assert shamr.cluster_boxes(32, [], np.zeros((0, 3), np.int32)) == []
     # two far-apart tags must not be merged into one big box at efficiency 0.7
