@@ -597,7 +597,9 @@ static void build_a1(const Level& L, int depth, std::vector<CopySeg>& segs, std:
   // x-padding before x = 0 and after the shell, which nothing reads) turns the partial
   // sector reads and writes of these runs into whole ones; the extra cells copy valid
   // cells.  Needs nx a multiple of the sector's element count and that much row padding.
-  if (L.boxes.size() == 1) {
+  // Done for float64 only: in float32 a sector holds 16 cells and the wider runs measured
+  // slower.
+  if (L.boxes.size() == 1 && L.g.esize == 8) {
     const int xo = L.g.xoff, nx = L.boxes[0].size(0);
     if (L.boxes[0].size(0) == L.M && nx % xo == 0 && nx >= xo && L.g.px[0] >= 2 * xo + nx && depth <= xo) {
       for (size_t i = 0; i < segs.size(); ++i) {
