@@ -124,8 +124,8 @@ def main():
                          "replays (per-kernel timing and the roofline are then not collected)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU path is a design, "
-              "not part of this build", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); sharding a level over several GPUs "
+              "is described but not implemented", file=sys.stderr)
         sys.exit(2)
 
     import torch
