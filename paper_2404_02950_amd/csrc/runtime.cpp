@@ -39,6 +39,19 @@ static sh_status fail(sh_status s, const std::string& msg) {
 // ---------------------------------------------------------------------------------
 // Device arrays for index tables (allocated at layout time only).
 // ---------------------------------------------------------------------------------
+// During a layout change the table uploads are staged in a pinned host buffer of the
+// hierarchy and queued on its stream instead of one synchronous copy each (a layout change
+// uploads a score of tables); the change synchronises the stream before the buffer is
+// used again.  Outside a layout change (no stage set on this thread) uploads are
+// synchronous.
+struct UploadStage {
+  hipStream_t st = nullptr;
+  char* buf = nullptr;  // pinned (hipHostMalloc)
+  size_t cap = 0, used = 0, want = 0;
+  bool queued = false;
+};
+thread_local UploadStage* g_stage = nullptr;
+
 template <typename T>
 struct DevArr {
   T* p = nullptr;
@@ -47,9 +60,21 @@ struct DevArr {
     release();
     n = v.size();
     if (n == 0) return hipSuccess;
-    hipError_t e = hipMalloc((void**)&p, n * sizeof(T));
+    const size_t bytes = n * sizeof(T);
+    hipError_t e = hipMalloc((void**)&p, bytes);
     if (e != hipSuccess) { p = nullptr; n = 0; return e; }
-    return hipMemcpy(p, v.data(), n * sizeof(T), hipMemcpyHostToDevice);
+    UploadStage* sg = g_stage;
+    if (sg) {
+      sg->want += (bytes + 255) / 256 * 256;
+      if (sg->buf && sg->used + bytes <= sg->cap) {
+        char* h = sg->buf + sg->used;
+        std::memcpy(h, v.data(), bytes);
+        sg->used += (bytes + 255) / 256 * 256;
+        sg->queued = true;
+        return hipMemcpyAsync(p, h, bytes, hipMemcpyHostToDevice, sg->st);
+      }
+    }
+    return hipMemcpy(p, v.data(), bytes, hipMemcpyHostToDevice);
   }
   void release() {
     if (p) (void)hipFree(p);
@@ -457,6 +482,7 @@ struct sh_hierarchy_s {
   SegPlan<AvgSeg> shadow_a5;
   long long layout_version = 0;  // bumped by every layout change (captured graphs go stale)
   LevelScal* d_ls = nullptr;  // 16 levels, then the shadow level
+  UploadStage stage;          // pinned staging of the table uploads of a layout change
   double* d_dbg = nullptr;
   std::vector<Level> lev;
   bool tracing = false;
@@ -912,9 +938,39 @@ sh_status sh_hierarchy_destroy(sh_hierarchy h) {
   for (Level& L : h->lev) L.release();
   if (h->d_ls) (void)hipFree(h->d_ls);
   if (h->d_dbg) (void)hipFree(h->d_dbg);
+  if (h->stage.buf) (void)hipHostFree(h->stage.buf);
   delete h;
   return SH_OK;
 }
+
+// Scope of one layout change: uploads go through the hierarchy's staging buffer; at the
+// end (every return path) the stream is synchronised if anything was queued, and the
+// buffer grows to what the change asked for, for the next one.
+struct StageScope {
+  sh_hierarchy h;
+  explicit StageScope(sh_hierarchy h_) : h(h_) {
+    h->stage.st = h->st;
+    h->stage.used = 0;
+    h->stage.want = 0;
+    h->stage.queued = false;
+    g_stage = &h->stage;
+  }
+  ~StageScope() {
+    g_stage = nullptr;
+    UploadStage& sg = h->stage;
+    if (sg.queued) (void)hipStreamSynchronize(h->st);
+    sg.queued = false;
+    sg.used = 0;
+    if (sg.want > sg.cap) {
+      if (sg.buf) (void)hipHostFree(sg.buf);
+      sg.buf = nullptr;
+      sg.cap = 0;
+      const size_t cap = std::max(sg.want + sg.want / 2, (size_t)(1 << 20));
+      if (hipHostMalloc((void**)&sg.buf, cap, hipHostMallocDefault) == hipSuccess) sg.cap = cap;
+      else sg.buf = nullptr;
+    }
+  }
+};
 
 int32_t sh_num_levels(sh_hierarchy h) { return h ? (int32_t)h->lev.size() : 0; }
 
@@ -965,6 +1021,7 @@ sh_status sh_set_level_layout(sh_hierarchy h, int32_t l, int32_t nboxes, const i
                               size_t arena_bytes) {
   if (!h) return fail(SH_EINVAL, "null handle");
   if (h->capturing) return not_capturing(h);
+  StageScope staged(h);
   h->layout_version += 1;
   const sh_params& p = h->p;
   if (l < 0 || l > p.max_level || l > (int)h->lev.size()) return fail(SH_EINVAL, "bad level");
