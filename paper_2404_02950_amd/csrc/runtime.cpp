@@ -945,7 +945,8 @@ sh_status sh_hierarchy_destroy(sh_hierarchy h) {
 
 // Scope of one layout change: uploads go through the hierarchy's staging buffer; at the
 // end (every return path) the stream is synchronised if anything was queued, and the
-// buffer grows to what the change asked for, for the next one.
+// buffer grows to what the change asked for, for the next one.  A hierarchy whose layout
+// is set once (an ensemble job) never allocates it.
 struct StageScope {
   sh_hierarchy h;
   explicit StageScope(sh_hierarchy h_) : h(h_) {
@@ -961,7 +962,7 @@ struct StageScope {
     if (sg.queued) (void)hipStreamSynchronize(h->st);
     sg.queued = false;
     sg.used = 0;
-    if (sg.want > sg.cap) {
+    if (sg.want > sg.cap && h->layout_version >= 2) {
       if (sg.buf) (void)hipHostFree(sg.buf);
       sg.buf = nullptr;
       sg.cap = 0;
