@@ -52,6 +52,16 @@ Paper passages followed:
   exceeds a threshold (te_crit, one for all components), alone or together with the
   plaquette criterion.  On a regrid the estimate of kept cells is kept and new cells
   start at 0.
+* Per-field estimates and their modifier (section IV.C, "Modifying truncation error
+  estimates"): with tee_fields on, each component c keeps its own estimate
+  Delta_c(X) = |C_c(X) - avg(children)_c| and a cell is tagged by estimate when
+  f_c(Delta_c) > eps_c for some component, with its own threshold eps_c (te_crit_phi)
+  and f_c(Delta) = s_c * Delta.  The paper's modifier is a user function with user
+  parameters; the one built here is the scaling it uses in appendix D (Delta_phi / max phi
+  and Delta_phi' / max phi'), with s_c given by the caller.  ``field_absmax`` gives the
+  maxima for that normalisation, read as max |U_c| over the valid cells of every level
+  (the whole simulation); ``normalising_scales`` turns them into s_c = 1 / max, leaving a
+  component whose maximum is 0 unscaled (s_c = 1).
 
 Interpolation and averaging are done in float64 from promoted values and rounded to
 the storage precision on store.
@@ -201,6 +211,22 @@ def tee_coarse(C: np.ndarray, F: np.ndarray) -> np.ndarray:
     return t
 
 
+def tee_coarse_fields(C: np.ndarray, F: np.ndarray) -> np.ndarray:
+    """Per-component TEE at the coarse resolution: (4, M, M, M) array of
+    |C_c - avg(F_c children)| (float64)."""
+    out = np.empty((4,) + C.shape[1:])
+    for c in range(4):
+        with np.errstate(all="ignore"):
+            out[c] = np.abs(C[c].astype(np.float64) - average_down_arrays(F[c]))
+    return out
+
+
+def normalising_scales(absmax) -> np.ndarray:
+    """s_c = 1 / max |U_c| (appendix D's normalisation); 1 where the maximum is 0."""
+    m = np.asarray(absmax, dtype=np.float64)
+    return np.where(m > 0.0, 1.0 / np.where(m > 0.0, m, 1.0), 1.0)
+
+
 def refine_values(T: np.ndarray) -> np.ndarray:
     """Each coarse value onto its 2^3 children."""
     return np.repeat(np.repeat(np.repeat(T, 2, axis=0), 2, axis=1), 2, axis=2)
@@ -270,6 +296,10 @@ class Hierarchy:
         self.trace: list[tuple] = []
         self.tee_on = False
         self.te_crit = 0.0
+        # per-field estimates: thresholds eps_c and modifier scales s_c
+        self.tee_fields = False
+        self.te_crit_c = np.zeros(4)
+        self.te_scale = np.ones(4)
         self.tag_mode = 1  # bit 0: plaquette winding, bit 1: truncation error estimate
         self.shadow: Level | None = None
 
@@ -284,7 +314,9 @@ class Hierarchy:
 
     def _new_level(self, lev: int) -> Level:
         M = self.n0 << lev
-        return Level(M, level_dx(self.L, self.n0, lev), level_dt(self.L, self.n0, self.cfl, lev))
+        L = Level(M, level_dx(self.L, self.n0, lev), level_dt(self.L, self.n0, self.cfl, lev))
+        L.tee = self._tee_zeros(M)
+        return L
 
     # ---- layout ------------------------------------------------------------------
     def set_level0(self, U0: np.ndarray, boxes=None):
@@ -326,8 +358,8 @@ class Hierarchy:
         keep = new_valid & old_valid
         if oldU is not None:
             U[:, keep] = oldU[:, keep]
-        tee = np.zeros((L.M,) * 3)
-        tee[keep] = L.tee[keep]
+        tee = self._tee_zeros(L.M)
+        tee[..., keep] = L.tee[..., keep] if L.tee.shape == tee.shape else 0.0
         L.tee = tee
         fresh = new_valid & ~old_valid
         fz, fy, fx = np.nonzero(fresh)
@@ -400,8 +432,12 @@ class Hierarchy:
         F, C = self.levels[fine], self.levels[fine - 1]
         cov = coarsen_mask(F.valid)
         if self.tee_on:
-            T = tee_coarse(C.U, F.U)
-            F.tee = np.where(F.valid, refine_values(T), 0.0)
+            if self.tee_fields:
+                T = tee_coarse_fields(C.U, F.U)
+                F.tee = np.stack([np.where(F.valid, refine_values(T[c]), 0.0) for c in range(4)])
+            else:
+                T = tee_coarse(C.U, F.U)
+                F.tee = np.where(F.valid, refine_values(T), 0.0)
         for c in range(4):
             with np.errstate(all="ignore"):
                 avg = average_down_arrays(F.U[c])
@@ -410,6 +446,37 @@ class Hierarchy:
     # ---- diagnostics -------------------------------------------------------------
     def set_tee(self, enable: bool, te_crit: float = 0.0, tag_mode: int = 1):
         self.tee_on, self.te_crit, self.tag_mode = bool(enable), float(te_crit), int(tag_mode)
+        self._reset_tee(False)
+
+    def set_tee_fields(self, enable: bool, te_crit, scale=(1.0, 1.0, 1.0, 1.0), tag_mode: int = 3):
+        """Per-field estimates: tag where scale_c * Delta_c > te_crit_c for some c."""
+        self.tee_on, self.tag_mode = bool(enable), int(tag_mode)
+        self.te_crit_c = np.asarray(te_crit, dtype=np.float64).reshape(4).copy()
+        self.te_scale = np.asarray(scale, dtype=np.float64).reshape(4).copy()
+        self._reset_tee(True)
+
+    def set_tee_scale(self, scale):
+        """New modifier scales; the estimates already formed are kept."""
+        self.te_scale = np.asarray(scale, dtype=np.float64).reshape(4).copy()
+
+    def _tee_zeros(self, M: int) -> np.ndarray:
+        return np.zeros((4, M, M, M) if self.tee_fields else (M, M, M))
+
+    def _reset_tee(self, fields: bool):
+        """Switching between one estimate per cell and one per component starts the
+        estimates again from 0."""
+        if fields != self.tee_fields:
+            self.tee_fields = fields
+            for L in self.levels:
+                L.tee = self._tee_zeros(L.M)
+
+    def field_absmax(self) -> np.ndarray:
+        """max |U_c| over the valid cells of every level, per component (float64)."""
+        out = np.zeros(4)
+        for L in self.levels:
+            for c in range(4):
+                out[c] = max(out[c], float(np.max(np.abs(L.U[c][L.valid].astype(np.float64)))))
+        return out
 
     def tags(self, lev: int) -> np.ndarray:
         L = self.levels[lev]
@@ -417,7 +484,11 @@ class Hierarchy:
         if self.tag_mode & 1:
             t |= tag_cells(L.U[0], L.U[1]).astype(bool)
         if self.tag_mode & 2:
-            t |= L.tee > self.te_crit
+            if self.tee_fields:
+                for c in range(4):
+                    t |= (self.te_scale[c] * L.tee[c]) > self.te_crit_c[c]
+            else:
+                t |= L.tee > self.te_crit
         return (t & L.valid).astype(np.uint8)
 
     # ---- shadow level (truncation error estimate of level 0) --------------------
@@ -455,7 +526,11 @@ class Hierarchy:
         S, L0 = self.shadow, self.levels[0]
         if S.k != S.k_start + 1 or L0.k != 2 * S.k:
             raise ValueError("level 0 and the shadow are not at the same time after one shadow step")
-        L0.tee = refine_values(tee_coarse(S.U, L0.U))
+        if self.tee_fields:
+            T = tee_coarse_fields(S.U, L0.U)
+            L0.tee = np.stack([refine_values(T[c]) for c in range(4)])
+        else:
+            L0.tee = refine_values(tee_coarse(S.U, L0.U))
         self.shadow = None
 
     def covered(self, lev: int) -> np.ndarray:

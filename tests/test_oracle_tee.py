@@ -4,7 +4,7 @@ regrid rule for kept cells."""
 import numpy as np
 import pytest
 
-from oracle.amr import Hierarchy, average_down_arrays, boxes_mask
+from oracle.amr import Hierarchy, average_down_arrays, boxes_mask, normalising_scales, refine_values
 from oracle.tagging import tag_cells
 from synth import random_state
 
@@ -144,3 +144,149 @@ def test_tag_modes_and_regrid_rule():
     kept = nv & boxes_mask(old, 16)
     assert np.array_equal(h.levels[1].tee[kept], before[kept])
     assert np.all(h.levels[1].tee[nv & ~kept] == 0)
+
+
+# ---- per-field estimates and the modifier of section IV.C ------------------------------
+
+def _plane_wave_two_levels(amp=0.7, kk=(2.0, 1.0, 1.0)):
+    n0, L = 16, 16.0
+    k = 2 * np.pi / L * np.array(kk)
+    zero = np.zeros((n0,) * 3)
+    h = Hierarchy(n0, L, 0.25, 0.1, 1, alpha=0.0, lam=0.0, beta=0)
+    h.set_level0(np.stack([_centred_cos(n0, L, k, amp), zero, zero, zero]))
+    h.set_layout(1, _full_cover_boxes(2 * n0))
+    h.levels[1].U[:] = 0.0
+    h.levels[1].U[0] = _centred_cos(2 * n0, L, k, amp)
+    return h, k, n0, L
+
+
+def test_per_field_plane_wave_estimates_and_maxima_closed_form():
+    amp = 0.7
+    h, k, n0, L = _plane_wave_two_levels(amp)
+    dx0, dt0 = L / n0, 0.25
+    h.set_tee_fields(True, te_crit=[1.0] * 4)
+    h.coarse_step()
+    Mc = _step_matrix(_omega2(k, dx0), dt0)
+    Mf = np.linalg.matrix_power(_step_matrix(_omega2(k, dx0 / 2), dt0 / 2), 2)
+    P = np.prod(np.cos(k * dx0 / 4))
+    cosc = np.abs(_centred_cos(n0, L, k, 1.0))
+    tee = h.levels[1].tee
+    assert tee.shape == (4, 2 * n0, 2 * n0, 2 * n0)
+    # psi1 and Pi1 carry the standing wave; psi2 and Pi2 stay 0
+    for c, row in ((0, 0), (2, 1)):
+        ref = abs(Mc[row, 0] - P * Mf[row, 0]) * amp * cosc
+        got = average_down_arrays(tee[c])
+        assert np.max(ref) > 1e-6
+        assert np.max(np.abs(got - ref)) < 1e-12
+    assert not tee[1].any() and not tee[3].any()
+    # the max-over-components estimate of the same run is their pointwise maximum
+    assert np.array_equal(np.maximum(tee[0], tee[2]), np.max(tee, axis=0))
+    # maxima over both levels: the fine level holds the wave after two fine steps, level 0
+    # its 2^3 means
+    fine_cos = np.max(np.abs(_centred_cos(2 * n0, L, k, 1.0)))
+    want = [max(abs(Mf[r, 0]) * fine_cos, abs(P * Mf[r, 0]) * np.max(cosc)) * amp for r in (0, 1)]
+    m = h.field_absmax()
+    assert abs(m[0] - want[0]) < 1e-12 and abs(m[2] - want[1]) < 1e-12
+    assert m[1] == 0.0 and m[3] == 0.0
+    s = normalising_scales(m)
+    assert s[1] == 1.0 and s[3] == 1.0 and abs(s[0] * want[0] - 1.0) < 1e-12
+
+
+def _nudge(vals, frac):
+    """A threshold near frac * max(vals) that no value lies within 1e-9 (relative) of."""
+    top = float(np.max(vals))
+    eps = frac * top
+    while np.min(np.abs(vals - eps)) < 1e-9 * top:
+        eps *= 1.0 + 1e-6
+    return eps
+
+
+@pytest.mark.parametrize("which", [0, 2])
+def test_per_field_thresholds_tag_each_component_on_its_own(which):
+    amp = 0.7
+    h, k, n0, L = _plane_wave_two_levels(amp)
+    dx0, dt0 = L / n0, 0.25
+    h.set_tee_fields(True, te_crit=[1e30] * 4)
+    h.coarse_step()
+    s = normalising_scales(h.field_absmax())
+    h.set_tee_scale(s)
+    Mc = _step_matrix(_omega2(k, dx0), dt0)
+    Mf = np.linalg.matrix_power(_step_matrix(_omega2(k, dx0 / 2), dt0 / 2), 2)
+    P = np.prod(np.cos(k * dx0 / 4))
+    row = 0 if which == 0 else 1
+    ref = refine_values(abs(Mc[row, 0] - P * Mf[row, 0]) * amp * np.abs(_centred_cos(n0, L, k, 1.0)))
+    f = s[which] * ref                                  # f_c(Delta_c) from the closed form
+    crit = [1e30] * 4
+    crit[which] = _nudge(f, 0.6)
+    h.te_crit_c = np.array(crit)
+    want = f > crit[which]
+    assert 0 < want.sum() < want.size
+    assert np.array_equal(h.tags(1).astype(bool), want)
+    # modifier scales matter: unscaled, the same threshold tags a different set
+    h.set_tee_scale(np.ones(4))
+    assert not np.array_equal(h.tags(1).astype(bool), want)
+
+
+def test_per_field_with_one_threshold_and_unit_scales_equals_the_max_estimate():
+    n0 = 8
+    U = random_state(n0, float(n0), 6)
+    runs = []
+    for fields in (False, True):
+        h = Hierarchy(n0, float(n0), 0.25, 0.1, 1, beta=0)
+        h.set_level0(U)
+        h.set_layout(1, [(0, 0, 0, 7, 7, 7), (8, 0, 0, 15, 7, 7), (0, 8, 8, 7, 15, 15)])
+        if fields:
+            h.set_tee_fields(True, te_crit=[2e-5] * 4, tag_mode=2)
+        else:
+            h.set_tee(True, te_crit=2e-5, tag_mode=2)
+        h.coarse_step()
+        runs.append(h)
+    a, b = runs
+    assert np.array_equal(np.max(b.levels[1].tee, axis=0), a.levels[1].tee)
+    crit = _nudge(a.levels[1].tee[a.levels[1].valid], 0.5)
+    a.te_crit = crit
+    b.te_crit_c = np.full(4, crit)
+    ta, tb = a.tags(1), b.tags(1)
+    assert 0 < ta.sum() < a.levels[1].valid.sum()
+    assert np.array_equal(ta, tb)
+
+
+def test_per_field_regrid_keeps_every_component_of_kept_cells():
+    n0 = 8
+    h = Hierarchy(n0, float(n0), 0.25, 0.1, 1, beta=0)
+    h.set_level0(random_state(n0, float(n0), 7))
+    old = [(0, 0, 0, 7, 7, 7), (8, 0, 0, 15, 7, 7)]
+    h.set_layout(1, old)
+    h.set_tee_fields(True, te_crit=[1e-4] * 4)
+    h.coarse_step()
+    before = h.levels[1].tee.copy()
+    assert before.shape[0] == 4 and np.all(before[:, ~h.levels[1].valid] == 0)
+    new = [(4, 0, 0, 11, 7, 7)]
+    h.set_layout(1, new)
+    nv = boxes_mask(new, 16)
+    kept = nv & boxes_mask(old, 16)
+    assert np.array_equal(h.levels[1].tee[:, kept], before[:, kept])
+    assert np.all(h.levels[1].tee[:, nv & ~kept] == 0)
+
+
+def test_per_field_shadow_level_closed_form():
+    n0, L, amp = 16, 16.0, 0.4
+    k = 2 * np.pi / L * np.array([1.0, 2.0, 0.0])
+    dx0, dt0 = L / n0, 0.25
+    zero = np.zeros((n0,) * 3)
+    h = Hierarchy(n0, L, 0.25, 0.1, 0, alpha=0.0, lam=0.0, beta=0)
+    h.set_level0(np.stack([zero, _centred_cos(n0, L, k, amp), zero, zero]))
+    h.set_tee_fields(True, te_crit=[1.0] * 4)
+    h.shadow_begin()
+    h.shadow_advance()
+    h.coarse_step()
+    h.coarse_step()
+    h.shadow_end()
+    Ms = _step_matrix(_omega2(k, 2 * dx0), 2 * dt0)
+    M0 = np.linalg.matrix_power(_step_matrix(_omega2(k, dx0), dt0), 2)
+    P = np.prod(np.cos(k * dx0 / 2))
+    tee = h.levels[0].tee
+    for c, row in ((1, 0), (3, 1)):
+        ref = P * abs(Ms[row, 0] - M0[row, 0]) * np.abs(_centred_cos(n0 // 2, L, k, 1.0)) * amp
+        assert np.max(np.abs(tee[c][::2, ::2, ::2] - ref)) < 1e-12
+    assert not tee[0].any() and not tee[2].any()
