@@ -53,39 +53,182 @@ def traffic_from_profiles(prec: str, n: int, kname: str):
     return rec.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(U0, n: int, integrator: int = 4, order: int = 1, ko_order: int = 0, ko_eps: float = 0.0):
-    """One full step of the oracle on the whole lattice, timed on this host (numpy, one
-    core; about 20 s at 512^3 for RK4)."""
-    from oracle.level import ko_coef, rk4_step, ssprk3_step
-    nst, step, name = (4, rk4_step, "RK4") if integrator == 4 else (3, ssprk3_step, "SSPRK3")
-    ko = (ko_order, ko_coef(ko_order, ko_eps, 1.0)) if ko_order else None
+# the whole lattice the slab workers step: set before the pool forks, read by the workers
+_SLAB_STATE = {}
+
+
+def _slab_step(task):
+    """One oracle step of z-planes [z0, z1) of the lattice in _SLAB_STATE: the slab is cut
+    out with `halo` planes on either side (periodically) and stepped by the oracle as a
+    periodic lattice of its own; the wrap corrupts at most `halo` planes at each end, so
+    the planes in between are the whole-lattice step's.  Returns (z0, interior or its
+    sum, seconds)."""
+    z0, z1, halo, kw, keep = task
+    import numpy as np
+    from oracle.level import rk4_step, ssprk3_step
+    U = _SLAB_STATE["U"]
+    n = U.shape[1]
     t0 = time.perf_counter()
-    step(U0, 0.1, 0.25, 1.0, 2.0, 1.0, 2, order=order, ko=ko)
+    X = U[:, np.arange(z0 - halo, z1 + halo) % n]
+    step = rk4_step if kw["integrator"] == 4 else ssprk3_step
+    Y = step(X, kw["eta"], kw["dt"], kw["inv_dx2"], kw["alpha"], kw["lam"], kw["beta"], order=kw["order"],
+             ko=kw["ko"])[:, halo:halo + (z1 - z0)]
     dt = time.perf_counter() - t0
-    return {"value": nst * n ** 3 / dt, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"one {name} step ({nst} stages) of the {n}^3 FP64 lattice, numpy oracle, "
-                      f"{dt:.1f} s on one host core"}
+    return z0, (Y.copy() if keep else float(Y.sum())), dt
 
 
-def copy_bandwidth(stream, nbytes: int = 2 ** 31, reps: int = 10) -> float:
-    """GB/s of a device-to-device copy of nbytes (read + write counted), events on stream."""
+def oracle_step_slabs(U, nslabs: int, workers: int, integrator: int = 4, order: int = 1, ko_order: int = 0,
+                      ko_eps: float = 0.0, keep: bool = False, first_only: bool = False):
+    """One oracle step (eta 0.1, dt 0.25, dx 1, alpha 2, lambda 1, beta 2) of the periodic
+    lattice U split into nslabs z-slabs run by `workers` forked processes (1: in this
+    process).  The oracle code is unchanged: each slab carries enough extra planes
+    (stages x stencil reach) that its own periodic wrap never reaches the planes it
+    keeps.  first_only runs the first slab alone.  Returns (seconds, the stepped state if
+    keep else the per-slab sums)."""
+    import numpy as np
+    from oracle.level import ko_coef
+    n = U.shape[1]
+    nst = 4 if integrator == 4 else 3
+    halo = nst * max(order, ko_order)
+    if n % nslabs:
+        raise ValueError("the lattice must split into whole slabs")
+    kw = {"integrator": integrator, "eta": 0.1, "dt": 0.25, "inv_dx2": 1.0, "alpha": 2.0, "lam": 1.0, "beta": 2,
+          "order": order, "ko": (ko_order, ko_coef(ko_order, ko_eps, 1.0)) if ko_order else None}
+    w = n // nslabs
+    tasks = [(i * w, (i + 1) * w, halo, kw, keep) for i in range(1 if first_only else nslabs)]
+    _SLAB_STATE["U"] = U
+    try:
+        if workers <= 1:
+            t0 = time.perf_counter()
+            res = [_slab_step(t) for t in tasks]
+            dt = time.perf_counter() - t0
+        else:
+            import multiprocessing as mp
+            with mp.get_context("fork").Pool(workers) as pool:
+                pool.map(len, [()] * workers)  # workers up before the clock starts
+                t0 = time.perf_counter()
+                res = pool.map(_slab_step, tasks, chunksize=1)
+                dt = time.perf_counter() - t0
+    finally:
+        _SLAB_STATE.clear()
+    res.sort(key=lambda r: r[0])
+    if keep:
+        return dt, np.concatenate([r[1] for r in res], axis=1)
+    return dt, [r[1] for r in res]
+
+
+def host_cpu():
+    """(cores this process may run on, capped at the 16 a one-GPU share holds; CPU model)."""
+    try:
+        ncpu = len(os.sched_getaffinity(0))
+    except AttributeError:
+        ncpu = os.cpu_count() or 1
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return ncpu, min(ncpu, 16), model
+
+
+def cpu_baseline(U0, n: int, integrator: int = 4, order: int = 1, ko_order: int = 0, ko_eps: float = 0.0):
+    """The oracle on this host's cores (run before the GPU is touched, so the forked
+    workers hold no device state): one full step of the n^3 lattice as z-slabs over all
+    usable cores, and the first of 8 such slabs alone on one core."""
+    nproc, workers, model = host_cpu()
+    nst, name = (4, "RK4") if integrator == 4 else (3, "SSPRK3")
+    nslabs = workers
+    while n % nslabs:
+        nslabs += 1
+    t_all, _ = oracle_step_slabs(U0, nslabs, workers, integrator, order, ko_order, ko_eps)
+    t_one, _ = oracle_step_slabs(U0, 8, 1, integrator, order, ko_order, ko_eps, first_only=True)
+    return {"value": nst * n ** 3 / t_all, "unit": "cell-updates/s", "cores": workers, "kind": "oracle",
+            "nproc": nproc, "cpu_model": model,
+            "value_1core": nst * (n // 8) * n * n / t_one,
+            "sample": f"one {name} step ({nst} stages) of the {n}^3 FP64 lattice: numpy oracle on {nslabs} z-slabs "
+                      f"in {workers} processes, {t_all:.1f} s wall; one core: one slab of {n // 8} planes, "
+                      f"{t_one:.1f} s"}
+
+
+def stream_bandwidth(stream, nbytes: int = 2 ** 32, reps: int = 10):
+    """GB/s of the library's streaming probes over nbytes buffers (well beyond the 256 MB
+    last-level cache), events on stream: {read, write, copy (read + write counted)}."""
     import torch
+    from paper_2404_02950_amd import shamr
+    out = {}
     with torch.cuda.stream(stream):
-        a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+        a = torch.zeros(nbytes // 8, dtype=torch.float64, device="cuda")
         b = torch.empty_like(a)
-        for _ in range(3):
-            b.copy_(a)
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        for _ in range(reps):
-            b.copy_(a)
-        e1.record(stream)
+        for kind, name, moved in ((1, "write", nbytes), (0, "read", nbytes), (2, "copy", 2 * nbytes)):
+            for _ in range(3):
+                shamr.stream_probe(kind, a, b, nbytes, stream)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(reps):
+                shamr.stream_probe(kind, a, b, nbytes, stream)
+            e1.record(stream)
+            e1.synchronize()
+            out[name] = moved * reps / (e0.elapsed_time(e1) / 1e3) / 1e9
     torch.cuda.synchronize()
-    bw = 2 * nbytes * reps / (e0.elapsed_time(e1) / 1e3) / 1e9
     del a, b
     torch.cuda.empty_cache()
-    return bw
+    return out
+
+
+DIVERGED_PSI = 10.0  # |psi| of the FP64 run beyond which the field counts as diverged
+
+
+def fp32_error_series(U0, n: int, steps: int, stream, args, beta: int = 2):
+    """FP32 storage against FP64 from the same initial state, after every step: the
+    largest |psi_32 - psi_64| and |Pi_32 - Pi_64| over all cells, with max |psi_64| for
+    scale.  The FP64 run is the library's FP64 path, which equals the FP64 oracle bit for
+    bit (the sampled full-size parity tests); values are compared on the device.  With
+    the paper's beta = 2 at dt = dx/4 the radial mode goes unstable within the run; the
+    divergence onset is the first step at which max |psi_64| exceeds DIVERGED_PSI (the
+    field is of order 1 before it) or turns non-finite."""
+    import math
+    import torch
+    from paper_2404_02950_amd import shamr
+    hs = {}
+    for prec in (shamr.SH_F64, shamr.SH_F32):
+        h = shamr.Hierarchy(n, float(n), 0.25, 0.1, 1.0, 2.0, beta, max_level=0, prec=prec, stream=stream,
+                            integrator=args.integrator, lap_order=args.lap_order, ko_order=args.ko_order,
+                            ko_eps=args.ko_eps)
+        h.set_layout(0, [(0, 0, 0, n - 1, n - 1, n - 1)])
+        h.write_dense(0, U0)
+        h.fill_ghosts(0)
+        hs[prec] = h
+    cells = n ** 3
+    e_psi, e_pi, m_psi, first_bad = [], [], [], None
+    log(f"FP32 vs FP64 error series over {steps} steps (beta {beta})")
+    for k in range(steps):
+        for h in hs.values():
+            h.advance(0)
+        with torch.cuda.stream(stream):
+            a = hs[shamr.SH_F32].read_device(0).view(4, cells)
+            b = hs[shamr.SH_F64].read_device(0).view(4, cells)
+            if first_bad is None and not bool(torch.isfinite(b).all()):
+                first_bad = k + 1
+            d = (a - b).abs_()
+            vals = torch.stack([d[:2].max(), d[2:].max(), b[:2].abs().max()]).cpu().tolist()
+        del a, b, d
+        for lst, v in zip((e_psi, e_pi, m_psi), vals):
+            lst.append(float(f"{v:.4g}") if math.isfinite(v) else None)
+    for h in hs.values():
+        h.close()
+    torch.cuda.empty_cache()
+    onset = next((k + 1 for k, m in enumerate(m_psi) if m is None or m > DIVERGED_PSI), None)
+    before = [k for k in range(steps) if onset is None or k + 1 < onset]
+    return {"reference": "FP64 run of the same lattice on the GPU (equal to the FP64 oracle bit for bit)",
+            "beta": beta, "steps": steps, "max_abs_err_psi": e_psi, "max_abs_err_pi": e_pi,
+            "max_abs_psi_fp64": m_psi, "first_nonfinite_step_fp64": first_bad,
+            "divergence_onset_step": onset, "divergence_rule": f"max |psi_64| > {DIVERGED_PSI} or non-finite",
+            "max_abs_err_psi_before_onset": max((e_psi[k] for k in before if e_psi[k] is not None), default=None),
+            "max_abs_err_pi_before_onset": max((e_pi[k] for k in before if e_pi[k] is not None), default=None)}
 
 
 def main():
@@ -97,6 +240,8 @@ def main():
     ap.add_argument("--prec", choices=("f64", "f32"), default="f64")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--error-steps", type=int, default=200,
+                    help="--prec f32: steps of the FP32-vs-FP64 error series (0: none)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 2 GiB device copy (calibrates rocprofv3 byte counters)")
     ap.add_argument("--workload", choices=("single", "amr256", "amr512", "serve"), default="single",
@@ -132,6 +277,16 @@ def main():
     from paper_2404_02950_amd import shamr
     from synth import random_state
 
+    n, K, W = args.n, args.steps, args.warmup
+    cpu = None
+    if args.workload == "single":
+        log(f"initial state {n}^3 (seed {args.seed})")
+        U0 = random_state(n, float(n), args.seed)
+        if not args.no_cpu_baseline and args.prec == "f64":
+            # before anything touches the GPU: the slab workers are forked from this process
+            log("cpu baseline (oracle over the host cores)")
+            cpu = cpu_baseline(U0, n, args.integrator, args.lap_order, args.ko_order, args.ko_eps)
+            log(f"cpu baseline {cpu['sample']}")
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
@@ -141,9 +296,6 @@ def main():
         from paper_2404_02950_amd.serve import bench_serving
         print(json.dumps(bench_serving(log=log)), flush=True)
         return
-    n, K, W = args.n, args.steps, args.warmup
-    log(f"initial state {n}^3 (seed {args.seed})")
-    U0 = random_state(n, float(n), args.seed)
     prec = shamr.SH_F64 if args.prec == "f64" else shamr.SH_F32
     stream = torch.cuda.Stream()
     h = shamr.Hierarchy(n, float(n), 0.25, 0.1, 1.0, 2.0, 2, max_level=0, prec=prec, stream=stream,
@@ -231,31 +383,35 @@ def main():
                    "integrator": args.integrator, "lap_order": args.lap_order, "ko_order": args.ko_order,
                    "graph_steps": G if graph is not None else None},
         "roofline": roofline,
-        # the same cell-update rate priced at the bytes a one-stage-per-pass kernel must
-        # move (mean over the stages), against the same peak
-        "per_stage_equivalent": {"bytes_per_cell_stage": sum(sb) / nst,
-                                 "achieved": value * sum(sb) / nst / 1e9, "peak": HBM_PEAK_GBS,
-                                 "frac": value * sum(sb) / nst / 1e9 / HBM_PEAK_GBS},
+        # a rate ratio, not a roofline: this cell-update rate over the most that a kernel
+        # running one RK stage per pass could reach at the HBM peak (it must move the
+        # mean per-stage bytes below for every cell-stage)
+        "vs_per_stage_peak_rate": {"bytes_per_cell_stage": sum(sb) / nst,
+                                   "per_stage_peak_rate": HBM_PEAK_GBS * 1e9 / (sum(sb) / nst),
+                                   "ratio": value / (HBM_PEAK_GBS * 1e9 / (sum(sb) / nst))},
         "cell_steps_per_s": value / nst,
         "kernel_ms": {k: (v[0] / v[1] if v[1] else None) for k, v in prof.items() if v[1]},
         "wall_ms_per_step": wall / K * 1e3,
         "nonfinite_cells_at_end": bad,
     }
-    if not args.no_cpu_baseline and args.prec == "f64":
-        log("cpu baseline (oracle, one full step)")
-        out["cpu_baseline"] = cpu_baseline(U0, n, args.integrator, args.lap_order, args.ko_order, args.ko_eps)
-    else:
-        out["cpu_baseline"] = None
+    out["cpu_baseline"] = cpu
     if graph is not None:
         graph.close()
     h.close()
     if out["roofline"] is not None:
-        # achievable HBM bandwidth on this machine: a plain device copy of 2 x 2 GiB, timed the
-        # same way (events on the same stream), beside the nominal peak
-        bw = copy_bandwidth(stream)
-        out["roofline"]["copy_GBs"] = bw
-        out["roofline"]["frac_of_copy"] = out["roofline"]["achieved"] / bw
-        log(f"device copy {bw:.0f} GB/s")
+        # achievable HBM bandwidth on this machine: the library's read, write and copy probes
+        # over 4 GiB buffers, timed the same way (events on the same stream), beside the
+        # nominal peak; the ceiling is the best of the three
+        bw = stream_bandwidth(stream)
+        ceil = max(bw.values())
+        out["roofline"]["stream_GBs"] = bw
+        out["roofline"]["ceiling_GBs"] = ceil
+        out["roofline"]["frac_of_ceiling"] = out["roofline"]["achieved"] / ceil
+        log("streaming probes " + ", ".join(f"{k} {v:.0f} GB/s" for k, v in bw.items()))
+    if args.prec == "f32" and args.error_steps > 0:
+        out["fp32_error_vs_fp64"] = fp32_error_series(U0, n, args.error_steps, stream, args)
+        # the stable companion: the same run with beta = 0 (no growing radial mode)
+        out["fp32_error_vs_fp64_beta0"] = fp32_error_series(U0, n, args.error_steps, stream, args, beta=0)
     if args.calib_copy:
         a = torch.empty(2 ** 28, dtype=torch.float64, device="cuda")
         b = torch.empty_like(a)

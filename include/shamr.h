@@ -101,13 +101,26 @@ typedef struct {
                            block-row stage kernel stages Pi through LDS as well, and the
                            fused step is not used */
   double ko_eps;        /* sim.dissipation_strength eps >= 0 */
+  int32_t tee_fields;   /* truncation error estimates kept per cell (Sec. IV.C): 0 = one,
+                           the maximum over the four components; 1 = one per component,
+                           so that each field can have its own threshold and modifier
+                           (sh_set_tee_fields); arenas then hold 32 instead of 8 bytes of
+                           estimates per valid cell */
 } sh_params;
 
-/* Device bytes needed for the arena of a level with the given boxes.  Returns 0 for
+/* Device bytes needed for the arena of a level with the given boxes (section II: a
+   level is a union of boxes; per box the four fields of eqs. EOM1/EOM2 in three state
+   buffers, a float64 accumulator for RK4, and the ghost shell the stencil needs).  The
+   caller allocates it; the library keeps no field storage of its own.  Returns 0 for
    invalid arguments. */
 size_t sh_arena_bytes(const sh_params* p, int32_t lev, int32_t nboxes, const int32_t* boxes);
 
-/* Create a hierarchy.  `hip_stream` is a hipStream_t (NULL = default stream) that all
+/* Create a hierarchy for the problem of section "Minimal example" (eqs. EOM1/EOM2 on
+   a periodic cube of n0^3 coarse cells of side L) with the simulation and AMR
+   parameters of appendix E (sim.L, sim.cfl, sim.t_start, amr.max_refinement_levels,
+   amr.blocking_factor, amr.n_error_buf, integrator.type, interpolation type) carried in
+   sh_params; the handle is host memory owned by the library until
+   sh_hierarchy_destroy.  `hip_stream` is a hipStream_t (NULL = default stream) that all
    device work of this hierarchy is queued on.  Errors: SH_EINVAL (n0 < 1, L or cfl not
    positive, beta < 0, max_level < 0 or > 15, blocking_factor < 2, prec not 0/1,
    integrator not 0, 3, 4 or 10, lap_order not 0..3, interp not 0, 1 or 4, ko_order not 0,
@@ -131,14 +144,18 @@ sh_status sh_hierarchy_create(const sh_params* p, void* hip_stream, sh_hierarchy
 sh_status sh_set_level_layout(sh_hierarchy h, int32_t lev, int32_t nboxes, const int32_t* boxes,
                               void* arena, size_t arena_bytes);
 
-/* Copy a dense float64 state (layout above) into buffer role `role` of level `lev`.
+/* Copy a dense float64 state (layout above) of the four fields psi1, psi2, Pi1, Pi2
+   (section "Minimal example": the two scalars and their conformal-time derivatives)
+   into buffer role `role` of level `lev`; values are rounded to the storage precision.
    `src` is host memory (src_is_device = 0, the call copies it before returning) or
    device memory (queued on the stream).  Errors: SH_EINVAL, SH_ESTATE (no layout). */
 sh_status sh_write_state(sh_hierarchy h, int32_t lev, int32_t role, const double* src, int32_t src_is_device,
                          int32_t with_ghosts);
 
-/* Copy buffer role `role` of level `lev` out as a dense float64 state.  Host `dst`
-   synchronises the stream. */
+/* Copy buffer role `role` of level `lev` out as a dense float64 state of the four
+   fields of section "Minimal example" (layout above).  `dst` is host memory (the call
+   synchronises the stream and reports kernel failures as SH_EDEVICE) or device memory
+   (queued).  Errors: SH_EINVAL, SH_ESTATE (no layout). */
 sh_status sh_read_state(sh_hierarchy h, int32_t lev, int32_t role, double* dst, int32_t dst_is_device,
                         int32_t with_ghosts);
 
@@ -235,9 +252,21 @@ sh_status sh_local_nest_boxes(int32_t M_level, int32_t nadded, const int32_t* ad
 /* Wait for all work queued by this hierarchy; SH_EDEVICE if any kernel failed. */
 sh_status sh_sync(sh_hierarchy h);
 
+/* Release the handle and the library's index tables (after waiting for its queued
+   work).  Caller-owned arenas are not touched and may be freed afterwards. */
 sh_status sh_hierarchy_destroy(sh_hierarchy h);
 
+/* Message of the last non-OK status returned on this thread (never NULL). */
 const char* sh_last_error(void);
+
+/* Measurement support, not part of the level step: the HBM bandwidth a plain kernel
+   reaches on this device, as the achievable ceiling beside the nominal peak.  One launch
+   of `bytes` (a positive multiple of 16) with 16-byte nontemporal accesses, on
+   `hip_stream`: kind 0 reads `src` (device; nothing is written to `dst`, which must
+   still be a device buffer of at least 16 bytes), 1 writes `dst` (device), 2 copies src
+   to dst (device, not overlapping).  Both pointers 16-byte aligned.  Queued; errors:
+   SH_EINVAL (bad kind, size or alignment), SH_EDEVICE (launch failed). */
+sh_status sh_stream_probe(int32_t kind, const void* src, void* dst, int64_t bytes, void* hip_stream);
 
 /* Stage scalars the device derives for `lev` at stage s (0..3 for RK4, 0..2 for SSPRK3)
    of the current step: out[0..6] = {eta_s, c_fric, c_pot, dt/6, dt/3, dt/2, dt}.
@@ -316,6 +345,27 @@ sh_status sh_shadow_begin(sh_hierarchy h);
 sh_status sh_shadow_advance(sh_hierarchy h);
 sh_status sh_shadow_end(sh_hierarchy h);
 sh_status sh_read_tee(sh_hierarchy h, int32_t lev, double* out_dev);
+
+/* Per-field estimates and their modifier (Sec. IV.C "Modifying truncation error
+   estimates"; App. D), for a hierarchy created with tee_fields = 1: every synchronisation
+   (and sh_shadow_end) keeps each component's own estimate D_c = |C_c - avg(children)_c|,
+   and tagging by estimate marks a cell where f_c(D_c) > te_crit[c] for some component c,
+   with the modifier f_c(D) = scale[c] * D (float64).  The paper's modifier is a user
+   function; the one built here is the rescaling its App. D applies (D_phi / max phi and
+   D_phi' / max phi'), with scale[c] supplied by the caller, e.g. 1 / sh_field_absmax.
+   te_crit[4] and scale[4] (NULL = all 1) are host arrays, finite and >= 0; they apply at
+   the next sh_tag_cells, so the scales can be renewed before each regrid without
+   touching the estimates already formed.  sh_set_tee on such a hierarchy sets every
+   threshold to te_crit and every scale to 1 (the same tags as one estimate per cell).
+   sh_read_tee then writes 4 x (valid cells) doubles, component after component.
+   Errors: SH_ESTATE (tee_fields = 0), SH_EINVAL (bad tag_mode, threshold or scale). */
+sh_status sh_set_tee_fields(sh_hierarchy h, int32_t enable, const double* te_crit, const double* scale,
+                            int32_t tag_mode);
+
+/* out_host[c] = max |U_c| over the valid cells of every level (c = psi1, psi2, Pi1, Pi2;
+   NaN if any value is NaN): the field maxima App. D normalises the estimates by.
+   Synchronises. */
+sh_status sh_field_absmax(sh_hierarchy h, double* out_host);
 
 /* Recorded level steps (HIP graphs).  The Berger-Oliger order of Sec. II.A (Fig. 2) is a
    fixed sequence of launches for a fixed layout, so a coarse step (or several) can be

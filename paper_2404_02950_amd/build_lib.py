@@ -28,7 +28,7 @@ HIP_FLAGS = [
 ]
 HOST_FLAGS = ["-O2", "-fPIC", "-std=c++17", "-ffp-contract=off", "-Wall"]
 
-HIP_SOURCES = ["kernels.hip", "kernels_hilap.hip", "kernels_ko.hip", "kernels_ko_lds.hip", "kernels_fused.hip", "runtime.cpp"]
+HIP_SOURCES = ["kernels.hip", "kernels_hilap.hip", "kernels_ko.hip", "kernels_ko_lds.hip", "kernels_fused.hip", "kernels_stream.hip", "runtime.cpp"]
 HOST_SOURCES = ["cluster.cpp", "local_regrid.cpp"]
 
 

@@ -188,17 +188,18 @@ __global__ __launch_bounds__(SH_BLOCK) void k_ghost_interp(const InterpSeg* __re
 // ---------------------------------------------------------------------------------
 // A5: average down, all 4 components, fine U_n -> coarse U_n:
 //   c = ((((f000+f100)+(f010+f110))+((f001+f101)+(f011+f111))) * 0.125)
-// With tee: first the truncation error estimate, max over the components of
-// |C - avg| (float64; the first component's value unless a later one compares greater),
-// stored on the 8 children in the fine level's per-cell array.  write_coarse = 0 keeps
-// the coarse state (the shadow-level comparison).
+// With tee: first the truncation error estimate |C - avg| (float64), stored on the 8
+// children in the fine level's per-cell array: for tee_nc = 1 the maximum over the
+// components (the first component's value unless a later one compares greater), for
+// tee_nc = 4 each component's own (component c at tee + c * tee_cs).  write_coarse = 0
+// keeps the coarse state (the shadow-level comparison).
 // ---------------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(SH_BLOCK) void k_avgdown(const AvgSeg* __restrict__ segs,
                                                       const SegBlock* __restrict__ blocks,
                                                       const BoxDev* __restrict__ cboxes,
                                                       const BoxDev* __restrict__ fboxes, double* __restrict__ tee,
-                                                      int write_coarse) {
+                                                      int tee_nc, long long tee_cs, int write_coarse) {
   const SegBlock sb = blocks[blockIdx.x];
   const AvgSeg s = segs[sb.seg];
   const int c = sb.start + threadIdx.x;
@@ -214,7 +215,7 @@ __global__ __launch_bounds__(SH_BLOCK) void k_avgdown(const AvgSeg* __restrict__
   const long long ec = elem<T>(C, s.clo[0] + i, s.clo[1] + j, s.clo[2] + k);
   const long long ef = elem<T>(F, s.f0[0] + 2 * i, s.f0[1] + 2 * j, s.f0[2] + 2 * k);
   const long long px = F.px, plane = px * F.py;
-  double t = 0.0;
+  double t = 0.0, dc[4];
   for (int comp = 0; comp < 4; ++comp) {
     const T* f = src + comp * F.cs + ef;
     const double f000 = f[0], f100 = f[1], f010 = f[px], f110 = f[px + 1];
@@ -222,6 +223,7 @@ __global__ __launch_bounds__(SH_BLOCK) void k_avgdown(const AvgSeg* __restrict__
     const double avg = ((((f000 + f100) + (f010 + f110)) + ((f001 + f101) + (f011 + f111))) * 0.125);
     if (tee) {
       const double d = fabs((double)dst[comp * C.cs + ec] - avg);
+      dc[comp] = d;
       t = (comp == 0 || d > t) ? d : t;
     }
     if (write_coarse) dst[comp * C.cs + ec] = (T)avg;
@@ -231,8 +233,15 @@ __global__ __launch_bounds__(SH_BLOCK) void k_avgdown(const AvgSeg* __restrict__
     for (int dz = 0; dz < 2; ++dz)
       for (int dy = 0; dy < 2; ++dy) {
         const long long row = F.mask_off + ((long long)(z0 + dz) * F.ny + (y0 + dy)) * F.nx + x0;
-        tee[row] = t;
-        tee[row + 1] = t;
+        if (tee_nc == 4) {
+          for (int comp = 0; comp < 4; ++comp) {
+            tee[comp * tee_cs + row] = dc[comp];
+            tee[comp * tee_cs + row + 1] = dc[comp];
+          }
+        } else {
+          tee[row] = t;
+          tee[row + 1] = t;
+        }
       }
   }
 }
@@ -244,7 +253,8 @@ __global__ __launch_bounds__(SH_BLOCK) void k_regrid_copy(const CopySeg* __restr
                                                           const BoxDev* __restrict__ dboxes,
                                                           const BoxDev* __restrict__ sboxes,
                                                           const double* __restrict__ tee_src,
-                                                          double* __restrict__ tee_dst) {
+                                                          double* __restrict__ tee_dst, int tee_nc,
+                                                          long long tee_cs_src, long long tee_cs_dst) {
   const SegBlock sb = blocks[blockIdx.x];
   const CopySeg s = segs[sb.seg];
   const int c = sb.start + threadIdx.x;
@@ -261,9 +271,11 @@ __global__ __launch_bounds__(SH_BLOCK) void k_regrid_copy(const CopySeg* __restr
   const long long es = elem<T>(Sb, s.slo[0] + i, s.slo[1] + j, s.slo[2] + k);
   for (int comp = 0; comp < 4; ++comp) dst[comp * D.cs + ed] = src[comp * Sb.cs + es];
   // the truncation error estimate of a kept cell stays with it
-  if (tee_src)
-    tee_dst[D.mask_off + ((long long)(s.dlo[2] + k) * D.ny + (s.dlo[1] + j)) * D.nx + (s.dlo[0] + i)] =
-        tee_src[Sb.mask_off + ((long long)(s.slo[2] + k) * Sb.ny + (s.slo[1] + j)) * Sb.nx + (s.slo[0] + i)];
+  if (tee_src) {
+    const long long cd = D.mask_off + ((long long)(s.dlo[2] + k) * D.ny + (s.dlo[1] + j)) * D.nx + (s.dlo[0] + i);
+    const long long cs = Sb.mask_off + ((long long)(s.slo[2] + k) * Sb.ny + (s.slo[1] + j)) * Sb.nx + (s.slo[0] + i);
+    for (int comp = 0; comp < tee_nc; ++comp) tee_dst[comp * tee_cs_dst + cd] = tee_src[comp * tee_cs_src + cs];
+  }
 }
 
 // ---------------------------------------------------------------------------------
@@ -292,7 +304,7 @@ template <typename T>
 __global__ __launch_bounds__(SH_BLOCK) void k_tag(const Tile* __restrict__ tiles, int ntiles,
                                                   const BoxDev* __restrict__ boxes, uint8_t* __restrict__ mask,
                                                   int* __restrict__ tile_count, const double* __restrict__ tee,
-                                                  double te_crit, int mode) {
+                                                  const TeeSpec te, int mode) {
   const int lane = threadIdx.x & (SH_WAVE - 1);
   const int t = blockIdx.x * (SH_BLOCK / SH_WAVE) + (threadIdx.x >> 6);
   if (t >= ntiles) return;
@@ -313,7 +325,15 @@ __global__ __launch_bounds__(SH_BLOCK) void k_tag(const Tile* __restrict__ tiles
   int count = 0;
   for (int z = z0; z < zend; ++z) {
     const long long cell = B.mask_off + ((long long)z * B.ny + y) * B.nx + x;
-    bool tag = (mode & 2) && tee[cell] > te_crit;
+    bool tag = false;
+    if (mode & 2) {
+      if (te.nc == 4) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) tag = tag || (te.scale[c] * tee[c * te.cs + cell] > te.crit[c]);
+      } else {
+        tag = tee[cell] > te.crit[0];
+      }
+    }
     if (!(mode & 1)) {
       tag = tag && active;
       if (active) mask[cell] = tag ? 1 : 0;
@@ -492,6 +512,65 @@ __global__ __launch_bounds__(SH_BLOCK) void k_energy(const Tile* __restrict__ ti
   }
 }
 
+// Largest |U_c| per component over the valid cells of each tile (the maxima appendix D
+// normalises truncation error estimates by).  A NaN anywhere makes the maximum NaN.
+__device__ __forceinline__ double nanmax(double m, double v) { return (v > m || v != v) ? v : m; }
+
+__device__ __forceinline__ double wave_nanmax(double v) {
+#pragma unroll
+  for (int o = SH_WAVE / 2; o >= 1; o >>= 1) v = nanmax(v, __shfl_xor(v, o));
+  return v;
+}
+
+template <typename T>
+__global__ __launch_bounds__(SH_BLOCK) void k_absmax(const Tile* __restrict__ tiles, int ntiles,
+                                                     const BoxDev* __restrict__ boxes, double* __restrict__ part) {
+  const int lane = threadIdx.x & (SH_WAVE - 1);
+  const int t = blockIdx.x * (SH_BLOCK / SH_WAVE) + (threadIdx.x >> 6);
+  if (t >= ntiles) return;
+  const Tile tl = tiles[t];
+  double m[4] = {0.0, 0.0, 0.0, 0.0};
+  if (tl.box >= 0) {
+    const BoxDev B = boxes[tl.box];
+    const T* __restrict__ U = (const T*)slot_base(B, role_slot(ROLE_UN, *B.ls));
+    const int tx = lane & ((1 << tl.txs) - 1), ty = lane >> tl.txs;
+    const int x = (tl.xy & 0xffff) + tx, y = (tl.xy >> 16) + ty;
+    if (x < B.nx && y < B.ny) {
+      const int z0 = tl.zz & 0xffff, zend = min(z0 + (tl.zz >> 16), B.nz);
+      for (int z = z0; z < zend; ++z) {
+        const long long e = elem<T>(B, x, y, z);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) m[c] = nanmax(m[c], fabs((double)U[c * B.cs + e]));
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 4; ++c) m[c] = wave_nanmax(m[c]);
+  if (lane == 0)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) part[4 * (long long)t + c] = m[c];
+}
+
+// Maximum over the per-tile partials (one block), per component.
+__global__ __launch_bounds__(256) void k_absmax_final(const double* __restrict__ part, int n, double* __restrict__ out) {
+  __shared__ double sm[4][256];
+  const int tid = threadIdx.x;
+  double m[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int i = tid; i < n; i += 256)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) m[c] = nanmax(m[c], part[4 * (long long)i + c]);
+#pragma unroll
+  for (int c = 0; c < 4; ++c) sm[c][tid] = m[c];
+  __syncthreads();
+  for (int o = 128; o >= 1; o >>= 1) {
+    if (tid < o)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) sm[c][tid] = nanmax(sm[c][tid], sm[c][tid + o]);
+    __syncthreads();
+  }
+  if (tid < 4) out[tid] = sm[tid][0];
+}
+
 // Fixed-order final sum of the per-tile partials (one block): out = [kin, grad, pot, nonfinite].
 __global__ __launch_bounds__(256) void k_energy_final(const EnergyPartial* __restrict__ part, int n,
                                                       double vol, double* __restrict__ out) {
@@ -637,37 +716,39 @@ void sh_launch_ghost_interp(int prec, int interp, const InterpSeg* segs, const S
 }
 
 void sh_launch_avgdown(int prec, const AvgSeg* segs, const SegBlock* blocks, int nblocks, const BoxDev* cboxes,
-                       const BoxDev* fboxes, double* tee, int write_coarse, hipStream_t st) {
+                       const BoxDev* fboxes, double* tee, int tee_nc, long long tee_cs, int write_coarse,
+                       hipStream_t st) {
   if (nblocks == 0) return;
   if (prec == 0)
     hipLaunchKernelGGL(k_avgdown<double>, dim3(nblocks), dim3(SH_BLOCK), 0, st, segs, blocks, cboxes, fboxes, tee,
-                       write_coarse);
+                       tee_nc, tee_cs, write_coarse);
   else
     hipLaunchKernelGGL(k_avgdown<float>, dim3(nblocks), dim3(SH_BLOCK), 0, st, segs, blocks, cboxes, fboxes, tee,
-                       write_coarse);
+                       tee_nc, tee_cs, write_coarse);
 }
 
 void sh_launch_regrid_copy(int prec, const CopySeg* segs, const SegBlock* blocks, int nblocks, const BoxDev* dboxes,
-                           const BoxDev* sboxes, const double* tee_src, double* tee_dst, hipStream_t st) {
+                           const BoxDev* sboxes, const double* tee_src, double* tee_dst, int tee_nc,
+                           long long tee_cs_src, long long tee_cs_dst, hipStream_t st) {
   if (nblocks == 0) return;
   if (prec == 0)
     hipLaunchKernelGGL(k_regrid_copy<double>, dim3(nblocks), dim3(SH_BLOCK), 0, st, segs, blocks, dboxes, sboxes,
-                       tee_src, tee_dst);
+                       tee_src, tee_dst, tee_nc, tee_cs_src, tee_cs_dst);
   else
     hipLaunchKernelGGL(k_regrid_copy<float>, dim3(nblocks), dim3(SH_BLOCK), 0, st, segs, blocks, dboxes, sboxes,
-                       tee_src, tee_dst);
+                       tee_src, tee_dst, tee_nc, tee_cs_src, tee_cs_dst);
 }
 
 void sh_launch_tag(int prec, const Tile* tiles, int ntiles, const BoxDev* boxes, uint8_t* mask, int* tile_count,
-                   const double* tee, double te_crit, int mode, hipStream_t st) {
+                   const double* tee, const TeeSpec& te, int mode, hipStream_t st) {
   const int nb = nblk(ntiles, SH_BLOCK / SH_WAVE);
   if (nb == 0) return;
   if (prec == 0)
     hipLaunchKernelGGL(k_tag<double>, dim3(nb), dim3(SH_BLOCK), 0, st, tiles, ntiles, boxes, mask, tile_count, tee,
-                       te_crit, mode);
+                       te, mode);
   else
     hipLaunchKernelGGL(k_tag<float>, dim3(nb), dim3(SH_BLOCK), 0, st, tiles, ntiles, boxes, mask, tile_count, tee,
-                       te_crit, mode);
+                       te, mode);
 }
 
 void sh_launch_scan(const int* in, long long* out, int n, hipStream_t st) {
@@ -727,4 +808,14 @@ __global__ void k_debug_scalars(const LevelScal* ls, int s, double* out) {
 
 void sh_launch_debug_scalars(const LevelScal* ls, int s, double* out, hipStream_t st) {
   hipLaunchKernelGGL(k_debug_scalars, dim3(1), dim3(1), 0, st, ls, s, out);
+}
+
+void sh_launch_absmax(int prec, const Tile* tiles, int ntiles, const BoxDev* boxes, double* part, double* out,
+                      hipStream_t st) {
+  const int nb = nblk(ntiles, SH_BLOCK / SH_WAVE);
+  if (nb > 0) {
+    if (prec == 0) hipLaunchKernelGGL(k_absmax<double>, dim3(nb), dim3(SH_BLOCK), 0, st, tiles, ntiles, boxes, part);
+    else hipLaunchKernelGGL(k_absmax<float>, dim3(nb), dim3(SH_BLOCK), 0, st, tiles, ntiles, boxes, part);
+  }
+  hipLaunchKernelGGL(k_absmax_final, dim3(1), dim3(256), 0, st, part, ntiles, out);
 }

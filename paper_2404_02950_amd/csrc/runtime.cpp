@@ -117,6 +117,7 @@ struct SegPlan {
 
 struct LayoutGeom {
   int ng = 1;                       // ghost layers
+  int tee_nc = 1;                   // truncation error estimates per valid cell (1 or 4)
   int esize;                        // bytes of a stored value (8 or 4)
   int xoff;                         // elements before x = 0 in a row
   std::vector<long long> box_off;   // element offset of each box block
@@ -176,11 +177,14 @@ static double ko_coef(const sh_params& p, double dx) {
 static int stencil_depth(const sh_params& p) { return std::max(lap_order_of(p), ko_of(p)); }
 static int fill_comps(const sh_params& p) { return ko_of(p) ? 4 : 2; }
 static int refined_ng(const sh_params& p) { return std::max(stencil_depth(p), interp_reach(p)); }
+// truncation error estimates kept per cell: one per component when asked for, else their maximum
+static int tee_comps(const sh_params& p) { return p.tee_fields ? 4 : 1; }
 // the fused level-0 step: 7-point stencil, no dissipation
 static bool fusable(const sh_params& p) { return lap_order_of(p) == 1 && ko_of(p) == 0; }
 
-static void make_geom(int prec, int ng, const std::vector<IBox>& boxes, LayoutGeom& g, bool acc) {
+static void make_geom(int prec, int ng, const std::vector<IBox>& boxes, LayoutGeom& g, bool acc, int tee_nc = 1) {
   g.ng = ng;
+  g.tee_nc = tee_nc;
   g.esize = prec == SH_F64 ? 8 : 4;
   g.xoff = 64 / g.esize;
   g.box_off.clear();
@@ -232,7 +236,7 @@ static void make_geom(int prec, int ng, const std::vector<IBox>& boxes, LayoutGe
   g.off_toff = take((size_t)(nt + 1) * 8);
   g.off_part = take((size_t)nt * sizeof(EnergyPartial));
   g.off_eout = take(4 * 8);
-  g.off_tee = take((size_t)g.nvalid * 8);  // truncation error estimate per valid cell
+  g.off_tee = take((size_t)g.nvalid * 8 * g.tee_nc);  // truncation error estimates per valid cell
   g.total = o + 256;  // slack for aligning the arena base
 }
 
@@ -469,9 +473,10 @@ struct sh_hierarchy_s {
   bool capturing = false;
   std::vector<long long> k_at_capture;
   // truncation error estimates (computed at every synchronisation when on) and the
-  // tagging criterion: bit 0 plaquette winding, bit 1 estimate above te_crit
+  // tagging criterion: bit 0 plaquette winding, bit 1 estimate above its threshold
+  // (te.crit[0] for one estimate per cell; te.scale[c] * estimate_c > te.crit[c] per field)
   bool tee_on = false;
-  double te_crit = 0.0;
+  TeeSpec te = {{0.0, 0.0, 0.0, 0.0}, {1.0, 1.0, 1.0, 1.0}, 1, 0};
   int tag_mode = 1;
   // shadow level: level 0 averaged onto half its resolution, evolved by one step of
   // twice the level-0 step (its scalars live in d_ls[SH_SHADOW_LS]; arena owned here)
@@ -890,6 +895,7 @@ static sh_status check_params(const sh_params* p) {
   if ((p->ko_order != 0 && p->ko_order != 2 && p->ko_order != 3) || !(p->ko_eps >= 0) || p->ko_eps == HUGE_VAL)
     return fail(SH_EINVAL, "ko_order must be 0, 2 or 3 and ko_eps finite and >= 0");
   if ((long long)p->n0 << p->max_level > 32767) return fail(SH_EINVAL, "finest level too large");
+  if (p->tee_fields != 0 && p->tee_fields != 1) return fail(SH_EINVAL, "tee_fields must be 0 or 1");
   return SH_OK;
 }
 
@@ -898,7 +904,7 @@ size_t sh_arena_bytes(const sh_params* p, int32_t lev, int32_t nboxes, const int
   std::vector<IBox> b;
   if (parse_boxes(*p, lev, nboxes, boxes, b) != SH_OK) return 0;
   LayoutGeom g;
-  make_geom(p->prec, lev == 0 ? SH_NG0 : refined_ng(*p), b, g, stages_of(*p) == 4);
+  make_geom(p->prec, lev == 0 ? SH_NG0 : refined_ng(*p), b, g, stages_of(*p) == 4, tee_comps(*p));
   return g.total;
 }
 
@@ -908,7 +914,9 @@ sh_status sh_hierarchy_create(const sh_params* p, void* hip_stream, sh_hierarchy
   sh_status s = check_params(p);
   if (s != SH_OK) return s;
   int ndev = 0;
-  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(SH_EDEVICE, "no HIP device");
+  const hipError_t de = hipGetDeviceCount(&ndev);
+  if (de != hipSuccess || ndev < 1)
+    return fail(SH_EDEVICE, std::string("no HIP device (hipGetDeviceCount: ") + hipGetErrorString(de) + ")");
   sh_hierarchy h = new (std::nothrow) sh_hierarchy_s;
   if (!h) return fail(SH_ENOMEM, "host allocation failed");
   h->p = *p;
@@ -1046,7 +1054,7 @@ sh_status sh_set_level_layout(sh_hierarchy h, int32_t l, int32_t nboxes, const i
     for (auto& b : N.boxes) v += b.volume();
     if (v != (long long)N.M * N.M * N.M) return fail(SH_EINVAL, "level 0 boxes must cover the domain");
   }
-  make_geom(p.prec, l == 0 ? SH_NG0 : refined_ng(p), N.boxes, N.g, stages_of(p) == 4);
+  make_geom(p.prec, l == 0 ? SH_NG0 : refined_ng(p), N.boxes, N.g, stages_of(p) == 4, tee_comps(p));
   if (!arena || arena_bytes < N.g.total) return fail(SH_ENOMEM, "arena smaller than sh_arena_bytes");
   N.base = (char*)round_up((long long)(uintptr_t)arena, 256);
   N.bins.build(N.boxes, N.M);
@@ -1125,10 +1133,10 @@ sh_status sh_set_level_layout(sh_hierarchy h, int32_t l, int32_t nboxes, const i
   s = upload_ls(h, l);
   if (s != SH_OK) return s;
   // truncation error estimates: 0 for new cells, kept cells keep theirs
-  HIPCHK(hipMemsetAsync(N.tee(), 0, (size_t)N.g.nvalid * 8, h->st));
+  HIPCHK(hipMemsetAsync(N.tee(), 0, (size_t)N.g.nvalid * 8 * N.g.tee_nc, h->st));
   if (existing) {
     sh_launch_regrid_copy(p.prec, keep.segs.p, keep.blocks.p, keep.nblocks(), N.dbox.p, old.dbox.p, old.tee(),
-                          N.tee(), h->st);
+                          N.tee(), N.g.tee_nc, old.g.nvalid, N.g.nvalid, h->st);
     LAUNCHCHK();
   }
   if (l > 0) {
@@ -1293,7 +1301,7 @@ sh_status sh_average_down(sh_hierarchy h, int32_t f) {
   h->rec(4, f, 0, 0);
   hipEvent_t ev = h->prof_begin();
   sh_launch_avgdown(h->p.prec, F.a5.segs.p, F.a5.blocks.p, F.a5.nblocks(), C.dbox.p, F.dbox.p,
-                    h->tee_on ? F.tee() : nullptr, 1, h->st);
+                    h->tee_on ? F.tee() : nullptr, F.g.tee_nc, F.g.nvalid, 1, h->st);
   h->prof_end(ev, 6);
   LAUNCHCHK();
   if ((s = same_level_fill(h, f - 1, ROLE_UN)) != SH_OK) return s;
@@ -1306,8 +1314,57 @@ sh_status sh_set_tee(sh_hierarchy h, int32_t enable, double te_crit, int32_t tag
   if (tag_mode < 1 || tag_mode > 3 || !(te_crit >= 0) || te_crit == HUGE_VAL)
     return fail(SH_EINVAL, "tag_mode must be 1, 2 or 3 and te_crit finite and >= 0");
   h->tee_on = enable != 0;
-  h->te_crit = te_crit;
+  for (int c = 0; c < 4; ++c) {
+    h->te.crit[c] = te_crit;
+    h->te.scale[c] = 1.0;
+  }
   h->tag_mode = tag_mode;
+  return SH_OK;
+}
+
+sh_status sh_set_tee_fields(sh_hierarchy h, int32_t enable, const double* te_crit, const double* scale,
+                            int32_t tag_mode) {
+  sh_status s = not_capturing(h);
+  if (s != SH_OK) return s;
+  if (!h->p.tee_fields) return fail(SH_ESTATE, "the hierarchy keeps one estimate per cell (sh_params.tee_fields = 0)");
+  if (!te_crit || tag_mode < 1 || tag_mode > 3) return fail(SH_EINVAL, "tag_mode must be 1, 2 or 3 and te_crit given");
+  for (int c = 0; c < 4; ++c) {
+    const double sc = scale ? scale[c] : 1.0;
+    if (!(te_crit[c] >= 0) || te_crit[c] == HUGE_VAL || !(sc >= 0) || sc == HUGE_VAL)
+      return fail(SH_EINVAL, "thresholds and scales must be finite and >= 0");
+  }
+  h->tee_on = enable != 0;
+  for (int c = 0; c < 4; ++c) {
+    h->te.crit[c] = te_crit[c];
+    h->te.scale[c] = scale ? scale[c] : 1.0;
+  }
+  h->tag_mode = tag_mode;
+  return SH_OK;
+}
+
+sh_status sh_field_absmax(sh_hierarchy h, double* out_host) {
+  if (!h || !out_host) return fail(SH_EINVAL, "null argument");
+  if (h->capturing) return not_capturing(h);
+  if (h->lev.empty()) return fail(SH_ESTATE, "no levels");
+  const int nl = (int)h->lev.size();
+  for (int l = 0; l < nl; ++l) {
+    Level& L = h->lev[l];
+    if (L.stale) return fail(SH_ESTATE, "stale level");
+    sh_launch_absmax(h->p.prec, L.tiles.p, L.ntiles(), L.dbox.p, (double*)L.epart(), L.eout(), h->st);
+    LAUNCHCHK();
+  }
+  std::vector<double> all(4 * nl);
+  for (int l = 0; l < nl; ++l)
+    HIPCHK(hipMemcpyAsync(&all[4 * l], h->lev[l].eout(), 32, hipMemcpyDeviceToHost, h->st));
+  HIPCHK(hipStreamSynchronize(h->st));
+  for (int c = 0; c < 4; ++c) {
+    double m = 0.0;
+    for (int l = 0; l < nl; ++l) {
+      const double v = all[4 * l + c];
+      m = (v > m || v != v) ? v : m;
+    }
+    out_host[c] = m;
+  }
   return SH_OK;
 }
 
@@ -1378,7 +1435,7 @@ sh_status sh_shadow_begin(sh_hierarchy h) {
   HIPCHK(hipMemcpyAsync(h->d_ls + SH_SHADOW_LS, &ls, sizeof(ls), hipMemcpyHostToDevice, h->st));
   // the shadow's state: level 0 averaged onto it, then its periodic ghosts
   sh_launch_avgdown(p.prec, h->shadow_a5.segs.p, h->shadow_a5.blocks.p, h->shadow_a5.nblocks(), Sh.dbox.p,
-                    L0.dbox.p, nullptr, 1, h->st);
+                    L0.dbox.p, nullptr, 1, 0, 1, h->st);
   LAUNCHCHK();
   shadow_copy(h, ROLE_UN);
   LAUNCHCHK();
@@ -1426,7 +1483,7 @@ sh_status sh_shadow_end(sh_hierarchy h) {
   }
   // estimate on level 0: shadow against level 0 averaged, the shadow itself unchanged
   sh_launch_avgdown(h->p.prec, h->shadow_a5.segs.p, h->shadow_a5.blocks.p, h->shadow_a5.nblocks(), S.dbox.p,
-                    L0.dbox.p, L0.tee(), 0, h->st);
+                    L0.dbox.p, L0.tee(), L0.g.tee_nc, L0.g.nvalid, 0, h->st);
   LAUNCHCHK();
   shadow_release(h);
   return SH_OK;
@@ -1437,7 +1494,7 @@ sh_status sh_read_tee(sh_hierarchy h, int32_t l, double* out_dev) {
   if (s != SH_OK || (s = not_capturing(h)) != SH_OK) return s;
   if (!out_dev) return fail(SH_EINVAL, "null output");
   const Level& L = h->lev[l];
-  HIPCHK(hipMemcpyAsync(out_dev, L.tee(), (size_t)L.g.nvalid * 8, hipMemcpyDeviceToDevice, h->st));
+  HIPCHK(hipMemcpyAsync(out_dev, L.tee(), (size_t)L.g.nvalid * 8 * L.g.tee_nc, hipMemcpyDeviceToDevice, h->st));
   HIPCHK(hipStreamSynchronize(h->st));
   return SH_OK;
 }
@@ -1451,7 +1508,10 @@ sh_status sh_tag_cells(sh_hierarchy h, int32_t l, uint8_t* mask_dev, int32_t* id
   if ((s = fill(h, l, ROLE_UN, 4)) != SH_OK) return s;
   uint8_t* mask = mask_dev ? mask_dev : L.mask();
   const int nt = L.ntiles();
-  sh_launch_tag(h->p.prec, L.tiles.p, nt, L.dbox.p, mask, L.tile_count(), L.tee(), h->te_crit, h->tag_mode, h->st);
+  TeeSpec te = h->te;
+  te.nc = L.g.tee_nc;
+  te.cs = L.g.nvalid;
+  sh_launch_tag(h->p.prec, L.tiles.p, nt, L.dbox.p, mask, L.tile_count(), L.tee(), te, h->tag_mode, h->st);
   LAUNCHCHK();
   sh_launch_scan(L.tile_count(), L.tile_off(), nt, h->st);
   LAUNCHCHK();
@@ -1533,6 +1593,19 @@ sh_status sh_sync(sh_hierarchy h) {
   if (!h) return fail(SH_EINVAL, "null handle");
   if (h->capturing) return not_capturing(h);
   HIPCHK(hipStreamSynchronize(h->st));
+  HIPCHK(hipGetLastError());
+  return SH_OK;
+}
+
+sh_status sh_stream_probe(int32_t kind, const void* src, void* dst, int64_t bytes, void* hip_stream) {
+  if (kind < 0 || kind > 2) return fail(SH_EINVAL, "stream probe kind must be 0 (read), 1 (write) or 2 (copy)");
+  if (bytes <= 0 || (bytes & 15)) return fail(SH_EINVAL, "stream probe size must be a positive multiple of 16 bytes");
+  if (!dst || (kind != 1 && !src)) return fail(SH_EINVAL, "stream probe needs a destination (and a source to read)");
+  if (((uintptr_t)src & 15) || ((uintptr_t)dst & 15)) return fail(SH_EINVAL, "stream probe buffers must be 16-byte aligned");
+  const long long nwords = bytes / 16;
+  if ((nwords + sh_stream_words_per_block() - 1) / sh_stream_words_per_block() > 0x7fffffffLL)
+    return fail(SH_EINVAL, "stream probe size too large for one launch");
+  sh_launch_stream(kind, src, dst, nwords, (hipStream_t)hip_stream);
   HIPCHK(hipGetLastError());
   return SH_OK;
 }

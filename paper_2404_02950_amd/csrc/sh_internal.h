@@ -142,3 +142,15 @@ struct EnergyPartial {
   double kin, grad, pot;
   long long nonfinite;
 };
+
+// Truncation error estimates kept per cell: nc = 1 (the maximum over the components) or
+// 4 (one per component, component c at tee + c * cs, cs = the level's valid cells).
+// Tagging by estimate: nc = 1 tags where tee > crit[0]; nc = 4 where
+// scale[c] * tee_c > crit[c] for some component (the modifier f_c(D) = scale_c D).
+struct TeeSpec {
+  double crit[4];
+  double scale[4];
+  int nc;
+  long long cs;
+};
+

@@ -34,11 +34,17 @@ void sh_launch_ghost_interp(int prec, int interp, const InterpSeg* segs, const S
                             const BoxDev* fboxes, const BoxDev* cboxes, int role, int anum, int ncomp,
                             hipStream_t st);
 void sh_launch_avgdown(int prec, const AvgSeg* segs, const SegBlock* blocks, int nblocks, const BoxDev* cboxes,
-                       const BoxDev* fboxes, double* tee, int write_coarse, hipStream_t st);
+                       const BoxDev* fboxes, double* tee, int tee_nc, long long tee_cs, int write_coarse,
+                       hipStream_t st);
 void sh_launch_regrid_copy(int prec, const CopySeg* segs, const SegBlock* blocks, int nblocks, const BoxDev* dboxes,
-                           const BoxDev* sboxes, const double* tee_src, double* tee_dst, hipStream_t st);
+                           const BoxDev* sboxes, const double* tee_src, double* tee_dst, int tee_nc,
+                           long long tee_cs_src, long long tee_cs_dst, hipStream_t st);
 void sh_launch_tag(int prec, const Tile* tiles, int ntiles, const BoxDev* boxes, uint8_t* mask, int* tile_count,
-                   const double* tee, double te_crit, int mode, hipStream_t st);
+                   const double* tee, const TeeSpec& te, int mode, hipStream_t st);
+// max |U_c| over the valid cells of a level's tiles: one partial per tile (4 doubles),
+// then the maximum over the tiles into out[4]
+void sh_launch_absmax(int prec, const Tile* tiles, int ntiles, const BoxDev* boxes, double* part, double* out,
+                      hipStream_t st);
 void sh_launch_scan(const int* in, long long* out, int n, hipStream_t st);
 void sh_launch_tag_compact(const Tile* tiles, int ntiles, const BoxDev* boxes, const uint8_t* mask,
                            const long long* tile_off, int* idx, long long cap, hipStream_t st);
@@ -53,3 +59,7 @@ void sh_launch_debug_scalars(const LevelScal* ls, int s, double* out, hipStream_
 void sh_launch_fused(int prec, bool nt, int shape, int variant, int nst, const Tile* tiles, int ntiles,
                      const BoxDev* boxes, hipStream_t st);
 void sh_fused_footprint(int shape, int* tx, int* ty);
+// streaming probes (kernels_stream.hip): kind 0 = read, 1 = write, 2 = copy of nwords
+// 16-byte words
+void sh_launch_stream(int kind, const void* src, void* dst, long long nwords, hipStream_t st);
+long long sh_stream_words_per_block();

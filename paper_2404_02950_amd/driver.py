@@ -28,6 +28,14 @@ def coarse_step(h):
     _advance(h, 0, 0, h.num_levels() - 1)
 
 
+def normalised_tee_scales(h):
+    """Modifier scales s_c = 1 / max |U_c| over the whole hierarchy (appendix D's
+    normalisation of the truncation error estimates of each field, section IV.C), 1 for a
+    component whose maximum is 0; for sh_set_tee_fields before a regrid."""
+    m = h.field_absmax()
+    return [1.0 / v if v > 0.0 else 1.0 for v in m]
+
+
 def regrid(h, max_level: int, layout_for=None, efficiency: float = 0.7, max_level_bytes: int | None = None,
            log=None, timing: dict | None = None, start: int = 1):
     """Rebuild levels start..max_level from tags (levels below start are kept).

@@ -55,7 +55,7 @@ def make_hierarchy(job: Job, stream):
 
 
 def arena_bytes(job: Job) -> int:
-    p = shamr.sh_params(job.n, float(job.n), 0.25, 0.1, 1.0, 2.0, job.beta, 0, 8, 64, 2, job.prec, 4, 1, 1, 0, 0.0)
+    p = shamr.sh_params(job.n, float(job.n), 0.25, 0.1, 1.0, 2.0, job.beta, 0, 8, 64, 2, job.prec, 4, 1, 1, 0, 0.0, 0)
     b = np.array([0, 0, 0, job.n - 1, job.n - 1, job.n - 1], np.int32)
     import ctypes
     return int(shamr.load().sh_arena_bytes(ctypes.byref(p), 0, 1, b.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))

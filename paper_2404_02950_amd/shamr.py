@@ -33,7 +33,7 @@ class sh_params(Structure):
         ("lam", c_double), ("alpha_fric", c_double), ("beta_pot", c_int32),
         ("max_level", c_int32), ("blocking_factor", c_int32), ("max_box", c_int32),
         ("n_error_buf", c_int32), ("prec", c_int32), ("integrator", c_int32), ("lap_order", c_int32),
-        ("interp", c_int32), ("ko_order", c_int32), ("ko_eps", c_double),
+        ("interp", c_int32), ("ko_order", c_int32), ("ko_eps", c_double), ("tee_fields", c_int32),
     ]
 
 
@@ -82,6 +82,9 @@ _PROTOS = {
     "sh_shadow_advance": (c_int32, [c_void_p]),
     "sh_shadow_end": (c_int32, [c_void_p]),
     "sh_read_tee": (c_int32, [c_void_p, c_int32, c_void_p]),
+    "sh_set_tee_fields": (c_int32, [c_void_p, c_int32, POINTER(c_double), POINTER(c_double), c_int32]),
+    "sh_field_absmax": (c_int32, [c_void_p, POINTER(c_double)]),
+    "sh_stream_probe": (c_int32, [c_int32, c_void_p, c_void_p, c_int64, c_void_p]),
 }
 
 EXPORTED = tuple(_PROTOS)
@@ -95,6 +98,10 @@ def load(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is missing: build it first (python -m paper_2404_02950_amd.build_lib)")
+    # torch first: the library then binds to the HIP runtime torch has loaded (same soname)
+    # instead of loading the system copy beside it, which would leave two HIP runtimes,
+    # each with its own view of the device, in one process
+    import torch  # noqa: F401
     lib = ctypes.CDLL(path)
     for name, (res, args) in _PROTOS.items():
         fn = getattr(lib, name)
@@ -176,6 +183,14 @@ def local_nest_boxes(M_level: int, added_fine, level_boxes, blocking_factor: int
         max_box, out, cap, nb))
 
 
+def stream_probe(kind: int, src, dst, nbytes: int, stream):
+    """One launch of the library's streaming probe (0 read, 1 write, 2 copy) of nbytes
+    on `stream` (torch tensors as buffers)."""
+    lib = load()
+    _check(lib.sh_stream_probe(kind, c_void_p(src.data_ptr() if src is not None else 0),
+                               c_void_p(dst.data_ptr()), nbytes, c_void_p(stream.cuda_stream)))
+
+
 class Hierarchy:
     """One simulation: levels of boxes in caller-owned (torch) device arenas."""
 
@@ -183,12 +198,13 @@ class Hierarchy:
                  alpha: float = 2.0, beta: int = 2, max_level: int = 0, blocking_factor: int = 8,
                  max_box: int = 64, n_error_buf: int = 2, prec: int = SH_F64, stream=None,
                  integrator: int = 4, lap_order: int = 1, interp: int = 1, ko_order: int = 0,
-                 ko_eps: float = 0.0):
+                 ko_eps: float = 0.0, tee_fields: int = 0):
         import torch
         self.torch = torch
         self.lib = load()
         self.params = sh_params(n0, L, cfl, eta0, lam, alpha, beta, max_level, blocking_factor, max_box,
-                                n_error_buf, prec, integrator, lap_order, interp, ko_order, ko_eps)
+                                n_error_buf, prec, integrator, lap_order, interp, ko_order, ko_eps,
+                                int(tee_fields))
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         h = c_void_p()
         _check(self.lib.sh_hierarchy_create(ctypes.byref(self.params), c_void_p(self.stream.cuda_stream),
@@ -268,6 +284,13 @@ class Hierarchy:
             o += sz
         return out
 
+    def read_device(self, lev: int, role: int = ROLE_UN):
+        """Buffer `role` of level `lev` as a flat float64 device tensor in the dense box
+        order (no ghosts), queued on the hierarchy's stream."""
+        out = self.torch.empty(self._count(lev, False), dtype=self.torch.float64, device="cuda")
+        _check(self.lib.sh_read_state(self.h, lev, role, c_void_p(out.data_ptr()), 1, 0))
+        return out
+
     def write_dense(self, lev: int, U: np.ndarray, role: int = ROLE_UN):
         """Write a dense (4, M, M, M) level array (valid cells of each box are taken)."""
         arrs = []
@@ -342,22 +365,35 @@ class Hierarchy:
     def shadow_end(self):
         _check(self.lib.sh_shadow_end(self.h))
 
+    def set_tee_fields(self, enable: bool = True, te_crit=(0.0, 0.0, 0.0, 0.0), scale=None, tag_mode: int = 3):
+        """Per-field thresholds and modifier scales (see sh_set_tee_fields)."""
+        crit = (c_double * 4)(*[float(v) for v in te_crit])
+        sc = (c_double * 4)(*[float(v) for v in scale]) if scale is not None else None
+        _check(self.lib.sh_set_tee_fields(self.h, int(enable), crit, sc, int(tag_mode)))
+
+    def field_absmax(self) -> np.ndarray:
+        out = (c_double * 4)()
+        _check(self.lib.sh_field_absmax(self.h, out))
+        return np.array(list(out))
+
     def tee_dense(self, lev: int) -> np.ndarray:
-        """A level's estimates as a dense float64 (M, M, M) array (0 outside the level)."""
+        """A level's estimates as a dense float64 (M, M, M) array, or (4, M, M, M) with one
+        estimate per component (0 outside the level)."""
         torch = self.torch
+        nc = 4 if self.params.tee_fields else 1
         nv = sum(int(np.prod(box_shape(b))) for b in self.boxes[lev])
         with torch.cuda.stream(self.stream):
-            t = torch.empty(max(nv, 1), dtype=torch.float64, device="cuda")
+            t = torch.empty(max(nc * nv, 1), dtype=torch.float64, device="cuda")
         _check(self.lib.sh_read_tee(self.h, lev, c_void_p(t.data_ptr())))
-        th = t.cpu().numpy()
+        th = t.cpu().numpy()[:nc * nv].reshape(nc, max(nv, 0))
         M = self.params.n0 << lev
-        out = np.zeros((M, M, M))
+        out = np.zeros((nc, M, M, M))
         o = 0
         for b in self.boxes[lev]:
             nz, ny, nx = box_shape(b)
-            out[b[2]:b[5] + 1, b[1]:b[4] + 1, b[0]:b[3] + 1] = th[o:o + nz * ny * nx].reshape(nz, ny, nx)
+            out[:, b[2]:b[5] + 1, b[1]:b[4] + 1, b[0]:b[3] + 1] = th[:, o:o + nz * ny * nx].reshape(nc, nz, ny, nx)
             o += nz * ny * nx
-        return out
+        return out if nc == 4 else out[0]
 
     def energy(self):
         e = (c_double * 4)()

@@ -35,7 +35,7 @@ def test_library_exports_every_declared_symbol(shamr):
 
 def test_arena_bytes_and_argument_checks(shamr):
     lib = shamr.load()
-    p = shamr.sh_params(64, 64.0, 0.25, 0.1, 1.0, 2.0, 2, 2, 8, 64, 2, shamr.SH_F64, 4, 1, 1, 0, 0.0)
+    p = shamr.sh_params(64, 64.0, 0.25, 0.1, 1.0, 2.0, 2, 2, 8, 64, 2, shamr.SH_F64, 4, 1, 1, 0, 0.0, 0)
     b = np.array([0, 0, 0, 63, 63, 63], np.int32)
     ptr = b.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
     n64 = lib.sh_arena_bytes(ctypes.byref(p), 0, 1, ptr)
@@ -66,7 +66,7 @@ def test_create_without_device_fails_cleanly(shamr):
     if torch.cuda.is_available():
         pytest.skip("a GPU is present")
     lib = shamr.load()
-    p = shamr.sh_params(16, 16.0, 0.25, 0.1, 1.0, 2.0, 2, 0, 8, 64, 2, 0, 4, 1, 1, 0, 0.0)
+    p = shamr.sh_params(16, 16.0, 0.25, 0.1, 1.0, 2.0, 2, 0, 8, 64, 2, 0, 4, 1, 1, 0, 0.0, 0)
     h = ctypes.c_void_p()
     assert lib.sh_hierarchy_create(ctypes.byref(p), None, ctypes.byref(h)) == shamr.SH_EDEVICE
     assert b"device" in lib.sh_last_error()

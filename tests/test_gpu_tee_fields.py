@@ -1,0 +1,105 @@
+"""GPU parity of the per-field truncation error estimates and their modifier (section
+IV.C; appendix D's normalisation by the field maxima): each component's estimate at every
+synchronisation and from the shadow level, the field maxima, and tagging with a
+threshold and a scale per component, against the oracle bit for bit through regrids,
+FP64 and FP32."""
+import numpy as np
+import pytest
+
+from oracle.amr import Hierarchy as OHier, normalising_scales
+from oracle.layout import block_layout
+from synth import string_loop_state
+
+pytestmark = pytest.mark.gpu
+
+shamr = pytest.importorskip("paper_2404_02950_amd.shamr")
+from paper_2404_02950_amd import driver  # noqa: E402
+from gpu_util import assert_bitwise, decompose  # noqa: E402
+
+CRIT = [2e-2, 1e30, 3e-2, 1e30]   # thresholds on psi1 and Pi1 only
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_per_field_estimates_maxima_and_tags_through_regrids(prec):
+    n = 24
+    U0 = string_loop_state(n, float(n), seed=5, nloops=2, rmin=3.5, rmax=4.5, taper_in=2.0, taper_out=7.0)
+    dt = np.float64 if prec == 0 else np.float32
+    hg = shamr.Hierarchy(n, float(n), 0.25, 0.1, 1.0, 2.0, 0, max_level=2, prec=prec, max_box=32, tee_fields=1)
+    hg.set_layout(0, decompose(n))
+    hg.write_dense(0, U0)
+    hg.fill_ghosts(0)
+    ho = OHier(n, float(n), 0.25, 0.1, 2, beta=0, dtype=dt)
+    ho.set_level0(U0)
+    hg.set_tee_fields(True, CRIT, None, 1)
+    ho.set_tee_fields(True, CRIT, tag_mode=1)
+
+    def regrid():
+        for lev in range(2):
+            if lev >= len(ho.levels):
+                break
+            to = ho.tags(lev)
+            assert np.array_equal(hg.tag_mask_dense(lev), to), f"tags differ on level {lev} (mode {ho.tag_mode})"
+            boxes = block_layout(to, ho.levels[lev].valid, 8, 32, 2)
+            ho.set_layout(lev + 1, boxes)
+            hg.set_layout(lev + 1, boxes)
+            if not boxes:
+                break
+
+    regrid()
+    assert len(ho.levels) == 3
+    for mode in (3, 2):
+        hg.shadow_begin()
+        ho.shadow_begin()
+        hg.shadow_advance()
+        ho.shadow_advance()
+        for _ in range(2):
+            driver.coarse_step(hg)
+            ho.coarse_step()
+        hg.shadow_end()
+        ho.shadow_end()
+        for lev in range(len(ho.levels)):
+            t = hg.tee_dense(lev)
+            assert t.shape == ho.levels[lev].tee.shape == (4,) + (n << lev,) * 3
+            assert_bitwise(t, ho.levels[lev].tee, f"per-field estimates, level {lev} (mode {mode})")
+        mg, mo = hg.field_absmax(), ho.field_absmax()
+        assert_bitwise(mg, mo, "field maxima")
+        sg, so = driver.normalised_tee_scales(hg), normalising_scales(mo)
+        assert_bitwise(np.array(sg), so, "modifier scales")
+        hg.set_tee_fields(True, CRIT, sg, mode)
+        ho.set_tee_fields(True, CRIT, so, mode)
+        f0 = so[0] * ho.levels[0].tee[0]
+        assert np.any(f0 > CRIT[0]) and not np.all(f0[ho.levels[0].valid] > CRIT[0])
+        regrid()
+        for lev in range(1, len(ho.levels)):
+            assert_bitwise(hg.tee_dense(lev), ho.levels[lev].tee, f"estimates kept through the regrid, level {lev}")
+    hg.close()
+
+
+def test_per_field_calls_are_checked_and_maxima_propagate_nan():
+    n = 16
+    U0 = string_loop_state(n, float(n), seed=2, nloops=1, rmin=3.0, rmax=3.5, taper_in=1.0, taper_out=4.0)
+    one = shamr.Hierarchy(n, float(n), 0.25, 0.1, 1.0, 2.0, 0, max_level=1)
+    one.set_layout(0, decompose(n))
+    with pytest.raises(shamr.ShError) as e:
+        one.set_tee_fields(True, [0.1] * 4)
+    assert e.value.status == shamr.SH_ESTATE
+    one.close()
+    h = shamr.Hierarchy(n, float(n), 0.25, 0.1, 1.0, 2.0, 0, max_level=1, tee_fields=1)
+    h.set_layout(0, decompose(n, [[8], [8], [8]]))
+    for crit, scale in (([0.1, -1.0, 0.1, 0.1], None), ([0.1] * 4, [1.0, 1.0, -2.0, 1.0]),
+                        ([0.1] * 4, [1.0, float("inf"), 1.0, 1.0])):
+        with pytest.raises(shamr.ShError) as e:
+            h.set_tee_fields(True, crit, scale)
+        assert e.value.status == shamr.SH_EINVAL
+    U = U0.copy()
+    h.write_dense(0, U)
+    ho = OHier(n, float(n), 0.25, 0.1, 1, beta=0)
+    ho.set_level0(U)
+    assert_bitwise(h.field_absmax(), ho.field_absmax(), "field maxima")
+    U[1, 3, 9, 12] = np.nan
+    h.write_dense(0, U)
+    ho.set_level0(U)
+    m = h.field_absmax()
+    assert np.isnan(m[1]) and not np.isnan(m[0])
+    assert_bitwise(m, ho.field_absmax(), "field maxima with a NaN")
+    h.close()
