@@ -71,7 +71,7 @@ from __future__ import annotations
 import numpy as np
 
 from .scalars import level_dt, level_dx, level_time, int_power, stage_fractions
-from .level import ko_coef, rk4_stage, ssprk3_stage
+from .level import check_rkn, ko_coef, rk4_stage, rkn4_stage, ssprk3_stage
 from .tagging import tag_cells
 from .energy import energy as _energy
 
@@ -292,6 +292,8 @@ class Hierarchy:
         # so fills then cover Pi too, and ghost shells are as deep as the widest stencil
         self.ko_order, self.ko_eps = ko_order, ko_eps
         self.depth = max(order, ko_order)
+        if integrator == 21:
+            check_rkn(alpha, ko_order)
         self.levels: list[Level] = []
         self.trace: list[tuple] = []
         self.tee_on = False
@@ -416,6 +418,9 @@ class Hierarchy:
             if self.integrator == 4:
                 L.acc, Y = rk4_stage(s, X, L.U, L.acc if s else None, eta_n, L.dt,
                                      1.0 / (L.dx * L.dx), self.alpha, self.lam, self.beta, self.order, ko)
+            elif self.integrator == 21:
+                L.acc, Y = rkn4_stage(s, X, L.U, L.acc if s else None, eta_n, L.dt, 1.0 / (L.dx * L.dx),
+                                      self.lam, self.beta, self.order)
             else:
                 Y = ssprk3_stage(s, X, L.U, eta_n, L.dt, 1.0 / (L.dx * L.dx), self.alpha, self.lam, self.beta,
                                  self.order, ko)
@@ -471,11 +476,12 @@ class Hierarchy:
                 L.tee = self._tee_zeros(L.M)
 
     def field_absmax(self) -> np.ndarray:
-        """max |U_c| over the valid cells of every level, per component (float64)."""
+        """max |U_c| over the valid cells of every level, per component (float64); NaN
+        if any of those values is NaN."""
         out = np.zeros(4)
-        for L in self.levels:
-            for c in range(4):
-                out[c] = max(out[c], float(np.max(np.abs(L.U[c][L.valid].astype(np.float64)))))
+        for c in range(4):
+            vals = [np.abs(L.U[c][L.valid].astype(np.float64)) for L in self.levels]
+            out[c] = np.max(np.concatenate([v.ravel() for v in vals] + [np.zeros(1)]))
         return out
 
     def tags(self, lev: int) -> np.ndarray:
@@ -516,6 +522,9 @@ class Hierarchy:
                 if self.integrator == 4:
                     acc, X = rk4_stage(s, X, S.U, acc, eta_n, S.dt, 1.0 / (S.dx * S.dx), self.alpha, self.lam,
                                        self.beta, self.order, ko)
+                elif self.integrator == 21:
+                    acc, X = rkn4_stage(s, X, S.U, acc, eta_n, S.dt, 1.0 / (S.dx * S.dx), self.lam, self.beta,
+                                        self.order)
                 else:
                     X = ssprk3_stage(s, X, S.U, eta_n, S.dt, 1.0 / (S.dx * S.dx), self.alpha, self.lam, self.beta,
                                      self.order, ko)

@@ -52,6 +52,25 @@ third-order strong-stability-preserving method, stage times eta_n + (0, 1, 1/2) 
     stage 2: U_b     = 3/4 U_n + 1/4 (U_a + h f(U_a))
     stage 3: U_{n+1} = 1/3 U_n + 2/3 (U_b + h f(U_b))
 
+RKN4 (integrator type 21, appendix E; appendix B's fourth-order Runge-Kutta-Nystrom
+method).  The paper names the method but prints no tableau; it is read as Nystrom's
+classical three-stage fourth-order scheme for y'' = f(t, y) (nodes c = (0, 1/2, 1),
+a_21 = 1/8, a_31 = 0, a_32 = 1/2, position weights (1/6, 1/3, 0), velocity weights
+(1/6, 2/3, 1/6); Hairer, Norsett and Wanner, Solving ODEs I, section II.14).  It applies
+to the EOM only when the acceleration does not depend on Pi, i.e. without friction
+(alpha = 0) and without dissipation; then with y = psi_n, v = Pi_n, h = dt and the
+acceleration a(psi) = lap psi - c_pot (r2 - 1) psi (in the storage type, at the stage
+time eta_n + c_s h):
+
+    stage 1: a1 = a(U_n);  acc_psi = (y + h v) + (h^2/6) a1;  acc_Pi = v + (h/6) a1
+             Y_psi = (y + (h/2) v) + (h^2/8) a1
+    stage 2: a2 = a(Y);    acc_psi = acc_psi + (h^2/3) a2;    acc_Pi = acc_Pi + (2h/3) a2
+             Y_psi = (y + h v) + (h^2/2) a2
+    stage 3: a3 = a(Y);    psi_{n+1} = acc_psi;               Pi_{n+1} = acc_Pi + (h/6) a3
+
+(the stage states carry Pi_n unchanged; acc is float64; the weights times powers of h
+are formed once in float64, see scalars.rkn4_weights).
+
 Mixed precision (FP32 storage): U_n, U_a, U_b are float32 and the right-hand side is
 evaluated in float32 (scalars rounded to float32 once); every update above is done in
 float64 from the promoted float32 values and rounded to float32 on store, while ``acc``
@@ -61,7 +80,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from .scalars import rk4_weights, stage_scalars
+from .scalars import rk4_weights, rkn4_weights, stage_scalars
 
 
 def lap7(u: np.ndarray, inv_dx2) -> np.ndarray:
@@ -144,6 +163,53 @@ def rhs(U: np.ndarray, inv_dx2: float, c_fric: float, c_pot: float, order: int =
     return K
 
 
+def accel(U: np.ndarray, inv_dx2: float, c_pot: float, order: int = 1) -> np.ndarray:
+    """Acceleration of psi1, psi2 without friction, lap psi - c_pot (r2 - 1) psi, as a
+    (2, ...) array in U's precision."""
+    t = U.dtype.type
+    p1, p2 = U[0], U[1]
+    r2 = p1 * p1 + p2 * p2
+    pot = t(c_pot) * (r2 - t(1.0))
+    return np.stack([lap(p1, inv_dx2, order) - pot * p1, lap(p2, inv_dx2, order) - pot * p2])
+
+
+def rkn4_stage(s: int, X: np.ndarray, Un: np.ndarray, acc, eta_n: float, dt: float, inv_dx2: float,
+               lam: float, beta: int, order: int = 1):
+    """Stage s (0-based) of RKN4 (friction-free EOM): returns (acc, Y), acc the float64
+    (4, ...) accumulator (psi then Pi), Y the next stage state (s < 2) or U_{n+1} (s = 2),
+    in Un's precision."""
+    st = Un.dtype
+    hh6, hh3, hh8, hh2, h6, h23, h2, h1 = rkn4_weights(dt)
+    _, _, cp = stage_scalars(eta_n, dt, s, 0.0, lam, beta, integrator=21)
+    a = accel(X, inv_dx2, cp, order).astype(np.float64)
+    y = Un[:2].astype(np.float64)
+    v = Un[2:].astype(np.float64)
+    Y = np.empty_like(Un)
+    if s == 0:
+        acc = np.concatenate([(y + h1 * v) + hh6 * a, v + h6 * a])
+        Y[:2] = ((y + h2 * v) + hh8 * a).astype(st)
+        Y[2:] = Un[2:]
+    elif s == 1:
+        acc = np.concatenate([acc[:2] + hh3 * a, acc[2:] + h23 * a])
+        Y[:2] = ((y + h1 * v) + hh2 * a).astype(st)
+        Y[2:] = Un[2:]
+    else:
+        Y[:2] = acc[:2].astype(st)
+        Y[2:] = (acc[2:] + h6 * a).astype(st)
+    return acc, Y
+
+
+def rkn4_step(U: np.ndarray, eta_n: float, dt: float, inv_dx2: float, lam: float, beta: int, fill=None,
+              order: int = 1) -> np.ndarray:
+    """One RKN4 step of the friction-free EOM; ``fill(s, X)`` as for ``rk4_step``."""
+    X, acc = U, None
+    for s in range(3):
+        if s > 0 and fill is not None:
+            fill(s, X)
+        acc, X = rkn4_stage(s, X, U, acc, eta_n, dt, inv_dx2, lam, beta, order)
+    return X
+
+
 def rk4_stage(s: int, X: np.ndarray, Un: np.ndarray, acc, eta_n: float, dt: float,
               inv_dx2: float, alpha: float, lam: float, beta: int, order: int = 1, ko=None):
     """Stage s (0-based) of classic RK4 in accumulator form.
@@ -169,6 +235,12 @@ def rk4_stage(s: int, X: np.ndarray, Un: np.ndarray, acc, eta_n: float, dt: floa
         acc = acc + h3 * k
         Y = U64 + h1 * k
     return acc, Y.astype(st)
+
+
+def check_rkn(alpha: float, ko_order: int):
+    """RKN4 needs an acceleration independent of Pi: no friction, no dissipation."""
+    if alpha != 0.0 or ko_order:
+        raise ValueError("RKN4 integrates the friction-free EOM only (alpha = 0, no dissipation)")
 
 
 def ssprk3_stage(s: int, X: np.ndarray, Un: np.ndarray, eta_n: float, dt: float, inv_dx2: float,
@@ -227,9 +299,15 @@ def run_single_level(U0: np.ndarray, nsteps: int, eta0: float, dt: float, dx: fl
     """
     from .scalars import level_time, stage_fractions
     stage_fractions(integrator)  # validates
-    step = rk4_step if integrator == 4 else ssprk3_step
     inv_dx2 = 1.0 / (dx * dx)
     ko = (ko_order, ko_coef(ko_order, ko_eps, dx)) if ko_order else None
+    if integrator == 21:
+        check_rkn(alpha, ko_order)
+
+        def step(U, eta, dt, inv_dx2, alpha, lam, beta, order=1, ko=None):
+            return rkn4_step(U, eta, dt, inv_dx2, lam, beta, order=order)
+    else:
+        step = rk4_step if integrator == 4 else ssprk3_step
     U = U0.copy()
     for k in range(nsteps):
         U = step(U, level_time(eta0, k, dt), dt, inv_dx2, alpha, lam, beta, order=order, ko=ko)

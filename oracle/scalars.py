@@ -5,7 +5,8 @@
   add from integers, so levels that align in time hold bit-identical times.
 * Classic RK4 (integrator type 4) evaluates the right-hand side at eta_n + c_s dt with
   c = (0, 1/2, 1/2, 1); the three-stage SSPRK3 (integrator types 3 and 10, the latter
-  the same method stored in fewer buffers) at c = (0, 1, 1/2).
+  the same method stored in fewer buffers) at c = (0, 1, 1/2); the fourth-order
+  Runge-Kutta-Nystrom method (integrator type 21) at c = (0, 1/2, 1).
 * The EOM (eq. EOM2 with lambda and the friction/potential exponents exposed) is
       dPi_i/deta = lap psi_i - (alpha/eta) Pi_i - lambda eta^beta psi_i (|psi|^2 - 1)
   so each stage needs c_fric = alpha / eta_s and c_pot = lambda * eta_s^beta, the
@@ -15,14 +16,17 @@ from __future__ import annotations
 
 RK4_C = (0.0, 0.5, 0.5, 1.0)
 SSP3_C = (0.0, 1.0, 0.5)
+RKN4_C = (0.0, 0.5, 1.0)
 
 
 def stage_fractions(integrator: int):
-    """c_s of the integrator: 4 = classic RK4, 3 or 10 = SSPRK3."""
+    """c_s of the integrator: 4 = classic RK4, 3 or 10 = SSPRK3, 21 = RKN4."""
     if integrator == 4:
         return RK4_C
     if integrator in (3, 10):
         return SSP3_C
+    if integrator == 21:
+        return RKN4_C
     raise ValueError(f"unknown integrator {integrator}")
 
 
@@ -55,3 +59,12 @@ def stage_scalars(eta_n: float, dt: float, s: int, alpha: float, lam: float, bet
 def rk4_weights(dt: float):
     """(dt/6, dt/3, dt/2, dt): the classic RK4 stage and accumulation weights."""
     return dt / 6.0, dt / 3.0, dt * 0.5, dt
+
+
+def rkn4_weights(dt: float):
+    """Weights of the RKN4 tableau times powers of dt, each formed once in float64:
+    (dt^2/6, dt^2/3, dt^2/8, dt^2/2) for the position and (dt/6, 2dt/3, dt/2, dt) for the
+    velocity and the stage positions."""
+    hh = dt * dt
+    return hh / 6.0, hh / 3.0, hh * 0.125, hh * 0.5, dt / 6.0, (2.0 * dt) / 3.0, dt * 0.5, dt
+

@@ -290,3 +290,19 @@ def test_per_field_shadow_level_closed_form():
         ref = P * abs(Ms[row, 0] - M0[row, 0]) * np.abs(_centred_cos(n0 // 2, L, k, 1.0)) * amp
         assert np.max(np.abs(tee[c][::2, ::2, ::2] - ref)) < 1e-12
     assert not tee[0].any() and not tee[2].any()
+
+
+def test_field_maxima_take_every_level_and_propagate_nan():
+    n0 = 8
+    U = random_state(n0, float(n0), 9)
+    h = Hierarchy(n0, float(n0), 0.25, 0.1, 1, beta=0)
+    h.set_level0(U)
+    h.set_layout(1, [(4, 4, 4, 11, 11, 11)])
+    h.levels[1].U[2][5, 6, 7] = 40.0                    # a fine value larger than any on level 0
+    m = h.field_absmax()
+    assert m[2] == 40.0
+    assert m[0] == max(np.max(np.abs(U[0])), np.max(np.abs(h.levels[1].U[0][h.levels[1].valid])))
+    h.levels[0].U[1][1, 2, 3] = np.nan
+    m = h.field_absmax()
+    assert np.isnan(m[1]) and not np.isnan(m[0]) and not np.isnan(m[3])
+
