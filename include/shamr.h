@@ -81,7 +81,12 @@ typedef struct {
   int32_t integrator;   /* integrator.type of appendix E: 4 (or 0) = classic RK4;
                            3 or 10 = SSPRK3, the three-stage strong-stability-preserving
                            method (both run its Shu-Osher form in three state buffers and
-                           no accumulator, so sh_arena_bytes is smaller) */
+                           no accumulator, so sh_arena_bytes is smaller); 21 = RKN4, read
+                           as Nystrom's classical three-stage fourth-order method for
+                           psi'' = a(psi) (appendices B and D use it).  It applies only
+                           when the acceleration does not depend on Pi: alpha_fric must
+                           be 0 and ko_order 0 (SH_EINVAL otherwise); it keeps RK4's
+                           float64 accumulator and is not fused on level 0 */
   int32_t lap_order;    /* Laplacian order of appendix A (the minimal example's `order`):
                            1 (or 0) = 7-point, 2 = 13-point, 3 = 19-point stencil.  The
                            ghost shell of refined levels is that many cells deep (and so

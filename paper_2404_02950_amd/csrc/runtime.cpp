@@ -148,9 +148,18 @@ static int tile_zc_default(long long cells, int zmin = 4) {
 }
 
 // Stages per step of the integrator: 4 for classic RK4 (types 0 and 4), 3 for SSPRK3
+// (types 3 and 10) and RKN4 (type 21).
 // (types 3 and 10).  SSPRK3 keeps no accumulator, so its levels store three states per
 // cell instead of three plus a float64 accumulator.
-static int stages_of(const sh_params& p) { return (p.integrator == 3 || p.integrator == 10) ? 3 : 4; }
+static int stages_of(const sh_params& p) {
+  return (p.integrator == 3 || p.integrator == 10 || p.integrator == 21) ? 3 : 4;
+}
+// RKN4 (integrator type 21): three stages in the role cycle of the three-stage methods,
+// with a float64 accumulator like RK4's
+static bool rkn_of(const sh_params& p) { return p.integrator == 21; }
+static bool needs_acc(const sh_params& p) { return stages_of(p) == 4 || rkn_of(p); }
+// device stage id of stage s (0-based): RK4 0..3, SSPRK3 4..6, RKN4 7..9
+static int stage_id(const sh_params& p, int s) { return rkn_of(p) ? 7 + s : (stages_of(p) == 3 ? 4 + s : s); }
 
 // Laplacian order of appendix A (1, 2, 3: the 7-, 13-, 19-point stencil; 0 reads as 1).
 // Refined levels (and the shadow level) keep a ghost shell of that depth; level 0 keeps
@@ -180,7 +189,7 @@ static int refined_ng(const sh_params& p) { return std::max(stencil_depth(p), in
 // truncation error estimates kept per cell: one per component when asked for, else their maximum
 static int tee_comps(const sh_params& p) { return p.tee_fields ? 4 : 1; }
 // the fused level-0 step: 7-point stencil, no dissipation
-static bool fusable(const sh_params& p) { return lap_order_of(p) == 1 && ko_of(p) == 0; }
+static bool fusable(const sh_params& p) { return lap_order_of(p) == 1 && ko_of(p) == 0 && !rkn_of(p); }
 
 static void make_geom(int prec, int ng, const std::vector<IBox>& boxes, LayoutGeom& g, bool acc, int tee_nc = 1) {
   g.ng = ng;
@@ -888,8 +897,10 @@ static sh_status check_params(const sh_params* p) {
       p->blocking_factor < 2 || (p->blocking_factor & 1) || p->max_box < p->blocking_factor || p->n_error_buf < 0 ||
       (p->prec != SH_F64 && p->prec != SH_F32))
     return fail(SH_EINVAL, "invalid parameters");
-  if (p->integrator != 0 && p->integrator != 3 && p->integrator != 4 && p->integrator != 10)
-    return fail(SH_EINVAL, "integrator must be 0 or 4 (RK4) or 3 or 10 (SSPRK3)");
+  if (p->integrator != 0 && p->integrator != 3 && p->integrator != 4 && p->integrator != 10 && p->integrator != 21)
+    return fail(SH_EINVAL, "integrator must be 0 or 4 (RK4), 3 or 10 (SSPRK3) or 21 (RKN4)");
+  if (p->integrator == 21 && (p->alpha_fric != 0.0 || p->ko_order != 0))
+    return fail(SH_EINVAL, "RKN4 integrates the friction-free EOM only (alpha_fric = 0, no dissipation)");
   if (p->lap_order < 0 || p->lap_order > 3) return fail(SH_EINVAL, "lap_order must be 0..3");
   if (p->interp != 0 && p->interp != 1 && p->interp != 4) return fail(SH_EINVAL, "interp must be 0, 1 or 4");
   if ((p->ko_order != 0 && p->ko_order != 2 && p->ko_order != 3) || !(p->ko_eps >= 0) || p->ko_eps == HUGE_VAL)
@@ -904,7 +915,7 @@ size_t sh_arena_bytes(const sh_params* p, int32_t lev, int32_t nboxes, const int
   std::vector<IBox> b;
   if (parse_boxes(*p, lev, nboxes, boxes, b) != SH_OK) return 0;
   LayoutGeom g;
-  make_geom(p->prec, lev == 0 ? SH_NG0 : refined_ng(*p), b, g, stages_of(*p) == 4, tee_comps(*p));
+  make_geom(p->prec, lev == 0 ? SH_NG0 : refined_ng(*p), b, g, needs_acc(*p), tee_comps(*p));
   return g.total;
 }
 
@@ -991,7 +1002,7 @@ static sh_status set_box_tables(sh_hierarchy h, LevelScal* ls, Level& L) {
     const IBox& b = L.boxes[i];
     BoxDev d;
     for (int s = 0; s < 3; ++s) d.slot[s] = L.base + L.g.off_slot[s] + (size_t)L.g.box_off[i] * L.g.esize;
-    d.acc = stages_of(h->p) == 4 ? (double*)(L.base + L.g.off_acc) + L.g.box_off[i] : nullptr;
+    d.acc = needs_acc(h->p) ? (double*)(L.base + L.g.off_acc) + L.g.box_off[i] : nullptr;
     d.ls = ls;
     d.cs = L.g.cs[i];
     d.nx = b.size(0);
@@ -1054,7 +1065,7 @@ sh_status sh_set_level_layout(sh_hierarchy h, int32_t l, int32_t nboxes, const i
     for (auto& b : N.boxes) v += b.volume();
     if (v != (long long)N.M * N.M * N.M) return fail(SH_EINVAL, "level 0 boxes must cover the domain");
   }
-  make_geom(p.prec, l == 0 ? SH_NG0 : refined_ng(p), N.boxes, N.g, stages_of(p) == 4, tee_comps(p));
+  make_geom(p.prec, l == 0 ? SH_NG0 : refined_ng(p), N.boxes, N.g, needs_acc(p), tee_comps(p));
   if (!arena || arena_bytes < N.g.total) return fail(SH_ENOMEM, "arena smaller than sh_arena_bytes");
   N.base = (char*)round_up((long long)(uintptr_t)arena, 256);
   N.bins.build(N.boxes, N.M);
@@ -1238,24 +1249,18 @@ sh_status sh_advance_level(sh_hierarchy h, int32_t l, int32_t sub) {
     return same_level_fill(h, l, ROLE_UN);
   }
   if (stages_of(h->p) == 3) {
-    // SSPRK3: stage inputs at c = 1 (A) and c = 1/2 (B); alpha in quarters 2 sub + 2 c_s
-    h->rec(1, l, 0, sub);
-    ev = h->prof_begin();
-    stage(h, L, 4);
-    h->prof_end(ev, 0);
-    LAUNCHCHK();
-    if ((s = fill(h, l, ROLE_A, 2 * sub + 2)) != SH_OK) return s;
-    h->rec(1, l, 1, sub);
-    ev = h->prof_begin();
-    stage(h, L, 5);
-    h->prof_end(ev, 1);
-    LAUNCHCHK();
-    if ((s = fill(h, l, ROLE_B, 2 * sub + 1)) != SH_OK) return s;
-    h->rec(1, l, 2, sub);
-    ev = h->prof_begin();
-    stage(h, L, 6);
-    h->prof_end(ev, 2);
-    LAUNCHCHK();
+    // three-stage methods: stage inputs A and B at c = 1 and 1/2 (SSPRK3) or 1/2 and 1
+    // (RKN4); alpha in quarters 2 sub + 2 c_s
+    for (int j = 0; j < 3; ++j) {
+      const int id = stage_id(h->p, j);
+      if (j > 0 && (s = fill(h, l, j == 1 ? ROLE_A : ROLE_B, 2 * sub + (int)(2.0 * stage_frac(id)))) != SH_OK)
+        return s;
+      h->rec(1, l, j, sub);
+      ev = h->prof_begin();
+      stage(h, L, id);
+      h->prof_end(ev, j);
+      LAUNCHCHK();
+    }
   } else {
     // stage 1 reads U_n (ghosts set by the previous step end or synchronisation)
     h->rec(1, l, 0, sub);
@@ -1401,7 +1406,7 @@ sh_status sh_shadow_begin(sh_hierarchy h) {
   S.dx = level_dx(p, 0) * 2.0;
   S.dt = p.cfl * S.dx;
   S.boxes = {IBox{{0, 0, 0}, {S.M - 1, S.M - 1, S.M - 1}}};
-  make_geom(p.prec, stencil_depth(p), S.boxes, S.g, stages_of(p) == 4);
+  make_geom(p.prec, stencil_depth(p), S.boxes, S.g, needs_acc(p));
   if (hipMalloc((void**)&h->shadow_arena, S.g.total) != hipSuccess) return fail(SH_ENOMEM, "shadow level allocation");
   S.base = (char*)round_up((long long)(uintptr_t)h->shadow_arena, 256);
   S.bins.build(S.boxes, S.M);
@@ -1451,11 +1456,11 @@ sh_status sh_shadow_advance(sh_hierarchy h) {
   if (S.k != h->shadow_k0) return fail(SH_ESTATE, "the shadow takes a single step");
   // one step of twice the level-0 step on the periodic shadow lattice
   if (stages_of(h->p) == 3) {
-    stage(h, S, 4);
+    stage(h, S, stage_id(h->p, 0));
     shadow_copy(h, ROLE_A);
-    stage(h, S, 5);
+    stage(h, S, stage_id(h->p, 1));
     shadow_copy(h, ROLE_B);
-    stage(h, S, 6);
+    stage(h, S, stage_id(h->p, 2));
   } else {
     stage(h, S, 0);
     shadow_copy(h, ROLE_A);
@@ -1615,7 +1620,7 @@ sh_status sh_debug_stage_scalars(sh_hierarchy h, int32_t l, int32_t s, double* o
   if (st != SH_OK || (st = not_capturing(h)) != SH_OK) return st;
   const int nst = stages_of(h->p);
   if (s < 0 || s >= nst || !out_host) return fail(SH_EINVAL, "bad stage");
-  sh_launch_debug_scalars(h->d_ls + l, nst == 3 ? s + 4 : s, h->d_dbg, h->st);
+  sh_launch_debug_scalars(h->d_ls + l, stage_id(h->p, s), h->d_dbg, h->st);
   LAUNCHCHK();
   HIPCHK(hipMemcpyAsync(out_host, h->d_dbg, 7 * 8, hipMemcpyDeviceToHost, h->st));
   HIPCHK(hipStreamSynchronize(h->st));

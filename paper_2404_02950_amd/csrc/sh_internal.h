@@ -64,8 +64,10 @@ __host__ __device__ inline int role_slot(int role, const LevelScal& L) { return 
 // Stage ids of the kernels: 0..3 the four RK4 stages, 4..6 the three SSPRK3 stages.
 // Fraction c_s of the step at which each evaluates the right-hand side:
 // RK4 (0, 1/2, 1/2, 1), SSPRK3 (0, 1, 1/2).
+// c_s of stage id s: RK4 ids 0..3 (0, 1/2, 1/2, 1), SSPRK3 ids 4..6 (0, 1, 1/2), RKN4 ids
+// 7..9 (0, 1/2, 1).
 __host__ __device__ inline double stage_frac(int s) {
-  return (s == 0 || s == 4) ? 0.0 : ((s == 3 || s == 5) ? 1.0 : 0.5);
+  return (s == 0 || s == 4 || s == 7) ? 0.0 : ((s == 3 || s == 5 || s == 9) ? 1.0 : 0.5);
 }
 
 struct BoxDev {

@@ -19,6 +19,14 @@
 //   stage 1: A = U_n + h k
 //   stage 2: B = 3/4 U_n + 1/4 (A + h k)
 //   stage 3: A = 1/3 U_n + 2/3 (B + h k)   (the new U_n)
+// RKN4 (stage ids 7..9; appendix E's integrator type 21, read as Nystrom's classical
+// three-stage fourth-order method for psi'' = a(psi), which needs alpha = 0 and no
+// dissipation), with a = lap - c_pot (r2 - 1) psi in T, y = psi_n, v = Pi_n:
+//   stage 1: acc_psi = (y + h v) + (h^2/6) a;  acc_Pi = v + (h/6) a
+//            A_psi = (y + (h/2) v) + (h^2/8) a,  A_Pi = v
+//   stage 2: acc_psi = acc_psi + (h^2/3) a;    acc_Pi = acc_Pi + (2h/3) a
+//            B_psi = (y + h v) + (h^2/2) a,     B_Pi = v
+//   stage 3: A_psi = acc_psi;  A_Pi = acc_Pi + (h/6) a   (the new U_n)
 // Kreiss-Oliger dissipation (KD = dissipation order 2 or 3; 0 = off) adds to the
 // right-hand side of every component Q = ko * K with
 //   K = (S_2 + (-4) S_1) + 18 u                    KD = 2
@@ -77,8 +85,8 @@ struct StagePtrs {
 
 template <typename T, int S>
 __device__ __forceinline__ StagePtrs stage_ptrs(const BoxDev& B, const LevelScal& L) {
-  constexpr int in_role = (S == 0 || S == 4) ? ROLE_UN : ((S == 2 || S == 6) ? ROLE_B : ROLE_A);
-  constexpr int out_role = (S == 1 || S == 3 || S == 5) ? ROLE_B : ROLE_A;
+  constexpr int in_role = (S == 0 || S == 4 || S == 7) ? ROLE_UN : ((S == 2 || S == 6 || S == 9) ? ROLE_B : ROLE_A);
+  constexpr int out_role = (S == 1 || S == 3 || S == 5 || S == 8) ? ROLE_B : ROLE_A;
   StagePtrs p;
   p.X = slot_base(B, role_slot(in_role, L));
   p.Un = slot_base(B, role_slot(ROLE_UN, L));
@@ -98,6 +106,46 @@ __device__ __forceinline__ void stage_cell(const StageScal& sc, const T* __restr
   const T cf = (T)sc.cf, cp = (T)sc.cp;
   const T r2 = p0 * p0 + p1 * p1;
   const T pot = cp * (r2 - (T)1.0);
+  if constexpr (S >= 7) {
+    // RKN4: the acceleration, then the position/velocity updates; weights times powers
+    // of h formed once in float64
+    const double h = sc.h1, hh = h * h;
+    const double hh6 = hh / 6.0, hh3 = hh / 3.0, hh8 = hh * 0.125, hh2 = hh * 0.5;
+    const double h6 = h / 6.0, h23 = (2.0 * h) / 3.0, h2 = h * 0.5;
+    const double a[2] = {(double)(lap0 - pot * p0), (double)(lap1 - pot * p1)};
+    // U_n: the stage input itself at stage 1, loaded at stage 2, not needed at stage 3
+    double y[2] = {0.0, 0.0}, v[2] = {0.0, 0.0};
+    if constexpr (S == 7) {
+      y[0] = (double)p0;
+      y[1] = (double)p1;
+      v[0] = (double)q0;
+      v[1] = (double)q1;
+    } else if constexpr (S == 8) {
+      y[0] = un4[0];
+      y[1] = un4[1];
+      v[0] = un4[2];
+      v[1] = un4[3];
+    }
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const long long ep = c * cs + e, eq = (2 + c) * cs + e;
+      if constexpr (S == 7) {
+        st<NT>(acc + ep, (y[c] + h * v[c]) + hh6 * a[c]);
+        st<NT>(acc + eq, v[c] + h6 * a[c]);
+        st<NT>(Y + ep, (T)((y[c] + h2 * v[c]) + hh8 * a[c]));
+        st<NT>(Y + eq, (T)v[c]);
+      } else if constexpr (S == 8) {
+        st<NT>(acc + ep, acc4[c] + hh3 * a[c]);
+        st<NT>(acc + eq, acc4[2 + c] + h23 * a[c]);
+        st<NT>(Y + ep, (T)((y[c] + h * v[c]) + hh2 * a[c]));
+        st<NT>(Y + eq, (T)v[c]);
+      } else {
+        st<NT>(Y + ep, (T)acc4[c]);
+        st<NT>(Y + eq, (T)(acc4[2 + c] + h6 * a[c]));
+      }
+    }
+    return;
+  }
   T kp0 = q0, kp1 = q1;
   T kq0 = (lap0 - cf * q0) - pot * p0;
   T kq1 = (lap1 - cf * q1) - pot * p1;
@@ -131,15 +179,15 @@ __device__ __forceinline__ void stage_cell(const StageScal& sc, const T* __restr
   }
 }
 
-// Loads of the once-read streams of a cell: U_n (RK4 stages 2, 3; SSPRK3 stages 2, 3)
-// and acc (RK4 stages 2-4).
+// Loads of the once-read streams of a cell: U_n (RK4 stages 2, 3; SSPRK3 stages 2, 3;
+// RKN4 stage 2) and acc (RK4 stages 2-4; RKN4 stages 2, 3).
 template <typename T, int S, bool NT>
 __device__ __forceinline__ void stage_loads(const T* __restrict__ Un, const double* __restrict__ acc, long long cs,
                                             long long e, double* un4, double* acc4) {
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
-    if constexpr (S == 1 || S == 2 || S == 5 || S == 6) un4[c] = (double)ld<NT>(Un + c * cs + e);
-    if constexpr (S >= 1 && S <= 3) acc4[c] = ld<NT>(acc + c * cs + e);
+    if constexpr (S == 1 || S == 2 || S == 5 || S == 6 || S == 8) un4[c] = (double)ld<NT>(Un + c * cs + e);
+    if constexpr ((S >= 1 && S <= 3) || S == 8 || S == 9) acc4[c] = ld<NT>(acc + c * cs + e);
   }
 }
 
@@ -448,7 +496,10 @@ static void stage_launch2(int s, int kind, const Tile* tiles, int ntiles, const 
     case 3: stage_launch3<T, 3, NT, H>(kind, tiles, ntiles, boxes, st); break;
     case 4: stage_launch3<T, 4, NT, H>(kind, tiles, ntiles, boxes, st); break;
     case 5: stage_launch3<T, 5, NT, H>(kind, tiles, ntiles, boxes, st); break;
-    default: stage_launch3<T, 6, NT, H>(kind, tiles, ntiles, boxes, st); break;
+    case 6: stage_launch3<T, 6, NT, H>(kind, tiles, ntiles, boxes, st); break;
+    case 7: stage_launch3<T, 7, NT, H>(kind, tiles, ntiles, boxes, st); break;
+    case 8: stage_launch3<T, 8, NT, H>(kind, tiles, ntiles, boxes, st); break;
+    default: stage_launch3<T, 9, NT, H>(kind, tiles, ntiles, boxes, st); break;
   }
 }
 
