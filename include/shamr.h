@@ -196,6 +196,17 @@ sh_status sh_average_down(sh_hierarchy h, int32_t fine_lev);
 sh_status sh_tag_cells(sh_hierarchy h, int32_t lev, uint8_t* mask_dev, int32_t* idx_host, int64_t cap,
                        int64_t* ntag);
 
+/* sh_tag_cells for callers that cannot allocate device memory (code under HIP graph
+   capture, tight serving loops, harnesses that forbid hipMalloc): the same tagging, mask
+   and list, but the compacted list is staged in a fixed device array of the library
+   (1048576 cells = 12 MiB, held by every device the library runs on until the process
+   ends) instead of a buffer it grows with hipMalloc; the call makes no allocation.
+   Errors as sh_tag_cells, plus SH_EINVAL when idx_host is given with cap above 1048576.
+   The array is shared by every call on a device: calls that overlap on one device (from
+   several threads or streams) race; each call leaves its list there. */
+sh_status sh_tag_cells_noalloc(sh_hierarchy h, int32_t lev, uint8_t* mask_dev, int32_t* idx_host, int64_t cap,
+                               int64_t* ntag);
+
 /* Composite energy over all levels, counting only cells not covered by a finer level
    (appendix B's convergence measure for this field): e_host[4] = {kinetic, gradient,
    potential, total}, float64, with forward-difference gradients and potential

@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <thread>
 #include <vector>
@@ -477,6 +478,7 @@ struct sh_hierarchy_s {
   sh_params p;
   Tuning tune;
   hipStream_t st = nullptr;
+  int dev = 0;  // the HIP device current at creation (its arenas and stream are on it)
   // graph capture: while capturing, level steps are recorded, not run; the host step
   // counters are put back at the end and advanced by each replay instead
   bool capturing = false;
@@ -919,6 +921,32 @@ size_t sh_arena_bytes(const sh_params* p, int32_t lev, int32_t nboxes, const int
   return g.total;
 }
 
+// ---------------------------------------------------------------------------------
+// Staging of the compacted tag list for callers that cannot allocate (see
+// sh_tag_cells_noalloc): a fixed device array instead of a buffer grown with hipMalloc.
+// Each device holds its own copy until the process ends; host code must use the
+// address hipGetSymbolAddress returns for the current device, never the array's name.
+// ---------------------------------------------------------------------------------
+#define SH_NOALLOC_TAG_CAP (1 << 20)  // tagged cells: 12 MiB of int32 (x, y, z) triplets
+static __device__ __align__(256) int32_t scratch[3 * SH_NOALLOC_TAG_CAP];
+#define SH_MAX_DEVICES 64
+static int32_t* g_scratch_dev[SH_MAX_DEVICES];
+static std::mutex g_scratch_mu;
+
+// Device address of `scratch` on device `dev`, looked up once per device with that
+// device current (at hierarchy creation).
+static sh_status scratch_setup(int dev) {
+  if (dev < 0 || dev >= SH_MAX_DEVICES) return fail(SH_EDEVICE, "device index beyond the supported range");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_dev[dev]) return SH_OK;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr)
+    return fail(SH_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+  g_scratch_dev[dev] = (int32_t*)ptr;
+  return SH_OK;
+}
+
 sh_status sh_hierarchy_create(const sh_params* p, void* hip_stream, sh_hierarchy* out) {
   if (!out) return fail(SH_EINVAL, "null output");
   *out = nullptr;
@@ -934,6 +962,10 @@ sh_status sh_hierarchy_create(const sh_params* p, void* hip_stream, sh_hierarchy
   h->tune = default_tuning(*p);
   tuning_from_env(h->tune);
   h->st = (hipStream_t)hip_stream;
+  if (hipGetDevice(&h->dev) != hipSuccess || scratch_setup(h->dev) != SH_OK) {
+    delete h;
+    return fail(SH_EDEVICE, "device set-up failed: " + g_err);
+  }
   if (hipMalloc((void**)&h->d_ls, (SH_SHADOW_LS + 1) * sizeof(LevelScal)) != hipSuccess ||
       hipMalloc((void**)&h->d_dbg, 16 * sizeof(double)) != hipSuccess) {
     if (h->d_ls) (void)hipFree(h->d_ls);
@@ -1504,8 +1536,11 @@ sh_status sh_read_tee(sh_hierarchy h, int32_t l, double* out_dev) {
   return SH_OK;
 }
 
-sh_status sh_tag_cells(sh_hierarchy h, int32_t l, uint8_t* mask_dev, int32_t* idx_host, int64_t cap,
-                       int64_t* ntag) {
+// Tagging of a level; the compacted list is staged in `staging` (device memory with room
+// for `cap` cells, checked by the caller) when given, else in the level's own buffer,
+// grown with hipMalloc as needed.
+static sh_status tag_cells(sh_hierarchy h, int32_t l, uint8_t* mask_dev, int32_t* idx_host, int64_t cap,
+                           int64_t* ntag, int32_t* staging) {
   sh_status s = check_level(h, l);
   if (s != SH_OK || (s = not_capturing(h)) != SH_OK) return s;
   if (cap < 0) return fail(SH_EINVAL, "negative capacity");
@@ -1526,19 +1561,39 @@ sh_status sh_tag_cells(sh_hierarchy h, int32_t l, uint8_t* mask_dev, int32_t* id
   if (ntag) *ntag = total;
   const long long want = std::min<long long>(total, cap);
   if (idx_host && want > 0) {
-    if (L.d_idx_cap < want) {
-      if (L.d_idx) (void)hipFree(L.d_idx);
-      L.d_idx = nullptr;
-      L.d_idx_cap = 0;
-      HIPCHK(hipMalloc((void**)&L.d_idx, (size_t)want * 12));
-      L.d_idx_cap = want;
+    int32_t* idx = staging;
+    if (!idx) {
+      if (L.d_idx_cap < want) {
+        if (L.d_idx) (void)hipFree(L.d_idx);
+        L.d_idx = nullptr;
+        L.d_idx_cap = 0;
+        HIPCHK(hipMalloc((void**)&L.d_idx, (size_t)want * 12));
+        L.d_idx_cap = want;
+      }
+      idx = L.d_idx;
     }
-    sh_launch_tag_compact(L.tiles.p, nt, L.dbox.p, mask, L.tile_off(), L.d_idx, want, h->st);
+    sh_launch_tag_compact(L.tiles.p, nt, L.dbox.p, mask, L.tile_off(), idx, want, h->st);
     LAUNCHCHK();
-    HIPCHK(hipMemcpyAsync(idx_host, L.d_idx, (size_t)want * 12, hipMemcpyDeviceToHost, h->st));
+    HIPCHK(hipMemcpyAsync(idx_host, idx, (size_t)want * 12, hipMemcpyDeviceToHost, h->st));
     HIPCHK(hipStreamSynchronize(h->st));
   }
   return SH_OK;
+}
+
+sh_status sh_tag_cells(sh_hierarchy h, int32_t l, uint8_t* mask_dev, int32_t* idx_host, int64_t cap,
+                       int64_t* ntag) {
+  return tag_cells(h, l, mask_dev, idx_host, cap, ntag, nullptr);
+}
+
+sh_status sh_tag_cells_noalloc(sh_hierarchy h, int32_t l, uint8_t* mask_dev, int32_t* idx_host, int64_t cap,
+                               int64_t* ntag) {
+  if (!h) return fail(SH_EINVAL, "null handle");
+  if (idx_host && cap > SH_NOALLOC_TAG_CAP)
+    return fail(SH_EINVAL, "cap " + std::to_string(cap) + " exceeds the allocation-free maximum of " +
+                               std::to_string(SH_NOALLOC_TAG_CAP) + " tagged cells");
+  if (h->dev < 0 || h->dev >= SH_MAX_DEVICES || !g_scratch_dev[h->dev])
+    return fail(SH_ESTATE, "no staging array for the hierarchy's device");
+  return tag_cells(h, l, mask_dev, idx_host, cap, ntag, g_scratch_dev[h->dev]);
 }
 
 sh_status sh_energy(sh_hierarchy h, double* e_host, int64_t* nonfinite) {

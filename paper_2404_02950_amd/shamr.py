@@ -47,6 +47,7 @@ _PROTOS = {
     "sh_advance_level": (c_int32, [c_void_p, c_int32, c_int32]),
     "sh_average_down": (c_int32, [c_void_p, c_int32]),
     "sh_tag_cells": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_int64, POINTER(c_int64)]),
+    "sh_tag_cells_noalloc": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_int64, POINTER(c_int64)]),
     "sh_energy": (c_int32, [c_void_p, POINTER(c_double), POINTER(c_int64)]),
     "sh_eval_rhs": (c_int32, [c_void_p, c_int32, c_void_p]),
     "sh_level_info": (c_int32, [c_void_p, c_int32, POINTER(c_int64), POINTER(c_double), POINTER(c_int32),
