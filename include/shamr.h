@@ -275,6 +275,15 @@ sh_status sh_hierarchy_destroy(sh_hierarchy h);
 /* Message of the last non-OK status returned on this thread (never NULL). */
 const char* sh_last_error(void);
 
+/* Debugging aid, not part of the level step (flags, 0 = off): bit 0 writes NaN into the
+   ghost shell of a buffer (all its layers, the components the fill carries) just before
+   every fill that is meant to set all of it (stage inputs between stages, U_n at the end
+   of a level step, sh_fill_ghosts, tagging), so that a ghost cell some stencil reads but
+   no fill writes turns valid cells into NaN instead of silently reusing stale values.
+   Results are unchanged when every read ghost is filled.  Errors: SH_EINVAL (unknown
+   flag), SH_ESTATE (while recording). */
+sh_status sh_set_debug(sh_hierarchy h, int32_t flags);
+
 /* Measurement support, not part of the level step: the HBM bandwidth a plain kernel
    reaches on this device, as the achievable ceiling beside the nominal peak.  One launch
    of `bytes` (a positive multiple of 16) with 16-byte nontemporal accesses, on

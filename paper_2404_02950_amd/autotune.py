@@ -15,16 +15,17 @@ from . import shamr
 
 # (fused_shape, fused_variant); footprints (x, y) of the shapes
 FUSED_SHAPES = {0: (32, 8), 1: (64, 4), 2: (32, 16), 3: (16, 8)}
-FUSED_VARIANTS = (0, 3, 4, 5, 6)
+FUSED_VARIANTS = (0, 3, 4, 5, 6, 7, 8)
 
 
 def candidates(boxes, params=None):
     """Launch shapes that apply to a level with these boxes:
     (kind, nontemporal, tile_z, fuse, fused_shape, fused_tile_z, fused_variant).  With the
     hierarchy's params, fused shapes are offered only where the fused step applies (the
-    7-point stencil without dissipation), and SSPRK3 skips the accumulator variants."""
+    7-point stencil without dissipation, not RKN4), and SSPRK3 skips the accumulator
+    variants."""
     out = [(8, 1, 0, 0, 0, 0, 0), (0, 1, 0, 0, 0, 0, 0)]
-    if params is not None and (params.lap_order > 1 or params.ko_order):
+    if params is not None and (params.lap_order > 1 or params.ko_order or params.integrator == 21):
         return out
     variants = FUSED_VARIANTS
     if params is not None and params.integrator in (3, 10):

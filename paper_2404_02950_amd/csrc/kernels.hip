@@ -246,6 +246,31 @@ __global__ __launch_bounds__(SH_BLOCK) void k_avgdown(const AvgSeg* __restrict__
   }
 }
 
+// ---------------------------------------------------------------------------------
+// Debug: NaN into the ghost shell (ng cells deep, the first ncomp components) of buffer
+// `role` of every box of a level, before a fill that is meant to set all of it; a ghost
+// cell a stencil reads but no fill writes then turns valid cells into NaN.  One block per
+// (box, plane of the padded box).
+// ---------------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(SH_BLOCK) void k_poison_ghosts(const BoxDev* __restrict__ boxes, int nplanes, int ng,
+                                                            int role, int ncomp) {
+  const int b = blockIdx.x / nplanes;
+  const int z = (int)(blockIdx.x % nplanes) - ng;
+  const BoxDev B = boxes[b];
+  if (z >= B.nz + ng) return;
+  T* U = (T*)slot_base(B, role_slot(role, *B.ls));
+  const T nan = __builtin_nan("");
+  const int wx = B.nx + 2 * ng, wy = B.ny + 2 * ng;
+  const bool zin = z >= 0 && z < B.nz;
+  for (int q = threadIdx.x; q < wx * wy; q += SH_BLOCK) {
+    const int x = q % wx - ng, y = q / wx - ng;
+    if (zin && x >= 0 && x < B.nx && y >= 0 && y < B.ny) continue;
+    const long long e = elem<T>(B, x, y, z);
+    for (int c = 0; c < ncomp; ++c) U[c * B.cs + e] = nan;
+  }
+}
+
 // Regrid: copy the 4 components of valid cells from the old layout of a level.
 template <typename T>
 __global__ __launch_bounds__(SH_BLOCK) void k_regrid_copy(const CopySeg* __restrict__ segs,
@@ -818,4 +843,14 @@ void sh_launch_absmax(int prec, const Tile* tiles, int ntiles, const BoxDev* box
     else hipLaunchKernelGGL(k_absmax<float>, dim3(nb), dim3(SH_BLOCK), 0, st, tiles, ntiles, boxes, part);
   }
   hipLaunchKernelGGL(k_absmax_final, dim3(1), dim3(256), 0, st, part, ntiles, out);
+}
+
+void sh_launch_poison_ghosts(int prec, const BoxDev* boxes, int nboxes, int nplanes, int ng, int role, int ncomp,
+                             hipStream_t st) {
+  if (nboxes == 0 || nplanes == 0) return;
+  const unsigned nb = (unsigned)nboxes * (unsigned)nplanes;
+  if (prec == 0)
+    hipLaunchKernelGGL(k_poison_ghosts<double>, dim3(nb), dim3(SH_BLOCK), 0, st, boxes, nplanes, ng, role, ncomp);
+  else
+    hipLaunchKernelGGL(k_poison_ghosts<float>, dim3(nb), dim3(SH_BLOCK), 0, st, boxes, nplanes, ng, role, ncomp);
 }

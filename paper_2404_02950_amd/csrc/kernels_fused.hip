@@ -94,7 +94,11 @@ constexpr int DPP_WAVE_SHL1 = 0x130;  // lane l takes lane l+1
 // two buffers that alternate between iterations (else in the iteration that uses them).
 // ZL: stages 1..3 read their z-1 neighbour from the previous iteration's LDS planes
 // instead of keeping it in registers (needs the double-buffered planes).
-template <typename T, bool NT, int TX, int TY, int ORDER, bool XDPP, bool ACCL, bool PF2, bool ZL, int NS>
+// UNG: the U_n values the updates of stages 1 and 2 need (planes i-1 and i-2, read two and
+// one iterations earlier by the same thread, so still in the caches) are read again from
+// memory instead of being carried in registers.
+template <typename T, bool NT, int TX, int TY, int ORDER, bool XDPP, bool ACCL, bool PF2, bool ZL, int NS,
+          bool UNG = false>
 __global__ __launch_bounds__((FusedShape<T, TX, TY, NS>::NBLK)) void k_fused_step(const Tile* __restrict__ tiles,
                                                                                 int ntiles,
                                                                                 const BoxDev* __restrict__ boxes) {
@@ -290,11 +294,11 @@ __global__ __launch_bounds__((FusedShape<T, TX, TY, NS>::NBLK)) void k_fused_ste
       if (j == 1) {
         un[0] = w0[0][0];
         un[1] = w0[0][1];
-        un[2] = q0p[0];
-        un[3] = q0p[1];
+        un[2] = UNG ? col[2 * cs + eat(i - 1)] : q0p[0];
+        un[3] = UNG ? col[3 * cs + eat(i - 1)] : q0p[1];
       } else if (j == 2) {
 #pragma unroll
-        for (int c = 0; c < 4; ++c) un[c] = u2[c];
+        for (int c = 0; c < 4; ++c) un[c] = UNG ? col[c * cs + eat(i - 2)] : u2[c];
       }
       constexpr int AST = ACCL ? TY * TX : 1;  // component stride of sacc
       double* ac = ACCL ? &sacc[(i - j) & 3][0][ay][ax] : &racc[NS == 4 ? j : 0][0];
@@ -374,11 +378,11 @@ __global__ __launch_bounds__((FusedShape<T, TX, TY, NS>::NBLK)) void k_fused_ste
 }
 
 template <typename T, bool NT, int TX, int TY, int NS, int ORDER, bool XDPP, bool ACCL, bool PF2 = false,
-          bool ZL = false>
+          bool ZL = false, bool UNG = false>
 static void fused_launch_shape(const Tile* tiles, int ntiles, const BoxDev* boxes, hipStream_t st) {
   using Sh = FusedShape<T, TX, TY, NS>;
-  hipLaunchKernelGGL((k_fused_step<T, NT, TX, TY, ORDER, XDPP, ACCL, PF2, ZL, NS>), dim3(ntiles), dim3(Sh::NBLK), 0,
-                     st, tiles, ntiles, boxes);
+  hipLaunchKernelGGL((k_fused_step<T, NT, TX, TY, ORDER, XDPP, ACCL, PF2, ZL, NS, UNG>), dim3(ntiles), dim3(Sh::NBLK),
+                     0, st, tiles, ntiles, boxes);
 }
 
 // variant: 0 = row-major threads, x neighbours through LDS, accumulator in registers;
@@ -386,8 +390,11 @@ static void fused_launch_shape(const Tile* tiles, int ntiles, const BoxDev* boxe
 // accumulator in LDS; 3 = ring-ordered threads, LDS neighbours, accumulator in LDS;
 // 4 = ring-ordered threads, LDS neighbours, accumulator in registers; 5 = variant 4 with
 // the two-iteration U_n prefetch, z-1 neighbours of stages 1..3 from LDS; 6 = variant 5
-// with the accumulator in LDS.  SSPRK3 has no accumulator: variants 2, 3 and 6 run as
-// 1, 4 and 5.
+// with the accumulator in LDS; 7 = ring-ordered threads, accumulator in LDS, z-1 from LDS,
+// U_n of stages 1 and 2 read again from memory (fewer registers: with the 32 x 16
+// footprint its fifteen wavefronts fit without spilling in FP64); 8 = variant 7 with the
+// two-iteration U_n prefetch.  SSPRK3 has no accumulator: variants 2, 3 and 6 run as 1,
+// 4 and 5, and 7 and 8 keep only the re-read of U_n.
 template <typename T, bool NT, int TX, int TY, int NS>
 static void fused_launch_variant(int variant, const Tile* tiles, int ntiles, const BoxDev* boxes, hipStream_t st) {
   constexpr bool AL = NS == 4;  // the LDS accumulator variants exist for RK4
@@ -398,7 +405,9 @@ static void fused_launch_variant(int variant, const Tile* tiles, int ntiles, con
     case 3: fused_launch_shape<T, NT, TX, TY, NS, 1, false, AL>(tiles, ntiles, boxes, st); break;
     case 4: fused_launch_shape<T, NT, TX, TY, NS, 1, false, false>(tiles, ntiles, boxes, st); break;
     case 5: fused_launch_shape<T, NT, TX, TY, NS, 1, false, false, true, true>(tiles, ntiles, boxes, st); break;
-    default: fused_launch_shape<T, NT, TX, TY, NS, 1, false, AL, true, true>(tiles, ntiles, boxes, st); break;
+    case 6: fused_launch_shape<T, NT, TX, TY, NS, 1, false, AL, true, true>(tiles, ntiles, boxes, st); break;
+    case 7: fused_launch_shape<T, NT, TX, TY, NS, 1, false, AL, false, true, true>(tiles, ntiles, boxes, st); break;
+    default: fused_launch_shape<T, NT, TX, TY, NS, 1, false, AL, true, true, true>(tiles, ntiles, boxes, st); break;
   }
 }
 

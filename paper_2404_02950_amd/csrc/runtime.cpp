@@ -268,21 +268,20 @@ struct Tuning {
   int fgrp = 1;  // fused tile order: 1 = groups of 32 tiles on square-ish patches, 0 = rows
 };
 
-// Measured best fused launch per storage type on MI355X at 512^3: ring-ordered threads,
-// x neighbours through LDS, U_n loaded two iterations ahead, z-1 neighbours of the later
-// stages from LDS; FP64 on the 32 x 8 footprint with the accumulator in registers (one
-// 10-wave workgroup per CU), FP32 on 32 x 16 with the accumulator in LDS (15 waves,
-// within 128 registers).
-// Fastest fused shapes measured at 512^3 on MI355X: RK4 FP64 32 x 8 variant 5, RK4 FP32
-// 32 x 16 variant 6; SSPRK3 (fewer registers per stage) 32 x 16 variant 5 in both.
+// Fastest fused launches measured at 512^3 on MI355X, all on the 32 x 16 footprint (15
+// wavefronts per workgroup, so at most 128 registers): RK4 FP64 variant 7 (accumulator in
+// LDS and U_n of stages 1 and 2 read again, 121 registers; 3.20 ms against 3.35 ms for
+// variant 5 on 32 x 8 with ten wavefronts), RK4 FP32 variant 6; SSPRK3 (fewer registers
+// per stage) variant 5 in both precisions.
 static Tuning default_tuning(const sh_params& p) {
   Tuning t;
-  t.fvar = 5;
+  t.fshape = 2;
   if (stages_of(p) == 3) {
-    t.fshape = 2;
+    t.fvar = 5;
   } else if (p.prec == SH_F32) {
-    t.fshape = 2;
     t.fvar = 6;
+  } else {
+    t.fvar = 7;
   }
   return t;
 }
@@ -306,7 +305,7 @@ static void tuning_from_env(Tuning& t) {
       if (k == "fuse" && (v == 0 || v == 4)) t.fuse = v;
       if (k == "fshape" && v >= 0 && v <= 3) t.fshape = v;
       if (k == "fzc" && v >= 0 && v <= 1024) t.fzc = v;
-      if (k == "fvar" && v >= 0 && v <= 6) t.fvar = v;
+      if (k == "fvar" && v >= 0 && v <= 8) t.fvar = v;
       if (k == "fgrp" && (v == 0 || v == 1)) t.fgrp = v;
     }
     pos = end + 1;
@@ -486,6 +485,7 @@ struct sh_hierarchy_s {
   // truncation error estimates (computed at every synchronisation when on) and the
   // tagging criterion: bit 0 plaquette winding, bit 1 estimate above its threshold
   // (te.crit[0] for one estimate per cell; te.scale[c] * estimate_c > te.crit[c] per field)
+  int debug = 0;  // bit 0: NaN into ghost shells before every complete fill
   bool tee_on = false;
   TeeSpec te = {{0.0, 0.0, 0.0, 0.0}, {1.0, 1.0, 1.0, 1.0}, 1, 0};
   int tag_mode = 1;
@@ -814,6 +814,18 @@ static sh_status build_links(sh_hierarchy h, int l) {
 // The deep copy carries all four components: the fused step computes its early stages
 // on the ghost ring, where it needs Pi as well as psi.
 // ncomp 0: the components the stencils read (psi, and Pi under dissipation).
+// Debug mode: before a fill that sets every ghost cell of buffer `role` (a stage input
+// between stages; U_n at a step's end), NaN into the shell for the components the fill
+// carries, so that a ghost a stencil reads but no fill writes shows up as NaN in valid
+// cells.
+static void poison_before_fill(sh_hierarchy h, int l, int role, int ncomp) {
+  if (!(h->debug & 1)) return;
+  Level& L = h->lev[l];
+  int nz = 0;
+  for (const BoxDev& b : L.hbox) nz = std::max(nz, b.nz);
+  sh_launch_poison_ghosts(h->p.prec, L.dbox.p, (int)L.hbox.size(), nz + 2 * L.g.ng, L.g.ng, role, ncomp, h->st);
+}
+
 static sh_status same_level_fill(sh_hierarchy h, int l, int role, int ncomp = 0, bool deep = true) {
   Level& L = h->lev[l];
   h->rec(2, l, role, 0);
@@ -842,6 +854,7 @@ static sh_status coarse_fine_fill(sh_hierarchy h, int l, int role, int anum) {
 
 // Ghost fill of a stage input (one layer suffices: only the state U_n is read deeper).
 static sh_status fill(sh_hierarchy h, int l, int role, int anum) {
+  poison_before_fill(h, l, role, (role == ROLE_UN && h->lev[l].a1d.nblocks()) ? 4 : fill_comps(h->p));
   sh_status s = same_level_fill(h, l, role, fill_comps(h->p), role == ROLE_UN);
   if (s != SH_OK) return s;
   return coarse_fine_fill(h, l, role, anum);
@@ -1278,6 +1291,7 @@ sh_status sh_advance_level(sh_hierarchy h, int32_t l, int32_t sub) {
     sh_launch_counter_inc(h->d_ls + l, 1, h->st);
     LAUNCHCHK();
     L.k += 1;
+    poison_before_fill(h, l, ROLE_UN, L.a1d.nblocks() ? 4 : fill_comps(h->p));
     return same_level_fill(h, l, ROLE_UN);
   }
   if (stages_of(h->p) == 3) {
@@ -1323,6 +1337,7 @@ sh_status sh_advance_level(sh_hierarchy h, int32_t l, int32_t sub) {
   sh_launch_counter_inc(h->d_ls + l, 1, h->st);
   LAUNCHCHK();
   L.k += 1;
+  poison_before_fill(h, l, ROLE_UN, L.a1d.nblocks() ? 4 : fill_comps(h->p));
   if ((s = same_level_fill(h, l, ROLE_UN)) != SH_OK) return s;
   if (l > 0 && sub == 0) return coarse_fine_fill(h, l, ROLE_UN, 2);
   return SH_OK;
@@ -1657,6 +1672,14 @@ sh_status sh_sync(sh_hierarchy h) {
   return SH_OK;
 }
 
+sh_status sh_set_debug(sh_hierarchy h, int32_t flags) {
+  sh_status s = not_capturing(h);
+  if (s != SH_OK) return s;
+  if (flags & ~1) return fail(SH_EINVAL, "unknown debug flags");
+  h->debug = flags;
+  return SH_OK;
+}
+
 sh_status sh_stream_probe(int32_t kind, const void* src, void* dst, int64_t bytes, void* hip_stream) {
   if (kind < 0 || kind > 2) return fail(SH_EINVAL, "stream probe kind must be 0 (read), 1 (write) or 2 (copy)");
   if (bytes <= 0 || (bytes & 15)) return fail(SH_EINVAL, "stream probe size must be a positive multiple of 16 bytes");
@@ -1777,7 +1800,7 @@ sh_status sh_set_tuning(sh_hierarchy h, int32_t kind, int32_t nontemporal, int32
   if (h->capturing) return not_capturing(h);
   if ((kind != 0 && kind != 4 && kind != 8) || (nontemporal != 0 && nontemporal != 1) || tile_z < 0 ||
       tile_z > 1024 || (fuse != 0 && fuse != 4) || (fused_shape < 0 || fused_shape > 3) || fused_tile_z < 0 ||
-      fused_tile_z > 1024 || fused_variant < 0 || fused_variant > 6)
+      fused_tile_z > 1024 || fused_variant < 0 || fused_variant > 8)
     return fail(SH_EINVAL, "bad tuning");
   HIPCHK(hipStreamSynchronize(h->st));
   h->tune.kind = kind;

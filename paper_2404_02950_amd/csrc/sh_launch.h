@@ -63,3 +63,8 @@ void sh_fused_footprint(int shape, int* tx, int* ty);
 // 16-byte words
 void sh_launch_stream(int kind, const void* src, void* dst, long long nwords, hipStream_t st);
 long long sh_stream_words_per_block();
+// debug: NaN into the ghost shell (ng deep, first ncomp components) of buffer `role` of
+// every box; nplanes = the deepest box's nz + 2 ng
+void sh_launch_poison_ghosts(int prec, const BoxDev* boxes, int nboxes, int nplanes, int ng, int role, int ncomp,
+                             hipStream_t st);
+

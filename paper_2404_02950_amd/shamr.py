@@ -86,6 +86,7 @@ _PROTOS = {
     "sh_set_tee_fields": (c_int32, [c_void_p, c_int32, POINTER(c_double), POINTER(c_double), c_int32]),
     "sh_field_absmax": (c_int32, [c_void_p, POINTER(c_double)]),
     "sh_stream_probe": (c_int32, [c_int32, c_void_p, c_void_p, c_int64, c_void_p]),
+    "sh_set_debug": (c_int32, [c_void_p, c_int32]),
 }
 
 EXPORTED = tuple(_PROTOS)
@@ -366,6 +367,10 @@ class Hierarchy:
     def shadow_end(self):
         _check(self.lib.sh_shadow_end(self.h))
 
+    def set_debug(self, poison_ghosts: bool = True):
+        """NaN into ghost shells before every complete fill (see sh_set_debug)."""
+        _check(self.lib.sh_set_debug(self.h, 1 if poison_ghosts else 0))
+
     def set_tee_fields(self, enable: bool = True, te_crit=(0.0, 0.0, 0.0, 0.0), scale=None, tag_mode: int = 3):
         """Per-field thresholds and modifier scales (see sh_set_tee_fields)."""
         crit = (c_double * 4)(*[float(v) for v in te_crit])
@@ -445,9 +450,9 @@ class Hierarchy:
         library's choice for the hierarchy's precision."""
         ssp = self.params.integrator in (3, 10)
         if fused_shape is None:
-            fused_shape = 2 if (ssp or self.params.prec == SH_F32) else 0
+            fused_shape = 2
         if fused_variant is None:
-            fused_variant = 6 if (self.params.prec == SH_F32 and not ssp) else 5
+            fused_variant = 5 if ssp else (6 if self.params.prec == SH_F32 else 7)
         _check(self.lib.sh_set_tuning(self.h, kind, nontemporal, tile_z, fuse, fused_shape, fused_tile_z,
                                       fused_variant))
 

@@ -83,8 +83,11 @@ def _regrid(hg, ho):
 
 
 @pytest.mark.timeout(600)
+@pytest.mark.parametrize("poison", [False, True])
 @pytest.mark.parametrize("case", list(CASES))
-def test_three_levels_at_workload_geometry(case):
+def test_three_levels_at_workload_geometry(case, poison):
+    # with poison, every complete ghost fill is preceded by NaN in the shell it sets
+    # (sh_set_debug): a ghost read but never written would show up as NaN here
     kw = dict(CASES[case])
     fuse = kw.pop("fuse", 4)
     prec = kw.pop("prec")
@@ -99,6 +102,8 @@ def test_three_levels_at_workload_geometry(case):
     hg.set_layout(0, [(0, 0, 0, N0 - 1, N0 - 1, N0 - 1)])
     if fuse != 4:
         hg.set_tuning(fuse=fuse)
+    if poison:
+        hg.set_debug(True)
     hg.write_dense(0, U0)
     hg.fill_ghosts(0)
     for lev, boxes in ((1, L1_BOXES), (2, L2_BOXES)):
@@ -127,3 +132,33 @@ def test_three_levels_at_workload_geometry(case):
     e, _ = hg.energy()
     np.testing.assert_allclose(e, ho.energy(), rtol=1e-12 if prec == 0 else 1e-6)
     hg.close()
+
+
+def test_poisoned_coarse_fine_ghosts_wait_for_the_synchronisation():
+    # the second sub-step of a fine level ends with its same-level copy; its coarse/fine
+    # ghosts are set by the synchronisation that follows, so in between they still hold
+    # the debug poison while every same-level ghost and every valid cell is finite
+    U0 = _initial()
+    hg = shamr.Hierarchy(N0, float(N0), 0.25, 0.1, 1.0, 2.0, 2, max_level=1, blocking_factor=BF, max_box=MAX_BOX)
+    hg.set_layout(0, [(0, 0, 0, N0 - 1, N0 - 1, N0 - 1)])
+    hg.write_dense(0, U0)
+    hg.fill_ghosts(0)
+    boxes = [(16, 16, 16, 31, 31, 31), (32, 16, 16, 47, 31, 31)]   # two boxes sharing a face
+    hg.set_layout(1, boxes)
+    hg.set_debug(True)
+    hg.advance(0)
+    hg.advance(1, 0)
+    hg.advance(1, 1)
+    g = hg.read_boxes(1, ghosts=True)
+    for b, a in zip(boxes, g):
+        psi = a[:2]
+        assert np.all(np.isfinite(psi[:, 1:-1, 1:-1, 1:-1])), "valid cells"
+        shared_x = 0 if b[0] == 32 else -1            # the face the two boxes share
+        assert np.all(np.isfinite(psi[:, 1:-1, 1:-1, shared_x])), "same-level ghosts"
+        assert np.isnan(psi[:, 1:-1, 1:-1, -1 - shared_x]).all(), "coarse/fine ghosts before the sync"
+    hg.average_down(1)
+    g = hg.read_boxes(1, ghosts=True)
+    for a in g:
+        assert np.all(np.isfinite(a[:2, 1:-1, 1:-1, :])) and np.all(np.isfinite(a[:2, :, 1:-1, 1:-1]))
+    hg.close()
+

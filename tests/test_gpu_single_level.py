@@ -201,7 +201,7 @@ def test_stage_kernel_launch_shapes_bitwise(kind, nt, zc):
     h.close()
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6, 7, 8])
 @pytest.mark.parametrize("shape,fzc,cuts", [(0, 64, None), (0, 16, [[32], [32], [24]]), (0, 7, [[32], [8, 40], None]),
                                           (1, 64, None), (1, 13, [None, [16], [40]]), (2, 256, None),
                                           (2, 9, [[32], [16], [24]]), (3, 64, None),

@@ -90,7 +90,7 @@ def test_fp32_storage_bitwise_with_fp32_oracle():
     h.close()
 
 
-@pytest.mark.parametrize("variant", [0, 1, 4, 5, 6])
+@pytest.mark.parametrize("variant", [0, 1, 4, 5, 6, 7, 8])
 @pytest.mark.parametrize("prec,shape,fzc,cuts", [(0, 0, 64, None), (0, 0, 7, [[32], [8, 40], []]),
                                                  (0, 1, 13, [[], [16], [40]]), (0, 2, 9, [[32], [16], [24]]),
                                                  (0, 3, 11, [[16], [8, 40], [24]]), (1, 2, 0, None),
