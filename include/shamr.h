@@ -275,6 +275,20 @@ sh_status sh_hierarchy_destroy(sh_hierarchy h);
 /* Message of the last non-OK status returned on this thread (never NULL). */
 const char* sh_last_error(void);
 
+/* Rebind the hierarchy to another HIP stream (its later work is queued there).  The
+   caller orders the switch: work still queued on the old stream must be complete or
+   waited for before the new stream touches the hierarchy (e.g. set up on one stream,
+   record an event, and join a batch on another once it has passed).  Used by the
+   ensemble server to set jobs up beside the running batch. */
+sh_status sh_set_stream(sh_hierarchy h, void* hip_stream);
+
+/* Set every level's step counter back to 0 (time eta0), queued on the stream, so that
+   a hierarchy can be reused for a new run of the same layout after sh_write_state of the
+   new initial state and sh_fill_ghosts (the ensemble server reuses the hierarchies of
+   finished jobs instead of allocating new ones).  Errors: SH_ESTATE (no levels, an active
+   shadow level, while recording). */
+sh_status sh_restart(sh_hierarchy h);
+
 /* Debugging aid, not part of the level step (flags, 0 = off): bit 0 writes NaN into the
    ghost shell of a buffer (all its layers, the components the fill carries) just before
    every fill that is meant to set all of it (stage inputs between stages, U_n at the end
@@ -347,6 +361,12 @@ sh_status sh_profile_read(sh_hierarchy h, double* ms, int64_t* counts);
    SH_ESTATE from sh_batch_advance if a member's layout changed
    since the batch was built. */
 sh_status sh_batch_create(int32_t njobs, const sh_hierarchy* jobs, sh_batch* out);
+/* Replace a batch's members (same rules as sh_batch_create) without releasing its device
+   tables: the new tables are copied in stream order, so launches queued before the call
+   still run on the old members, and the call waits for the stream only when a table
+   outgrows its buffer.  Graphs recorded from the batch before the call must not be
+   launched afterwards. */
+sh_status sh_batch_update(sh_batch b, int32_t njobs, const sh_hierarchy* jobs);
 sh_status sh_batch_advance(sh_batch b);
 sh_status sh_batch_destroy(sh_batch b);
 

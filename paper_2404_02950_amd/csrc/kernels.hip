@@ -24,6 +24,11 @@ __global__ void k_counter_inc(LevelScal* ls, int n) {
   if (i < n) ls[i].k += 1;
 }
 
+__global__ void k_counter_zero(LevelScal* ls, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) ls[i].k = 0;
+}
+
 // ---------------------------------------------------------------------------------
 // A1: same-level ghost copy (periodic images included) of the first ncomp components:
 // the psi pair on the stepping path, all four before a regrid interpolates from them.
@@ -854,3 +859,8 @@ void sh_launch_poison_ghosts(int prec, const BoxDev* boxes, int nboxes, int npla
   else
     hipLaunchKernelGGL(k_poison_ghosts<float>, dim3(nb), dim3(SH_BLOCK), 0, st, boxes, nplanes, ng, role, ncomp);
 }
+
+void sh_launch_counter_zero(LevelScal* ls, int n, hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(k_counter_zero, dim3(nblk(n, 64)), dim3(64), 0, st, ls, n);
+}
+

@@ -1672,6 +1672,24 @@ sh_status sh_sync(sh_hierarchy h) {
   return SH_OK;
 }
 
+sh_status sh_set_stream(sh_hierarchy h, void* hip_stream) {
+  sh_status s = not_capturing(h);
+  if (s != SH_OK) return s;
+  h->st = (hipStream_t)hip_stream;
+  return SH_OK;
+}
+
+sh_status sh_restart(sh_hierarchy h) {
+  sh_status s = not_capturing(h);
+  if (s != SH_OK) return s;
+  if (h->lev.empty()) return fail(SH_ESTATE, "no levels");
+  if (h->has_shadow) return fail(SH_ESTATE, "a shadow level is active");
+  for (Level& L : h->lev) L.k = 0;
+  sh_launch_counter_zero(h->d_ls, (int)h->lev.size(), h->st);
+  LAUNCHCHK();
+  return SH_OK;
+}
+
 sh_status sh_set_debug(sh_hierarchy h, int32_t flags) {
   sh_status s = not_capturing(h);
   if (s != SH_OK) return s;
@@ -1930,43 +1948,75 @@ sh_status sh_graph_destroy(sh_graph g) {
 // ---------------------------------------------------------------------------------
 // Batches: one RK4 step of level 0 of many single-level hierarchies per launch
 // ---------------------------------------------------------------------------------
+// Batch tables stay allocated while the batch lives: a new member list is planned on the
+// host and its tables are copied into the same device buffers in stream order (a launch
+// queued before the change still reads the old contents), staged through pinned host
+// buffers that rotate so the host waits for none of them in the common case.  Only a
+// table that outgrows its buffer makes the change wait for the stream.
+template <typename T>
+struct DevVec {
+  T* p = nullptr;
+  size_t n = 0, cap = 0;
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = cap = 0;
+  }
+};
+
+#define SH_BATCH_STAGES 4
+struct BatchStage {
+  char* buf = nullptr;
+  size_t cap = 0;
+  hipEvent_t done = nullptr;  // recorded after the copies out of buf
+  bool used = false;
+};
+
 struct sh_batch_s {
   std::vector<sh_hierarchy> jobs;
   hipStream_t st = nullptr;
   int prec = 0;
   Tuning tune;
-  DevArr<BoxDev> boxes;          // every job's level-0 boxes, job after job
-  DevArr<Tile> ftiles;           // fused-step tiles of the jobs that take the fused path
-  DevArr<Tile> wtiles, btiles;   // per-stage tiles of the other jobs
-  SegPlan<CopySeg, SH_WAVE> a1_stage;  // one-layer ghost copy of the per-stage jobs
-  SegPlan<CopySeg, SH_WAVE> a1_deep;   // full-depth ghost copy of every job (after the step)
-  DevArr<LevelScal*> counters;
+  DevVec<BoxDev> boxes;                // every job's level-0 boxes, job after job
+  DevVec<Tile> ftiles;                 // fused-step tiles of the jobs that take the fused path
+  DevVec<Tile> wtiles, btiles;         // per-stage tiles of the other jobs
+  DevVec<CopySeg> a1s_segs, a1d_segs;  // one-layer ghost copy of the per-stage jobs; full-depth
+  DevVec<SegBlock> a1s_blocks, a1d_blocks;  // ghost copy of every job (after the step)
+  DevVec<LevelScal*> counters;
   std::vector<long long> versions;  // each job's layout version when the batch was built
+  BatchStage stage[SH_BATCH_STAGES];
+  int next_stage = 0;
   void release() {
     boxes.release();
     ftiles.release();
     wtiles.release();
     btiles.release();
-    a1_stage.release();
-    a1_deep.release();
+    a1s_segs.release();
+    a1d_segs.release();
+    a1s_blocks.release();
+    a1d_blocks.release();
     counters.release();
+    for (BatchStage& g : stage) {
+      if (g.buf) (void)hipHostFree(g.buf);
+      if (g.done) (void)hipEventDestroy(g.done);
+      g = BatchStage();
+    }
   }
 };
 
-extern "C" {
+static std::vector<SegBlock> wave_blocks(const std::vector<long long>& ncell_per_seg) {
+  std::vector<SegBlock> b;
+  for (size_t i = 0; i < ncell_per_seg.size(); ++i)
+    for (long long s = 0; s < ncell_per_seg[i]; s += SH_WAVE) b.push_back(SegBlock{(int)i, (int)s});
+  return b;
+}
 
-sh_status sh_batch_create(int32_t njobs, const sh_hierarchy* jobs, sh_batch* out) {
-  if (!out || njobs < 1 || !jobs) return fail(SH_EINVAL, "bad batch arguments");
-  *out = nullptr;
-  sh_batch b = new (std::nothrow) sh_batch_s;
-  if (!b) return fail(SH_ENOMEM, "host allocation failed");
-  b->st = jobs[0]->st;
-  b->prec = jobs[0]->p.prec;
-  b->tune = jobs[0]->tune;
+// Plan the tables of a member list and copy them into the batch's buffers.
+static sh_status batch_set_jobs(sh_batch b, int njobs, const sh_hierarchy* jobs) {
   std::vector<BoxDev> boxes;
   std::vector<Tile> ft, wt, bt;
   std::vector<CopySeg> s1, sd;
-  std::vector<long long> n1, nd;
+  std::vector<long long> n1, nd, versions;
   std::vector<LevelScal*> ctr;
   // one fused tile depth for the whole batch, from all members' columns together
   long long columns = 0;
@@ -1980,19 +2030,12 @@ sh_status sh_batch_create(int32_t njobs, const sh_hierarchy* jobs, sh_batch* out
   const int batch_zc = fused_zc(b->tune, columns, nz_max);
   for (int j = 0; j < njobs; ++j) {
     sh_hierarchy h = jobs[j];
-    if (!h || h->lev.size() != 1 || h->st != b->st || h->p.prec != b->prec) {
-      delete b;
+    if (!h || h->lev.size() != 1 || h->st != b->st || h->p.prec != b->prec)
       return fail(SH_EINVAL, "batched jobs must be single-level hierarchies of one precision on one stream");
-    }
-    if (stages_of(h->p) != 4 || lap_order_of(h->p) != 1 || ko_of(h->p) != 0) {
-      delete b;
+    if (stages_of(h->p) != 4 || lap_order_of(h->p) != 1 || ko_of(h->p) != 0)
       return fail(SH_EINVAL, "batched jobs must use the RK4 integrator, the 7-point Laplacian and no dissipation");
-    }
-    if (h->capturing) {
-      delete b;
-      return not_capturing(h);
-    }
-    b->versions.push_back(h->layout_version);
+    if (h->capturing) return not_capturing(h);
+    versions.push_back(h->layout_version);
     const Level& L = h->lev[0];
     const int off = (int)boxes.size();
     boxes.insert(boxes.end(), L.hbox.begin(), L.hbox.end());
@@ -2025,17 +2068,100 @@ sh_status sh_batch_create(int32_t njobs, const sh_hierarchy* jobs, sh_batch* out
       nd.push_back(nc[i]);
     }
   }
+  const std::vector<SegBlock> b1 = wave_blocks(n1), bd = wave_blocks(nd);
+  // byte sizes of the tables, in a fixed order
+  struct Part {
+    void** dev;
+    size_t* n;
+    size_t* cap;
+    const void* src;
+    size_t count, elem;
+  };
+  Part parts[] = {
+      {(void**)&b->boxes.p, &b->boxes.n, &b->boxes.cap, boxes.data(), boxes.size(), sizeof(BoxDev)},
+      {(void**)&b->ftiles.p, &b->ftiles.n, &b->ftiles.cap, ft.data(), ft.size(), sizeof(Tile)},
+      {(void**)&b->wtiles.p, &b->wtiles.n, &b->wtiles.cap, wt.data(), wt.size(), sizeof(Tile)},
+      {(void**)&b->btiles.p, &b->btiles.n, &b->btiles.cap, bt.data(), bt.size(), sizeof(Tile)},
+      {(void**)&b->a1s_segs.p, &b->a1s_segs.n, &b->a1s_segs.cap, s1.data(), s1.size(), sizeof(CopySeg)},
+      {(void**)&b->a1s_blocks.p, &b->a1s_blocks.n, &b->a1s_blocks.cap, b1.data(), b1.size(), sizeof(SegBlock)},
+      {(void**)&b->a1d_segs.p, &b->a1d_segs.n, &b->a1d_segs.cap, sd.data(), sd.size(), sizeof(CopySeg)},
+      {(void**)&b->a1d_blocks.p, &b->a1d_blocks.n, &b->a1d_blocks.cap, bd.data(), bd.size(), sizeof(SegBlock)},
+      {(void**)&b->counters.p, &b->counters.n, &b->counters.cap, ctr.data(), ctr.size(), sizeof(LevelScal*)},
+  };
+  // grow the buffers that are too small (the stream must first finish with them)
+  bool grow = false;
+  size_t total = 0;
+  for (const Part& q : parts) {
+    grow = grow || q.count > *q.cap;
+    total += (q.count * q.elem + 255) / 256 * 256;
+  }
+  if (grow) {
+    HIPCHK(hipStreamSynchronize(b->st));
+    for (const Part& q : parts)
+      if (q.count > *q.cap) {
+        if (*q.dev) (void)hipFree(*q.dev);
+        *q.dev = nullptr;
+        *q.cap = 0;
+        const size_t c = std::max(q.count + q.count / 2, (size_t)64);
+        HIPCHK(hipMalloc(q.dev, c * q.elem));
+        *q.cap = c;
+      }
+  }
+  // stage the contents in the next pinned buffer (waiting only if its last copies are
+  // still queued) and copy them in stream order
+  BatchStage& g = b->stage[b->next_stage];
+  b->next_stage = (b->next_stage + 1) % SH_BATCH_STAGES;
+  if (g.used) HIPCHK(hipEventSynchronize(g.done));
+  if (g.cap < total) {
+    if (g.buf) (void)hipHostFree(g.buf);
+    g.buf = nullptr;
+    g.cap = 0;
+    const size_t c = std::max(total + total / 2, (size_t)1 << 16);
+    HIPCHK(hipHostMalloc((void**)&g.buf, c, hipHostMallocDefault));
+    g.cap = c;
+  }
+  if (!g.done) HIPCHK(hipEventCreateWithFlags(&g.done, hipEventDisableTiming));
+  size_t o = 0;
+  for (const Part& q : parts) {
+    const size_t bytes = q.count * q.elem;
+    *q.n = q.count;
+    if (bytes) {
+      std::memcpy(g.buf + o, q.src, bytes);
+      HIPCHK(hipMemcpyAsync(*q.dev, g.buf + o, bytes, hipMemcpyHostToDevice, b->st));
+    }
+    o += (bytes + 255) / 256 * 256;
+  }
+  HIPCHK(hipEventRecord(g.done, b->st));
+  g.used = true;
   b->jobs.assign(jobs, jobs + njobs);
-  if (b->boxes.upload(boxes) != hipSuccess || b->ftiles.upload(ft) != hipSuccess ||
-      b->wtiles.upload(wt) != hipSuccess || b->btiles.upload(bt) != hipSuccess ||
-      b->a1_stage.upload(s1, n1) != hipSuccess || b->a1_deep.upload(sd, nd) != hipSuccess ||
-      b->counters.upload(ctr) != hipSuccess) {
+  b->versions = versions;
+  return SH_OK;
+}
+
+extern "C" {
+
+sh_status sh_batch_create(int32_t njobs, const sh_hierarchy* jobs, sh_batch* out) {
+  if (!out || njobs < 1 || !jobs || !jobs[0]) return fail(SH_EINVAL, "bad batch arguments");
+  *out = nullptr;
+  sh_batch b = new (std::nothrow) sh_batch_s;
+  if (!b) return fail(SH_ENOMEM, "host allocation failed");
+  b->st = jobs[0]->st;
+  b->prec = jobs[0]->p.prec;
+  b->tune = jobs[0]->tune;
+  sh_status s = batch_set_jobs(b, njobs, jobs);
+  if (s != SH_OK) {
+    (void)hipStreamSynchronize(b->st);
     b->release();
     delete b;
-    return fail(SH_EDEVICE, "batch table upload failed");
+    return s;
   }
   *out = b;
   return SH_OK;
+}
+
+sh_status sh_batch_update(sh_batch b, int32_t njobs, const sh_hierarchy* jobs) {
+  if (!b || njobs < 1 || !jobs) return fail(SH_EINVAL, "bad batch arguments");
+  return batch_set_jobs(b, njobs, jobs);
 }
 
 sh_status sh_batch_advance(sh_batch b) {
@@ -2052,7 +2178,7 @@ sh_status sh_batch_advance(sh_batch b) {
     const int role_in[4] = {ROLE_UN, ROLE_A, ROLE_B, ROLE_A};
     for (int s = 0; s < 4; ++s) {
       if (s > 0) {
-        sh_launch_ghost_copy(prec, b->a1_stage.segs.p, b->a1_stage.blocks.p, b->a1_stage.nblocks(), b->boxes.p,
+        sh_launch_ghost_copy(prec, b->a1s_segs.p, b->a1s_blocks.p, (int)b->a1s_blocks.n, b->boxes.p,
                              role_in[s], 2, b->st);
         LAUNCHCHK();
       }
@@ -2065,7 +2191,7 @@ sh_status sh_batch_advance(sh_batch b) {
   sh_launch_counter_inc_list(b->counters.p, (int)b->counters.n, b->st);
   LAUNCHCHK();
   for (sh_hierarchy h : b->jobs) h->lev[0].k += 1;
-  sh_launch_ghost_copy(prec, b->a1_deep.segs.p, b->a1_deep.blocks.p, b->a1_deep.nblocks(), b->boxes.p, ROLE_UN, 4,
+  sh_launch_ghost_copy(prec, b->a1d_segs.p, b->a1d_blocks.p, (int)b->a1d_blocks.n, b->boxes.p, ROLE_UN, 4,
                        b->st);
   LAUNCHCHK();
   return SH_OK;

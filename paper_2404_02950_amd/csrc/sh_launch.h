@@ -25,6 +25,7 @@ void sh_launch_stage_hilap(int prec, int s, int kind, bool nt, int order, const 
 void sh_launch_rhs_hilap(int prec, int order, const Tile* tiles, int ntiles, const BoxDev* boxes,
                          const long long* out_off, double* out, hipStream_t st);
 void sh_launch_counter_inc(LevelScal* ls, int n, hipStream_t st);
+void sh_launch_counter_zero(LevelScal* ls, int n, hipStream_t st);
 void sh_launch_counter_inc_list(LevelScal* const* ls, int n, hipStream_t st);
 // chunks of up to SH_WAVE cells (one wavefront each)
 void sh_launch_ghost_copy(int prec, const CopySeg* segs, const SegBlock* chunks, int nchunks, const BoxDev* boxes,

@@ -87,6 +87,9 @@ _PROTOS = {
     "sh_field_absmax": (c_int32, [c_void_p, POINTER(c_double)]),
     "sh_stream_probe": (c_int32, [c_int32, c_void_p, c_void_p, c_int64, c_void_p]),
     "sh_set_debug": (c_int32, [c_void_p, c_int32]),
+    "sh_set_stream": (c_int32, [c_void_p, c_void_p]),
+    "sh_restart": (c_int32, [c_void_p]),
+    "sh_batch_update": (c_int32, [c_void_p, c_int32, POINTER(c_void_p)]),
 }
 
 EXPORTED = tuple(_PROTOS)
@@ -293,6 +296,13 @@ class Hierarchy:
         _check(self.lib.sh_read_state(self.h, lev, role, c_void_p(out.data_ptr()), 1, 0))
         return out
 
+    def write_device(self, lev: int, flat, role: int = ROLE_UN):
+        """Write a float64 device tensor holding the level's boxes in the dense box order
+        (no ghosts); queued on the hierarchy's stream, nothing allocated."""
+        if flat.numel() != self._count(lev, False) or flat.dtype != self.torch.float64 or not flat.is_cuda:
+            raise ValueError("state size, type or device does not match the layout")
+        _check(self.lib.sh_write_state(self.h, lev, role, c_void_p(flat.data_ptr()), 1, 0))
+
     def write_dense(self, lev: int, U: np.ndarray, role: int = ROLE_UN):
         """Write a dense (4, M, M, M) level array (valid cells of each box are taken)."""
         arrs = []
@@ -366,6 +376,18 @@ class Hierarchy:
 
     def shadow_end(self):
         _check(self.lib.sh_shadow_end(self.h))
+
+    def set_stream(self, stream):
+        """Queue this hierarchy's later work on ``stream`` (see sh_set_stream); the arenas
+        are marked as used there for torch's allocator."""
+        _check(self.lib.sh_set_stream(self.h, c_void_p(stream.cuda_stream)))
+        for a in self.arenas.values():
+            a.record_stream(stream)
+        self.stream = stream
+
+    def restart(self):
+        """Step counters back to 0 (see sh_restart)."""
+        _check(self.lib.sh_restart(self.h))
 
     def set_debug(self, poison_ghosts: bool = True):
         """NaN into ghost shells before every complete fill (see sh_set_debug)."""
@@ -497,6 +519,12 @@ class Batch:
 
     def advance(self):
         _check(self.lib.sh_batch_advance(self.b))
+
+    def update(self, hierarchies):
+        """New members, same device tables (see sh_batch_update)."""
+        self.members = list(hierarchies)
+        arr = (c_void_p * len(self.members))(*[m.h.value for m in self.members])
+        _check(self.lib.sh_batch_update(self.b, len(self.members), arr))
 
     def capture(self, nsteps: int) -> "Graph":
         """Record ``nsteps`` batch steps as one replayable graph (see sh_batch_capture)."""

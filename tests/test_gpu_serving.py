@@ -76,3 +76,56 @@ def test_nan_job_is_isolated():
             continue
         _, solo = serve.solo_runtime(j, stream, keep=True)
         assert_bitwise(j.result, solo, f"job {j.jid} next to a NaN job")
+
+
+def test_batch_update_keeps_every_job_exact():
+    # members change between steps (sh_batch_update rewrites the tables in stream order):
+    # every job still ends bit for bit where it would alone
+    import torch
+    stream = torch.cuda.Stream()
+    jobs = [_job(i, n, 9, shamr.SH_F64) for i, n in enumerate((32, 48, 64, 32))]
+    hs = [serve.make_hierarchy(j, stream) for j in jobs]
+    b = shamr.Batch(hs[:2])
+    for _ in range(3):
+        b.advance()
+    b.update(hs)                       # two more join
+    for _ in range(3):
+        b.advance()
+    b.update([hs[1], hs[2], hs[3]])    # the first leaves
+    for _ in range(3):
+        b.advance()
+    b.update([hs[2], hs[3]])
+    for _ in range(3):
+        b.advance()
+    b.close()
+    steps = {0: 6, 1: 9, 2: 9, 3: 9}
+    for j, h in zip(jobs, hs):
+        j.steps = steps[j.jid]
+        _, solo = serve.solo_runtime(j, stream, keep=True)
+        assert_bitwise(h.read_dense(0), solo, f"job {j.jid}")
+        assert h.level_info(0)["k"] == steps[j.jid]
+        h.close()
+
+
+def test_pooled_hierarchies_and_the_one_at_a_time_server():
+    # one class of jobs under a budget of one job: every job after the first reuses the
+    # previous job's hierarchy (new state written on the device, counter set back to 0);
+    # the batched and the one-at-a-time servers give every job its solo result
+    import torch
+    stream = torch.cuda.Stream()
+    jobs = [_job(i, 48, 5 + 3 * i, shamr.SH_F32, arrival=0.002 * i) for i in range(5)]
+    budget = jobs[0].nbytes
+    keep = {j.jid for j in jobs}
+    pool = serve.Pool()
+    done, _ = serve.serve(jobs, budget, stream=stream, keep_results=keep, pool=pool)
+    assert len(pool.all) == 1, "one hierarchy served every job"
+    batched = {j.jid: j.result for j in done}
+    serve._reset(jobs)
+    done, _ = serve.serve_fifo(jobs, stream=stream, keep_results=keep, graph_steps=4)
+    for j in done:
+        _, solo = serve.solo_runtime(j, stream, keep=True)
+        assert_bitwise(batched[j.jid], solo, f"job {j.jid} batched")
+        assert_bitwise(j.result, solo, f"job {j.jid} one at a time")
+        assert j.t_done >= j.t_admit >= j.arrival
+    pool.close()
+

@@ -108,9 +108,11 @@ def test_regrid_removes_a_level_above_the_size_cap():
     assert h2.layouts == [(1, small), (2, big), (3, small)]
 
 
-def test_fifo_timeline():
-    jobs = [serve.Job(jid=i, n=32, steps=1, prec=0, seed=0, arrival=a) for i, a in enumerate((0.0, 0.5, 0.6, 5.0))]
-    solo = {0: 1.0, 1: 1.0, 2: 1.0, 3: 0.5}
-    lat, end = serve.fifo_timeline(jobs, solo)
-    assert lat == pytest.approx({0: 1.0, 1: 1.5, 2: 2.4, 3: 0.5})
-    assert end == pytest.approx(5.5)
+def test_serving_report_percentiles_and_rate():
+    jobs = [serve.Job(jid=i, n=32, steps=10, prec=0, seed=0, arrival=a) for i, a in enumerate((0.0, 0.5, 1.0, 1.5))]
+    for j, lat in zip(jobs, (0.1, 0.2, 0.3, 1.3)):
+        j.t_done = j.arrival + lat
+    r = serve._report(jobs, 2.8)
+    assert r["p50_s"] == pytest.approx(0.25)
+    assert r["p99_s"] == pytest.approx(0.3 + 0.97 * 1.0)
+    assert r["cell_updates_per_s"] == pytest.approx(4 * 32 ** 3 * 4 * 10 / 2.8)
