@@ -72,30 +72,55 @@ def _run(cmd, verbose):
     return r
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every source (in parallel) and link libshamr.so; returns the library path."""
+# Host-code sanitizer build (a debugging aid, run on the CPU only): AddressSanitizer and
+# UndefinedBehaviorSanitizer on the host side of every source (the device code is built as
+# usual), all host code compiled by ROCm's clang so that one sanitizer runtime serves it.
+SAN_BUILD = os.path.join(PKG, "_build_san")
+SAN_LIB = os.path.join(SAN_BUILD, "libshamr_san.so")
+SAN_HIP = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+           "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-g"]
+
+
+def _clangxx() -> str:
+    c = os.path.join(os.path.dirname(os.path.realpath(_hipcc())), "..", "llvm", "bin", "clang++")
+    return os.path.realpath(c) if os.path.exists(c) else "/opt/rocm/llvm/bin/clang++"
+
+
+def build(verbose: bool = False, sanitize: bool = False) -> str:
+    """Compile every source (in parallel) and link libshamr.so; returns the library path.
+    With ``sanitize``, build the host-sanitizer variant in _build_san/ instead."""
     from concurrent.futures import ThreadPoolExecutor
-    os.makedirs(BUILD, exist_ok=True)
+    out_dir = SAN_BUILD if sanitize else BUILD
+    lib = SAN_LIB if sanitize else LIB
+    os.makedirs(out_dir, exist_ok=True)
     hipcc = _hipcc()
     inc = ["-I", INCLUDE, "-I", CSRC]
     cmds, objs = [], []
     for src in HIP_SOURCES:
-        obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
+        obj = os.path.join(out_dir, os.path.splitext(src)[0] + ".o")
         lang = ["-x", "hip"] if src.endswith(".cpp") else []
-        cmds.append([hipcc] + HIP_FLAGS + inc + lang + ["-c", os.path.join(CSRC, src), "-o", obj])
+        extra = SAN_HIP if sanitize else []
+        cmds.append([hipcc] + HIP_FLAGS + extra + inc + lang + ["-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
     for src in HOST_SOURCES:
-        obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-        cmds.append(["g++"] + HOST_FLAGS + inc + ["-c", os.path.join(CSRC, src), "-o", obj])
+        obj = os.path.join(out_dir, os.path.splitext(src)[0] + ".o")
+        if sanitize:
+            cmds.append([_clangxx()] + HOST_FLAGS + ["-fsanitize=address,undefined", "-fno-omit-frame-pointer", "-g"]
+                        + inc + ["-c", os.path.join(CSRC, src), "-o", obj])
+        else:
+            cmds.append(["g++"] + HOST_FLAGS + inc + ["-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
     with ThreadPoolExecutor(max_workers=max(1, min(len(cmds), os.cpu_count() or 1))) as ex:
         for f in [ex.submit(_run, c, verbose) for c in cmds]:
             f.result()
-    tmp = LIB + ".tmp"
-    _run([hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs, verbose)
-    os.replace(tmp, LIB)
-    return LIB
+    tmp = lib + ".tmp"
+    link = [hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs
+    if sanitize:
+        link += ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined", "-shared-libsan"]
+    _run(link, verbose)
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":
-    print(build(verbose=True))
+    print(build(verbose=True, sanitize="--sanitize" in sys.argv[1:]))

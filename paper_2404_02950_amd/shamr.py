@@ -96,17 +96,21 @@ EXPORTED = tuple(_PROTOS)
 _lib = None
 
 
-def load(path: str = LIB_PATH):
-    """Load libshamr.so (raises if it has not been built)."""
+def load(path: str = None):
+    """Load libshamr.so (raises if it has not been built).  SHAMR_LIB in the environment
+    names another build of the same library (the host-sanitizer build)."""
     global _lib
     if _lib is not None:
         return _lib
+    path = path or os.environ.get("SHAMR_LIB") or LIB_PATH
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is missing: build it first (python -m paper_2404_02950_amd.build_lib)")
     # torch first: the library then binds to the HIP runtime torch has loaded (same soname)
     # instead of loading the system copy beside it, which would leave two HIP runtimes,
-    # each with its own view of the device, in one process
-    import torch  # noqa: F401
+    # each with its own view of the device, in one process (the host-sanitizer build runs
+    # on the CPU only and leaves torch out)
+    if not os.environ.get("SHAMR_LIB"):
+        import torch  # noqa: F401
     lib = ctypes.CDLL(path)
     for name, (res, args) in _PROTOS.items():
         fn = getattr(lib, name)

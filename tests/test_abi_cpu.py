@@ -27,7 +27,7 @@ def test_library_exports_every_declared_symbol(shamr):
     hdr = open(os.path.join(ROOT, "include", "shamr.h")).read()
     declared = set(re.findall(r"^\s*(?:[\w\*]+\s+)+\**(sh_\w+)\s*\(", hdr, flags=re.M))
     assert len(declared) >= 20
-    lib = ctypes.CDLL(shamr.LIB_PATH)
+    lib = shamr.load()
     for name in declared:
         assert hasattr(lib, name), name
     assert declared == set(shamr.EXPORTED)
