@@ -12,6 +12,8 @@ from __future__ import annotations
 
 import time
 
+import numpy as np
+
 from . import shamr
 
 
@@ -36,19 +38,59 @@ def normalised_tee_scales(h):
     return [1.0 / v if v > 0.0 else 1.0 for v in m]
 
 
+def carried_tags(idx_fine, M_coarse: int, grow: int = 1):
+    """Tags of level l+1 carried down to level l: each tagged cell's coarse parent and the
+    parents' neighbours within ``grow`` cells (periodic, M_coarse cells per axis), as a
+    sorted (n, 3) int32 list of (x, y, z).  Added to level l's own tags, they make the
+    rebuilt level l+1 extend at least (grow + n_error_buf) coarse cells beyond the parent
+    of every tag that level l+1 holds now, which with the default n_error_buf = 2 and one
+    cell of growth covers that tag's own buffer and the nesting gap of half a blocking
+    factor (8) that the level l+2 box refining it needs."""
+    idx = np.asarray(idx_fine, dtype=np.int64).reshape(-1, 3)
+    if idx.size == 0:
+        return np.zeros((0, 3), np.int32)
+    c = np.unique(idx // 2, axis=0)
+    r = np.arange(-grow, grow + 1)
+    off = np.stack(np.meshgrid(r, r, r, indexing="ij"), -1).reshape(-1, 3)
+    out = (c[:, None, :] + off[None, :, :]).reshape(-1, 3) % M_coarse
+    return np.unique(out, axis=0).astype(np.int32)
+
+
+def merge_tags(a, b):
+    """Union of two (n, 3) tag lists."""
+    a = np.asarray(a, np.int32).reshape(-1, 3)
+    b = np.asarray(b, np.int32).reshape(-1, 3)
+    if not len(b):
+        return a
+    return np.unique(np.concatenate([a, b]), axis=0).astype(np.int32)
+
+
 def regrid(h, max_level: int, layout_for=None, efficiency: float = 0.7, max_level_bytes: int | None = None,
-           log=None, timing: dict | None = None, start: int = 1):
+           log=None, timing: dict | None = None, start: int = 1, carry: bool = True):
     """Rebuild levels start..max_level from tags (levels below start are kept).
 
     ``layout_for(lev, ntag, idx)`` may return the boxes of level lev+1; by default the
-    tags are clustered by the library (Berger-Rigoutsos).  ``max_level_bytes`` caps the
-    device arena of any one new level: a layout above it is not built, and that level
-    and every finer one are removed instead (a field that has blown up tags nearly every
-    plaquette, and refining all of it would not fit in memory).  ``timing``, if given,
-    accumulates host seconds spent in tagging, clustering and layout changes.  Returns
-    the tag counts.
+    tags are clustered by the library (Berger-Rigoutsos).  With ``carry``, the tags of
+    every existing finer level are taken first, on the hierarchy as it stands, and each
+    level's tags are joined by those of the level above it (``carried_tags``): levels are
+    rebuilt coarsest first, and a level l+1 built from level l's tags alone could be too
+    small to nest the refinement of a tag level l+1 holds near its edge, which clustering
+    would then drop.  ``max_level_bytes`` caps the device arena of any one new level: a
+    layout above it is not built, and that level and every finer one are removed instead
+    (a field that has blown up tags nearly every plaquette, and refining all of it would
+    not fit in memory).  ``timing``, if given, accumulates host seconds spent in tagging,
+    clustering and layout changes.  Returns the tag counts (each level's own).
     """
     counts = []
+    carried = {}
+    if carry and layout_for is None:
+        t0 = time.perf_counter()
+        for lev in range(max(1, start), min(h.num_levels(), max_level)):
+            _, idx = h.tag(lev)
+            if idx is not None and len(idx):
+                carried[lev] = idx
+        if timing is not None:
+            timing["tag"] = timing.get("tag", 0.0) + time.perf_counter() - t0
     for lev in range(max(0, start - 1), max_level):
         if lev >= h.num_levels():
             break
@@ -56,6 +98,8 @@ def regrid(h, max_level: int, layout_for=None, efficiency: float = 0.7, max_leve
         ntag, idx = h.tag(lev)
         t1 = time.perf_counter()
         counts.append(ntag)
+        if lev + 1 in carried:
+            idx = merge_tags(idx, carried_tags(carried[lev + 1], h.params.n0 << lev))
         boxes = layout_for(lev, ntag, idx) if layout_for is not None else h.cluster(lev, idx, efficiency)
         t2 = time.perf_counter()
         if boxes and max_level_bytes is not None:

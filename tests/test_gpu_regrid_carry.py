@@ -1,0 +1,82 @@
+"""The driver's regrid with tags carried down from finer levels, on the GPU: layouts obey
+the nesting rules, the rebuilt level 1 holds every carried tag with its buffer, and the
+state after the regrid and after further coarse steps equals the oracle's on the same
+layouts bit for bit (section II.C: tagging, clustering, regrid; levels rebuilt coarsest
+first)."""
+import numpy as np
+import pytest
+
+from oracle.amr import Hierarchy as OHier, boxes_mask
+from oracle.layout import check_layout
+from synth import string_loop_state
+
+pytestmark = pytest.mark.gpu
+
+shamr = pytest.importorskip("paper_2404_02950_amd.shamr")
+from paper_2404_02950_amd import driver  # noqa: E402
+from gpu_util import assert_bitwise  # noqa: E402
+
+N0, BF, MAX_BOX, NBUF = 32, 8, 64, 2
+L1_BOXES = [(0, 8, 8, 63, 39, 39), (16, 40, 16, 31, 55, 31), (40, 48, 40, 55, 55, 47)]
+L2_BOXES = [(16, 24, 24, 79, 55, 47), (80, 24, 24, 95, 39, 39)]
+
+
+def _compare(hg, ho, what):
+    assert hg.num_levels() == len(ho.levels), what
+    for lev, L in enumerate(ho.levels):
+        v = L.valid
+        assert_bitwise(hg.read_dense(lev)[:, v], L.U[:, v], f"{what}, level {lev}")
+
+
+@pytest.mark.timeout(300)
+def test_carried_regrid_on_the_gpu_matches_the_oracle_on_its_layouts():
+    U0 = string_loop_state(N0, float(N0), seed=7, nloops=2, rmin=5.0, rmax=7.0, taper_in=1.5, taper_out=8.5)
+    ho = OHier(N0, float(N0), 0.25, 0.1, 2, beta=2, dtype=np.float64)
+    ho.set_level0(U0)
+    hg = shamr.Hierarchy(N0, float(N0), 0.25, 0.1, 1.0, 2.0, 2, max_level=2, blocking_factor=BF,
+                         max_box=MAX_BOX, n_error_buf=NBUF, prec=shamr.SH_F64)
+    hg.set_layout(0, [(0, 0, 0, N0 - 1, N0 - 1, N0 - 1)])
+    hg.write_dense(0, U0)
+    hg.fill_ghosts(0)
+    for lev, boxes in ((1, L1_BOXES), (2, L2_BOXES)):
+        ho.set_layout(lev, boxes)
+        hg.set_layout(lev, boxes)
+    for _ in range(2):
+        driver.coarse_step(hg)
+        ho.coarse_step()
+    _compare(hg, ho, "before the regrid")
+    z, y, x = np.nonzero(ho.tags(1))
+    carried = driver.carried_tags(np.stack([x, y, z], 1), N0)
+    made = {}
+    cluster = hg.cluster
+
+    def recording_cluster(lev, idx, efficiency=0.7):
+        boxes = cluster(lev, idx, efficiency)
+        made[lev + 1] = boxes
+        return boxes
+
+    hg.cluster = recording_cluster
+    driver.regrid(hg, 2, carry=True)
+    assert 1 in made and made[1], "level 1 must be rebuilt"
+    valid0 = np.ones((N0,) * 3, bool)
+    assert not check_layout(made[1], 2 * N0, valid0, BF, MAX_BOX)
+    # every carried coarse cell and its buffer lies under the rebuilt level 1
+    cover = boxes_mask(made[1], 2 * N0)
+    for cx, cy, cz in carried:
+        for dz in range(-NBUF, NBUF + 1):
+            for dy in range(-NBUF, NBUF + 1):
+                for dx in range(-NBUF, NBUF + 1):
+                    fx, fy, fz = [2 * ((c + d) % N0) for c, d in ((cx, dx), (cy, dy), (cz, dz))]
+                    assert cover[fz, fy, fx], (cx, cy, cz)
+    ho.set_layout(1, made[1])
+    if made.get(2):
+        assert not check_layout(made[2], 4 * N0, boxes_mask(made[1], 2 * N0), BF, MAX_BOX)
+        ho.set_layout(2, made[2])
+    else:
+        ho.set_layout(2, [])
+    _compare(hg, ho, "after the regrid")
+    for step in range(2):
+        driver.coarse_step(hg)
+        ho.coarse_step()
+        _compare(hg, ho, f"coarse step {step + 1} after the regrid")
+    hg.close()

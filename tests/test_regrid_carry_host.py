@@ -1,0 +1,62 @@
+"""Host-side check of the driver's tag carry (no GPU): levels are rebuilt coarsest first,
+so a tag that level 1 holds away from everything level 0 tags would lose its refinement
+(the rebuilt level 1 would not contain it, and clustering drops tags whose refinement
+cannot nest); carried down to level 0 it keeps it.  Layouts come from the library's
+Berger-Rigoutsos (host code) and are checked with the oracle's layout rules."""
+import numpy as np
+import pytest
+
+from oracle.amr import boxes_mask, coarsen_mask
+from oracle.layout import check_layout
+from paper_2404_02950_amd import driver
+
+shamr = pytest.importorskip("paper_2404_02950_amd.shamr")
+
+M0, BF, MAX_BOX, NBUF = 32, 8, 64, 2
+
+
+def _blob(lo, hi):
+    r = [np.arange(a, b + 1) for a, b in zip(lo, hi)]
+    x, y, z = np.meshgrid(*r, indexing="ij")
+    return np.stack([x.ravel(), y.ravel(), z.ravel()], 1).astype(np.int32)
+
+
+def _rebuild(carry):
+    t0 = _blob((10, 10, 10), (13, 13, 13))            # level-0 tags (coarse cells)
+    t1 = _blob((44, 24, 24), (46, 26, 26))            # tags level 1 holds now, far from t0's refinement
+    level0 = [(0, 0, 0, M0 - 1, M0 - 1, M0 - 1)]
+    tags0 = driver.merge_tags(t0, driver.carried_tags(t1, M0)) if carry else t0
+    l1 = shamr.cluster_boxes(M0, level0, tags0, BF, MAX_BOX, NBUF)
+    l2 = shamr.cluster_boxes(2 * M0, l1, t1, BF, MAX_BOX, NBUF) if l1 else []
+    return t1, l1, l2
+
+
+def test_carried_tags_are_the_grown_coarse_parents():
+    fine = np.array([[0, 0, 0], [1, 1, 1], [9, 4, 63]], np.int32)
+    c = driver.carried_tags(fine, 32, grow=1)
+    want = set()
+    for px, py, pz in {(0, 0, 0), (4, 2, 31)}:
+        for dx in (-1, 0, 1):
+            for dy in (-1, 0, 1):
+                for dz in (-1, 0, 1):
+                    want.add(((px + dx) % 32, (py + dy) % 32, (pz + dz) % 32))
+    assert set(map(tuple, c.tolist())) == want
+    assert len(driver.carried_tags(np.zeros((0, 3), np.int32), 32)) == 0
+    m = driver.merge_tags(fine, fine[:1])
+    assert len(m) == 3
+
+
+@pytest.mark.parametrize("carry", [False, True])
+def test_a_level_one_tag_keeps_its_refinement_only_when_carried(carry):
+    t1, l1, l2 = _rebuild(carry)
+    assert not check_layout(l1, 2 * M0, np.ones((M0,) * 3, bool), BF, MAX_BOX)
+    l1_valid = boxes_mask(l1, 2 * M0)
+    if l2:
+        assert not check_layout(l2, 4 * M0, l1_valid, BF, MAX_BOX)
+    refined = coarsen_mask(boxes_mask(l2, 4 * M0)) if l2 else np.zeros((2 * M0,) * 3, bool)
+    # every tagged level-1 cell and its buffer refined by level 2
+    want = np.zeros((2 * M0,) * 3, bool)
+    for x, y, z in t1:
+        want[(z - NBUF):(z + NBUF + 1), (y - NBUF):(y + NBUF + 1), (x - NBUF):(x + NBUF + 1)] = True
+    covered = bool(np.all(refined[want]))
+    assert covered == carry
