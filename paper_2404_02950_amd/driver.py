@@ -38,18 +38,61 @@ def normalised_tee_scales(h):
     return [1.0 / v if v > 0.0 else 1.0 for v in m]
 
 
-def carried_tags(idx_fine, M_coarse: int, grow: int = 1):
-    """Tags of level l+1 carried down to level l: each tagged cell's coarse parent and the
-    parents' neighbours within ``grow`` cells (periodic, M_coarse cells per axis), as a
-    sorted (n, 3) int32 list of (x, y, z).  Added to level l's own tags, they make the
-    rebuilt level l+1 extend at least (grow + n_error_buf) coarse cells beyond the parent
-    of every tag that level l+1 holds now, which with the default n_error_buf = 2 and one
-    cell of growth covers that tag's own buffer and the nesting gap of half a blocking
-    factor (8) that the level l+2 box refining it needs."""
-    idx = np.asarray(idx_fine, dtype=np.int64).reshape(-1, 3)
+def carried_tags(idx_fine, M_coarse: int, grow: int = 1, n_error_buf: int = 2, blocking_factor: int = 8):
+    """Tags of level l+1 carried down to level l, as a (n, 3) int32 list of level-l cells
+    (x, y, z).  Clustering grows every tag by ``n_error_buf`` cells and tags the blocks of
+    bf/2 cells it meets, so what a carried set must reproduce is the set of blocks met by
+    the coarse parents of the fine tags grown by ``grow + n_error_buf`` cells (periodic,
+    M_coarse cells per axis).  That set is built on a dense mask of blocks and returned
+    as one cell per pair of adjacent blocks (a cell n_error_buf cells into the lower
+    block meets exactly the two once grown), so its size follows the number of tagged
+    blocks, not the number of fine tags.  With n_error_buf = 2 and one cell of growth the
+    rebuilt level l+1 extends at least 6 fine cells beyond every fine tag: the tag's own
+    buffer of 2 and the nesting gap of half a blocking factor (4) that the level-l+2 box
+    refining it needs."""
+    b = blocking_factor // 2
+    n = n_error_buf
+    r = grow + n
+    idx = np.asarray(idx_fine).reshape(-1, 3)
     if idx.size == 0:
         return np.zeros((0, 3), np.int32)
-    c = np.unique(idx // 2, axis=0)
+    # a cell n into block a meets blocks a and a+1 once grown; p +- r meets two or three
+    if not (b <= 2 * n < 2 * b) or M_coarse % b or not (b < 2 * r + 1 and r < b):
+        return _carried_cells(idx, M_coarse, grow)
+    nb = M_coarse // b
+    # per axis: blocks A..B (two or three) met by parent +- r, i.e. block pairs A..B-1,
+    # kept as the key (A, s) with s = B - A - 1 (0: one pair, 1: two)
+    kt = np.int32 if (2 * nb) ** 3 < 2**31 else np.int64
+    keys = np.zeros(idx.shape[0], kt)
+    pow2 = (b & (b - 1)) == 0 and (nb & (nb - 1)) == 0
+    sh = b.bit_length() - 1
+    for d in (2, 1, 0):          # z, y, x: key = ((A_z*2 + s_z) * 2nb + A_y*2 + s_y) * 2nb + ...
+        p = idx[:, d].astype(kt) >> 1
+        if pow2:                 # floor division and periodic wrap by shifts and masks
+            A = (p - r) >> sh
+            s = ((p + r) >> sh) - A - 1
+            A &= nb - 1
+        else:
+            A = np.floor_divide(p - r, b)
+            s = np.floor_divide(p + r, b) - A - 1
+            A = np.mod(A, nb)
+        keys *= 2 * nb
+        keys += (A << 1) | s
+    seen = np.zeros((2 * nb) ** 3, bool)
+    seen[keys] = True
+    # pairs: a pair a of an axis comes from the key (a, any s) and from (a - 1, s = 1)
+    pr = seen.reshape(nb, 2, nb, 2, nb, 2)
+    pr = pr[:, 0] | pr[:, 1] | np.roll(pr[:, 1], 1, axis=0)                       # z
+    pr = pr[:, :, 0] | pr[:, :, 1] | np.roll(pr[:, :, 1], 1, axis=1)              # y
+    pr = pr[:, :, :, 0] | pr[:, :, :, 1] | np.roll(pr[:, :, :, 1], 1, axis=2)     # x
+    az, ay, ax = np.nonzero(pr)
+    return np.stack([ax * b + n, ay * b + n, az * b + n], 1).astype(np.int32)
+
+
+def _carried_cells(idx, M_coarse: int, grow: int):
+    """Carried tags as cells (coarse parents grown by ``grow``), for clustering
+    parameters the block form does not cover."""
+    c = np.unique(idx.astype(np.int64) // 2, axis=0)
     r = np.arange(-grow, grow + 1)
     off = np.stack(np.meshgrid(r, r, r, indexing="ij"), -1).reshape(-1, 3)
     out = (c[:, None, :] + off[None, :, :]).reshape(-1, 3) % M_coarse
@@ -57,12 +100,12 @@ def carried_tags(idx_fine, M_coarse: int, grow: int = 1):
 
 
 def merge_tags(a, b):
-    """Union of two (n, 3) tag lists."""
+    """Both tag lists in one (clustering counts a cell tagged twice once)."""
     a = np.asarray(a, np.int32).reshape(-1, 3)
     b = np.asarray(b, np.int32).reshape(-1, 3)
     if not len(b):
         return a
-    return np.unique(np.concatenate([a, b]), axis=0).astype(np.int32)
+    return np.concatenate([a, b])
 
 
 def regrid(h, max_level: int, layout_for=None, efficiency: float = 0.7, max_level_bytes: int | None = None,
@@ -99,7 +142,9 @@ def regrid(h, max_level: int, layout_for=None, efficiency: float = 0.7, max_leve
         t1 = time.perf_counter()
         counts.append(ntag)
         if lev + 1 in carried:
-            idx = merge_tags(idx, carried_tags(carried[lev + 1], h.params.n0 << lev))
+            idx = merge_tags(idx, carried_tags(carried[lev + 1], h.params.n0 << lev,
+                                                n_error_buf=h.params.n_error_buf,
+                                                blocking_factor=h.params.blocking_factor))
         boxes = layout_for(lev, ntag, idx) if layout_for is not None else h.cluster(lev, idx, efficiency)
         t2 = time.perf_counter()
         if boxes and max_level_bytes is not None:

@@ -31,19 +31,44 @@ def _rebuild(carry):
     return t1, l1, l2
 
 
-def test_carried_tags_are_the_grown_coarse_parents():
-    fine = np.array([[0, 0, 0], [1, 1, 1], [9, 4, 63]], np.int32)
-    c = driver.carried_tags(fine, 32, grow=1)
-    want = set()
-    for px, py, pz in {(0, 0, 0), (4, 2, 31)}:
-        for dx in (-1, 0, 1):
-            for dy in (-1, 0, 1):
-                for dz in (-1, 0, 1):
-                    want.add(((px + dx) % 32, (py + dy) % 32, (pz + dz) % 32))
-    assert set(map(tuple, c.tolist())) == want
+def _blocks_met(cells, M, grow, b=4):
+    """Blocks of b cells that cells grown by ``grow`` meet (periodic), by brute force."""
+    out = set()
+    for x, y, z in np.asarray(cells).reshape(-1, 3).tolist():
+        rng = [range(c - grow, c + grow + 1) for c in (x, y, z)]
+        for cx in rng[0]:
+            for cy in rng[1]:
+                for cz in rng[2]:
+                    out.add(((cx % M) // b, (cy % M) // b, (cz % M) // b))
+    return out
+
+
+def test_carried_tags_meet_the_blocks_of_the_grown_parents():
+    # clustering grows each tag by n_error_buf = 2 and tags the blocks of bf/2 = 4 cells
+    # it meets: the carried list must meet exactly the blocks the coarse parents grown by
+    # 1 + 2 meet (fine tags at every residue mod 8, at both periodic ends, and a cluster)
+    rng = np.random.default_rng(3)
+    fine = np.concatenate([np.array([[0, 0, 0], [1, 1, 1], [9, 4, 63], [63, 62, 61], [5, 13, 22]], np.int32),
+                           rng.integers(0, 64, (40, 3), dtype=np.int32)])
+    c = driver.carried_tags(fine, 32)
+    parents = fine // 2
+    assert _blocks_met(c, 32, 2) == _blocks_met(parents, 32, 3)
+    # far fewer cells than the grown parents: one per pair of blocks
+    assert len(c) < len(driver._carried_cells(fine, 32, 1))
+    assert _blocks_met(driver._carried_cells(fine, 32, 1), 32, 2) == _blocks_met(parents, 32, 3)
     assert len(driver.carried_tags(np.zeros((0, 3), np.int32), 32)) == 0
-    m = driver.merge_tags(fine, fine[:1])
-    assert len(m) == 3
+    m = driver.merge_tags(fine[:3], fine[:1])
+    assert len(m) == 4
+
+
+def test_carried_tags_of_many_fine_tags_are_fast():
+    import time
+    rng = np.random.default_rng(4)
+    fine = rng.integers(0, 1024, (20_000_000, 3), dtype=np.int32)
+    t0 = time.perf_counter()
+    c = driver.carried_tags(fine, 512)
+    assert time.perf_counter() - t0 < 20.0
+    assert c.shape[1] == 3 and len(c) <= (512 // 4) ** 3
 
 
 @pytest.mark.parametrize("carry", [False, True])
