@@ -107,10 +107,8 @@ def load(path: str = None):
         raise RuntimeError(f"{path} is missing: build it first (python -m paper_2404_02950_amd.build_lib)")
     # torch first: the library then binds to the HIP runtime torch has loaded (same soname)
     # instead of loading the system copy beside it, which would leave two HIP runtimes,
-    # each with its own view of the device, in one process (the host-sanitizer build runs
-    # on the CPU only and leaves torch out)
-    if not os.environ.get("SHAMR_LIB"):
-        import torch  # noqa: F401
+    # each with its own view of the device, in one process
+    import torch  # noqa: F401
     lib = ctypes.CDLL(path)
     for name, (res, args) in _PROTOS.items():
         fn = getattr(lib, name)
@@ -478,7 +476,7 @@ class Hierarchy:
         if fused_shape is None:
             fused_shape = 2
         if fused_variant is None:
-            fused_variant = 5 if ssp else (6 if self.params.prec == SH_F32 else 7)
+            fused_variant = 5 if ssp else (6 if self.params.prec == SH_F32 else 3)
         _check(self.lib.sh_set_tuning(self.h, kind, nontemporal, tile_z, fuse, fused_shape, fused_tile_z,
                                       fused_variant))
 
