@@ -328,12 +328,13 @@ sh_status sh_debug_stage_scalars(sh_hierarchy h, int32_t lev, int32_t s, double*
    fused_variant: thread order / x-neighbour exchange / accumulator placement / U_n
      prefetch of the fused kernel: 0 = row-major, LDS, registers; 1 = row-major, lane
      shifts, registers; 2 = row-major, lane shifts, LDS; 3 = ring order, LDS, LDS; 4 =
-     ring order, LDS, registers; 5 = as 4 with U_n planes loaded two iterations ahead and
-     the later stages' z-1 neighbours from LDS; 6 = as 5 with the accumulator in LDS
-     (SSPRK3 has no accumulator: 2, 3 and 6 run as 1, 4 and 5).
+     ring order, LDS, registers; 5 = as 4 with U_n planes loaded two iterations ahead; 6 =
+     as 5 with the accumulator in LDS; 7 = as 3 with the U_n values of stages 1 and 2
+     read again from memory instead of kept in registers; 8 = as 7 with the two-iteration
+     prefetch (SSPRK3 has no accumulator: 2, 3 and 6 run as 1, 4 and 5).
    Applies to every level.  Defaults at creation: kind 8, nontemporal 1, tile_z 0, fuse 4,
-   fused_tile_z 0, fused_shape / fused_variant 0 / 5 for RK4 in SH_F64, 2 / 6 for RK4 in
-   SH_F32 and 2 / 5 for SSPRK3.  The environment variable SHAMR_TUNE (e.g.
+   fused_tile_z 0, fused_shape 2 with fused_variant 3 for RK4 in SH_F64, 6 for RK4 in
+   SH_F32 and 5 for SSPRK3.  The environment variable SHAMR_TUNE (e.g.
    "kind=8,nt=1,zc=0,fuse=4,fshape=0,fzc=0,fvar=5,fgrp=1") overrides them; fgrp 1 = fused
    tiles launched in groups of 32 covering square-ish patches, 0 = in rows. */
 sh_status sh_set_tuning(sh_hierarchy h, int32_t kind, int32_t nontemporal, int32_t tile_z, int32_t fuse,

@@ -15,8 +15,10 @@
 // beyond where it is computed, so stage j is computed on the footprint grown by
 // NS - 1 - j cells (overlapped tiles), and the threads cover the footprint grown by NS
 // cells, the outermost ring only loading U_n.  Each iteration every stage publishes its
-// input plane to LDS (two buffers alternating by iteration), one barrier, then the stages
-// run in order reading x/y neighbours from LDS.
+// input plane to LDS, a barrier, the stages run in order reading x/y neighbours from LDS,
+// and a second barrier closes the iteration.  (Two plane buffers alternating by
+// iteration, which need only the first barrier and can also serve the z-1 neighbour of
+// stages 1..3, measured slower in every variant and precision at 512^3: 5-25 %.)
 // The z-range is extended the same way (stage j covers NS - 1 - j extra planes below and
 // above), so U_n is read from z0-NS to z0+zc+NS-1: the level keeps a 4-deep ghost shell.
 // The RK4 accumulator exists only on the footprint's own columns (registers or LDS).
@@ -92,12 +94,10 @@ constexpr int DPP_WAVE_SHL1 = 0x130;  // lane l takes lane l+1
 // LDS.
 // PF2: U_n planes are loaded two iterations before they enter the stage-0 window, into
 // two buffers that alternate between iterations (else in the iteration that uses them).
-// ZL: stages 1..3 read their z-1 neighbour from the previous iteration's LDS planes
-// instead of keeping it in registers (needs the double-buffered planes).
 // UNG: the U_n values the updates of stages 1 and 2 need (planes i-1 and i-2, read two and
 // one iterations earlier by the same thread, so still in the caches) are read again from
 // memory instead of being carried in registers.
-template <typename T, bool NT, int TX, int TY, int ORDER, bool XDPP, bool ACCL, bool PF2, bool ZL, int NS,
+template <typename T, bool NT, int TX, int TY, int ORDER, bool XDPP, bool ACCL, bool PF2, int NS,
           bool UNG = false>
 __global__ __launch_bounds__((FusedShape<T, TX, TY, NS>::NBLK)) void k_fused_step(const Tile* __restrict__ tiles,
                                                                                 int ntiles,
@@ -108,13 +108,9 @@ __global__ __launch_bounds__((FusedShape<T, TX, TY, NS>::NBLK)) void k_fused_ste
   constexpr int FG = FD - 1;  // compute ring of stage 0 beyond the footprint
   using Sh = FusedShape<T, TX, TY, FD>;
   constexpr int W = Sh::W, H = Sh::H;
-  // stage input planes, double-buffered by iteration parity where LDS allows: a buffer is
-  // rewritten two iterations later, after the next iteration's barrier, so one barrier per
-  // iteration orders every write after the reads of the same buffer (single-buffered, a
-  // second barrier closes each iteration)
-  constexpr size_t LDS_ACC = ACCL ? sizeof(double) * 4 * 4 * TY * TX : 0;
-  constexpr int NBUF = (2 * sizeof(T) * FD * 2 * H * W + LDS_ACC <= 160 * 1024) ? 2 : 1;
-  __shared__ T sm2[NBUF][FD][2][H][W];
+  // stage input planes (psi of both components); every write of an iteration comes after
+  // the previous iteration's closing barrier, every read before this one's
+  __shared__ T sm[FD][2][H][W];
   // RK4 accumulator of the footprint's own columns for the four planes in flight (slot =
   // plane mod 4); each thread touches only its own column, so no barrier is involved
   __shared__ double sacc[ACCL ? 4 : 1][4][ACCL ? TY : 1][ACCL ? TX : 1];
@@ -216,10 +212,6 @@ __global__ __launch_bounds__((FusedShape<T, TX, TY, NS>::NBLK)) void k_fused_ste
   };
   auto iteration = [&](const int i, auto fill_tag, T(&ldb)[2][2], T(&useb)[2][2]) {
     constexpr bool FILL = decltype(fill_tag)::value;
-    T(*sm)[2][H][W] = sm2[NBUF == 2 ? (i & 1) : 0];
-    // with two buffers the other one still holds the planes published one iteration ago
-    constexpr bool ZLDS = ZL && NBUF == 2;
-    T(*smp)[2][H][W] = sm2[NBUF == 2 ? ((i + 1) & 1) : 0];
     load_planes(PF2 ? i + 3 : i + 2, ldb);
     // publish every stage's input plane: stage 0 = U_n psi at i, stage j = its window top
 #pragma unroll
@@ -241,7 +233,7 @@ __global__ __launch_bounds__((FusedShape<T, TX, TY, NS>::NBLK)) void k_fused_ste
         // push stage j-1's output plane (p+1) into stage j's window
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
-          if (!ZLDS) wj[j][0][c] = wj[j][1][c];
+          wj[j][0][c] = wj[j][1][c];
           wj[j][1][c] = wj[j][2][c];
           wj[j][2][c] = out[c];
           qj[j][0][c] = qj[j][1][c];
@@ -279,7 +271,7 @@ __global__ __launch_bounds__((FusedShape<T, TX, TY, NS>::NBLK)) void k_fused_ste
           xp = sm[j][c][cy][cx + 1];
         }
         const T ym = sm[j][c][cym][cx], yp = sm[j][c][cyp][cx];
-        const T zm = (ZLDS && j > 0) ? smp[j][c][cy][cx] : w[0][c];
+        const T zm = w[0][c];
         lap[c] = ((((xm + xp) + (ym + yp)) + (zm + w[2][c])) - (T)6.0 * w[1][c]) * idx2;
       }
       const T p0 = w[1][0], p1 = w[1][1];
@@ -337,7 +329,7 @@ __global__ __launch_bounds__((FusedShape<T, TX, TY, NS>::NBLK)) void k_fused_ste
         }
       }
     }
-    if (NBUF == 1) lds_barrier();
+    lds_barrier();
     if constexpr (NS == 4 && !ACCL) {
       // register accumulator: advance the per-plane chain by one plane
 #pragma unroll
@@ -378,10 +370,10 @@ __global__ __launch_bounds__((FusedShape<T, TX, TY, NS>::NBLK)) void k_fused_ste
 }
 
 template <typename T, bool NT, int TX, int TY, int NS, int ORDER, bool XDPP, bool ACCL, bool PF2 = false,
-          bool ZL = false, bool UNG = false>
+          bool UNG = false>
 static void fused_launch_shape(const Tile* tiles, int ntiles, const BoxDev* boxes, hipStream_t st) {
   using Sh = FusedShape<T, TX, TY, NS>;
-  hipLaunchKernelGGL((k_fused_step<T, NT, TX, TY, ORDER, XDPP, ACCL, PF2, ZL, NS, UNG>), dim3(ntiles), dim3(Sh::NBLK),
+  hipLaunchKernelGGL((k_fused_step<T, NT, TX, TY, ORDER, XDPP, ACCL, PF2, NS, UNG>), dim3(ntiles), dim3(Sh::NBLK),
                      0, st, tiles, ntiles, boxes);
 }
 
@@ -389,12 +381,11 @@ static void fused_launch_shape(const Tile* tiles, int ntiles, const BoxDev* boxe
 // 1 = row-major, x neighbours by lane shifts, registers; 2 = row-major, lane shifts,
 // accumulator in LDS; 3 = ring-ordered threads, LDS neighbours, accumulator in LDS;
 // 4 = ring-ordered threads, LDS neighbours, accumulator in registers; 5 = variant 4 with
-// the two-iteration U_n prefetch, z-1 neighbours of stages 1..3 from LDS; 6 = variant 5
-// with the accumulator in LDS; 7 = ring-ordered threads, accumulator in LDS, z-1 from LDS,
-// U_n of stages 1 and 2 read again from memory (fewer registers: with the 32 x 16
-// footprint its fifteen wavefronts fit without spilling in FP64); 8 = variant 7 with the
-// two-iteration U_n prefetch.  SSPRK3 has no accumulator: variants 2, 3 and 6 run as 1,
-// 4 and 5, and 7 and 8 keep only the re-read of U_n.
+// the two-iteration U_n prefetch; 6 = variant 5 with the accumulator in LDS; 7 =
+// ring-ordered threads, accumulator in LDS, U_n of stages 1 and 2 read again from memory
+// (fewer registers); 8 = variant 7 with the two-iteration U_n prefetch.  SSPRK3 has no
+// accumulator: variants 2, 3 and 6 run as 1, 4 and 5, and 7 and 8 keep only the re-read
+// of U_n.
 template <typename T, bool NT, int TX, int TY, int NS>
 static void fused_launch_variant(int variant, const Tile* tiles, int ntiles, const BoxDev* boxes, hipStream_t st) {
   constexpr bool AL = NS == 4;  // the LDS accumulator variants exist for RK4
@@ -404,10 +395,10 @@ static void fused_launch_variant(int variant, const Tile* tiles, int ntiles, con
     case 2: fused_launch_shape<T, NT, TX, TY, NS, 0, true, AL>(tiles, ntiles, boxes, st); break;
     case 3: fused_launch_shape<T, NT, TX, TY, NS, 1, false, AL>(tiles, ntiles, boxes, st); break;
     case 4: fused_launch_shape<T, NT, TX, TY, NS, 1, false, false>(tiles, ntiles, boxes, st); break;
-    case 5: fused_launch_shape<T, NT, TX, TY, NS, 1, false, false, true, true>(tiles, ntiles, boxes, st); break;
-    case 6: fused_launch_shape<T, NT, TX, TY, NS, 1, false, AL, true, true>(tiles, ntiles, boxes, st); break;
-    case 7: fused_launch_shape<T, NT, TX, TY, NS, 1, false, AL, false, true, true>(tiles, ntiles, boxes, st); break;
-    default: fused_launch_shape<T, NT, TX, TY, NS, 1, false, AL, true, true, true>(tiles, ntiles, boxes, st); break;
+    case 5: fused_launch_shape<T, NT, TX, TY, NS, 1, false, false, true>(tiles, ntiles, boxes, st); break;
+    case 6: fused_launch_shape<T, NT, TX, TY, NS, 1, false, AL, true>(tiles, ntiles, boxes, st); break;
+    case 7: fused_launch_shape<T, NT, TX, TY, NS, 1, false, AL, false, true>(tiles, ntiles, boxes, st); break;
+    default: fused_launch_shape<T, NT, TX, TY, NS, 1, false, AL, true, true>(tiles, ntiles, boxes, st); break;
   }
 }
 

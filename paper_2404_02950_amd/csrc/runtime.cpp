@@ -269,10 +269,9 @@ struct Tuning {
 };
 
 // Fastest fused launches measured at 512^3 on MI355X, all on the 32 x 16 footprint (15
-// wavefronts per workgroup, so at most 128 registers): RK4 FP64 variant 7 (accumulator in
-// LDS and U_n of stages 1 and 2 read again, 121 registers; 3.20 ms against 3.35 ms for
-// variant 5 on 32 x 8 with ten wavefronts), RK4 FP32 variant 6; SSPRK3 (fewer registers
-// per stage) variant 5 in both precisions.
+// wavefronts per workgroup, so at most 128 registers): RK4 FP64 variant 3 (accumulator in
+// LDS, ring-ordered threads; 3.11 ms against 3.23 ms for variant 7), RK4 FP32 variant 6
+// (1.92 ms); SSPRK3 variant 5 in both precisions (2.18 and 1.36 ms).
 static Tuning default_tuning(const sh_params& p) {
   Tuning t;
   t.fshape = 2;
@@ -281,7 +280,7 @@ static Tuning default_tuning(const sh_params& p) {
   } else if (p.prec == SH_F32) {
     t.fvar = 6;
   } else {
-    t.fvar = 7;
+    t.fvar = 3;
   }
   return t;
 }
