@@ -51,9 +51,9 @@ __global__ __launch_bounds__(SH_BLOCK) void k_ghost_copy(const CopySeg* __restri
   const int k = r / s.n[1];
   const BoxDev& D = boxes[s.dbox];
   const BoxDev& Sb = boxes[s.sbox];
-  const int sl = role_slot(role, *D.ls);
-  T* dst = (T*)D.slot[sl];
-  const T* src = (const T*)Sb.slot[sl];
+  const int sl = role_slot(role, load_level(D.ls));
+  Glob<T>* dst = (Glob<T>*)D.slot[sl];
+  const Glob<T>* src = (const Glob<T>*)Sb.slot[sl];
   const long long ed = elem<T>(D, s.dlo[0] + i, s.dlo[1] + j, s.dlo[2] + k);
   const long long es = elem<T>(Sb, s.slo[0] + i, s.slo[1] + j, s.slo[2] + k);
   for (int comp = 0; comp < ncomp; ++comp) dst[comp * D.cs + ed] = src[comp * Sb.cs + es];
@@ -71,7 +71,7 @@ __global__ __launch_bounds__(SH_BLOCK) void k_ghost_copy(const CopySeg* __restri
 // Arithmetic in float64, rounded to T on store.
 // ---------------------------------------------------------------------------------
 template <typename T>
-__device__ __forceinline__ double tinterp(const T* Cold, const T* Cnew, long long e, int anum, double a) {
+__device__ __forceinline__ double tinterp(const Glob<T>* Cold, const Glob<T>* Cnew, long long e, int anum, double a) {
   if (anum == 4) return (double)Cnew[e];
   if (anum == 0) return (double)Cold[e];
   return (1.0 - a) * (double)Cold[e] + a * (double)Cnew[e];
@@ -110,18 +110,18 @@ __global__ __launch_bounds__(SH_BLOCK) void k_ghost_interp(const InterpSeg* __re
   const int sx = tn[0] + 2 * G, sy = tn[1] + 2 * G, sz = tn[2] + 2 * G;
   const BoxDev& F = fboxes[s.fbox];
   const BoxDev& C = cboxes[s.cbox];
-  const LevelScal& LC = *C.ls;
-  const T* Cnew = (const T*)C.slot[role_slot(ROLE_UN, LC)];
-  const T* Cold = (const T*)C.slot[role_slot(ROLE_OLD, LC)];
-  T* dst = (T*)F.slot[role_slot(role, *F.ls)];
+  const LevelScal LC = load_level(C.ls);
+  const Glob<T>* Cnew = (const Glob<T>*)C.slot[role_slot(ROLE_UN, LC)];
+  const Glob<T>* Cold = (const Glob<T>*)C.slot[role_slot(ROLE_OLD, LC)];
+  Glob<T>* dst = (Glob<T>*)F.slot[role_slot(role, load_level(F.ls))];
   const double a = 0.25 * (double)anum;
   const int tid = threadIdx.x;
   const bool has_p = tid < tn[0] * tn[1] * tn[2];
   const int pi = tid % tn[0], pj = (tid / tn[0]) % tn[1], pk = tid / (tn[0] * tn[1]);
   const double lo1 = -11.0 / 64.0, lo2 = 3.0 / 128.0, hi1 = 11.0 / 64.0, hi2 = -3.0 / 128.0;
   for (int comp = 0; comp < ncomp; ++comp) {
-    const T* co = Cold + comp * C.cs;
-    const T* cn = Cnew + comp * C.cs;
+    const Glob<T>* co = Cold + comp * C.cs;
+    const Glob<T>* cn = Cnew + comp * C.cs;
     for (int idx = tid; idx < sx * sy * sz; idx += SH_BLOCK) {
       const int u = idx % sx, v = (idx / sx) % sy, w = idx / (sx * sy);
       const long long e = elem<T>(C, t0[0] + u - G + s.cshift[0], t0[1] + v - G + s.cshift[1],
@@ -215,14 +215,14 @@ __global__ __launch_bounds__(SH_BLOCK) void k_avgdown(const AvgSeg* __restrict__
   const int k = r / s.n[1];
   const BoxDev& C = cboxes[s.cbox];
   const BoxDev& F = fboxes[s.fbox];
-  T* dst = (T*)slot_base(C, role_slot(ROLE_UN, *C.ls));
-  const T* src = (const T*)slot_base(F, role_slot(ROLE_UN, *F.ls));
+  Glob<T>* dst = (Glob<T>*)slot_base(C, role_slot(ROLE_UN, load_level(C.ls)));
+  const Glob<T>* src = (const Glob<T>*)slot_base(F, role_slot(ROLE_UN, load_level(F.ls)));
   const long long ec = elem<T>(C, s.clo[0] + i, s.clo[1] + j, s.clo[2] + k);
   const long long ef = elem<T>(F, s.f0[0] + 2 * i, s.f0[1] + 2 * j, s.f0[2] + 2 * k);
   const long long px = F.px, plane = px * F.py;
   double t = 0.0, dc[4];
   for (int comp = 0; comp < 4; ++comp) {
-    const T* f = src + comp * F.cs + ef;
+    const Glob<T>* f = src + comp * F.cs + ef;
     const double f000 = f[0], f100 = f[1], f010 = f[px], f110 = f[px + 1];
     const double f001 = f[plane], f101 = f[plane + 1], f011 = f[plane + px], f111 = f[plane + px + 1];
     const double avg = ((((f000 + f100) + (f010 + f110)) + ((f001 + f101) + (f011 + f111))) * 0.125);

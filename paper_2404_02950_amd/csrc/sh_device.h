@@ -83,6 +83,26 @@ __device__ __forceinline__ long long elem(const BoxDev& B, int i, int j, int k) 
   return ((long long)(k + B.ng) * B.py + (j + B.ng)) * (long long)B.px + Xoff<T>::v + i;
 }
 
+// Box storage is global memory, but the box records hold generic pointers; reading it
+// through pointers of the global address space lets the compiler use global (not flat)
+// memory instructions.
+template <typename T>
+using Glob = __attribute__((address_space(1))) T;
+
+// A level's scalars do not change while a kernel runs (only the counter kernel between
+// launches writes them): read through the constant address space, a record at a
+// wave-uniform address is fetched with scalar loads.
+__device__ __forceinline__ LevelScal load_level(const LevelScal* p) {
+  static_assert(sizeof(LevelScal) % 8 == 0, "whole 8-byte words");
+  typedef const __attribute__((address_space(4))) unsigned long long* cq;
+  unsigned long long w[sizeof(LevelScal) / 8];
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(LevelScal) / 8); ++i) w[i] = ((cq)p)[i];
+  LevelScal L;
+  __builtin_memcpy(&L, w, sizeof(L));
+  return L;
+}
+
 // Streams read or written once can be marked nontemporal so they do not displace data
 // that neighbouring tiles re-read from L2.
 template <bool NT, typename V>
@@ -91,7 +111,12 @@ __device__ __forceinline__ V ld(const V* p) {
   else return *p;
 }
 template <bool NT, typename V>
-__device__ __forceinline__ void st(V* p, V v) {
+__device__ __forceinline__ V ld(const Glob<V>* p) {
+  if constexpr (NT) return __builtin_nontemporal_load(p);
+  else return *p;
+}
+template <bool NT, typename P, typename V>
+__device__ __forceinline__ void st(P p, V v) {
   if constexpr (NT) __builtin_nontemporal_store(v, p);
   else *p = v;
 }

@@ -72,26 +72,27 @@ __device__ __forceinline__ T ko_sum(const T* S, T u) {
 
 // Six-neighbour sum at distance r read straight from memory (x, y, z).
 template <typename T>
-__device__ __forceinline__ T nsum(const T* u, long long e, int r, long long px, long long plane) {
+__device__ __forceinline__ T nsum(const Glob<T>* u, long long e, int r, long long px, long long plane) {
   return ((u[e - r] + u[e + r]) + (u[e - r * px] + u[e + r * px])) + (u[e - r * plane] + u[e + r * plane]);
 }
 
+template <typename T>
 struct StagePtrs {
-  const void* X;
-  const void* Un;
-  void* Y;
-  double* acc;
+  const Glob<T>* X;
+  const Glob<T>* Un;
+  Glob<T>* Y;
+  Glob<double>* acc;
 };
 
 template <typename T, int S>
-__device__ __forceinline__ StagePtrs stage_ptrs(const BoxDev& B, const LevelScal& L) {
+__device__ __forceinline__ StagePtrs<T> stage_ptrs(const BoxDev& B, const LevelScal& L) {
   constexpr int in_role = (S == 0 || S == 4 || S == 7) ? ROLE_UN : ((S == 2 || S == 6 || S == 9) ? ROLE_B : ROLE_A);
   constexpr int out_role = (S == 1 || S == 3 || S == 5 || S == 8) ? ROLE_B : ROLE_A;
-  StagePtrs p;
-  p.X = slot_base(B, role_slot(in_role, L));
-  p.Un = slot_base(B, role_slot(ROLE_UN, L));
-  p.Y = slot_base(B, role_slot(out_role, L));
-  p.acc = B.acc;
+  StagePtrs<T> p;
+  p.X = (const Glob<T>*)slot_base(B, role_slot(in_role, L));
+  p.Un = (const Glob<T>*)slot_base(B, role_slot(ROLE_UN, L));
+  p.Y = (Glob<T>*)slot_base(B, role_slot(out_role, L));
+  p.acc = (Glob<double>*)B.acc;
   return p;
 }
 
@@ -99,8 +100,8 @@ __device__ __forceinline__ StagePtrs stage_ptrs(const BoxDev& B, const LevelScal
 // Laplacians, q0/q1 = Pi at the cell (all in T); e = element index of the cell.
 // With KO, ko4 holds the dissipation terms Q of the four components.
 template <typename T, int S, bool NT, bool KO = false>
-__device__ __forceinline__ void stage_cell(const StageScal& sc, const T* __restrict__ Un, T* __restrict__ Y,
-                                           double* __restrict__ acc, long long cs, long long e, T p0, T p1,
+__device__ __forceinline__ void stage_cell(const StageScal& sc, const Glob<T>* __restrict__ Un, Glob<T>* __restrict__ Y,
+                                           Glob<double>* __restrict__ acc, long long cs, long long e, T p0, T p1,
                                            T q0, T q1, T lap0, T lap1, const double* un4, const double* acc4,
                                            const T* ko4 = nullptr) {
   const T cf = (T)sc.cf, cp = (T)sc.cp;
@@ -182,7 +183,7 @@ __device__ __forceinline__ void stage_cell(const StageScal& sc, const T* __restr
 // Loads of the once-read streams of a cell: U_n (RK4 stages 2, 3; SSPRK3 stages 2, 3;
 // RKN4 stage 2) and acc (RK4 stages 2-4; RKN4 stages 2, 3).
 template <typename T, int S, bool NT>
-__device__ __forceinline__ void stage_loads(const T* __restrict__ Un, const double* __restrict__ acc, long long cs,
+__device__ __forceinline__ void stage_loads(const Glob<T>* __restrict__ Un, const Glob<double>* __restrict__ acc, long long cs,
                                             long long e, double* un4, double* acc4) {
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
@@ -201,17 +202,20 @@ __global__ __launch_bounds__(SH_BLOCK) void k_stage(const Tile* __restrict__ til
                                                     const BoxDev* __restrict__ boxes) {
   constexpr int HR = H > KD ? H : KD;
   const int lane = threadIdx.x & (SH_WAVE - 1);
-  const int t = xcd_remap(blockIdx.x, gridDim.x) * (SH_BLOCK / SH_WAVE) + (threadIdx.x >> 6);
+  // one tile per wavefront: the index is uniform over the wave, which keeps the tile and
+  // box records and the storage bases in scalar registers
+  const int t = __builtin_amdgcn_readfirstlane(xcd_remap(blockIdx.x, gridDim.x) * (SH_BLOCK / SH_WAVE) +
+                                               (threadIdx.x >> 6));
   if (t >= ntiles) return;
   const Tile tl = tiles[t];
   if (tl.box < 0) return;
   const BoxDev B = boxes[tl.box];
-  const LevelScal L = *B.ls;
+  const LevelScal L = load_level(B.ls);
   const StageScal sc = stage_scalars(L, S);
-  const StagePtrs P = stage_ptrs<T, S>(B, L);
-  const T* __restrict__ X = (const T*)P.X;
-  const T* __restrict__ Un = (const T*)P.Un;
-  T* __restrict__ Y = (T*)P.Y;
+  const StagePtrs<T> P = stage_ptrs<T, S>(B, L);
+  const Glob<T>* __restrict__ X = P.X;
+  const Glob<T>* __restrict__ Un = P.Un;
+  Glob<T>* __restrict__ Y = P.Y;
 
   const int tx = lane & ((1 << tl.txs) - 1);
   const int ty = lane >> tl.txs;
@@ -242,7 +246,7 @@ __global__ __launch_bounds__(SH_BLOCK) void k_stage(const Tile* __restrict__ til
     T Ssum[2][HR];
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
-      const T* u = X + c * cs;
+      const Glob<T>* u = X + c * cs;
 #pragma unroll
       for (int r = 1; r <= HR; ++r)
         Ssum[c][r - 1] = ((u[e - r] + u[e + r]) + (u[e - r * px] + u[e + r * px])) + (w[c][HR - r] + w[c][HR + r]);
@@ -298,12 +302,12 @@ __global__ __launch_bounds__(SH_WAVE * ROWS) void k_stage_lds(const Tile* __rest
   const Tile tl = tiles[t];
   if (tl.box < 0) return;
   const BoxDev B = boxes[tl.box];
-  const LevelScal L = *B.ls;
+  const LevelScal L = load_level(B.ls);
   const StageScal sc = stage_scalars(L, S);
-  const StagePtrs P = stage_ptrs<T, S>(B, L);
-  const T* __restrict__ X = (const T*)P.X;
-  const T* __restrict__ Un = (const T*)P.Un;
-  T* __restrict__ Y = (T*)P.Y;
+  const StagePtrs<T> P = stage_ptrs<T, S>(B, L);
+  const Glob<T>* __restrict__ X = P.X;
+  const Glob<T>* __restrict__ Un = P.Un;
+  Glob<T>* __restrict__ Y = P.Y;
 
   const int x0 = tl.xy & 0xffff, y0 = tl.xy >> 16;
   const int z0 = tl.zz & 0xffff, zc = tl.zz >> 16;
@@ -421,9 +425,9 @@ __global__ __launch_bounds__(SH_BLOCK) void k_rhs(const Tile* __restrict__ tiles
   const Tile tl = tiles[t];
   if (tl.box < 0) return;
   const BoxDev B = boxes[tl.box];
-  const LevelScal L = *B.ls;
+  const LevelScal L = load_level(B.ls);
   const StageScal sc = stage_scalars(L, 0);
-  const T* __restrict__ X = (const T*)slot_base(B, role_slot(ROLE_UN, L));
+  const Glob<T>* __restrict__ X = (const Glob<T>*)slot_base(B, role_slot(ROLE_UN, L));
   const int tx = lane & ((1 << tl.txs) - 1), ty = lane >> tl.txs;
   const int x = (tl.xy & 0xffff) + tx, y = (tl.xy >> 16) + ty;
   if (x >= B.nx || y >= B.ny) return;
@@ -437,7 +441,7 @@ __global__ __launch_bounds__(SH_BLOCK) void k_rhs(const Tile* __restrict__ tiles
     const long long e = elem<T>(B, x, y, z);
     T lap[2], ko4[4] = {(T)0, (T)0, (T)0, (T)0};
     for (int c = 0; c < 2; ++c) {
-      const T* u = X + c * cs;
+      const Glob<T>* u = X + c * cs;
       T Ssum[HR];
 #pragma unroll
       for (int r = 1; r <= HR; ++r) Ssum[r - 1] = nsum(u, e, r, px, plane);
