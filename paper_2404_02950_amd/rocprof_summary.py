@@ -6,6 +6,12 @@
 
 ``stats`` tabulates a ``--kernel-trace --stats`` run (calls, mean duration, share).
 
+``counters`` tabulates one ``--pmc`` run of SQ counters for one kernel (mean per dispatch,
+wait and activity ratios):
+
+    python -m paper_2404_02950_amd.rocprof_summary counters COUNTER_CSV OUT_MD \\
+        --kernel SUBSTRING --workload "..." --cmd "..."
+
 ``traffic`` takes one ``--pmc FETCH_SIZE`` and one ``--pmc WRITE_SIZE`` run of the same
 program.  Both counters report KiB per dispatch.  Each is scaled by the factor that makes
 the library's plain copy kernel ``k_xfer`` read back its known size (it reads a dense FP64
@@ -49,6 +55,14 @@ def stats(args):
         name = r["Name"] if len(r["Name"]) < 110 else r["Name"][:107] + "..."
         lines.append(f"| `{name}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
                      f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | {float(r['Percentage']):.2f} |")
+    if args.trace:
+        # the launches a timed region covers are the last ones: their mean, for comparison
+        # with the figure the program measured itself
+        durs = [(int(r["Dispatch_Id"]), (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+                for r in csv.DictReader(open(args.trace)) if args.timed_kernel in r["Kernel_Name"]]
+        durs = [d for _, d in sorted(durs)][-args.timed_last:]
+        lines += ["", f"Mean over the last {len(durs)} launches of `{args.timed_kernel}` (the timed steps; "
+                      f"kernel trace): {statistics.mean(durs):.1f} us (min {min(durs):.1f}, max {max(durs):.1f})."]
     open(args.out, "w").write("\n".join(lines) + "\n")
 
 
@@ -104,6 +118,36 @@ def traffic(args):
     open(args.out_md, "w").write("\n".join(md))
 
 
+def counters(args):
+    """Mean per dispatch of every counter of one --pmc run for the kernel matching
+    ``--kernel``, with the wait and activity ratios the SQ counters give."""
+    rows = list(csv.DictReader(open(args.csv)))
+    names = sorted({r["Kernel_Name"] for r in rows if args.kernel in r["Kernel_Name"]})
+    if len(names) != 1:
+        raise SystemExit(f"expected one kernel matching {args.kernel!r}, found {names}")
+    kname = names[0]
+    per = defaultdict(lambda: defaultdict(float))
+    for r in rows:
+        if r["Kernel_Name"] == kname:
+            per[r["Counter_Name"]][r["Dispatch_Id"]] += float(r["Counter_Value"])
+    mean = {c: statistics.mean(v.values()) for c, v in per.items()}
+    nd = len(next(iter(per.values())))
+    lines = [f"# SQ counters of `{kname}`", "", f"Workload: {args.workload}; {nd} dispatches (mean per dispatch).",
+             "", f"Command: `{args.cmd}`", "", "| Counter | Mean per dispatch |", "|---|---|"]
+    lines += [f"| {c} | {v:.4g} |" for c, v in sorted(mean.items())]
+    ratios = []
+    cyc = mean.get("SQ_WAVE_CYCLES")
+    if cyc:
+        for c in ("SQ_WAIT_ANY", "SQ_WAIT_INST_ANY", "SQ_ACTIVE_INST_VALU", "SQ_ACTIVE_INST_LDS"):
+            if c in mean:
+                ratios.append(f"{c} / SQ_WAVE_CYCLES = {mean[c] / cyc:.2f}")
+    if "SQ_INSTS_VALU" in mean and mean.get("SQ_WAVES"):
+        ratios.append(f"VALU instructions per wave = {mean['SQ_INSTS_VALU'] / mean['SQ_WAVES']:.0f}")
+    if ratios:
+        lines += ["", "Ratios: " + "; ".join(ratios) + "."]
+    open(args.out, "w").write("\n".join(lines) + "\n")
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="mode", required=True)
@@ -111,6 +155,15 @@ def main(argv=None):
     s.add_argument("csv")
     s.add_argument("out")
     s.add_argument("--cmd", required=True)
+    s.add_argument("--trace", help="kernel trace CSV of the same run")
+    s.add_argument("--timed-kernel", default="k_fused_step")
+    s.add_argument("--timed-last", type=int, default=20)
+    q = sub.add_parser("counters")
+    q.add_argument("csv")
+    q.add_argument("out")
+    q.add_argument("--kernel", required=True)
+    q.add_argument("--workload", required=True)
+    q.add_argument("--cmd", required=True)
     t = sub.add_parser("traffic")
     t.add_argument("fetch")
     t.add_argument("write")
@@ -123,7 +176,7 @@ def main(argv=None):
     t.add_argument("--cmd-fetch", required=True)
     t.add_argument("--cmd-write", required=True)
     args = ap.parse_args(argv)
-    stats(args) if args.mode == "stats" else traffic(args)
+    {"stats": stats, "counters": counters, "traffic": traffic}[args.mode](args)
 
 
 if __name__ == "__main__":
