@@ -234,7 +234,7 @@ def fp32_error_series(U0, n: int, steps: int, stream, args, beta: int = 2):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n", type=int, default=512)
     ap.add_argument("--prec", choices=("f64", "f32"), default="f64")
@@ -460,7 +460,7 @@ def bench_amr(args):
         h.close()
         out.update({"value": rep["cell_updates_per_s_end_to_end"], "dtype": args.prec, "report": rep})
     else:
-        res = workloads.fp32_vs_fp64(U0, levels, steps, beta=args.beta, log=log)
+        res = workloads.fp32_vs_fp64(U0, levels, steps, beta=args.beta, log=log, regrid_mode=args.regrid)
         out.update({"value": res["f64"]["cell_updates_per_s_end_to_end"], "dtype": "f64 and f32",
                     "value_f32": res["f32"]["cell_updates_per_s_end_to_end"], "report": res})
     print(json.dumps(out), flush=True)

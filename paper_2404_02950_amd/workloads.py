@@ -150,7 +150,8 @@ def run_amr(U0: np.ndarray, max_level: int, coarse_steps: int, prec: int = shamr
     return h, report
 
 
-def fp32_vs_fp64(U0: np.ndarray, max_level: int, coarse_steps: int, beta: int = 2, log=print):
+def fp32_vs_fp64(U0: np.ndarray, max_level: int, coarse_steps: int, beta: int = 2, log=print,
+                 regrid_mode: str = "global"):
     """The same AMR run in FP64 and FP32-storage mode: energies, tag-mask differences
     on the coarse level and the largest coarse-level field difference at the end.
 
@@ -162,7 +163,7 @@ def fp32_vs_fp64(U0: np.ndarray, max_level: int, coarse_steps: int, beta: int = 
     fields = {}
     masks = {}
     for name, prec in (("f64", shamr.SH_F64), ("f32", shamr.SH_F32)):
-        h, rep = run_amr(U0, max_level, coarse_steps, prec=prec, beta=beta, log=log)
+        h, rep = run_amr(U0, max_level, coarse_steps, prec=prec, beta=beta, log=log, regrid_mode=regrid_mode)
         res[name] = rep
         fields[name] = h.read_dense(0)
         masks[name] = h.tag_mask_dense(0)
