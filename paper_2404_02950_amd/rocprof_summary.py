@@ -6,6 +6,9 @@
 
 ``stats`` tabulates a ``--kernel-trace --stats`` run (calls, mean duration, share).
 
+``amr-traffic`` sums FETCH_SIZE / WRITE_SIZE runs of an AMR workload by kernel class and
+sets the per-stage kernels against their algorithmic bytes.
+
 ``counters`` tabulates one ``--pmc`` run of SQ counters for one kernel (mean per dispatch,
 wait and activity ratios):
 
@@ -148,6 +151,55 @@ def counters(args):
     open(args.out, "w").write("\n".join(lines) + "\n")
 
 
+def amr_traffic(args):
+    """HBM bytes per kernel class of an AMR run (one FETCH_SIZE and one WRITE_SIZE run,
+    summed over all dispatches, scaled by the k_xfer calibration as in ``traffic``), with
+    the algorithmic bytes of the per-stage RK4 kernels: the refined levels' cells per
+    stage class are (cell-stage updates - 4 x level-0 cells x coarse steps) / 4, at 96 /
+    160 / 160 / 96 B per cell (FP64) for stages 1-4."""
+    def load(path, counter):
+        tot, n = defaultdict(float), defaultdict(int)
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] == counter:
+                tot[r["Kernel_Name"]] += float(r["Counter_Value"])
+                n[r["Kernel_Name"]] += 1
+        return tot, n
+    fetch, nf = load(args.fetch, "FETCH_SIZE")
+    write, nw = load(args.write, "WRITE_SIZE")
+    xk = [k for k in fetch if "k_xfer" in k]
+    if len(xk) != 1:
+        raise SystemExit("expected one k_xfer dispatch kernel for the calibration")
+    ref = 4 * args.n0 ** 3 * 8
+    ff = ref / (fetch[xk[0]] / nf[xk[0]] * 1024)
+    fw = ref / (write[xk[0]] / nw[xk[0]] * 1024)
+    ref_cells = (args.cell_stage_updates - 4 * args.n0 ** 3 * args.coarse_steps) / 4
+    alg = (96, 160, 160, 96)
+
+    def bytes_of(sel):
+        rb = sum(fetch[k] for k in fetch if sel(k)) * 1024 * ff
+        wb = sum(write[k] for k in write if sel(k)) * 1024 * fw
+        return rb, wb
+    lines = ["# HBM traffic of an AMR run by kernel class", "", f"Workload: {args.workload}.", "",
+             f"FETCH_SIZE run: `{args.cmd_fetch}`", "", f"WRITE_SIZE run: `{args.cmd_write}`", "",
+             f"Calibration (k_xfer, {ref} B read and written): factors {ff:.3f} (read), {fw:.3f} (write). "
+             f"Refined-level cells per stage class: {ref_cells:.4g}.", "",
+             "| Kernels | Dispatches | HBM read GB | HBM write GB | Algorithmic GB | Traffic / algorithmic |",
+             "|---|---|---|---|---|---|"]
+    for s in range(4):
+        sel = (lambda k, s=s: k.startswith((f"void k_stage<double, {s}, ", f"void k_stage_lds<double, {s}, ")))
+        rb, wb = bytes_of(sel)
+        nd = sum(nf[k] for k in fetch if sel(k))
+        a = ref_cells * alg[s]
+        lines.append(f"| RK4 stage {s + 1} (`k_stage`, `k_stage_lds`) | {nd} | {rb / 1e9:.1f} | {wb / 1e9:.1f} | "
+                     f"{a / 1e9:.1f} | {(rb + wb) / a:.2f} |")
+    for label, sub in (("coarse/fine interpolation", "k_ghost_interp"), ("same-level copy", "k_ghost_copy"),
+                       ("average down", "k_avgdown"), ("fused level-0 step", "k_fused_step"), ("tagging", "k_tag")):
+        rb, wb = bytes_of(lambda k, sub=sub: sub in k)
+        nd = sum(nf[k] for k in fetch if sub in k)
+        lines.append(f"| {label} (`{sub}`) | {nd} | {rb / 1e9:.1f} | {wb / 1e9:.1f} | | |")
+    open(args.out, "w").write("\n".join(lines) + "\n")
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="mode", required=True)
@@ -164,6 +216,16 @@ def main(argv=None):
     q.add_argument("--kernel", required=True)
     q.add_argument("--workload", required=True)
     q.add_argument("--cmd", required=True)
+    a = sub.add_parser("amr-traffic")
+    a.add_argument("fetch")
+    a.add_argument("write")
+    a.add_argument("out")
+    a.add_argument("--n0", type=int, required=True)
+    a.add_argument("--coarse-steps", type=int, required=True)
+    a.add_argument("--cell-stage-updates", type=float, required=True)
+    a.add_argument("--workload", required=True)
+    a.add_argument("--cmd-fetch", required=True)
+    a.add_argument("--cmd-write", required=True)
     t = sub.add_parser("traffic")
     t.add_argument("fetch")
     t.add_argument("write")
@@ -176,7 +238,7 @@ def main(argv=None):
     t.add_argument("--cmd-fetch", required=True)
     t.add_argument("--cmd-write", required=True)
     args = ap.parse_args(argv)
-    {"stats": stats, "counters": counters, "traffic": traffic}[args.mode](args)
+    {"stats": stats, "counters": counters, "traffic": traffic, "amr-traffic": amr_traffic}[args.mode](args)
 
 
 if __name__ == "__main__":
