@@ -118,11 +118,13 @@ def serve(jobs, budget_bytes: int, stream=None, keep_results=(), inflight: int =
     on a stream of their own (a finished job's hierarchy of the same class reused when one
     is free), so the running batch never waits for an admission; a job joins the batch
     once its set-up has run.  All resident jobs of one precision advance together, one
-    batched launch per kernel per step, recorded as a graph of up to ``graph_steps`` steps
-    (a power of two, never past the first job to finish).  A change of members rewrites
-    the batch tables in stream order (sh_batch_update), and a finished job is noticed from
-    its step count and released once the stream has passed its last step, so neither
-    drains the GPU.  ``keep_results``: job ids whose final state is copied out;
+    batched launch per kernel per step, recorded as a graph of ``graph_steps`` steps while
+    every stepping job has that many steps left (single steps after that); a job alone in
+    its precision steps on its own hierarchy instead, with a graph recorded once per pooled
+    hierarchy.  A job that arrives while nothing is resident or being set up is set up
+    on the batch stream itself and joins at once.  A change of members rewrites the batch tables in stream order
+    (sh_batch_update), and a finished job is noticed from its step count and released once
+    the stream has passed its last step, so neither drains the GPU.  ``keep_results``: job ids whose final state is copied out;
     ``poison``: optional callable(job) -> bool marking jobs whose state is set to NaN at
     admission (failure-isolation checks).  Returns the jobs and the wall time from the
     start to the last completion; each job gets t_admit (set-up queued), t_join (in the
@@ -138,6 +140,7 @@ def serve(jobs, budget_bytes: int, stream=None, keep_results=(), inflight: int =
     staging, resident, retiring = [], [], []
     used = 0
     batches, graphs, graveyard = {}, {}, []
+    solo_graphs = {}
     members = {}
     dirty = set()
     events = collections.deque()
@@ -170,16 +173,25 @@ def serve(jobs, budget_bytes: int, stream=None, keep_results=(), inflight: int =
         while queue and used + queue[0].nbytes <= budget_bytes:
             j = queue.popleft()
             j.out = None
-            j.h = pool.take(j, side)
+            # with nothing resident the batch stream is idle: set the job up there, so it
+            # joins without waiting for a side-stream event
+            direct = not (resident or staging)
+            j.h = pool.take(j, stream if direct else side)
             if poison is not None and poison(j):
-                with torch.cuda.stream(side):
+                with torch.cuda.stream(stream if direct else side):
                     j.staged = torch.full((j.U0.size,), float("nan"), dtype=torch.float64, device="cuda")
                 j.h.write_device(0, j.staged)
                 j.h.fill_ghosts(0)
-            j.ready = torch.cuda.Event()
-            j.ready.record(side)
             j.t_admit = now()
             used += j.nbytes
+            if direct:
+                j.staged = None
+                j.t_join = j.t_admit
+                resident.append(j)
+                dirty.add(j.prec)
+                continue
+            j.ready = torch.cuda.Event()
+            j.ready.record(side)
             staging.append(j)
         if queue and not (staging or resident or retiring):
             raise RuntimeError(f"job {queue[0].jid} needs {queue[0].nbytes} bytes, more than the budget")
@@ -211,15 +223,29 @@ def serve(jobs, budget_bytes: int, stream=None, keep_results=(), inflight: int =
             else:
                 batches[p] = shamr.Batch(hs)
         dirty.clear()
-        nstep = 1
-        if use_graphs:
-            left = min(j.steps - j.done_steps for j in resident)
-            while nstep * 2 <= min(graph_steps, left):
-                nstep *= 2
+        # a graph of graph_steps steps while every resident job has that many left, else
+        # single steps (recording shorter graphs would cost more than it saves)
+        left = min(j.steps - j.done_steps for j in resident)
+        nstep = graph_steps if use_graphs and left >= graph_steps else 1
         for p, b in batches.items():
-            if not members.get(p):
+            hs = members.get(p)
+            if not hs:
                 continue
-            if nstep > 1:
+            if len(hs) == 1:
+                # a job alone in its class steps on its own hierarchy, whose recorded
+                # graph outlives the job (pooled hierarchies are reused)
+                h = hs[0]
+                if nstep > 1:
+                    g = solo_graphs.get(id(h))
+                    if g is None:
+                        with h.capture() as c:
+                            for _ in range(nstep):
+                                h.advance(0)
+                        g = solo_graphs[id(h)] = c.graph
+                    g.launch()
+                else:
+                    h.advance(0)
+            elif nstep > 1:
                 g = graphs.get((p, nstep))
                 if g is None:
                     g = graphs[(p, nstep)] = b.capture(nstep)
@@ -247,7 +273,7 @@ def serve(jobs, budget_bytes: int, stream=None, keep_results=(), inflight: int =
     stream.synchronize()
     retire_ready()
     wall = max((j.t_done for j in jobs), default=now())
-    for g in graphs.values():
+    for g in list(graphs.values()) + list(solo_graphs.values()):
         g.close()
     for g, _ in graveyard:
         g.close()

@@ -129,3 +129,19 @@ def test_pooled_hierarchies_and_the_one_at_a_time_server():
         assert j.t_done >= j.t_admit >= j.arrival
     pool.close()
 
+
+
+
+def test_a_job_arriving_to_an_idle_server_is_set_up_on_the_batch_stream():
+    # nothing resident: the job is set up where it will step and joins at once; later
+    # arrivals that find it running go through the side stream; all results are solo
+    import torch
+    stream = torch.cuda.Stream()
+    jobs = [_job(0, 64, 40, shamr.SH_F64, arrival=0.0), _job(1, 32, 12, shamr.SH_F32, arrival=0.0),
+            _job(2, 48, 20, shamr.SH_F64, arrival=0.0)]
+    done, _ = serve.serve(jobs, 1 << 40, stream=stream, keep_results={0, 1, 2})
+    by = {j.jid: j for j in done}
+    assert by[0].t_join == by[0].t_admit
+    for j in done:
+        _, solo = serve.solo_runtime(j, stream, keep=True)
+        assert_bitwise(j.result, solo, f"job {j.jid}")

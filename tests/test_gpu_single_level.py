@@ -148,7 +148,8 @@ def test_energy_matches_oracle_fp64():
     h.close()
 
 
-@pytest.mark.parametrize("prec,integrator", [(shamr.SH_F64, 4), (shamr.SH_F32, 4), (shamr.SH_F64, 10)])
+@pytest.mark.parametrize("prec,integrator", [(shamr.SH_F64, 4), (shamr.SH_F32, 4), (shamr.SH_F64, 10),
+                                            (shamr.SH_F32, 10)])
 def test_full_size_512_sampled_parity(prec, integrator):
     # the 512^3 lattice in the launch configuration bench.py times (FP64 and FP32 storage,
     # RK4 and SSPRK3): 2 steps, then sampled cells against the oracle run on periodic crops
@@ -206,21 +207,23 @@ def test_stage_kernel_launch_shapes_bitwise(kind, nt, zc):
                                           (1, 64, None), (1, 13, [None, [16], [40]]), (2, 256, None),
                                           (2, 9, [[32], [16], [24]]), (3, 64, None),
                                           (3, 11, [[16], [8, 40], [24]])])
-def test_fused_four_stage_step_bitwise(shape, fzc, cuts, variant):
+@pytest.mark.parametrize("prec", [shamr.SH_F64, shamr.SH_F32])
+def test_fused_four_stage_step_bitwise(shape, fzc, cuts, variant, prec):
     # the fused step (all four stages in one kernel, overlapped tiles, z pipeline) must
-    # give the oracle's bits: single and multi-box level 0, ragged z chunks
+    # give the oracle's bits: single and multi-box level 0, ragged z chunks, FP64 and FP32
+    # storage
     n = 64
     U0 = random_state(n, float(n), 6)
     boxes = decompose(n, [c if c is not None else [] for c in cuts]) if cuts else decompose(n)
-    h = single_level(U0, boxes=boxes, beta=0)
+    h = single_level(U0, boxes=boxes, beta=0, prec=prec)
     h.set_tuning(8, 1, 0, fuse=4, fused_shape=shape, fused_tile_z=fzc, fused_variant=variant)
     h.profile(True)
-    ref = run_single_level(U0, 5, 0.1, 0.25, 1.0, beta=0)
+    ref = run_single_level(U0 if prec == shamr.SH_F64 else U0.astype(np.float32), 5, 0.1, 0.25, 1.0, beta=0)
     for _ in range(5):
         h.advance(0)
     prof = h.profile_read()
     assert prof["fused_step"][1] == 5 and prof["stage1"][1] == 0, prof
-    assert_bitwise(h.read_dense(0), ref, f"shape={shape} fzc={fzc} cuts={cuts} variant={variant}")
+    assert_bitwise(h.read_dense(0), ref.astype(np.float64), f"shape={shape} fzc={fzc} cuts={cuts} variant={variant}")
     h.close()
 
 
