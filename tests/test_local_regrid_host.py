@@ -1,7 +1,15 @@
 """Local regrid on the host (no GPU): the library's box computation equals the oracle's on
 random layouts and tags (box lists compared exactly, level by level through the nesting
 expansion), bad inputs are refused, the driver lays changed levels out coarsest first,
-and the local/global regrid policy follows its thresholds."""
+and the local/global regrid policy follows its thresholds.
+
+What the equality pins: the paper defines which cells a local regrid must add (every
+tagged cell with its buffer refined, the coarser levels grown for nesting, nothing
+removed) but not how added blocks are merged into boxes.  Those properties are pinned on
+the oracle alone (tests/test_oracle_local_regrid.py: coverage, nesting, no removal,
+periodic wrap); the merge order (x runs, then y, then z) is a choice made once for both
+sides, so on box lists the equality below checks that the library implements that
+choice, not the paper."""
 import numpy as np
 import pytest
 
