@@ -294,6 +294,11 @@ class Hierarchy:
         self.depth = max(order, ko_order)
         if integrator == 21:
             check_rkn(alpha, ko_order)
+        if integrator == 22:
+            # RKN5 is read for single periodic levels (appendix B's use), where
+            # run_single_level integrates it; a hierarchy would need coarse/fine fills at
+            # the nodes 1/5 and 2/3 of a step
+            raise ValueError("RKN5 (integrator 22) runs on single levels only (oracle.level.run_single_level)")
         self.levels: list[Level] = []
         self.trace: list[tuple] = []
         self.tee_on = False

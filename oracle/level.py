@@ -71,6 +71,25 @@ time eta_n + c_s h):
 (the stage states carry Pi_n unchanged; acc is float64; the weights times powers of h
 are formed once in float64, see scalars.rkn4_weights).
 
+RKN5 (integrator type 22, appendix E; appendix B's fifth-order Runge-Kutta-Nystrom
+method), also without a printed tableau: read as the four-stage fifth-order Nystrom
+tableau of scalars.RKN5_TABLEAU (nodes c = (0, 1/5, 2/3, 1); its order conditions up to
+order five are checked exactly in the tests).  Same EOM restriction as RKN4.  With
+w_ij = a_ij h^2, pb_i = bbar_i h^2, vb_i = b_i h, ch_i = c_i h (scalars.rkn5_weights)
+and the stage accelerations a_i = a(Y_i), Y_1 = psi_n:
+
+    stage 1: P = pb_1 a_1;  V = vb_1 a_1;  Y_2 = (y + ch_2 v) + w_21 a_1
+             S_3 = w_31 a_1;  S_4 = w_41 a_1
+    stage 2: P = P + pb_2 a_2;  V = V + vb_2 a_2;  Y_3 = (y + ch_3 v) + (S_3 + w_32 a_2)
+             S_4 = S_4 + w_42 a_2
+    stage 3: P = P + pb_3 a_3;  V = V + vb_3 a_3;  Y_4 = (y + h v) + (S_4 + w_43 a_3)
+    stage 4: psi_{n+1} = (y + h v) + P;  Pi_{n+1} = v + (V + vb_4 a_4)
+
+(bbar_4 = 0).  P and V are the float64 accumulator; the partial sums S_3 and S_4 of the
+later stage arguments are kept in the storage type (they ride in the Pi components of
+the stage states, which a Nystrom stage does not otherwise use): exact in FP64 storage,
+rounded to float32 in FP32 storage.
+
 Mixed precision (FP32 storage): U_n, U_a, U_b are float32 and the right-hand side is
 evaluated in float32 (scalars rounded to float32 once); every update above is done in
 float64 from the promoted float32 values and rounded to float32 on store, while ``acc``
@@ -80,7 +99,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from .scalars import rk4_weights, rkn4_weights, stage_scalars
+from .scalars import rk4_weights, rkn4_weights, rkn5_weights, stage_scalars
 
 
 def lap7(u: np.ndarray, inv_dx2) -> np.ndarray:
@@ -210,6 +229,53 @@ def rkn4_step(U: np.ndarray, eta_n: float, dt: float, inv_dx2: float, lam: float
     return X
 
 
+def rkn5_stage(s: int, X: np.ndarray, Un: np.ndarray, acc, S, eta_n: float, dt: float, inv_dx2: float,
+               lam: float, beta: int, order: int = 1):
+    """Stage s (0-based) of RKN5 (friction-free EOM).  X: the stage argument (psi in
+    X[:2]); acc: the float64 (P, V) accumulator, (4, ...); S: the partial sums in the
+    storage type, {3: S_3, 4: S_4} (2 components each).  Returns (acc, S, Y): Y the next
+    stage argument's psi (s < 3) or U_{n+1} (s = 3), in Un's precision."""
+    st = Un.dtype
+    W = rkn5_weights(dt)
+    w, pb, vb, ch = W["w"], W["pb"], W["vb"], W["ch"]
+    _, _, cp = stage_scalars(eta_n, dt, s, 0.0, lam, beta, integrator=22)
+    a = accel(X, inv_dx2, cp, order).astype(np.float64)
+    y = Un[:2].astype(np.float64)
+    v = Un[2:].astype(np.float64)
+    if s == 0:
+        acc = np.concatenate([pb[0] * a, vb[0] * a])
+        S = {3: (w[(3, 1)] * a).astype(st), 4: (w[(4, 1)] * a).astype(st)}
+        return acc, S, ((y + ch[1] * v) + w[(2, 1)] * a).astype(st)
+    if s == 1:
+        acc = np.concatenate([acc[:2] + pb[1] * a, acc[2:] + vb[1] * a])
+        Y = ((y + ch[2] * v) + (S[3].astype(np.float64) + w[(3, 2)] * a)).astype(st)
+        S = {3: S[3], 4: (S[4].astype(np.float64) + w[(4, 2)] * a).astype(st)}
+        return acc, S, Y
+    if s == 2:
+        acc = np.concatenate([acc[:2] + pb[2] * a, acc[2:] + vb[2] * a])
+        return acc, S, ((y + ch[3] * v) + (S[4].astype(np.float64) + w[(4, 3)] * a)).astype(st)
+    Y = np.empty_like(Un)
+    Y[:2] = ((y + ch[3] * v) + acc[:2]).astype(st)
+    Y[2:] = (v + (acc[2:] + vb[3] * a)).astype(st)
+    return acc, S, Y
+
+
+def rkn5_step(U: np.ndarray, eta_n: float, dt: float, inv_dx2: float, lam: float, beta: int, fill=None,
+              order: int = 1) -> np.ndarray:
+    """One RKN5 step of the friction-free EOM; ``fill(s, X)`` as for ``rk4_step`` (X holds
+    the stage argument's psi in X[:2])."""
+    X, acc, S = U, None, None
+    for s in range(4):
+        if s > 0 and fill is not None:
+            fill(s, X)
+        acc, S, Y = rkn5_stage(s, X, U, acc, S, eta_n, dt, inv_dx2, lam, beta, order)
+        if s < 3:
+            X = np.concatenate([Y, U[2:]])
+        else:
+            X = Y
+    return X
+
+
 def rk4_stage(s: int, X: np.ndarray, Un: np.ndarray, acc, eta_n: float, dt: float,
               inv_dx2: float, alpha: float, lam: float, beta: int, order: int = 1, ko=None):
     """Stage s (0-based) of classic RK4 in accumulator form.
@@ -238,9 +304,10 @@ def rk4_stage(s: int, X: np.ndarray, Un: np.ndarray, acc, eta_n: float, dt: floa
 
 
 def check_rkn(alpha: float, ko_order: int):
-    """RKN4 needs an acceleration independent of Pi: no friction, no dissipation."""
+    """The Nystrom methods (RKN4, RKN5) need an acceleration independent of Pi: no
+    friction, no dissipation."""
     if alpha != 0.0 or ko_order:
-        raise ValueError("RKN4 integrates the friction-free EOM only (alpha = 0, no dissipation)")
+        raise ValueError("RKN4 and RKN5 integrate the friction-free EOM only (alpha = 0, no dissipation)")
 
 
 def ssprk3_stage(s: int, X: np.ndarray, Un: np.ndarray, eta_n: float, dt: float, inv_dx2: float,
@@ -291,7 +358,7 @@ def run_single_level(U0: np.ndarray, nsteps: int, eta0: float, dt: float, dx: fl
                      alpha: float = 2.0, lam: float = 1.0, beta: int = 2,
                      callback=None, integrator: int = 4, order: int = 1, ko_order: int = 0,
                      ko_eps: float = 0.0) -> np.ndarray:
-    """nsteps steps (RK4, or SSPRK3 for integrator 3/10) of a periodic lattice with the
+    """nsteps steps (RK4; SSPRK3 for integrator 3/10; RKN4 / RKN5 for 21 / 22) of a periodic lattice with the
     Laplacian of the given order and, for ko_order 2 or 3, Kreiss-Oliger dissipation of
     strength ko_eps; step k starts at eta0 + k*dt.
 
@@ -301,11 +368,12 @@ def run_single_level(U0: np.ndarray, nsteps: int, eta0: float, dt: float, dx: fl
     stage_fractions(integrator)  # validates
     inv_dx2 = 1.0 / (dx * dx)
     ko = (ko_order, ko_coef(ko_order, ko_eps, dx)) if ko_order else None
-    if integrator == 21:
+    if integrator in (21, 22):
         check_rkn(alpha, ko_order)
+        nystrom = rkn4_step if integrator == 21 else rkn5_step
 
         def step(U, eta, dt, inv_dx2, alpha, lam, beta, order=1, ko=None):
-            return rkn4_step(U, eta, dt, inv_dx2, lam, beta, order=order)
+            return nystrom(U, eta, dt, inv_dx2, lam, beta, order=order)
     else:
         step = rk4_step if integrator == 4 else ssprk3_step
     U = U0.copy()
