@@ -86,7 +86,10 @@ typedef struct {
                            psi'' = a(psi) (appendices B and D use it).  It applies only
                            when the acceleration does not depend on Pi: alpha_fric must
                            be 0 and ko_order 0 (SH_EINVAL otherwise); it keeps RK4's
-                           float64 accumulator and is not fused on level 0 */
+                           float64 accumulator and is not fused on level 0; 22 = RKN5,
+                           read as a four-stage fifth-order Nystrom tableau (appendix B),
+                           with RKN4's restrictions, on single periodic levels only
+                           (max_level 0; no shadow level, no batching, not fused) */
   int32_t lap_order;    /* Laplacian order of appendix A (the minimal example's `order`):
                            1 (or 0) = 7-point, 2 = 13-point, 3 = 19-point stencil.  The
                            ghost shell of refined levels is that many cells deep (and so
@@ -128,8 +131,9 @@ size_t sh_arena_bytes(const sh_params* p, int32_t lev, int32_t nboxes, const int
    sh_hierarchy_destroy.  `hip_stream` is a hipStream_t (NULL = default stream) that all
    device work of this hierarchy is queued on.  Errors: SH_EINVAL (n0 < 1, L or cfl not
    positive, beta < 0, max_level < 0 or > 15, blocking_factor < 2, prec not 0/1,
-   integrator not 0, 3, 4 or 10, lap_order not 0..3, interp not 0, 1 or 4, ko_order not 0,
-   2 or 3, ko_eps negative or not finite), SH_EDEVICE (no HIP device). */
+   integrator not 0, 3, 4, 10, 21 or 22, RKN4/RKN5 with friction or dissipation, RKN5 with
+   max_level > 0, lap_order not 0..3, interp not 0, 1 or 4, ko_order not 0, 2 or 3,
+   ko_eps negative or not finite), SH_EDEVICE (no HIP device). */
 sh_status sh_hierarchy_create(const sh_params* p, void* hip_stream, sh_hierarchy* out);
 
 /* Set, change or remove the box layout of level `lev` (section II: boxes whose sides

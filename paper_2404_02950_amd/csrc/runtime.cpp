@@ -156,11 +156,18 @@ static int stages_of(const sh_params& p) {
   return (p.integrator == 3 || p.integrator == 10 || p.integrator == 21) ? 3 : 4;
 }
 // RKN4 (integrator type 21): three stages in the role cycle of the three-stage methods,
-// with a float64 accumulator like RK4's
-static bool rkn_of(const sh_params& p) { return p.integrator == 21; }
+// with a float64 accumulator like RK4's.  RKN5 (type 22): four stages over three slots in
+// a cycle of its own (role_slot), the float64 accumulator holding the position and
+// velocity sums; single periodic levels only.
+static bool rkn5_of(const sh_params& p) { return p.integrator == 22; }
+static bool rkn_of(const sh_params& p) { return p.integrator == 21 || rkn5_of(p); }
 static bool needs_acc(const sh_params& p) { return stages_of(p) == 4 || rkn_of(p); }
-// device stage id of stage s (0-based): RK4 0..3, SSPRK3 4..6, RKN4 7..9
-static int stage_id(const sh_params& p, int s) { return rkn_of(p) ? 7 + s : (stages_of(p) == 3 ? 4 + s : s); }
+// device stage id of stage s (0-based): RK4 0..3, SSPRK3 4..6, RKN4 7..9, RKN5 10..13
+static int stage_id(const sh_params& p, int s) {
+  return rkn5_of(p) ? 10 + s : (p.integrator == 21 ? 7 + s : (stages_of(p) == 3 ? 4 + s : s));
+}
+// slot-cycle code kept with the level scalars: the stage count, or 5 for RKN5
+static int slot_cycle(const sh_params& p) { return rkn5_of(p) ? 5 : stages_of(p); }
 
 // Laplacian order of appendix A (1, 2, 3: the 7-, 13-, 19-point stencil; 0 reads as 1).
 // Refined levels (and the shadow level) keep a ghost shell of that depth; level 0 keeps
@@ -564,7 +571,7 @@ static LevelScal make_ls(const sh_params& p, int l, long long k) {
   s.inv_dx2 = 1.0 / (s.dx * s.dx);
   s.ko = ko_coef(p, s.dx);
   s.beta = p.beta_pot;
-  s.nst = stages_of(p);
+  s.nst = slot_cycle(p);
   s.k = k;
   return s;
 }
@@ -911,10 +918,13 @@ static sh_status check_params(const sh_params* p) {
       p->blocking_factor < 2 || (p->blocking_factor & 1) || p->max_box < p->blocking_factor || p->n_error_buf < 0 ||
       (p->prec != SH_F64 && p->prec != SH_F32))
     return fail(SH_EINVAL, "invalid parameters");
-  if (p->integrator != 0 && p->integrator != 3 && p->integrator != 4 && p->integrator != 10 && p->integrator != 21)
-    return fail(SH_EINVAL, "integrator must be 0 or 4 (RK4), 3 or 10 (SSPRK3) or 21 (RKN4)");
-  if (p->integrator == 21 && (p->alpha_fric != 0.0 || p->ko_order != 0))
-    return fail(SH_EINVAL, "RKN4 integrates the friction-free EOM only (alpha_fric = 0, no dissipation)");
+  if (p->integrator != 0 && p->integrator != 3 && p->integrator != 4 && p->integrator != 10 && p->integrator != 21 &&
+      p->integrator != 22)
+    return fail(SH_EINVAL, "integrator must be 0 or 4 (RK4), 3 or 10 (SSPRK3), 21 (RKN4) or 22 (RKN5)");
+  if ((p->integrator == 21 || p->integrator == 22) && (p->alpha_fric != 0.0 || p->ko_order != 0))
+    return fail(SH_EINVAL, "RKN4 and RKN5 integrate the friction-free EOM only (alpha_fric = 0, no dissipation)");
+  if (p->integrator == 22 && p->max_level != 0)
+    return fail(SH_EINVAL, "RKN5 runs on single periodic levels only (max_level = 0)");
   if (p->lap_order < 0 || p->lap_order > 3) return fail(SH_EINVAL, "lap_order must be 0..3");
   if (p->interp != 0 && p->interp != 1 && p->interp != 4) return fail(SH_EINVAL, "interp must be 0, 1 or 4");
   if ((p->ko_order != 0 && p->ko_order != 2 && p->ko_order != 3) || !(p->ko_eps >= 0) || p->ko_eps == HUGE_VAL)
@@ -1293,7 +1303,19 @@ sh_status sh_advance_level(sh_hierarchy h, int32_t l, int32_t sub) {
     poison_before_fill(h, l, ROLE_UN, L.a1d.nblocks() ? 4 : fill_comps(h->p));
     return same_level_fill(h, l, ROLE_UN);
   }
-  if (stages_of(h->p) == 3) {
+  if (rkn5_of(h->p)) {
+    // RKN5 (level 0 only): stage inputs U_n, A, B, A; their same-level ghosts are filled
+    // before stages 2-4 (no coarse level to interpolate from)
+    const int in_role[4] = {ROLE_UN, ROLE_A, ROLE_B, ROLE_A};
+    for (int j = 0; j < 4; ++j) {
+      if (j > 0 && (s = fill(h, l, in_role[j], 0)) != SH_OK) return s;
+      h->rec(1, l, j, sub);
+      ev = h->prof_begin();
+      stage(h, L, stage_id(h->p, j));
+      h->prof_end(ev, j);
+      LAUNCHCHK();
+    }
+  } else if (stages_of(h->p) == 3) {
     // three-stage methods: stage inputs A and B at c = 1 and 1/2 (SSPRK3) or 1/2 and 1
     // (RKN4); alpha in quarters 2 sub + 2 c_s
     for (int j = 0; j < 3; ++j) {
@@ -1441,6 +1463,7 @@ sh_status sh_shadow_begin(sh_hierarchy h) {
   if (s != SH_OK || (s = not_capturing(h)) != SH_OK) return s;
   const sh_params& p = h->p;
   Level& L0 = h->lev[0];
+  if (rkn5_of(p)) return fail(SH_EINVAL, "no shadow level with RKN5 (single levels only)");
   if (L0.k % 2) return fail(SH_ESTATE, "the shadow starts when level 0 has taken an even number of steps");
   if (p.n0 % 2) return fail(SH_EINVAL, "the shadow level needs an even coarse size");
   for (const IBox& b : L0.boxes)
@@ -2031,7 +2054,7 @@ static sh_status batch_set_jobs(sh_batch b, int njobs, const sh_hierarchy* jobs)
     sh_hierarchy h = jobs[j];
     if (!h || h->lev.size() != 1 || h->st != b->st || h->p.prec != b->prec)
       return fail(SH_EINVAL, "batched jobs must be single-level hierarchies of one precision on one stream");
-    if (stages_of(h->p) != 4 || lap_order_of(h->p) != 1 || ko_of(h->p) != 0)
+    if (stages_of(h->p) != 4 || rkn5_of(h->p) || lap_order_of(h->p) != 1 || ko_of(h->p) != 0)
       return fail(SH_EINVAL, "batched jobs must use the RK4 integrator, the 7-point Laplacian and no dissipation");
     if (h->capturing) return not_capturing(h);
     versions.push_back(h->layout_version);

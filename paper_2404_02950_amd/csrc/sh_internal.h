@@ -43,7 +43,16 @@ __host__ __device__ inline int mod3(long long k) {
   return (int)(((unsigned)u % 3u + (unsigned)(u >> 32) % 3u) % 3u);
 }
 
+// RKN5 (nst = 5 here: four stages over three slots): U_n = slot[q] with q = 2k mod 3, A =
+// slot[q+1], B = slot[q+2]; the stages read (U_n, A, B, A) and write (A, B, A, B), so
+// U_{n+1} lands in slot[q+2] = slot[2(k+1) mod 3].
 __host__ __device__ inline int role_slot(int role, long long k, int nst) {
+  if (nst == 5) {
+    const int q = mod3(2 * k);
+    if (role == ROLE_UN) return q;
+    if (role == ROLE_B) return q == 0 ? 2 : q - 1;
+    return q == 2 ? 0 : q + 1;  // ROLE_A and ROLE_OLD
+  }
   if (nst == 3) {
     const int q = mod3(k);
     if (role == ROLE_UN) return q;
@@ -65,8 +74,9 @@ __host__ __device__ inline int role_slot(int role, const LevelScal& L) { return 
 // Fraction c_s of the step at which each evaluates the right-hand side:
 // RK4 (0, 1/2, 1/2, 1), SSPRK3 (0, 1, 1/2).
 // c_s of stage id s: RK4 ids 0..3 (0, 1/2, 1/2, 1), SSPRK3 ids 4..6 (0, 1, 1/2), RKN4 ids
-// 7..9 (0, 1/2, 1).
+// 7..9 (0, 1/2, 1), RKN5 ids 10..13 (0, 1/5, 2/3, 1).
 __host__ __device__ inline double stage_frac(int s) {
+  if (s >= 10) return s == 10 ? 0.0 : (s == 11 ? 0.2 : (s == 12 ? 2.0 / 3.0 : 1.0));
   return (s == 0 || s == 4 || s == 7) ? 0.0 : ((s == 3 || s == 5 || s == 9) ? 1.0 : 0.5);
 }
 

@@ -27,6 +27,14 @@
 //   stage 2: acc_psi = acc_psi + (h^2/3) a;    acc_Pi = acc_Pi + (2h/3) a
 //            B_psi = (y + h v) + (h^2/2) a,     B_Pi = v
 //   stage 3: A_psi = acc_psi;  A_Pi = acc_Pi + (h/6) a   (the new U_n)
+// RKN5 (stage ids 10..13; integrator type 22, read as a four-stage fifth-order Nystrom
+// tableau with nodes (0, 1/5, 2/3, 1); same restrictions, single periodic levels), with
+// w_ij = a_ij h^2, pb_i = bbar_i h^2, vb_i = b_i h, acc = (P, V):
+//   stage 1: P = pb1 a;  V = vb1 a;  A_psi = (y + h/5 v) + w21 a;  A_Pi = S_3 = w31 a;
+//            B_Pi = S_4 = w41 a
+//   stage 2: P += pb2 a; V += vb2 a; B_psi = (y + 2h/3 v) + (S_3 + w32 a);  B_Pi = S_4 + w42 a
+//   stage 3: P += pb3 a; V += vb3 a; A_psi = (y + h v) + (S_4 + w43 a)
+//   stage 4: B_psi = (y + h v) + P;  B_Pi = v + (V + vb4 a)   (the new U_n)
 // Kreiss-Oliger dissipation (KD = dissipation order 2 or 3; 0 = off) adds to the
 // right-hand side of every component Q = ko * K with
 //   K = (S_2 + (-4) S_1) + 18 u                    KD = 2
@@ -82,17 +90,20 @@ struct StagePtrs {
   const Glob<T>* Un;
   Glob<T>* Y;
   Glob<double>* acc;
+  Glob<T>* Z;  // RKN5 stage 1: slot B, whose Pi components take the partial sum S_4
 };
 
 template <typename T, int S>
 __device__ __forceinline__ StagePtrs<T> stage_ptrs(const BoxDev& B, const LevelScal& L) {
-  constexpr int in_role = (S == 0 || S == 4 || S == 7) ? ROLE_UN : ((S == 2 || S == 6 || S == 9) ? ROLE_B : ROLE_A);
-  constexpr int out_role = (S == 1 || S == 3 || S == 5 || S == 8) ? ROLE_B : ROLE_A;
+  constexpr int in_role =
+      (S == 0 || S == 4 || S == 7 || S == 10) ? ROLE_UN : ((S == 2 || S == 6 || S == 9 || S == 12) ? ROLE_B : ROLE_A);
+  constexpr int out_role = (S == 1 || S == 3 || S == 5 || S == 8 || S == 11 || S == 13) ? ROLE_B : ROLE_A;
   StagePtrs<T> p;
   p.X = (const Glob<T>*)slot_base(B, role_slot(in_role, L));
   p.Un = (const Glob<T>*)slot_base(B, role_slot(ROLE_UN, L));
   p.Y = (Glob<T>*)slot_base(B, role_slot(out_role, L));
   p.acc = (Glob<double>*)B.acc;
+  p.Z = S == 10 ? (Glob<T>*)slot_base(B, role_slot(ROLE_B, L)) : nullptr;
   return p;
 }
 
@@ -103,11 +114,45 @@ template <typename T, int S, bool NT, bool KO = false>
 __device__ __forceinline__ void stage_cell(const StageScal& sc, const Glob<T>* __restrict__ Un, Glob<T>* __restrict__ Y,
                                            Glob<double>* __restrict__ acc, long long cs, long long e, T p0, T p1,
                                            T q0, T q1, T lap0, T lap1, const double* un4, const double* acc4,
-                                           const T* ko4 = nullptr) {
+                                           const T* ko4 = nullptr, Glob<T>* __restrict__ Z = nullptr) {
   const T cf = (T)sc.cf, cp = (T)sc.cp;
   const T r2 = p0 * p0 + p1 * p1;
   const T pot = cp * (r2 - (T)1.0);
-  if constexpr (S >= 7) {
+  if constexpr (S >= 10) {
+    // RKN5: the acceleration, then the accumulator (position sum P, velocity sum V), the
+    // next stage argument and the partial sums S_3 (in the Pi components of the stage
+    // state) and S_4 (those of slot B); the tableau weights times powers of h formed
+    // once in float64 (numerator times the power, then the division)
+    const double h = sc.h1, hh = h * h;
+    const double a[2] = {(double)(lap0 - pot * p0), (double)(lap1 - pot * p1)};
+    const double s_in[2] = {(double)q0, (double)q1};  // S_3 at stage 2, S_4 at stage 3
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const double y = un4[c], v = un4[2 + c];
+      const long long ep = c * cs + e, eq = (2 + c) * cs + e;
+      if constexpr (S == 10) {
+        st<NT>(acc + ep, (hh / 24.0) * a[c]);
+        st<NT>(acc + eq, (h / 24.0) * a[c]);
+        st<NT>(Y + ep, (T)((y + (h / 5.0) * v) + (hh / 50.0) * a[c]));
+        st<NT>(Y + eq, (T)((-(hh / 27.0)) * a[c]));
+        st<NT>(Z + eq, (T)(((3.0 * hh) / 10.0) * a[c]));
+      } else if constexpr (S == 11) {
+        const double s4 = (double)ld<NT>((const Glob<T>*)(Y + eq));
+        st<NT>(acc + ep, acc4[c] + ((25.0 * hh) / 84.0) * a[c]);
+        st<NT>(acc + eq, acc4[2 + c] + ((125.0 * h) / 336.0) * a[c]);
+        st<NT>(Y + ep, (T)((y + ((2.0 * h) / 3.0) * v) + (s_in[c] + ((7.0 * hh) / 27.0) * a[c])));
+        st<NT>(Y + eq, (T)(s4 + (-((2.0 * hh) / 35.0)) * a[c]));
+      } else if constexpr (S == 12) {
+        st<NT>(acc + ep, acc4[c] + ((9.0 * hh) / 56.0) * a[c]);
+        st<NT>(acc + eq, acc4[2 + c] + ((27.0 * h) / 56.0) * a[c]);
+        st<NT>(Y + ep, (T)((y + h * v) + (s_in[c] + ((9.0 * hh) / 35.0) * a[c])));
+      } else {
+        st<NT>(Y + ep, (T)((y + h * v) + acc4[c]));
+        st<NT>(Y + eq, (T)(v + (acc4[2 + c] + ((5.0 * h) / 48.0) * a[c])));
+      }
+    }
+    return;
+  } else if constexpr (S >= 7) {
     // RKN4: the acceleration, then the position/velocity updates; weights times powers
     // of h formed once in float64
     const double h = sc.h1, hh = h * h;
@@ -181,14 +226,15 @@ __device__ __forceinline__ void stage_cell(const StageScal& sc, const Glob<T>* _
 }
 
 // Loads of the once-read streams of a cell: U_n (RK4 stages 2, 3; SSPRK3 stages 2, 3;
-// RKN4 stage 2) and acc (RK4 stages 2-4; RKN4 stages 2, 3).
+// RKN4 stage 2; every RKN5 stage) and acc (RK4 stages 2-4; RKN4 stages 2, 3; RKN5 stages
+// 2-4).
 template <typename T, int S, bool NT>
 __device__ __forceinline__ void stage_loads(const Glob<T>* __restrict__ Un, const Glob<double>* __restrict__ acc, long long cs,
                                             long long e, double* un4, double* acc4) {
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
-    if constexpr (S == 1 || S == 2 || S == 5 || S == 6 || S == 8) un4[c] = (double)ld<NT>(Un + c * cs + e);
-    if constexpr ((S >= 1 && S <= 3) || S == 8 || S == 9) acc4[c] = ld<NT>(acc + c * cs + e);
+    if constexpr (S == 1 || S == 2 || S == 5 || S == 6 || S == 8 || S >= 10) un4[c] = (double)ld<NT>(Un + c * cs + e);
+    if constexpr ((S >= 1 && S <= 3) || S == 8 || S == 9 || S >= 11) acc4[c] = ld<NT>(acc + c * cs + e);
   }
 }
 
@@ -268,9 +314,11 @@ __global__ __launch_bounds__(SH_BLOCK) void k_stage(const Tile* __restrict__ til
       ko4[2] = kc * ko_sum<T, KD>(Sq[0], q0);
       ko4[3] = kc * ko_sum<T, KD>(Sq[1], q1);
       if (active)
-        stage_cell<T, S, NT, true>(sc, Un, Y, P.acc, cs, e, w[0][HR], w[1][HR], q0, q1, lap0, lap1, un4, acc4, ko4);
+        stage_cell<T, S, NT, true>(sc, Un, Y, P.acc, cs, e, w[0][HR], w[1][HR], q0, q1, lap0, lap1, un4, acc4, ko4,
+                                   P.Z);
     } else {
-      if (active) stage_cell<T, S, NT>(sc, Un, Y, P.acc, cs, e, w[0][HR], w[1][HR], q0, q1, lap0, lap1, un4, acc4);
+      if (active)
+        stage_cell<T, S, NT>(sc, Un, Y, P.acc, cs, e, w[0][HR], w[1][HR], q0, q1, lap0, lap1, un4, acc4, nullptr, P.Z);
     }
 #pragma unroll
     for (int c = 0; c < 2; ++c)
@@ -404,7 +452,9 @@ __global__ __launch_bounds__(SH_WAVE * ROWS) void k_stage_lds(const Tile* __rest
         stage_cell<T, S, NT, true>(sc, Un, Y, P.acc, cs, e, win[0][HR], win[1][HR], q0, q1, lap0, lap1, un4, acc4,
                                    ko4);
     } else {
-      if (active) stage_cell<T, S, NT>(sc, Un, Y, P.acc, cs, e, win[0][HR], win[1][HR], q0, q1, lap0, lap1, un4, acc4);
+      if (active)
+        stage_cell<T, S, NT>(sc, Un, Y, P.acc, cs, e, win[0][HR], win[1][HR], q0, q1, lap0, lap1, un4, acc4, nullptr,
+                             P.Z);
     }
 #pragma unroll
     for (int c = 0; c < NC; ++c)
@@ -503,7 +553,11 @@ static void stage_launch2(int s, int kind, const Tile* tiles, int ntiles, const 
     case 6: stage_launch3<T, 6, NT, H>(kind, tiles, ntiles, boxes, st); break;
     case 7: stage_launch3<T, 7, NT, H>(kind, tiles, ntiles, boxes, st); break;
     case 8: stage_launch3<T, 8, NT, H>(kind, tiles, ntiles, boxes, st); break;
-    default: stage_launch3<T, 9, NT, H>(kind, tiles, ntiles, boxes, st); break;
+    case 9: stage_launch3<T, 9, NT, H>(kind, tiles, ntiles, boxes, st); break;
+    case 10: stage_launch3<T, 10, NT, H>(kind, tiles, ntiles, boxes, st); break;
+    case 11: stage_launch3<T, 11, NT, H>(kind, tiles, ntiles, boxes, st); break;
+    case 12: stage_launch3<T, 12, NT, H>(kind, tiles, ntiles, boxes, st); break;
+    default: stage_launch3<T, 13, NT, H>(kind, tiles, ntiles, boxes, st); break;
   }
 }
 
