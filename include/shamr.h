@@ -245,6 +245,25 @@ sh_status sh_cluster_boxes(int32_t M, int32_t nlevel_boxes, const int32_t* level
                            int32_t max_box, int32_t n_error_buf, double efficiency, int64_t ntag,
                            const int32_t* tags, int32_t* boxes_out, int32_t cap, int32_t* nboxes);
 
+/* Clustering with the tags of the next finer level carried down (section II.B: every
+   tagged cell is refined with its buffer; levels are rebuilt coarsest first, so level l's
+   new boxes must already leave room for the refinement of level l+1's tags).  As
+   sh_cluster_tags / sh_cluster_boxes, plus `ncarried` cells of level l+1 (x, y, z int32
+   triples in its index space, 0 <= x < 2M) whose coarse parents (x / 2), grown by
+   grow + n_error_buf cells (periodic), are clustered as if tagged; grow = 1 with
+   n_error_buf = 2 makes the rebuilt level l+1 reach at least 6 of its cells past every
+   carried tag (the tag's buffer of 2 and the nesting gap of half a blocking factor).
+   The tag lists are read only and stay the caller's.  Errors: those of the plain
+   calls, and SH_EINVAL for a carried cell outside level l+1's index space, ncarried < 0,
+   grow < 0 or grow > M. */
+sh_status sh_cluster_tags_carried(sh_hierarchy h, int32_t lev, int64_t ntag, const int32_t* tags, int64_t ncarried,
+                                  const int32_t* carried, int32_t grow, double efficiency, int32_t* boxes_out,
+                                  int32_t cap, int32_t* nboxes);
+sh_status sh_cluster_boxes_carried(int32_t M, int32_t nlevel_boxes, const int32_t* level_boxes,
+                                   int32_t blocking_factor, int32_t max_box, int32_t n_error_buf, double efficiency,
+                                   int64_t ntag, const int32_t* tags, int64_t ncarried, const int32_t* carried,
+                                   int32_t grow, int32_t* boxes_out, int32_t cap, int32_t* nboxes);
+
 /* Local regrid (section II, "Local versus global regrid"): instead of clustering all tags
    anew, keep every box of the finer level and grow it, by whole blocks of the blocking
    factor bf, where tagged cells (with their n_error_buf buffer) reach past it; coarser

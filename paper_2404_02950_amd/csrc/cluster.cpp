@@ -190,8 +190,60 @@ void br(Ctx& C, long long first, long long count) {
 
 }  // namespace
 
+// Marks the blocks met by the cubes [c - r, c + r] (periodic) around the cells c of a
+// list; with `halve`, c is the coarse parent (x / 2) of each listed finer-level cell.
+// Neighbouring entries (lists come in row order) mostly need the same blocks: entries
+// with the same y and z block ranges whose x block ranges overlap or touch are merged
+// into one range before anything is marked.
+static bool mark_blocks(Bits& tagged, int M, int b, int r, bool halve, const int32_t* cells, long long n,
+                        std::string& err) {
+  const int nb = M / b;
+  const int lim = halve ? 2 * M : M;
+  int plo[3] = {1, 1, 1}, phi[3] = {0, 0, 0};   // pending ranges (none while plo > phi)
+  auto flush = [&]() {
+    if (plo[0] > phi[0]) return;
+    if (phi[0] - plo[0] >= nb) {
+      plo[0] = 0;
+      phi[0] = nb - 1;
+    }
+    for (int z = plo[2]; z <= phi[2]; ++z)
+      for (int y = plo[1]; y <= phi[1]; ++y) tagged.set_x(plo[0], phi[0], wrap(y, nb), wrap(z, nb));
+  };
+  for (long long t = 0; t < n; ++t) {
+    int c[3], lo[3], hi[3];
+    for (int d = 0; d < 3; ++d) {
+      c[d] = cells[3 * t + d];
+      if (c[d] < 0 || c[d] >= lim) {
+        err = halve ? "carried tag outside the finer level" : "tag outside the level";
+        return false;
+      }
+      if (halve) c[d] >>= 1;
+      lo[d] = floordiv(c[d] - r, b);
+      hi[d] = floordiv(c[d] + r, b);
+      if (hi[d] - lo[d] >= nb) {
+        lo[d] = 0;
+        hi[d] = nb - 1;
+      }
+    }
+    if (lo[1] == plo[1] && lo[2] == plo[2] && hi[1] == phi[1] && hi[2] == phi[2] && lo[0] <= phi[0] + 1 &&
+        hi[0] >= plo[0] - 1) {
+      plo[0] = std::min(plo[0], lo[0]);
+      phi[0] = std::max(phi[0], hi[0]);
+      continue;
+    }
+    flush();
+    for (int d = 0; d < 3; ++d) {
+      plo[d] = lo[d];
+      phi[d] = hi[d];
+    }
+  }
+  flush();
+  return true;
+}
+
 bool cluster_level(int M, const std::vector<IBox>& level_boxes, bool full_level, int bf, int max_box, int nbuf,
-                   double efficiency, const int32_t* tags, long long ntag, std::vector<IBox>& out, std::string& err) {
+                   double efficiency, const int32_t* tags, long long ntag, std::vector<IBox>& out, std::string& err,
+                   const int32_t* carried, long long ncarried, int carry_grow) {
   out.clear();
   if (bf < 2 || (bf & 1)) {
     err = "blocking factor must be even";
@@ -213,34 +265,9 @@ bool cluster_level(int M, const std::vector<IBox>& level_boxes, bool full_level,
   // few MB would be page-faulted in on every regrid)
   thread_local Bits tagged, cov;
   tagged.init(nb);
-  // neighbouring tags (the list comes in row order) mostly need the same blocks: a tag
-  // whose block ranges equal the previous tag's marks nothing new
-  int plo[3] = {1, 1, 1}, phi[3] = {0, 0, 0};
-  for (long long t = 0; t < ntag; ++t) {
-    int c[3], lo[3], hi[3];
-    for (int d = 0; d < 3; ++d) {
-      c[d] = tags[3 * t + d];
-      if (c[d] < 0 || c[d] >= M) {
-        err = "tag outside the level";
-        return false;
-      }
-      lo[d] = floordiv(c[d] - nbuf, b);
-      hi[d] = floordiv(c[d] + nbuf, b);
-      if (hi[d] - lo[d] >= nb) {
-        lo[d] = 0;
-        hi[d] = nb - 1;
-      }
-    }
-    if (lo[0] == plo[0] && lo[1] == plo[1] && lo[2] == plo[2] && hi[0] == phi[0] && hi[1] == phi[1] &&
-        hi[2] == phi[2])
-      continue;
-    for (int d = 0; d < 3; ++d) {
-      plo[d] = lo[d];
-      phi[d] = hi[d];
-    }
-    for (int z = lo[2]; z <= hi[2]; ++z)
-      for (int y = lo[1]; y <= hi[1]; ++y) tagged.set_x(lo[0], hi[0], wrap(y, nb), wrap(z, nb));
-  }
+  if (!mark_blocks(tagged, M, b, nbuf, false, tags, ntag, err)) return false;
+  // tags of the next finer level: their coarse parents grown by carry_grow + nbuf cells
+  if (ncarried > 0 && !mark_blocks(tagged, M, b, carry_grow + nbuf, true, carried, ncarried, err)) return false;
   if (!full_level) {
     cov.init(nb);
     for (const IBox& L : level_boxes) {

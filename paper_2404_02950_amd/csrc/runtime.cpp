@@ -1779,6 +1779,33 @@ sh_status sh_cluster_boxes(int32_t M, int32_t nlevel_boxes, const int32_t* level
   return emit_boxes(out, boxes_out, cap, nboxes);
 }
 
+sh_status sh_cluster_boxes_carried(int32_t M, int32_t nlevel_boxes, const int32_t* level_boxes, int32_t bf,
+                                   int32_t max_box, int32_t n_error_buf, double efficiency, int64_t ntag,
+                                   const int32_t* tags, int64_t ncarried, const int32_t* carried, int32_t grow,
+                                   int32_t* boxes_out, int32_t cap, int32_t* nboxes) {
+  if (ncarried < 0 || (ncarried > 0 && !carried) || grow < 0 || grow > M)
+    return fail(SH_EINVAL, "bad carried tags");
+  if (M < 1 || nlevel_boxes < 0 || (nlevel_boxes > 0 && !level_boxes) || ntag < 0 || (ntag > 0 && !tags) ||
+      !nboxes || cap < 0 || (cap > 0 && !boxes_out) || !(efficiency > 0) || efficiency > 1 || n_error_buf < 0 ||
+      max_box < bf)
+    return fail(SH_EINVAL, "bad clustering arguments");
+  std::vector<IBox> lb;
+  for (int i = 0; i < nlevel_boxes; ++i) {
+    IBox b;
+    for (int d = 0; d < 3; ++d) {
+      b.lo[d] = level_boxes[6 * i + d];
+      b.hi[d] = level_boxes[6 * i + 3 + d];
+    }
+    lb.push_back(b);
+  }
+  std::vector<IBox> out;
+  std::string err;
+  if (!cluster_level(M, lb, nlevel_boxes == 0, bf, max_box, n_error_buf, efficiency, tags, ntag, out, err, carried,
+                     ncarried, grow))
+    return fail(SH_EINVAL, err);
+  return emit_boxes(out, boxes_out, cap, nboxes);
+}
+
 static bool read_boxes(int32_t n, const int32_t* in, std::vector<IBox>& out) {
   out.clear();
   if (n < 0 || (n > 0 && !in)) return false;
@@ -1830,6 +1857,24 @@ sh_status sh_cluster_tags(sh_hierarchy h, int32_t l, int64_t ntag, const int32_t
   std::string err;
   if (!cluster_level(L.M, L.boxes, l == 0, p.blocking_factor, p.max_box, p.n_error_buf, efficiency, tags, ntag, out,
                      err))
+    return fail(SH_EINVAL, err);
+  return emit_boxes(out, boxes_out, cap, nboxes);
+}
+
+sh_status sh_cluster_tags_carried(sh_hierarchy h, int32_t l, int64_t ntag, const int32_t* tags, int64_t ncarried,
+                                  const int32_t* carried, int32_t grow, double efficiency, int32_t* boxes_out,
+                                  int32_t cap, int32_t* nboxes) {
+  sh_status s = check_level(h, l);
+  if (s != SH_OK) return s;
+  if (ntag < 0 || (ntag > 0 && !tags) || ncarried < 0 || (ncarried > 0 && !carried) || grow < 0 ||
+      grow > h->lev[l].M || !nboxes || cap < 0 || (cap > 0 && !boxes_out) || !(efficiency > 0) || efficiency > 1)
+    return fail(SH_EINVAL, "bad clustering arguments");
+  const sh_params& p = h->p;
+  const Level& L = h->lev[l];
+  std::vector<IBox> out;
+  std::string err;
+  if (!cluster_level(L.M, L.boxes, l == 0, p.blocking_factor, p.max_box, p.n_error_buf, efficiency, tags, ntag, out,
+                     err, carried, ncarried, grow))
     return fail(SH_EINVAL, err);
   return emit_boxes(out, boxes_out, cap, nboxes);
 }

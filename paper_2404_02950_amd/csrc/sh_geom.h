@@ -170,9 +170,11 @@ inline long long covered_volume(const IBox& q, int M, const BoxBins& bins, const
 }
 
 // Berger-Rigoutsos clustering of the tags of a level into boxes of the next level
-// (implemented in cluster.cpp).
+// (implemented in cluster.cpp).  `carried` (ncarried cells of the level above, index
+// space 2M) adds the blocks met by their coarse parents grown by carry_grow + nbuf cells.
 bool cluster_level(int M, const std::vector<IBox>& level_boxes, bool full_level, int bf, int max_box, int nbuf,
-                   double efficiency, const int32_t* tags, long long ntag, std::vector<IBox>& out, std::string& err);
+                   double efficiency, const int32_t* tags, long long ntag, std::vector<IBox>& out, std::string& err,
+                   const int32_t* carried = nullptr, long long ncarried = 0, int carry_grow = 0);
 
 // Local regrid (implemented in local_regrid.cpp), on the block grid of the finer level
 // (blocks of bf cells).  local_tag_boxes: boxes to add to level l+1 (fine index, M_fine

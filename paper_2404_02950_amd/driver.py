@@ -141,11 +141,10 @@ def regrid(h, max_level: int, layout_for=None, efficiency: float = 0.7, max_leve
         ntag, idx = h.tag(lev)
         t1 = time.perf_counter()
         counts.append(ntag)
-        if lev + 1 in carried:
-            idx = merge_tags(idx, carried_tags(carried[lev + 1], h.params.n0 << lev,
-                                                n_error_buf=h.params.n_error_buf,
-                                                blocking_factor=h.params.blocking_factor))
-        boxes = layout_for(lev, ntag, idx) if layout_for is not None else h.cluster(lev, idx, efficiency)
+        if layout_for is not None:
+            boxes = layout_for(lev, ntag, idx)
+        else:      # the carried tags join inside the clustering (as carried_tags would)
+            boxes = h.cluster(lev, idx, efficiency, carried=carried.get(lev + 1))
         t2 = time.perf_counter()
         if boxes and max_level_bytes is not None:
             need = h.arena_bytes(lev + 1, boxes)

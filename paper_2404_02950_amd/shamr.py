@@ -57,6 +57,11 @@ _PROTOS = {
                                   POINTER(c_int32)]),
     "sh_cluster_boxes": (c_int32, [c_int32, c_int32, c_void_p, c_int32, c_int32, c_int32, c_double, c_int64,
                                    c_void_p, c_void_p, c_int32, POINTER(c_int32)]),
+    "sh_cluster_tags_carried": (c_int32, [c_void_p, c_int32, c_int64, c_void_p, c_int64, c_void_p, c_int32,
+                                          c_double, c_void_p, c_int32, POINTER(c_int32)]),
+    "sh_cluster_boxes_carried": (c_int32, [c_int32, c_int32, c_void_p, c_int32, c_int32, c_int32, c_double,
+                                           c_int64, c_void_p, c_int64, c_void_p, c_int32, c_void_p, c_int32,
+                                           POINTER(c_int32)]),
     "sh_local_tag_boxes": (c_int32, [c_int32, c_int32, c_void_p, c_int32, c_int32, c_int32, c_int64, c_void_p,
                                      c_void_p, c_int32, POINTER(c_int32)]),
     "sh_local_nest_boxes": (c_int32, [c_int32, c_int32, c_void_p, c_int32, c_void_p, c_int32, c_int32, c_void_p,
@@ -134,18 +139,27 @@ def box_shape(b):
 
 
 def cluster_boxes(M: int, level_boxes, tags, blocking_factor: int = 8, max_box: int = 64,
-                  n_error_buf: int = 2, efficiency: float = 0.7):
-    """Berger-Rigoutsos clustering of level tags into next-level boxes (host only)."""
+                  n_error_buf: int = 2, efficiency: float = 0.7, carried=None, grow: int = 1):
+    """Berger-Rigoutsos clustering of level tags into next-level boxes (host only).
+    ``carried``: tags of the next finer level (its index space) clustered through their
+    coarse parents grown by ``grow`` + n_error_buf cells (sh_cluster_boxes_carried)."""
     lib = load()
     lb = np.ascontiguousarray(np.asarray(level_boxes, np.int32).reshape(-1, 6))
     t = np.ascontiguousarray(np.asarray(tags, np.int32).reshape(-1, 3))
+    f = None if carried is None else np.ascontiguousarray(np.asarray(carried, np.int32).reshape(-1, 3))
     cap = 4096
     while True:
         out = np.empty((cap, 6), np.int32)
         nb = c_int32()
-        st = lib.sh_cluster_boxes(M, len(lb), lb.ctypes.data_as(c_void_p), blocking_factor, max_box, n_error_buf,
-                                  efficiency, len(t), t.ctypes.data_as(c_void_p), out.ctypes.data_as(c_void_p),
-                                  cap, ctypes.byref(nb))
+        if f is None:
+            st = lib.sh_cluster_boxes(M, len(lb), lb.ctypes.data_as(c_void_p), blocking_factor, max_box,
+                                      n_error_buf, efficiency, len(t), t.ctypes.data_as(c_void_p),
+                                      out.ctypes.data_as(c_void_p), cap, ctypes.byref(nb))
+        else:
+            st = lib.sh_cluster_boxes_carried(M, len(lb), lb.ctypes.data_as(c_void_p), blocking_factor, max_box,
+                                              n_error_buf, efficiency, len(t), t.ctypes.data_as(c_void_p), len(f),
+                                              f.ctypes.data_as(c_void_p), grow, out.ctypes.data_as(c_void_p), cap,
+                                              ctypes.byref(nb))
         if st == SH_ENOMEM and nb.value > cap:
             cap = nb.value
             continue
@@ -446,14 +460,22 @@ class Hierarchy:
             o += sz
         return res
 
-    def cluster(self, lev: int, tags: np.ndarray, efficiency: float = 0.7):
+    def cluster(self, lev: int, tags: np.ndarray, efficiency: float = 0.7, carried=None, grow: int = 1):
+        """Boxes of level lev+1 from level lev's tags (sh_cluster_tags); with ``carried``,
+        tags of level lev+1 join through their grown coarse parents (sh_cluster_tags_carried)."""
         t = np.ascontiguousarray(np.asarray(tags, np.int32).reshape(-1, 3))
+        f = None if carried is None else np.ascontiguousarray(np.asarray(carried, np.int32).reshape(-1, 3))
         cap = 4096
         while True:
             out = np.empty((cap, 6), np.int32)
             nb = c_int32()
-            st = self.lib.sh_cluster_tags(self.h, lev, len(t), t.ctypes.data_as(c_void_p), efficiency,
-                                          out.ctypes.data_as(c_void_p), cap, ctypes.byref(nb))
+            if f is None:
+                st = self.lib.sh_cluster_tags(self.h, lev, len(t), t.ctypes.data_as(c_void_p), efficiency,
+                                              out.ctypes.data_as(c_void_p), cap, ctypes.byref(nb))
+            else:
+                st = self.lib.sh_cluster_tags_carried(self.h, lev, len(t), t.ctypes.data_as(c_void_p), len(f),
+                                                      f.ctypes.data_as(c_void_p), grow, efficiency,
+                                                      out.ctypes.data_as(c_void_p), cap, ctypes.byref(nb))
             if st == SH_ENOMEM and nb.value > cap:
                 cap = nb.value
                 continue

@@ -50,8 +50,11 @@ def test_carried_regrid_on_the_gpu_matches_the_oracle_on_its_layouts():
     made = {}
     cluster = hg.cluster
 
-    def recording_cluster(lev, idx, efficiency=0.7):
-        boxes = cluster(lev, idx, efficiency)
+    def recording_cluster(lev, idx, efficiency=0.7, carried=None):
+        boxes = cluster(lev, idx, efficiency, carried=carried)
+        if carried is not None:      # carried inside the library = the carried list joined
+            joined = driver.merge_tags(idx, driver.carried_tags(carried, N0 << lev))
+            assert boxes == cluster(lev, joined, efficiency), lev
         made[lev + 1] = boxes
         return boxes
 

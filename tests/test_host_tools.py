@@ -81,7 +81,7 @@ class _FakeHierarchy:
     def tag(self, lev):
         return 10 * (lev + 1), None
 
-    def cluster(self, lev, idx, efficiency):
+    def cluster(self, lev, idx, efficiency, carried=None):
         return self._boxes[lev]
 
     def arena_bytes(self, lev, boxes):

@@ -25,6 +25,10 @@ def _rebuild(carry):
     t0 = _blob((10, 10, 10), (13, 13, 13))            # level-0 tags (coarse cells)
     t1 = _blob((44, 24, 24), (46, 26, 26))            # tags level 1 holds now, far from t0's refinement
     level0 = [(0, 0, 0, M0 - 1, M0 - 1, M0 - 1)]
+    if carry == "library":                            # carried inside the clustering call
+        l1 = shamr.cluster_boxes(M0, level0, t0, BF, MAX_BOX, NBUF, carried=t1)
+        l2 = shamr.cluster_boxes(2 * M0, l1, t1, BF, MAX_BOX, NBUF) if l1 else []
+        return t1, l1, l2
     tags0 = driver.merge_tags(t0, driver.carried_tags(t1, M0)) if carry else t0
     l1 = shamr.cluster_boxes(M0, level0, tags0, BF, MAX_BOX, NBUF)
     l2 = shamr.cluster_boxes(2 * M0, l1, t1, BF, MAX_BOX, NBUF) if l1 else []
@@ -71,7 +75,7 @@ def test_carried_tags_of_many_fine_tags_are_fast():
     assert c.shape[1] == 3 and len(c) <= (512 // 4) ** 3
 
 
-@pytest.mark.parametrize("carry", [False, True])
+@pytest.mark.parametrize("carry", [False, True, "library"])
 def test_a_level_one_tag_keeps_its_refinement_only_when_carried(carry):
     t1, l1, l2 = _rebuild(carry)
     assert not check_layout(l1, 2 * M0, np.ones((M0,) * 3, bool), BF, MAX_BOX)
@@ -84,4 +88,56 @@ def test_a_level_one_tag_keeps_its_refinement_only_when_carried(carry):
     for x, y, z in t1:
         want[(z - NBUF):(z + NBUF + 1), (y - NBUF):(y + NBUF + 1), (x - NBUF):(x + NBUF + 1)] = True
     covered = bool(np.all(refined[want]))
-    assert covered == carry
+    assert covered == bool(carry)
+
+
+def _random_layout(rng, M, n):
+    """n boxes of whole blocking-factor blocks, disjoint (first come first kept)."""
+    occ = np.zeros((M // BF,) * 3, bool)
+    out = []
+    for _ in range(50 * n):
+        if len(out) == n:
+            break
+        lo = rng.integers(0, M // BF, 3)
+        sz = rng.integers(1, 5, 3)
+        hi = np.minimum(lo + sz, M // BF)
+        if occ[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]].any():
+            continue
+        occ[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]] = True
+        out.append(tuple(int(v) for v in np.concatenate([lo * BF, hi * BF - 1])))
+    return out
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_carried_inside_the_clustering_equals_the_carried_list(seed):
+    # the library marks the blocks met by the fine tags' grown parents itself: the boxes
+    # must equal those of clustering the level's tags joined by carried_tags (whose block
+    # set is pinned by brute force above), on level 0 and on a refined level, with tags
+    # at the periodic ends and fine tags far from and next to the level's own tags
+    rng = np.random.default_rng(seed)
+    for M, level in ((32, [(0, 0, 0, 31, 31, 31)]), (64, None)):
+        if level is None:
+            level = _random_layout(rng, M, 12)
+        valid = boxes_mask(level, M)
+        cells = np.argwhere(valid)[:, ::-1].astype(np.int32)          # (x, y, z)
+        tags = cells[rng.choice(len(cells), min(len(cells), 40), replace=False)]
+        fine = rng.integers(0, 2 * M, (60, 3), dtype=np.int32)
+        fine = np.concatenate([fine, 2 * tags[:10] + 1, np.array([[0, 0, 0], [2 * M - 1] * 3], np.int32)])
+        for eff in (0.5, 0.7, 0.9):
+            want = shamr.cluster_boxes(M, level, driver.merge_tags(tags, driver.carried_tags(fine, M)), BF,
+                                       MAX_BOX, NBUF, eff)
+            got = shamr.cluster_boxes(M, level, tags, BF, MAX_BOX, NBUF, eff, carried=fine)
+            assert got == want, (M, eff)
+        assert shamr.cluster_boxes(M, level, tags, BF, MAX_BOX, NBUF, carried=fine[:0]) == \
+            shamr.cluster_boxes(M, level, tags, BF, MAX_BOX, NBUF)
+
+
+def test_carried_cells_outside_the_finer_level_are_refused():
+    level0 = [(0, 0, 0, M0 - 1, M0 - 1, M0 - 1)]
+    for bad in ([2 * M0, 0, 0], [0, -1, 0]):
+        with pytest.raises(shamr.ShError):
+            shamr.cluster_boxes(M0, level0, _blob((1, 1, 1), (2, 2, 2)), BF, MAX_BOX, NBUF,
+                                carried=np.array([bad], np.int32))
+    with pytest.raises(shamr.ShError):
+        shamr.cluster_boxes(M0, level0, _blob((1, 1, 1), (2, 2, 2)), BF, MAX_BOX, NBUF,
+                            carried=_blob((1, 1, 1), (2, 2, 2)), grow=-1)
