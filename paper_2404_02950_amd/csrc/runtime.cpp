@@ -120,7 +120,7 @@ struct LayoutGeom {
   int ng = 1;                       // ghost layers
   int tee_nc = 1;                   // truncation error estimates per valid cell (1 or 4)
   int esize;                        // bytes of a stored value (8 or 4)
-  int xoff;                         // elements before x = 0 in a row
+  int xoff;                         // elements before x = 0 in a row (x = 0 on 64 or 128 B)
   std::vector<long long> box_off;   // element offset of each box block
   std::vector<int> px;              // per-box x pitch
   std::vector<long long> cs;        // per-box component stride
@@ -203,7 +203,11 @@ static void make_geom(int prec, int ng, const std::vector<IBox>& boxes, LayoutGe
   g.ng = ng;
   g.tee_nc = tee_nc;
   g.esize = prec == SH_F64 ? 8 : 4;
-  g.xoff = 64 / g.esize;
+  // x = 0 starts a 128-byte line for float64 where the ghost shell is thin (refined and
+  // shadow levels: narrow rows of 8-64 cells then fill whole lines), 64 bytes in
+  // otherwise (level 0's shell of 4, whose x-ghost runs the copy plan widens to whole
+  // sectors; float32 rows, which a 128-byte start only makes longer)
+  g.xoff = (ng < SH_NG0 && g.esize == 8 ? 128 : 64) / g.esize;
   g.box_off.clear();
   g.px.clear();
   g.cs.clear();
@@ -1068,6 +1072,7 @@ static sh_status set_box_tables(sh_hierarchy h, LevelScal* ls, Level& L) {
     if (moff > 0x7fffffffLL) return fail(SH_EINVAL, "level too large for 32-bit mask offsets");
     d.mask_off = (int)moff;
     d.ng = L.g.ng;
+    d.xoff = L.g.xoff;
     moff += (long long)d.nx * d.ny * d.nz;
     L.hbox.push_back(d);
     xv.push_back(xv.back() + 4LL * d.nx * d.ny * d.nz);

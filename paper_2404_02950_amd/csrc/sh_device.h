@@ -6,9 +6,6 @@
 
 #pragma clang fp contract(off)
 
-template <typename T> struct Xoff;
-template <> struct Xoff<double> { static constexpr int v = 8; };
-template <> struct Xoff<float> { static constexpr int v = 16; };
 
 // ---------------------------------------------------------------------------------
 // Per-stage scalars from the level's device scalars.  The right-hand side of stage s is
@@ -80,7 +77,7 @@ __device__ __forceinline__ int xcd_remap(int b, int n) {
 // Element index of box-local cell (i, j, k), -ng <= i < nx + ng etc., in component 0.
 template <typename T>
 __device__ __forceinline__ long long elem(const BoxDev& B, int i, int j, int k) {
-  return ((long long)(k + B.ng) * B.py + (j + B.ng)) * (long long)B.px + Xoff<T>::v + i;
+  return ((long long)(k + B.ng) * B.py + (j + B.ng)) * (long long)B.px + B.xoff + i;
 }
 
 // Box storage is global memory, but the box records hold generic pointers; reading it

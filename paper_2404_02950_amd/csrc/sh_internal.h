@@ -90,6 +90,7 @@ struct BoxDev {
   int lo[3];          // global index of cell (0,0,0) on the box's level
   int mask_off;       // offset of the box's valid cells in per-level byte masks
   int ng;             // ghost layers stored around the box
+  int xoff;           // elements before x = 0 in a row
 };
 
 // Wave tile: one wavefront covers a TX x (64/TX) footprint of a box and marches in z.
