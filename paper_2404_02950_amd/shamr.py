@@ -147,7 +147,7 @@ def cluster_boxes(M: int, level_boxes, tags, blocking_factor: int = 8, max_box: 
     lb = np.ascontiguousarray(np.asarray(level_boxes, np.int32).reshape(-1, 6))
     t = np.ascontiguousarray(np.asarray(tags, np.int32).reshape(-1, 3))
     f = None if carried is None else np.ascontiguousarray(np.asarray(carried, np.int32).reshape(-1, 3))
-    cap = 4096
+    cap = _cluster_cap(len(t) + (0 if f is None else len(f)))
     while True:
         out = np.empty((cap, 6), np.int32)
         nb = c_int32()
@@ -167,9 +167,18 @@ def cluster_boxes(M: int, level_boxes, tags, blocking_factor: int = 8, max_box: 
         return [tuple(r) for r in out[:nb.value].tolist()]
 
 
+def _cluster_cap(ntags: int) -> int:
+    """First output capacity of a clustering call: a call whose boxes do not fit is run
+    again with the count it reports, which clusters everything a second time, so the
+    first buffer is sized from the tag count (a box holds at least one tag; in practice
+    well under one box per 8 tags) and never below 65536 boxes (1.5 MiB, not touched
+    beyond what is written)."""
+    return max(1 << 16, ntags // 8)
+
+
 def _boxes_call(fn):
     """Run a box-producing library call with a growing output capacity."""
-    cap = 4096
+    cap = 1 << 16
     while True:
         out = np.empty((cap, 6), np.int32)
         nb = c_int32()
@@ -465,7 +474,7 @@ class Hierarchy:
         tags of level lev+1 join through their grown coarse parents (sh_cluster_tags_carried)."""
         t = np.ascontiguousarray(np.asarray(tags, np.int32).reshape(-1, 3))
         f = None if carried is None else np.ascontiguousarray(np.asarray(carried, np.int32).reshape(-1, 3))
-        cap = 4096
+        cap = _cluster_cap(len(t) + (0 if f is None else len(f)))
         while True:
             out = np.empty((cap, 6), np.int32)
             nb = c_int32()
