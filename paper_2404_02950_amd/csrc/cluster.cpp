@@ -195,10 +195,15 @@ void br(Ctx& C, long long first, long long count) {
 // Neighbouring entries (lists come in row order) mostly need the same blocks: entries
 // with the same y and z block ranges whose x block ranges overlap or touch are merged
 // into one range before anything is marked.
-static bool mark_blocks(Bits& tagged, int M, int b, int r, bool halve, const int32_t* cells, long long n,
-                        std::string& err) {
+template <bool POW2>
+static bool mark_blocks_t(Bits& tagged, int M, int b, int r, bool halve, const int32_t* cells, long long n,
+                          std::string& err) {
   const int nb = M / b;
   const int lim = halve ? 2 * M : M;
+  int sh = 0;
+  while ((1 << sh) < b) ++sh;
+  // floor division by the block size (an arithmetic shift rounds down for negative values)
+  auto fdiv = [&](int a) { return POW2 ? (a >> sh) : floordiv(a, b); };
   int plo[3] = {1, 1, 1}, phi[3] = {0, 0, 0};   // pending ranges (none while plo > phi)
   auto flush = [&]() {
     if (plo[0] > phi[0]) return;
@@ -218,8 +223,8 @@ static bool mark_blocks(Bits& tagged, int M, int b, int r, bool halve, const int
         return false;
       }
       if (halve) c[d] >>= 1;
-      lo[d] = floordiv(c[d] - r, b);
-      hi[d] = floordiv(c[d] + r, b);
+      lo[d] = fdiv(c[d] - r);
+      hi[d] = fdiv(c[d] + r);
       if (hi[d] - lo[d] >= nb) {
         lo[d] = 0;
         hi[d] = nb - 1;
@@ -239,6 +244,70 @@ static bool mark_blocks(Bits& tagged, int M, int b, int r, bool halve, const int
   }
   flush();
   return true;
+}
+
+// The level's own tags when 2r equals the block size b (the usual n_error_buf = 2 with
+// a blocking factor of 8): every axis then meets exactly two blocks, the tag's block B and
+// B + 1 when its offset in the block is >= r, else B - 1 and B.  One bit per tag goes into
+// the bitset of its octant (the direction of the second block along each axis), each
+// octant bitset is grown by one block towards its octant along x, y and z (periodically)
+// and ORed into the tagged blocks: the same set as marking each tag's 2 x 2 x 2 blocks,
+// at one bit write per tag.  Used for long lists on rows of whole words.
+static bool mark_octants(Bits& tagged, int M, int b, int sh, const int32_t* cells, long long n, std::string& err) {
+  const int nb = M / b, r = b / 2, W = nb / 64;
+  thread_local Bits oct[8];
+  for (Bits& o : oct) o.init(nb);
+  for (long long t = 0; t < n; ++t) {
+    const int x = cells[3 * t], y = cells[3 * t + 1], z = cells[3 * t + 2];
+    if (x < 0 || x >= M || y < 0 || y >= M || z < 0 || z >= M) {
+      err = "tag outside the level";
+      return false;
+    }
+    const int o = ((x & (b - 1)) >= r ? 1 : 0) | ((y & (b - 1)) >= r ? 2 : 0) | ((z & (b - 1)) >= r ? 4 : 0);
+    oct[o].set(x >> sh, y >> sh, z >> sh);
+  }
+  const size_t nw = oct[0].w.size(), row = W, plane = (size_t)nb * W;
+  std::vector<uint64_t> a(nw), c(nw);
+  for (int o = 0; o < 8; ++o) {
+    const std::vector<uint64_t>& s = oct[o].w;
+    // x: each row of W words, shifted by one block up (o & 1) or down, with wrap
+    for (size_t r0 = 0; r0 < nw; r0 += row)
+      for (int k = 0; k < W; ++k) {
+        const uint64_t v = s[r0 + k];
+        uint64_t sh1;
+        if (o & 1) sh1 = (v << 1) | (s[r0 + (k + W - 1) % W] >> 63);
+        else sh1 = (v >> 1) | (s[r0 + (k + 1) % W] << 63);
+        a[r0 + k] = v | sh1;
+      }
+    // y: whole rows, from row y to row y +- 1 of the same plane
+    for (size_t p0 = 0; p0 < nw; p0 += plane)
+      for (int yy = 0; yy < nb; ++yy) {
+        const int src = (o & 2) ? (yy + nb - 1) % nb : (yy + 1) % nb;
+        for (int k = 0; k < W; ++k) c[p0 + (size_t)yy * W + k] = a[p0 + (size_t)yy * W + k] | a[p0 + (size_t)src * W + k];
+      }
+    // z: whole planes, then into the tagged blocks
+    for (int zz = 0; zz < nb; ++zz) {
+      const int src = (o & 4) ? (zz + nb - 1) % nb : (zz + 1) % nb;
+      const size_t d0 = (size_t)zz * plane, s0 = (size_t)src * plane;
+      for (size_t k = 0; k < plane; ++k) tagged.w[d0 + k] |= c[d0 + k] | c[s0 + k];
+    }
+  }
+  return true;
+}
+
+static bool mark_blocks(Bits& tagged, int M, int b, int r, bool halve, const int32_t* cells, long long n,
+                        std::string& err) {
+  const bool pow2 = (b & (b - 1)) == 0;
+  const int nb = M / b;
+  // the dense form costs a few passes over eight block bitsets: worth it from about one
+  // tag per 32 blocks of the level on
+  if (pow2 && !halve && 2 * r == b && nb % 64 == 0 && n >= (long long)nb * nb * nb / 32) {
+    int sh = 0;
+    while ((1 << sh) < b) ++sh;
+    return mark_octants(tagged, M, b, sh, cells, n, err);
+  }
+  return pow2 ? mark_blocks_t<true>(tagged, M, b, r, halve, cells, n, err)
+              : mark_blocks_t<false>(tagged, M, b, r, halve, cells, n, err);
 }
 
 bool cluster_level(int M, const std::vector<IBox>& level_boxes, bool full_level, int bf, int max_box, int nbuf,
