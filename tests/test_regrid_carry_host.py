@@ -143,24 +143,41 @@ def test_carried_cells_outside_the_finer_level_are_refused():
                             carried=_blob((1, 1, 1), (2, 2, 2)), grow=-1)
 
 
-@pytest.mark.parametrize("M,seed", [(256, 0), (256, 1), (512, 2)])
-def test_long_tag_lists_mark_the_same_blocks(M, seed):
-    # from one tag per 32 blocks on, the level's own tags are marked through octant
-    # bitsets (n_error_buf = 2 = half of bf/2); the carried form of the same cells (fine
-    # cells 2c + 1, grown by 0 + n_error_buf) marks them one by one: equal boxes, on the
-    # whole domain and on a refined layout, with tags on the periodic faces and in runs
-    rng = np.random.default_rng(seed)
-    nb = M // (BF // 2)
-    n = nb ** 3 // 32 + 500
+def _blob_tags(rng, M, n):
     blobs = [np.floor(c + rng.normal(0, M / 16, (n // 4, 3))).astype(np.int64) % M
              for c in rng.integers(0, M, (4, 3))]
     faces = np.array([[0, 5, 7], [M - 1, 5, 7], [3, 0, M - 1], [M - 1, M - 1, M - 1], [0, 0, 0]])
     run = np.stack([np.arange(M), np.full(M, 9), np.full(M, M - 2)], 1)
     tags = np.unique(np.concatenate(blobs + [faces, run]), axis=0).astype(np.int32)
-    tags = tags[np.lexsort((tags[:, 0], tags[:, 1], tags[:, 2]))]
-    assert len(tags) >= nb ** 3 // 32
+    return tags[np.lexsort((tags[:, 0], tags[:, 1], tags[:, 2]))]
+
+
+def _one_by_one(fn):
+    import os
+    os.environ["SHAMR_DENSE_MARKING"] = "0"
+    try:
+        return fn()
+    finally:
+        del os.environ["SHAMR_DENSE_MARKING"]
+
+
+@pytest.mark.parametrize("M,seed", [(256, 0), (256, 1), (512, 2)])
+def test_long_tag_lists_mark_the_same_blocks(M, seed):
+    # from one tag per 32 blocks on, a level's own tags are marked through octant bitsets;
+    # marking them one by one (the dense form switched off) gives the same boxes, on the
+    # whole domain and on a refined layout, with tags on the periodic faces and in runs;
+    # long carried lists (marked one by one) equal clustering numpy's carried cell list
+    rng = np.random.default_rng(seed)
+    nb = M // (BF // 2)
+    tags = _blob_tags(rng, M, nb ** 3 // 32 + 500)
+    fine = _blob_tags(rng, 2 * M, nb ** 3 // 32 + 500)
+    assert len(tags) >= nb ** 3 // 32 and len(fine) >= nb ** 3 // 32
+    few = tags[::97]
     for level in ([(0, 0, 0, M - 1, M - 1, M - 1)], _random_layout(rng, M, 40)):
-        dense = shamr.cluster_boxes(M, level, tags, BF, MAX_BOX, NBUF, 0.7)
-        one_by_one = shamr.cluster_boxes(M, level, tags[:0], BF, MAX_BOX, NBUF, 0.7, carried=2 * tags + 1, grow=0)
-        assert dense == one_by_one
-        assert dense or level[0][3] != M - 1
+        own = shamr.cluster_boxes(M, level, tags, BF, MAX_BOX, NBUF, 0.7)
+        assert own == _one_by_one(lambda: shamr.cluster_boxes(M, level, tags, BF, MAX_BOX, NBUF, 0.7))
+        car = shamr.cluster_boxes(M, level, few, BF, MAX_BOX, NBUF, 0.7, carried=fine)
+        assert car == _one_by_one(lambda: shamr.cluster_boxes(M, level, few, BF, MAX_BOX, NBUF, 0.7, carried=fine))
+        joined = driver.merge_tags(few, driver.carried_tags(fine, M))
+        assert car == _one_by_one(lambda: shamr.cluster_boxes(M, level, joined, BF, MAX_BOX, NBUF, 0.7))
+        assert own or level[0][3] != M - 1
