@@ -246,40 +246,25 @@ static bool mark_blocks_t(Bits& tagged, int M, int b, int r, bool halve, const i
   return true;
 }
 
-// Long lists with b/2 <= r < b (the level's own tags with n_error_buf = 2 and a blocking
-// factor of 8: r = 2, b = 4; also correct for carried tags, r = 3): along every axis the
-// cube [c - r, c + r] then meets the block B of c and one or both of its neighbours, B - 1
-// when the offset of c in its block is < r and B + 1 when offset + r >= b.  Each tag sets
-// the bit of B in the bitsets of the octants (the neighbour taken along x, y and z) its
-// choices allow, 1 to 8 of them; each octant bitset is grown by one block towards its
-// octant along x, y and z (periodically) and ORed into the tagged blocks: the union is the
-// set marking each tag's blocks one by one gives, at a few bit writes per tag.  Rows must
-// be whole words.
-static bool mark_octants(Bits& tagged, int M, int b, int sh, int r, bool halve, const int32_t* cells, long long n,
-                         std::string& err) {
-  const int nb = M / b, W = nb / 64;
-  const int lim = halve ? 2 * M : M;
+// The level's own tags when 2r equals the block size b (the usual n_error_buf = 2 with
+// a blocking factor of 8): every axis then meets exactly two blocks, the tag's block B and
+// B + 1 when its offset in the block is >= r, else B - 1 and B.  One bit per tag goes into
+// the bitset of its octant (the direction of the second block along each axis), each
+// octant bitset is grown by one block towards its octant along x, y and z (periodically)
+// and ORed into the tagged blocks: the same set as marking each tag's 2 x 2 x 2 blocks,
+// at one bit write per tag.  Used for long lists on rows of whole words.
+static bool mark_octants(Bits& tagged, int M, int b, int sh, const int32_t* cells, long long n, std::string& err) {
+  const int nb = M / b, r = b / 2, W = nb / 64;
   thread_local Bits oct[8];
   for (Bits& o : oct) o.init(nb);
   for (long long t = 0; t < n; ++t) {
-    int c[3], opt[3];
-    for (int d = 0; d < 3; ++d) {
-      c[d] = cells[3 * t + d];
-      if (c[d] < 0 || c[d] >= lim) {
-        err = halve ? "carried tag outside the finer level" : "tag outside the level";
-        return false;
-      }
-      if (halve) c[d] >>= 1;
-      const int off = c[d] & (b - 1);
-      opt[d] = (off < r ? 1 : 0) | (off + r >= b ? 2 : 0);  // bit 0: B - 1 met, bit 1: B + 1 met
+    const int x = cells[3 * t], y = cells[3 * t + 1], z = cells[3 * t + 2];
+    if (x < 0 || x >= M || y < 0 || y >= M || z < 0 || z >= M) {
+      err = "tag outside the level";
+      return false;
     }
-    const int bx = c[0] >> sh, by = c[1] >> sh, bz = c[2] >> sh;
-    for (int oz = 0; oz < 2; ++oz)
-      if (opt[2] >> oz & 1)
-        for (int oy = 0; oy < 2; ++oy)
-          if (opt[1] >> oy & 1)
-            for (int ox = 0; ox < 2; ++ox)
-              if (opt[0] >> ox & 1) oct[ox | oy << 1 | oz << 2].set(bx, by, bz);
+    const int o = ((x & (b - 1)) >= r ? 1 : 0) | ((y & (b - 1)) >= r ? 2 : 0) | ((z & (b - 1)) >= r ? 4 : 0);
+    oct[o].set(x >> sh, y >> sh, z >> sh);
   }
   const size_t nw = oct[0].w.size(), row = W, plane = (size_t)nb * W;
   std::vector<uint64_t> a(nw), c(nw);
@@ -315,17 +300,17 @@ static bool mark_blocks(Bits& tagged, int M, int b, int r, bool halve, const int
   const bool pow2 = (b & (b - 1)) == 0;
   const int nb = M / b;
   // the dense form costs a few passes over eight block bitsets: worth it for the level's
-  // own tags from about one tag per 32 blocks on (4.6 M tags: 57 -> 40 ms).  Carried
+  // own tags from about one tag per 32 blocks on (4.6 M tags: 56 -> 40 ms).  Carried
   // lists stay one by one: neighbouring fine tags share parents, which the run merging
-  // absorbs, while a carried tag sets up to eight octant bits (4.6 M: 62 ms one by one,
-  // 161 ms dense).  SHAMR_DENSE_MARKING=0 in the environment turns the dense form off,
-  // for comparing the two.
+  // absorbs, while a carried tag (parent grown by 3) would set up to eight octant bits
+  // (4.6 M: 62 ms one by one, 161 ms dense).  SHAMR_DENSE_MARKING=0 in the environment
+  // turns the dense form off, for comparing the two.
   const char* env = std::getenv("SHAMR_DENSE_MARKING");
   const bool dense_ok = !(env && env[0] == '0');
-  if (dense_ok && !halve && pow2 && 2 * r >= b && r < b && nb % 64 == 0 && n >= (long long)nb * nb * nb / 32) {
+  if (dense_ok && !halve && pow2 && 2 * r == b && nb % 64 == 0 && n >= (long long)nb * nb * nb / 32) {
     int sh = 0;
     while ((1 << sh) < b) ++sh;
-    return mark_octants(tagged, M, b, sh, r, halve, cells, n, err);
+    return mark_octants(tagged, M, b, sh, cells, n, err);
   }
   return pow2 ? mark_blocks_t<true>(tagged, M, b, r, halve, cells, n, err)
               : mark_blocks_t<false>(tagged, M, b, r, halve, cells, n, err);
