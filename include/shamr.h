@@ -264,6 +264,43 @@ sh_status sh_cluster_boxes_carried(int32_t M, int32_t nlevel_boxes, const int32_
                                    int64_t ntag, const int32_t* tags, int64_t ncarried, const int32_t* carried,
                                    int32_t grow, int32_t* boxes_out, int32_t cap, int32_t* nboxes);
 
+/* Clustering from tagged blocks instead of tag lists (section II.C, global regrid): for
+   levels with many tags no list crosses to the host.  Clustering works on blocks of bf/2
+   cells; the bitset of a level of M cells per axis has one bit per block, bit k = x +
+   nb (y + nb z) of block (x, y, z), nb = M / (bf/2), in nwords = ceil(nb^3 / 64) uint64
+   words owned by the caller.
+   sh_tag_blocks: tags level `lev` on the GPU (as sh_tag_cells) and ORs into `bits_host`
+   every block met by the cube [c - r, c + r] (periodic) around each tagged cell c: blocks
+   of level lev (halve = 0; r = n_error_buf gives the blocks sh_cluster_tags marks for
+   those tags) or of level lev - 1 (halve = 1, c replaced by its parent c / 2; r = grow +
+   n_error_buf gives the blocks sh_cluster_tags_carried marks for carried tags).  With
+   at least one tagged cell per 16 blocks (bf/2 a power of two, bf/4 <= r < bf/2), each
+   tagged cell sets, on the GPU, the bit of its own block in the octant bitsets of the
+   neighbours its cube reaches, and only those come to the host (8 nwords words), each
+   grown there by one block towards its octant; otherwise the tag list comes to the host
+   and is marked there.  *ntag (may be NULL) receives the
+   number of tagged cells.  Synchronises.  Errors: SH_EINVAL (no such level, halve on
+   level 0, r < 0, a null bitset or one of the wrong size), SH_ESTATE (stale level, or
+   called during capture), SH_EDEVICE.
+   sh_cluster_blocks: the boxes of level lev+1 from a bitset of level lev's blocks (the OR
+   of sh_tag_blocks calls): the boxes sh_cluster_tags(_carried) gives for the tags that
+   set those bits; output and errors as sh_cluster_tags, SH_EINVAL for a bitset of the
+   wrong size.
+   sh_cluster_boxes_bits is the same clustering without a hierarchy (host only; the
+   level's layout as in sh_cluster_boxes), and sh_dilate_octants the host step of
+   sh_tag_blocks: ORs into `bits` eight octant bitsets of nwords words each (one after
+   the other; bit 0 of the octant index: the +x neighbour, else -x; bit 1: +y; bit 2:
+   +z), each grown by one block towards its octant (periodic). */
+sh_status sh_tag_blocks(sh_hierarchy h, int32_t lev, int32_t halve, int32_t r, uint64_t* bits_host, int64_t nwords,
+                        int64_t* ntag);
+sh_status sh_cluster_blocks(sh_hierarchy h, int32_t lev, const uint64_t* bits, int64_t nwords, double efficiency,
+                            int32_t* boxes_out, int32_t cap, int32_t* nboxes);
+sh_status sh_cluster_boxes_bits(int32_t M, int32_t nlevel_boxes, const int32_t* level_boxes,
+                                int32_t blocking_factor, int32_t max_box, double efficiency, const uint64_t* bits,
+                                int64_t nwords, int32_t* boxes_out, int32_t cap, int32_t* nboxes);
+sh_status sh_dilate_octants(int32_t M, int32_t blocking_factor, const uint64_t* octants, uint64_t* bits,
+                            int64_t nwords);
+
 /* Local regrid (section II, "Local versus global regrid"): instead of clustering all tags
    anew, keep every box of the finer level and grow it, by whole blocks of the blocking
    factor bf, where tagged cells (with their n_error_buf buffer) reach past it; coarser

@@ -246,26 +246,29 @@ static bool mark_blocks_t(Bits& tagged, int M, int b, int r, bool halve, const i
   return true;
 }
 
-// The level's own tags when 2r equals the block size b (the usual n_error_buf = 2 with
-// a blocking factor of 8): every axis then meets exactly two blocks, the tag's block B and
-// B + 1 when its offset in the block is >= r, else B - 1 and B.  One bit per tag goes into
-// the bitset of its octant (the direction of the second block along each axis), each
-// octant bitset is grown by one block towards its octant along x, y and z (periodically)
-// and ORed into the tagged blocks: the same set as marking each tag's 2 x 2 x 2 blocks,
-// at one bit write per tag.  Used for long lists on rows of whole words.
-static bool mark_octants(Bits& tagged, int M, int b, int sh, const int32_t* cells, long long n, std::string& err) {
-  const int nb = M / b, r = b / 2, W = nb / 64;
-  thread_local Bits oct[8];
-  for (Bits& o : oct) o.init(nb);
-  for (long long t = 0; t < n; ++t) {
-    const int x = cells[3 * t], y = cells[3 * t + 1], z = cells[3 * t + 2];
-    if (x < 0 || x >= M || y < 0 || y >= M || z < 0 || z >= M) {
-      err = "tag outside the level";
-      return false;
+// ORs into `tagged` every octant bitset grown by one block towards its octant along x
+// (bit 0 of the octant index: +x, else -x), y (bit 1) and z (bit 2), periodically.  On
+// rows of whole words by word shifts and row / plane copies; otherwise set bit by set
+// bit (small levels).
+static void dilate_into(Bits& tagged, const Bits* oct) {
+  const int nb = tagged.n;
+  if (nb % 64) {
+    for (int o = 0; o < 8; ++o) {
+      const int dx = (o & 1) ? 1 : -1, dy = (o & 2) ? 1 : -1, dz = (o & 4) ? 1 : -1;
+      const std::vector<uint64_t>& w = oct[o].w;
+      for (size_t wi = 0; wi < w.size(); ++wi)
+        for (uint64_t word = w[wi]; word; word &= word - 1) {
+          const size_t k = (wi << 6) + __builtin_ctzll(word);
+          const int x = (int)(k % nb), y = (int)((k / nb) % nb), z = (int)(k / ((size_t)nb * nb));
+          for (int sz = 0; sz < 2; ++sz)
+            for (int sy = 0; sy < 2; ++sy)
+              for (int sx = 0; sx < 2; ++sx)
+                tagged.set(wrap(x + sx * dx, nb), wrap(y + sy * dy, nb), wrap(z + sz * dz, nb));
+        }
     }
-    const int o = ((x & (b - 1)) >= r ? 1 : 0) | ((y & (b - 1)) >= r ? 2 : 0) | ((z & (b - 1)) >= r ? 4 : 0);
-    oct[o].set(x >> sh, y >> sh, z >> sh);
+    return;
   }
+  const int W = nb / 64;
   const size_t nw = oct[0].w.size(), row = W, plane = (size_t)nb * W;
   std::vector<uint64_t> a(nw), c(nw);
   for (int o = 0; o < 8; ++o) {
@@ -292,6 +295,29 @@ static bool mark_octants(Bits& tagged, int M, int b, int sh, const int32_t* cell
       for (size_t k = 0; k < plane; ++k) tagged.w[d0 + k] |= c[d0 + k] | c[s0 + k];
     }
   }
+}
+
+// The level's own tags when 2r equals the block size b (the usual n_error_buf = 2 with
+// a blocking factor of 8): every axis then meets exactly two blocks, the tag's block B and
+// B + 1 when its offset in the block is >= r, else B - 1 and B.  One bit per tag goes into
+// the bitset of its octant (the direction of the second block along each axis), each
+// octant bitset is grown by one block towards its octant along x, y and z (periodically)
+// and ORed into the tagged blocks: the same set as marking each tag's 2 x 2 x 2 blocks,
+// at one bit write per tag.  Used for long lists on rows of whole words.
+static bool mark_octants(Bits& tagged, int M, int b, int sh, const int32_t* cells, long long n, std::string& err) {
+  const int nb = M / b, r = b / 2;
+  thread_local Bits oct[8];
+  for (Bits& o : oct) o.init(nb);
+  for (long long t = 0; t < n; ++t) {
+    const int x = cells[3 * t], y = cells[3 * t + 1], z = cells[3 * t + 2];
+    if (x < 0 || x >= M || y < 0 || y >= M || z < 0 || z >= M) {
+      err = "tag outside the level";
+      return false;
+    }
+    const int o = ((x & (b - 1)) >= r ? 1 : 0) | ((y & (b - 1)) >= r ? 2 : 0) | ((z & (b - 1)) >= r ? 4 : 0);
+    oct[o].set(x >> sh, y >> sh, z >> sh);
+  }
+  dilate_into(tagged, oct);
   return true;
 }
 
@@ -316,33 +342,100 @@ static bool mark_blocks(Bits& tagged, int M, int b, int r, bool halve, const int
               : mark_blocks_t<false>(tagged, M, b, r, halve, cells, n, err);
 }
 
-bool cluster_level(int M, const std::vector<IBox>& level_boxes, bool full_level, int bf, int max_box, int nbuf,
-                   double efficiency, const int32_t* tags, long long ntag, std::vector<IBox>& out, std::string& err,
-                   const int32_t* carried, long long ncarried, int carry_grow) {
-  out.clear();
+static bool check_level_args(int M, const std::vector<IBox>& level_boxes, int bf, std::string& err) {
   if (bf < 2 || (bf & 1)) {
     err = "blocking factor must be even";
     return false;
   }
-  const int b = bf / 2;
-  if (M % b) {
+  if (M % (bf / 2)) {
     err = "level size not a multiple of half the blocking factor";
     return false;
   }
-  const int nb = M / b;
   for (const IBox& L : level_boxes)
     for (int d = 0; d < 3; ++d)
       if (L.lo[d] < 0 || L.hi[d] >= M || L.lo[d] > L.hi[d]) {
         err = "level box outside the level";
         return false;
       }
-  // the two bitsets keep their storage between calls on a thread (fresh allocations of a
-  // few MB would be page-faulted in on every regrid)
-  thread_local Bits tagged, cov;
-  tagged.init(nb);
+  return true;
+}
+
+static bool cluster_core(int M, const std::vector<IBox>& level_boxes, bool full_level, int bf, int max_box,
+                         double efficiency, const Bits& tagged, std::vector<IBox>& out);
+
+// the bitsets keep their storage between calls on a thread (fresh allocations of a few MB
+// would be page-faulted in on every regrid)
+static thread_local Bits g_tagged;
+
+bool cluster_level(int M, const std::vector<IBox>& level_boxes, bool full_level, int bf, int max_box, int nbuf,
+                   double efficiency, const int32_t* tags, long long ntag, std::vector<IBox>& out, std::string& err,
+                   const int32_t* carried, long long ncarried, int carry_grow) {
+  out.clear();
+  if (!check_level_args(M, level_boxes, bf, err)) return false;
+  const int b = bf / 2;
+  Bits& tagged = g_tagged;
+  tagged.init(M / b);
   if (!mark_blocks(tagged, M, b, nbuf, false, tags, ntag, err)) return false;
   // tags of the next finer level: their coarse parents grown by carry_grow + nbuf cells
   if (ncarried > 0 && !mark_blocks(tagged, M, b, carry_grow + nbuf, true, carried, ncarried, err)) return false;
+  return cluster_core(M, level_boxes, full_level, bf, max_box, efficiency, tagged, out);
+}
+
+long long block_words(int M, int bf) {
+  const long long nb = M / (bf / 2);
+  return (nb * nb * nb + 63) / 64;
+}
+
+// A caller's block bitset (x fastest) as the working bitset `t` of a level of M cells.
+static bool load_bits(Bits& t, int M, int bf, const uint64_t* bits, long long nwords, std::string& err) {
+  if (bf < 2 || (bf & 1) || M % (bf / 2)) {
+    err = "bad blocking factor or level size";
+    return false;
+  }
+  if (nwords != block_words(M, bf)) {
+    err = "block bitset of the wrong size";
+    return false;
+  }
+  t.init(M / (bf / 2));
+  std::copy(bits, bits + nwords, t.w.begin());
+  // bits past the last block (in a partial last word) are not blocks
+  const long long nblk = (long long)t.n * t.n * t.n;
+  if (nblk % 64) t.w.back() &= (1ull << (nblk % 64)) - 1;
+  return true;
+}
+
+bool cluster_bits(int M, const std::vector<IBox>& level_boxes, bool full_level, int bf, int max_box,
+                  double efficiency, const uint64_t* bits, long long nwords, std::vector<IBox>& out,
+                  std::string& err) {
+  out.clear();
+  if (!check_level_args(M, level_boxes, bf, err) || !load_bits(g_tagged, M, bf, bits, nwords, err)) return false;
+  return cluster_core(M, level_boxes, full_level, bf, max_box, efficiency, g_tagged, out);
+}
+
+bool mark_list_blocks(int M, int bf, int r, bool halve, const int32_t* cells, long long n, uint64_t* bits,
+                      long long nwords, std::string& err) {
+  thread_local Bits t;
+  if (r < 0 || !load_bits(t, M, bf, bits, nwords, err)) return false;
+  if (!mark_blocks(t, M, bf / 2, r, halve, cells, n, err)) return false;
+  std::copy(t.w.begin(), t.w.end(), bits);
+  return true;
+}
+
+bool dilate_octants(int M, int bf, const uint64_t* oct, uint64_t* bits, long long nwords, std::string& err) {
+  thread_local Bits t, o8[8];
+  if (!load_bits(t, M, bf, bits, nwords, err)) return false;
+  for (int o = 0; o < 8; ++o)
+    if (!load_bits(o8[o], M, bf, oct + (size_t)o * nwords, nwords, err)) return false;
+  dilate_into(t, o8);
+  std::copy(t.w.begin(), t.w.end(), bits);
+  return true;
+}
+
+static bool cluster_core(int M, const std::vector<IBox>& level_boxes, bool full_level, int bf, int max_box,
+                         double efficiency, const Bits& tagged, std::vector<IBox>& out) {
+  const int b = bf / 2;
+  const int nb = M / b;
+  thread_local Bits cov;
   if (!full_level) {
     cov.init(nb);
     for (const IBox& L : level_boxes) {

@@ -476,6 +476,58 @@ __global__ __launch_bounds__(SH_BLOCK) void k_tag_compact(const Tile* __restrict
   }
 }
 
+// Tagged blocks for clustering, without a tag list: every tagged cell c (its parent c / 2
+// when `halve`) sets, in the bitsets of the octants its cube [c - r, c + r] reaches, the
+// bit of its own block B = c / b (b = 2^bsh cells; b/2 <= r < b, so along each axis the
+// cube meets B and B - 1 when c's offset in B is < r, B + 1 when offset + r >= b, or both).
+// The host grows each octant bitset by one block towards its octant.  Bit k = x + nb (y +
+// nb z) of B lies in word k / 64 of octant o's nwords words.  Lanes with the same word
+// are ORed together first, and one lane per word does the atomic.
+__global__ __launch_bounds__(SH_BLOCK) void k_tag_octants(const Tile* __restrict__ tiles, int ntiles,
+                                                          const BoxDev* __restrict__ boxes,
+                                                          const uint8_t* __restrict__ mask, int halve, int r,
+                                                          int bsh, int nb, unsigned long long* __restrict__ oct,
+                                                          long long nwords) {
+  const int lane = threadIdx.x & (SH_WAVE - 1);
+  const int t = blockIdx.x * (SH_BLOCK / SH_WAVE) + (threadIdx.x >> 6);
+  if (t >= ntiles) return;
+  const Tile tl = tiles[t];
+  if (tl.box < 0) return;
+  const BoxDev B = boxes[tl.box];
+  const int tx = lane & ((1 << tl.txs) - 1), ty = lane >> tl.txs;
+  const int x = (tl.xy & 0xffff) + tx, y = (tl.xy >> 16) + ty;
+  const bool active = (x < B.nx) && (y < B.ny);
+  const int z0 = tl.zz & 0xffff, zend = min(z0 + (tl.zz >> 16), B.nz);
+  const int b = 1 << bsh;
+  const int cx = (B.lo[0] + x) >> halve, cy = (B.lo[1] + y) >> halve;
+  const int ox = ((cx & (b - 1)) < r ? 1 : 0) | ((cx & (b - 1)) + r >= b ? 2 : 0);
+  const int oy = ((cy & (b - 1)) < r ? 1 : 0) | ((cy & (b - 1)) + r >= b ? 2 : 0);
+  for (int z = z0; z < zend; ++z) {
+    const bool tag = active && mask[B.mask_off + ((long long)z * B.ny + y) * B.nx + x];
+    if (!__ballot(tag)) continue;
+    const int cz = (B.lo[2] + z) >> halve;
+    const int oz = ((cz & (b - 1)) < r ? 1 : 0) | ((cz & (b - 1)) + r >= b ? 2 : 0);
+    const long long k = ((long long)(cz >> bsh) * nb + (cy >> bsh)) * nb + (cx >> bsh);
+    const unsigned long long bit = 1ull << (k & 63);
+    // octant index: bit 0 set for +x, bit 1 for +y, bit 2 for +z
+    for (int o = 0; o < 8; ++o) {
+      const bool want = tag && ((o & 1) ? (ox & 2) : (ox & 1)) && ((o & 2) ? (oy & 2) : (oy & 1)) &&
+                        ((o & 4) ? (oz & 2) : (oz & 1));
+      const long long key = want ? (long long)o * nwords + (k >> 6) : -1;
+      unsigned long long pending = __ballot(want);
+      while (pending) {
+        const int leader = __ffsll((long long)pending) - 1;
+        const long long lk = __shfl(key, leader);
+        const bool mine = want && key == lk;
+        unsigned long long v = mine ? bit : 0ull;
+        for (int off = 32; off >= 1; off >>= 1) v |= __shfl_xor(v, off);
+        if (lane == leader) atomicOr(oct + lk, v);
+        pending &= ~__ballot(mine);
+      }
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------------
 // A6: energy.  Per cell (not covered by a finer level):
 //   kin = 1/2 (Pi1^2 + Pi2^2),  grad = 1/2 sum_i sum_d (psi_i(x+e_d) - psi_i(x))^2 inv_dx2,
@@ -790,6 +842,14 @@ void sh_launch_tag_compact(const Tile* tiles, int ntiles, const BoxDev* boxes, c
   const int nb = nblk(ntiles, SH_BLOCK / SH_WAVE);
   if (nb == 0) return;
   hipLaunchKernelGGL(k_tag_compact, dim3(nb), dim3(SH_BLOCK), 0, st, tiles, ntiles, boxes, mask, tile_off, idx, cap);
+}
+
+void sh_launch_tag_octants(const Tile* tiles, int ntiles, const BoxDev* boxes, const uint8_t* mask, int halve, int r,
+                           int bsh, int nb, unsigned long long* oct, long long nwords, hipStream_t st) {
+  const int n = nblk(ntiles, SH_BLOCK / SH_WAVE);
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_tag_octants, dim3(n), dim3(SH_BLOCK), 0, st, tiles, ntiles, boxes, mask, halve, r, bsh, nb, oct,
+                     nwords);
 }
 
 void sh_launch_energy(int prec, const Tile* tiles, int ntiles, const BoxDev* boxes, const uint8_t* covered,

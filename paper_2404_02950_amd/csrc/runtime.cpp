@@ -509,6 +509,11 @@ struct sh_hierarchy_s {
   long long layout_version = 0;  // bumped by every layout change (captured graphs go stale)
   LevelScal* d_ls = nullptr;  // 16 levels, then the shadow level
   UploadStage stage;          // pinned staging of the table uploads of a layout change
+  // octant bitsets of tagged blocks (sh_tag_blocks): device buffer of 8 x oct_words words
+  // and its host copy
+  unsigned long long* d_oct = nullptr;
+  long long oct_words = 0;
+  std::vector<uint64_t> h_oct;
   double* d_dbg = nullptr;
   std::vector<Level> lev;
   bool tracing = false;
@@ -1015,6 +1020,7 @@ sh_status sh_hierarchy_destroy(sh_hierarchy h) {
   for (Level& L : h->lev) L.release();
   if (h->d_ls) (void)hipFree(h->d_ls);
   if (h->d_dbg) (void)hipFree(h->d_dbg);
+  if (h->d_oct) (void)hipFree(h->d_oct);
   if (h->stage.buf) (void)hipHostFree(h->stage.buf);
   delete h;
   return SH_OK;
@@ -1581,6 +1587,9 @@ sh_status sh_read_tee(sh_hierarchy h, int32_t l, double* out_dev) {
 // Tagging of a level; the compacted list is staged in `staging` (device memory with room
 // for `cap` cells, checked by the caller) when given, else in the level's own buffer,
 // grown with hipMalloc as needed.
+static sh_status compact_tags(sh_hierarchy h, int32_t l, const uint8_t* mask, int32_t* idx_host, long long want,
+                              int32_t* staging);
+
 static sh_status tag_cells(sh_hierarchy h, int32_t l, uint8_t* mask_dev, int32_t* idx_host, int64_t cap,
                            int64_t* ntag, int32_t* staging) {
   sh_status s = check_level(h, l);
@@ -1601,7 +1610,15 @@ static sh_status tag_cells(sh_hierarchy h, int32_t l, uint8_t* mask_dev, int32_t
   HIPCHK(hipMemcpyAsync(&total, L.tile_off() + nt, 8, hipMemcpyDeviceToHost, h->st));
   HIPCHK(hipStreamSynchronize(h->st));
   if (ntag) *ntag = total;
-  const long long want = std::min<long long>(total, cap);
+  return compact_tags(h, l, mask, idx_host, std::min<long long>(total, cap), staging);
+}
+
+// The first `want` tagged cells of the mask just computed by tag_cells (its tile offsets
+// are current), as (x, y, z) triples into idx_host.
+static sh_status compact_tags(sh_hierarchy h, int32_t l, const uint8_t* mask, int32_t* idx_host, long long want,
+                              int32_t* staging) {
+  Level& L = h->lev[l];
+  const int nt = L.ntiles();
   if (idx_host && want > 0) {
     int32_t* idx = staging;
     if (!idx) {
@@ -1882,6 +1899,87 @@ sh_status sh_cluster_tags_carried(sh_hierarchy h, int32_t l, int64_t ntag, const
                      err, carried, ncarried, grow))
     return fail(SH_EINVAL, err);
   return emit_boxes(out, boxes_out, cap, nboxes);
+}
+
+sh_status sh_tag_blocks(sh_hierarchy h, int32_t l, int32_t halve, int32_t r, uint64_t* bits_host, int64_t nwords,
+                        int64_t* ntag) {
+  sh_status s = check_level(h, l);
+  if (s != SH_OK || (s = not_capturing(h)) != SH_OK) return s;
+  if ((halve != 0 && halve != 1) || (halve && l == 0) || r < 0 || !bits_host || nwords < 0)
+    return fail(SH_EINVAL, "bad block tagging arguments");
+  Level& L = h->lev[l];
+  const int bf = h->p.blocking_factor, b = bf / 2;
+  const int M = halve ? L.M / 2 : L.M;
+  if (nwords != block_words(M, bf)) return fail(SH_EINVAL, "block bitset of the wrong size");
+  int bsh = 0;
+  while ((1 << bsh) < b) ++bsh;
+  int64_t n = 0;
+  if ((s = tag_cells(h, l, nullptr, nullptr, 0, &n, nullptr)) != SH_OK) return s;
+  if (ntag) *ntag = n;
+  if (n == 0) return SH_OK;
+  // octant bitsets cost 8 bits per block of the target level to clear, copy and grow, a
+  // tag list 12 bytes and a marking step per tag: octants from one tag per 16 blocks on
+  const long long nb = M / b;
+  const bool octants = (1 << bsh) == b && 2 * r >= b && r < b && n >= nb * nb * nb / 16;
+  std::string err;
+  if (!octants) {
+    std::vector<int32_t> idx((size_t)n * 3);
+    if ((s = compact_tags(h, l, L.mask(), idx.data(), n, nullptr)) != SH_OK) return s;
+    if (!mark_list_blocks(M, bf, r, halve != 0, idx.data(), n, bits_host, nwords, err)) return fail(SH_EINVAL, err);
+    return SH_OK;
+  }
+  if (h->oct_words < nwords) {
+    if (h->d_oct) (void)hipFree(h->d_oct);
+    h->d_oct = nullptr;
+    h->oct_words = 0;
+    HIPCHK(hipMalloc((void**)&h->d_oct, (size_t)8 * nwords * 8));
+    h->oct_words = nwords;
+  }
+  HIPCHK(hipMemsetAsync(h->d_oct, 0, (size_t)8 * nwords * 8, h->st));
+  sh_launch_tag_octants(L.tiles.p, L.ntiles(), L.dbox.p, L.mask(), halve, r, bsh, (int)nb, h->d_oct, nwords, h->st);
+  LAUNCHCHK();
+  h->h_oct.resize((size_t)8 * nwords);
+  HIPCHK(hipMemcpyAsync(h->h_oct.data(), h->d_oct, (size_t)8 * nwords * 8, hipMemcpyDeviceToHost, h->st));
+  HIPCHK(hipStreamSynchronize(h->st));
+  if (!dilate_octants(M, bf, h->h_oct.data(), bits_host, nwords, err)) return fail(SH_EINVAL, err);
+  return SH_OK;
+}
+
+sh_status sh_cluster_blocks(sh_hierarchy h, int32_t l, const uint64_t* bits, int64_t nwords, double efficiency,
+                            int32_t* boxes_out, int32_t cap, int32_t* nboxes) {
+  sh_status s = check_level(h, l);
+  if (s != SH_OK) return s;
+  if (!bits || nwords < 0 || !nboxes || cap < 0 || (cap > 0 && !boxes_out) || !(efficiency > 0) || efficiency > 1)
+    return fail(SH_EINVAL, "bad clustering arguments");
+  const sh_params& p = h->p;
+  const Level& L = h->lev[l];
+  std::vector<IBox> out;
+  std::string err;
+  if (!cluster_bits(L.M, L.boxes, l == 0, p.blocking_factor, p.max_box, efficiency, bits, nwords, out, err))
+    return fail(SH_EINVAL, err);
+  return emit_boxes(out, boxes_out, cap, nboxes);
+}
+
+sh_status sh_cluster_boxes_bits(int32_t M, int32_t nlevel_boxes, const int32_t* level_boxes, int32_t bf,
+                                int32_t max_box, double efficiency, const uint64_t* bits, int64_t nwords,
+                                int32_t* boxes_out, int32_t cap, int32_t* nboxes) {
+  std::vector<IBox> lb;
+  if (M < 1 || !read_boxes(nlevel_boxes, level_boxes, lb) || !bits || nwords < 0 || !nboxes || cap < 0 ||
+      (cap > 0 && !boxes_out) || !(efficiency > 0) || efficiency > 1 || max_box < bf)
+    return fail(SH_EINVAL, "bad clustering arguments");
+  std::vector<IBox> out;
+  std::string err;
+  if (!cluster_bits(M, lb, nlevel_boxes == 0, bf, max_box, efficiency, bits, nwords, out, err))
+    return fail(SH_EINVAL, err);
+  return emit_boxes(out, boxes_out, cap, nboxes);
+}
+
+sh_status sh_dilate_octants(int32_t M, int32_t blocking_factor, const uint64_t* octants, uint64_t* bits,
+                            int64_t nwords) {
+  if (M < 1 || !octants || !bits || nwords < 0) return fail(SH_EINVAL, "bad octant arguments");
+  std::string err;
+  if (!dilate_octants(M, blocking_factor, octants, bits, nwords, err)) return fail(SH_EINVAL, err);
+  return SH_OK;
 }
 
 sh_status sh_set_tuning(sh_hierarchy h, int32_t kind, int32_t nontemporal, int32_t tile_z, int32_t fuse,

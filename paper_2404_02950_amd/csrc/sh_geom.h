@@ -176,6 +176,21 @@ bool cluster_level(int M, const std::vector<IBox>& level_boxes, bool full_level,
                    double efficiency, const int32_t* tags, long long ntag, std::vector<IBox>& out, std::string& err,
                    const int32_t* carried = nullptr, long long ncarried = 0, int carry_grow = 0);
 
+// Bitsets of tagged blocks (bf/2 cells; bit x + nb (y + nb z); block_words(M, bf) 64-bit
+// words for a level of M cells per axis, nb = M / (bf/2)):
+long long block_words(int M, int bf);
+// the same clustering from such a bitset;
+bool cluster_bits(int M, const std::vector<IBox>& level_boxes, bool full_level, int bf, int max_box,
+                  double efficiency, const uint64_t* bits, long long nwords, std::vector<IBox>& out,
+                  std::string& err);
+// OR into it the blocks met by cells grown by r (the cells' parents, from a level of 2M
+// cells, when halve);
+bool mark_list_blocks(int M, int bf, int r, bool halve, const int32_t* cells, long long n, uint64_t* bits,
+                      long long nwords, std::string& err);
+// OR into it eight octant bitsets (the same size, one after the other), each grown by one
+// block towards its octant: bit 0 of the octant index +x (else -x), bit 1 +y, bit 2 +z.
+bool dilate_octants(int M, int bf, const uint64_t* oct, uint64_t* bits, long long nwords, std::string& err);
+
 // Local regrid (implemented in local_regrid.cpp), on the block grid of the finer level
 // (blocks of bf cells).  local_tag_boxes: boxes to add to level l+1 (fine index, M_fine
 // cells per axis) so that every tagged level-l cell with its n_error_buf buffer is

@@ -49,6 +49,8 @@ void sh_launch_absmax(int prec, const Tile* tiles, int ntiles, const BoxDev* box
 void sh_launch_scan(const int* in, long long* out, int n, hipStream_t st);
 void sh_launch_tag_compact(const Tile* tiles, int ntiles, const BoxDev* boxes, const uint8_t* mask,
                            const long long* tile_off, int* idx, long long cap, hipStream_t st);
+void sh_launch_tag_octants(const Tile* tiles, int ntiles, const BoxDev* boxes, const uint8_t* mask, int halve, int r,
+                           int bsh, int nb, unsigned long long* oct, long long nwords, hipStream_t st);
 void sh_launch_energy(int prec, const Tile* tiles, int ntiles, const BoxDev* boxes, const uint8_t* covered,
                       EnergyPartial* part, hipStream_t st);
 void sh_launch_energy_final(const EnergyPartial* part, int n, double vol, double* out, hipStream_t st);

@@ -112,10 +112,12 @@ def regrid(h, max_level: int, layout_for=None, efficiency: float = 0.7, max_leve
            log=None, timing: dict | None = None, start: int = 1, carry: bool = True):
     """Rebuild levels start..max_level from tags (levels below start are kept).
 
-    ``layout_for(lev, ntag, idx)`` may return the boxes of level lev+1; by default the
-    tags are clustered by the library (Berger-Rigoutsos).  With ``carry``, the tags of
-    every existing finer level are taken first, on the hierarchy as it stands, and each
-    level's tags are joined by those of the level above it (``carried_tags``): levels are
+    ``layout_for(lev, ntag, idx)`` may return the boxes of level lev+1 from the tag list;
+    by default the library clusters (Berger-Rigoutsos) the blocks the tags meet, marked on
+    the GPU (``tag_blocks``, ``cluster_blocks``: no tag list crosses to the host).  With
+    ``carry``, the tags of every existing finer level are taken first, on the hierarchy as
+    it stands, and each level's blocks are joined by those the grown parents of the level
+    above it meet (what ``carried_tags`` gives as a cell list): levels are
     rebuilt coarsest first, and a level l+1 built from level l's tags alone could be too
     small to nest the refinement of a tag level l+1 holds near its edge, which clustering
     would then drop.  ``max_level_bytes`` caps the device arena of any one new level: a
@@ -125,26 +127,30 @@ def regrid(h, max_level: int, layout_for=None, efficiency: float = 0.7, max_leve
     clustering and layout changes.  Returns the tag counts (each level's own).
     """
     counts = []
-    carried = {}
+    nbuf = h.params.n_error_buf
+    carried = {}      # level -> bitset of its blocks met by the finer level's grown tag parents
     if carry and layout_for is None:
         t0 = time.perf_counter()
         for lev in range(max(1, start), min(h.num_levels(), max_level)):
-            _, idx = h.tag(lev)
-            if idx is not None and len(idx):
-                carried[lev] = idx
+            n, bits = h.tag_blocks(lev, 1 + nbuf, halve=True)
+            if n:
+                carried[lev - 1] = bits
         if timing is not None:
             timing["tag"] = timing.get("tag", 0.0) + time.perf_counter() - t0
     for lev in range(max(0, start - 1), max_level):
         if lev >= h.num_levels():
             break
         t0 = time.perf_counter()
-        ntag, idx = h.tag(lev)
+        if layout_for is not None:
+            ntag, idx = h.tag(lev)
+        else:      # tagged blocks: the level's own tags grown by n_error_buf, the carried ones joined
+            ntag, bits = h.tag_blocks(lev, nbuf, bits=carried.get(lev))
         t1 = time.perf_counter()
         counts.append(ntag)
         if layout_for is not None:
             boxes = layout_for(lev, ntag, idx)
-        else:      # the carried tags join inside the clustering (as carried_tags would)
-            boxes = h.cluster(lev, idx, efficiency, carried=carried.get(lev + 1))
+        else:
+            boxes = h.cluster_blocks(lev, bits, efficiency)
         t2 = time.perf_counter()
         if boxes and max_level_bytes is not None:
             need = h.arena_bytes(lev + 1, boxes)

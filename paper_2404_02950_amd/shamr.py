@@ -62,6 +62,12 @@ _PROTOS = {
     "sh_cluster_boxes_carried": (c_int32, [c_int32, c_int32, c_void_p, c_int32, c_int32, c_int32, c_double,
                                            c_int64, c_void_p, c_int64, c_void_p, c_int32, c_void_p, c_int32,
                                            POINTER(c_int32)]),
+    "sh_tag_blocks": (c_int32, [c_void_p, c_int32, c_int32, c_int32, c_void_p, c_int64, POINTER(c_int64)]),
+    "sh_cluster_blocks": (c_int32, [c_void_p, c_int32, c_void_p, c_int64, c_double, c_void_p, c_int32,
+                                    POINTER(c_int32)]),
+    "sh_cluster_boxes_bits": (c_int32, [c_int32, c_int32, c_void_p, c_int32, c_int32, c_double, c_void_p, c_int64,
+                                        c_void_p, c_int32, POINTER(c_int32)]),
+    "sh_dilate_octants": (c_int32, [c_int32, c_int32, c_void_p, c_void_p, c_int64]),
     "sh_local_tag_boxes": (c_int32, [c_int32, c_int32, c_void_p, c_int32, c_int32, c_int32, c_int64, c_void_p,
                                      c_void_p, c_int32, POINTER(c_int32)]),
     "sh_local_nest_boxes": (c_int32, [c_int32, c_int32, c_void_p, c_int32, c_void_p, c_int32, c_int32, c_void_p,
@@ -174,6 +180,34 @@ def _cluster_cap(ntags: int) -> int:
     well under one box per 8 tags) and never below 65536 boxes (1.5 MiB, not touched
     beyond what is written)."""
     return max(1 << 16, ntags // 8)
+
+
+def block_words(M: int, blocking_factor: int) -> int:
+    """Words of the tagged-block bitset of a level of M cells per axis (blocks of bf/2)."""
+    nb = M // (blocking_factor // 2)
+    return (nb ** 3 + 63) // 64
+
+
+def cluster_boxes_bits(M: int, level_boxes, bits, blocking_factor: int = 8, max_box: int = 64,
+                       efficiency: float = 0.7):
+    """Berger-Rigoutsos clustering from a tagged-block bitset (host only)."""
+    lib = load()
+    lb = np.ascontiguousarray(np.asarray(level_boxes, np.int32).reshape(-1, 6))
+    bb = np.ascontiguousarray(bits, np.uint64)
+    return _boxes_call(lambda out, cap, nb: lib.sh_cluster_boxes_bits(
+        M, len(lb), lb.ctypes.data_as(c_void_p), blocking_factor, max_box, efficiency, bb.ctypes.data_as(c_void_p),
+        len(bb), out, cap, nb))
+
+
+def dilate_octants(M: int, octants, blocking_factor: int = 8, bits=None):
+    """OR eight octant bitsets (shape (8, nwords)), each grown by one block towards its
+    octant, into a block bitset (host only; sh_dilate_octants)."""
+    lib = load()
+    nw = block_words(M, blocking_factor)
+    o = np.ascontiguousarray(octants, np.uint64).reshape(8, nw)
+    out = np.zeros(nw, np.uint64) if bits is None else bits
+    _check(lib.sh_dilate_octants(M, blocking_factor, o.ctypes.data_as(c_void_p), out.ctypes.data_as(c_void_p), nw))
+    return out
 
 
 def _boxes_call(fn):
@@ -468,6 +502,23 @@ class Hierarchy:
             res.append(flat[o:o + sz].reshape(4, nz, ny, nx))
             o += sz
         return res
+
+    def tag_blocks(self, lev: int, r: int, halve: bool = False, bits=None):
+        """Tag a level on the GPU and OR the blocks its tagged cells, grown by r, meet into
+        a block bitset of that level (of the level below with ``halve``, from the cells'
+        parents): (tag count, uint64 bitset).  See sh_tag_blocks."""
+        M = (self.params.n0 << lev) >> (1 if halve else 0)
+        nw = block_words(M, self.params.blocking_factor)
+        out = np.zeros(nw, np.uint64) if bits is None else bits
+        n = c_int64()
+        _check(self.lib.sh_tag_blocks(self.h, lev, int(halve), r, out.ctypes.data_as(c_void_p), nw, ctypes.byref(n)))
+        return n.value, out
+
+    def cluster_blocks(self, lev: int, bits, efficiency: float = 0.7):
+        """Boxes of level lev+1 from a bitset of level lev's tagged blocks (sh_cluster_blocks)."""
+        bb = np.ascontiguousarray(bits, np.uint64)
+        return _boxes_call(lambda out, cap, nb: self.lib.sh_cluster_blocks(
+            self.h, lev, bb.ctypes.data_as(c_void_p), len(bb), efficiency, out, cap, nb))
 
     def cluster(self, lev: int, tags: np.ndarray, efficiency: float = 0.7, carried=None, grow: int = 1):
         """Boxes of level lev+1 from level lev's tags (sh_cluster_tags); with ``carried``,

@@ -48,17 +48,21 @@ def test_carried_regrid_on_the_gpu_matches_the_oracle_on_its_layouts():
     z, y, x = np.nonzero(ho.tags(1))
     carried = driver.carried_tags(np.stack([x, y, z], 1), N0)
     made = {}
-    cluster = hg.cluster
+    cluster_blocks = hg.cluster_blocks
+    # the tag lists of the hierarchy as it stands (level 1 is rebuilt first, from level 0's
+    # tags and level 1's carried ones)
+    lists = {lev: hg.tag(lev)[1] for lev in range(2)}
 
-    def recording_cluster(lev, idx, efficiency=0.7, carried=None):
-        boxes = cluster(lev, idx, efficiency, carried=carried)
-        if carried is not None:      # carried inside the library = the carried list joined
-            joined = driver.merge_tags(idx, driver.carried_tags(carried, N0 << lev))
-            assert boxes == cluster(lev, joined, efficiency), lev
+    def recording_cluster_blocks(lev, bits, efficiency=0.7):
+        boxes = cluster_blocks(lev, bits, efficiency)
+        if lev == 0:     # blocks marked on the GPU = the tag lists clustered, carried list joined
+            joined = driver.merge_tags(lists[0], driver.carried_tags(lists[1], N0))
+            assert boxes == hg.cluster(0, joined, efficiency)
+            assert boxes == hg.cluster(0, lists[0], efficiency, carried=lists[1])
         made[lev + 1] = boxes
         return boxes
 
-    hg.cluster = recording_cluster
+    hg.cluster_blocks = recording_cluster_blocks
     driver.regrid(hg, 2, carry=True)
     assert 1 in made and made[1], "level 1 must be rebuilt"
     valid0 = np.ones((N0,) * 3, bool)

@@ -78,10 +78,18 @@ class _FakeHierarchy:
     def num_levels(self):
         return self.levels
 
+    params = type("P", (), {"n_error_buf": 2})()
+
     def tag(self, lev):
         return 10 * (lev + 1), None
 
+    def tag_blocks(self, lev, r, halve=False, bits=None):
+        return (0, None) if halve else (10 * (lev + 1), None)
+
     def cluster(self, lev, idx, efficiency, carried=None):
+        return self._boxes[lev]
+
+    def cluster_blocks(self, lev, bits, efficiency):
         return self._boxes[lev]
 
     def arena_bytes(self, lev, boxes):

@@ -181,3 +181,46 @@ def test_long_tag_lists_mark_the_same_blocks(M, seed):
         joined = driver.merge_tags(few, driver.carried_tags(fine, M))
         assert car == _one_by_one(lambda: shamr.cluster_boxes(M, level, joined, BF, MAX_BOX, NBUF, 0.7))
         assert own or level[0][3] != M - 1
+
+
+def _octants_of(cells, M, r, halve=False):
+    """Octant bitsets (8, nwords) of tagged cells: the bit of each cell's block (of its
+    parent's, halved) in every octant its cube [c - r, c + r] reaches (per axis: -1 when
+    the offset in the block is < r, +1 when offset + r >= b)."""
+    b = BF // 2
+    nb = M // b
+    nw = shamr.block_words(M, BF)
+    flat = np.zeros((8, nw * 64), bool)
+    for c in np.asarray(cells).reshape(-1, 3):
+        c = c >> 1 if halve else c
+        opts = [[s for s, ok in ((0, v % b < r), (1, v % b + r >= b)) if ok] for v in c]
+        k = (c[2] // b * nb + c[1] // b) * nb + c[0] // b
+        for ox in opts[0]:
+            for oy in opts[1]:
+                for oz in opts[2]:
+                    flat[ox | oy << 1 | oz << 2, k] = True
+    return np.packbits(flat, axis=1, bitorder="little").view(np.uint64)
+
+
+@pytest.mark.parametrize("M,seed", [(64, 0), (64, 1), (256, 2)])
+def test_octant_bitsets_grown_cluster_like_tag_lists(M, seed):
+    # the host half of block tagging: octant bitsets of a level's own tags (grown by 2)
+    # and of carried fine tags (parents grown by 3), each grown by one block towards its
+    # octant and ORed, cluster into the boxes of the tag lists (rows of whole words at
+    # 256, set bit by set bit at 64), on level 0 and on a refined layout
+    rng = np.random.default_rng(20 + seed)
+    for level in ([(0, 0, 0, M - 1, M - 1, M - 1)], _random_layout(rng, M, 12)):
+        valid = np.argwhere(boxes_mask(level, M))[:, ::-1].astype(np.int32)
+        tags = valid[rng.choice(len(valid), min(len(valid), 400), replace=False)]
+        tags = np.concatenate([tags, valid[:3], valid[-3:]])
+        fine = rng.integers(0, 2 * M, (300, 3), dtype=np.int32)
+        fine = np.concatenate([fine, np.array([[0, 0, 0], [2 * M - 1] * 3], np.int32)])
+        bits = shamr.dilate_octants(M, _octants_of(tags, M, NBUF), BF)
+        assert shamr.cluster_boxes_bits(M, level, bits, BF, MAX_BOX) == shamr.cluster_boxes(M, level, tags, BF, MAX_BOX, NBUF)
+        shamr.dilate_octants(M, _octants_of(fine, M, 1 + NBUF, halve=True), BF, bits=bits)
+        want = shamr.cluster_boxes(M, level, tags, BF, MAX_BOX, NBUF, carried=fine, grow=1)
+        assert shamr.cluster_boxes_bits(M, level, bits, BF, MAX_BOX) == want
+    nw = shamr.block_words(M, BF)
+    assert shamr.cluster_boxes_bits(M, [(0, 0, 0, M - 1, M - 1, M - 1)], np.zeros(nw, np.uint64)) == []
+    with pytest.raises(shamr.ShError):
+        shamr.cluster_boxes_bits(M, [(0, 0, 0, M - 1, M - 1, M - 1)], np.zeros(nw - 1, np.uint64))
